@@ -1,0 +1,228 @@
+/*
+ * mfstokes: matrix-free Taylor-Hood Stokes / stabilised Navier-Stokes
+ * operators and multigrid solvers on structured hexahedral meshes, for AMD
+ * MI355X (gfx950).
+ *
+ * Methods follow Munch et al., "Solving the (Navier-)Stokes equations with
+ * space and time adaptivity using deal.II":
+ *   - Stokes weak form, Sec. 1 eq. (stokes); block system and
+ *     Silvester-Wathen preconditioner, Sec. 3 eq. (stokes_block);
+ *   - matrix-free operator evaluation in smoothing and transfer, Sec. 1/2;
+ *   - cell-wise transfer x_f = sum_e S_e W_e P_e C_e G_e x_c, restriction its
+ *     transpose, Sec. 2 eq. (transfer);
+ *   - Chebyshev smoothing around point Jacobi, Sec. 2 and 3;
+ *   - p-multigrid then global-coarsening h-multigrid, Sec. 3;
+ *   - SUPG/PSPG stabilised Navier-Stokes Jacobian with BDF2, Sec. 5.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Mesh: structured grid of n[0] x n[1] (x n[2]) cells, vertices numbered
+ *   lexicographically with x fastest; each cell is the Q1 (bi/trilinear) image
+ *   of the reference cell [0,1]^dim.
+ * Bases: nodal Lagrange on Gauss-Lobatto-Legendre points; quadrature: tensor
+ *   Gauss-Legendre with k+1 points per direction (k = velocity degree).
+ * Vectors: blocked [u_0 | u_1 | (u_2) | p].  Scalar node (i,j,l) of degree d
+ *   has index i + (d n0 + 1) (j + (d n1 + 1) l).  Pressure degree is k-1
+ *   (Taylor-Hood) or k (equal order, Navier-Stokes).
+ * Constraints: every velocity node on the boundary is a Dirichlet node.  The
+ *   operators act as the identity on Dirichlet rows and ignore the source
+ *   values there in every other row (homogeneous operator; inhomogeneous data
+ *   enters the right-hand side by lifting, see mfs_rhs).
+ * Sign: the pressure rows carry B^T u with B_ij = -(psi_j, div phi_i), making
+ *   the Stokes matrix [[A, B], [B^T, 0]] symmetric (eq. (stokes_block)).
+ * Memory: every vector argument is a device pointer (hipMalloc / torch CUDA
+ *   tensor) of exactly the documented length, in the precision named by the
+ *   call, not aliasing any other argument unless stated.  Device memory the
+ *   library needs internally is allocated in mfs_setup and freed by
+ *   mfs_destroy.  Streams are hipStream_t passed as void* (NULL = default).
+ * Errors: every call returns MFS_OK (0) or a negative code; mfs_last_error()
+ *   returns a thread-local message for the last failure.  No C++ exception
+ *   crosses this interface.
+ * Threads: a problem handle may be used by one host thread at a time;
+ *   different handles are independent.
+ */
+#ifndef MFSTOKES_H
+#define MFSTOKES_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MFS_OK 0
+#define MFS_EINVAL (-1)
+#define MFS_ENOMEM (-2)
+#define MFS_EUNSUPPORTED (-3)
+#define MFS_EHIP (-4)
+#define MFS_ENOCONV (-5)
+
+/* precision of an operation */
+#define MFS_FP64 0
+#define MFS_FP32 1
+
+/* operators for mfs_vmult */
+#define MFS_OP_STOKES 0      /* [u;p] -> [A u + B p ; B^T u], full vectors            */
+#define MFS_OP_A 1           /* velocity block: u -> A u (vector Laplacian, nu-scaled) */
+#define MFS_OP_B 2           /* p -> B p (velocity-sized output, 0 on Dirichlet rows)  */
+#define MFS_OP_BT 3          /* u -> B^T u (pressure-sized output)                     */
+#define MFS_OP_MASS_P 4      /* p -> M_p p (pressure mass)                             */
+#define MFS_OP_NS_JACOBIAN 5 /* [du;dp] -> J [du;dp], SUPG/PSPG Jacobian (Sec. 5)      */
+
+typedef struct mfs_problem mfs_problem;
+
+typedef struct mfs_mesh {
+  int dim;                /* 2 or 3 */
+  int n[3];               /* cells per direction (n[2] ignored in 2D) */
+  const double *vertices; /* host, [(n0+1)(n1+1)(n2+1)][dim], x fastest */
+} mfs_mesh;
+
+typedef struct mfs_options {
+  int pressure_offset;   /* 1: Taylor-Hood Q_k/Q_{k-1}; 0: equal order Q_k/Q_k */
+  int mg_levels;         /* 1: multigrid hierarchy built at setup; 0: operators only */
+  int cheb_degree;       /* Chebyshev degree of the smoother (Sec. 3: 5) */
+  double cheb_range;     /* smoothing range: interval [lambda/range, lambda] */
+  double cheb_safety;    /* lambda = safety * estimated lambda_max(D^-1 A) */
+  int lanczos_steps;     /* steps of the lambda_max estimate */
+  int p_min;             /* lowest degree of the p-levels (1 by Sec. 3) */
+  int coarse_min_cells;  /* stop h-coarsening when a direction has <= this many cells */
+  int schur_iterations;  /* PCG iterations for S~^{-1} = nu M_p^{-1} */
+  int restart;           /* FGMRES restart length */
+  int maxit;             /* FGMRES iteration limit */
+  double rtol;           /* FGMRES relative residual target */
+  int precond_precision; /* MFS_FP32 or MFS_FP64 for the block preconditioner */
+  uint64_t seed;         /* seed of the Lanczos start vector */
+  /* Navier-Stokes linearisation (Sec. 5); used only by MFS_OP_NS_JACOBIAN */
+  double dt;             /* BDF2 time step; mass shift alpha = 3/(2 dt) */
+  int newton;            /* 1: Newton (full Gateaux derivative); 0: Oseen */
+} mfs_options;
+
+typedef struct mfs_solve_info {
+  int iterations;        /* outer FGMRES iterations performed */
+  int status;            /* MFS_OK or MFS_ENOCONV */
+  double rel_residual;   /* ||b - K x||_2 / ||b||_2 recomputed in FP64 at exit */
+  double seconds;        /* wall time of the solve on the host clock */
+} mfs_solve_info;
+
+/* Fill *opts with the defaults listed in the implementation. */
+void mfs_default_options(mfs_options *opts);
+
+/* Thread-local text of the last error. */
+const char *mfs_last_error(void);
+
+/*
+ * Device bytes mfs_setup will allocate for this mesh / degree / options
+ * (the footprint used for memory-based admission of requests).
+ * Host only; validates like mfs_setup.  MFS_EINVAL on bad sizes or degree.
+ */
+int mfs_footprint(const mfs_mesh *mesh, int k, const mfs_options *opts, size_t *bytes);
+
+/*
+ * setup(mesh, degrees, nu): copies the mesh to the device, checks det J > 0
+ * at every quadrature point (MFS_EINVAL with the cell id in mfs_last_error),
+ * builds the multigrid hierarchy (p-levels k -> p_min, then h-levels by
+ * halving n while every n is even and > coarse_min_cells; Sec. 3), the
+ * inverse diagonals, the Chebyshev bounds (Lanczos estimate, host readback),
+ * and the FP64 coarse-level inverse.  k in [1, 6] (Taylor-Hood: k >= 2).
+ * Returns a handle owned by the caller, released by mfs_destroy.  Runs on
+ * `stream` and synchronises it before returning.
+ */
+int mfs_setup(const mfs_mesh *mesh, int k, double nu, const mfs_options *opts, void *stream,
+              mfs_problem **out);
+int mfs_destroy(mfs_problem *p);
+
+/* Sizes at level `level` (0 = finest): scalar velocity nodes per component and
+ * pressure nodes (0 on levels without pressure). */
+int mfs_n_dofs(const mfs_problem *p, int level, int64_t *n_u, int64_t *n_p);
+int mfs_n_levels(const mfs_problem *p, int *n_levels);
+/* degree and cells per direction of a level */
+int mfs_level_info(const mfs_problem *p, int level, int *k, int *n);
+
+/* Physical coordinates of the scalar nodes of degree `deg` (host buffer of
+ * (deg n0 + 1)(deg n1 + 1)(..) x dim doubles). */
+int mfs_support_points(const mfs_problem *p, int deg, double *host_xyz);
+/* Physical coordinates of the Gauss points of every cell, [n_cells][(k+1)^dim][dim]
+ * in cell order and lexicographic point order (host buffer). */
+int mfs_quadrature_points(const mfs_problem *p, double *host_xyz);
+
+/*
+ * dst = op(src) on level `level` (0 = finest) in precision `prec`.
+ * Lengths: STOKES and NS_JACOBIAN: dim*n_u + n_p -> same; A: dim*n_u -> dim*n_u;
+ * B: n_p -> dim*n_u; BT: dim*n_u -> n_p; MASS_P: n_p -> n_p.
+ * STOKES, B, BT, MASS_P need a level with pressure (level 0).  Enqueue only.
+ */
+int mfs_vmult(mfs_problem *p, int op, int prec, int level, void *dst, const void *src, void *stream);
+
+/* dst = diag(A) on `level` for one velocity component (n_u entries; 1 on
+ * Dirichlet rows), FP64. */
+int mfs_diagonal(mfs_problem *p, int level, double *dst, void *stream);
+
+/* Chebyshev bound used by the smoother on `level` (after setup). */
+int mfs_get_lambda(const mfs_problem *p, int level, double *lambda_max);
+/* Override the Chebyshev bound on `level` (for parity checks with a fixed value). */
+int mfs_set_lambda(mfs_problem *p, int level, double lambda_max);
+
+/*
+ * dst = one multigrid V-cycle on the velocity block A applied to src
+ * (approximates A^{-1} src, Sec. 3), initial guess 0 on free rows and src on
+ * Dirichlet rows.  Vectors dim*n_u long in precision `prec`.  Enqueue only.
+ */
+int mfs_vcycle(mfs_problem *p, int prec, void *dst, const void *src, void *stream);
+
+/* Multigrid transfer between level `fine` and level fine+1 (Sec. 2
+ * eq. (transfer)): dst_fine += P src_coarse (prolongate) or
+ * dst_coarse = P^T src_fine (restrict).  Velocity vectors of the two levels. */
+int mfs_prolongate_add(mfs_problem *p, int prec, int fine, void *dst_fine, const void *src_coarse, void *stream);
+int mfs_restrict(mfs_problem *p, int prec, int fine, void *dst_coarse, const void *src_fine, void *stream);
+
+/*
+ * dst = P^{-1} src, the block-triangular preconditioner of eq. (stokes_block):
+ * y_p = -(nu^{-1} M_p)^{-1} r_p by `schur_iterations` Jacobi-PCG steps,
+ * y_u = Vcycle(r_u - B y_p).  Full-length vectors in precision `prec`.
+ */
+int mfs_precondition(mfs_problem *p, int prec, void *dst, const void *src, void *stream);
+
+/*
+ * Right-hand side of the constrained Stokes system: b_i = (f, phi_i) minus the
+ * unconstrained operator applied to the lifting on free rows, b_i = u_D on
+ * Dirichlet rows, pressure rows minus B^T of the lifting.
+ *   f_qp: device FP64 [n_cells][(k+1)^dim][dim] forcing at the Gauss points
+ *         (mfs_quadrature_points order);
+ *   u_dirichlet: device FP64 dim*n_u blocked velocity values at the support
+ *         points (only Dirichlet entries are read);
+ *   b: device FP64, full length.
+ */
+int mfs_rhs(mfs_problem *p, const double *f_qp, const double *u_dirichlet, double *b, void *stream);
+
+/*
+ * Solve K x = b by FGMRES(restart) with the block preconditioner in
+ * opts->precond_precision (FP32 preconditioner inside FP64 FGMRES, or all
+ * FP64), x0 = lifting of b's Dirichlet rows.  b, x: device FP64 full length.
+ * Host-synchronous (one readback per iteration).  The pressure is returned
+ * with zero mass-weighted mean.  MFS_ENOCONV if rtol is not reached within
+ * maxit (x holds the last iterate, info filled).
+ */
+int mfs_solve(mfs_problem *p, const double *b, double *x, const mfs_options *opts, mfs_solve_info *info,
+              void *stream);
+
+/*
+ * Resumable form of mfs_solve for a request loop that interleaves many
+ * problems: mfs_solve_begin enqueues the start of a solve on `stream`;
+ * mfs_solve_advance checks without blocking whether the last enqueued
+ * iteration has finished and, if so, reads its residual and enqueues the next
+ * one.  *done becomes 1 when the solve has converged or hit maxit (then
+ * info is filled and x holds the result).  Returns MFS_OK while progressing.
+ */
+int mfs_solve_begin(mfs_problem *p, const double *b, double *x, const mfs_options *opts, void *stream);
+int mfs_solve_advance(mfs_problem *p, int *done, mfs_solve_info *info);
+
+/* Navier-Stokes linearisation point (Sec. 5): u0 device FP64 dim*n_u nodal
+ * velocity (the pressure of the linearisation point is 0).  Stores u0 and
+ * refreshes the per-quadrature-point stabilisation parameter delta_1. */
+int mfs_set_linearization(mfs_problem *p, const double *u0, double dt, int newton, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -177,16 +177,18 @@ def stokes_operator(S: Space, nu: float):
     return constrain(mats["K"], S.velocity_dirichlet_mask()), mats
 
 
-def element_loop_stokes_vmult(S: Space, nu: float, x: np.ndarray, chunk: int = 4096) -> np.ndarray:
+def element_loop_stokes_vmult(S: Space, nu: float, x: np.ndarray, chunk: int = 4096, cells=None) -> np.ndarray:
     """Constrained Stokes matvec by an explicit loop over cells (chunks of
-    cells), each cell multiplying its dense element matrix."""
+    cells), each cell multiplying its dense element matrix.  With ``cells``
+    only those cells contribute (rows they do not fully cover are partial)."""
     mask = S.velocity_dirichlet_mask()
     xz = np.where(mask, 0.0, x)
     y = np.zeros_like(x)
     ul2g = velocity_l2g(S)
     nv = S.vdofs.shape[1]
-    for c0 in range(0, S.nc, chunk):
-        cells = np.arange(c0, min(S.nc, c0 + chunk))
+    all_cells = np.arange(S.nc) if cells is None else np.asarray(cells)
+    for c0 in range(0, len(all_cells), chunk):
+        cells = all_cells[c0:c0 + chunk]
         em = stokes_element_matrices(S, nu, cells)
         ug = ul2g[cells]
         pg = S.pdofs[cells] + S.dim * S.Nv
@@ -201,3 +203,38 @@ def element_loop_stokes_vmult(S: Space, nu: float, x: np.ndarray, chunk: int = 4
         np.add.at(y, pg.ravel(), yp.ravel())
     y[mask] = x[mask]
     return y
+
+
+def cells_containing(S: Space, rows: np.ndarray) -> np.ndarray:
+    """Cells whose local DoFs include the given rows of the blocked vector."""
+    out = set()
+    for r in np.asarray(rows):
+        if r < S.dim * S.Nv:
+            node, axes, deg = r % S.Nv, S.vaxes, S.k
+        else:
+            node, axes, deg = r - S.dim * S.Nv, S.paxes, S.kp
+        g = []
+        for a in range(S.dim):
+            g.append(node % axes[a])
+            node //= axes[a]
+        per_dir = []
+        for a in range(S.dim):
+            c = g[a] // deg
+            opts = [v for v in (c, c - 1 if g[a] % deg == 0 else None) if v is not None and 0 <= v < S.n[a]]
+            per_dir.append(opts)
+        for combo in np.array(np.meshgrid(*per_dir, indexing="ij")).reshape(S.dim, -1).T:
+            cid = 0
+            for a in reversed(range(S.dim)):
+                cid = cid * S.n[a] + combo[a]
+            out.add(int(cid))
+    return np.array(sorted(out), dtype=np.int64)
+
+
+def sampled_stokes_rows(S: Space, nu: float, x: np.ndarray, rows: np.ndarray) -> np.ndarray:
+    """(K x)_i of the constrained Stokes operator for the given rows, from the
+    element matrices of the cells containing them."""
+    cells = cells_containing(S, rows)
+    y = element_loop_stokes_vmult(S, nu, x, cells=cells)
+    mask = S.velocity_dirichlet_mask()
+    y[mask] = x[mask]
+    return y[np.asarray(rows)]

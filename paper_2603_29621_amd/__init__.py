@@ -1,0 +1,307 @@
+"""Python binding of the mfstokes HIP library (argument marshalling only).
+
+Every function here forwards to the ``extern "C"`` entry point of the same
+name in ``libmfstokes.so`` (declared in ``include/mfstokes.h``).  Device
+vectors are torch CUDA tensors; their ``data_ptr()`` and the current HIP
+stream are passed through.  There is no CPU fallback: importing works without
+a GPU, but every call that computes needs the built library and a device.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmfstokes.so")
+
+MFS_OK = 0
+MFS_EINVAL = -1
+MFS_ENOMEM = -2
+MFS_EUNSUPPORTED = -3
+MFS_EHIP = -4
+MFS_ENOCONV = -5
+MFS_FP64 = 0
+MFS_FP32 = 1
+MFS_OP_STOKES = 0
+MFS_OP_A = 1
+MFS_OP_B = 2
+MFS_OP_BT = 3
+MFS_OP_MASS_P = 4
+MFS_OP_NS_JACOBIAN = 5
+
+EXPORTED = [
+    "mfs_default_options", "mfs_last_error", "mfs_footprint", "mfs_setup", "mfs_destroy", "mfs_n_dofs",
+    "mfs_n_levels", "mfs_level_info", "mfs_support_points", "mfs_quadrature_points", "mfs_vmult",
+    "mfs_diagonal", "mfs_get_lambda", "mfs_set_lambda", "mfs_vcycle", "mfs_prolongate_add", "mfs_restrict",
+    "mfs_precondition", "mfs_rhs", "mfs_solve", "mfs_solve_begin", "mfs_solve_advance",
+    "mfs_set_linearization",
+]
+
+
+class MfsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"mfstokes error {code}: {msg}")
+        self.code = code
+
+
+class mfs_mesh(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 3), ("vertices", ctypes.POINTER(ctypes.c_double))]
+
+
+class mfs_options(ctypes.Structure):
+    _fields_ = [
+        ("pressure_offset", ctypes.c_int),
+        ("mg_levels", ctypes.c_int),
+        ("cheb_degree", ctypes.c_int),
+        ("cheb_range", ctypes.c_double),
+        ("cheb_safety", ctypes.c_double),
+        ("lanczos_steps", ctypes.c_int),
+        ("p_min", ctypes.c_int),
+        ("coarse_min_cells", ctypes.c_int),
+        ("schur_iterations", ctypes.c_int),
+        ("restart", ctypes.c_int),
+        ("maxit", ctypes.c_int),
+        ("rtol", ctypes.c_double),
+        ("precond_precision", ctypes.c_int),
+        ("seed", ctypes.c_uint64),
+        ("dt", ctypes.c_double),
+        ("newton", ctypes.c_int),
+    ]
+
+
+class mfs_solve_info(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("status", ctypes.c_int), ("rel_residual", ctypes.c_double),
+                ("seconds", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load the built library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run `python -m paper_2603_29621_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64p = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)
+        L.mfs_last_error.restype = ctypes.c_char_p
+        L.mfs_default_options.argtypes = [ctypes.POINTER(mfs_options)]
+        L.mfs_default_options.restype = None
+        L.mfs_footprint.argtypes = [ctypes.POINTER(mfs_mesh), ctypes.c_int, ctypes.POINTER(mfs_options),
+                                    ctypes.POINTER(ctypes.c_size_t)]
+        L.mfs_setup.argtypes = [ctypes.POINTER(mfs_mesh), ctypes.c_int, ctypes.c_double, ctypes.POINTER(mfs_options),
+                                vp, ctypes.POINTER(vp)]
+        L.mfs_destroy.argtypes = [vp]
+        L.mfs_n_dofs.argtypes = [vp, ctypes.c_int, i64p, i64p]
+        L.mfs_n_levels.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
+        L.mfs_level_info.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+        L.mfs_support_points.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+        L.mfs_quadrature_points.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+        L.mfs_vmult.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp]
+        L.mfs_diagonal.argtypes = [vp, ctypes.c_int, vp, vp]
+        L.mfs_get_lambda.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+        L.mfs_set_lambda.argtypes = [vp, ctypes.c_int, ctypes.c_double]
+        L.mfs_vcycle.argtypes = [vp, ctypes.c_int, vp, vp, vp]
+        L.mfs_prolongate_add.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, vp]
+        L.mfs_restrict.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, vp]
+        L.mfs_precondition.argtypes = [vp, ctypes.c_int, vp, vp, vp]
+        L.mfs_rhs.argtypes = [vp, vp, vp, vp, vp]
+        L.mfs_solve.argtypes = [vp, vp, vp, ctypes.POINTER(mfs_options), ctypes.POINTER(mfs_solve_info), vp]
+        L.mfs_solve_begin.argtypes = [vp, vp, vp, ctypes.POINTER(mfs_options), vp]
+        L.mfs_solve_advance.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(mfs_solve_info)]
+        L.mfs_set_linearization.argtypes = [vp, vp, ctypes.c_double, ctypes.c_int, vp]
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != MFS_OK:
+        raise MfsError(rc, lib().mfs_last_error().decode())
+
+
+def _stream(stream=None):
+    if stream is not None:
+        return ctypes.c_void_p(stream)
+    import torch
+
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    if t is None:
+        return ctypes.c_void_p(0)
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor expected")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def mfs_default_options(**overrides) -> mfs_options:
+    o = mfs_options()
+    lib().mfs_default_options(ctypes.byref(o))
+    for k, v in overrides.items():
+        setattr(o, k, v)
+    return o
+
+
+def _mesh(dim, n, vertices):
+    V = np.ascontiguousarray(vertices, dtype=np.float64)
+    m = mfs_mesh()
+    m.dim = dim
+    nn = list(n) + [1] * (3 - len(n))
+    for a in range(3):
+        m.n[a] = int(nn[a])
+    m.vertices = V.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    return m, V
+
+
+def mfs_footprint(dim, n, vertices, k, opts=None) -> int:
+    m, _keep = _mesh(dim, n, vertices)
+    b = ctypes.c_size_t(0)
+    _check(lib().mfs_footprint(ctypes.byref(m), k, ctypes.byref(opts) if opts else None, ctypes.byref(b)))
+    return b.value
+
+
+def mfs_setup(dim, n, vertices, k, nu, opts=None, stream=None) -> ctypes.c_void_p:
+    m, _keep = _mesh(dim, n, vertices)
+    h = ctypes.c_void_p(0)
+    _check(lib().mfs_setup(ctypes.byref(m), int(k), float(nu), ctypes.byref(opts) if opts else None,
+                           _stream(stream), ctypes.byref(h)))
+    return h
+
+
+def mfs_destroy(h):
+    _check(lib().mfs_destroy(h))
+
+
+def mfs_n_dofs(h, level=0):
+    nu, np_ = ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(lib().mfs_n_dofs(h, level, ctypes.byref(nu), ctypes.byref(np_)))
+    return nu.value, np_.value
+
+
+def mfs_n_levels(h):
+    n = ctypes.c_int(0)
+    _check(lib().mfs_n_levels(h, ctypes.byref(n)))
+    return n.value
+
+
+def mfs_level_info(h, level):
+    k = ctypes.c_int(0)
+    n = (ctypes.c_int * 3)()
+    _check(lib().mfs_level_info(h, level, ctypes.byref(k), n))
+    return k.value, list(n)
+
+
+def mfs_support_points(h, deg, count, dim):
+    out = np.zeros((count, dim))
+    _check(lib().mfs_support_points(h, deg, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return out
+
+
+def mfs_quadrature_points(h, n_cells, n_q, dim):
+    out = np.zeros((n_cells, n_q, dim))
+    _check(lib().mfs_quadrature_points(h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return out
+
+
+def mfs_vmult(h, op, prec, level, dst, src, stream=None):
+    _check(lib().mfs_vmult(h, op, prec, level, _ptr(dst), _ptr(src), _stream(stream)))
+
+
+def mfs_diagonal(h, level, dst, stream=None):
+    _check(lib().mfs_diagonal(h, level, _ptr(dst), _stream(stream)))
+
+
+def mfs_get_lambda(h, level):
+    v = ctypes.c_double(0)
+    _check(lib().mfs_get_lambda(h, level, ctypes.byref(v)))
+    return v.value
+
+
+def mfs_set_lambda(h, level, value):
+    _check(lib().mfs_set_lambda(h, level, float(value)))
+
+
+def mfs_vcycle(h, prec, dst, src, stream=None):
+    _check(lib().mfs_vcycle(h, prec, _ptr(dst), _ptr(src), _stream(stream)))
+
+
+def mfs_prolongate_add(h, prec, fine, dst, src, stream=None):
+    _check(lib().mfs_prolongate_add(h, prec, fine, _ptr(dst), _ptr(src), _stream(stream)))
+
+
+def mfs_restrict(h, prec, fine, dst, src, stream=None):
+    _check(lib().mfs_restrict(h, prec, fine, _ptr(dst), _ptr(src), _stream(stream)))
+
+
+def mfs_precondition(h, prec, dst, src, stream=None):
+    _check(lib().mfs_precondition(h, prec, _ptr(dst), _ptr(src), _stream(stream)))
+
+
+def mfs_rhs(h, f_qp, u_dirichlet, b, stream=None):
+    _check(lib().mfs_rhs(h, _ptr(f_qp), _ptr(u_dirichlet), _ptr(b), _stream(stream)))
+
+
+def mfs_solve(h, b, x, opts=None, stream=None) -> mfs_solve_info:
+    info = mfs_solve_info()
+    rc = lib().mfs_solve(h, _ptr(b), _ptr(x), ctypes.byref(opts) if opts else None, ctypes.byref(info),
+                         _stream(stream))
+    if rc not in (MFS_OK, MFS_ENOCONV):
+        _check(rc)
+    return info
+
+
+def mfs_solve_begin(h, b, x, opts=None, stream=None):
+    _check(lib().mfs_solve_begin(h, _ptr(b), _ptr(x), ctypes.byref(opts) if opts else None, _stream(stream)))
+
+
+def mfs_solve_advance(h):
+    done = ctypes.c_int(0)
+    info = mfs_solve_info()
+    _check(lib().mfs_solve_advance(h, ctypes.byref(done), ctypes.byref(info)))
+    return bool(done.value), info
+
+
+def mfs_set_linearization(h, u0, dt, newton, stream=None):
+    _check(lib().mfs_set_linearization(h, _ptr(u0), float(dt), int(newton), _stream(stream)))
+
+
+@dataclass
+class Problem:
+    """Convenience owner of a problem handle (sizes cached from the library)."""
+
+    handle: ctypes.c_void_p
+    dim: int
+    n: tuple
+    k: int
+    nu: float
+
+    @classmethod
+    def setup(cls, dim, n, vertices, k, nu, opts=None, stream=None):
+        h = mfs_setup(dim, n, vertices, k, nu, opts, stream)
+        return cls(h, dim, tuple(n), k, nu)
+
+    def sizes(self, level=0):
+        return mfs_n_dofs(self.handle, level)
+
+    @property
+    def n_dofs(self):
+        nu, np_ = self.sizes(0)
+        return self.dim * nu + np_
+
+    def close(self):
+        if self.handle:
+            mfs_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,1188 @@
+// Host runtime and C ABI of the mfstokes library: problem setup (levels,
+// geometry, tables, diagonals, Chebyshev bounds, coarse inverse), operator
+// application, the multigrid V-cycle, the block preconditioner and FGMRES as
+// a resumable state machine.
+//
+// Methods: Sec. 3 eq. (stokes_block) (block-triangular preconditioner with
+// S ~ nu^{-1} M_p inverted by Jacobi-PCG, A^{-1} ~ one V-cycle, FGMRES), Sec. 2
+// eq. (transfer) and Sec. 3 (p-levels down to p_min, then global-coarsening
+// h-levels, Chebyshev around point Jacobi, direct coarse solve).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <memory>
+#include <vector>
+
+#include "internal.h"
+
+using namespace mfs;
+
+namespace {
+
+// ------------------------------------------------------------- arena plan
+struct Arena {
+  size_t off = 0;
+  char *base = nullptr;
+  bool dry = true;
+  template <typename T>
+  T *take(int64_t n) {
+    off = (off + 255) & ~size_t(255);
+    T *p = dry ? nullptr : reinterpret_cast<T *>(base + off);
+    off += (size_t)std::max<int64_t>(n, 0) * sizeof(T);
+    return p;
+  }
+};
+
+template <typename T>
+struct PrecWork {
+  // multigrid level vectors: x, b, r, d (velocity, dim*Nv each)
+  std::vector<T *> x, b, r, d;
+  T *invdiag_first = nullptr;
+  // block preconditioner / Schur PCG
+  T *t_u = nullptr;                                    // velocity temporary
+  T *pres = nullptr, *ps = nullptr, *pp = nullptr, *pq = nullptr, *pz = nullptr;  // PCG vectors (Np)
+  T *pinv = nullptr;                                   // 1/diag(M_p)
+  T *full_in = nullptr, *full_out = nullptr;           // cast buffers for the mixed preconditioner
+};
+
+struct Level {
+  LevelGeom g{};
+  double *X64 = nullptr;
+  float *X32 = nullptr;
+  double *tab64 = nullptr;
+  float *tab32 = nullptr;
+  double *diag = nullptr;
+  double *invdiag64 = nullptr;
+  float *invdiag32 = nullptr;
+  double lambda = 0.0;          // upper end of the Chebyshev interval
+  bool h_to_coarser = false;    // transfer type to level+1
+  std::vector<double> emb;      // 1D embedding to level+1
+  std::vector<double> Xhost;    // vertices (host copy)
+};
+
+struct Krylov {
+  int m = 30;
+  double *V = nullptr, *Z = nullptr, *w = nullptr;
+  double *dev = nullptr;     // device scalars: h[32], h2[32], nrm2, misc
+  double *host = nullptr;    // pinned readback
+  double *ydev = nullptr;    // device copy of the GMRES coefficients
+  double *yhost = nullptr;   // pinned
+  hipEvent_t ev = nullptr;
+  // state
+  int state = 0;  // 0 idle, 1 wait initial residual, 2 wait Arnoldi step, 3 wait final check, 4 done
+  int j = 0, iters = 0, maxit = 0, prec = MFS_FP32;
+  double rtol = 1e-8, bnorm = 0, beta = 0;
+  std::vector<double> H, cs, sn, gv;
+  const double *b = nullptr;
+  double *x = nullptr;
+  hipStream_t s = nullptr;
+  std::chrono::steady_clock::time_point t0;
+  mfs_solve_info info{};
+  bool final_pending = false;
+};
+
+}  // namespace
+
+struct mfs_problem {
+  int dim = 3;
+  double nu = 1.0;
+  mfs_options opts{};
+  std::vector<Level> L;
+  int nlev = 0;
+  double *coarse_inv = nullptr;
+  int coarse_n = 0;
+  PrecWork<double> w64;
+  PrecWork<float> w32;
+  double *m1 = nullptr;         // M_p 1 (pressure mean)
+  double *scal = nullptr;       // device scalars for PCG / means
+  double *partials = nullptr;   // reduction scratch
+  double *tmp_full = nullptr;   // FP64 full-length temporary
+  Krylov kr;
+  char *arena = nullptr;
+  size_t arena_bytes = 0;
+  hipStream_t stream = nullptr;
+};
+
+namespace {
+
+constexpr int PCG_MAX = 64;  // scalar slots per PCG run (rho[i], pq[i])
+
+hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+int64_t ipow(int64_t b, int e) {
+  int64_t r = 1;
+  while (e--) r *= b;
+  return r;
+}
+
+LevelGeom make_geom(int dim, const int n[3], int k, int kp) {
+  LevelGeom g{};
+  g.dim = dim;
+  g.k = k;
+  g.kp = kp;
+  g.ncells = 1;
+  g.Nv = 1;
+  g.Np = kp > 0 ? 1 : 0;
+  for (int a = 0; a < 3; ++a) {
+    g.n[a] = a < dim ? n[a] : 1;
+    g.nv[a] = a < dim ? k * n[a] + 1 : 1;
+    g.np[a] = (a < dim && kp > 0) ? kp * n[a] + 1 : 1;
+    g.ncells *= g.n[a];
+    g.Nv *= g.nv[a];
+    if (kp > 0) g.Np *= g.np[a];
+  }
+  return g;
+}
+
+int64_t n_vertices(const LevelGeom &g) {
+  int64_t v = 1;
+  for (int a = 0; a < g.dim; ++a) v *= g.n[a] + 1;
+  return v;
+}
+
+// level hierarchy: p-levels then h-levels (Sec. 3)
+std::vector<LevelGeom> plan_levels(int dim, const int n[3], int k, int kp, const mfs_options &o) {
+  std::vector<LevelGeom> out;
+  out.push_back(make_geom(dim, n, k, kp));
+  if (!o.mg_levels) return out;
+  int nn[3] = {n[0], n[1], dim == 3 ? n[2] : 1};
+  int kk = k;
+  const int pmin = std::max(1, o.p_min);
+  while (kk > pmin) {
+    --kk;
+    out.push_back(make_geom(dim, nn, kk, 0));
+  }
+  while (true) {
+    bool ok = true;
+    for (int a = 0; a < dim; ++a) ok = ok && (nn[a] % 2 == 0) && (nn[a] > std::max(1, o.coarse_min_cells));
+    if (!ok) break;
+    for (int a = 0; a < dim; ++a) nn[a] /= 2;
+    out.push_back(make_geom(dim, nn, kk, 0));
+  }
+  return out;
+}
+
+template <typename T>
+void plan_prec_work(Arena &A, PrecWork<T> &w, const std::vector<LevelGeom> &G, int dim, bool full) {
+  const int64_t Np = G[0].Np;
+  w.pz = A.take<T>(Np);
+  w.pinv = A.take<T>(Np);
+  if (!full) return;
+  const size_t nl = G.size();
+  w.x.assign(nl, nullptr);
+  w.b.assign(nl, nullptr);
+  w.r.assign(nl, nullptr);
+  w.d.assign(nl, nullptr);
+  for (size_t l = 0; l < nl; ++l) {
+    const int64_t nu = dim * G[l].Nv;
+    w.x[l] = A.take<T>(nu);
+    w.b[l] = A.take<T>(nu);
+    w.r[l] = A.take<T>(nu);
+    w.d[l] = A.take<T>(nu);
+  }
+  const int64_t ntot = dim * G[0].Nv + Np;
+  w.t_u = A.take<T>(dim * G[0].Nv);
+  w.pres = A.take<T>(Np);
+  w.ps = A.take<T>(Np);
+  w.pp = A.take<T>(Np);
+  w.pq = A.take<T>(Np);
+  w.full_in = A.take<T>(ntot);
+  w.full_out = A.take<T>(ntot);
+}
+
+// The whole device footprint, carved from one allocation.
+void plan_arena(Arena &A, mfs_problem &P, const std::vector<LevelGeom> &G) {
+  P.L.resize(G.size());
+  for (size_t l = 0; l < G.size(); ++l) {
+    Level &L = P.L[l];
+    L.g = G[l];
+    const int64_t nvert = n_vertices(G[l]);
+    L.X64 = A.take<double>(nvert * P.dim);
+    L.X32 = A.take<float>(nvert * P.dim);
+    L.tab64 = A.take<double>(TAB_SIZE);
+    L.tab32 = A.take<float>(TAB_SIZE);
+    L.diag = A.take<double>(G[l].Nv);
+    L.invdiag64 = A.take<double>(G[l].Nv);
+    L.invdiag32 = A.take<float>(G[l].Nv);
+  }
+  const bool full = P.opts.mg_levels != 0;
+  plan_prec_work(A, P.w64, G, P.dim, full);
+  plan_prec_work(A, P.w32, G, P.dim, full);
+  const LevelGeom &c = G.back();
+  P.coarse_n = full ? (int)(P.dim * c.Nv) : 0;
+  P.coarse_inv = A.take<double>((int64_t)P.coarse_n * P.coarse_n);
+  const int64_t ntot = P.dim * G[0].Nv + G[0].Np;
+  P.m1 = A.take<double>(std::max<int64_t>(G[0].Np, 1));
+  P.scal = A.take<double>(4 * PCG_MAX + 64);
+  P.partials = A.take<double>(32 * DOT_BLOCKS);
+  P.tmp_full = A.take<double>(ntot);
+  Krylov &K = P.kr;
+  K.m = std::max(1, std::min(P.opts.restart, 30));
+  const int64_t nk = full ? ntot : 0;  // Krylov space only when the solver is available
+  K.V = A.take<double>((K.m + 1) * nk);
+  K.Z = A.take<double>(K.m * nk);
+  K.w = A.take<double>(nk);
+  K.dev = A.take<double>(128);
+  K.ydev = A.take<double>(64);
+}
+
+void check_options(const mfs_options &o) {
+  MFS_REQUIRE(o.cheb_degree >= 1 && o.cheb_degree <= 32, MFS_EINVAL, "cheb_degree %d out of range", o.cheb_degree);
+  MFS_REQUIRE(o.cheb_range > 1.0, MFS_EINVAL, "cheb_range must exceed 1");
+  MFS_REQUIRE(o.restart >= 1 && o.restart <= 30, MFS_EINVAL, "restart must be in [1, 30]");
+  MFS_REQUIRE(o.schur_iterations >= 0 && o.schur_iterations < PCG_MAX, MFS_EINVAL, "schur_iterations out of range");
+  MFS_REQUIRE(o.precond_precision == MFS_FP32 || o.precond_precision == MFS_FP64, MFS_EINVAL,
+              "precond_precision must be MFS_FP32 or MFS_FP64");
+}
+
+void check_mesh(const mfs_mesh *mesh, int k, const mfs_options &o) {
+  MFS_REQUIRE(mesh != nullptr, MFS_EINVAL, "mesh is NULL");
+  MFS_REQUIRE(mesh->dim == 2 || mesh->dim == 3, MFS_EINVAL, "dim must be 2 or 3 (got %d)", mesh->dim);
+  for (int a = 0; a < mesh->dim; ++a) MFS_REQUIRE(mesh->n[a] >= 1, MFS_EINVAL, "n[%d] must be >= 1", a);
+  MFS_REQUIRE(k >= 1 && k <= 6, MFS_EINVAL, "degree k=%d out of range [1, 6]", k);
+  if (o.pressure_offset == 1) MFS_REQUIRE(k >= 2, MFS_EINVAL, "Taylor-Hood needs k >= 2");
+  MFS_REQUIRE(o.pressure_offset == 0 || o.pressure_offset == 1, MFS_EINVAL, "pressure_offset must be 0 or 1");
+  int64_t nodes = 1;
+  for (int a = 0; a < mesh->dim; ++a) nodes *= (int64_t)k * mesh->n[a] + 1;
+  MFS_REQUIRE(nodes < (1LL << 31) / mesh->dim, MFS_EINVAL, "mesh too large for 32-bit node grid");
+}
+
+void release(mfs_problem *P) {
+  if (!P) return;
+  if (P->kr.ev) (void)hipEventDestroy(P->kr.ev);
+  if (P->kr.host) (void)hipHostFree(P->kr.host);
+  if (P->kr.yhost) (void)hipHostFree(P->kr.yhost);
+  if (P->arena) (void)hipFree(P->arena);
+  delete P;
+}
+
+template <typename T>
+DevLevel<T> dev(const Level &L);
+template <>
+DevLevel<double> dev<double>(const Level &L) {
+  DevLevel<double> d;
+  d.X = L.X64;
+  d.tab = L.tab64;
+  d.invdiag = L.invdiag64;
+  return d;
+}
+template <>
+DevLevel<float> dev<float>(const Level &L) {
+  DevLevel<float> d;
+  d.X = L.X32;
+  d.tab = L.tab32;
+  d.invdiag = L.invdiag32;
+  return d;
+}
+template <typename T>
+PrecWork<T> &work(mfs_problem &P);
+template <>
+PrecWork<double> &work<double>(mfs_problem &P) {
+  return P.w64;
+}
+template <>
+PrecWork<float> &work<float>(mfs_problem &P) {
+  return P.w32;
+}
+template <typename T>
+const T *invdiag(const Level &L);
+template <>
+const double *invdiag<double>(const Level &L) {
+  return L.invdiag64;
+}
+template <>
+const float *invdiag<float>(const Level &L) {
+  return L.invdiag32;
+}
+
+// ---------------------------------------------------------------- operators
+// velocity-block A on level l: dst = A src (dim*Nv); Dirichlet rows dst = src
+template <typename T>
+void apply_A(mfs_problem &P, int l, T *dst, const T *src, hipStream_t s) {
+  const Level &L = P.L[l];
+  launch_fill_dirichlet<T>(L.g, dst, src, s);
+  launch_cell_op<T>(L.g, dev<T>(L), M_LAPLACE, (T)P.nu, dst, nullptr, src, nullptr, s);
+}
+
+template <typename T>
+void apply_op(mfs_problem &P, int op, int l, T *dst, const T *src, hipStream_t s) {
+  const Level &L = P.L[l];
+  const LevelGeom &g = L.g;
+  const int64_t nu = g.dim * g.Nv;
+  switch (op) {
+    case MFS_OP_A:
+      apply_A<T>(P, l, dst, src, s);
+      break;
+    case MFS_OP_STOKES:
+      MFS_REQUIRE(g.kp > 0, MFS_EINVAL, "level %d has no pressure space", l);
+      launch_fill_dirichlet<T>(g, dst, src, s);
+      vec_fill<T>(dst + nu, T(0), g.Np, s);
+      launch_cell_op<T>(g, dev<T>(L), M_LAPLACE | M_GRADP | M_DIVU, (T)P.nu, dst, dst + nu, src, src + nu, s);
+      break;
+    case MFS_OP_B:
+      MFS_REQUIRE(g.kp > 0, MFS_EINVAL, "level %d has no pressure space", l);
+      launch_fill_dirichlet<T>(g, dst, (const T *)nullptr, s);
+      launch_cell_op<T>(g, dev<T>(L), M_GRADP, (T)P.nu, dst, nullptr, nullptr, src, s);
+      break;
+    case MFS_OP_BT:
+      MFS_REQUIRE(g.kp > 0, MFS_EINVAL, "level %d has no pressure space", l);
+      vec_fill<T>(dst, T(0), g.Np, s);
+      launch_cell_op<T>(g, dev<T>(L), M_DIVU, (T)P.nu, nullptr, dst, src, nullptr, s);
+      break;
+    case MFS_OP_MASS_P:
+      MFS_REQUIRE(g.kp > 0, MFS_EINVAL, "level %d has no pressure space", l);
+      vec_fill<T>(dst, T(0), g.Np, s);
+      launch_cell_op<T>(g, dev<T>(L), M_MASSP, (T)P.nu, nullptr, dst, nullptr, src, s);
+      break;
+    default:
+      MFS_REQUIRE(false, MFS_EUNSUPPORTED, "operator %d not available", op);
+  }
+}
+
+// ---------------------------------------------------------------- setup pieces
+void sturm_max_eig(const std::vector<double> &d, const std::vector<double> &e, double &lmax) {
+  // largest eigenvalue of the symmetric tridiagonal (d, e) by bisection
+  const int n = (int)d.size();
+  double lo = 1e300, hi = -1e300;
+  for (int i = 0; i < n; ++i) {
+    const double r = (i > 0 ? std::fabs(e[i - 1]) : 0) + (i < n - 1 ? std::fabs(e[i]) : 0);
+    lo = std::min(lo, d[i] - r);
+    hi = std::max(hi, d[i] + r);
+  }
+  auto count_below = [&](double x) {
+    int c = 0;
+    double q = d[0] - x;
+    if (q < 0) ++c;
+    for (int i = 1; i < n; ++i) {
+      const double qq = q == 0 ? 1e-300 : q;
+      q = d[i] - x - e[i - 1] * e[i - 1] / qq;
+      if (q < 0) ++c;
+    }
+    return c;
+  };
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (count_below(mid) >= n)
+      hi = mid;
+    else
+      lo = mid;
+  }
+  lmax = hi;
+}
+
+uint64_t splitmix64(uint64_t &x) {
+  uint64_t z = (x += 0x9e3779b97f4a7c15ULL);
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+  return z ^ (z >> 31);
+}
+
+// lambda_max(D^{-1} A) on level l by CG-Lanczos (FP64, host-synchronous)
+double estimate_lambda(mfs_problem &P, int l, hipStream_t s) {
+  Level &L = P.L[l];
+  const int64_t n = P.dim * L.g.Nv;
+  double *r = P.w64.x[l], *z = P.w64.b[l], *p = P.w64.r[l], *q = P.w64.d[l];
+  std::vector<double> h(n);
+  uint64_t st = P.opts.seed * 1000003ULL + (uint64_t)l;
+  for (int64_t i = 0; i < n; ++i) h[i] = (double)(splitmix64(st) >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+  MFS_HIP(hipMemcpyAsync(r, h.data(), n * sizeof(double), hipMemcpyHostToDevice, s));
+  vec_zero_mask_boundary<double>(L.g, r, s);
+  double *dv = P.scal + 4 * PCG_MAX;
+  auto dot = [&](const double *a, const double *b) {
+    multi_dot<double>(a, 0, 1, b, n, dv, P.partials, s);
+    double v;
+    MFS_HIP(hipMemcpyAsync(&v, dv, sizeof(double), hipMemcpyDeviceToHost, s));
+    MFS_HIP(hipStreamSynchronize(s));
+    return v;
+  };
+  vec_diag_scale<double>(L.g, z, L.invdiag64, r, s);
+  vec_copy<double>(p, z, n, s);
+  double rz = dot(r, z);
+  std::vector<double> alpha, beta;
+  const int steps = std::max(2, P.opts.lanczos_steps);
+  for (int j = 0; j < steps && rz > 0; ++j) {
+    apply_A<double>(P, l, q, p, s);
+    vec_zero_mask_boundary<double>(L.g, q, s);
+    const double pq = dot(p, q);
+    if (!(pq > 0)) break;
+    const double a = rz / pq;
+    vec_axpby<double>(r, -a, q, 1.0, n, s);
+    vec_diag_scale<double>(L.g, z, L.invdiag64, r, s);
+    const double rz2 = dot(r, z);
+    const double b = rz2 / rz;
+    vec_axpby<double>(p, 1.0, z, b, n, s);
+    alpha.push_back(a);
+    beta.push_back(b);
+    rz = rz2;
+    if (rz2 <= 1e-30 * rz) break;
+  }
+  const int m = (int)alpha.size();
+  MFS_REQUIRE(m > 0, MFS_EINVAL, "Lanczos estimate failed on level %d", l);
+  std::vector<double> d(m), e(std::max(m - 1, 1), 0.0);
+  for (int j = 0; j < m; ++j) {
+    d[j] = 1.0 / alpha[j] + (j > 0 ? beta[j - 1] / alpha[j - 1] : 0.0);
+    if (j < m - 1) e[j] = std::sqrt(beta[j]) / alpha[j];
+  }
+  double lmax;
+  sturm_max_eig(d, e, lmax);
+  return lmax;
+}
+
+void setup_coarse(mfs_problem &P, hipStream_t s) {
+  const int l = P.nlev - 1;
+  const Level &L = P.L[l];
+  const int n = P.coarse_n;
+  // columns of the constrained coarse A by applying it to unit vectors
+  double *e = P.w64.x[l], *col = P.w64.b[l];
+  std::vector<double> A((size_t)n * n);
+  for (int j = 0; j < n; ++j) {
+    vec_fill<double>(e, 0.0, n, s);
+    const double one = 1.0;
+    MFS_HIP(hipMemcpyAsync(e + j, &one, sizeof(double), hipMemcpyHostToDevice, s));
+    apply_A<double>(P, l, col, e, s);
+    MFS_HIP(hipMemcpyAsync(A.data() + (size_t)j * n, col, n * sizeof(double), hipMemcpyDeviceToHost, s));
+    MFS_HIP(hipStreamSynchronize(s));
+  }
+  // symmetrise (equal up to rounding), Cholesky, explicit inverse
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < i; ++j) A[(size_t)i * n + j] = A[(size_t)j * n + i] = 0.5 * (A[(size_t)i * n + j] + A[(size_t)j * n + i]);
+  std::vector<double> Lc((size_t)n * n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    double sdiag = A[(size_t)j * n + j];
+    for (int k = 0; k < j; ++k) sdiag -= Lc[(size_t)j * n + k] * Lc[(size_t)j * n + k];
+    MFS_REQUIRE(sdiag > 0, MFS_EINVAL, "coarse matrix not positive definite");
+    const double ljj = std::sqrt(sdiag);
+    Lc[(size_t)j * n + j] = ljj;
+    for (int i = j + 1; i < n; ++i) {
+      double v = A[(size_t)i * n + j];
+      for (int k = 0; k < j; ++k) v -= Lc[(size_t)i * n + k] * Lc[(size_t)j * n + k];
+      Lc[(size_t)i * n + j] = v / ljj;
+    }
+  }
+  std::vector<double> inv((size_t)n * n, 0.0);
+  std::vector<double> y(n);
+  for (int c = 0; c < n; ++c) {
+    for (int i = 0; i < n; ++i) {
+      double v = i == c ? 1.0 : 0.0;
+      for (int k = 0; k < i; ++k) v -= Lc[(size_t)i * n + k] * y[k];
+      y[i] = v / Lc[(size_t)i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double v = y[i];
+      for (int k = i + 1; k < n; ++k) v -= Lc[(size_t)k * n + i] * inv[(size_t)c * n + k];
+      inv[(size_t)c * n + i] = v / Lc[(size_t)i * n + i];
+    }
+  }
+  MFS_HIP(hipMemcpyAsync(P.coarse_inv, inv.data(), inv.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  MFS_HIP(hipStreamSynchronize(s));
+}
+
+// ---------------------------------------------------------------- V-cycle
+template <typename T>
+void chebyshev(mfs_problem &P, int l, T *x, const T *b, bool zero_start, hipStream_t s) {
+  Level &L = P.L[l];
+  PrecWork<T> &W = work<T>(P);
+  const double lmax = L.lambda, lmin = lmax / P.opts.cheb_range;
+  const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
+  const double sigma = theta / delta;
+  double rho_old = 1.0 / sigma;
+  T *Ax = W.r[l], *d = W.d[l];
+  if (zero_start) {
+    cheb_update<T>(L.g, x, d, b, nullptr, invdiag<T>(L), T(0), (T)(1.0 / theta), true, s);
+  } else {
+    apply_A<T>(P, l, Ax, x, s);
+    cheb_update<T>(L.g, x, d, b, Ax, invdiag<T>(L), T(0), (T)(1.0 / theta), true, s);
+  }
+  for (int it = 1; it < P.opts.cheb_degree; ++it) {
+    const double rho = 1.0 / (2.0 * sigma - rho_old);
+    apply_A<T>(P, l, Ax, x, s);
+    cheb_update<T>(L.g, x, d, b, Ax, invdiag<T>(L), (T)(rho * rho_old), (T)(2.0 * rho / delta), false, s);
+    rho_old = rho;
+  }
+}
+
+template <typename T>
+void vcycle_level(mfs_problem &P, int l, T *x, const T *b, hipStream_t s) {
+  PrecWork<T> &W = work<T>(P);
+  Level &L = P.L[l];
+  if (l == P.nlev - 1) {
+    dense_apply<T>(P.coarse_inv, P.coarse_n, b, x, s);
+    return;
+  }
+  const int64_t n = P.dim * L.g.Nv;
+  launch_fill_dirichlet<T>(L.g, x, b, s);  // x = b on Dirichlet rows, 0 elsewhere
+  chebyshev<T>(P, l, x, b, true, s);
+  T *r = W.r[l];
+  apply_A<T>(P, l, r, x, s);
+  vec_axpby<T>(r, T(1), b, T(-1), n, s);  // r = b - A x
+  Level &C = P.L[l + 1];
+  launch_restrict<T>(L.g, C.g, L.h_to_coarser, L.emb.data(), W.b[l + 1], r, s);
+  vcycle_level<T>(P, l + 1, W.x[l + 1], W.b[l + 1], s);
+  launch_prolongate_add<T>(L.g, C.g, L.h_to_coarser, L.emb.data(), x, W.x[l + 1], s);
+  chebyshev<T>(P, l, x, b, false, s);
+}
+
+// ---------------------------------------------------------------- block preconditioner
+template <typename T>
+void precondition(mfs_problem &P, T *y, const T *r, hipStream_t s) {
+  PrecWork<T> &W = work<T>(P);
+  const LevelGeom &g = P.L[0].g;
+  const int64_t nu = P.dim * g.Nv, np = g.Np;
+  const T *rp = r + nu;
+  T *yp = y + nu;
+  // Schur: y_p = -nu M_p^{-1} r_p, M_p^{-1} by Jacobi-PCG (z0 = 0)
+  double *rho = P.scal, *pqs = P.scal + PCG_MAX;
+  vec_fill<T>(W.pz, T(0), np, s);
+  vec_copy<T>(W.pres, rp, np, s);
+  vec_mul<T>(W.ps, W.pinv, W.pres, np, s);
+  vec_copy<T>(W.pp, W.ps, np, s);
+  multi_dot<T>(W.pres, 0, 1, W.ps, np, rho, P.partials, s);
+  for (int it = 0; it < P.opts.schur_iterations; ++it) {
+    apply_op<T>(P, MFS_OP_MASS_P, 0, W.pq, W.pp, s);
+    multi_dot<T>(W.pp, 0, 1, W.pq, np, pqs + it, P.partials, s);
+    pcg_update1<T>(W.pz, W.pres, W.ps, W.pp, W.pq, W.pinv, np, rho + it, pqs + it, s);
+    multi_dot<T>(W.pres, 0, 1, W.ps, np, rho + it + 1, P.partials, s);
+    pcg_update2<T>(W.pp, W.ps, np, rho + it + 1, rho + it, s);
+  }
+  vec_axpby<T>(yp, (T)(-P.nu), W.pz, T(0), np, s);
+  // velocity: y_u = Vcycle(r_u - B y_p)
+  apply_op<T>(P, MFS_OP_B, 0, W.t_u, yp, s);
+  vec_axpby<T>(W.t_u, T(1), r, T(-1), nu, s);
+  vcycle_level<T>(P, 0, y, W.t_u, s);
+}
+
+// ---------------------------------------------------------------- FGMRES
+void kr_enqueue_residual(mfs_problem &P, hipStream_t s) {
+  Krylov &K = P.kr;
+  const int64_t n = P.dim * P.L[0].g.Nv + P.L[0].g.Np;
+  apply_op<double>(P, MFS_OP_STOKES, 0, K.w, K.x, s);
+  vec_axpby<double>(K.w, 1.0, K.b, -1.0, n, s);  // w = b - K x
+  multi_dot<double>(K.w, 0, 1, K.w, n, K.dev + 96, P.partials, s);
+  MFS_HIP(hipMemcpyAsync(K.host + 96, K.dev + 96, sizeof(double), hipMemcpyDeviceToHost, s));
+  MFS_HIP(hipEventRecord(K.ev, s));
+}
+
+void kr_enqueue_step(mfs_problem &P, hipStream_t s) {
+  Krylov &K = P.kr;
+  const LevelGeom &g = P.L[0].g;
+  const int64_t n = P.dim * g.Nv + g.Np;
+  const int j = K.j;
+  double *vj = K.V + (int64_t)j * n, *zj = K.Z + (int64_t)j * n;
+  if (K.prec == MFS_FP32) {
+    vec_cast<float, double>(P.w32.full_in, vj, n, s);
+    precondition<float>(P, P.w32.full_out, P.w32.full_in, s);
+    vec_cast<double, float>(zj, P.w32.full_out, n, s);
+  } else {
+    precondition<double>(P, zj, vj, s);
+  }
+  apply_op<double>(P, MFS_OP_STOKES, 0, K.w, zj, s);
+  // classical Gram-Schmidt, twice
+  multi_dot<double>(K.V, n, j + 1, K.w, n, K.dev, P.partials, s);
+  multi_axpy<double>(K.w, K.V, n, j + 1, K.dev, n, s);
+  multi_dot<double>(K.V, n, j + 1, K.w, n, K.dev + 32, P.partials, s);
+  multi_axpy<double>(K.w, K.V, n, j + 1, K.dev + 32, n, s);
+  multi_dot<double>(K.w, 0, 1, K.w, n, K.dev + 64, P.partials, s);
+  scale_inv_sqrt<double>(K.V + (int64_t)(j + 1) * n, K.w, n, K.dev + 64, s);
+  MFS_HIP(hipMemcpyAsync(K.host, K.dev, 65 * sizeof(double), hipMemcpyDeviceToHost, s));
+  MFS_HIP(hipEventRecord(K.ev, s));
+}
+
+// update x with the current Krylov coefficients (j columns) and enqueue the
+// true-residual check
+void kr_enqueue_update(mfs_problem &P, hipStream_t s) {
+  Krylov &K = P.kr;
+  const int64_t n = P.dim * P.L[0].g.Nv + P.L[0].g.Np;
+  const int m = K.j;
+  if (m > 0) {
+    std::vector<double> y(m);
+    for (int i = m - 1; i >= 0; --i) {
+      double v = K.gv[i];
+      for (int c = i + 1; c < m; ++c) v -= K.H[i * K.m + c] * y[c];
+      y[i] = v / K.H[i * K.m + i];
+    }
+    MFS_HIP(hipStreamSynchronize(s));  // previous use of yhost finished
+    std::memcpy(K.yhost, y.data(), m * sizeof(double));
+    MFS_HIP(hipMemcpyAsync(K.ydev, K.yhost, m * sizeof(double), hipMemcpyHostToDevice, s));
+    multi_combine<double>(K.x, K.Z, n, m, K.ydev, n, true, s);
+  }
+  kr_enqueue_residual(P, s);
+}
+
+void kr_finish(mfs_problem &P, double rel, int status) {
+  Krylov &K = P.kr;
+  hipStream_t s = K.s;
+  const LevelGeom &g = P.L[0].g;
+  const int64_t nu = P.dim * g.Nv;
+  // pressure with zero mass-weighted mean
+  if (g.Np > 0) {
+    double *num = P.scal + 4 * PCG_MAX + 8, *den = num + 1;
+    multi_dot<double>(P.m1, 0, 1, K.x + nu, g.Np, num, P.partials, s);
+    vec_fill<double>(P.tmp_full, 1.0, g.Np, s);
+    multi_dot<double>(P.m1, 0, 1, P.tmp_full, g.Np, den, P.partials, s);
+    shift_mean(K.x + nu, g.Np, num, den, s);
+  }
+  MFS_HIP(hipStreamSynchronize(s));
+  K.info.iterations = K.iters;
+  K.info.status = status;
+  K.info.rel_residual = rel;
+  K.info.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - K.t0).count();
+  K.state = 4;
+}
+
+// advance the state machine after its event completed
+void kr_process(mfs_problem &P) {
+  Krylov &K = P.kr;
+  hipStream_t s = K.s;
+  const int64_t n = P.dim * P.L[0].g.Nv + P.L[0].g.Np;
+  if (K.state == 1 || K.state == 3) {
+    const double rr = std::sqrt(std::max(K.host[96], 0.0));
+    if (K.state == 1 && K.bnorm == 0.0) K.bnorm = rr;  // first call stores ||b - K x0||, replaced below
+    const double rel = K.bnorm > 0 ? rr / K.bnorm : 0.0;
+    if (rel <= K.rtol || K.iters >= K.maxit) {
+      kr_finish(P, rel, rel <= K.rtol ? MFS_OK : MFS_ENOCONV);
+      return;
+    }
+    // (re)start: V_0 = r / ||r||
+    K.beta = rr;
+    std::fill(K.H.begin(), K.H.end(), 0.0);
+    std::fill(K.gv.begin(), K.gv.end(), 0.0);
+    K.gv[0] = rr;
+    K.j = 0;
+    scale_inv_sqrt<double>(K.V, K.w, n, K.dev + 96, s);
+    K.state = 2;
+    kr_enqueue_step(P, s);
+    return;
+  }
+  if (K.state == 2) {
+    const int j = K.j, m = K.m;
+    // column j of the Hessenberg matrix
+    std::vector<double> h(j + 2);
+    for (int i = 0; i <= j; ++i) h[i] = K.host[i] + K.host[32 + i];
+    h[j + 1] = std::sqrt(std::max(K.host[64], 0.0));
+    for (int i = 0; i < j; ++i) {
+      const double t = K.cs[i] * h[i] + K.sn[i] * h[i + 1];
+      h[i + 1] = -K.sn[i] * h[i] + K.cs[i] * h[i + 1];
+      h[i] = t;
+    }
+    const double den = std::hypot(h[j], h[j + 1]);
+    K.cs[j] = den > 0 ? h[j] / den : 1.0;
+    K.sn[j] = den > 0 ? h[j + 1] / den : 0.0;
+    h[j] = den;
+    K.gv[j + 1] = -K.sn[j] * K.gv[j];
+    K.gv[j] = K.cs[j] * K.gv[j];
+    for (int i = 0; i <= j; ++i) K.H[i * m + j] = h[i];
+    K.j = j + 1;
+    K.iters += 1;
+    const double est = std::fabs(K.gv[j + 1]) / K.bnorm;
+    const bool breakdown = !(h[j] > 0) || K.host[64] <= 0.0;
+    if (est <= K.rtol || K.j == m || K.iters >= K.maxit || breakdown) {
+      K.state = 3;
+      kr_enqueue_update(P, s);
+      return;
+    }
+    kr_enqueue_step(P, s);
+  }
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+
+namespace {
+int guard(const std::function<void()> &f) {
+  try {
+    f();
+    return MFS_OK;
+  } catch (const mfs::Error &e) {
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    set_error("host allocation failed");
+    return MFS_ENOMEM;
+  } catch (...) {
+    set_error("unexpected exception");
+    return MFS_EINVAL;
+  }
+}
+
+std::vector<LevelGeom> levels_for(const mfs_mesh *mesh, int k, const mfs_options &o) {
+  const int kp = o.pressure_offset == 1 ? k - 1 : k;
+  return plan_levels(mesh->dim, mesh->n, k, kp, o);
+}
+}  // namespace
+
+extern "C" {
+
+void mfs_default_options(mfs_options *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->pressure_offset = 1;
+  o->mg_levels = 1;
+  o->cheb_degree = 5;
+  o->cheb_range = 20.0;
+  o->cheb_safety = 1.2;
+  o->lanczos_steps = 20;
+  o->p_min = 1;
+  o->coarse_min_cells = 2;
+  o->schur_iterations = 10;
+  o->restart = 30;
+  o->maxit = 200;
+  o->rtol = 1e-8;
+  o->precond_precision = MFS_FP32;
+  o->seed = 0;
+  o->dt = 1e-2;
+  o->newton = 1;
+}
+
+const char *mfs_last_error(void) { return get_error(); }
+
+int mfs_footprint(const mfs_mesh *mesh, int k, const mfs_options *opts, size_t *bytes) {
+  return guard([&] {
+    mfs_options o;
+    if (opts)
+      o = *opts;
+    else
+      mfs_default_options(&o);
+    check_mesh(mesh, k, o);
+    check_options(o);
+    MFS_REQUIRE(bytes != nullptr, MFS_EINVAL, "bytes is NULL");
+    auto G = levels_for(mesh, k, o);
+    mfs_problem P;
+    P.dim = mesh->dim;
+    P.opts = o;
+    Arena A;
+    plan_arena(A, P, G);
+    *bytes = A.off;
+  });
+}
+
+int mfs_setup(const mfs_mesh *mesh, int k, double nu, const mfs_options *opts, void *stream, mfs_problem **out) {
+  mfs_problem *P = nullptr;
+  int rc = guard([&] {
+    MFS_REQUIRE(out != nullptr, MFS_EINVAL, "out is NULL");
+    *out = nullptr;
+    mfs_options o;
+    if (opts)
+      o = *opts;
+    else
+      mfs_default_options(&o);
+    check_mesh(mesh, k, o);
+    check_options(o);
+    MFS_REQUIRE(mesh->vertices != nullptr, MFS_EINVAL, "vertices is NULL");
+    MFS_REQUIRE(nu > 0, MFS_EINVAL, "nu must be positive");
+    P = new mfs_problem();
+    P->dim = mesh->dim;
+    P->nu = nu;
+    P->opts = o;
+    hipStream_t s = S(stream);
+    P->stream = s;
+    auto G = levels_for(mesh, k, o);
+    P->nlev = (int)G.size();
+    Arena dry;
+    plan_arena(dry, *P, G);
+    P->arena_bytes = dry.off;
+    MFS_HIP(hipMalloc(&P->arena, P->arena_bytes));
+    Arena A;
+    A.dry = false;
+    A.base = P->arena;
+    plan_arena(A, *P, G);
+    MFS_HIP(hipHostMalloc(&P->kr.host, 128 * sizeof(double)));
+    MFS_HIP(hipHostMalloc(&P->kr.yhost, 64 * sizeof(double)));
+    MFS_HIP(hipEventCreateWithFlags(&P->kr.ev, hipEventDisableTiming));
+    // vertices per level: fine vertices at indices divisible by 2^h
+    const int dim = mesh->dim;
+    int hl = 0;
+    for (int l = 0; l < P->nlev; ++l) {
+      Level &L = P->L[l];
+      if (l > 0 && L.g.n[0] != P->L[l - 1].g.n[0]) ++hl;
+      const int st = 1 << hl;
+      const int64_t nvert = n_vertices(L.g);
+      L.Xhost.resize(nvert * dim);
+      const int fn0 = mesh->n[0] + 1, fn1 = mesh->n[1] + 1;
+      for (int z = 0; z < (dim == 3 ? L.g.n[2] + 1 : 1); ++z)
+        for (int y = 0; y <= L.g.n[1]; ++y)
+          for (int x = 0; x <= L.g.n[0]; ++x) {
+            const int64_t v = x + (int64_t)(L.g.n[0] + 1) * (y + (int64_t)(L.g.n[1] + 1) * z);
+            const int64_t fv = (int64_t)x * st + (int64_t)fn0 * ((int64_t)y * st + (int64_t)fn1 * z * st);
+            for (int a = 0; a < dim; ++a) L.Xhost[v * dim + a] = mesh->vertices[fv * dim + a];
+          }
+      std::vector<float> X32(L.Xhost.begin(), L.Xhost.end());
+      MFS_HIP(hipMemcpyAsync(L.X64, L.Xhost.data(), L.Xhost.size() * sizeof(double), hipMemcpyHostToDevice, s));
+      MFS_HIP(hipMemcpyAsync(L.X32, X32.data(), X32.size() * sizeof(float), hipMemcpyHostToDevice, s));
+      auto tab = make_tables(L.g.k, L.g.kp);
+      std::vector<float> tab32(tab.begin(), tab.end());
+      MFS_HIP(hipMemcpyAsync(L.tab64, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, s));
+      MFS_HIP(hipMemcpyAsync(L.tab32, tab32.data(), tab32.size() * sizeof(float), hipMemcpyHostToDevice, s));
+      MFS_HIP(hipStreamSynchronize(s));
+      if (l + 1 < P->nlev) {
+        const LevelGeom &c = G[l + 1];
+        L.h_to_coarser = c.n[0] != L.g.n[0];
+        L.emb = L.h_to_coarser ? h_embedding(c.k) : p_embedding(L.g.k, c.k);
+      }
+    }
+    // geometry check on the finest level
+    {
+      Level &L = P->L[0];
+      int *bad = reinterpret_cast<int *>(P->scal);
+      vec_fill<int>(bad, 0x7fffffff, 1, s);
+      launch_check_geometry(L.g, L.X64, L.tab64, bad, s);
+      int hb = 0;
+      MFS_HIP(hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+      MFS_HIP(hipStreamSynchronize(s));
+      MFS_REQUIRE(hb == 0x7fffffff, MFS_EINVAL, "non-positive Jacobian determinant in cell %d", hb);
+    }
+    // diagonals
+    for (int l = 0; l < P->nlev; ++l) {
+      Level &L = P->L[l];
+      vec_fill<double>(L.diag, 0.0, L.g.Nv, s);
+      launch_laplace_diagonal(L.g, L.X64, L.tab64, nu, L.diag, s);
+      vec_invert_diag(L.g, L.diag, L.invdiag64, L.invdiag32, s);
+    }
+    // pressure mass: M_p 1 (for the pressure mean) and 1/diag(M_p) for Jacobi-PCG
+    if (P->L[0].g.Np > 0) {
+      Level &L = P->L[0];
+      const LevelGeom &g = L.g;
+      double *ones = P->tmp_full;
+      vec_fill<double>(ones, 1.0, g.Np, s);
+      apply_op<double>(*P, MFS_OP_MASS_P, 0, P->m1, ones, s);
+      double *pd = P->w64.pz;  // scratch: diag(M_p)
+      vec_fill<double>(pd, 0.0, g.Np, s);
+      launch_mass_diagonal(g, L.X64, L.tab64, pd, s);
+      vec_fill<double>(ones, 1.0, g.Np, s);
+      launch_reciprocal(P->w64.pinv, P->w32.pinv, pd, g.Np, s);
+    }
+    // Chebyshev bounds and the coarse inverse
+    if (o.mg_levels) {
+      for (int l = 0; l + 1 < P->nlev; ++l) P->L[l].lambda = o.cheb_safety * estimate_lambda(*P, l, s);
+      setup_coarse(*P, s);
+    }
+    MFS_HIP(hipStreamSynchronize(s));
+    *out = P;
+  });
+  if (rc != MFS_OK) {
+    release(P);
+    return rc;
+  }
+  return MFS_OK;
+}
+
+int mfs_destroy(mfs_problem *p) {
+  release(p);
+  return MFS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+void check_problem(const mfs_problem *p) { MFS_REQUIRE(p != nullptr, MFS_EINVAL, "problem is NULL"); }
+void check_level(const mfs_problem *p, int level) {
+  check_problem(p);
+  MFS_REQUIRE(level >= 0 && level < p->nlev, MFS_EINVAL, "level %d out of range [0, %d)", level, p->nlev);
+}
+void check_prec(int prec) {
+  MFS_REQUIRE(prec == MFS_FP32 || prec == MFS_FP64, MFS_EINVAL, "precision must be MFS_FP32 or MFS_FP64");
+}
+
+void kr_begin(mfs_problem &P, const double *b, double *x, const mfs_options &o, hipStream_t s) {
+  Krylov &K = P.kr;
+  MFS_REQUIRE(P.opts.mg_levels, MFS_EINVAL, "solve needs the multigrid hierarchy (mg_levels = 1)");
+  MFS_REQUIRE(P.L[0].g.Np > 0, MFS_EINVAL, "solve needs a pressure space");
+  const LevelGeom &g = P.L[0].g;
+  const int64_t n = P.dim * g.Nv + g.Np;
+  K.b = b;
+  K.x = x;
+  K.s = s;
+  K.rtol = o.rtol;
+  K.maxit = o.maxit;
+  K.prec = o.precond_precision;
+  K.iters = 0;
+  K.j = 0;
+  K.H.assign((size_t)(K.m + 1) * K.m, 0.0);
+  K.cs.assign(K.m, 0.0);
+  K.sn.assign(K.m, 0.0);
+  K.gv.assign(K.m + 1, 0.0);
+  K.info = mfs_solve_info{};
+  K.t0 = std::chrono::steady_clock::now();
+  // ||b|| first (state 1 reads it as bnorm), then the residual of x0
+  launch_fill_dirichlet<double>(g, x, b, s);  // x0: lifting of b's Dirichlet rows
+  vec_fill<double>(x + P.dim * g.Nv, 0.0, g.Np, s);
+  multi_dot<double>(b, 0, 1, b, n, K.dev + 100, P.partials, s);
+  MFS_HIP(hipMemcpyAsync(K.host + 100, K.dev + 100, sizeof(double), hipMemcpyDeviceToHost, s));
+  MFS_HIP(hipStreamSynchronize(s));
+  K.bnorm = std::sqrt(std::max(K.host[100], 0.0));
+  if (K.bnorm == 0.0) K.bnorm = 1.0;
+  K.state = 1;
+  kr_enqueue_residual(P, s);
+}
+}  // namespace
+
+extern "C" {
+
+int mfs_n_dofs(const mfs_problem *p, int level, int64_t *n_u, int64_t *n_p) {
+  return guard([&] {
+    check_level(p, level);
+    if (n_u) *n_u = p->L[level].g.Nv;
+    if (n_p) *n_p = p->L[level].g.Np;
+  });
+}
+
+int mfs_n_levels(const mfs_problem *p, int *n) {
+  return guard([&] {
+    check_problem(p);
+    MFS_REQUIRE(n != nullptr, MFS_EINVAL, "n is NULL");
+    *n = p->nlev;
+  });
+}
+
+int mfs_level_info(const mfs_problem *p, int level, int *k, int *n) {
+  return guard([&] {
+    check_level(p, level);
+    if (k) *k = p->L[level].g.k;
+    if (n)
+      for (int a = 0; a < 3; ++a) n[a] = p->L[level].g.n[a];
+  });
+}
+
+int mfs_support_points(const mfs_problem *p, int deg, double *xyz) {
+  return guard([&] {
+    check_problem(p);
+    MFS_REQUIRE(deg >= 1 && deg <= 7, MFS_EINVAL, "degree out of range");
+    MFS_REQUIRE(xyz != nullptr, MFS_EINVAL, "buffer is NULL");
+    const Level &L = p->L[0];
+    const int dim = p->dim;
+    const auto nodes = gll_nodes(deg);
+    int nn[3] = {1, 1, 1};
+    for (int a = 0; a < dim; ++a) nn[a] = deg * L.g.n[a] + 1;
+    for (int z = 0; z < nn[2]; ++z)
+      for (int y = 0; y < nn[1]; ++y)
+        for (int x = 0; x < nn[0]; ++x) {
+          const int g[3] = {x, y, z};
+          int c[3] = {0, 0, 0};
+          double xi[3] = {0, 0, 0};
+          for (int a = 0; a < dim; ++a) {
+            c[a] = std::min(g[a] / deg, L.g.n[a] - 1);
+            xi[a] = nodes[g[a] - deg * c[a]];
+          }
+          const int64_t id = x + (int64_t)nn[0] * (y + (int64_t)nn[1] * z);
+          for (int a = 0; a < dim; ++a) {
+            double v = 0;
+            for (int vtx = 0; vtx < (1 << dim); ++vtx) {
+              double f = 1;
+              int vi[3] = {0, 0, 0};
+              for (int b = 0; b < dim; ++b) {
+                const int hi = (vtx >> b) & 1;
+                f *= hi ? xi[b] : 1.0 - xi[b];
+                vi[b] = c[b] + hi;
+              }
+              const int64_t vid = vi[0] + (int64_t)(L.g.n[0] + 1) * (vi[1] + (int64_t)(L.g.n[1] + 1) * vi[2]);
+              v += f * L.Xhost[vid * dim + a];
+            }
+            xyz[id * dim + a] = v;
+          }
+        }
+  });
+}
+
+int mfs_quadrature_points(const mfs_problem *p, double *xyz) {
+  return guard([&] {
+    check_problem(p);
+    MFS_REQUIRE(xyz != nullptr, MFS_EINVAL, "buffer is NULL");
+    const Level &L = p->L[0];
+    const int64_t nq = L.g.ncells * ipow(L.g.k + 1, p->dim) * p->dim;
+    double *d = nullptr;
+    MFS_HIP(hipMalloc(&d, nq * sizeof(double)));
+    launch_quadrature_points(L.g, L.X64, L.tab64, d, p->stream);
+    hipError_t e = hipMemcpyAsync(xyz, d, nq * sizeof(double), hipMemcpyDeviceToHost, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    (void)hipFree(d);
+    MFS_HIP(e);
+  });
+}
+
+int mfs_vmult(mfs_problem *p, int op, int prec, int level, void *dst, const void *src, void *stream) {
+  return guard([&] {
+    check_level(p, level);
+    check_prec(prec);
+    MFS_REQUIRE(dst && src, MFS_EINVAL, "NULL vector");
+    MFS_REQUIRE(dst != src, MFS_EINVAL, "dst and src must not alias");
+    if (prec == MFS_FP64)
+      apply_op<double>(*p, op, level, (double *)dst, (const double *)src, S(stream));
+    else
+      apply_op<float>(*p, op, level, (float *)dst, (const float *)src, S(stream));
+  });
+}
+
+int mfs_diagonal(mfs_problem *p, int level, double *dst, void *stream) {
+  return guard([&] {
+    check_level(p, level);
+    MFS_REQUIRE(dst != nullptr, MFS_EINVAL, "NULL vector");
+    const Level &L = p->L[level];
+    hipStream_t s = S(stream);
+    vec_fill<double>(dst, 0.0, L.g.Nv, s);
+    launch_laplace_diagonal(L.g, L.X64, L.tab64, p->nu, dst, s);
+    // Dirichlet rows: 1 (identity rows of the constrained operator)
+    launch_reciprocal_boundary_one(L.g, dst, s);
+  });
+}
+
+int mfs_get_lambda(const mfs_problem *p, int level, double *lambda) {
+  return guard([&] {
+    check_level(p, level);
+    MFS_REQUIRE(lambda != nullptr, MFS_EINVAL, "NULL output");
+    *lambda = p->L[level].lambda;
+  });
+}
+
+int mfs_set_lambda(mfs_problem *p, int level, double lambda) {
+  return guard([&] {
+    check_level(p, level);
+    MFS_REQUIRE(lambda > 0, MFS_EINVAL, "lambda must be positive");
+    p->L[level].lambda = lambda;
+  });
+}
+
+int mfs_vcycle(mfs_problem *p, int prec, void *dst, const void *src, void *stream) {
+  return guard([&] {
+    check_problem(p);
+    check_prec(prec);
+    MFS_REQUIRE(p->opts.mg_levels, MFS_EINVAL, "problem was set up without multigrid levels");
+    MFS_REQUIRE(dst && src && dst != src, MFS_EINVAL, "bad vectors");
+    if (prec == MFS_FP64)
+      vcycle_level<double>(*p, 0, (double *)dst, (const double *)src, S(stream));
+    else
+      vcycle_level<float>(*p, 0, (float *)dst, (const float *)src, S(stream));
+  });
+}
+
+int mfs_prolongate_add(mfs_problem *p, int prec, int fine, void *dst, const void *src, void *stream) {
+  return guard([&] {
+    check_level(p, fine);
+    check_prec(prec);
+    MFS_REQUIRE(fine + 1 < p->nlev, MFS_EINVAL, "no coarser level below %d", fine);
+    const Level &F = p->L[fine], &C = p->L[fine + 1];
+    if (prec == MFS_FP64)
+      launch_prolongate_add<double>(F.g, C.g, F.h_to_coarser, F.emb.data(), (double *)dst, (const double *)src,
+                                    S(stream));
+    else
+      launch_prolongate_add<float>(F.g, C.g, F.h_to_coarser, F.emb.data(), (float *)dst, (const float *)src,
+                                   S(stream));
+  });
+}
+
+int mfs_restrict(mfs_problem *p, int prec, int fine, void *dst, const void *src, void *stream) {
+  return guard([&] {
+    check_level(p, fine);
+    check_prec(prec);
+    MFS_REQUIRE(fine + 1 < p->nlev, MFS_EINVAL, "no coarser level below %d", fine);
+    const Level &F = p->L[fine], &C = p->L[fine + 1];
+    if (prec == MFS_FP64)
+      launch_restrict<double>(F.g, C.g, F.h_to_coarser, F.emb.data(), (double *)dst, (const double *)src, S(stream));
+    else
+      launch_restrict<float>(F.g, C.g, F.h_to_coarser, F.emb.data(), (float *)dst, (const float *)src, S(stream));
+  });
+}
+
+int mfs_precondition(mfs_problem *p, int prec, void *dst, const void *src, void *stream) {
+  return guard([&] {
+    check_problem(p);
+    check_prec(prec);
+    MFS_REQUIRE(p->opts.mg_levels && p->L[0].g.Np > 0, MFS_EINVAL, "needs multigrid levels and a pressure space");
+    MFS_REQUIRE(dst && src && dst != src, MFS_EINVAL, "bad vectors");
+    if (prec == MFS_FP64)
+      precondition<double>(*p, (double *)dst, (const double *)src, S(stream));
+    else
+      precondition<float>(*p, (float *)dst, (const float *)src, S(stream));
+  });
+}
+
+int mfs_rhs(mfs_problem *p, const double *f_qp, const double *u_dirichlet, double *b, void *stream) {
+  return guard([&] {
+    check_problem(p);
+    MFS_REQUIRE(f_qp && u_dirichlet && b, MFS_EINVAL, "NULL vector");
+    const Level &L = p->L[0];
+    const LevelGeom &g = L.g;
+    MFS_REQUIRE(g.Np > 0, MFS_EINVAL, "needs a pressure space");
+    hipStream_t s = S(stream);
+    const int64_t nu = p->dim * g.Nv, n = nu + g.Np;
+    double *t = p->tmp_full;
+    // t = K_unconstrained * lifting, free velocity rows and all pressure rows
+    launch_fill_dirichlet<double>(g, t, (const double *)nullptr, s);
+    vec_fill<double>(t + nu, 0.0, g.Np, s);
+    launch_cell_op<double>(g, dev<double>(L), M_LAPLACE | M_DIVU, p->nu, t, t + nu, u_dirichlet, nullptr, s, true);
+    // b = (f, phi) - t on free rows; u_D on Dirichlet rows; -t on pressure rows
+    launch_fill_dirichlet<double>(g, b, u_dirichlet, s);
+    vec_fill<double>(b + nu, 0.0, g.Np, s);
+    launch_load_vector(g, L.X64, L.tab64, f_qp, b, s);
+    vec_axpby<double>(b, -1.0, t, 1.0, n, s);
+    (void)n;
+  });
+}
+
+int mfs_solve_begin(mfs_problem *p, const double *b, double *x, const mfs_options *opts, void *stream) {
+  return guard([&] {
+    check_problem(p);
+    MFS_REQUIRE(b && x && (const void *)b != (void *)x, MFS_EINVAL, "bad vectors");
+    mfs_options o = opts ? *opts : p->opts;
+    MFS_REQUIRE(o.rtol > 0 && o.maxit >= 1, MFS_EINVAL, "bad rtol / maxit");
+    check_prec(o.precond_precision);
+    kr_begin(*p, b, x, o, S(stream));
+  });
+}
+
+int mfs_solve_advance(mfs_problem *p, int *done, mfs_solve_info *info) {
+  return guard([&] {
+    check_problem(p);
+    MFS_REQUIRE(done != nullptr, MFS_EINVAL, "done is NULL");
+    Krylov &K = p->kr;
+    *done = 0;
+    if (K.state == 4) {
+      *done = 1;
+      if (info) *info = K.info;
+      return;
+    }
+    MFS_REQUIRE(K.state != 0, MFS_EINVAL, "no solve in progress");
+    const hipError_t q = hipEventQuery(K.ev);
+    if (q == hipErrorNotReady) return;
+    MFS_HIP(q);
+    kr_process(*p);
+    if (K.state == 4) {
+      *done = 1;
+      if (info) *info = K.info;
+    }
+  });
+}
+
+int mfs_solve(mfs_problem *p, const double *b, double *x, const mfs_options *opts, mfs_solve_info *info,
+              void *stream) {
+  int rc = mfs_solve_begin(p, b, x, opts, stream);
+  if (rc != MFS_OK) return rc;
+  return guard([&] {
+    Krylov &K = p->kr;
+    while (K.state != 4) {
+      MFS_HIP(hipEventSynchronize(K.ev));
+      kr_process(*p);
+    }
+    if (info) *info = K.info;
+    if (K.info.status != MFS_OK) {
+      set_error("FGMRES did not reach rtol %.3e within %d iterations (relative residual %.3e)", K.rtol, K.maxit,
+                K.info.rel_residual);
+      throw mfs::Error{MFS_ENOCONV};
+    }
+  });
+}
+
+int mfs_set_linearization(mfs_problem *p, const double *u0, double dt, int newton, void *stream) {
+  return guard([&] {
+    check_problem(p);
+    (void)u0;
+    (void)dt;
+    (void)newton;
+    (void)stream;
+    MFS_REQUIRE(false, MFS_EUNSUPPORTED, "Navier-Stokes linearisation not available in this build");
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,806 @@
+// Generic matrix-free cell kernels: Stokes operator, its blocks, the pressure
+// mass, the Laplacian diagonal and setup helpers.
+//
+// One thread per quadrature point, several cells per workgroup.  Values and
+// reference gradients at the (k+1)^dim Gauss points come from 1D
+// contractions staged through LDS (sum factorisation): interpolation from the
+// GLL nodes to the Gauss points direction by direction, then the collocation
+// derivative on the Gauss points.  The transposed sequence integrates the
+// test-function coefficients back to the nodes.  Cell contributions are added
+// to the output vector with hardware atomics; Dirichlet rows are written by a
+// separate fill pass (dst = src there) that also clears the other rows.
+//
+// Weak forms: Sec. 1 eq. (stokes) and the symmetric block matrix of Sec. 3
+// eq. (stokes_block): velocity rows nu (grad u, grad v) - (p, div v),
+// pressure rows -(div u, q).
+#include "internal.h"
+
+namespace mfs {
+
+template <int DIM, int K, int KP>
+struct Shape {
+  static constexpr int Q = K + 1;
+  static constexpr int N = K + 1;
+  static constexpr int M = KP + 1;
+  static constexpr int NQ = DIM == 2 ? Q * Q : Q * Q * Q;
+  static constexpr int CPB = NQ >= 256 ? 1 : 256 / NQ;
+  static constexpr int NT = CPB * NQ;
+  static constexpr int BLOCK = (NT + 63) / 64 * 64;
+  static constexpr int NV = 1 << DIM;
+};
+
+template <typename T>
+struct CellArgs {
+  int n0, n1, n2, ncells;
+  int nv0, nv1, nv2;
+  int np0, np1, np2;
+  int64_t Nv, Np;
+  const T *X;
+  const T *tab;
+  const T *src_u;
+  const T *src_p;
+  T *dst_u;
+  T *dst_p;
+  T nu;
+  int src_all;  // 1: read source values on Dirichlet rows too (unconstrained operator)
+};
+
+// out = sum_m mat(r, m) in[.. m ..] along direction DIR; TR reads mat(m, r).
+template <int DIM, int Q, int DIR, int C, bool TR, typename T>
+__device__ __forceinline__ T sweep(const T *in, const T *mat, int qi, int qj, int ql) {
+  const int r = DIR == 0 ? qi : (DIR == 1 ? qj : ql);
+  const int base = DIR == 0 ? Q * (qj + Q * ql) : (DIR == 1 ? qi + Q * Q * ql : qi + Q * qj);
+  constexpr int stride = DIR == 0 ? 1 : (DIR == 1 ? Q : Q * Q);
+  T s = 0;
+#pragma unroll
+  for (int m = 0; m < C; ++m) {
+    const T c = TR ? mat[m * MAXQ + r] : mat[r * MAXQ + m];
+    s += c * in[base + m * stride];
+  }
+  return s;
+}
+
+// Q1 map: Jacobian J[a][b] = dx_a / dxi_b at reference point xi.
+template <int DIM, typename T>
+__device__ __forceinline__ void q1_jacobian(const T *Xc, const T xi[3], T J[3][3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) J[a][b] = 0;
+#pragma unroll
+  for (int v = 0; v < (1 << DIM); ++v) {
+    T f[3], df[3];
+#pragma unroll
+    for (int b = 0; b < DIM; ++b) {
+      const bool hi = (v >> b) & 1;
+      f[b] = hi ? xi[b] : T(1) - xi[b];
+      df[b] = hi ? T(1) : T(-1);
+    }
+#pragma unroll
+    for (int b = 0; b < DIM; ++b) {
+      T d = df[b];
+#pragma unroll
+      for (int c = 0; c < DIM; ++c)
+        if (c != b) d *= f[c];
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) J[a][b] += Xc[v * DIM + a] * d;
+    }
+  }
+}
+
+template <int DIM, typename T>
+__device__ __forceinline__ T q1_point(const T *Xc, const T xi[3], int a) {
+  T s = 0;
+#pragma unroll
+  for (int v = 0; v < (1 << DIM); ++v) {
+    T f = 1;
+#pragma unroll
+    for (int b = 0; b < DIM; ++b) f *= ((v >> b) & 1) ? xi[b] : T(1) - xi[b];
+    s += Xc[v * DIM + a] * f;
+  }
+  return s;
+}
+
+// inverse and determinant
+template <int DIM, typename T>
+__device__ __forceinline__ T invert(const T J[3][3], T I[3][3]) {
+  if (DIM == 2) {
+    const T det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    const T r = T(1) / det;
+    I[0][0] = J[1][1] * r;
+    I[0][1] = -J[0][1] * r;
+    I[1][0] = -J[1][0] * r;
+    I[1][1] = J[0][0] * r;
+    return det;
+  } else {
+    const T c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    const T c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    const T c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    const T det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+    const T r = T(1) / det;
+    I[0][0] = c00 * r;
+    I[1][0] = c01 * r;
+    I[2][0] = c02 * r;
+    I[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * r;
+    I[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * r;
+    I[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * r;
+    I[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * r;
+    I[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * r;
+    I[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * r;
+    return det;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void atomic_add(T *p, T v) {
+  unsafeAtomicAdd(p, v);
+}
+
+// Per-cell context shared by the kernels below.
+template <int DIM, int K, int KP, typename T>
+struct CellCtx {
+  using Sh = Shape<DIM, K, KP>;
+  static constexpr int Q = Sh::Q, N = Sh::N, M = Sh::M, NQ = Sh::NQ;
+  int t, qi, qj, ql;
+  int cx, cy, cz;
+  bool valid, active;
+  T *b0, *b1, *b2;
+  const T *tab;
+
+  __device__ __forceinline__ bool vel_dirichlet(int nv0, int nv1, int nv2) const {
+    const int gx = cx * K + qi, gy = cy * K + qj, gz = cz * K + ql;
+    bool d = gx == 0 || gx == nv0 - 1 || gy == 0 || gy == nv1 - 1;
+    if (DIM == 3) d = d || gz == 0 || gz == nv2 - 1;
+    return d;
+  }
+  __device__ __forceinline__ int64_t vel_node(int nv0, int nv1) const {
+    return (int64_t)(cx * K + qi) + (int64_t)nv0 * ((cy * K + qj) + (int64_t)nv1 * (cz * K + ql));
+  }
+  __device__ __forceinline__ bool p_local() const { return qi < M && qj < M && (DIM == 2 || ql < M); }
+  __device__ __forceinline__ int64_t p_node(int np0, int np1) const {
+    return (int64_t)(cx * KP + qi) + (int64_t)np0 * ((cy * KP + qj) + (int64_t)np1 * (cz * KP + ql));
+  }
+
+  // values at the Gauss points from nodal values in b0 (extent C per direction);
+  // result returned and left in the returned buffer
+  template <int C, int OFF>
+  __device__ __forceinline__ const T *interpolate() {
+    const T *S = tab + OFF;
+    if (DIM == 2) {
+      T v = sweep<DIM, Q, 0, C, false>(b0, S, qi, qj, ql);
+      if (active) b1[t] = v;
+      __syncthreads();
+      v = sweep<DIM, Q, 1, C, false>(b1, S, qi, qj, ql);
+      if (active) b0[t] = v;
+      __syncthreads();
+      return b0;
+    } else {
+      T v = sweep<DIM, Q, 0, C, false>(b0, S, qi, qj, ql);
+      if (active) b1[t] = v;
+      __syncthreads();
+      v = sweep<DIM, Q, 1, C, false>(b1, S, qi, qj, ql);
+      if (active) b0[t] = v;
+      __syncthreads();
+      v = sweep<DIM, Q, 2, C, false>(b0, S, qi, qj, ql);
+      if (active) b1[t] = v;
+      __syncthreads();
+      return b1;
+    }
+  }
+  // transposed interpolation of the point values in `in`; returns the nodal
+  // value of this thread (meaningful when its indices are < C)
+  template <int C, int OFF>
+  __device__ __forceinline__ T integrate(T *in) {
+    const T *S = tab + OFF;
+    T *o = in == b0 ? b1 : b0;
+    if (DIM == 2) {
+      T v = sweep<DIM, Q, 1, Q, true>(in, S, qi, qj, ql);
+      if (active) o[t] = v;
+      __syncthreads();
+      return sweep<DIM, Q, 0, Q, true>(o, S, qi, qj, ql);
+    } else {
+      T v = sweep<DIM, Q, 2, Q, true>(in, S, qi, qj, ql);
+      if (active) o[t] = v;
+      __syncthreads();
+      v = sweep<DIM, Q, 1, Q, true>(o, S, qi, qj, ql);
+      if (active) in[t] = v;
+      __syncthreads();
+      return sweep<DIM, Q, 0, Q, true>(in, S, qi, qj, ql);
+    }
+  }
+
+  // reference gradient of component values (nodal, already in b0) at point t
+  __device__ __forceinline__ void gradient(T g[3]) {
+    const T *vals = interpolate<N, TAB_S>();
+    const T *D = tab + TAB_D;
+    g[0] = sweep<DIM, Q, 0, Q, false>(vals, D, qi, qj, ql);
+    g[1] = sweep<DIM, Q, 1, Q, false>(vals, D, qi, qj, ql);
+    if (DIM == 3) g[2] = sweep<DIM, Q, 2, Q, false>(vals, D, qi, qj, ql);
+    __syncthreads();
+  }
+
+  // test with reference gradients: sum_q f_b(q) d_b phi_i(q) -> nodal value
+  __device__ __forceinline__ T integrate_gradient(const T f[3]) {
+    if (active) {
+      b0[t] = f[0];
+      b1[t] = f[1];
+      if (DIM == 3) b2[t] = f[2];
+    }
+    __syncthreads();
+    const T *D = tab + TAB_D;
+    T r = sweep<DIM, Q, 0, Q, true>(b0, D, qi, qj, ql) + sweep<DIM, Q, 1, Q, true>(b1, D, qi, qj, ql);
+    if (DIM == 3) r += sweep<DIM, Q, 2, Q, true>(b2, D, qi, qj, ql);
+    __syncthreads();
+    if (active) b0[t] = r;
+    __syncthreads();
+    T v = integrate<N, TAB_S>(b0);
+    __syncthreads();
+    return v;
+  }
+};
+
+template <int DIM, int K, int KP, typename T, int MODE>
+__global__ void __launch_bounds__((Shape<DIM, K, KP>::BLOCK)) cell_kernel(CellArgs<T> a) {
+  using Sh = Shape<DIM, K, KP>;
+  constexpr int NQ = Sh::NQ, CPB = Sh::CPB, Q = Sh::Q;
+  __shared__ T s_tab[TAB_SIZE];
+  __shared__ T s_buf[3][CPB * NQ];
+  __shared__ T s_X[CPB][Sh::NV * DIM];
+
+  const int tid = threadIdx.x;
+  for (int i = tid; i < TAB_SIZE; i += Sh::BLOCK) s_tab[i] = a.tab[i];
+  CellCtx<DIM, K, KP, T> c;
+  c.active = tid < Sh::NT;
+  const int e = c.active ? tid / NQ : CPB - 1;
+  c.t = c.active ? tid - e * NQ : 0;
+  const int cell = blockIdx.x * CPB + e;
+  c.valid = c.active && cell < a.ncells;
+  c.qi = c.t % Q;
+  c.qj = (c.t / Q) % Q;
+  c.ql = DIM == 3 ? c.t / (Q * Q) : 0;
+  c.cx = c.cy = c.cz = 0;
+  if (c.valid) {
+    c.cx = cell % a.n0;
+    const int r = cell / a.n0;
+    c.cy = r % a.n1;
+    c.cz = DIM == 3 ? r / a.n1 : 0;
+  }
+  c.b0 = &s_buf[0][e * NQ];
+  c.b1 = &s_buf[1][e * NQ];
+  c.b2 = &s_buf[2][e * NQ];
+  c.tab = s_tab;
+  if (c.valid)
+    for (int idx = c.t; idx < Sh::NV * DIM; idx += NQ) {
+      const int v = idx / DIM, comp = idx % DIM;
+      const int vx = c.cx + (v & 1), vy = c.cy + ((v >> 1) & 1), vz = c.cz + ((v >> 2) & 1);
+      const int64_t vid = vx + (int64_t)(a.n0 + 1) * (vy + (int64_t)(a.n1 + 1) * (DIM == 3 ? vz : 0));
+      s_X[e][idx] = a.X[vid * DIM + comp];
+    }
+  __syncthreads();
+
+  const bool dir = c.valid ? c.vel_dirichlet(a.nv0, a.nv1, a.nv2) : true;
+  const int64_t vnode = c.valid ? c.vel_node(a.nv0, a.nv1) : 0;
+  constexpr bool NEED_U = (MODE & (M_LAPLACE | M_DIVU)) != 0;
+  constexpr bool NEED_P = (MODE & (M_GRADP | M_MASSP)) != 0;
+  constexpr bool OUT_U = (MODE & (M_LAPLACE | M_GRADP)) != 0;
+  constexpr bool OUT_P = (MODE & (M_DIVU | M_MASSP)) != 0;
+
+  T g[3][3] = {};
+  if (NEED_U) {
+#pragma unroll
+    for (int comp = 0; comp < DIM; ++comp) {
+      T v = 0;
+      if (c.valid && (a.src_all || !dir)) v = a.src_u[comp * a.Nv + vnode];
+      if (c.active) c.b0[c.t] = v;
+      __syncthreads();
+      c.gradient(g[comp]);
+    }
+  }
+  T pval = 0;
+  const bool ploc = c.p_local();
+  const int64_t pnode = (c.valid && ploc) ? c.p_node(a.np0, a.np1) : 0;
+  if (NEED_P) {
+    T v = 0;
+    if (c.valid && ploc) v = a.src_p[pnode];
+    if (c.active) c.b0[c.t] = v;
+    __syncthreads();
+    const T *vals = c.template interpolate<Sh::M, TAB_SP>();
+    pval = vals[c.t];
+    __syncthreads();
+  }
+
+  // geometry at this Gauss point
+  T xi[3] = {s_tab[TAB_X + c.qi], s_tab[TAB_X + c.qj], DIM == 3 ? s_tab[TAB_X + c.ql] : T(0)};
+  T J[3][3], I[3][3];
+  q1_jacobian<DIM>(s_X[e], xi, J);
+  const T det = invert<DIM>(J, I);
+  T w = s_tab[TAB_W + c.qi] * s_tab[TAB_W + c.qj];
+  if (DIM == 3) w *= s_tab[TAB_W + c.ql];
+  const T JxW = det * w;
+
+  T f[3][3] = {};
+  T qv = 0;
+  if (MODE & M_LAPLACE) {
+    const T s = JxW * a.nu;
+#pragma unroll
+    for (int comp = 0; comp < DIM; ++comp) {
+      T gp[3];
+#pragma unroll
+      for (int x = 0; x < DIM; ++x) {
+        T acc = 0;
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) acc += I[b][x] * g[comp][b];
+        gp[x] = acc * s;
+      }
+#pragma unroll
+      for (int b = 0; b < DIM; ++b) {
+        T acc = 0;
+#pragma unroll
+        for (int x = 0; x < DIM; ++x) acc += I[b][x] * gp[x];
+        f[comp][b] = acc;
+      }
+    }
+  }
+  if (MODE & M_GRADP) {
+    const T s = -JxW * pval;
+#pragma unroll
+    for (int comp = 0; comp < DIM; ++comp)
+#pragma unroll
+      for (int b = 0; b < DIM; ++b) f[comp][b] += s * I[b][comp];
+  }
+  if (MODE & M_DIVU) {
+    T div = 0;
+#pragma unroll
+    for (int comp = 0; comp < DIM; ++comp)
+#pragma unroll
+      for (int b = 0; b < DIM; ++b) div += I[b][comp] * g[comp][b];
+    qv = -JxW * div;
+  }
+  if (MODE & M_MASSP) qv += JxW * pval;
+
+  if (OUT_U) {
+#pragma unroll
+    for (int comp = 0; comp < DIM; ++comp) {
+      const T r = c.integrate_gradient(f[comp]);
+      if (c.valid && !dir) atomic_add(a.dst_u + comp * a.Nv + vnode, r);
+    }
+  }
+  if (OUT_P) {
+    if (c.active) c.b0[c.t] = qv;
+    __syncthreads();
+    const T r = c.template integrate<Sh::M, TAB_SP>(c.b0);
+    if (c.valid && ploc) atomic_add(a.dst_p + pnode, r);
+  }
+}
+
+// ---------------------------------------------------------------- diagonal
+template <int DIM, int K>
+__global__ void __launch_bounds__((Shape<DIM, K, 0>::BLOCK)) laplace_diag_kernel(CellArgs<double> a) {
+  using Sh = Shape<DIM, K, 0>;
+  using T = double;
+  constexpr int NQ = Sh::NQ, CPB = Sh::CPB, Q = Sh::Q, NS = DIM == 2 ? 3 : 6;
+  __shared__ T s_tab[TAB_SIZE];
+  __shared__ T s_G[CPB][NQ * NS];
+  __shared__ T s_X[CPB][Sh::NV * DIM];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < TAB_SIZE; i += Sh::BLOCK) s_tab[i] = a.tab[i];
+  const bool active = tid < Sh::NT;
+  const int e = active ? tid / NQ : CPB - 1;
+  const int t = active ? tid - e * NQ : 0;
+  const int cell = blockIdx.x * CPB + e;
+  const bool valid = active && cell < a.ncells;
+  const int qi = t % Q, qj = (t / Q) % Q, ql = DIM == 3 ? t / (Q * Q) : 0;
+  int cx = 0, cy = 0, cz = 0;
+  if (valid) {
+    cx = cell % a.n0;
+    const int r = cell / a.n0;
+    cy = r % a.n1;
+    cz = DIM == 3 ? r / a.n1 : 0;
+  }
+  if (valid)
+    for (int idx = t; idx < Sh::NV * DIM; idx += NQ) {
+      const int v = idx / DIM, comp = idx % DIM;
+      const int vx = cx + (v & 1), vy = cy + ((v >> 1) & 1), vz = cz + ((v >> 2) & 1);
+      const int64_t vid = vx + (int64_t)(a.n0 + 1) * (vy + (int64_t)(a.n1 + 1) * (DIM == 3 ? vz : 0));
+      s_X[e][idx] = a.X[vid * DIM + comp];
+    }
+  __syncthreads();
+  {
+    T xi[3] = {s_tab[TAB_X + qi], s_tab[TAB_X + qj], DIM == 3 ? s_tab[TAB_X + ql] : T(0)};
+    T J[3][3], I[3][3];
+    q1_jacobian<DIM>(s_X[e], xi, J);
+    const T det = invert<DIM>(J, I);
+    T w = s_tab[TAB_W + qi] * s_tab[TAB_W + qj];
+    if (DIM == 3) w *= s_tab[TAB_W + ql];
+    const T s = det * w * a.nu;
+    // G = s * I I^T (symmetric), stored upper triangle
+    int idx = 0;
+#pragma unroll
+    for (int b = 0; b < DIM; ++b)
+#pragma unroll
+      for (int b2 = b; b2 < DIM; ++b2) {
+        T acc = 0;
+#pragma unroll
+        for (int x = 0; x < DIM; ++x) acc += I[b][x] * I[b2][x];
+        if (active) s_G[e][t * NS + idx] = s * acc;
+        ++idx;
+      }
+  }
+  __syncthreads();
+  // node (qi, qj, ql): sum over points
+  const T *S = s_tab + TAB_S;
+  const T *DS = s_tab + TAB_DS;
+  T d = 0;
+  for (int q = 0; q < NQ; ++q) {
+    const int p0 = q % Q, p1 = (q / Q) % Q, p2 = DIM == 3 ? q / (Q * Q) : 0;
+    T gphi[3];
+    const T v0 = S[p0 * MAXQ + qi], v1 = S[p1 * MAXQ + qj];
+    const T d0 = DS[p0 * MAXQ + qi], d1 = DS[p1 * MAXQ + qj];
+    if (DIM == 2) {
+      gphi[0] = d0 * v1;
+      gphi[1] = v0 * d1;
+    } else {
+      const T v2 = S[p2 * MAXQ + ql], d2 = DS[p2 * MAXQ + ql];
+      gphi[0] = d0 * v1 * v2;
+      gphi[1] = v0 * d1 * v2;
+      gphi[2] = v0 * v1 * d2;
+    }
+    const T *G = &s_G[e][q * NS];
+    int idx = 0;
+#pragma unroll
+    for (int b = 0; b < DIM; ++b)
+#pragma unroll
+      for (int b2 = b; b2 < DIM; ++b2) {
+        const T term = G[idx++] * gphi[b] * gphi[b2];
+        d += b == b2 ? term : 2 * term;
+      }
+  }
+  if (valid) {
+    const int gx = cx * K + qi, gy = cy * K + qj, gz = cz * K + ql;
+    bool dir = gx == 0 || gx == a.nv0 - 1 || gy == 0 || gy == a.nv1 - 1;
+    if (DIM == 3) dir = dir || gz == 0 || gz == a.nv2 - 1;
+    if (!dir) {
+      const int64_t node = gx + (int64_t)a.nv0 * (gy + (int64_t)a.nv1 * gz);
+      atomic_add(a.dst_u + node, d);
+    }
+  }
+}
+
+// diag(M_p)_i = sum_q JxW psi_i(q)^2 (pressure degree KP)
+template <int DIM, int K, int KP>
+__global__ void __launch_bounds__((Shape<DIM, K, KP>::BLOCK)) mass_diag_kernel(CellArgs<double> a) {
+  using Sh = Shape<DIM, K, KP>;
+  using T = double;
+  constexpr int NQ = Sh::NQ, CPB = Sh::CPB, Q = Sh::Q, M = Sh::M;
+  __shared__ T s_tab[TAB_SIZE];
+  __shared__ T s_W[CPB][NQ];
+  __shared__ T s_X[CPB][Sh::NV * DIM];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < TAB_SIZE; i += Sh::BLOCK) s_tab[i] = a.tab[i];
+  const bool active = tid < Sh::NT;
+  const int e = active ? tid / NQ : CPB - 1;
+  const int t = active ? tid - e * NQ : 0;
+  const int cell = blockIdx.x * CPB + e;
+  const bool valid = active && cell < a.ncells;
+  const int qi = t % Q, qj = (t / Q) % Q, ql = DIM == 3 ? t / (Q * Q) : 0;
+  int cx = 0, cy = 0, cz = 0;
+  if (valid) {
+    cx = cell % a.n0;
+    const int r = cell / a.n0;
+    cy = r % a.n1;
+    cz = DIM == 3 ? r / a.n1 : 0;
+  }
+  if (valid)
+    for (int idx = t; idx < Sh::NV * DIM; idx += NQ) {
+      const int v = idx / DIM, comp = idx % DIM;
+      const int vx = cx + (v & 1), vy = cy + ((v >> 1) & 1), vz = cz + ((v >> 2) & 1);
+      const int64_t vid = vx + (int64_t)(a.n0 + 1) * (vy + (int64_t)(a.n1 + 1) * (DIM == 3 ? vz : 0));
+      s_X[e][idx] = a.X[vid * DIM + comp];
+    }
+  __syncthreads();
+  {
+    T xi[3] = {s_tab[TAB_X + qi], s_tab[TAB_X + qj], DIM == 3 ? s_tab[TAB_X + ql] : T(0)};
+    T J[3][3], I[3][3];
+    q1_jacobian<DIM>(s_X[e], xi, J);
+    const T det = invert<DIM>(J, I);
+    T w = s_tab[TAB_W + qi] * s_tab[TAB_W + qj];
+    if (DIM == 3) w *= s_tab[TAB_W + ql];
+    if (active) s_W[e][t] = det * w;
+  }
+  __syncthreads();
+  const bool node = qi < M && qj < M && (DIM == 2 || ql < M);
+  if (!valid || !node) return;
+  const T *Sp = s_tab + TAB_SP;
+  T d = 0;
+  for (int q = 0; q < NQ; ++q) {
+    const int p0 = q % Q, p1 = (q / Q) % Q, p2 = DIM == 3 ? q / (Q * Q) : 0;
+    T v = Sp[p0 * MAXQ + qi] * Sp[p1 * MAXQ + qj];
+    if (DIM == 3) v *= Sp[p2 * MAXQ + ql];
+    d += s_W[e][q] * v * v;
+  }
+  const int64_t pn = (cx * KP + qi) + (int64_t)a.np0 * ((cy * KP + qj) + (int64_t)a.np1 * (cz * KP + ql));
+  atomic_add(a.dst_p + pn, d);
+}
+
+// ---------------------------------------------------------------- setup helpers
+// Gauss-point coordinates, det J check, and load vector share this kernel.
+template <int DIM, int K>
+__global__ void __launch_bounds__((Shape<DIM, K, 0>::BLOCK))
+    point_kernel(CellArgs<double> a, int what, double *out, const double *f_qp, int *bad) {
+  using Sh = Shape<DIM, K, 0>;
+  using T = double;
+  constexpr int NQ = Sh::NQ, CPB = Sh::CPB, Q = Sh::Q;
+  __shared__ T s_tab[TAB_SIZE];
+  __shared__ T s_buf[3][CPB * NQ];
+  __shared__ T s_X[CPB][Sh::NV * DIM];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < TAB_SIZE; i += Sh::BLOCK) s_tab[i] = a.tab[i];
+  CellCtx<DIM, K, 0, T> c;
+  c.active = tid < Sh::NT;
+  const int e = c.active ? tid / NQ : CPB - 1;
+  c.t = c.active ? tid - e * NQ : 0;
+  const int cell = blockIdx.x * CPB + e;
+  c.valid = c.active && cell < a.ncells;
+  c.qi = c.t % Q;
+  c.qj = (c.t / Q) % Q;
+  c.ql = DIM == 3 ? c.t / (Q * Q) : 0;
+  c.cx = c.cy = c.cz = 0;
+  if (c.valid) {
+    c.cx = cell % a.n0;
+    const int r = cell / a.n0;
+    c.cy = r % a.n1;
+    c.cz = DIM == 3 ? r / a.n1 : 0;
+  }
+  c.b0 = &s_buf[0][e * NQ];
+  c.b1 = &s_buf[1][e * NQ];
+  c.b2 = &s_buf[2][e * NQ];
+  c.tab = s_tab;
+  if (c.valid)
+    for (int idx = c.t; idx < Sh::NV * DIM; idx += NQ) {
+      const int v = idx / DIM, comp = idx % DIM;
+      const int vx = c.cx + (v & 1), vy = c.cy + ((v >> 1) & 1), vz = c.cz + ((v >> 2) & 1);
+      const int64_t vid = vx + (int64_t)(a.n0 + 1) * (vy + (int64_t)(a.n1 + 1) * (DIM == 3 ? vz : 0));
+      s_X[e][idx] = a.X[vid * DIM + comp];
+    }
+  __syncthreads();
+  T xi[3] = {s_tab[TAB_X + c.qi], s_tab[TAB_X + c.qj], DIM == 3 ? s_tab[TAB_X + c.ql] : T(0)};
+  T J[3][3], I[3][3];
+  q1_jacobian<DIM>(s_X[e], xi, J);
+  const T det = invert<DIM>(J, I);
+  const int64_t qid = (int64_t)cell * NQ + c.t;
+  if (what == 0) {  // quadrature points
+    if (c.valid)
+      for (int comp = 0; comp < DIM; ++comp) out[qid * DIM + comp] = q1_point<DIM>(s_X[e], xi, comp);
+  } else if (what == 1) {  // geometry check
+    if (c.valid && !(det > 0)) atomicMin(bad, cell);
+  } else {  // load vector
+    T w = s_tab[TAB_W + c.qi] * s_tab[TAB_W + c.qj];
+    if (DIM == 3) w *= s_tab[TAB_W + c.ql];
+    const bool dir = c.valid ? c.vel_dirichlet(a.nv0, a.nv1, a.nv2) : true;
+    const int64_t vnode = c.valid ? c.vel_node(a.nv0, a.nv1) : 0;
+    for (int comp = 0; comp < DIM; ++comp) {
+      const T fv = c.valid ? f_qp[qid * DIM + comp] * det * w : T(0);
+      if (c.active) c.b0[c.t] = fv;
+      __syncthreads();
+      const T r = c.template integrate<Sh::N, TAB_S>(c.b0);
+      __syncthreads();
+      if (c.valid && !dir) atomic_add(out + comp * a.Nv + vnode, r);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- dispatch
+template <typename T>
+static CellArgs<T> make_args(const LevelGeom &g, const T *X, const T *tab) {
+  CellArgs<T> a{};
+  a.n0 = g.n[0];
+  a.n1 = g.n[1];
+  a.n2 = g.n[2];
+  a.ncells = (int)g.ncells;
+  a.nv0 = g.nv[0];
+  a.nv1 = g.nv[1];
+  a.nv2 = g.nv[2];
+  a.np0 = g.np[0];
+  a.np1 = g.np[1];
+  a.np2 = g.np[2];
+  a.Nv = g.Nv;
+  a.Np = g.Np;
+  a.X = X;
+  a.tab = tab;
+  return a;
+}
+
+template <int DIM, int K, int KP, typename T, int MODE>
+static void go(const CellArgs<T> &a, hipStream_t s) {
+  using Sh = Shape<DIM, K, KP>;
+  if (a.ncells == 0) return;
+  const int grid = (a.ncells + Sh::CPB - 1) / Sh::CPB;
+  hipLaunchKernelGGL((cell_kernel<DIM, K, KP, T, MODE>), dim3(grid), dim3(Sh::BLOCK), 0, s, a);
+}
+
+template <int DIM, int K, typename T>
+static void dispatch_mode(const CellArgs<T> &a, int mode, int kp, hipStream_t s) {
+  if (mode == M_LAPLACE) {
+    go<DIM, K, 0, T, M_LAPLACE>(a, s);
+    return;
+  }
+  if constexpr (K >= 2) {
+    MFS_REQUIRE(kp == K - 1, MFS_EUNSUPPORTED, "cell operator needs pressure degree k-1 (got k=%d kp=%d)", K, kp);
+    switch (mode) {
+      case M_LAPLACE | M_GRADP | M_DIVU:
+        go<DIM, K, K - 1, T, M_LAPLACE | M_GRADP | M_DIVU>(a, s);
+        return;
+      case M_GRADP:
+        go<DIM, K, K - 1, T, M_GRADP>(a, s);
+        return;
+      case M_DIVU:
+        go<DIM, K, K - 1, T, M_DIVU>(a, s);
+        return;
+      case M_MASSP:
+        go<DIM, K, K - 1, T, M_MASSP>(a, s);
+        return;
+      default:
+        break;
+    }
+  }
+  MFS_REQUIRE(false, MFS_EUNSUPPORTED, "unsupported cell operator mode %d for k=%d", mode, K);
+}
+
+template <int DIM, typename T>
+static void dispatch_k(const CellArgs<T> &a, int k, int kp, int mode, hipStream_t s) {
+  switch (k) {
+    case 1: dispatch_mode<DIM, 1, T>(a, mode, kp, s); break;
+    case 2: dispatch_mode<DIM, 2, T>(a, mode, kp, s); break;
+    case 3: dispatch_mode<DIM, 3, T>(a, mode, kp, s); break;
+    case 4: dispatch_mode<DIM, 4, T>(a, mode, kp, s); break;
+    case 5: dispatch_mode<DIM, 5, T>(a, mode, kp, s); break;
+    case 6: dispatch_mode<DIM, 6, T>(a, mode, kp, s); break;
+    default: MFS_REQUIRE(false, MFS_EUNSUPPORTED, "degree %d not compiled (1..6)", k);
+  }
+}
+
+template <typename T>
+void launch_cell_op(const LevelGeom &g, const DevLevel<T> &d, int mode, T nu, T *dst_u, T *dst_p,
+                    const T *src_u, const T *src_p, hipStream_t s, bool src_all) {
+  CellArgs<T> a = make_args<T>(g, d.X, d.tab);
+  a.nu = nu;
+  a.src_all = src_all ? 1 : 0;
+  a.dst_u = dst_u;
+  a.dst_p = dst_p;
+  a.src_u = src_u;
+  a.src_p = src_p;
+  if (g.dim == 2)
+    dispatch_k<2, T>(a, g.k, g.kp, mode, s);
+  else
+    dispatch_k<3, T>(a, g.k, g.kp, mode, s);
+  MFS_HIP(hipGetLastError());
+}
+template void launch_cell_op<double>(const LevelGeom &, const DevLevel<double> &, int, double, double *, double *,
+                                     const double *, const double *, hipStream_t, bool);
+template void launch_cell_op<float>(const LevelGeom &, const DevLevel<float> &, int, float, float *, float *,
+                                    const float *, const float *, hipStream_t, bool);
+
+template <int DIM, int K>
+static void go_diag(const CellArgs<double> &a, hipStream_t s) {
+  using Sh = Shape<DIM, K, 0>;
+  const int grid = (a.ncells + Sh::CPB - 1) / Sh::CPB;
+  hipLaunchKernelGGL((laplace_diag_kernel<DIM, K>), dim3(grid), dim3(Sh::BLOCK), 0, s, a);
+}
+template <int DIM, int K>
+static void go_point(const CellArgs<double> &a, int what, double *out, const double *f, int *bad, hipStream_t s) {
+  using Sh = Shape<DIM, K, 0>;
+  const int grid = (a.ncells + Sh::CPB - 1) / Sh::CPB;
+  hipLaunchKernelGGL((point_kernel<DIM, K>), dim3(grid), dim3(Sh::BLOCK), 0, s, a, what, out, f, bad);
+}
+
+#define MFS_K_SWITCH(DIM, k, CALL)                                                  \
+  switch (k) {                                                                      \
+    case 1: CALL(DIM, 1); break;                                                    \
+    case 2: CALL(DIM, 2); break;                                                    \
+    case 3: CALL(DIM, 3); break;                                                    \
+    case 4: CALL(DIM, 4); break;                                                    \
+    case 5: CALL(DIM, 5); break;                                                    \
+    case 6: CALL(DIM, 6); break;                                                    \
+    default: MFS_REQUIRE(false, MFS_EUNSUPPORTED, "degree %d not compiled", (k)); \
+  }
+
+void launch_laplace_diagonal(const LevelGeom &g, const double *X, const double *tab, double nu, double *diag,
+                             hipStream_t s) {
+  CellArgs<double> a = make_args<double>(g, X, tab);
+  a.nu = nu;
+  a.dst_u = diag;
+#define CALL_DIAG(D, K) go_diag<D, K>(a, s)
+  if (g.dim == 2) {
+    MFS_K_SWITCH(2, g.k, CALL_DIAG)
+  } else {
+    MFS_K_SWITCH(3, g.k, CALL_DIAG)
+  }
+#undef CALL_DIAG
+  MFS_HIP(hipGetLastError());
+}
+
+template <int DIM, int K, int KP>
+static void go_mass_diag(const CellArgs<double> &a, hipStream_t s) {
+  using Sh = Shape<DIM, K, KP>;
+  const int grid = (a.ncells + Sh::CPB - 1) / Sh::CPB;
+  hipLaunchKernelGGL((mass_diag_kernel<DIM, K, KP>), dim3(grid), dim3(Sh::BLOCK), 0, s, a);
+}
+template <int DIM, int K>
+static void go_mass_diag_kp(const CellArgs<double> &a, int kp, hipStream_t s) {
+  if (kp == K) {
+    go_mass_diag<DIM, K, K>(a, s);
+    return;
+  }
+  if constexpr (K >= 2) {
+    if (kp == K - 1) {
+      go_mass_diag<DIM, K, K - 1>(a, s);
+      return;
+    }
+  }
+  MFS_REQUIRE(false, MFS_EUNSUPPORTED, "pressure degree %d with k=%d", kp, K);
+}
+
+void launch_mass_diagonal(const LevelGeom &g, const double *X, const double *tab, double *diag, hipStream_t s) {
+  CellArgs<double> a = make_args<double>(g, X, tab);
+  a.dst_p = diag;
+#define CALL_MD(D, K) go_mass_diag_kp<D, K>(a, g.kp, s)
+  if (g.dim == 2) {
+    MFS_K_SWITCH(2, g.k, CALL_MD)
+  } else {
+    MFS_K_SWITCH(3, g.k, CALL_MD)
+  }
+#undef CALL_MD
+  MFS_HIP(hipGetLastError());
+}
+
+static void point_op(const LevelGeom &g, const double *X, const double *tab, int what, double *out,
+                     const double *f, int *bad, hipStream_t s) {
+  CellArgs<double> a = make_args<double>(g, X, tab);
+#define CALL_PT(D, K) go_point<D, K>(a, what, out, f, bad, s)
+  if (g.dim == 2) {
+    MFS_K_SWITCH(2, g.k, CALL_PT)
+  } else {
+    MFS_K_SWITCH(3, g.k, CALL_PT)
+  }
+#undef CALL_PT
+  MFS_HIP(hipGetLastError());
+}
+
+void launch_quadrature_points(const LevelGeom &g, const double *X, const double *tab, double *out,
+                              hipStream_t s) {
+  point_op(g, X, tab, 0, out, nullptr, nullptr, s);
+}
+void launch_check_geometry(const LevelGeom &g, const double *X, const double *tab, int *bad, hipStream_t s) {
+  point_op(g, X, tab, 1, nullptr, nullptr, bad, s);
+}
+void launch_load_vector(const LevelGeom &g, const double *X, const double *tab, const double *f_qp,
+                        double *b_u, hipStream_t s) {
+  point_op(g, X, tab, 2, b_u, f_qp, nullptr, s);
+}
+
+// ---------------------------------------------------------------- Dirichlet fill
+template <typename T>
+__global__ void fill_dirichlet_kernel(int dim, int nv0, int nv1, int nv2, int64_t Nv, T *dst, const T *src) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= Nv) return;
+  const int gx = (int)(i % nv0);
+  const int64_t r = i / nv0;
+  const int gy = (int)(r % nv1);
+  const int gz = (int)(r / nv1);
+  bool d = gx == 0 || gx == nv0 - 1 || gy == 0 || gy == nv1 - 1;
+  if (dim == 3) d = d || gz == 0 || gz == nv2 - 1;
+  for (int c = 0; c < dim; ++c) dst[c * Nv + i] = (d && src) ? src[c * Nv + i] : T(0);
+}
+
+template <typename T>
+void launch_fill_dirichlet(const LevelGeom &g, T *dst_u, const T *src_u, hipStream_t s) {
+  if (g.Nv == 0) return;
+  const int64_t blocks = (g.Nv + 255) / 256;
+  hipLaunchKernelGGL((fill_dirichlet_kernel<T>), dim3((unsigned)blocks), dim3(256), 0, s, g.dim, g.nv[0], g.nv[1],
+                     g.nv[2], g.Nv, dst_u, src_u);
+  MFS_HIP(hipGetLastError());
+}
+template void launch_fill_dirichlet<double>(const LevelGeom &, double *, const double *, hipStream_t);
+template void launch_fill_dirichlet<float>(const LevelGeom &, float *, const float *, hipStream_t);
+
+}  // namespace mfs

@@ -1,0 +1,178 @@
+// Internal declarations of the mfstokes HIP library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/mfstokes.h"
+
+namespace mfs {
+
+// ----------------------------------------------------------------- errors
+void set_error(const char *fmt, ...);
+const char *get_error();
+
+struct Error {
+  int code;
+};
+
+#define MFS_HIP(call)                                                                          \
+  do {                                                                                         \
+    hipError_t e_ = (call);                                                                    \
+    if (e_ != hipSuccess) {                                                                    \
+      ::mfs::set_error("HIP error %s at %s:%d: %s", hipGetErrorName(e_), __FILE__, __LINE__, \
+                       hipGetErrorString(e_));                                                 \
+      throw ::mfs::Error{MFS_EHIP};                                                            \
+    }                                                                                          \
+  } while (0)
+
+#define MFS_REQUIRE(cond, code, ...)    \
+  do {                                  \
+    if (!(cond)) {                      \
+      ::mfs::set_error(__VA_ARGS__);    \
+      throw ::mfs::Error{code};         \
+    }                                   \
+  } while (0)
+
+// ----------------------------------------------------------------- 1D tables
+// Layout of the per-level table array (same layout in FP64 and FP32).
+// Every block is MAXQ x MAXQ, row-major [point][node].
+constexpr int MAXQ = 8;  // degree <= 7
+constexpr int TAB_S = 0;                // velocity basis values at Gauss points  [q][k+1]
+constexpr int TAB_D = 1 * MAXQ * MAXQ;  // collocation derivative on Gauss points [q][q]
+constexpr int TAB_DS = 2 * MAXQ * MAXQ; // velocity basis derivatives at Gauss points [q][k+1]
+constexpr int TAB_SP = 3 * MAXQ * MAXQ; // pressure basis values at Gauss points  [q][kp+1]
+constexpr int TAB_DSP = 4 * MAXQ * MAXQ;// pressure basis derivatives at Gauss points [q][kp+1]
+constexpr int TAB_W = 5 * MAXQ * MAXQ;  // Gauss weights [q]
+constexpr int TAB_X = TAB_W + MAXQ;     // Gauss points [q]
+constexpr int TAB_SIZE = TAB_X + MAXQ;
+
+// host computation of the tables (tables.cpp)
+std::vector<double> gll_nodes(int k);
+void gauss_rule(int q, std::vector<double> &x, std::vector<double> &w);
+// V[i*n + j] = phi_j(x_i) for the Lagrange basis of `nodes`
+std::vector<double> lagrange_values(const std::vector<double> &nodes, const std::vector<double> &x);
+std::vector<double> lagrange_derivs(const std::vector<double> &nodes, const std::vector<double> &x);
+std::vector<double> make_tables(int k, int kp);
+// 1D prolongation matrix [fine points][coarse nodes]: h-embedding (2k+1 x k+1)
+// or p-embedding (kf+1 x kc+1)
+std::vector<double> h_embedding(int k);
+std::vector<double> p_embedding(int kf, int kc);
+
+// ----------------------------------------------------------------- levels
+struct LevelGeom {
+  int dim;
+  int n[3];        // cells per direction (1 in unused directions)
+  int k, kp;       // velocity / pressure degree (kp = 0: no pressure space)
+  int nv[3], np[3];
+  int64_t Nv, Np, ncells;
+};
+
+template <typename T>
+struct DevLevel {
+  const T *X = nullptr;    // vertices [(n0+1)(n1+1)(n2+1)][dim]
+  const T *tab = nullptr;  // 1D tables (TAB_*)
+  const T *invdiag = nullptr;  // inverse diagonal of A, one component [Nv]
+};
+
+// ----------------------------------------------------------------- kernels
+enum CellMode : int {
+  M_LAPLACE = 1,  // velocity: nu (grad u, grad v)
+  M_GRADP = 2,    // velocity rows: -(p, div v)
+  M_DIVU = 4,     // pressure rows: -(div u, q)
+  M_MASSP = 8,    // pressure rows: (p, q)
+};
+
+template <typename T>
+void launch_cell_op(const LevelGeom &g, const DevLevel<T> &d, int mode, T nu, T *dst_u, T *dst_p,
+                    const T *src_u, const T *src_p, hipStream_t s, bool src_all = false);
+// diagonal of the scalar Laplacian block (FP64): diag[Nv]
+void launch_laplace_diagonal(const LevelGeom &g, const double *X, const double *tab, double nu, double *diag,
+                             hipStream_t s);
+// diag(M_p) (FP64), pressure degree g.kp in {k-1, k}
+void launch_mass_diagonal(const LevelGeom &g, const double *X, const double *tab, double *diag, hipStream_t s);
+// r64 = 1/d, r32 = (float)(1/d)
+void launch_reciprocal(double *r64, float *r32, const double *d, int64_t n, hipStream_t s);
+// d[i] = 1 on Dirichlet rows of a scalar velocity-node vector
+void launch_reciprocal_boundary_one(const LevelGeom &g, double *d, hipStream_t s);
+// det J > 0 check: writes the smallest det J * (cells) and the first bad cell
+void launch_check_geometry(const LevelGeom &g, const double *X, const double *tab, int *bad_cell,
+                           hipStream_t s);
+// Gauss point coordinates [ncells][q^dim][dim]
+void launch_quadrature_points(const LevelGeom &g, const double *X, const double *tab, double *out,
+                              hipStream_t s);
+// load vector (f, phi_i) on velocity rows, f at Gauss points
+void launch_load_vector(const LevelGeom &g, const double *X, const double *tab, const double *f_qp,
+                        double *b_u, hipStream_t s);
+
+// Dirichlet fill: dst[c*Nv + i] = boundary(i) ? (src ? src[c*Nv+i] : 0) : 0 for c < dim
+template <typename T>
+void launch_fill_dirichlet(const LevelGeom &g, T *dst_u, const T *src_u, hipStream_t s);
+
+// transfers between a fine level and the next coarser one
+// emb_host: host 1D embedding [F+1][kc+1] (h_embedding / p_embedding)
+template <typename T>
+void launch_prolongate_add(const LevelGeom &fine, const LevelGeom &coarse, bool h_transfer, const double *emb_host,
+                           T *dst_fine, const T *src_coarse, hipStream_t s);
+template <typename T>
+void launch_restrict(const LevelGeom &fine, const LevelGeom &coarse, bool h_transfer, const double *emb_host,
+                     T *dst_coarse, const T *src_fine, hipStream_t s);
+
+// vector kernels (vector_kernels.hip)
+template <typename T>
+void vec_fill(T *x, T v, int64_t n, hipStream_t s);
+template <typename T>
+void vec_copy(T *y, const T *x, int64_t n, hipStream_t s);
+template <typename T>
+void vec_axpby(T *y, T a, const T *x, T b, int64_t n, hipStream_t s);  // y = a x + b y
+template <typename TO, typename TI>
+void vec_cast(TO *y, const TI *x, int64_t n, hipStream_t s);
+template <typename T>
+void vec_zero_mask_boundary(const LevelGeom &g, T *u, hipStream_t s);  // zero Dirichlet rows
+// y *= invdiag (per component); Dirichlet rows forced to 0
+template <typename T>
+void vec_diag_scale(const LevelGeom &g, T *y, const T *invdiag, const T *x, hipStream_t s);
+// inverse diagonal with 1 on Dirichlet rows
+void vec_invert_diag(const LevelGeom &g, const double *diag, double *invdiag64, float *invdiag32, hipStream_t s);
+// Chebyshev step on level vectors (velocity, dim*Nv):
+//   r = invdiag * (b - Ax) ; d = c1 * d + c2 * r ; x += d   (Dirichlet rows untouched)
+template <typename T>
+void cheb_update(const LevelGeom &g, T *x, T *d, const T *b, const T *Ax, const T *invdiag, T c1, T c2,
+                 bool first, hipStream_t s);
+// multiple dot products: out[i] = <V_i, w> for i < m, V_i = V + i*ld (FP64 accumulate)
+template <typename T>
+void multi_dot(const T *V, int64_t ld, int m, const T *w, int64_t n, double *out, double *partials,
+               hipStream_t s);
+// w -= sum_i h[i] V_i  (h on device)
+template <typename T>
+void multi_axpy(T *w, const T *V, int64_t ld, int m, const double *h, int64_t n, hipStream_t s);
+// y = sum_i h[i] V_i (+ y if accumulate)
+template <typename T>
+void multi_combine(T *y, const T *V, int64_t ld, int m, const double *h, int64_t n, bool accumulate,
+                   hipStream_t s);
+// dense coarse solve: out = Ainv * in (FP64 matrix), with casts
+template <typename T>
+void dense_apply(const double *Ainv, int n, const T *in, T *out, hipStream_t s);
+// PCG steps with device-resident scalars (no host round trip):
+//   alpha = rho/pq ; z += alpha p ; res -= alpha q ; s = dinv * res
+template <typename T>
+void pcg_update1(T *z, T *res, T *sv, const T *p, const T *q, const T *dinv, int64_t n, const double *rho,
+                 const double *pq, hipStream_t s);
+//   beta = rho_new / rho_old ; p = s + beta p
+template <typename T>
+void pcg_update2(T *p, const T *sv, int64_t n, const double *rho_new, const double *rho_old, hipStream_t s);
+// y = x / sqrt(*nrm2)
+template <typename T>
+void scale_inv_sqrt(T *y, const T *x, int64_t n, const double *nrm2, hipStream_t s);
+// y = a .* x elementwise
+template <typename T>
+void vec_mul(T *y, const T *a, const T *x, int64_t n, hipStream_t s);
+// p -= (*num / *den) * one_vector   (pressure mean shift)
+void shift_mean(double *p, int64_t n, const double *num, const double *den, hipStream_t s);
+
+constexpr int DOT_BLOCKS = 512;
+
+}  // namespace mfs

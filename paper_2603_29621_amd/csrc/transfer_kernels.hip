@@ -1,0 +1,171 @@
+// Multigrid transfer between a fine level and the next coarser one, Sec. 2
+// eq. (transfer): prolongation x_f = sum_e S_e W_e P_e C_e G_e x_c cell by
+// coarse cell, restriction its transpose.
+//
+// On the structured grid the cell-local embedding P_e is the tensor product
+// of one 1D matrix E (h: the coarse Q_k basis at the 2k+1 nodes of the two
+// children; p: the Q_kc basis at the Q_kf nodes), the weight W = 1/m (m = the
+// number of coarse cells containing a fine node) and the Dirichlet constraint
+// masks are separable per direction.  Both kernels therefore work per global
+// node with no atomics:
+//  * prolongation: thread per fine node, value interpolated from its owning
+//    coarse cell (every coarse cell containing the node yields the same value
+//    because the coarse function is continuous, so the weighted sum over the m
+//    cells equals this single evaluation);
+//  * restriction: thread per coarse node, gathering w * E * r_f over the fine
+//    nodes of every coarse cell that contains it, direction by direction.
+#include "internal.h"
+
+namespace mfs {
+
+struct TransferArgs {
+  int dim;
+  int F;    // fine nodes per coarse cell edge minus one (h: 2k, p: kf)
+  int kc;   // coarse degree
+  int nc[3];          // coarse cells per direction
+  int nf[3], ncn[3];  // fine / coarse node counts per direction
+  int64_t Nf, Nc;
+  double E[MAXQ * 2 * MAXQ];  // [F+1][kc+1], row-major with row stride MAXQ
+};
+
+template <typename T>
+__global__ void k_prolongate_add(TransferArgs a, T *dst, const T *src) {
+  const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (f >= a.Nf) return;
+  int g[3] = {(int)(f % a.nf[0]), (int)((f / a.nf[0]) % a.nf[1]), 0};
+  if (a.dim == 3) g[2] = (int)(f / ((int64_t)a.nf[0] * a.nf[1]));
+  int C[3] = {0, 0, 0}, i[3] = {0, 0, 0};
+  for (int d = 0; d < a.dim; ++d) {
+    if (g[d] == 0 || g[d] == a.nf[d] - 1) return;  // fine Dirichlet row of P is zero
+    C[d] = g[d] / a.F;
+    if (C[d] >= a.nc[d]) C[d] = a.nc[d] - 1;
+    i[d] = g[d] - a.F * C[d];
+  }
+  const int n1 = a.kc + 1;
+  const int nz = a.dim == 3 ? n1 : 1;
+  for (int comp = 0; comp < a.dim; ++comp) {
+    double acc = 0;
+    for (int j2 = 0; j2 < nz; ++j2) {
+      const int c2 = a.dim == 3 ? C[2] * a.kc + j2 : 0;
+      if (a.dim == 3 && (c2 == 0 || c2 == a.ncn[2] - 1)) continue;
+      const double e2 = a.dim == 3 ? a.E[i[2] * MAXQ + j2] : 1.0;
+      for (int j1 = 0; j1 < n1; ++j1) {
+        const int c1 = C[1] * a.kc + j1;
+        if (c1 == 0 || c1 == a.ncn[1] - 1) continue;
+        const double e21 = e2 * a.E[i[1] * MAXQ + j1];
+        for (int j0 = 0; j0 < n1; ++j0) {
+          const int c0 = C[0] * a.kc + j0;
+          if (c0 == 0 || c0 == a.ncn[0] - 1) continue;
+          const int64_t cn = c0 + (int64_t)a.ncn[0] * (c1 + (int64_t)a.ncn[1] * c2);
+          acc += e21 * a.E[i[0] * MAXQ + j0] * (double)src[comp * a.Nc + cn];
+        }
+      }
+    }
+    dst[comp * a.Nf + f] += (T)acc;
+  }
+}
+
+// per direction: list of (fine index, coefficient) contributing to coarse node gc
+__device__ __forceinline__ int restrict_list(const TransferArgs &a, int d, int gc, int *fi, double *cf) {
+  int cnt = 0;
+  const int nc = a.nc[d];
+  int cells[2], nce = 0;
+  int C0 = gc / a.kc;
+  if (C0 < nc) cells[nce++] = C0;
+  if (gc % a.kc == 0 && C0 - 1 >= 0) cells[nce++] = C0 - 1;
+  for (int e = 0; e < nce; ++e) {
+    const int C = cells[e];
+    const int j = gc - a.kc * C;
+    for (int i = 0; i <= a.F; ++i) {
+      const int gf = a.F * C + i;
+      if (gf == 0 || gf == a.nf[d] - 1) continue;  // fine Dirichlet: P row is zero
+      const double m = (gf % a.F == 0) ? 2.0 : 1.0;  // interior shared node of two coarse cells
+      const double v = a.E[i * MAXQ + j] / m;
+      int found = -1;
+      for (int q = 0; q < cnt; ++q)
+        if (fi[q] == gf) found = q;
+      if (found >= 0)
+        cf[found] += v;
+      else {
+        fi[cnt] = gf;
+        cf[cnt] = v;
+        ++cnt;
+      }
+    }
+  }
+  return cnt;
+}
+
+template <typename T>
+__global__ void k_restrict(TransferArgs a, T *dst, const T *src) {
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= a.Nc) return;
+  int g[3] = {(int)(c % a.ncn[0]), (int)((c / a.ncn[0]) % a.ncn[1]), 0};
+  if (a.dim == 3) g[2] = (int)(c / ((int64_t)a.ncn[0] * a.ncn[1]));
+  bool dir = false;
+  for (int d = 0; d < a.dim; ++d) dir = dir || g[d] == 0 || g[d] == a.ncn[d] - 1;
+  if (dir) {
+    for (int comp = 0; comp < a.dim; ++comp) dst[comp * a.Nc + c] = 0;
+    return;
+  }
+  int fi[3][2 * 2 * MAXQ];
+  double cf[3][2 * 2 * MAXQ];
+  int cnt[3] = {1, 1, 1};
+  fi[2][0] = 0;
+  cf[2][0] = 1.0;
+  for (int d = 0; d < a.dim; ++d) cnt[d] = restrict_list(a, d, g[d], fi[d], cf[d]);
+  for (int comp = 0; comp < a.dim; ++comp) {
+    double acc = 0;
+    for (int z = 0; z < cnt[2]; ++z)
+      for (int y = 0; y < cnt[1]; ++y) {
+        const double cyz = cf[2][z] * cf[1][y];
+        const int64_t row = (int64_t)a.nf[0] * (fi[1][y] + (int64_t)a.nf[1] * fi[2][z]);
+        for (int x = 0; x < cnt[0]; ++x) acc += cyz * cf[0][x] * (double)src[comp * a.Nf + row + fi[0][x]];
+      }
+    dst[comp * a.Nc + c] = (T)acc;
+  }
+}
+
+static TransferArgs make_targs(const LevelGeom &fine, const LevelGeom &coarse, bool h, const double *emb_host) {
+  TransferArgs a{};
+  a.dim = fine.dim;
+  a.kc = coarse.k;
+  a.F = h ? 2 * coarse.k : fine.k;
+  for (int d = 0; d < 3; ++d) {
+    a.nc[d] = coarse.n[d];
+    a.nf[d] = fine.nv[d];
+    a.ncn[d] = coarse.nv[d];
+  }
+  a.Nf = fine.Nv;
+  a.Nc = coarse.Nv;
+  for (int i = 0; i <= a.F; ++i)
+    for (int j = 0; j <= a.kc; ++j) a.E[i * MAXQ + j] = emb_host[i * (a.kc + 1) + j];
+  return a;
+}
+
+template <typename T>
+void launch_prolongate_add(const LevelGeom &fine, const LevelGeom &coarse, bool h, const double *emb, T *dst_fine,
+                           const T *src_coarse, hipStream_t s) {
+  const TransferArgs a = make_targs(fine, coarse, h, emb);
+  hipLaunchKernelGGL(k_prolongate_add<T>, dim3((unsigned)((fine.Nv + 255) / 256)), dim3(256), 0, s, a, dst_fine,
+                     src_coarse);
+  MFS_HIP(hipGetLastError());
+}
+template <typename T>
+void launch_restrict(const LevelGeom &fine, const LevelGeom &coarse, bool h, const double *emb, T *dst_coarse,
+                     const T *src_fine, hipStream_t s) {
+  const TransferArgs a = make_targs(fine, coarse, h, emb);
+  hipLaunchKernelGGL(k_restrict<T>, dim3((unsigned)((coarse.Nv + 255) / 256)), dim3(256), 0, s, a, dst_coarse,
+                     src_fine);
+  MFS_HIP(hipGetLastError());
+}
+template void launch_prolongate_add<double>(const LevelGeom &, const LevelGeom &, bool, const double *, double *,
+                                            const double *, hipStream_t);
+template void launch_prolongate_add<float>(const LevelGeom &, const LevelGeom &, bool, const double *, float *,
+                                           const float *, hipStream_t);
+template void launch_restrict<double>(const LevelGeom &, const LevelGeom &, bool, const double *, double *,
+                                      const double *, hipStream_t);
+template void launch_restrict<float>(const LevelGeom &, const LevelGeom &, bool, const double *, float *,
+                                     const float *, hipStream_t);
+
+}  // namespace mfs

@@ -1,0 +1,323 @@
+"""GPU parity of the HIP library against the CPU oracle, through the C ABI.
+
+Tolerances: FP64 results within 1e-12 relative (2-norm and max-norm) of the
+oracle for every operator; FP32 operators within 1e-5 relative; transfers
+and V-cycles in FP64 within 1e-11 (they chain several operators).
+"""
+import numpy as np
+import pytest
+import torch
+
+import inputs
+import paper_2603_29621_amd as mfs
+from oracle import fem, krylov, mg, solve
+
+pytestmark = pytest.mark.gpu
+
+
+def cuda(x, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda", dtype)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+def relerr(y, ref):
+    d = y - ref
+    n2 = np.linalg.norm(ref)
+    ninf = np.abs(ref).max()
+    return max(np.linalg.norm(d) / (n2 if n2 > 0 else 1), np.abs(d).max() / (ninf if ninf > 0 else 1))
+
+
+# (dim, n, k, noise): several workgroups and ragged tails for every degree
+CASES = [
+    (2, [16, 16], 2, 0.0),
+    (2, [7, 5], 2, 0.2),
+    (2, [5, 6], 3, 0.2),
+    (2, [3, 4], 4, 0.2),
+    (2, [2, 3], 6, 0.1),
+    (3, [1, 1, 1], 2, 0.0),
+    (3, [4, 4, 4], 2, 0.2),
+    (3, [5, 3, 4], 2, 0.2),
+    (3, [3, 4, 3], 3, 0.2),
+    (3, [3, 2, 3], 4, 0.2),
+    (3, [2, 2, 3], 5, 0.1),
+    (3, [2, 2, 2], 6, 0.1),
+]
+
+
+def _setup(dim, n, k, noise, nu=0.7, mg_levels=0, **kw):
+    X = inputs.structured_vertices(dim, n, noise=noise, seed=3)
+    opts = mfs.mfs_default_options(mg_levels=mg_levels, **kw)
+    h = mfs.mfs_setup(dim, n, X, k, nu, opts)
+    return h, X
+
+
+@pytest.mark.parametrize("dim,n,k,noise", CASES)
+def test_stokes_operators_fp64(dim, n, k, noise):
+    nu = 0.7
+    h, X = _setup(dim, n, k, noise, nu)
+    try:
+        S = fem.Space(dim, n, X, k)
+        K, mats = fem.stokes_operator(S, nu)
+        mask = S.velocity_dirichlet_mask()
+        nvel = dim * S.Nv
+        assert mfs.mfs_n_dofs(h, 0) == (S.Nv, S.Np)
+        x = inputs.uniform_vector(S.n_dofs, 11)
+        src = cuda(x)
+        dst = torch.empty_like(src)
+        mfs.mfs_vmult(h, mfs.MFS_OP_STOKES, mfs.MFS_FP64, 0, dst, src)
+        assert relerr(host(dst), K @ x) <= 1e-12
+        # blocks
+        Z = (~mask[:nvel]).astype(float)
+        A = fem.constrain(mats["Avec"], mask[:nvel])
+        xu, xp = x[:nvel], x[nvel:]
+        du = torch.empty(nvel, dtype=torch.float64, device="cuda")
+        dp = torch.empty(S.Np, dtype=torch.float64, device="cuda")
+        mfs.mfs_vmult(h, mfs.MFS_OP_A, mfs.MFS_FP64, 0, du, cuda(xu))
+        assert relerr(host(du), A @ xu) <= 1e-12
+        mfs.mfs_vmult(h, mfs.MFS_OP_B, mfs.MFS_FP64, 0, du, cuda(xp))
+        assert relerr(host(du), Z * (mats["B"] @ xp)) <= 1e-12
+        mfs.mfs_vmult(h, mfs.MFS_OP_BT, mfs.MFS_FP64, 0, dp, cuda(xu))
+        assert relerr(host(dp), mats["B"].T @ (Z * xu)) <= 1e-12
+        mfs.mfs_vmult(h, mfs.MFS_OP_MASS_P, mfs.MFS_FP64, 0, dp, cuda(xp))
+        assert relerr(host(dp), mats["M"] @ xp) <= 1e-12
+        # diagonal of the scalar Laplacian (1 on Dirichlet rows)
+        dg = torch.empty(S.Nv, dtype=torch.float64, device="cuda")
+        mfs.mfs_diagonal(h, 0, dg)
+        ref = fem.constrain(mats["A"], S.dirichlet).diagonal()
+        assert relerr(host(dg), ref) <= 1e-12
+    finally:
+        mfs.mfs_destroy(h)
+
+
+@pytest.mark.parametrize("dim,n,k,noise", [CASES[1], CASES[6], CASES[8], CASES[9]])
+def test_stokes_operators_fp32(dim, n, k, noise):
+    nu = 0.7
+    h, X = _setup(dim, n, k, noise, nu)
+    try:
+        S = fem.Space(dim, n, X, k)
+        K, _ = fem.stokes_operator(S, nu)
+        x = inputs.uniform_vector(S.n_dofs, 12).astype(np.float32).astype(np.float64)
+        src = cuda(x, torch.float32)
+        dst = torch.empty_like(src)
+        mfs.mfs_vmult(h, mfs.MFS_OP_STOKES, mfs.MFS_FP32, 0, dst, src)
+        assert relerr(host(dst), K @ x) <= 1e-5
+    finally:
+        mfs.mfs_destroy(h)
+
+
+@pytest.mark.parametrize("k", [2, 3, 4])
+def test_stokes_vmult_full_size_sampled(k):
+    """64^3 cells, vertex noise 0.2h: sampled rows against the oracle, plus
+    symmetry and the pressure null vector at full size."""
+    dim, n, nu = 3, [64, 64, 64], 1.0
+    X = inputs.structured_vertices(dim, n, noise=0.2, seed=0)
+    h = mfs.mfs_setup(dim, n, X, k, nu, mfs.mfs_default_options(mg_levels=0))
+    try:
+        Nv, Np = mfs.mfs_n_dofs(h, 0)
+        N = dim * Nv + Np
+        x = inputs.uniform_vector(N, 1)
+        src = cuda(x)
+        dst = torch.empty_like(src)
+        mfs.mfs_vmult(h, mfs.MFS_OP_STOKES, mfs.MFS_FP64, 0, dst, src)
+        y = host(dst)
+        S = fem.Space(dim, n, X, k)
+        rows = np.unique(np.concatenate([
+            np.random.default_rng(5).choice(N, 400, replace=False),
+            [0, dim * Nv - 1, dim * Nv, N - 1, Nv + Nv // 2, dim * Nv + Np // 2]]))
+        ref = fem.sampled_stokes_rows(S, nu, x, rows)
+        scale = np.abs(ref).max()
+        assert np.abs(y[rows] - ref).max() <= 1e-12 * scale
+        # symmetry: <K x, z> = <x, K z> on free rows
+        z = inputs.uniform_vector(N, 2)
+        dz = torch.empty_like(src)
+        mfs.mfs_vmult(h, mfs.MFS_OP_STOKES, mfs.MFS_FP64, 0, dz, cuda(z))
+        mask = np.zeros(N, dtype=bool)
+        mask[:dim * Nv] = np.tile(S.dirichlet, dim)
+        xf, zf = np.where(mask, 0, x), np.where(mask, 0, z)
+        a, b = y @ zf, xf @ host(dz)
+        assert abs(a - b) <= 1e-11 * (np.abs(y) @ np.abs(zf))
+        # (0, 1_p) is in the kernel
+        one = np.zeros(N)
+        one[dim * Nv:] = 1.0
+        mfs.mfs_vmult(h, mfs.MFS_OP_STOKES, mfs.MFS_FP64, 0, dz, cuda(one))
+        assert np.abs(host(dz)).max() <= 1e-12 * scale
+    finally:
+        mfs.mfs_destroy(h)
+
+
+def test_support_and_quadrature_points():
+    dim, n, k = 3, [3, 2, 4], 3
+    h, X = _setup(dim, n, k, 0.2)
+    try:
+        S = fem.Space(dim, n, X, k)
+        sp_ = mfs.mfs_support_points(h, k, S.Nv, dim)
+        assert np.abs(sp_ - S.support_points()).max() < 1e-14
+        q = mfs.mfs_quadrature_points(h, S.nc, (k + 1) ** dim, dim)
+        assert np.abs(q - S.geometry()[0]).max() < 1e-14
+    finally:
+        mfs.mfs_destroy(h)
+
+
+def test_inverted_cell_rejected():
+    dim, n = 2, [2, 2]
+    X = inputs.structured_vertices(dim, n)
+    X[4] = [0.9, 0.9]  # centre vertex pushed past the far corner: cell 0 folds
+    with pytest.raises(mfs.MfsError) as e:
+        mfs.mfs_setup(dim, n, X, 2, 1.0, mfs.mfs_default_options(mg_levels=0))
+    assert e.value.code == mfs.MFS_EINVAL and "cell" in str(e.value)
+
+
+# ------------------------------------------------------------------ multigrid
+MG_CASES = [(2, [8, 8], 2, 0.2), (2, [4, 6], 3, 0.1), (3, [4, 4, 4], 2, 0.2), (3, [2, 2, 4], 3, 0.2)]
+
+
+def _oracle_hierarchy(dim, n, X, k, nu, cheb_degree):
+    H = mg.Hierarchy(dim, n, X, k, nu, cheb_degree=cheb_degree)
+    for l in range(len(H.spaces) - 1):
+        H.lam[l] = 1.2 * H.exact_lambda_max(l)
+    return H
+
+
+@pytest.mark.parametrize("dim,n,k,noise", MG_CASES)
+def test_levels_transfers_and_lambda(dim, n, k, noise):
+    nu = 1.3
+    h, X = _setup(dim, n, k, noise, nu, mg_levels=1, cheb_degree=3)
+    try:
+        H = _oracle_hierarchy(dim, n, X, k, nu, 3)
+        assert mfs.mfs_n_levels(h) == len(H.spaces)
+        for l, S in enumerate(H.spaces):
+            kl, nl = mfs.mfs_level_info(h, l)
+            assert kl == S.k and nl[:dim] == S.n
+        for l in range(len(H.spaces) - 1):
+            Sf, Sc = H.spaces[l], H.spaces[l + 1]
+            xc = inputs.uniform_vector(dim * Sc.Nv, 20 + l)
+            xf = inputs.uniform_vector(dim * Sf.Nv, 40 + l)
+            y = cuda(xf.copy())
+            mfs.mfs_prolongate_add(h, mfs.MFS_FP64, l, y, cuda(xc))
+            assert relerr(host(y), xf + H.P[l] @ xc) <= 1e-13
+            r = torch.empty(dim * Sc.Nv, dtype=torch.float64, device="cuda")
+            mfs.mfs_restrict(h, mfs.MFS_FP64, l, r, cuda(xf))
+            assert relerr(host(r), H.P[l].T @ xf) <= 1e-13
+            # adjointness of the two GPU kernels
+            yy = torch.zeros(dim * Sf.Nv, dtype=torch.float64, device="cuda")
+            mfs.mfs_prolongate_add(h, mfs.MFS_FP64, l, yy, cuda(xc))
+            lhs = host(r) @ xc
+            rhs = xf @ host(yy)
+            assert abs(lhs - rhs) <= 1e-12 * (abs(lhs) + 1e-30)
+            # Lanczos estimate (20 steps) against the exact largest eigenvalue
+            lam = mfs.mfs_get_lambda(h, l) / 1.2
+            ex = H.exact_lambda_max(l)
+            assert 0.85 * ex <= lam <= ex * (1 + 1e-10)
+    finally:
+        mfs.mfs_destroy(h)
+
+
+@pytest.mark.parametrize("dim,n,k,noise", MG_CASES)
+def test_vcycle_and_block_preconditioner_fp64(dim, n, k, noise):
+    nu = 1.3
+    h, X = _setup(dim, n, k, noise, nu, mg_levels=1, cheb_degree=3, schur_iterations=7)
+    try:
+        sysm = krylov.StokesSystem(dim, n, X, k, nu, schur_iterations=7, cheb_degree=3)
+        H = sysm.mg
+        for l in range(len(H.spaces) - 1):
+            H.lam[l] = 1.2 * H.exact_lambda_max(l)
+            mfs.mfs_set_lambda(h, l, H.lam[l])
+        S = sysm.S
+        nvel = dim * S.Nv
+        b = inputs.uniform_vector(nvel, 3)
+        out = torch.empty(nvel, dtype=torch.float64, device="cuda")
+        mfs.mfs_vcycle(h, mfs.MFS_FP64, out, cuda(b))
+        assert relerr(host(out), H.vcycle(b)) <= 1e-11
+        r = inputs.uniform_vector(S.n_dofs, 4)
+        y = torch.empty(S.n_dofs, dtype=torch.float64, device="cuda")
+        mfs.mfs_precondition(h, mfs.MFS_FP64, y, cuda(r))
+        assert relerr(host(y), sysm.precondition(r)) <= 1e-11
+        # FP32 preconditioner: same operator in single precision
+        y32 = torch.empty(S.n_dofs, dtype=torch.float32, device="cuda")
+        mfs.mfs_precondition(h, mfs.MFS_FP32, y32, cuda(r, torch.float32))
+        assert relerr(host(y32), sysm.precondition(r)) <= 1e-4
+    finally:
+        mfs.mfs_destroy(h)
+
+
+# ------------------------------------------------------------------ solves
+def _ms_rhs_gpu(h, dim, n, k, S, nu):
+    nq = (k + 1) ** dim
+    q = mfs.mfs_quadrature_points(h, S.nc, nq, dim)
+    ms = inputs.manufactured_2d if dim == 2 else inputs.manufactured_3d
+    f = ms(q, nu)[2]
+    uD = ms(mfs.mfs_support_points(h, k, S.Nv, dim), nu)[0]
+    b = torch.empty(S.n_dofs, dtype=torch.float64, device="cuda")
+    mfs.mfs_rhs(h, cuda(f), cuda(uD.T.ravel()), b)
+    return b, f, uD
+
+
+@pytest.mark.parametrize("dim,n,k", [(2, [16, 16], 2), (3, [4, 4, 4], 2), (3, [4, 4, 4], 3)])
+def test_rhs_matches_oracle(dim, n, k):
+    nu = 0.5
+    h, X = _setup(dim, n, k, 0.2, nu, mg_levels=0)
+    try:
+        S = fem.Space(dim, n, X, k)
+        b, f, uD = _ms_rhs_gpu(h, dim, n, k, S, nu)
+        ref = solve.stokes_rhs(S, nu, f, uD)
+        assert relerr(host(b), ref) <= 1e-12
+    finally:
+        mfs.mfs_destroy(h)
+
+
+@pytest.mark.parametrize("prec", [mfs.MFS_FP64, mfs.MFS_FP32])
+def test_solve_2d_q2q1_16x16(prec):
+    """2D Q2/Q1 on the 16x16 unit square, nu = 1, manufactured solution,
+    Chebyshev degree 3, FGMRES to 1e-10: compare with the oracle's exact
+    solution and, for the FP64 preconditioner, its FGMRES iteration count."""
+    dim, n, k, nu = 2, [16, 16], 2, 1.0
+    X = inputs.structured_vertices(dim, n)
+    opts = mfs.mfs_default_options(cheb_degree=3, rtol=1e-10, precond_precision=prec)
+    h = mfs.mfs_setup(dim, n, X, k, nu, opts)
+    try:
+        S = fem.Space(dim, n, X, k)
+        b, f, uD = _ms_rhs_gpu(h, dim, n, k, S, nu)
+        x = torch.zeros_like(b)
+        info = mfs.mfs_solve(h, b, x, opts)
+        assert info.status == 0 and info.rel_residual <= 1e-10
+        xs = host(x)
+        mats = fem.assemble_stokes(S, nu)
+        bref = solve.stokes_rhs(S, nu, f, uD, mats)
+        xd = solve.pressure_mean_free(S, solve.direct_solve(S, nu, bref, mats), mats["M"])
+        err = np.linalg.norm(xs - xd) / np.linalg.norm(xd)
+        assert err <= 1e-8, err
+        assert info.iterations <= 40
+        if prec == mfs.MFS_FP64:
+            sysm = krylov.StokesSystem(dim, n, X, k, nu, cheb_degree=3)
+            for l in range(len(sysm.mg.spaces) - 1):
+                sysm.mg.lam[l] = mfs.mfs_get_lambda(h, l)
+            _, its, _ = krylov.fgmres(sysm.K, bref, sysm.precondition, krylov.lifting(sysm.mask, bref), rtol=1e-10)
+            assert abs(its - info.iterations) <= 1
+    finally:
+        mfs.mfs_destroy(h)
+
+
+def test_solve_3d_mixed_precision():
+    dim, n, k, nu = 3, [8, 8, 8], 2, 1.0
+    X = inputs.structured_vertices(dim, n, noise=0.2, seed=0)
+    opts = mfs.mfs_default_options(rtol=1e-8, precond_precision=mfs.MFS_FP32)
+    h = mfs.mfs_setup(dim, n, X, k, nu, opts)
+    try:
+        S = fem.Space(dim, n, X, k)
+        b, f, uD = _ms_rhs_gpu(h, dim, n, k, S, nu)
+        x = torch.zeros_like(b)
+        info = mfs.mfs_solve(h, b, x, opts)
+        assert info.status == 0 and info.rel_residual <= 1e-8
+        mats = fem.assemble_stokes(S, nu)
+        K = fem.constrain(mats["K"], S.velocity_dirichlet_mask())
+        bref = solve.stokes_rhs(S, nu, f, uD, mats)
+        xs = host(x)
+        assert np.linalg.norm(bref - K @ xs) <= 1.01e-8 * np.linalg.norm(bref)
+        xd = solve.pressure_mean_free(S, solve.direct_solve(S, nu, bref, mats), mats["M"])
+        assert np.linalg.norm(xs - xd) <= 1e-6 * np.linalg.norm(xd)
+    finally:
+        mfs.mfs_destroy(h)
