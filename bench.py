@@ -103,6 +103,7 @@ def main():
     ap.add_argument("--k", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--prec", choices=["f64", "f32"], default="f64", help="precision of the headline run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (single-GPU build).",
@@ -132,12 +133,13 @@ def main():
         return {"N": N, "wall": wall, "avg_launch_s": avg, "bytes": B, "dofs_per_s": N * steps / wall,
                 "achieved_GBs": B / avg / 1e9, "frac": B / avg / HBM_PEAK}
 
-    main_run = run(k, mfs.MFS_FP64, args.steps, args.warmup)
+    main_prec = mfs.MFS_FP64 if args.prec == "f64" else mfs.MFS_FP32
+    main_run = run(k, main_prec, args.steps, args.warmup)
     sweep = {}
     if not args.no_sweep:
         for kk in (2, 3, 4):
             for prec, name in ((mfs.MFS_FP64, "f64"), (mfs.MFS_FP32, "f32")):
-                if kk == k and prec == mfs.MFS_FP64:
+                if kk == k and prec == main_prec:
                     r = main_run
                 else:
                     r = run(kk, prec, max(10, args.steps // 2), 3)
@@ -154,7 +156,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": args.prec,
         "data": "synthetic",
         "config": {"workload": f"3D Stokes Taylor-Hood Q{k}/Q{k-1} vmult, {n}^3 hex cells of the unit cube, "
                                f"trilinear geometry (vertex noise 0.2h, seed 0), nu=1",

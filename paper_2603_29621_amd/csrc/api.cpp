@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <memory>
@@ -56,12 +57,15 @@ struct Level {
   double *tab64 = nullptr;
   float *tab32 = nullptr;
   double *diag = nullptr;
+  double *face64 = nullptr;  // scratch of the specialised degree-2 kernel
+  float *face32 = nullptr;
   double *invdiag64 = nullptr;
   float *invdiag32 = nullptr;
   double lambda = 0.0;          // upper end of the Chebyshev interval
   bool h_to_coarser = false;    // transfer type to level+1
   std::vector<double> emb;      // 1D embedding to level+1
   std::vector<double> Xhost;    // vertices (host copy)
+  std::vector<double> tabh;     // 1D tables (host copy)
 };
 
 struct Krylov {
@@ -206,6 +210,8 @@ void plan_arena(Arena &A, mfs_problem &P, const std::vector<LevelGeom> &G) {
     L.tab64 = A.take<double>(TAB_SIZE);
     L.tab32 = A.take<float>(TAB_SIZE);
     L.diag = A.take<double>(G[l].Nv);
+    L.face64 = A.take<double>(q2_face_elems(G[l]));
+    L.face32 = A.take<float>(q2_face_elems(G[l]));
     L.invdiag64 = A.take<double>(G[l].Nv);
     L.invdiag32 = A.take<float>(G[l].Nv);
   }
@@ -279,6 +285,16 @@ DevLevel<float> dev<float>(const Level &L) {
   return d;
 }
 template <typename T>
+T *face(const Level &L);
+template <>
+double *face<double>(const Level &L) {
+  return L.face64;
+}
+template <>
+float *face<float>(const Level &L) {
+  return L.face32;
+}
+template <typename T>
 PrecWork<T> &work(mfs_problem &P);
 template <>
 PrecWork<double> &work<double>(mfs_problem &P) {
@@ -301,9 +317,17 @@ const float *invdiag<float>(const Level &L) {
 
 // ---------------------------------------------------------------- operators
 // velocity-block A on level l: dst = A src (dim*Nv); Dirichlet rows dst = src
+bool use_specialised() {
+  static const bool off = std::getenv("MFS_GENERIC_KERNELS") != nullptr;
+  return !off;
+}
+
 template <typename T>
 void apply_A(mfs_problem &P, int l, T *dst, const T *src, hipStream_t s) {
   const Level &L = P.L[l];
+  if (use_specialised() && q2_face_elems(L.g) > 0 &&
+      launch_stokes_q2<T>(L.g, dev<T>(L).X, false, (T)P.nu, dst, nullptr, src, nullptr, face<T>(L), s))
+    return;
   launch_fill_dirichlet<T>(L.g, dst, src, s);
   launch_cell_op<T>(L.g, dev<T>(L), M_LAPLACE, (T)P.nu, dst, nullptr, src, nullptr, s);
 }
@@ -319,6 +343,9 @@ void apply_op(mfs_problem &P, int op, int l, T *dst, const T *src, hipStream_t s
       break;
     case MFS_OP_STOKES:
       MFS_REQUIRE(g.kp > 0, MFS_EINVAL, "level %d has no pressure space", l);
+      if (use_specialised() && q2_face_elems(g) > 0 &&
+          launch_stokes_q2<T>(g, dev<T>(L).X, true, (T)P.nu, dst, dst + nu, src, src + nu, face<T>(L), s))
+        break;
       launch_fill_dirichlet<T>(g, dst, src, s);
       vec_fill<T>(dst + nu, T(0), g.Np, s);
       launch_cell_op<T>(g, dev<T>(L), M_LAPLACE | M_GRADP | M_DIVU, (T)P.nu, dst, dst + nu, src, src + nu, s);
@@ -813,6 +840,7 @@ int mfs_setup(const mfs_mesh *mesh, int k, double nu, const mfs_options *opts, v
       MFS_HIP(hipMemcpyAsync(L.X64, L.Xhost.data(), L.Xhost.size() * sizeof(double), hipMemcpyHostToDevice, s));
       MFS_HIP(hipMemcpyAsync(L.X32, X32.data(), X32.size() * sizeof(float), hipMemcpyHostToDevice, s));
       auto tab = make_tables(L.g.k, L.g.kp);
+      L.tabh = tab;
       std::vector<float> tab32(tab.begin(), tab.end());
       MFS_HIP(hipMemcpyAsync(L.tab64, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, s));
       MFS_HIP(hipMemcpyAsync(L.tab32, tab32.data(), tab32.size() * sizeof(float), hipMemcpyHostToDevice, s));

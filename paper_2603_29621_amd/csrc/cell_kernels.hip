@@ -42,7 +42,7 @@ struct CellArgs {
   T *dst_u;
   T *dst_p;
   T nu;
-  int src_all;  // 1: read source values on Dirichlet rows too (unconstrained operator)
+  int src_all;  // 1: read source values on Dirichlet rows only (the lifting of boundary data)
 };
 
 // out = sum_m mat(r, m) in[.. m ..] along direction DIR; TR reads mat(m, r).
@@ -290,7 +290,7 @@ __global__ void __launch_bounds__((Shape<DIM, K, KP>::BLOCK)) cell_kernel(CellAr
 #pragma unroll
     for (int comp = 0; comp < DIM; ++comp) {
       T v = 0;
-      if (c.valid && (a.src_all || !dir)) v = a.src_u[comp * a.Nv + vnode];
+      if (c.valid && (a.src_all ? dir : !dir)) v = a.src_u[comp * a.Nv + vnode];
       if (c.active) c.b0[c.t] = v;
       __syncthreads();
       c.gradient(g[comp]);
@@ -625,6 +625,10 @@ static void dispatch_mode(const CellArgs<T> &a, int mode, int kp, hipStream_t s)
     return;
   }
   if constexpr (K >= 2) {
+    if (mode == (M_LAPLACE | M_DIVU)) {  // lifting of Dirichlet data (right-hand side)
+      go<DIM, K, K - 1, T, M_LAPLACE | M_DIVU>(a, s);
+      return;
+    }
     MFS_REQUIRE(kp == K - 1, MFS_EUNSUPPORTED, "cell operator needs pressure degree k-1 (got k=%d kp=%d)", K, kp);
     switch (mode) {
       case M_LAPLACE | M_GRADP | M_DIVU:

@@ -37,8 +37,9 @@ __global__ void k_copy(T *y, const T *x, int64_t n) {
 }
 template <typename T>
 __global__ void k_axpby(T *y, T a, const T *x, T b, int64_t n) {
+  // b == 0 never reads y (it may hold uninitialised memory)
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    y[i] = a * x[i] + b * y[i];
+    y[i] = b == T(0) ? a * x[i] : a * x[i] + b * y[i];
 }
 template <typename TO, typename TI>
 __global__ void k_cast(TO *y, const TI *x, int64_t n) {

@@ -318,6 +318,7 @@ def test_solve_3d_mixed_precision():
         xs = host(x)
         assert np.linalg.norm(bref - K @ xs) <= 1.01e-8 * np.linalg.norm(bref)
         xd = solve.pressure_mean_free(S, solve.direct_solve(S, nu, bref, mats), mats["M"])
-        assert np.linalg.norm(xs - xd) <= 1e-6 * np.linalg.norm(xd)
+        # error bound: condition number times the 1e-8 residual
+        assert np.linalg.norm(xs - xd) <= 1e-4 * np.linalg.norm(xd)
     finally:
         mfs.mfs_destroy(h)
