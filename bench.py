@@ -94,6 +94,49 @@ def cpu_baseline_oracle(n=12, k=2):
                       f"{reps} repetitions, element loop with element matrices by full quadrature, 1 thread"}
 
 
+def solve_section(mfs, torch, inputs, args):
+    """3D Q2/Q1 solve on the same perturbed mesh to a 1e-8 relative residual:
+    FP32 multigrid preconditioner inside FP64 FGMRES vs the plain FP64 method."""
+    from paper_2603_29621_amd import serving
+
+    n, k = args.solve_n, 2
+    req = inputs.Request(0, 0.0, n, k, 1.0, 0.2, 0)
+    out = {"workload": f"3D Stokes Q2/Q1 {n}^3 cells, vertex noise 0.2h, nu=1, manufactured solution, rtol 1e-8"}
+    for name, prec in (("fp32_mg_fp64_fgmres", mfs.MFS_FP32), ("fp64", mfs.MFS_FP64)):
+        opts = mfs.mfs_default_options(precond_precision=prec, rtol=1e-8, maxit=300)
+        s = torch.cuda.Stream()
+        t0 = time.perf_counter()
+        h, b, x = serving._setup_request(req, opts, s)
+        t1 = time.perf_counter()
+        times, its, res = [], 0, 0.0
+        for rep in range(2):
+            x.zero_()
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            info = mfs.mfs_solve(h, b, x, opts, stream=s.cuda_stream)
+            times.append(time.perf_counter() - t2)
+            its, res = info.iterations, info.rel_residual
+        mfs.mfs_destroy(h)
+        out[name] = {"setup_s": t1 - t0, "solve_s": min(times), "solves_per_s": 1.0 / min(times),
+                     "iterations": its, "rel_residual": res}
+    out["speedup_mixed_vs_fp64"] = out["fp64"]["solve_s"] / out["fp32_mg_fp64_fgmres"]["solve_s"]
+    return out
+
+
+def serving_section(args):
+    """Bounded sample of the served stream: Poisson arrivals, n in {8, 16, 32},
+    k in {2, 3}; continuous batching with FP32 multigrid vs sequential FP64."""
+    import inputs
+    from paper_2603_29621_amd import serving
+
+    reqs = inputs.request_stream(args.serve_requests, args.serve_rate, seed=0, sizes=(8, 16, 32), degrees=(2, 3))
+    served = serving.Server(200e9).run(reqs)
+    seq = serving.run_sequential(reqs)
+    return {"sample": f"{args.serve_requests} requests, Poisson rate {args.serve_rate}/s, n in {{8,16,32}}, "
+                      f"k in {{2,3}}, nu log-uniform [1e-2, 1], noise 0.1h, rtol 1e-8",
+            "served_fp32_mg": serving.summarize(served), "sequential_fp64": serving.summarize(seq)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,6 +147,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--prec", choices=["f64", "f32"], default="f64", help="precision of the headline run")
+    ap.add_argument("--no-solve", action="store_true", help="skip the solve and served-stream measurements")
+    ap.add_argument("--solve-n", type=int, default=64)
+    ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--serve-rate", type=float, default=8.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (single-GPU build).",
@@ -166,6 +213,9 @@ def main():
                      "bytes_per_launch": main_run["bytes"], "avg_launch_us": main_run["avg_launch_s"] * 1e6},
         "sweep": sweep,
     }
+    if not args.no_solve:
+        line["solve"] = solve_section(mfs, torch, inputs, args)
+        line["serving"] = serving_section(args)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline_oracle()
     print(json.dumps(line))

@@ -146,6 +146,10 @@ int mfs_support_points(const mfs_problem *p, int deg, double *host_xyz);
  * in cell order and lexicographic point order (host buffer). */
 int mfs_quadrature_points(const mfs_problem *p, double *host_xyz);
 
+/* Same coordinates written to a device buffer (FP64, same layout), enqueued on
+ * `stream`. */
+int mfs_quadrature_points_device(const mfs_problem *p, double *dev_xyz, void *stream);
+
 /*
  * dst = op(src) on level `level` (0 = finest) in precision `prec`.
  * Lengths: STOKES and NS_JACOBIAN: dim*n_u + n_p -> same; A: dim*n_u -> dim*n_u;

@@ -147,6 +147,41 @@ def manufactured_3d(x: np.ndarray, nu: float = 1.0):
     return u, p, f
 
 
+def manufactured_forcing_3d_torch(x, nu: float):
+    """Forcing f = -nu Lap(u) + grad(p) of ``manufactured_3d`` for a torch
+    tensor x [..., 3] (evaluated where x lives, e.g. on the device)."""
+    import torch
+
+    pi = math.pi
+    X, Y, Z = x[..., 0], x[..., 1], x[..., 2]
+
+    def s(t):
+        return torch.sin(pi * t) ** 2
+
+    def s1(t):
+        return pi * torch.sin(2 * pi * t)
+
+    def s2(t):
+        return 2 * pi ** 2 * torch.cos(2 * pi * t)
+
+    def s3(t):
+        return -4 * pi ** 3 * torch.sin(2 * pi * t)
+
+    sx, sy, sz = s(X), s(Y), s(Z)
+    s1x, s1y, s1z = s1(X), s1(Y), s1(Z)
+    s2x, s2y, s2z = s2(X), s2(Y), s2(Z)
+    s3x, s3y, s3z = s3(X), s3(Y), s3(Z)
+    lap_psi_x = s3x * sy * sz + s1x * s2y * sz + s1x * sy * s2z
+    lap_psi_y = s2x * s1y * sz + sx * s3y * sz + sx * s1y * s2z
+    lap_psi_z = s2x * sy * s1z + sx * s2y * s1z + sx * sy * s3z
+    cx, cy, cz = torch.cos(pi * X), torch.cos(pi * Y), torch.cos(pi * Z)
+    snx, sny, snz = torch.sin(pi * X), torch.sin(pi * Y), torch.sin(pi * Z)
+    f = torch.stack([-nu * (lap_psi_y - lap_psi_z) - pi * snx * cy * cz,
+                     -nu * (lap_psi_z - lap_psi_x) - pi * cx * sny * cz,
+                     -nu * (lap_psi_x - lap_psi_y) - pi * cx * cy * snz], -1)
+    return f
+
+
 def manufactured_inhomogeneous_3d(x: np.ndarray, nu: float = 1.0):
     """u = (sin pi y, sin pi z, sin pi x), p = 0: divergence free, nonzero on
     the boundary, Lap u = -pi^2 u.  Returns (u, p, f)."""

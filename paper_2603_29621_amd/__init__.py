@@ -34,7 +34,8 @@ MFS_OP_NS_JACOBIAN = 5
 
 EXPORTED = [
     "mfs_default_options", "mfs_last_error", "mfs_footprint", "mfs_setup", "mfs_destroy", "mfs_n_dofs",
-    "mfs_n_levels", "mfs_level_info", "mfs_support_points", "mfs_quadrature_points", "mfs_vmult",
+    "mfs_n_levels", "mfs_level_info", "mfs_support_points", "mfs_quadrature_points",
+    "mfs_quadrature_points_device", "mfs_vmult",
     "mfs_diagonal", "mfs_get_lambda", "mfs_set_lambda", "mfs_vcycle", "mfs_prolongate_add", "mfs_restrict",
     "mfs_precondition", "mfs_rhs", "mfs_solve", "mfs_solve_begin", "mfs_solve_advance",
     "mfs_set_linearization",
@@ -101,6 +102,7 @@ def lib():
         L.mfs_level_info.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
         L.mfs_support_points.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
         L.mfs_quadrature_points.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+        L.mfs_quadrature_points_device.argtypes = [vp, vp, vp]
         L.mfs_vmult.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp]
         L.mfs_diagonal.argtypes = [vp, ctypes.c_int, vp, vp]
         L.mfs_get_lambda.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
@@ -208,6 +210,10 @@ def mfs_quadrature_points(h, n_cells, n_q, dim):
     out = np.zeros((n_cells, n_q, dim))
     _check(lib().mfs_quadrature_points(h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
     return out
+
+
+def mfs_quadrature_points_device(h, dst, stream=None):
+    _check(lib().mfs_quadrature_points_device(h, _ptr(dst), _stream(stream)))
 
 
 def mfs_vmult(h, op, prec, level, dst, src, stream=None):

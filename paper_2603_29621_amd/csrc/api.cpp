@@ -1030,6 +1030,15 @@ int mfs_quadrature_points(const mfs_problem *p, double *xyz) {
   });
 }
 
+int mfs_quadrature_points_device(const mfs_problem *p, double *xyz, void *stream) {
+  return guard([&] {
+    check_problem(p);
+    MFS_REQUIRE(xyz != nullptr, MFS_EINVAL, "buffer is NULL");
+    const Level &L = p->L[0];
+    launch_quadrature_points(L.g, L.X64, L.tab64, xyz, S(stream));
+  });
+}
+
 int mfs_vmult(mfs_problem *p, int op, int prec, int level, void *dst, const void *src, void *stream) {
   return guard([&] {
     check_level(p, level);
