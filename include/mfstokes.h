@@ -93,9 +93,9 @@ typedef struct mfs_options {
   double rtol;           /* FGMRES relative residual target */
   int precond_precision; /* MFS_FP32 or MFS_FP64 for the block preconditioner */
   uint64_t seed;         /* seed of the Lanczos start vector */
-  /* Navier-Stokes linearisation (Sec. 5); used only by MFS_OP_NS_JACOBIAN */
-  double dt;             /* BDF2 time step; mass shift alpha = 3/(2 dt) */
-  int newton;            /* 1: Newton (full Gateaux derivative); 0: Oseen */
+  /* monolithic Navier-Stokes multigrid (Sec. 5) */
+  int relax_steps;       /* damped point-Jacobi sweeps before and after the coarse correction (5) */
+  double relax_omega;    /* Jacobi damping omega (0.5) */
 } mfs_options;
 
 typedef struct mfs_solve_info {
@@ -125,6 +125,11 @@ int mfs_footprint(const mfs_mesh *mesh, int k, const mfs_options *opts, size_t *
  * halving n while every n is even and > coarse_min_cells; Sec. 3), the
  * inverse diagonals, the Chebyshev bounds (Lanczos estimate, host readback),
  * and the FP64 coarse-level inverse.  k in [1, 6] (Taylor-Hood: k >= 2).
+ * With pressure_offset = 0 the problem is the equal-order SUPG/PSPG
+ * Navier-Stokes system of Sec. 5 instead: the hierarchy coarsens the mesh
+ * first and the degree afterwards (h-levels, then p-levels down to p_min),
+ * every level is equal order, k <= 2 with mg_levels = 1 and k <= 3 without,
+ * and the operator data is computed by mfs_set_linearization.
  * Returns a handle owned by the caller, released by mfs_destroy.  Runs on
  * `stream` and synchronises it before returning.
  */
@@ -133,7 +138,8 @@ int mfs_setup(const mfs_mesh *mesh, int k, double nu, const mfs_options *opts, v
 int mfs_destroy(mfs_problem *p);
 
 /* Sizes at level `level` (0 = finest): scalar velocity nodes per component and
- * pressure nodes (0 on levels without pressure). */
+ * pressure nodes (0 on levels without pressure; n_u on every level of a
+ * Navier-Stokes problem). */
 int mfs_n_dofs(const mfs_problem *p, int level, int64_t *n_u, int64_t *n_p);
 int mfs_n_levels(const mfs_problem *p, int *n_levels);
 /* degree and cells per direction of a level */
@@ -154,12 +160,16 @@ int mfs_quadrature_points_device(const mfs_problem *p, double *dev_xyz, void *st
  * dst = op(src) on level `level` (0 = finest) in precision `prec`.
  * Lengths: STOKES and NS_JACOBIAN: dim*n_u + n_p -> same; A: dim*n_u -> dim*n_u;
  * B: n_p -> dim*n_u; BT: dim*n_u -> n_p; MASS_P: n_p -> n_p.
- * STOKES, B, BT, MASS_P need a level with pressure (level 0).  Enqueue only.
+ * STOKES, B, BT, MASS_P need a level with pressure (level 0).  NS_JACOBIAN
+ * works on every level of a Navier-Stokes problem after
+ * mfs_set_linearization (the level's own rediscretised Jacobian).  Enqueue
+ * only.
  */
 int mfs_vmult(mfs_problem *p, int op, int prec, int level, void *dst, const void *src, void *stream);
 
 /* dst = diag(A) on `level` for one velocity component (n_u entries; 1 on
- * Dirichlet rows), FP64. */
+ * Dirichlet rows), FP64.  Navier-Stokes problem: the diagonal of the
+ * level's Jacobian, (dim+1)*n_u entries (after mfs_set_linearization). */
 int mfs_diagonal(mfs_problem *p, int level, double *dst, void *stream);
 
 /* Chebyshev bound used by the smoother on `level` (after setup). */
@@ -170,13 +180,18 @@ int mfs_set_lambda(mfs_problem *p, int level, double lambda_max);
 /*
  * dst = one multigrid V-cycle on the velocity block A applied to src
  * (approximates A^{-1} src, Sec. 3), initial guess 0 on free rows and src on
- * Dirichlet rows.  Vectors dim*n_u long in precision `prec`.  Enqueue only.
+ * Dirichlet rows.  Vectors dim*n_u long in precision `prec`.  Navier-Stokes
+ * problem: one monolithic V-cycle on J (Sec. 5; damped Jacobi relaxation,
+ * pinned direct coarse solve, see mfs_set_linearization) on full vectors.
+ * Enqueue only.
  */
 int mfs_vcycle(mfs_problem *p, int prec, void *dst, const void *src, void *stream);
 
 /* Multigrid transfer between level `fine` and level fine+1 (Sec. 2
  * eq. (transfer)): dst_fine += P src_coarse (prolongate) or
- * dst_coarse = P^T src_fine (restrict).  Velocity vectors of the two levels. */
+ * dst_coarse = P^T src_fine (restrict).  Velocity vectors of the two levels;
+ * full vectors of a Navier-Stokes problem, whose pressure component is
+ * transferred without constraints. */
 int mfs_prolongate_add(mfs_problem *p, int prec, int fine, void *dst_fine, const void *src_coarse, void *stream);
 int mfs_restrict(mfs_problem *p, int prec, int fine, void *dst_coarse, const void *src_fine, void *stream);
 
@@ -184,6 +199,7 @@ int mfs_restrict(mfs_problem *p, int prec, int fine, void *dst_coarse, const voi
  * dst = P^{-1} src, the block-triangular preconditioner of eq. (stokes_block):
  * y_p = -(nu^{-1} M_p)^{-1} r_p by `schur_iterations` Jacobi-PCG steps,
  * y_u = Vcycle(r_u - B y_p).  Full-length vectors in precision `prec`.
+ * Navier-Stokes problem: one monolithic V-cycle (as mfs_vcycle).
  */
 int mfs_precondition(mfs_problem *p, int prec, void *dst, const void *src, void *stream);
 
@@ -205,7 +221,11 @@ int mfs_rhs(mfs_problem *p, const double *f_qp, const double *u_dirichlet, doubl
  * FP64), x0 = lifting of b's Dirichlet rows.  b, x: device FP64 full length.
  * Host-synchronous (one readback per iteration).  The pressure is returned
  * with zero mass-weighted mean.  MFS_ENOCONV if rtol is not reached within
- * maxit (x holds the last iterate, info filled).
+ * maxit (x holds the last iterate, info filled).  Navier-Stokes problem:
+ * K = the Jacobian J at the linearisation point, preconditioner = one
+ * monolithic V-cycle; J is singular (constant pressures), so b must have
+ * pressure rows summing to zero (true for b = J y); the pressure is returned
+ * with zero nodal mean.
  */
 int mfs_solve(mfs_problem *p, const double *b, double *x, const mfs_options *opts, mfs_solve_info *info,
               void *stream);
@@ -221,9 +241,22 @@ int mfs_solve(mfs_problem *p, const double *b, double *x, const mfs_options *opt
 int mfs_solve_begin(mfs_problem *p, const double *b, double *x, const mfs_options *opts, void *stream);
 int mfs_solve_advance(mfs_problem *p, int *done, mfs_solve_info *info);
 
-/* Navier-Stokes linearisation point (Sec. 5): u0 device FP64 dim*n_u nodal
- * velocity (the pressure of the linearisation point is 0).  Stores u0 and
- * refreshes the per-quadrature-point stabilisation parameter delta_1. */
+/*
+ * Navier-Stokes linearisation point (Sec. 5) of a problem set up with
+ * pressure_offset = 0.  u0: device FP64 dim*n_u nodal velocity (every node,
+ * boundary included; the pressure of the point is 0).  dt > 0: BDF2 step,
+ * mass shift alpha = 3/(2 dt).  newton = 1: full Gateaux derivative;
+ * 0: Oseen (drops du.grad u0 and (R(u0), du.grad v)).
+ * Computes, on every level, u0 at the level's nodes (copied from the fine
+ * nodes they coincide with), the per-Gauss-point data u0, grad u0,
+ * R(u0) = u0.grad u0 - nu Lap u0 and the frozen SUPG/PSPG parameter
+ * delta_1 = [(2/dt)^2 + (2|u0|/h_K)^2 + 9 (4 nu/h_K^2)^2]^(-1/2),
+ * h_K = |K|^(1/dim)/k (FP64 and FP32 copies); with mg_levels also the
+ * diagonals of J (by applying J to node colourings) and the FP64 inverse of
+ * the coarsest J with pressure node 0 pinned (its row and column replaced by
+ * the identity and its right-hand side entry ignored).  Host-synchronous on
+ * `stream`.  MFS_EINVAL for a Taylor-Hood problem or dt <= 0.
+ */
 int mfs_set_linearization(mfs_problem *p, const double *u0, double dt, int newton, void *stream);
 
 #ifdef __cplusplus

@@ -277,3 +277,24 @@ def smooth_mapped_vertices(dim: int, n, amp: float = 0.1) -> np.ndarray:
     X = structured_vertices(dim, n)
     bump = np.prod(np.sin(_pi * X), axis=1)
     return np.ascontiguousarray(X + amp * bump[:, None])
+
+
+def ns_velocity(dim: int, node_counts, seed: int = 0, n_modes: int = 8) -> np.ndarray:
+    """Smooth linearisation point for the Navier-Stokes Jacobian: the Fourier
+    field of ``fourier_field(seed)`` sampled on a uniform grid of the unit cube
+    with ``node_counts`` points per direction (node index / (count - 1), so
+    no basis or mesh information is used), blocked [u_0 | u_1 | (u_2)] with x
+    fastest.  Unit RMS; nonzero on the boundary."""
+    F = fourier_field(seed, n_modes)
+    c = [int(v) for v in node_counts][:dim]
+    axes = [np.linspace(0.0, 1.0, v) if v > 1 else np.zeros(1) for v in c]
+    while len(axes) < 3:
+        axes.append(np.full(1, 0.3))
+    out = np.empty((dim, int(np.prod(c))))
+    zz, yy = np.meshgrid(axes[2], axes[1], indexing="ij")
+    for iz in range(len(axes[2])):  # slab by slab (bounded memory on large grids)
+        pts = np.stack(np.broadcast_arrays(axes[0][None, :], yy[iz][:, None], zz[iz][:, None]), -1)
+        v = F(pts.reshape(-1, 3))[:, :dim]
+        m = v.shape[0]
+        out[:, iz * m:(iz + 1) * m] = v.T
+    return out.ravel()

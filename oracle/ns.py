@@ -33,10 +33,10 @@ from . import basis
 from .fem import Space, _assemble, constrain
 
 
-def _qp_data(S: Space):
+def _qp_data(S: Space, cells=None):
     """Per cell and Gauss point: JxW, physical gradients and Laplacians of the
     Q_k basis, values; velocity and pressure use the same (equal-order) basis."""
-    xq, J, det, invJ, JxW = S.geometry()
+    xq, J, det, invJ, JxW = S.geometry(cells)
     q1 = basis.gauss_rule(S.k + 1)[0]
     N, dN, H = basis.tensor_basis(S.dim, S.k, q1)
     G = np.einsum("qib,cqba->cqia", dN, invJ)  # [c, q, i, a]
@@ -46,16 +46,17 @@ def _qp_data(S: Space):
     return N, G, L, JxW, vol
 
 
-def linearization_data(S: Space, u0: np.ndarray, nu: float, dt: float):
-    """u0, grad u0, R(u0, 0) and delta_1 at every Gauss point.  u0: blocked
-    nodal velocity [dim*Nv]."""
-    N, G, L, JxW, vol = _qp_data(S)
+def linearization_data(S: Space, u0: np.ndarray, nu: float, dt: float, cells=None):
+    """u0, grad u0, R(u0, 0) and delta_1 at every Gauss point (of the given
+    cells; all by default).  u0: blocked nodal velocity [dim*Nv]."""
+    N, G, L, JxW, vol = _qp_data(S, cells)
+    vdofs = S.vdofs if cells is None else S.vdofs[np.asarray(cells)]
     d = S.dim
     uq = np.zeros(JxW.shape + (d,))
     gu = np.zeros(JxW.shape + (d, d))  # [c, q, comp, a]
     lap = np.zeros(JxW.shape + (d,))
     for c in range(d):
-        loc = u0[S.vdofs + c * S.Nv]  # [cells, nb]
+        loc = u0[vdofs + c * S.Nv]  # [cells, nb]
         uq[..., c] = loc @ N.T
         gu[..., c, :] = np.einsum("ei,eqia->eqa", loc, G)
         lap[..., c] = np.einsum("ei,eqi->eq", loc, L)
@@ -63,15 +64,16 @@ def linearization_data(S: Space, u0: np.ndarray, nu: float, dt: float):
     hK = vol ** (1.0 / d) / S.k
     speed = np.linalg.norm(uq, axis=-1)
     delta = ((2.0 / dt) ** 2 + (2.0 * speed / hK[:, None]) ** 2 + 9.0 * (4.0 * nu / hK[:, None] ** 2) ** 2) ** -0.5
-    return {"u": uq, "grad": gu, "R0": R0, "delta": delta, "N": N, "G": G, "L": L, "JxW": JxW}
+    return {"u": uq, "grad": gu, "R0": R0, "delta": delta, "N": N, "G": G, "L": L, "JxW": JxW, "vdofs": vdofs}
 
 
 def _local_fields(S, data, x):
     """Values, gradients and Laplacians of a blocked [u; p] vector at the qp."""
     N, G, L = data["N"], data["G"], data["L"]
     d = S.dim
-    ul = np.stack([x[S.vdofs + c * S.Nv] for c in range(d)], -1)  # [e, i, c]
-    pl = x[d * S.Nv:][S.vdofs]  # equal order: same local numbering
+    vdofs = data["vdofs"]
+    ul = np.stack([x[vdofs + c * S.Nv] for c in range(d)], -1)  # [e, i, c]
+    pl = x[d * S.Nv:][vdofs]  # equal order: same local numbering
     u = np.einsum("qi,eic->eqc", N, ul)
     gu = np.einsum("eqia,eic->eqca", G, ul)
     lu = np.einsum("eqi,eic->eqc", L, ul)
@@ -85,13 +87,14 @@ def _assemble_test(S, val_u, grad_u, val_p, grad_p, data):
     grad_u [e,q,c,a] multiplies d_a v_c, val_p multiplies q, grad_p [e,q,a]
     multiplies d_a q."""
     N, G, JxW = data["N"], data["G"], data["JxW"]
+    vdofs = data["vdofs"]
     d = S.dim
     out = np.zeros(d * S.Nv + S.Nv)
     for c in range(d):
         loc = np.einsum("eq,qi->ei", JxW * val_u[..., c], N) + np.einsum("eq,eqa,eqia->ei", JxW, grad_u[..., c, :], G)
-        np.add.at(out, (S.vdofs + c * S.Nv).ravel(), loc.ravel())
+        np.add.at(out, (vdofs + c * S.Nv).ravel(), loc.ravel())
     loc = np.einsum("eq,qi->ei", JxW * val_p, N) + np.einsum("eq,eqa,eqia->ei", JxW, grad_p, G)
-    np.add.at(out, (S.vdofs + d * S.Nv).ravel(), loc.ravel())
+    np.add.at(out, (vdofs + d * S.Nv).ravel(), loc.ravel())
     return out
 
 
@@ -195,6 +198,20 @@ def jacobian_matrix(S: Space, data, nu, dt, newton=True):
         E[:, d, :, cp, :] += np.einsum("eq,eqic,eqcj->eij", W * dl, G, rl_all)  # PSPG
     E[:, d, :, d, :] += np.einsum("eq,eqia,eqja->eij", W * dl, G, G)
     del I
-    l2g = np.concatenate([S.vdofs + c * S.Nv for c in range(nd)], axis=1)
+    l2g = np.concatenate([data["vdofs"] + c * S.Nv for c in range(nd)], axis=1)
     K = _assemble(l2g, l2g, E.reshape(ne, nd * nb, nd * nb), (nd * S.Nv, nd * S.Nv))
     return constrain(K, ns_dirichlet_mask(S))
+
+
+def sampled_jacobian_rows(S: Space, dx, u0, nu, dt, rows, newton=True):
+    """Rows of the constrained Jacobian applied to dx, from the cells that
+    contain them only (for meshes too large for a full evaluation)."""
+    from .fem import cells_containing
+
+    rows = np.asarray(rows)
+    cells = cells_containing(S, rows)
+    data = linearization_data(S, u0, nu, dt, cells)
+    mask = ns_dirichlet_mask(S)
+    y = jacobian_apply(S, np.where(mask, 0.0, dx), data, nu, dt, newton)
+    y[mask] = dx[mask]
+    return y[rows]

@@ -68,8 +68,8 @@ class mfs_options(ctypes.Structure):
         ("rtol", ctypes.c_double),
         ("precond_precision", ctypes.c_int),
         ("seed", ctypes.c_uint64),
-        ("dt", ctypes.c_double),
-        ("newton", ctypes.c_int),
+        ("relax_steps", ctypes.c_int),
+        ("relax_omega", ctypes.c_double),
     ]
 
 

@@ -6,7 +6,10 @@
 // Methods: Sec. 3 eq. (stokes_block) (block-triangular preconditioner with
 // S ~ nu^{-1} M_p inverted by Jacobi-PCG, A^{-1} ~ one V-cycle, FGMRES), Sec. 2
 // eq. (transfer) and Sec. 3 (p-levels down to p_min, then global-coarsening
-// h-levels, Chebyshev around point Jacobi, direct coarse solve).
+// h-levels, Chebyshev around point Jacobi, direct coarse solve); Sec. 5
+// (equal-order SUPG/PSPG Navier-Stokes Jacobian, monolithic multigrid with
+// h-levels first, damped point-Jacobi relaxation and a direct coarse solve,
+// inside FGMRES).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -66,6 +69,12 @@ struct Level {
   std::vector<double> emb;      // 1D embedding to level+1
   std::vector<double> Xhost;    // vertices (host copy)
   std::vector<double> tabh;     // 1D tables (host copy)
+  // Navier-Stokes (equal order): linearisation point, per-point data, 1/diag(J)
+  double *u0 = nullptr;
+  double *qd64 = nullptr;
+  float *qd32 = nullptr;
+  double *nsinv64 = nullptr;
+  float *nsinv32 = nullptr;
 };
 
 struct Krylov {
@@ -105,10 +114,16 @@ struct mfs_problem {
   double *scal = nullptr;       // device scalars for PCG / means
   double *partials = nullptr;   // reduction scratch
   double *tmp_full = nullptr;   // FP64 full-length temporary
+  double *tmp2 = nullptr;       // second one (Navier-Stokes set-up)
   Krylov kr;
   char *arena = nullptr;
   size_t arena_bytes = 0;
   hipStream_t stream = nullptr;
+  // Navier-Stokes problem (pressure_offset = 0)
+  bool ns = false;
+  bool ns_ready = false;
+  double ns_dt = 0.0;
+  int ns_newton = 1;
 };
 
 namespace {
@@ -149,7 +164,25 @@ int64_t n_vertices(const LevelGeom &g) {
 }
 
 // level hierarchy: p-levels then h-levels (Sec. 3)
+// equal order (Navier-Stokes, Sec. 5): h-levels first, then p-levels
+std::vector<LevelGeom> plan_levels_ns(int dim, const int n[3], int k, const mfs_options &o) {
+  std::vector<LevelGeom> out;
+  out.push_back(make_geom(dim, n, k, k));
+  if (!o.mg_levels) return out;
+  int nn[3] = {n[0], n[1], dim == 3 ? n[2] : 1};
+  while (true) {
+    bool ok = true;
+    for (int a = 0; a < dim; ++a) ok = ok && (nn[a] % 2 == 0) && (nn[a] > std::max(1, o.coarse_min_cells));
+    if (!ok) break;
+    for (int a = 0; a < dim; ++a) nn[a] /= 2;
+    out.push_back(make_geom(dim, nn, k, k));
+  }
+  for (int kk = k - 1; kk >= std::max(1, o.p_min); --kk) out.push_back(make_geom(dim, nn, kk, kk));
+  return out;
+}
+
 std::vector<LevelGeom> plan_levels(int dim, const int n[3], int k, int kp, const mfs_options &o) {
+  if (o.pressure_offset == 0) return plan_levels_ns(dim, n, k, o);
   std::vector<LevelGeom> out;
   out.push_back(make_geom(dim, n, k, kp));
   if (!o.mg_levels) return out;
@@ -198,9 +231,65 @@ void plan_prec_work(Arena &A, PrecWork<T> &w, const std::vector<LevelGeom> &G, i
   w.full_out = A.take<T>(ntot);
 }
 
+// Navier-Stokes: level vectors are full equal-order vectors ((dim+1) Nv)
+template <typename T>
+void plan_ns_work(Arena &A, PrecWork<T> &w, const std::vector<LevelGeom> &G, int dim, bool full) {
+  if (!full) return;
+  const size_t nl = G.size();
+  w.x.assign(nl, nullptr);
+  w.b.assign(nl, nullptr);
+  w.r.assign(nl, nullptr);
+  w.d.assign(nl, nullptr);
+  for (size_t l = 0; l < nl; ++l) {
+    const int64_t n = (dim + 1) * G[l].Nv;
+    w.x[l] = A.take<T>(n);
+    w.b[l] = A.take<T>(n);
+    w.r[l] = A.take<T>(n);
+    w.d[l] = A.take<T>(n);
+  }
+  w.full_in = A.take<T>((dim + 1) * G[0].Nv);
+  w.full_out = A.take<T>((dim + 1) * G[0].Nv);
+}
+
 // The whole device footprint, carved from one allocation.
 void plan_arena(Arena &A, mfs_problem &P, const std::vector<LevelGeom> &G) {
   P.L.resize(G.size());
+  if (P.ns) {
+    for (size_t l = 0; l < G.size(); ++l) {
+      Level &L = P.L[l];
+      L.g = G[l];
+      const int64_t nvert = n_vertices(G[l]);
+      L.X64 = A.take<double>(nvert * P.dim);
+      L.X32 = A.take<float>(nvert * P.dim);
+      L.tab64 = A.take<double>(TAB_SIZE);
+      L.tab32 = A.take<float>(TAB_SIZE);
+      L.u0 = A.take<double>(P.dim * G[l].Nv);
+      L.qd64 = A.take<double>(ns_qd_elems(G[l]));
+      L.qd32 = A.take<float>(ns_qd_elems(G[l]));
+      L.nsinv64 = A.take<double>((P.dim + 1) * G[l].Nv);
+      L.nsinv32 = A.take<float>((P.dim + 1) * G[l].Nv);
+    }
+    const bool full = P.opts.mg_levels != 0;
+    plan_ns_work(A, P.w64, G, P.dim, full);
+    plan_ns_work(A, P.w32, G, P.dim, full);
+    P.coarse_n = full ? (int)((P.dim + 1) * G.back().Nv) : 0;
+    P.coarse_inv = A.take<double>((int64_t)P.coarse_n * P.coarse_n);
+    const int64_t ntot = (P.dim + 1) * G[0].Nv;
+    P.m1 = A.take<double>(G[0].Nv);
+    P.scal = A.take<double>(4 * PCG_MAX + 64);
+    P.partials = A.take<double>(32 * DOT_BLOCKS);
+    P.tmp_full = A.take<double>(ntot);
+    P.tmp2 = A.take<double>(ntot);
+    Krylov &K = P.kr;
+    K.m = std::max(1, std::min(P.opts.restart, 30));
+    const int64_t nk = full ? ntot : 0;
+    K.V = A.take<double>((K.m + 1) * nk);
+    K.Z = A.take<double>(K.m * nk);
+    K.w = A.take<double>(nk);
+    K.dev = A.take<double>(128);
+    K.ydev = A.take<double>(64);
+    return;
+  }
   for (size_t l = 0; l < G.size(); ++l) {
     Level &L = P.L[l];
     L.g = G[l];
@@ -243,6 +332,8 @@ void check_options(const mfs_options &o) {
   MFS_REQUIRE(o.schur_iterations >= 0 && o.schur_iterations < PCG_MAX, MFS_EINVAL, "schur_iterations out of range");
   MFS_REQUIRE(o.precond_precision == MFS_FP32 || o.precond_precision == MFS_FP64, MFS_EINVAL,
               "precond_precision must be MFS_FP32 or MFS_FP64");
+  MFS_REQUIRE(o.relax_steps >= 1 && o.relax_steps <= 64, MFS_EINVAL, "relax_steps out of range");
+  MFS_REQUIRE(o.relax_omega > 0 && o.relax_omega < 2, MFS_EINVAL, "relax_omega must be in (0, 2)");
 }
 
 void check_mesh(const mfs_mesh *mesh, int k, const mfs_options &o) {
@@ -251,6 +342,11 @@ void check_mesh(const mfs_mesh *mesh, int k, const mfs_options &o) {
   for (int a = 0; a < mesh->dim; ++a) MFS_REQUIRE(mesh->n[a] >= 1, MFS_EINVAL, "n[%d] must be >= 1", a);
   MFS_REQUIRE(k >= 1 && k <= 6, MFS_EINVAL, "degree k=%d out of range [1, 6]", k);
   if (o.pressure_offset == 1) MFS_REQUIRE(k >= 2, MFS_EINVAL, "Taylor-Hood needs k >= 2");
+  if (o.pressure_offset == 0) {
+    MFS_REQUIRE(k <= 3, MFS_EUNSUPPORTED, "Navier-Stokes operator supports k <= 3 (got %d)", k);
+    MFS_REQUIRE(!o.mg_levels || k <= 2, MFS_EUNSUPPORTED,
+                "Navier-Stokes multigrid needs nested nodes, k <= 2 (got %d)", k);
+  }
   MFS_REQUIRE(o.pressure_offset == 0 || o.pressure_offset == 1, MFS_EINVAL, "pressure_offset must be 0 or 1");
   int64_t nodes = 1;
   for (int a = 0; a < mesh->dim; ++a) nodes *= (int64_t)k * mesh->n[a] + 1;
@@ -333,10 +429,51 @@ void apply_A(mfs_problem &P, int l, T *dst, const T *src, hipStream_t s) {
 }
 
 template <typename T>
+const T *ns_qd(const Level &L);
+template <>
+const double *ns_qd<double>(const Level &L) {
+  return L.qd64;
+}
+template <>
+const float *ns_qd<float>(const Level &L) {
+  return L.qd32;
+}
+template <typename T>
+const T *ns_invdiag(const Level &L);
+template <>
+const double *ns_invdiag<double>(const Level &L) {
+  return L.nsinv64;
+}
+template <>
+const float *ns_invdiag<float>(const Level &L) {
+  return L.nsinv32;
+}
+
+// constrained Navier-Stokes Jacobian on level l: identity on the velocity
+// Dirichlet rows, cell terms elsewhere (Dirichlet source values ignored)
+template <typename T>
+void apply_ns(mfs_problem &P, int l, T *dst, const T *src, hipStream_t s) {
+  MFS_REQUIRE(P.ns, MFS_EINVAL, "the Navier-Stokes Jacobian needs a problem set up with pressure_offset = 0");
+  MFS_REQUIRE(P.ns_ready, MFS_EINVAL, "mfs_set_linearization has not been called");
+  const Level &L = P.L[l];
+  const LevelGeom &g = L.g;
+  launch_fill_dirichlet<T>(g, dst, src, s);
+  vec_fill<T>(dst + g.dim * g.Nv, T(0), g.Nv, s);
+  launch_ns<T>(g, dev<T>(L).X, dev<T>(L).tab, 1, (T)P.nu, (T)P.ns_dt, P.ns_newton, src, dst,
+               const_cast<T *>(ns_qd<T>(L)), s);
+}
+
+template <typename T>
 void apply_op(mfs_problem &P, int op, int l, T *dst, const T *src, hipStream_t s) {
   const Level &L = P.L[l];
   const LevelGeom &g = L.g;
   const int64_t nu = g.dim * g.Nv;
+  if (op == MFS_OP_NS_JACOBIAN) {
+    apply_ns<T>(P, l, dst, src, s);
+    return;
+  }
+  MFS_REQUIRE(!P.ns, MFS_EUNSUPPORTED, "operator %d is not available on an equal-order (Navier-Stokes) problem",
+              op);
   switch (op) {
     case MFS_OP_A:
       apply_A<T>(P, l, dst, src, s);
@@ -508,6 +645,141 @@ void setup_coarse(mfs_problem &P, hipStream_t s) {
   MFS_HIP(hipStreamSynchronize(s));
 }
 
+// ---------------------------------------------------------------- Navier-Stokes set-up
+// diag(J) on level l: J applied to the indicator of one node colour and one
+// component at a time (colour = node index mod (k+1) per direction, so no two
+// nodes of a colour share a cell and each row sees only its own column)
+void ns_diagonal(mfs_problem &P, int l, double *diag, hipStream_t s) {
+  const Level &L = P.L[l];
+  const LevelGeom &g = L.g;
+  const int q = g.k + 1;
+  int ncol = 1;
+  for (int a = 0; a < g.dim; ++a) ncol *= q;
+  double *e = P.tmp_full, *y = P.tmp2;
+  for (int c = 0; c < ncol; ++c)
+    for (int comp = 0; comp <= P.dim; ++comp) {
+      launch_color_indicator(g, P.dim + 1, q, c, comp, e, s);
+      apply_ns<double>(P, l, y, e, s);
+      launch_color_extract(g, q, c, comp, y, diag, s);
+    }
+}
+
+// dense inverse of the coarsest J with pressure node 0 pinned; columns of J
+// from colourings with spacing 2k+1 (the stencils of two nodes of a colour
+// do not overlap, so every entry of J e_colour belongs to one column)
+void ns_setup_coarse(mfs_problem &P, hipStream_t s) {
+  const int l = P.nlev - 1;
+  const Level &L = P.L[l];
+  const LevelGeom &g = L.g;
+  const int n = P.coarse_n;
+  const int64_t Nv = g.Nv;
+  const int k = g.k, q = 2 * k + 1;
+  int ncol = 1;
+  for (int a = 0; a < g.dim; ++a) ncol *= q;
+  std::vector<double> A((size_t)n * n, 0.0), y(n);  // row-major
+  double *e = P.tmp_full, *yd = P.tmp2;
+  auto coord = [&](int64_t i, int c[3]) {
+    c[0] = (int)(i % g.nv[0]);
+    c[1] = (int)((i / g.nv[0]) % g.nv[1]);
+    c[2] = (int)(i / ((int64_t)g.nv[0] * g.nv[1]));
+  };
+  for (int col = 0; col < ncol; ++col)
+    for (int comp = 0; comp <= P.dim; ++comp) {
+      launch_color_indicator(g, P.dim + 1, q, col, comp, e, s);
+      apply_ns<double>(P, l, yd, e, s);
+      MFS_HIP(hipMemcpyAsync(y.data(), yd, n * sizeof(double), hipMemcpyDeviceToHost, s));
+      MFS_HIP(hipStreamSynchronize(s));
+      for (int64_t j = 0; j < Nv; ++j) {
+        int cj[3];
+        coord(j, cj);
+        if (cj[0] % q + q * (cj[1] % q + q * (cj[2] % q)) != col) continue;
+        int lo[3], hi[3];
+        for (int a = 0; a < 3; ++a) {
+          lo[a] = std::max(0, cj[a] - k);
+          hi[a] = std::min(g.nv[a] - 1, cj[a] + k);
+        }
+        for (int z = lo[2]; z <= hi[2]; ++z)
+          for (int yy = lo[1]; yy <= hi[1]; ++yy)
+            for (int x = lo[0]; x <= hi[0]; ++x) {
+              const int64_t i = x + (int64_t)g.nv[0] * (yy + (int64_t)g.nv[1] * z);
+              for (int r = 0; r <= P.dim; ++r)
+                A[(size_t)(r * Nv + i) * n + comp * Nv + j] = y[r * Nv + i];
+            }
+      }
+    }
+  const int pin = (int)(P.dim * Nv);
+  for (int i = 0; i < n; ++i) {
+    A[(size_t)pin * n + i] = 0.0;
+    A[(size_t)i * n + pin] = 0.0;
+  }
+  A[(size_t)pin * n + pin] = 1.0;
+  // LU with partial pivoting (row-major, in place)
+  std::vector<int> piv(n);
+  for (int c = 0; c < n; ++c) {
+    int pr = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(A[(size_t)r * n + c]) > std::fabs(A[(size_t)pr * n + c])) pr = r;
+    MFS_REQUIRE(A[(size_t)pr * n + c] != 0.0, MFS_EINVAL, "coarse Navier-Stokes matrix is singular");
+    piv[c] = pr;
+    if (pr != c)
+      for (int j = 0; j < n; ++j) std::swap(A[(size_t)c * n + j], A[(size_t)pr * n + j]);
+    const double inv = 1.0 / A[(size_t)c * n + c];
+    for (int r = c + 1; r < n; ++r) {
+      const double f = A[(size_t)r * n + c] * inv;
+      A[(size_t)r * n + c] = f;
+      if (f != 0.0)
+        for (int j = c + 1; j < n; ++j) A[(size_t)r * n + j] -= f * A[(size_t)c * n + j];
+    }
+  }
+  // inverse, column-major for dense_apply; the pinned column is dropped
+  std::vector<double> inv((size_t)n * n, 0.0), v(n);
+  for (int c = 0; c < n; ++c) {
+    if (c == pin) continue;
+    std::fill(v.begin(), v.end(), 0.0);
+    v[c] = 1.0;
+    for (int i = 0; i < n; ++i) std::swap(v[i], v[piv[i]]);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < i; ++j) v[i] -= A[(size_t)i * n + j] * v[j];
+    for (int i = n - 1; i >= 0; --i) {
+      for (int j = i + 1; j < n; ++j) v[i] -= A[(size_t)i * n + j] * v[j];
+      v[i] /= A[(size_t)i * n + i];
+    }
+    std::copy(v.begin(), v.end(), inv.begin() + (size_t)c * n);
+  }
+  MFS_HIP(hipMemcpyAsync(P.coarse_inv, inv.data(), inv.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  MFS_HIP(hipStreamSynchronize(s));
+}
+
+void ns_set_linearization(mfs_problem &P, const double *u0, double dt, int newton, hipStream_t s) {
+  P.ns_ready = false;
+  P.ns_dt = dt;
+  P.ns_newton = newton ? 1 : 0;
+  MFS_HIP(hipMemcpyAsync(P.L[0].u0, u0, P.dim * P.L[0].g.Nv * sizeof(double), hipMemcpyDeviceToDevice, s));
+  for (int l = 1; l < P.nlev; ++l) launch_ns_inject(P.L[l - 1].g, P.L[l].g, P.L[l - 1].u0, P.L[l].u0, s);
+  for (int l = 0; l < P.nlev; ++l) {
+    Level &L = P.L[l];
+    launch_ns<double>(L.g, L.X64, L.tab64, 0, P.nu, dt, P.ns_newton, L.u0, nullptr, L.qd64, s);
+    vec_cast<float, double>(L.qd32, L.qd64, ns_qd_elems(L.g), s);
+  }
+  P.ns_ready = true;
+  try {
+    if (P.opts.mg_levels) {
+      for (int l = 0; l + 1 < P.nlev; ++l) {
+        Level &L = P.L[l];
+        const int64_t n = (P.dim + 1) * L.g.Nv;
+        double *d = P.w64.x[l];
+        ns_diagonal(P, l, d, s);
+        launch_reciprocal(L.nsinv64, L.nsinv32, d, n, s);
+      }
+      ns_setup_coarse(P, s);
+    }
+    MFS_HIP(hipStreamSynchronize(s));
+  } catch (...) {
+    P.ns_ready = false;
+    throw;
+  }
+}
+
 // ---------------------------------------------------------------- V-cycle
 template <typename T>
 void chebyshev(mfs_problem &P, int l, T *x, const T *b, bool zero_start, hipStream_t s) {
@@ -553,6 +825,44 @@ void vcycle_level(mfs_problem &P, int l, T *x, const T *b, hipStream_t s) {
   chebyshev<T>(P, l, x, b, false, s);
 }
 
+// ---------------------------------------------------------------- Navier-Stokes V-cycle
+// One monolithic V-cycle on J (Sec. 5): x = (b on Dirichlet rows, 0 free),
+// relax_steps damped Jacobi sweeps, restriction of the residual (pressure
+// unconstrained), recursion, prolongation, relax_steps sweeps; on the
+// coarsest level x = C b with the pinned dense inverse C.
+template <typename T>
+void ns_relax(mfs_problem &P, int l, T *x, const T *b, hipStream_t s) {
+  PrecWork<T> &W = work<T>(P);
+  const Level &L = P.L[l];
+  const int64_t n = (P.dim + 1) * L.g.Nv;
+  for (int it = 0; it < P.opts.relax_steps; ++it) {
+    apply_ns<T>(P, l, W.d[l], x, s);
+    jacobi_relax<T>(x, b, W.d[l], ns_invdiag<T>(L), (T)P.opts.relax_omega, n, s);
+  }
+}
+
+template <typename T>
+void ns_vcycle(mfs_problem &P, int l, T *x, const T *b, hipStream_t s) {
+  PrecWork<T> &W = work<T>(P);
+  Level &L = P.L[l];
+  if (l == P.nlev - 1) {
+    dense_apply<T>(P.coarse_inv, P.coarse_n, b, x, s);
+    return;
+  }
+  const int64_t n = (P.dim + 1) * L.g.Nv;
+  launch_fill_dirichlet<T>(L.g, x, b, s);
+  vec_fill<T>(x + P.dim * L.g.Nv, T(0), L.g.Nv, s);
+  ns_relax<T>(P, l, x, b, s);
+  T *r = W.r[l];
+  apply_ns<T>(P, l, r, x, s);
+  vec_axpby<T>(r, T(1), b, T(-1), n, s);  // r = b - J x
+  Level &C = P.L[l + 1];
+  launch_restrict<T>(L.g, C.g, L.h_to_coarser, L.emb.data(), W.b[l + 1], r, s, 1);
+  ns_vcycle<T>(P, l + 1, W.x[l + 1], W.b[l + 1], s);
+  launch_prolongate_add<T>(L.g, C.g, L.h_to_coarser, L.emb.data(), x, W.x[l + 1], s, 1);
+  ns_relax<T>(P, l, x, b, s);
+}
+
 // ---------------------------------------------------------------- block preconditioner
 template <typename T>
 void precondition(mfs_problem &P, T *y, const T *r, hipStream_t s) {
@@ -582,11 +892,24 @@ void precondition(mfs_problem &P, T *y, const T *r, hipStream_t s) {
   vcycle_level<T>(P, 0, y, W.t_u, s);
 }
 
+// the system operator and its preconditioner: Stokes (block preconditioner)
+// or Navier-Stokes Jacobian (monolithic V-cycle)
+void apply_system(mfs_problem &P, double *dst, const double *src, hipStream_t s) {
+  apply_op<double>(P, P.ns ? MFS_OP_NS_JACOBIAN : MFS_OP_STOKES, 0, dst, src, s);
+}
+template <typename T>
+void precondition_any(mfs_problem &P, T *y, const T *r, hipStream_t s) {
+  if (P.ns)
+    ns_vcycle<T>(P, 0, y, r, s);
+  else
+    precondition<T>(P, y, r, s);
+}
+
 // ---------------------------------------------------------------- FGMRES
 void kr_enqueue_residual(mfs_problem &P, hipStream_t s) {
   Krylov &K = P.kr;
   const int64_t n = P.dim * P.L[0].g.Nv + P.L[0].g.Np;
-  apply_op<double>(P, MFS_OP_STOKES, 0, K.w, K.x, s);
+  apply_system(P, K.w, K.x, s);
   vec_axpby<double>(K.w, 1.0, K.b, -1.0, n, s);  // w = b - K x
   multi_dot<double>(K.w, 0, 1, K.w, n, K.dev + 96, P.partials, s);
   MFS_HIP(hipMemcpyAsync(K.host + 96, K.dev + 96, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -601,12 +924,12 @@ void kr_enqueue_step(mfs_problem &P, hipStream_t s) {
   double *vj = K.V + (int64_t)j * n, *zj = K.Z + (int64_t)j * n;
   if (K.prec == MFS_FP32) {
     vec_cast<float, double>(P.w32.full_in, vj, n, s);
-    precondition<float>(P, P.w32.full_out, P.w32.full_in, s);
+    precondition_any<float>(P, P.w32.full_out, P.w32.full_in, s);
     vec_cast<double, float>(zj, P.w32.full_out, n, s);
   } else {
-    precondition<double>(P, zj, vj, s);
+    precondition_any<double>(P, zj, vj, s);
   }
-  apply_op<double>(P, MFS_OP_STOKES, 0, K.w, zj, s);
+  apply_system(P, K.w, zj, s);
   // classical Gram-Schmidt, twice
   multi_dot<double>(K.V, n, j + 1, K.w, n, K.dev, P.partials, s);
   multi_axpy<double>(K.w, K.V, n, j + 1, K.dev, n, s);
@@ -644,7 +967,7 @@ void kr_finish(mfs_problem &P, double rel, int status) {
   hipStream_t s = K.s;
   const LevelGeom &g = P.L[0].g;
   const int64_t nu = P.dim * g.Nv;
-  // pressure with zero mass-weighted mean
+  // pressure with zero mass-weighted mean (Navier-Stokes: m1 = 1, nodal mean)
   if (g.Np > 0) {
     double *num = P.scal + 4 * PCG_MAX + 8, *den = num + 1;
     multi_dot<double>(P.m1, 0, 1, K.x + nu, g.Np, num, P.partials, s);
@@ -760,8 +1083,8 @@ void mfs_default_options(mfs_options *o) {
   o->rtol = 1e-8;
   o->precond_precision = MFS_FP32;
   o->seed = 0;
-  o->dt = 1e-2;
-  o->newton = 1;
+  o->relax_steps = 5;
+  o->relax_omega = 0.5;
 }
 
 const char *mfs_last_error(void) { return get_error(); }
@@ -780,6 +1103,7 @@ int mfs_footprint(const mfs_mesh *mesh, int k, const mfs_options *opts, size_t *
     mfs_problem P;
     P.dim = mesh->dim;
     P.opts = o;
+    P.ns = o.pressure_offset == 0;
     Arena A;
     plan_arena(A, P, G);
     *bytes = A.off;
@@ -804,6 +1128,7 @@ int mfs_setup(const mfs_mesh *mesh, int k, double nu, const mfs_options *opts, v
     P->dim = mesh->dim;
     P->nu = nu;
     P->opts = o;
+    P->ns = o.pressure_offset == 0;
     hipStream_t s = S(stream);
     P->stream = s;
     auto G = levels_for(mesh, k, o);
@@ -862,6 +1187,13 @@ int mfs_setup(const mfs_mesh *mesh, int k, double nu, const mfs_options *opts, v
       MFS_HIP(hipStreamSynchronize(s));
       MFS_REQUIRE(hb == 0x7fffffff, MFS_EINVAL, "non-positive Jacobian determinant in cell %d", hb);
     }
+    if (P->ns) {
+      // everything operator-specific waits for mfs_set_linearization
+      vec_fill<double>(P->m1, 1.0, P->L[0].g.Nv, s);
+      MFS_HIP(hipStreamSynchronize(s));
+      *out = P;
+      return;
+    }
     // diagonals
     for (int l = 0; l < P->nlev; ++l) {
       Level &L = P->L[l];
@@ -918,6 +1250,7 @@ void kr_begin(mfs_problem &P, const double *b, double *x, const mfs_options &o, 
   Krylov &K = P.kr;
   MFS_REQUIRE(P.opts.mg_levels, MFS_EINVAL, "solve needs the multigrid hierarchy (mg_levels = 1)");
   MFS_REQUIRE(P.L[0].g.Np > 0, MFS_EINVAL, "solve needs a pressure space");
+  MFS_REQUIRE(!P.ns || P.ns_ready, MFS_EINVAL, "mfs_set_linearization has not been called");
   const LevelGeom &g = P.L[0].g;
   const int64_t n = P.dim * g.Nv + g.Np;
   K.b = b;
@@ -1058,6 +1391,11 @@ int mfs_diagonal(mfs_problem *p, int level, double *dst, void *stream) {
     MFS_REQUIRE(dst != nullptr, MFS_EINVAL, "NULL vector");
     const Level &L = p->L[level];
     hipStream_t s = S(stream);
+    if (p->ns) {
+      MFS_REQUIRE(p->ns_ready, MFS_EINVAL, "mfs_set_linearization has not been called");
+      ns_diagonal(*p, level, dst, s);
+      return;
+    }
     vec_fill<double>(dst, 0.0, L.g.Nv, s);
     launch_laplace_diagonal(L.g, L.X64, L.tab64, p->nu, dst, s);
     // Dirichlet rows: 1 (identity rows of the constrained operator)
@@ -1087,7 +1425,13 @@ int mfs_vcycle(mfs_problem *p, int prec, void *dst, const void *src, void *strea
     check_prec(prec);
     MFS_REQUIRE(p->opts.mg_levels, MFS_EINVAL, "problem was set up without multigrid levels");
     MFS_REQUIRE(dst && src && dst != src, MFS_EINVAL, "bad vectors");
-    if (prec == MFS_FP64)
+    MFS_REQUIRE(!p->ns || p->ns_ready, MFS_EINVAL, "mfs_set_linearization has not been called");
+    if (p->ns) {
+      if (prec == MFS_FP64)
+        ns_vcycle<double>(*p, 0, (double *)dst, (const double *)src, S(stream));
+      else
+        ns_vcycle<float>(*p, 0, (float *)dst, (const float *)src, S(stream));
+    } else if (prec == MFS_FP64)
       vcycle_level<double>(*p, 0, (double *)dst, (const double *)src, S(stream));
     else
       vcycle_level<float>(*p, 0, (float *)dst, (const float *)src, S(stream));
@@ -1100,12 +1444,13 @@ int mfs_prolongate_add(mfs_problem *p, int prec, int fine, void *dst, const void
     check_prec(prec);
     MFS_REQUIRE(fine + 1 < p->nlev, MFS_EINVAL, "no coarser level below %d", fine);
     const Level &F = p->L[fine], &C = p->L[fine + 1];
+    const int ncp = p->ns ? 1 : 0;
     if (prec == MFS_FP64)
       launch_prolongate_add<double>(F.g, C.g, F.h_to_coarser, F.emb.data(), (double *)dst, (const double *)src,
-                                    S(stream));
+                                    S(stream), ncp);
     else
       launch_prolongate_add<float>(F.g, C.g, F.h_to_coarser, F.emb.data(), (float *)dst, (const float *)src,
-                                   S(stream));
+                                   S(stream), ncp);
   });
 }
 
@@ -1115,10 +1460,13 @@ int mfs_restrict(mfs_problem *p, int prec, int fine, void *dst, const void *src,
     check_prec(prec);
     MFS_REQUIRE(fine + 1 < p->nlev, MFS_EINVAL, "no coarser level below %d", fine);
     const Level &F = p->L[fine], &C = p->L[fine + 1];
+    const int ncp = p->ns ? 1 : 0;
     if (prec == MFS_FP64)
-      launch_restrict<double>(F.g, C.g, F.h_to_coarser, F.emb.data(), (double *)dst, (const double *)src, S(stream));
+      launch_restrict<double>(F.g, C.g, F.h_to_coarser, F.emb.data(), (double *)dst, (const double *)src, S(stream),
+                              ncp);
     else
-      launch_restrict<float>(F.g, C.g, F.h_to_coarser, F.emb.data(), (float *)dst, (const float *)src, S(stream));
+      launch_restrict<float>(F.g, C.g, F.h_to_coarser, F.emb.data(), (float *)dst, (const float *)src, S(stream),
+                             ncp);
   });
 }
 
@@ -1128,10 +1476,11 @@ int mfs_precondition(mfs_problem *p, int prec, void *dst, const void *src, void 
     check_prec(prec);
     MFS_REQUIRE(p->opts.mg_levels && p->L[0].g.Np > 0, MFS_EINVAL, "needs multigrid levels and a pressure space");
     MFS_REQUIRE(dst && src && dst != src, MFS_EINVAL, "bad vectors");
+    MFS_REQUIRE(!p->ns || p->ns_ready, MFS_EINVAL, "mfs_set_linearization has not been called");
     if (prec == MFS_FP64)
-      precondition<double>(*p, (double *)dst, (const double *)src, S(stream));
+      precondition_any<double>(*p, (double *)dst, (const double *)src, S(stream));
     else
-      precondition<float>(*p, (float *)dst, (const float *)src, S(stream));
+      precondition_any<float>(*p, (float *)dst, (const float *)src, S(stream));
   });
 }
 
@@ -1139,6 +1488,7 @@ int mfs_rhs(mfs_problem *p, const double *f_qp, const double *u_dirichlet, doubl
   return guard([&] {
     check_problem(p);
     MFS_REQUIRE(f_qp && u_dirichlet && b, MFS_EINVAL, "NULL vector");
+    MFS_REQUIRE(!p->ns, MFS_EUNSUPPORTED, "mfs_rhs assembles the Stokes right-hand side only");
     const Level &L = p->L[0];
     const LevelGeom &g = L.g;
     MFS_REQUIRE(g.Np > 0, MFS_EINVAL, "needs a pressure space");
@@ -1214,11 +1564,10 @@ int mfs_solve(mfs_problem *p, const double *b, double *x, const mfs_options *opt
 int mfs_set_linearization(mfs_problem *p, const double *u0, double dt, int newton, void *stream) {
   return guard([&] {
     check_problem(p);
-    (void)u0;
-    (void)dt;
-    (void)newton;
-    (void)stream;
-    MFS_REQUIRE(false, MFS_EUNSUPPORTED, "Navier-Stokes linearisation not available in this build");
+    MFS_REQUIRE(p->ns, MFS_EINVAL, "linearisation needs a problem set up with pressure_offset = 0");
+    MFS_REQUIRE(u0 != nullptr, MFS_EINVAL, "u0 is NULL");
+    MFS_REQUIRE(dt > 0 && std::isfinite(dt), MFS_EINVAL, "dt must be positive");
+    ns_set_linearization(*p, u0, dt, newton, S(stream));
   });
 }
 

@@ -121,13 +121,45 @@ template <typename T>
 void launch_fill_dirichlet(const LevelGeom &g, T *dst_u, const T *src_u, hipStream_t s);
 
 // transfers between a fine level and the next coarser one
-// emb_host: host 1D embedding [F+1][kc+1] (h_embedding / p_embedding)
+// emb_host: host 1D embedding [F+1][kc+1] (h_embedding / p_embedding);
+// vectors: dim constrained velocity components, then `ncp` unconstrained
+// components (1: the equal-order pressure)
 template <typename T>
 void launch_prolongate_add(const LevelGeom &fine, const LevelGeom &coarse, bool h_transfer, const double *emb_host,
-                           T *dst_fine, const T *src_coarse, hipStream_t s);
+                           T *dst_fine, const T *src_coarse, hipStream_t s, int ncp = 0);
 template <typename T>
 void launch_restrict(const LevelGeom &fine, const LevelGeom &coarse, bool h_transfer, const double *emb_host,
-                     T *dst_coarse, const T *src_fine, hipStream_t s);
+                     T *dst_coarse, const T *src_fine, hipStream_t s, int ncp = 0);
+
+// ----------------------------------------------------------------- Navier-Stokes (ns_kernels.hip)
+// per-quadrature-point linearisation data: u0 (3), grad u0 (9), R(u0) (3),
+// delta_1 (1), stored [cell][field][point]
+constexpr int NS_QD = 16;
+inline int64_t ns_qd_elems(const LevelGeom &g) {
+  int64_t nq = 1;
+  for (int a = 0; a < g.dim; ++a) nq *= g.k + 1;
+  return g.ncells * nq * NS_QD;
+}
+// what = 0: qd = linearisation data of the nodal velocity src (dim*Nv);
+// what = 1: dst += J src on the free velocity rows and all pressure rows
+// (src, dst full equal-order vectors; the Dirichlet rows of dst untouched)
+template <typename T>
+void launch_ns(const LevelGeom &g, const T *X, const T *tab, int what, T nu, T dt, int newton, const T *src, T *dst,
+               T *qd, hipStream_t s);
+// coarse velocity = fine velocity at the shared nodes (fine index 2 * coarse
+// index per direction; h-coarsening at k <= 2 and p-coarsening 2 -> 1)
+void launch_ns_inject(const LevelGeom &fine, const LevelGeom &coarse, const double *u_fine, double *u_coarse,
+                      hipStream_t s);
+// node colouring by (i mod q, j mod q, l mod q): with q = k+1 no two nodes of
+// a colour share a cell.  indicator: out = 1 on component `comp` at the nodes
+// of `color`, 0 elsewhere (ncomp*Nv entries); extract: diag[comp*Nv + i] =
+// y[comp*Nv + i] at those nodes.
+void launch_color_indicator(const LevelGeom &g, int ncomp, int q, int color, int comp, double *out, hipStream_t s);
+void launch_color_extract(const LevelGeom &g, int q, int color, int comp, const double *y, double *diag,
+                          hipStream_t s);
+// damped Jacobi sweep: x += omega * invdiag * (b - t)
+template <typename T>
+void jacobi_relax(T *x, const T *b, const T *t, const T *invdiag, T omega, int64_t n, hipStream_t s);
 
 // vector kernels (vector_kernels.hip)
 template <typename T>

@@ -1,0 +1,523 @@
+// SUPG/PSPG-stabilised Navier-Stokes Jacobian (Sec. 5) on equal-order
+// Q_k/Q_k elements, matrix-free, one thread per quadrature point.
+//
+// At the linearisation point (u0, p0 = 0) with BDF2 mass shift
+// alpha = 3 / (2 dt), the Jacobian applied to (du, dp) tested with (v, q) is
+//   (alpha du + du.grad u0 + u0.grad du, v) + nu (grad du, grad v)
+//   - (dp, div v) + (div du, q)
+//   + delta_1 (R_lin, u0.grad v) + delta_1 (R(u0), du.grad v) + delta_1 (R_lin, grad q)
+// with R_lin = alpha du + du.grad u0 + u0.grad du + grad dp - nu Lap du and
+// R(u0) = u0.grad u0 - nu Lap u0; the Oseen variant drops du.grad u0 and the
+// R(u0) term.  delta_1 = [(2/dt)^2 + (2|u0|/h_K)^2 + 9 (4 nu / h_K^2)^2]^(-1/2),
+// h_K = |K|^(1/d) / k, frozen.  Laplacians are J^{-T} H J^{-1} of the
+// reference Hessian (exact on affine cells).
+//
+// The linearisation kernel stores per quadrature point: u0 (3), grad u0 (9,
+// [comp][direction]), R(u0) (3), delta_1 (1): NS_QD = 16 values, laid out
+// [cell][field][point] so the threads of a cell read consecutive words.
+#include <algorithm>
+
+#include "internal.h"
+
+namespace mfs {
+
+namespace nsk {
+
+template <int DIM, int K>
+struct Shape {
+  static constexpr int Q = K + 1;
+  static constexpr int NQ = DIM == 2 ? Q * Q : Q * Q * Q;
+  static constexpr int CPB = NQ >= 256 ? 1 : 256 / NQ;
+  static constexpr int NT = CPB * NQ;
+  static constexpr int BLOCK = (NT + 63) / 64 * 64;
+  static constexpr int NV = 1 << DIM;
+};
+
+template <typename T>
+struct Args {
+  int n0, n1, n2, ncells;
+  int nv0, nv1, nv2;
+  int64_t Nv;
+  const T *X, *tab, *src;
+  T *dst;
+  T *qd;
+  T nu, alpha, dt;
+  int newton;
+};
+
+template <int DIM, int Q, int DIR, int C, bool TR, typename T>
+__device__ __forceinline__ T sweep(const T *in, const T *mat, int qi, int qj, int ql) {
+  const int r = DIR == 0 ? qi : (DIR == 1 ? qj : ql);
+  const int base = DIR == 0 ? Q * (qj + Q * ql) : (DIR == 1 ? qi + Q * Q * ql : qi + Q * qj);
+  constexpr int stride = DIR == 0 ? 1 : (DIR == 1 ? Q : Q * Q);
+  T s = 0;
+#pragma unroll
+  for (int m = 0; m < C; ++m) s += (TR ? mat[m * MAXQ + r] : mat[r * MAXQ + m]) * in[base + m * stride];
+  return s;
+}
+
+template <int DIM, typename T>
+__device__ __forceinline__ T jac_inv(const T *Xc, const T xi[3], T I[3][3]) {
+  T J[3][3] = {};
+  for (int v = 0; v < (1 << DIM); ++v) {
+    T f[3], df[3];
+    for (int b = 0; b < DIM; ++b) {
+      const bool hi = (v >> b) & 1;
+      f[b] = hi ? xi[b] : T(1) - xi[b];
+      df[b] = hi ? T(1) : T(-1);
+    }
+    for (int b = 0; b < DIM; ++b) {
+      T d = df[b];
+      for (int c = 0; c < DIM; ++c)
+        if (c != b) d *= f[c];
+      for (int a = 0; a < DIM; ++a) J[a][b] += Xc[v * DIM + a] * d;
+    }
+  }
+  if (DIM == 2) {
+    const T det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    const T r = T(1) / det;
+    I[0][0] = J[1][1] * r;
+    I[0][1] = -J[0][1] * r;
+    I[1][0] = -J[1][0] * r;
+    I[1][1] = J[0][0] * r;
+    return det;
+  }
+  const T c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+  const T c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+  const T c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+  const T det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+  const T r = T(1) / det;
+  I[0][0] = c00 * r;
+  I[1][0] = c01 * r;
+  I[2][0] = c02 * r;
+  I[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * r;
+  I[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * r;
+  I[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * r;
+  I[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * r;
+  I[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * r;
+  I[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * r;
+  return det;
+}
+
+// Per-cell thread context: LDS buffers and sum-factorised evaluation.
+template <int DIM, int K, typename T>
+struct Ctx {
+  static constexpr int Q = K + 1, NQ = Shape<DIM, K>::NQ;
+  int t, qi, qj, ql, cx, cy, cz;
+  bool valid, active;
+  T *b0, *b1, *b2;
+  const T *tab;
+
+  __device__ __forceinline__ int64_t node(int nv0, int nv1) const {
+    return (int64_t)(cx * K + qi) + (int64_t)nv0 * ((cy * K + qj) + (int64_t)nv1 * (cz * K + ql));
+  }
+  __device__ __forceinline__ bool dirichlet(int nv0, int nv1, int nv2) const {
+    const int gx = cx * K + qi, gy = cy * K + qj, gz = cz * K + ql;
+    bool d = gx == 0 || gx == nv0 - 1 || gy == 0 || gy == nv1 - 1;
+    if (DIM == 3) d = d || gz == 0 || gz == nv2 - 1;
+    return d;
+  }
+  // nodal value of this thread in b0 on entry: value, reference gradient,
+  // and (HESS) reference Hessian (00, 01, 11 | 00, 01, 02, 11, 12, 22) at the point
+  template <bool HESS>
+  __device__ __forceinline__ void evaluate(T &val, T g[3], T h[6]) {
+    const T *S = tab + TAB_S;
+    T v = sweep<DIM, Q, 0, Q, false>(b0, S, qi, qj, ql);
+    if (active) b1[t] = v;
+    __syncthreads();
+    v = sweep<DIM, Q, 1, Q, false>(b1, S, qi, qj, ql);
+    if (active) b0[t] = v;
+    __syncthreads();
+    T *vals = b0;
+    if (DIM == 3) {
+      v = sweep<DIM, Q, 2, Q, false>(b0, S, qi, qj, ql);
+      if (active) b1[t] = v;
+      __syncthreads();
+      vals = b1;
+    }
+    val = vals[t];
+    const T *D = tab + TAB_D;
+    g[0] = sweep<DIM, Q, 0, Q, false>(vals, D, qi, qj, ql);
+    g[1] = sweep<DIM, Q, 1, Q, false>(vals, D, qi, qj, ql);
+    g[2] = DIM == 3 ? sweep<DIM, Q, 2, Q, false>(vals, D, qi, qj, ql) : T(0);
+    __syncthreads();
+    if (HESS) {
+      if (active) {
+        b0[t] = g[0];
+        b1[t] = g[1];
+        if (DIM == 3) b2[t] = g[2];
+      }
+      __syncthreads();
+      if (DIM == 2) {
+        h[0] = sweep<DIM, Q, 0, Q, false>(b0, D, qi, qj, ql);
+        h[1] = sweep<DIM, Q, 0, Q, false>(b1, D, qi, qj, ql);
+        h[2] = sweep<DIM, Q, 1, Q, false>(b1, D, qi, qj, ql);
+      } else {
+        h[0] = sweep<DIM, Q, 0, Q, false>(b0, D, qi, qj, ql);
+        h[1] = sweep<DIM, Q, 0, Q, false>(b1, D, qi, qj, ql);
+        h[2] = sweep<DIM, Q, 0, Q, false>(b2, D, qi, qj, ql);
+        h[3] = sweep<DIM, Q, 1, Q, false>(b1, D, qi, qj, ql);
+        h[4] = sweep<DIM, Q, 1, Q, false>(b2, D, qi, qj, ql);
+        h[5] = sweep<DIM, Q, 2, Q, false>(b2, D, qi, qj, ql);
+      }
+      __syncthreads();
+    }
+  }
+  // test with value and reference-gradient coefficients -> nodal value
+  __device__ __forceinline__ T integrate(T val, const T f[3]) {
+    if (active) {
+      b0[t] = f[0];
+      b1[t] = f[1];
+      if (DIM == 3) b2[t] = f[2];
+    }
+    __syncthreads();
+    const T *D = tab + TAB_D;
+    T r = val + sweep<DIM, Q, 0, Q, true>(b0, D, qi, qj, ql) + sweep<DIM, Q, 1, Q, true>(b1, D, qi, qj, ql);
+    if (DIM == 3) r += sweep<DIM, Q, 2, Q, true>(b2, D, qi, qj, ql);
+    __syncthreads();
+    if (active) b0[t] = r;
+    __syncthreads();
+    const T *S = tab + TAB_S;
+    T out;
+    if (DIM == 2) {
+      T v = sweep<DIM, Q, 1, Q, true>(b0, S, qi, qj, ql);
+      if (active) b1[t] = v;
+      __syncthreads();
+      out = sweep<DIM, Q, 0, Q, true>(b1, S, qi, qj, ql);
+    } else {
+      T v = sweep<DIM, Q, 2, Q, true>(b0, S, qi, qj, ql);
+      if (active) b1[t] = v;
+      __syncthreads();
+      v = sweep<DIM, Q, 1, Q, true>(b1, S, qi, qj, ql);
+      if (active) b0[t] = v;
+      __syncthreads();
+      out = sweep<DIM, Q, 0, Q, true>(b0, S, qi, qj, ql);
+    }
+    __syncthreads();
+    return out;
+  }
+};
+
+// physical Laplacian from the reference Hessian: sum_a sum_bc I[b][a] I[c][a] H_bc
+template <int DIM, typename T>
+__device__ __forceinline__ T laplacian(const T h[6], const T I[3][3]) {
+  T H[3][3];
+  if (DIM == 2) {
+    H[0][0] = h[0];
+    H[0][1] = H[1][0] = h[1];
+    H[1][1] = h[2];
+  } else {
+    H[0][0] = h[0];
+    H[0][1] = H[1][0] = h[1];
+    H[0][2] = H[2][0] = h[2];
+    H[1][1] = h[3];
+    H[1][2] = H[2][1] = h[4];
+    H[2][2] = h[5];
+  }
+  T s = 0;
+  for (int a = 0; a < DIM; ++a)
+    for (int b = 0; b < DIM; ++b)
+      for (int c = 0; c < DIM; ++c) s += I[b][a] * I[c][a] * H[b][c];
+  return s;
+}
+
+#define NSK_PROLOGUE                                                                                   \
+  using Sh = Shape<DIM, K>;                                                                            \
+  constexpr int NQ = Sh::NQ, CPB = Sh::CPB, Q = Sh::Q;                                                 \
+  __shared__ T s_tab[TAB_SIZE];                                                                        \
+  __shared__ T s_buf[3][CPB * NQ];                                                                     \
+  __shared__ T s_X[CPB][Sh::NV * DIM];                                                                 \
+  const int tid = threadIdx.x;                                                                         \
+  for (int i = tid; i < TAB_SIZE; i += Sh::BLOCK) s_tab[i] = a.tab[i];                                 \
+  Ctx<DIM, K, T> c;                                                                                    \
+  c.active = tid < Sh::NT;                                                                             \
+  const int e = c.active ? tid / NQ : CPB - 1;                                                         \
+  c.t = c.active ? tid - e * NQ : 0;                                                                   \
+  const int cell = blockIdx.x * CPB + e;                                                               \
+  c.valid = c.active && cell < a.ncells;                                                               \
+  c.qi = c.t % Q;                                                                                      \
+  c.qj = (c.t / Q) % Q;                                                                                \
+  c.ql = DIM == 3 ? c.t / (Q * Q) : 0;                                                                 \
+  c.cx = c.cy = c.cz = 0;                                                                              \
+  if (c.valid) {                                                                                       \
+    c.cx = cell % a.n0;                                                                                \
+    const int r_ = cell / a.n0;                                                                        \
+    c.cy = r_ % a.n1;                                                                                  \
+    c.cz = DIM == 3 ? r_ / a.n1 : 0;                                                                   \
+  }                                                                                                    \
+  c.b0 = &s_buf[0][e * NQ];                                                                            \
+  c.b1 = &s_buf[1][e * NQ];                                                                            \
+  c.b2 = &s_buf[2][e * NQ];                                                                            \
+  c.tab = s_tab;                                                                                       \
+  if (c.valid)                                                                                         \
+    for (int idx = c.t; idx < Sh::NV * DIM; idx += NQ) {                                               \
+      const int v_ = idx / DIM, comp_ = idx % DIM;                                                     \
+      const int vx = c.cx + (v_ & 1), vy = c.cy + ((v_ >> 1) & 1), vz = c.cz + ((v_ >> 2) & 1);        \
+      const int64_t vid = vx + (int64_t)(a.n0 + 1) * (vy + (int64_t)(a.n1 + 1) * (DIM == 3 ? vz : 0)); \
+      s_X[e][idx] = a.X[vid * DIM + comp_];                                                            \
+    }                                                                                                  \
+  __syncthreads();                                                                                     \
+  T xi[3] = {s_tab[TAB_X + c.qi], s_tab[TAB_X + c.qj], DIM == 3 ? s_tab[TAB_X + c.ql] : T(0)};         \
+  T I[3][3] = {};                                                                                      \
+  const T det = jac_inv<DIM>(s_X[e], xi, I);                                                           \
+  T wq = s_tab[TAB_W + c.qi] * s_tab[TAB_W + c.qj];                                                    \
+  if (DIM == 3) wq *= s_tab[TAB_W + c.ql];                                                             \
+  const T JxW = det * wq;                                                                              \
+  const int64_t nd = c.valid ? c.node(a.nv0, a.nv1) : 0;                                               \
+  const bool dir = c.valid ? c.dirichlet(a.nv0, a.nv1, a.nv2) : true;                                  \
+  T *qd = a.qd + ((int64_t)(c.valid ? cell : 0) * NS_QD) * NQ + c.t;
+
+// linearisation data at the quadrature points from the nodal velocity u0
+template <int DIM, int K, typename T>
+__global__ void __launch_bounds__((Shape<DIM, K>::BLOCK)) ns_linearize_kernel(Args<T> a) {
+  NSK_PROLOGUE
+  __shared__ T s_vol[CPB];
+  T u[3] = {}, U[3][3] = {}, lap[3] = {};
+  for (int comp = 0; comp < DIM; ++comp) {
+    if (c.active) c.b0[c.t] = c.valid ? a.src[comp * a.Nv + nd] : T(0);
+    __syncthreads();
+    T val, g[3], h[6];
+    c.template evaluate<true>(val, g, h);
+    u[comp] = val;
+    for (int x = 0; x < DIM; ++x) {
+      T s = 0;
+      for (int b = 0; b < DIM; ++b) s += I[b][x] * g[b];
+      U[comp][x] = s;
+    }
+    lap[comp] = laplacian<DIM>(h, I);
+  }
+  // cell volume
+  if (c.active && c.t == 0) s_vol[e] = 0;
+  __syncthreads();
+  if (c.valid) atomicAdd(&s_vol[e], JxW);
+  __syncthreads();
+  const T hK = pow(s_vol[e], T(1) / T(DIM)) / T(K);
+  T speed2 = 0, R0[3];
+  for (int comp = 0; comp < DIM; ++comp) {
+    speed2 += u[comp] * u[comp];
+    T s = 0;
+    for (int x = 0; x < DIM; ++x) s += u[x] * U[comp][x];
+    R0[comp] = s - a.nu * lap[comp];
+  }
+  const T t1 = T(2) / a.dt, t2 = T(2) * sqrt(speed2) / hK, t3 = T(4) * a.nu / (hK * hK);
+  const T delta = T(1) / sqrt(t1 * t1 + t2 * t2 + T(9) * t3 * t3);
+  if (c.valid) {
+    for (int f = 0; f < NS_QD; ++f) {
+      T v = 0;
+      if (f < 3) v = f < DIM ? u[f] : T(0);
+      else if (f < 12) v = ((f - 3) / 3 < DIM && (f - 3) % 3 < DIM) ? U[(f - 3) / 3][(f - 3) % 3] : T(0);
+      else if (f < 15) v = f - 12 < DIM ? R0[f - 12] : T(0);
+      else v = delta;
+      qd[f * NQ] = v;
+    }
+  }
+}
+
+// Jacobian application
+template <int DIM, int K, typename T>
+__global__ void __launch_bounds__((Shape<DIM, K>::BLOCK)) ns_jacobian_kernel(Args<T> a) {
+  NSK_PROLOGUE
+  // linearisation data of this point
+  T u0[3] = {}, U[3][3] = {}, R0[3] = {}, dl = 0;
+  if (c.valid) {
+    for (int x = 0; x < DIM; ++x) u0[x] = qd[x * NQ];
+    for (int cc = 0; cc < DIM; ++cc)
+      for (int x = 0; x < DIM; ++x) U[cc][x] = qd[(3 + 3 * cc + x) * NQ];
+    for (int x = 0; x < DIM; ++x) R0[x] = qd[(12 + x) * NQ];
+    dl = qd[15 * NQ];
+  }
+  // trial fields
+  T w[3] = {}, G[3][3] = {}, L[3] = {};
+  for (int comp = 0; comp < DIM; ++comp) {
+    if (c.active) c.b0[c.t] = (c.valid && !dir) ? a.src[comp * a.Nv + nd] : T(0);
+    __syncthreads();
+    T val, g[3], h[6];
+    c.template evaluate<true>(val, g, h);
+    w[comp] = val;
+    for (int x = 0; x < DIM; ++x) {
+      T s = 0;
+      for (int b = 0; b < DIM; ++b) s += I[b][x] * g[b];
+      G[comp][x] = s;
+    }
+    L[comp] = laplacian<DIM>(h, I);
+  }
+  T P, gP[3] = {};
+  {
+    if (c.active) c.b0[c.t] = c.valid ? a.src[DIM * a.Nv + nd] : T(0);
+    __syncthreads();
+    T g[3], h[6];
+    c.template evaluate<false>(P, g, h);
+    for (int x = 0; x < DIM; ++x) {
+      T s = 0;
+      for (int b = 0; b < DIM; ++b) s += I[b][x] * g[b];
+      gP[x] = s;
+    }
+  }
+  // point physics
+  T val_u[3], grad_u[3][3], Rl[3];
+  for (int cc = 0; cc < DIM; ++cc) {
+    T conv = 0, newt = 0;
+    for (int x = 0; x < DIM; ++x) {
+      conv += u0[x] * G[cc][x];
+      newt += w[x] * U[cc][x];
+    }
+    if (!a.newton) newt = 0;
+    val_u[cc] = a.alpha * w[cc] + newt + conv;
+    Rl[cc] = val_u[cc] + gP[cc] - a.nu * L[cc];
+  }
+  T div = 0;
+  for (int cc = 0; cc < DIM; ++cc) {
+    div += G[cc][cc];
+    for (int x = 0; x < DIM; ++x) {
+      T v = a.nu * G[cc][x] + dl * Rl[cc] * u0[x];
+      if (a.newton) v += dl * R0[cc] * w[x];
+      if (x == cc) v -= P;
+      grad_u[cc][x] = v;
+    }
+  }
+  // test: physical gradient coefficients -> reference (I f), times JxW
+  for (int comp = 0; comp < DIM; ++comp) {
+    T f[3] = {};
+    for (int b = 0; b < DIM; ++b) {
+      T s = 0;
+      for (int x = 0; x < DIM; ++x) s += I[b][x] * grad_u[comp][x];
+      f[b] = JxW * s;
+    }
+    const T r = c.integrate(JxW * val_u[comp], f);
+    if (c.valid && !dir) atomicAdd(a.dst + comp * a.Nv + nd, r);
+  }
+  {
+    T f[3] = {};
+    for (int b = 0; b < DIM; ++b) {
+      T s = 0;
+      for (int x = 0; x < DIM; ++x) s += I[b][x] * dl * Rl[x];
+      f[b] = JxW * s;
+    }
+    const T r = c.integrate(JxW * div, f);
+    if (c.valid) atomicAdd(a.dst + DIM * a.Nv + nd, r);
+  }
+}
+
+#undef NSK_PROLOGUE
+
+}  // namespace nsk
+
+template <typename T>
+void launch_ns(const LevelGeom &g, const T *X, const T *tab, int what, T nu, T dt, int newton, const T *src, T *dst,
+               T *qd, hipStream_t s) {
+  MFS_REQUIRE(g.kp == g.k, MFS_EUNSUPPORTED, "Navier-Stokes operator needs equal-order elements");
+  nsk::Args<T> a{};
+  a.n0 = g.n[0];
+  a.n1 = g.n[1];
+  a.n2 = g.n[2];
+  a.ncells = (int)g.ncells;
+  a.nv0 = g.nv[0];
+  a.nv1 = g.nv[1];
+  a.nv2 = g.nv[2];
+  a.Nv = g.Nv;
+  a.X = X;
+  a.tab = tab;
+  a.src = src;
+  a.dst = dst;
+  a.qd = qd;
+  a.nu = nu;
+  a.dt = dt;
+  a.alpha = T(1.5) / dt;
+  a.newton = newton;
+#define NS_GO(D, KK)                                                                                             \
+  {                                                                                                              \
+    using Sh = nsk::Shape<D, KK>;                                                                                \
+    const int grid = (int)((g.ncells + Sh::CPB - 1) / Sh::CPB);                                                  \
+    if (what == 0)                                                                                               \
+      hipLaunchKernelGGL((nsk::ns_linearize_kernel<D, KK, T>), dim3(grid), dim3(Sh::BLOCK), 0, s, a);            \
+    else                                                                                                         \
+      hipLaunchKernelGGL((nsk::ns_jacobian_kernel<D, KK, T>), dim3(grid), dim3(Sh::BLOCK), 0, s, a);             \
+  }
+  if (g.dim == 2) {
+    if (g.k == 1) NS_GO(2, 1) else if (g.k == 2) NS_GO(2, 2) else if (g.k == 3) NS_GO(2, 3)
+    else MFS_REQUIRE(false, MFS_EUNSUPPORTED, "Navier-Stokes degree %d", g.k);
+  } else {
+    if (g.k == 1) NS_GO(3, 1) else if (g.k == 2) NS_GO(3, 2) else if (g.k == 3) NS_GO(3, 3)
+    else MFS_REQUIRE(false, MFS_EUNSUPPORTED, "Navier-Stokes degree %d", g.k);
+  }
+#undef NS_GO
+  MFS_HIP(hipGetLastError());
+}
+
+template void launch_ns<double>(const LevelGeom &, const double *, const double *, int, double, double, int,
+                                const double *, double *, double *, hipStream_t);
+template void launch_ns<float>(const LevelGeom &, const float *, const float *, int, float, float, int, const float *,
+                               float *, float *, hipStream_t);
+
+namespace {
+
+__global__ void k_ns_inject(int dim, int nf0, int nf1, int64_t Nf, int nc0, int nc1, int64_t Nc, const double *uf,
+                            double *uc) {
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= Nc) return;
+  const int64_t i = c % nc0, j = (c / nc0) % nc1, l = c / ((int64_t)nc0 * nc1);
+  const int64_t f = 2 * i + (int64_t)nf0 * (2 * j + (int64_t)nf1 * 2 * l);
+  for (int comp = 0; comp < dim; ++comp) uc[comp * Nc + c] = uf[comp * Nf + f];
+}
+
+__device__ __forceinline__ int node_color(const LevelGeom &g, int q, int64_t i) {
+  const int64_t x = i % g.nv[0], y = (i / g.nv[0]) % g.nv[1], z = i / ((int64_t)g.nv[0] * g.nv[1]);
+  return (int)(x % q) + q * ((int)(y % q) + q * (int)(z % q));
+}
+
+__global__ void k_color_indicator(LevelGeom g, int ncomp, int q, int color, int comp, double *out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= g.Nv) return;
+  const bool on = node_color(g, q, i) == color;
+  for (int c = 0; c < ncomp; ++c) out[c * g.Nv + i] = (on && c == comp) ? 1.0 : 0.0;
+}
+
+__global__ void k_color_extract(LevelGeom g, int q, int color, int comp, const double *y, double *diag) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= g.Nv) return;
+  if (node_color(g, q, i) == color) diag[comp * g.Nv + i] = y[comp * g.Nv + i];
+}
+
+template <typename T>
+__global__ void k_jacobi_relax(T *x, const T *b, const T *t, const T *invdiag, T omega, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    x[i] += omega * invdiag[i] * (b[i] - t[i]);
+}
+
+unsigned blocks_for(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192)); }
+
+}  // namespace
+
+void launch_ns_inject(const LevelGeom &fine, const LevelGeom &coarse, const double *u_fine, double *u_coarse,
+                      hipStream_t s) {
+  for (int a = 0; a < fine.dim; ++a)
+    MFS_REQUIRE(fine.nv[a] == 2 * coarse.nv[a] - 1, MFS_EUNSUPPORTED,
+                "coarse nodes are not every second fine node (degree > 2)");
+  hipLaunchKernelGGL(k_ns_inject, dim3((unsigned)((coarse.Nv + 255) / 256)), dim3(256), 0, s, fine.dim, fine.nv[0],
+                     fine.nv[1], fine.Nv, coarse.nv[0], coarse.nv[1], coarse.Nv, u_fine, u_coarse);
+  MFS_HIP(hipGetLastError());
+}
+
+void launch_color_indicator(const LevelGeom &g, int ncomp, int q, int color, int comp, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_color_indicator, dim3((unsigned)((g.Nv + 255) / 256)), dim3(256), 0, s, g, ncomp, q, color,
+                     comp, out);
+  MFS_HIP(hipGetLastError());
+}
+
+void launch_color_extract(const LevelGeom &g, int q, int color, int comp, const double *y, double *diag,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_color_extract, dim3((unsigned)((g.Nv + 255) / 256)), dim3(256), 0, s, g, q, color, comp, y,
+                     diag);
+  MFS_HIP(hipGetLastError());
+}
+
+template <typename T>
+void jacobi_relax(T *x, const T *b, const T *t, const T *invdiag, T omega, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_jacobi_relax<T>, dim3(blocks_for(n)), dim3(256), 0, s, x, b, t, invdiag, omega, n);
+  MFS_HIP(hipGetLastError());
+}
+template void jacobi_relax<double>(double *, const double *, const double *, const double *, double, int64_t,
+                                   hipStream_t);
+template void jacobi_relax<float>(float *, const float *, const float *, const float *, float, int64_t, hipStream_t);
+
+}  // namespace mfs

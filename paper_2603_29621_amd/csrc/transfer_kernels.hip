@@ -14,12 +14,16 @@
 //    cells equals this single evaluation);
 //  * restriction: thread per coarse node, gathering w * E * r_f over the fine
 //    nodes of every coarse cell that contains it, direction by direction.
+// Vectors hold `ncu` components carrying the Dirichlet constraints (the
+// velocity) followed by `ncp` unconstrained ones (the equal-order pressure of
+// the monolithic Navier-Stokes hierarchy), each of one scalar node grid.
 #include "internal.h"
 
 namespace mfs {
 
 struct TransferArgs {
   int dim;
+  int ncu, ncp;  // constrained / unconstrained components
   int F;    // fine nodes per coarse cell edge minus one (h: 2k, p: kf)
   int kc;   // coarse degree
   int nc[3];          // coarse cells per direction
@@ -35,27 +39,30 @@ __global__ void k_prolongate_add(TransferArgs a, T *dst, const T *src) {
   int g[3] = {(int)(f % a.nf[0]), (int)((f / a.nf[0]) % a.nf[1]), 0};
   if (a.dim == 3) g[2] = (int)(f / ((int64_t)a.nf[0] * a.nf[1]));
   int C[3] = {0, 0, 0}, i[3] = {0, 0, 0};
+  bool fine_bnd = false;
   for (int d = 0; d < a.dim; ++d) {
-    if (g[d] == 0 || g[d] == a.nf[d] - 1) return;  // fine Dirichlet row of P is zero
+    fine_bnd = fine_bnd || g[d] == 0 || g[d] == a.nf[d] - 1;  // fine Dirichlet row of P is zero
     C[d] = g[d] / a.F;
     if (C[d] >= a.nc[d]) C[d] = a.nc[d] - 1;
     i[d] = g[d] - a.F * C[d];
   }
   const int n1 = a.kc + 1;
   const int nz = a.dim == 3 ? n1 : 1;
-  for (int comp = 0; comp < a.dim; ++comp) {
+  for (int comp = 0; comp < a.ncu + a.ncp; ++comp) {
+    const bool con = comp < a.ncu;
+    if (con && fine_bnd) continue;
     double acc = 0;
     for (int j2 = 0; j2 < nz; ++j2) {
       const int c2 = a.dim == 3 ? C[2] * a.kc + j2 : 0;
-      if (a.dim == 3 && (c2 == 0 || c2 == a.ncn[2] - 1)) continue;
+      if (con && a.dim == 3 && (c2 == 0 || c2 == a.ncn[2] - 1)) continue;
       const double e2 = a.dim == 3 ? a.E[i[2] * MAXQ + j2] : 1.0;
       for (int j1 = 0; j1 < n1; ++j1) {
         const int c1 = C[1] * a.kc + j1;
-        if (c1 == 0 || c1 == a.ncn[1] - 1) continue;
+        if (con && (c1 == 0 || c1 == a.ncn[1] - 1)) continue;
         const double e21 = e2 * a.E[i[1] * MAXQ + j1];
         for (int j0 = 0; j0 < n1; ++j0) {
           const int c0 = C[0] * a.kc + j0;
-          if (c0 == 0 || c0 == a.ncn[0] - 1) continue;
+          if (con && (c0 == 0 || c0 == a.ncn[0] - 1)) continue;
           const int64_t cn = c0 + (int64_t)a.ncn[0] * (c1 + (int64_t)a.ncn[1] * c2);
           acc += e21 * a.E[i[0] * MAXQ + j0] * (double)src[comp * a.Nc + cn];
         }
@@ -66,7 +73,8 @@ __global__ void k_prolongate_add(TransferArgs a, T *dst, const T *src) {
 }
 
 // per direction: list of (fine index, coefficient) contributing to coarse node gc
-__device__ __forceinline__ int restrict_list(const TransferArgs &a, int d, int gc, int *fi, double *cf) {
+// (con: skip the fine Dirichlet nodes, whose rows of P are zero)
+__device__ __forceinline__ int restrict_list(const TransferArgs &a, int d, int gc, bool con, int *fi, double *cf) {
   int cnt = 0;
   const int nc = a.nc[d];
   int cells[2], nce = 0;
@@ -78,8 +86,9 @@ __device__ __forceinline__ int restrict_list(const TransferArgs &a, int d, int g
     const int j = gc - a.kc * C;
     for (int i = 0; i <= a.F; ++i) {
       const int gf = a.F * C + i;
-      if (gf == 0 || gf == a.nf[d] - 1) continue;  // fine Dirichlet: P row is zero
-      const double m = (gf % a.F == 0) ? 2.0 : 1.0;  // interior shared node of two coarse cells
+      const bool edge = gf == 0 || gf == a.nf[d] - 1;
+      if (con && edge) continue;
+      const double m = (gf % a.F == 0 && !edge) ? 2.0 : 1.0;  // interior node shared by two coarse cells
       const double v = a.E[i * MAXQ + j] / m;
       int found = -1;
       for (int q = 0; q < cnt; ++q)
@@ -104,31 +113,39 @@ __global__ void k_restrict(TransferArgs a, T *dst, const T *src) {
   if (a.dim == 3) g[2] = (int)(c / ((int64_t)a.ncn[0] * a.ncn[1]));
   bool dir = false;
   for (int d = 0; d < a.dim; ++d) dir = dir || g[d] == 0 || g[d] == a.ncn[d] - 1;
-  if (dir) {
-    for (int comp = 0; comp < a.dim; ++comp) dst[comp * a.Nc + c] = 0;
-    return;
-  }
   int fi[3][2 * 2 * MAXQ];
   double cf[3][2 * 2 * MAXQ];
-  int cnt[3] = {1, 1, 1};
-  fi[2][0] = 0;
-  cf[2][0] = 1.0;
-  for (int d = 0; d < a.dim; ++d) cnt[d] = restrict_list(a, d, g[d], fi[d], cf[d]);
-  for (int comp = 0; comp < a.dim; ++comp) {
-    double acc = 0;
-    for (int z = 0; z < cnt[2]; ++z)
-      for (int y = 0; y < cnt[1]; ++y) {
-        const double cyz = cf[2][z] * cf[1][y];
-        const int64_t row = (int64_t)a.nf[0] * (fi[1][y] + (int64_t)a.nf[1] * fi[2][z]);
-        for (int x = 0; x < cnt[0]; ++x) acc += cyz * cf[0][x] * (double)src[comp * a.Nf + row + fi[0][x]];
-      }
-    dst[comp * a.Nc + c] = (T)acc;
+  for (int pass = 0; pass < 2; ++pass) {
+    const bool con = pass == 0;
+    const int c0 = con ? 0 : a.ncu, c1 = con ? a.ncu : a.ncu + a.ncp;
+    if (c0 == c1) continue;
+    if (con && dir) {
+      for (int comp = c0; comp < c1; ++comp) dst[comp * a.Nc + c] = 0;
+      continue;
+    }
+    int cnt[3] = {1, 1, 1};
+    fi[2][0] = 0;
+    cf[2][0] = 1.0;
+    for (int d = 0; d < a.dim; ++d) cnt[d] = restrict_list(a, d, g[d], con, fi[d], cf[d]);
+    for (int comp = c0; comp < c1; ++comp) {
+      double acc = 0;
+      for (int z = 0; z < cnt[2]; ++z)
+        for (int y = 0; y < cnt[1]; ++y) {
+          const double cyz = cf[2][z] * cf[1][y];
+          const int64_t row = (int64_t)a.nf[0] * (fi[1][y] + (int64_t)a.nf[1] * fi[2][z]);
+          for (int x = 0; x < cnt[0]; ++x) acc += cyz * cf[0][x] * (double)src[comp * a.Nf + row + fi[0][x]];
+        }
+      dst[comp * a.Nc + c] = (T)acc;
+    }
   }
 }
 
-static TransferArgs make_targs(const LevelGeom &fine, const LevelGeom &coarse, bool h, const double *emb_host) {
+static TransferArgs make_targs(const LevelGeom &fine, const LevelGeom &coarse, bool h, const double *emb_host,
+                               int ncp) {
   TransferArgs a{};
   a.dim = fine.dim;
+  a.ncu = fine.dim;
+  a.ncp = ncp;
   a.kc = coarse.k;
   a.F = h ? 2 * coarse.k : fine.k;
   for (int d = 0; d < 3; ++d) {
@@ -145,27 +162,27 @@ static TransferArgs make_targs(const LevelGeom &fine, const LevelGeom &coarse, b
 
 template <typename T>
 void launch_prolongate_add(const LevelGeom &fine, const LevelGeom &coarse, bool h, const double *emb, T *dst_fine,
-                           const T *src_coarse, hipStream_t s) {
-  const TransferArgs a = make_targs(fine, coarse, h, emb);
+                           const T *src_coarse, hipStream_t s, int ncp) {
+  const TransferArgs a = make_targs(fine, coarse, h, emb, ncp);
   hipLaunchKernelGGL(k_prolongate_add<T>, dim3((unsigned)((fine.Nv + 255) / 256)), dim3(256), 0, s, a, dst_fine,
                      src_coarse);
   MFS_HIP(hipGetLastError());
 }
 template <typename T>
 void launch_restrict(const LevelGeom &fine, const LevelGeom &coarse, bool h, const double *emb, T *dst_coarse,
-                     const T *src_fine, hipStream_t s) {
-  const TransferArgs a = make_targs(fine, coarse, h, emb);
+                     const T *src_fine, hipStream_t s, int ncp) {
+  const TransferArgs a = make_targs(fine, coarse, h, emb, ncp);
   hipLaunchKernelGGL(k_restrict<T>, dim3((unsigned)((coarse.Nv + 255) / 256)), dim3(256), 0, s, a, dst_coarse,
                      src_fine);
   MFS_HIP(hipGetLastError());
 }
 template void launch_prolongate_add<double>(const LevelGeom &, const LevelGeom &, bool, const double *, double *,
-                                            const double *, hipStream_t);
+                                            const double *, hipStream_t, int);
 template void launch_prolongate_add<float>(const LevelGeom &, const LevelGeom &, bool, const double *, float *,
-                                           const float *, hipStream_t);
+                                           const float *, hipStream_t, int);
 template void launch_restrict<double>(const LevelGeom &, const LevelGeom &, bool, const double *, double *,
-                                      const double *, hipStream_t);
+                                      const double *, hipStream_t, int);
 template void launch_restrict<float>(const LevelGeom &, const LevelGeom &, bool, const double *, float *,
-                                     const float *, hipStream_t);
+                                     const float *, hipStream_t, int);
 
 }  // namespace mfs

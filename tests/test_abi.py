@@ -49,3 +49,23 @@ def test_footprint_and_validation_host_only():
     o = mfs.mfs_default_options(restart=40)
     with pytest.raises(mfs.MfsError):
         mfs.mfs_footprint(3, [4, 4, 4], X, 2, o)
+
+
+def test_navier_stokes_options_validated_on_host():
+    X = inputs.structured_vertices(3, [4, 4, 4])
+    o = mfs.mfs_default_options()
+    assert o.relax_steps == 5 and o.relax_omega == 0.5
+    # equal order: k <= 3 for the operator, k <= 2 with the multigrid hierarchy
+    with pytest.raises(mfs.MfsError) as e:
+        mfs.mfs_footprint(3, [4, 4, 4], X, 3, mfs.mfs_default_options(pressure_offset=0))
+    assert e.value.code == mfs.MFS_EUNSUPPORTED
+    assert mfs.mfs_footprint(3, [4, 4, 4], X, 3, mfs.mfs_default_options(pressure_offset=0, mg_levels=0)) > 0
+    with pytest.raises(mfs.MfsError) as e:
+        mfs.mfs_footprint(3, [4, 4, 4], X, 4, mfs.mfs_default_options(pressure_offset=0, mg_levels=0))
+    assert e.value.code == mfs.MFS_EUNSUPPORTED
+    with pytest.raises(mfs.MfsError):
+        mfs.mfs_footprint(3, [4, 4, 4], X, 2, mfs.mfs_default_options(pressure_offset=0, relax_omega=2.0))
+    # the footprint holds the per-point linearisation data of every level (FP64 + FP32)
+    fp1 = mfs.mfs_footprint(3, [8, 8, 8], inputs.structured_vertices(3, [8, 8, 8]), 1,
+                            mfs.mfs_default_options(pressure_offset=0, mg_levels=0))
+    assert fp1 >= 8 ** 3 * 8 * 16 * 12

@@ -95,3 +95,16 @@ def test_q1_laplacian_vanishes_on_affine_cells():
     S = fem.Space(3, [2, 2, 2], X, 1, kp=1)
     N, G, L, JxW, vol = ns._qp_data(S)
     assert np.abs(L).max() < 1e-12
+
+
+def test_sampled_rows_equal_full_evaluation():
+    X = inputs.structured_vertices(3, [3, 2, 3], noise=0.2, seed=5)
+    S = fem.Space(3, [3, 2, 3], X, 2, 2)
+    rng = np.random.default_rng(2)
+    u0 = rng.uniform(-1, 1, 3 * S.Nv)
+    dx = rng.uniform(-1, 1, 4 * S.Nv)
+    data = ns.linearization_data(S, u0, 0.05, 0.1)
+    full = ns.constrained_jacobian_apply(S, dx, data, 0.05, 0.1)
+    rows = rng.choice(4 * S.Nv, 40, replace=False)
+    np.testing.assert_allclose(ns.sampled_jacobian_rows(S, dx, u0, 0.05, 0.1, rows), full[rows], rtol=0,
+                               atol=1e-13 * np.abs(full).max())
