@@ -28,6 +28,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK = 8.0e12  # B/s, MI355X
+FP64_PEAK = 78.6e12  # flop/s, MI355X vector
+# Estimated algorithmic FP64 flops per DoF of the Q_k/Q_{k-1} vmult on trilinear
+# cells with even-odd sum factorisation (k = 2, 3, 4).
+FLOP_PER_DOF = {2: 318.0, 3: 243.0, 4: 217.0}
+# HBM bytes per FP64 Q2/Q1 vmult on 64^3 cells measured with rocprofv3 FETCH_SIZE and
+# WRITE_SIZE (scaled by 2.00 and 1.00, the factors a 256 MiB device copy gives) for the
+# current cell + combine kernels; to be re-measured whenever those kernels change.
+MEASURED_TRAFFIC = {(2, 64, "f64"): 308.4e6}
 
 
 def algorithmic_bytes(dim, n, k, word):
@@ -38,7 +46,8 @@ def algorithmic_bytes(dim, n, k, word):
     return N, 2 * N * word + verts
 
 
-def time_vmult(mfs, torch, h, N, prec, steps, warmup, rotate_bytes=600e6):
+def time_vmult(mfs, torch, h, N, prec, steps, warmup, rotate_bytes=600e6, op=None):
+    op = mfs.MFS_OP_STOKES if op is None else op
     dt = torch.float64 if prec == mfs.MFS_FP64 else torch.float32
     word = 8 if prec == mfs.MFS_FP64 else 4
     pairs = max(2, int(np.ceil(rotate_bytes / (2 * N * word))))
@@ -48,13 +57,13 @@ def time_vmult(mfs, torch, h, N, prec, steps, warmup, rotate_bytes=600e6):
     dsts = [torch.empty(N, dtype=dt, device="cuda") for _ in range(pairs)]
     stream = torch.cuda.current_stream()
     for i in range(warmup):
-        mfs.mfs_vmult(h, mfs.MFS_OP_STOKES, prec, 0, dsts[i % pairs], srcs[i % pairs])
+        mfs.mfs_vmult(h, op, prec, 0, dsts[i % pairs], srcs[i % pairs])
     torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     t0 = time.perf_counter()
     for i in range(steps):
         ev[i][0].record(stream)
-        mfs.mfs_vmult(h, mfs.MFS_OP_STOKES, prec, 0, dsts[i % pairs], srcs[i % pairs])
+        mfs.mfs_vmult(h, op, prec, 0, dsts[i % pairs], srcs[i % pairs])
         ev[i][1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -123,6 +132,76 @@ def solve_section(mfs, torch, inputs, args):
     return out
 
 
+def ns_section(mfs, torch, inputs, args):
+    """Stabilised Navier-Stokes (SUPG/PSPG, equal order): Jacobian vmult
+    throughput on n^3 Cartesian cells for Q1Q1 and Q2Q2 (BDF2 dt = 1e-2,
+    nu = 0.01, Newton linearisation about the 8-mode unit-RMS Fourier field),
+    and one Newton-step linear solve J x = b (b = J y, y ~ U[-1, 1] with zero
+    Dirichlet rows) with the monolithic FP32 multigrid inside FP64 FGMRES to
+    1e-8, against the all-FP64 method."""
+    out = {}
+    dt, nu = 1e-2, 0.01
+    for k in (1, 2):
+        n = args.ns_n
+        X = inputs.structured_vertices(3, [n] * 3)
+        h = mfs.mfs_setup(3, [n] * 3, X, k, nu, mfs.mfs_default_options(pressure_offset=0, mg_levels=0))
+        try:
+            nv = (k * n + 1) ** 3
+            N = 4 * nv
+            u0 = torch.from_numpy(inputs.ns_velocity(3, [k * n + 1] * 3, seed=0)).cuda()
+            mfs.mfs_set_linearization(h, u0, dt, 1)
+            del u0
+            for prec, name in ((mfs.MFS_FP64, "f64"), (mfs.MFS_FP32, "f32")):
+                word = 8 if prec == mfs.MFS_FP64 else 4
+                wall, per = time_vmult(mfs, torch, h, N, prec, max(10, args.steps // 2), 3,
+                                       op=mfs.MFS_OP_NS_JACOBIAN)
+                avg = float(per.mean())
+                # algorithmic: src + dst + nodal u0 (FP64) + vertices; the stored
+                # per-point linearisation data (16 words per Gauss point) on top
+                alg = 2 * N * word + 3 * nv * 8 + (n + 1) ** 3 * 3 * word
+                stored = n ** 3 * (k + 1) ** 3 * 16 * word
+                out[f"Q{k}Q{k}_{name}"] = {"N": N, "dofs_per_s": N / avg, "avg_launch_us": avg * 1e6,
+                                            "algorithmic_bytes": alg, "stored_qp_bytes": stored,
+                                            "frac_hbm_algorithmic": alg / avg / HBM_PEAK,
+                                            "frac_hbm_with_stored": (alg + stored) / avg / HBM_PEAK}
+        finally:
+            mfs.mfs_destroy(h)
+    out["workload"] = (f"3D SUPG/PSPG Navier-Stokes Jacobian, {args.ns_n}^3 Cartesian cells, BDF2 dt={dt}, "
+                       f"nu={nu}, Newton about the 8-mode Fourier field")
+    # Newton-step solve
+    n, k = args.ns_solve_n, 2
+    X = inputs.structured_vertices(3, [n] * 3)
+    solve = {"workload": f"Q2Q2 {n}^3, J x = J y, rtol 1e-8, monolithic MG (h then p, 5 Jacobi sweeps, omega 0.5)"}
+    for name, prec in (("fp32_mg_fp64_fgmres", mfs.MFS_FP32), ("fp64", mfs.MFS_FP64)):
+        opts = mfs.mfs_default_options(pressure_offset=0, precond_precision=prec, rtol=1e-8, maxit=200)
+        t0 = time.perf_counter()
+        h = mfs.mfs_setup(3, [n] * 3, X, k, nu, opts)
+        try:
+            nv = (k * n + 1) ** 3
+            N = 4 * nv
+            mfs.mfs_set_linearization(h, torch.from_numpy(inputs.ns_velocity(3, [k * n + 1] * 3, seed=0)).cuda(),
+                                      dt, 1)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            y = torch.from_numpy(inputs.uniform_vector(N, 3)).cuda()
+            b = torch.empty_like(y)
+            mfs.mfs_vmult(h, mfs.MFS_OP_NS_JACOBIAN, mfs.MFS_FP64, 0, b, y)  # Dirichlet rows of b = y
+            times, info = [], None
+            for rep in range(2):
+                x = torch.zeros(N, dtype=torch.float64, device="cuda")
+                torch.cuda.synchronize()
+                t2 = time.perf_counter()
+                info = mfs.mfs_solve(h, b, x, opts)
+                times.append(time.perf_counter() - t2)
+            solve[name] = {"setup_s": t1 - t0, "solve_s": min(times), "iterations": info.iterations,
+                           "rel_residual": info.rel_residual, "status": info.status}
+        finally:
+            mfs.mfs_destroy(h)
+    solve["speedup_mixed_vs_fp64"] = solve["fp64"]["solve_s"] / solve["fp32_mg_fp64_fgmres"]["solve_s"]
+    out["solve"] = solve
+    return out
+
+
 def serving_section(args):
     """Bounded sample of the served stream: Poisson arrivals, n in {8, 16, 32},
     k in {2, 3}; continuous batching with FP32 multigrid vs sequential FP64."""
@@ -151,6 +230,11 @@ def main():
     ap.add_argument("--solve-n", type=int, default=64)
     ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--serve-rate", type=float, default=8.0)
+    ap.add_argument("--no-ns", action="store_true", help="skip the Navier-Stokes measurements")
+    ap.add_argument("--ns-n", type=int, default=128)
+    ap.add_argument("--ns-solve-n", type=int, default=32)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one 256 MiB device copy first (reference kernel for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (single-GPU build).",
@@ -163,6 +247,11 @@ def main():
     import paper_2603_29621_amd as mfs
 
     mfs.lib()
+    if args.copy_calibration:
+        a = torch.ones(2 ** 25, dtype=torch.float64, device="cuda")
+        torch.empty_like(a).copy_(a)
+        torch.cuda.synchronize()
+        del a
     dim, n, k = 3, args.n, args.k
     X = inputs.structured_vertices(dim, [n] * dim, noise=0.2, seed=0)
     opts = mfs.mfs_default_options(mg_levels=0)
@@ -209,10 +298,16 @@ def main():
                                f"trilinear geometry (vertex noise 0.2h, seed 0), nu=1",
                    "n_dofs": main_run["N"], "rotating_buffers_bytes": 600e6},
         "roofline": {"bound": "hbm", "achieved": main_run["achieved_GBs"], "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                     "frac": main_run["frac"], "traffic": None,
+                     "frac": main_run["frac"], "traffic": MEASURED_TRAFFIC.get((k, n, args.prec)),
                      "bytes_per_launch": main_run["bytes"], "avg_launch_us": main_run["avg_launch_s"] * 1e6},
         "sweep": sweep,
     }
+    if args.prec == "f64" and k in FLOP_PER_DOF:
+        fl = FLOP_PER_DOF[k] * main_run["N"] / main_run["avg_launch_s"]
+        line["roofline_alu"] = {"bound": "alu", "achieved": fl / 1e12, "peak": FP64_PEAK / 1e12, "unit": "TFLOP/s",
+                                "frac": fl / FP64_PEAK, "flop_per_dof": FLOP_PER_DOF[k]}
+    if not args.no_ns:
+        line["navier_stokes"] = ns_section(mfs, torch, inputs, args)
     if not args.no_solve:
         line["solve"] = solve_section(mfs, torch, inputs, args)
         line["serving"] = serving_section(args)

@@ -25,8 +25,10 @@
 //    buffer (one wave per slice, lanes never collide within an instruction,
 //    so the accumulation order is fixed), then the brick is written out:
 //    nodes strictly inside the brick with plain stores, nodes on brick faces
-//    with global atomics into a destination cleared beforehand (Dirichlet
-//    rows carry src).
+//    into the brick's slot of a face buffer.  A second kernel sums the (at
+//    most 8) face-buffer contributions of every brick-face node in a fixed
+//    order and writes the Dirichlet rows (dst = src), so no global atomics
+//    and no cleared destination are needed and the result is deterministic.
 #include <algorithm>
 
 #include "internal.h"
