@@ -298,3 +298,14 @@ def ns_velocity(dim: int, node_counts, seed: int = 0, n_modes: int = 8) -> np.nd
         m = v.shape[0]
         out[:, iz * m:(iz + 1) * m] = v.T
     return out.ravel()
+
+
+def block_degrees(n, seed: int, block: int = 4, lo: int = 2, hi: int = 6) -> np.ndarray:
+    """Per-cell polynomial degrees of a 3D structured mesh with n cells per
+    direction: one degree per block^3 cell block, uniform on {lo..hi}
+    (PCG64), returned per cell in lexicographic order (x fastest)."""
+    n = [int(v) for v in (n if hasattr(n, "__len__") else [n] * 3)]
+    nb = [(v + block - 1) // block for v in n]
+    d = _rng(seed).integers(lo, hi + 1, size=nb[::-1])  # [bz, by, bx]
+    z, y, x = np.meshgrid(np.arange(n[2]), np.arange(n[1]), np.arange(n[0]), indexing="ij")
+    return d[z // block, y // block, x // block].ravel().astype(np.int32)
