@@ -137,6 +137,28 @@ int mfs_setup(const mfs_mesh *mesh, int k, double nu, const mfs_options *opts, v
               mfs_problem **out);
 int mfs_destroy(mfs_problem *p);
 
+/*
+ * setup for the hp variant of Sec. 3: velocity degree cell_degree[c] in [2, 6]
+ * per cell (host array, n0*n1*n2 entries, lexicographic cells), pressure degree
+ * cell_degree[c] - 1, 3D only, Taylor-Hood (pressure_offset = 1).  The space
+ * is the continuous one: on a face or edge shared by cells of different degree
+ * the trace has the lowest of their degrees (minimum rule), realised by the
+ * cell-local maps C_e of eq. (transfer).  Unknowns are numbered by mesh entity:
+ * vertices (lexicographic), edges along x, y, z (lexicographic over their index
+ * boxes; m-1 unknowns at the interior degree-m GLL points, m = lowest degree of
+ * the cells around the edge), faces normal to x, y, z ((m-1)^2 unknowns, lower
+ * free axis fastest), cell interiors ((k-1)^3, x fastest); vectors are blocked
+ * [u_0 | u_1 | u_2 | p].  Multigrid: hp p-levels with k <- max(k-1, 2) until
+ * every degree is 2 (levels 0 .. nhp-1), then the structured degree-2 levels
+ * of mfs_setup with the mesh halved (levels nhp ..).  mfs_vmult offers every
+ * operator on level 0 and MFS_OP_A on the others; mfs_rhs and the support
+ * point queries are not provided (MFS_EUNSUPPORTED).  Jacobi diagonals are
+ * computed by applying A to colour indicators (no two unknowns of a colour
+ * share a cell).  Returns MFS_EINVAL on a degree outside [2, 6].
+ */
+int mfs_setup_hp(const mfs_mesh *mesh, const int *cell_degree, double nu, const mfs_options *opts, void *stream,
+                 mfs_problem **out);
+
 /* Sizes at level `level` (0 = finest): scalar velocity nodes per component and
  * pressure nodes (0 on levels without pressure; n_u on every level of a
  * Navier-Stokes problem). */

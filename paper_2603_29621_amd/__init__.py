@@ -38,7 +38,7 @@ EXPORTED = [
     "mfs_quadrature_points_device", "mfs_vmult",
     "mfs_diagonal", "mfs_get_lambda", "mfs_set_lambda", "mfs_vcycle", "mfs_prolongate_add", "mfs_restrict",
     "mfs_precondition", "mfs_rhs", "mfs_solve", "mfs_solve_begin", "mfs_solve_advance",
-    "mfs_set_linearization",
+    "mfs_set_linearization", "mfs_setup_hp",
 ]
 
 
@@ -97,6 +97,8 @@ def lib():
         L.mfs_setup.argtypes = [ctypes.POINTER(mfs_mesh), ctypes.c_int, ctypes.c_double, ctypes.POINTER(mfs_options),
                                 vp, ctypes.POINTER(vp)]
         L.mfs_destroy.argtypes = [vp]
+        L.mfs_setup_hp.argtypes = [ctypes.POINTER(mfs_mesh), ctypes.POINTER(ctypes.c_int), ctypes.c_double,
+                                   ctypes.POINTER(mfs_options), vp, ctypes.POINTER(vp)]
         L.mfs_n_dofs.argtypes = [vp, ctypes.c_int, i64p, i64p]
         L.mfs_n_levels.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
         L.mfs_level_info.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
@@ -174,6 +176,16 @@ def mfs_setup(dim, n, vertices, k, nu, opts=None, stream=None) -> ctypes.c_void_
     h = ctypes.c_void_p(0)
     _check(lib().mfs_setup(ctypes.byref(m), int(k), float(nu), ctypes.byref(opts) if opts else None,
                            _stream(stream), ctypes.byref(h)))
+    return h
+
+
+def mfs_setup_hp(n, vertices, cell_degree, nu, opts=None, stream=None) -> ctypes.c_void_p:
+    """hp Taylor-Hood problem on a 3D structured mesh with per-cell velocity degrees."""
+    m, _keep = _mesh(3, n, vertices)
+    deg = np.ascontiguousarray(cell_degree, dtype=np.int32)
+    h = ctypes.c_void_p(0)
+    _check(lib().mfs_setup_hp(ctypes.byref(m), deg.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), float(nu),
+                              ctypes.byref(opts) if opts else None, _stream(stream), ctypes.byref(h)))
     return h
 
 

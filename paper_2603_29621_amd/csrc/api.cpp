@@ -19,8 +19,10 @@
 #include <cstring>
 #include <functional>
 #include <memory>
+#include <type_traits>
 #include <vector>
 
+#include "hp.h"
 #include "internal.h"
 
 using namespace mfs;
@@ -98,6 +100,97 @@ struct Krylov {
   bool final_pending = false;
 };
 
+// ------------------------------------------------------------- hp levels
+// Device copy of an hp space's maps (velocity: the gather drops Dirichlet
+// columns, the transposed map has no Dirichlet rows, owners of Dirichlet
+// unknowns are -1; pressure: no Dirichlet unknowns).
+struct HpDevSpace {
+  int64_t N = 0, nrows = 0;
+  int64_t *row_ptr = nullptr, *row_ev = nullptr;
+  int *col = nullptr, *row_nb = nullptr;
+  double *val = nullptr;
+  int64_t *tptr = nullptr, *tev = nullptr;
+  int *tnb = nullptr;
+  double *tval = nullptr;
+  uint8_t *dir = nullptr;
+  int64_t *owner_ev = nullptr;
+  int *owner_nb = nullptr;
+  int *colour = nullptr;
+  int ncolours = 0;
+};
+
+template <typename T>
+struct HpVecs {
+  T *x = nullptr, *b = nullptr, *r = nullptr, *d = nullptr;  // 3N
+  T *ev_in = nullptr, *ev_out = nullptr;                       // velocity E-vectors
+  T *invdiag = nullptr;                                        // N
+};
+
+struct HpLevel {
+  HpSpaceHost V;
+  HpDevSpace vd;
+  int64_t ev_size = 0;
+  int64_t *off_u = nullptr;  // per cell: E-vector offset of the cell's [3][(k+1)^3] block
+  int *deg = nullptr;        // per cell degree (device)
+  std::vector<int> class_k, class_n;
+  std::vector<int *> class_cells;
+  double lambda = 0.0;
+  double *diag = nullptr;
+  HpVecs<double> v64;
+  HpVecs<float> v32;
+};
+
+struct HpData {
+  int n[3] = {0, 0, 0};
+  int64_t ncells = 0;
+  std::vector<HpLevel> lev;
+  // pressure space of the finest level
+  HpSpaceHost Pr;
+  HpDevSpace pd;
+  int64_t evp_size = 0;
+  int64_t *off_p = nullptr;
+  double *evp_in64 = nullptr, *evp_out64 = nullptr;
+  float *evp_in32 = nullptr, *evp_out32 = nullptr;
+  // coarse side of the last hp transfer: the uniform degree-2 hp space and
+  // the index of each of its unknowns in the structured degree-2 node grid
+  HpSpaceHost V2;
+  HpDevSpace v2d;
+  int64_t ev2_size = 0;
+  int64_t *off_u2 = nullptr;
+  int *deg2 = nullptr;
+  int64_t *perm2 = nullptr;
+  double *ev2_64 = nullptr, *tmp2_64 = nullptr;
+  float *ev2_32 = nullptr, *tmp2_32 = nullptr;
+  double *embed = nullptr;  // [8][8][MAXQ*MAXQ] 1D embeddings [fine][coarse]
+  double *tab64[7] = {};
+  float *tab32[7] = {};
+  // block preconditioner
+  double *pdiag = nullptr, *m1 = nullptr, *ones = nullptr;
+  double *pinv64 = nullptr;
+  float *pinv32 = nullptr;
+  double *p64[5] = {};  // pres, ps, pp, pq, pz
+  float *p32[5] = {};
+  double *tu64 = nullptr;
+  float *tu32 = nullptr;
+  std::vector<void *> allocs;
+  template <typename T>
+  T *alloc(int64_t n) {
+    void *p = nullptr;
+    MFS_HIP(hipMalloc(&p, (size_t)std::max<int64_t>(n, 1) * sizeof(T)));
+    allocs.push_back(p);
+    return static_cast<T *>(p);
+  }
+  template <typename T>
+  T *upload(const std::vector<T> &v, hipStream_t s) {
+    T *p = alloc<T>((int64_t)v.size());
+    if (!v.empty()) MFS_HIP(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    return p;
+  }
+  ~HpData() {
+    for (void *p : allocs) (void)hipFree(p);
+  }
+};
+
 }  // namespace
 
 struct mfs_problem {
@@ -124,6 +217,10 @@ struct mfs_problem {
   bool ns_ready = false;
   double ns_dt = 0.0;
   int ns_newton = 1;
+  // hp problem: hp levels first (global level numbers 0 .. nhp-1), then the
+  // structured degree-2 levels in L
+  HpData *hp = nullptr;
+  int nhp = 0;
 };
 
 namespace {
@@ -359,6 +456,7 @@ void release(mfs_problem *P) {
   if (P->kr.host) (void)hipHostFree(P->kr.host);
   if (P->kr.yhost) (void)hipHostFree(P->kr.yhost);
   if (P->arena) (void)hipFree(P->arena);
+  delete P->hp;
   delete P;
 }
 
@@ -892,14 +990,244 @@ void precondition(mfs_problem &P, T *y, const T *r, hipStream_t s) {
   vcycle_level<T>(P, 0, y, W.t_u, s);
 }
 
+// ---------------------------------------------------------------- hp operators
+// Cell operators through E-vectors: gather the cells' local values through
+// the local->global maps, apply the cell kernels class by class, scatter the
+// local results back with the transposed maps (Sec. 3, minimum rule).
+template <typename T>
+HpVecs<T> &hpv(HpLevel &L);
+template <>
+HpVecs<double> &hpv<double>(HpLevel &L) {
+  return L.v64;
+}
+template <>
+HpVecs<float> &hpv<float>(HpLevel &L) {
+  return L.v32;
+}
+template <typename T>
+T *hp_tab(HpData &H, int k);
+template <>
+double *hp_tab<double>(HpData &H, int k) {
+  return H.tab64[k];
+}
+template <>
+float *hp_tab<float>(HpData &H, int k) {
+  return H.tab32[k];
+}
+template <typename T>
+T *hp_evp(HpData &H, bool out);
+template <>
+double *hp_evp<double>(HpData &H, bool out) {
+  return out ? H.evp_out64 : H.evp_in64;
+}
+template <>
+float *hp_evp<float>(HpData &H, bool out) {
+  return out ? H.evp_out32 : H.evp_in32;
+}
+
+template <typename T>
+void hp_gather_space(const HpDevSpace &d, int ncomp, const T *x, T *ev, hipStream_t s) {
+  hp_gather<T>(d.nrows, ncomp, d.row_ptr, d.col, d.val, d.row_ev, d.row_nb, x, d.N, ev, s);
+}
+
+// dst = op(src) on hp level l: mode of the cell kernels; velocity output
+// Dirichlet rows = src_u (A, Stokes) or 0 (B)
+template <typename T>
+void hp_apply(mfs_problem &P, int l, int mode, T *dst_u, T *dst_p, const T *src_u, const T *src_p, hipStream_t s) {
+  HpData &H = *P.hp;
+  HpLevel &L = H.lev[l];
+  HpVecs<T> &V = hpv<T>(L);
+  const bool need_u = mode & (M_LAPLACE | M_DIVU), need_p = mode & (M_GRADP | M_MASSP);
+  const bool out_u = mode & (M_LAPLACE | M_GRADP), out_p = mode & (M_DIVU | M_MASSP);
+  if (need_u) hp_gather_space<T>(L.vd, 3, src_u, V.ev_in, s);
+  if (need_p) hp_gather_space<T>(H.pd, 1, src_p, hp_evp<T>(H, false), s);
+  const Level &S0 = P.L[0];
+  EvArgs<T> ev{};
+  ev.off_u = L.off_u;
+  ev.off_p = H.off_p;
+  ev.in_u = V.ev_in;
+  ev.out_u = V.ev_out;
+  ev.in_p = hp_evp<T>(H, false);
+  ev.out_p = hp_evp<T>(H, true);
+  for (size_t c = 0; c < L.class_k.size(); ++c) {
+    ev.ncells = L.class_n[c];
+    ev.cells = L.class_cells[c];
+    launch_cell_op_ev<T>(S0.g, L.class_k[c], dev<T>(S0).X, hp_tab<T>(H, L.class_k[c]), mode, (T)P.nu, ev, s);
+  }
+  if (out_u)
+    hp_scatter<T>(L.vd.N, 3, L.vd.tptr, L.vd.tev, L.vd.tnb, L.vd.tval, L.vd.dir, V.ev_out,
+                  (mode & M_LAPLACE) ? src_u : nullptr, dst_u, s);
+  if (out_p)
+    hp_scatter<T>(H.pd.N, 1, H.pd.tptr, H.pd.tev, H.pd.tnb, H.pd.tval, nullptr, hp_evp<T>(H, true), nullptr, dst_p,
+                  s);
+}
+
+template <typename T>
+void hp_apply_A(mfs_problem &P, int l, T *dst, const T *src, hipStream_t s) {
+  hp_apply<T>(P, l, M_LAPLACE, dst, nullptr, src, nullptr, s);
+}
+
+// transfers between hp level l and the next level (hp, or the structured
+// degree-2 level 0 for the last hp level): gather coarse local values, embed
+// them in the fine cells' degrees, inject into the fine unknowns at their owner
+// nodes; restriction is the transposed sequence.
+template <typename T>
+void hp_prolongate_add(mfs_problem &P, int l, T *xf, const T *xc, hipStream_t s) {
+  HpData &H = *P.hp;
+  HpLevel &F = H.lev[l];
+  T *evf = hpv<T>(F).ev_out;
+  if (l + 1 < P.nhp) {
+    HpLevel &C = H.lev[l + 1];
+    T *evc = hpv<T>(C).ev_in;
+    hp_gather_space<T>(C.vd, 3, xc, evc, s);
+    hp_embed<T>(H.ncells, 3, F.deg, C.deg, H.embed, F.off_u, C.off_u, evc, evf, false, s);
+  } else {
+    T *tmp = std::is_same<T, double>::value ? (T *)H.tmp2_64 : (T *)H.tmp2_32;
+    T *evc = std::is_same<T, double>::value ? (T *)H.ev2_64 : (T *)H.ev2_32;
+    permute<T>(H.v2d.N, 3, H.perm2, xc, P.L[0].g.Nv, tmp, H.v2d.N, false, s);
+    hp_gather_space<T>(H.v2d, 3, tmp, evc, s);
+    hp_embed<T>(H.ncells, 3, F.deg, H.deg2, H.embed, F.off_u, H.off_u2, evc, evf, false, s);
+  }
+  hp_inject<T>(F.vd.N, 3, F.vd.owner_ev, F.vd.owner_nb, evf, xf, true, s);
+}
+
+template <typename T>
+void hp_restrict(mfs_problem &P, int l, T *bc, const T *rf, hipStream_t s) {
+  HpData &H = *P.hp;
+  HpLevel &F = H.lev[l];
+  T *evf = hpv<T>(F).ev_out;
+  vec_fill<T>(evf, T(0), F.ev_size, s);
+  hp_inject_t<T>(F.vd.N, 3, F.vd.owner_ev, F.vd.owner_nb, rf, evf, s);
+  if (l + 1 < P.nhp) {
+    HpLevel &C = H.lev[l + 1];
+    T *evc = hpv<T>(C).ev_in;
+    hp_embed<T>(H.ncells, 3, F.deg, C.deg, H.embed, F.off_u, C.off_u, evf, evc, true, s);
+    hp_scatter<T>(C.vd.N, 3, C.vd.tptr, C.vd.tev, C.vd.tnb, C.vd.tval, C.vd.dir, evc, nullptr, bc, s);
+  } else {
+    T *tmp = std::is_same<T, double>::value ? (T *)H.tmp2_64 : (T *)H.tmp2_32;
+    T *evc = std::is_same<T, double>::value ? (T *)H.ev2_64 : (T *)H.ev2_32;
+    hp_embed<T>(H.ncells, 3, F.deg, H.deg2, H.embed, F.off_u, H.off_u2, evf, evc, true, s);
+    hp_scatter<T>(H.v2d.N, 3, H.v2d.tptr, H.v2d.tev, H.v2d.tnb, H.v2d.tval, H.v2d.dir, evc, nullptr, tmp, s);
+    permute<T>(H.v2d.N, 3, H.perm2, tmp, H.v2d.N, bc, P.L[0].g.Nv, true, s);
+  }
+}
+
+template <typename T>
+void hp_chebyshev(mfs_problem &P, int l, T *x, const T *b, bool zero_start, hipStream_t s) {
+  HpLevel &L = P.hp->lev[l];
+  HpVecs<T> &V = hpv<T>(L);
+  const double lmax = L.lambda, lmin = lmax / P.opts.cheb_range;
+  const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
+  const double sigma = theta / delta;
+  double rho_old = 1.0 / sigma;
+  const int64_t N = L.vd.N;
+  if (zero_start) {
+    mask_cheb_update<T>(L.vd.dir, N, 3, x, V.d, b, nullptr, V.invdiag, T(0), (T)(1.0 / theta), true, s);
+  } else {
+    hp_apply_A<T>(P, l, V.r, x, s);
+    mask_cheb_update<T>(L.vd.dir, N, 3, x, V.d, b, V.r, V.invdiag, T(0), (T)(1.0 / theta), true, s);
+  }
+  for (int it = 1; it < P.opts.cheb_degree; ++it) {
+    const double rho = 1.0 / (2.0 * sigma - rho_old);
+    hp_apply_A<T>(P, l, V.r, x, s);
+    mask_cheb_update<T>(L.vd.dir, N, 3, x, V.d, b, V.r, V.invdiag, (T)(rho * rho_old), (T)(2.0 * rho / delta), false,
+                        s);
+    rho_old = rho;
+  }
+}
+
+// V-cycle of the velocity block: hp p-levels, then the structured levels
+template <typename T>
+void hp_vcycle(mfs_problem &P, int l, T *x, const T *b, hipStream_t s) {
+  if (l == P.nhp) {
+    vcycle_level<T>(P, 0, x, b, s);
+    return;
+  }
+  HpLevel &L = P.hp->lev[l];
+  HpVecs<T> &V = hpv<T>(L);
+  const int64_t n = 3 * L.vd.N;
+  mask_fill_dirichlet<T>(L.vd.dir, L.vd.N, 3, x, b, s);
+  hp_chebyshev<T>(P, l, x, b, true, s);
+  hp_apply_A<T>(P, l, V.r, x, s);
+  vec_axpby<T>(V.r, T(1), b, T(-1), n, s);
+  T *bc, *xc;
+  if (l + 1 < P.nhp) {
+    bc = hpv<T>(P.hp->lev[l + 1]).b;
+    xc = hpv<T>(P.hp->lev[l + 1]).x;
+  } else {
+    bc = work<T>(P).b[0];
+    xc = work<T>(P).x[0];
+  }
+  hp_restrict<T>(P, l, bc, V.r, s);
+  hp_vcycle<T>(P, l + 1, xc, bc, s);
+  hp_prolongate_add<T>(P, l, x, xc, s);
+  hp_chebyshev<T>(P, l, x, b, false, s);
+}
+
+template <typename T>
+HpVecs<T> &hp0(mfs_problem &P) {
+  return hpv<T>(P.hp->lev[0]);
+}
+template <typename T>
+T **hp_pvec(HpData &H);
+template <>
+double **hp_pvec<double>(HpData &H) {
+  return H.p64;
+}
+template <>
+float **hp_pvec<float>(HpData &H) {
+  return H.p32;
+}
+
+// block preconditioner on the hp system (as precondition())
+template <typename T>
+void hp_precondition(mfs_problem &P, T *y, const T *r, hipStream_t s) {
+  HpData &H = *P.hp;
+  const int64_t nu = 3 * H.lev[0].vd.N, np = H.pd.N;
+  const T *rp = r + nu;
+  T *yp = y + nu;
+  T **pv = hp_pvec<T>(H);
+  T *pres = pv[0], *ps = pv[1], *pp = pv[2], *pq = pv[3], *pz = pv[4];
+  const T *pinv = std::is_same<T, double>::value ? (const T *)H.pinv64 : (const T *)H.pinv32;
+  T *tu = std::is_same<T, double>::value ? (T *)H.tu64 : (T *)H.tu32;
+  double *rho = P.scal, *pqs = P.scal + PCG_MAX;
+  vec_fill<T>(pz, T(0), np, s);
+  vec_copy<T>(pres, rp, np, s);
+  vec_mul<T>(ps, pinv, pres, np, s);
+  vec_copy<T>(pp, ps, np, s);
+  multi_dot<T>(pres, 0, 1, ps, np, rho, P.partials, s);
+  for (int it = 0; it < P.opts.schur_iterations; ++it) {
+    hp_apply<T>(P, 0, M_MASSP, nullptr, pq, nullptr, pp, s);
+    multi_dot<T>(pp, 0, 1, pq, np, pqs + it, P.partials, s);
+    pcg_update1<T>(pz, pres, ps, pp, pq, pinv, np, rho + it, pqs + it, s);
+    multi_dot<T>(pres, 0, 1, ps, np, rho + it + 1, P.partials, s);
+    pcg_update2<T>(pp, ps, np, rho + it + 1, rho + it, s);
+  }
+  vec_axpby<T>(yp, (T)(-P.nu), pz, T(0), np, s);
+  hp_apply<T>(P, 0, M_GRADP, tu, nullptr, nullptr, yp, s);
+  vec_axpby<T>(tu, T(1), r, T(-1), nu, s);
+  hp_vcycle<T>(P, 0, y, tu, s);
+}
+
 // the system operator and its preconditioner: Stokes (block preconditioner)
 // or Navier-Stokes Jacobian (monolithic V-cycle)
 void apply_system(mfs_problem &P, double *dst, const double *src, hipStream_t s) {
+  if (P.hp) {
+    const int64_t nu = 3 * P.hp->lev[0].vd.N;
+    hp_apply<double>(P, 0, M_LAPLACE | M_GRADP | M_DIVU, dst, dst + nu, src, src + nu, s);
+    return;
+  }
   apply_op<double>(P, P.ns ? MFS_OP_NS_JACOBIAN : MFS_OP_STOKES, 0, dst, src, s);
 }
+// sizes of the system vectors
+int64_t sys_vel(const mfs_problem &P) { return P.hp ? 3 * P.hp->lev[0].vd.N : P.dim * P.L[0].g.Nv; }
+int64_t sys_pres(const mfs_problem &P) { return P.hp ? P.hp->pd.N : P.L[0].g.Np; }
+int64_t sys_n(const mfs_problem &P) { return sys_vel(P) + sys_pres(P); }
 template <typename T>
 void precondition_any(mfs_problem &P, T *y, const T *r, hipStream_t s) {
-  if (P.ns)
+  if (P.hp)
+    hp_precondition<T>(P, y, r, s);
+  else if (P.ns)
     ns_vcycle<T>(P, 0, y, r, s);
   else
     precondition<T>(P, y, r, s);
@@ -908,7 +1236,7 @@ void precondition_any(mfs_problem &P, T *y, const T *r, hipStream_t s) {
 // ---------------------------------------------------------------- FGMRES
 void kr_enqueue_residual(mfs_problem &P, hipStream_t s) {
   Krylov &K = P.kr;
-  const int64_t n = P.dim * P.L[0].g.Nv + P.L[0].g.Np;
+  const int64_t n = sys_n(P);
   apply_system(P, K.w, K.x, s);
   vec_axpby<double>(K.w, 1.0, K.b, -1.0, n, s);  // w = b - K x
   multi_dot<double>(K.w, 0, 1, K.w, n, K.dev + 96, P.partials, s);
@@ -918,8 +1246,7 @@ void kr_enqueue_residual(mfs_problem &P, hipStream_t s) {
 
 void kr_enqueue_step(mfs_problem &P, hipStream_t s) {
   Krylov &K = P.kr;
-  const LevelGeom &g = P.L[0].g;
-  const int64_t n = P.dim * g.Nv + g.Np;
+  const int64_t n = sys_n(P);
   const int j = K.j;
   double *vj = K.V + (int64_t)j * n, *zj = K.Z + (int64_t)j * n;
   if (K.prec == MFS_FP32) {
@@ -945,7 +1272,7 @@ void kr_enqueue_step(mfs_problem &P, hipStream_t s) {
 // true-residual check
 void kr_enqueue_update(mfs_problem &P, hipStream_t s) {
   Krylov &K = P.kr;
-  const int64_t n = P.dim * P.L[0].g.Nv + P.L[0].g.Np;
+  const int64_t n = sys_n(P);
   const int m = K.j;
   if (m > 0) {
     std::vector<double> y(m);
@@ -965,15 +1292,16 @@ void kr_enqueue_update(mfs_problem &P, hipStream_t s) {
 void kr_finish(mfs_problem &P, double rel, int status) {
   Krylov &K = P.kr;
   hipStream_t s = K.s;
-  const LevelGeom &g = P.L[0].g;
-  const int64_t nu = P.dim * g.Nv;
+  const int64_t nu = sys_vel(P), np = sys_pres(P);
+  const double *m1 = P.hp ? P.hp->m1 : P.m1;
   // pressure with zero mass-weighted mean (Navier-Stokes: m1 = 1, nodal mean)
-  if (g.Np > 0) {
+  if (np > 0) {
     double *num = P.scal + 4 * PCG_MAX + 8, *den = num + 1;
-    multi_dot<double>(P.m1, 0, 1, K.x + nu, g.Np, num, P.partials, s);
-    vec_fill<double>(P.tmp_full, 1.0, g.Np, s);
-    multi_dot<double>(P.m1, 0, 1, P.tmp_full, g.Np, den, P.partials, s);
-    shift_mean(K.x + nu, g.Np, num, den, s);
+    double *ones = P.hp ? P.hp->ones : P.tmp_full;  // scratch of >= np entries
+    multi_dot<double>(m1, 0, 1, K.x + nu, np, num, P.partials, s);
+    vec_fill<double>(ones, 1.0, np, s);
+    multi_dot<double>(m1, 0, 1, ones, np, den, P.partials, s);
+    shift_mean(K.x + nu, np, num, den, s);
   }
   MFS_HIP(hipStreamSynchronize(s));
   K.info.iterations = K.iters;
@@ -987,7 +1315,7 @@ void kr_finish(mfs_problem &P, double rel, int status) {
 void kr_process(mfs_problem &P) {
   Krylov &K = P.kr;
   hipStream_t s = K.s;
-  const int64_t n = P.dim * P.L[0].g.Nv + P.L[0].g.Np;
+  const int64_t n = sys_n(P);
   if (K.state == 1 || K.state == 3) {
     const double rr = std::sqrt(std::max(K.host[96], 0.0));
     if (K.state == 1 && K.bnorm == 0.0) K.bnorm = rr;  // first call stores ||b - K x0||, replaced below
@@ -1237,10 +1565,384 @@ int mfs_destroy(mfs_problem *p) {
 }  // extern "C"
 
 namespace {
+// ---------------------------------------------------------------- hp set-up
+// device copy of an hp space's maps; ev_off: per-cell E-vector offset of the
+// cell's first component block, ncomp_stride: whether rows carry a component
+// stride ((k+1)^3 for the velocity)
+void hp_upload(HpData &H, const HpSpaceHost &V, bool constrained, const std::vector<int64_t> &ev_off, bool vector_comp,
+               HpDevSpace &d, hipStream_t s) {
+  const int64_t ncells = (int64_t)V.deg.size();
+  d.N = V.N;
+  d.nrows = V.row_base[ncells];
+  std::vector<int64_t> ptr(d.nrows + 1, 0), rev(d.nrows);
+  std::vector<int> col, rnb(d.nrows);
+  std::vector<double> val;
+  col.reserve(V.col.size());
+  val.reserve(V.val.size());
+  // transposed lists, counted per unknown
+  std::vector<int64_t> tcount(V.N + 1, 0);
+  for (int64_t c = 0; c < ncells; ++c) {
+    const int k = V.deg[c], nb = (k + 1) * (k + 1) * (k + 1);
+    for (int j = 0; j < nb; ++j) {
+      const int64_t r = V.row_base[c] + j;
+      rev[r] = ev_off[c] + j;
+      rnb[r] = vector_comp ? nb : 0;
+      for (int64_t q = V.row_ptr[r]; q < V.row_ptr[r + 1]; ++q) {
+        const int g = V.col[q];
+        if (constrained && V.dirichlet[g]) continue;
+        col.push_back(g);
+        val.push_back(V.val[q]);
+        tcount[g + 1] += 1;
+      }
+      ptr[r + 1] = (int64_t)col.size();
+    }
+  }
+  for (int64_t g = 0; g < V.N; ++g) tcount[g + 1] += tcount[g];
+  std::vector<int64_t> tev(tcount[V.N]), fill(tcount.begin(), tcount.end() - 1);
+  std::vector<int> tnb(tcount[V.N]);
+  std::vector<double> tval(tcount[V.N]);
+  for (int64_t r = 0; r < d.nrows; ++r)
+    for (int64_t q = ptr[r]; q < ptr[r + 1]; ++q) {
+      const int64_t o = fill[col[q]]++;
+      tev[o] = rev[r];
+      tnb[o] = rnb[r];
+      tval[o] = val[q];
+    }
+  std::vector<int64_t> oev(V.N);
+  std::vector<int> onb(V.N);
+  for (int64_t g = 0; g < V.N; ++g) {
+    const int c = V.owner_cell[g], k = V.deg[c], nb = (k + 1) * (k + 1) * (k + 1);
+    oev[g] = (constrained && V.dirichlet[g]) ? -1 : ev_off[c] + V.owner_local[g];
+    onb[g] = vector_comp ? nb : 0;
+  }
+  d.row_ptr = H.upload(ptr, s);
+  d.col = H.upload(col, s);
+  d.val = H.upload(val, s);
+  d.row_ev = H.upload(rev, s);
+  d.row_nb = H.upload(rnb, s);
+  d.tptr = H.upload(tcount, s);
+  d.tev = H.upload(tev, s);
+  d.tnb = H.upload(tnb, s);
+  d.tval = H.upload(tval, s);
+  d.owner_ev = H.upload(oev, s);
+  d.owner_nb = H.upload(onb, s);
+  d.dir = constrained ? H.upload(V.dirichlet, s) : nullptr;
+  MFS_HIP(hipStreamSynchronize(s));  // the host vectors go out of scope
+}
+
+std::vector<int64_t> ev_offsets(const std::vector<int> &deg, int ncomp, int shift, int64_t *total) {
+  std::vector<int64_t> off(deg.size());
+  int64_t o = 0;
+  for (size_t c = 0; c < deg.size(); ++c) {
+    off[c] = o;
+    const int64_t m = deg[c] + 1 - shift;
+    o += ncomp * m * m * m;
+  }
+  *total = o;
+  return off;
+}
+
+template <typename T>
+void hp_alloc_vecs(HpData &H, HpVecs<T> &v, int64_t N, int64_t ev) {
+  v.x = H.alloc<T>(3 * N);
+  v.b = H.alloc<T>(3 * N);
+  v.r = H.alloc<T>(3 * N);
+  v.d = H.alloc<T>(3 * N);
+  v.ev_in = H.alloc<T>(ev);
+  v.ev_out = H.alloc<T>(ev);
+  v.invdiag = H.alloc<T>(N);
+}
+
+// lambda_max(D^{-1} A) of hp level l by CG-Lanczos (FP64), as for the
+// structured levels
+double hp_estimate_lambda(mfs_problem &P, int l, hipStream_t s) {
+  HpLevel &L = P.hp->lev[l];
+  const int64_t N = L.vd.N, n = 3 * N;
+  HpVecs<double> &V = L.v64;
+  double *r = V.x, *z = V.b, *p = V.d, *q = V.r;
+  std::vector<double> h(n);
+  uint64_t st = P.opts.seed * 1000003ULL + (uint64_t)l + 7919ULL;
+  for (int64_t i = 0; i < n; ++i) {
+    h[i] = (double)(splitmix64(st) >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+    if (L.V.dirichlet[i % N]) h[i] = 0.0;
+  }
+  MFS_HIP(hipMemcpyAsync(r, h.data(), n * sizeof(double), hipMemcpyHostToDevice, s));
+  double *dv = P.scal + 4 * PCG_MAX;
+  auto dot = [&](const double *a, const double *b) {
+    multi_dot<double>(a, 0, 1, b, n, dv, P.partials, s);
+    double v;
+    MFS_HIP(hipMemcpyAsync(&v, dv, sizeof(double), hipMemcpyDeviceToHost, s));
+    MFS_HIP(hipStreamSynchronize(s));
+    return v;
+  };
+  mask_diag_scale<double>(L.vd.dir, N, 3, z, V.invdiag, r, s);
+  vec_copy<double>(p, z, n, s);
+  double rz = dot(r, z);
+  std::vector<double> alpha, beta;
+  const int steps = std::max(2, P.opts.lanczos_steps);
+  for (int j = 0; j < steps && rz > 0; ++j) {
+    hp_apply_A<double>(P, l, q, p, s);
+    const double pq = dot(p, q);
+    if (!(pq > 0)) break;
+    const double a = rz / pq;
+    vec_axpby<double>(r, -a, q, 1.0, n, s);
+    mask_diag_scale<double>(L.vd.dir, N, 3, z, V.invdiag, r, s);
+    const double rz2 = dot(r, z);
+    const double b = rz2 / rz;
+    vec_axpby<double>(p, 1.0, z, b, n, s);
+    alpha.push_back(a);
+    beta.push_back(b);
+    rz = rz2;
+    if (rz2 <= 1e-30 * rz) break;
+  }
+  const int m = (int)alpha.size();
+  MFS_REQUIRE(m > 0, MFS_EINVAL, "Lanczos estimate failed on hp level %d", l);
+  std::vector<double> d(m), e(std::max(m - 1, 1), 0.0);
+  for (int j = 0; j < m; ++j) {
+    d[j] = 1.0 / alpha[j] + (j > 0 ? beta[j - 1] / alpha[j - 1] : 0.0);
+    if (j < m - 1) e[j] = std::sqrt(beta[j]) / alpha[j];
+  }
+  double lmax;
+  sturm_max_eig(d, e, lmax);
+  return lmax;
+}
+
+void hp_build(mfs_problem &P, const std::vector<int> &deg0, hipStream_t s) {
+  HpData &H = *P.hp;
+  const LevelGeom &g0 = P.L[0].g;
+  for (int a = 0; a < 3; ++a) H.n[a] = g0.n[a];
+  H.ncells = g0.ncells;
+  // degrees per hp level: k <- max(k - 1, 2) until all are 2; that last
+  // level is the structured degree-2 level
+  std::vector<std::vector<int>> degs{deg0};
+  while (P.opts.mg_levels && *std::max_element(degs.back().begin(), degs.back().end()) > 2) {
+    std::vector<int> d = degs.back();
+    for (int &k : d) k = std::max(k - 1, 2);
+    degs.push_back(d);
+  }
+  if (degs.size() > 1) degs.pop_back();
+  H.lev.resize(degs.size());
+  P.nhp = (int)degs.size();
+  for (size_t l = 0; l < degs.size(); ++l) {
+    HpLevel &L = H.lev[l];
+    L.V.build(H.n, degs[l]);
+    const auto off = ev_offsets(degs[l], 3, 0, &L.ev_size);
+    hp_upload(H, L.V, true, off, true, L.vd, s);
+    L.off_u = H.upload(off, s);
+    L.deg = H.upload(degs[l], s);
+    for (int k = 2; k <= 6; ++k) {
+      std::vector<int> cells;
+      for (int64_t c = 0; c < H.ncells; ++c)
+        if (degs[l][c] == k) cells.push_back((int)c);
+      if (cells.empty()) continue;
+      L.class_k.push_back(k);
+      L.class_n.push_back((int)cells.size());
+      L.class_cells.push_back(H.upload(cells, s));
+    }
+    hp_alloc_vecs(H, L.v64, L.V.N, L.ev_size);
+    hp_alloc_vecs(H, L.v32, L.V.N, L.ev_size);
+    L.diag = H.alloc<double>(L.V.N);
+  }
+  // pressure space of the finest level (degree k - 1, no Dirichlet unknowns)
+  {
+    std::vector<int> dp(deg0);
+    for (int &k : dp) k -= 1;
+    H.Pr.build(H.n, dp);
+    const auto off = ev_offsets(deg0, 1, 1, &H.evp_size);
+    hp_upload(H, H.Pr, false, off, false, H.pd, s);
+    H.off_p = H.upload(off, s);
+    H.evp_in64 = H.alloc<double>(H.evp_size);
+    H.evp_out64 = H.alloc<double>(H.evp_size);
+    H.evp_in32 = H.alloc<float>(H.evp_size);
+    H.evp_out32 = H.alloc<float>(H.evp_size);
+  }
+  // uniform degree 2 and its place in the structured node grid
+  {
+    std::vector<int> d2(H.ncells, 2);
+    H.V2.build(H.n, d2);
+    const auto off = ev_offsets(d2, 3, 0, &H.ev2_size);
+    hp_upload(H, H.V2, true, off, true, H.v2d, s);
+    H.off_u2 = H.upload(off, s);
+    H.deg2 = H.upload(d2, s);
+    std::vector<int64_t> perm(H.V2.N);
+    for (int64_t gi = 0; gi < H.V2.N; ++gi) {
+      double p[3];
+      H.V2.reference_point(gi, p);
+      int64_t idx[3];
+      for (int a = 0; a < 3; ++a) idx[a] = (int64_t)std::llround(2.0 * p[a]);
+      perm[gi] = idx[0] + (int64_t)g0.nv[0] * (idx[1] + (int64_t)g0.nv[1] * idx[2]);
+    }
+    H.perm2 = H.upload(perm, s);
+    H.ev2_64 = H.alloc<double>(H.ev2_size);
+    H.ev2_32 = H.alloc<float>(H.ev2_size);
+    H.tmp2_64 = H.alloc<double>(3 * H.V2.N);
+    H.tmp2_32 = H.alloc<float>(3 * H.V2.N);
+  }
+  // 1D embeddings [kf][kc] and per-degree tables
+  {
+    std::vector<double> E(8 * 8 * MAXQ * MAXQ, 0.0);
+    for (int kf = 1; kf <= 7; ++kf)
+      for (int kc = 1; kc <= kf; ++kc) {
+        double *T = E.data() + ((int64_t)kf * MAXQ + kc) * MAXQ * MAXQ;
+        if (kc == kf) {
+          for (int i = 0; i <= kf; ++i) T[i * MAXQ + i] = 1.0;
+        } else {
+          const auto pe = p_embedding(kf, kc);
+          for (int i = 0; i <= kf; ++i)
+            for (int j = 0; j <= kc; ++j) T[i * MAXQ + j] = pe[i * (kc + 1) + j];
+        }
+      }
+    H.embed = H.upload(E, s);
+    for (int k = 2; k <= 6; ++k) {
+      const auto t = make_tables(k, k - 1);
+      std::vector<float> t32(t.begin(), t.end());
+      H.tab64[k] = H.upload(t, s);
+      H.tab32[k] = H.upload(t32, s);
+    }
+  }
+  // block preconditioner vectors, Krylov space of the hp system
+  const int64_t Nu = H.lev[0].V.N, Np = H.Pr.N, ntot = 3 * Nu + Np;
+  for (int i = 0; i < 5; ++i) {
+    H.p64[i] = H.alloc<double>(Np);
+    H.p32[i] = H.alloc<float>(Np);
+  }
+  H.tu64 = H.alloc<double>(3 * Nu);
+  H.tu32 = H.alloc<float>(3 * Nu);
+  H.pdiag = H.alloc<double>(3 * Np);
+  H.m1 = H.alloc<double>(Np);
+  H.ones = H.alloc<double>(Np);
+  H.pinv64 = H.alloc<double>(Np);
+  H.pinv32 = H.alloc<float>(Np);
+  P.w32.full_in = H.alloc<float>(ntot);
+  P.w32.full_out = H.alloc<float>(ntot);
+  P.w64.full_in = H.alloc<double>(ntot);
+  P.w64.full_out = H.alloc<double>(ntot);
+  if (P.opts.mg_levels) {
+    Krylov &K = P.kr;
+    K.V = H.alloc<double>((K.m + 1) * ntot);
+    K.Z = H.alloc<double>(K.m * ntot);
+    K.w = H.alloc<double>(ntot);
+  }
+  MFS_HIP(hipStreamSynchronize(s));
+  // Jacobi diagonals of the velocity block on every hp level: A applied to
+  // the indicators of three colours at once (one per component)
+  for (int l = 0; l < P.nhp; ++l) {
+    HpLevel &L = H.lev[l];
+    int ncol = 0;
+    const auto col = L.V.colours(&ncol);
+    L.vd.colour = H.upload(col, s);
+    L.vd.ncolours = ncol;
+    double *e = L.v64.x, *y = L.v64.b;
+    for (int c = 0; c < ncol; c += 3) {
+      const int cols[3] = {c, c + 1 < ncol ? c + 1 : -1, c + 2 < ncol ? c + 2 : -1};
+      colour_indicator(L.vd.colour, L.V.N, cols, e, s);
+      hp_apply_A<double>(P, l, y, e, s);
+      colour_extract(L.vd.colour, L.V.N, cols, y, L.diag, s);
+    }
+    launch_reciprocal(L.v64.invdiag, L.v32.invdiag, L.diag, L.V.N, s);
+  }
+  // pressure mass: diagonal (Jacobi-PCG of the Schur complement) and M_p 1
+  {
+    int ncol = 0;
+    const auto col = H.Pr.colours(&ncol);
+    H.pd.colour = H.upload(col, s);
+    H.pd.ncolours = ncol;
+    double *e = H.p64[0], *y = H.p64[1], *ind = H.pdiag;  // pdiag: 3 Np scratch here
+    double *diag = H.p64[2];
+    for (int c = 0; c < ncol; ++c) {
+      const int cols[3] = {c, -1, -1};
+      colour_indicator(H.pd.colour, Np, cols, ind, s);
+      vec_copy<double>(e, ind, Np, s);
+      hp_apply<double>(P, 0, M_MASSP, nullptr, y, nullptr, e, s);
+      colour_extract(H.pd.colour, Np, cols, y, diag, s);
+    }
+    launch_reciprocal(H.pinv64, H.pinv32, diag, Np, s);
+    vec_copy<double>(H.pdiag, diag, Np, s);
+    vec_fill<double>(H.ones, 1.0, Np, s);
+    hp_apply<double>(P, 0, M_MASSP, nullptr, H.m1, nullptr, H.ones, s);
+  }
+  if (P.opts.mg_levels)
+    for (int l = 0; l < P.nhp; ++l) H.lev[l].lambda = P.opts.cheb_safety * hp_estimate_lambda(P, l, s);
+  MFS_HIP(hipStreamSynchronize(s));
+}
+// mfs_vmult on an hp problem: the hp levels (all operators on the finest,
+// the velocity block on the others), then the structured levels
+void hp_vmult(mfs_problem &P, int op, int prec, int level, void *dst, const void *src, hipStream_t s) {
+  if (level >= P.nhp) {
+    MFS_REQUIRE(op == MFS_OP_A, MFS_EUNSUPPORTED, "structured levels of an hp problem carry the velocity block only");
+    if (prec == MFS_FP64)
+      apply_A<double>(P, level - P.nhp, (double *)dst, (const double *)src, s);
+    else
+      apply_A<float>(P, level - P.nhp, (float *)dst, (const float *)src, s);
+    return;
+  }
+  MFS_REQUIRE(level == 0 || op == MFS_OP_A, MFS_EUNSUPPORTED, "coarser hp levels carry the velocity block only");
+  const int64_t nu = 3 * P.hp->lev[level].V.N;
+  auto run = [&](auto *d, auto *x) {
+    using T = std::remove_pointer_t<decltype(d)>;
+    switch (op) {
+      case MFS_OP_STOKES: hp_apply<T>(P, level, M_LAPLACE | M_GRADP | M_DIVU, d, d + nu, x, x + nu, s); break;
+      case MFS_OP_A: hp_apply<T>(P, level, M_LAPLACE, d, nullptr, x, nullptr, s); break;
+      case MFS_OP_B: hp_apply<T>(P, level, M_GRADP, d, nullptr, nullptr, x, s); break;
+      case MFS_OP_BT: hp_apply<T>(P, level, M_DIVU, nullptr, d, x, nullptr, s); break;
+      case MFS_OP_MASS_P: hp_apply<T>(P, level, M_MASSP, nullptr, d, nullptr, x, s); break;
+      default: MFS_REQUIRE(false, MFS_EUNSUPPORTED, "operator %d is not available on hp problems", op);
+    }
+  };
+  if (prec == MFS_FP64)
+    run((double *)dst, (const double *)src);
+  else
+    run((float *)dst, (const float *)src);
+}
+}  // namespace
+
+extern "C" {
+
+int mfs_setup_hp(const mfs_mesh *mesh, const int *cell_degree, double nu, const mfs_options *opts, void *stream,
+                 mfs_problem **out) {
+  mfs_problem *P = nullptr;
+  int rc = guard([&] {
+    MFS_REQUIRE(out != nullptr, MFS_EINVAL, "out is NULL");
+    *out = nullptr;
+    MFS_REQUIRE(mesh != nullptr && mesh->dim == 3, MFS_EUNSUPPORTED, "hp problems are three-dimensional");
+    MFS_REQUIRE(cell_degree != nullptr, MFS_EINVAL, "cell_degree is NULL");
+    mfs_options o;
+    if (opts)
+      o = *opts;
+    else
+      mfs_default_options(&o);
+    MFS_REQUIRE(o.pressure_offset == 1, MFS_EINVAL, "hp problems are Taylor-Hood (pressure_offset = 1)");
+    for (int a = 0; a < 3; ++a) MFS_REQUIRE(mesh->n[a] >= 1, MFS_EINVAL, "n[%d] must be >= 1", a);
+    const int64_t ncells = (int64_t)mesh->n[0] * mesh->n[1] * mesh->n[2];
+    std::vector<int> deg(cell_degree, cell_degree + ncells);
+    for (int64_t c = 0; c < ncells; ++c)
+      MFS_REQUIRE(deg[c] >= 2 && deg[c] <= 6, MFS_EINVAL, "cell %lld: degree %d out of range [2, 6]", (long long)c,
+                  deg[c]);
+    mfs_options ob = o;
+    ob.p_min = 2;
+    const int rcb = mfs_setup(mesh, 2, nu, &ob, stream, &P);
+    if (rcb != MFS_OK) throw mfs::Error{rcb};
+    P->opts = o;
+    P->opts.p_min = 2;
+    P->hp = new HpData();
+    hp_build(*P, deg, S(stream));
+    *out = P;
+  });
+  if (rc != MFS_OK) {
+    release(P);
+    return rc;
+  }
+  return MFS_OK;
+}
+
+}  // extern "C"
+
+namespace {
 void check_problem(const mfs_problem *p) { MFS_REQUIRE(p != nullptr, MFS_EINVAL, "problem is NULL"); }
 void check_level(const mfs_problem *p, int level) {
   check_problem(p);
-  MFS_REQUIRE(level >= 0 && level < p->nlev, MFS_EINVAL, "level %d out of range [0, %d)", level, p->nlev);
+  MFS_REQUIRE(level >= 0 && level < p->nhp + p->nlev, MFS_EINVAL, "level %d out of range [0, %d)", level,
+              p->nhp + p->nlev);
 }
 void check_prec(int prec) {
   MFS_REQUIRE(prec == MFS_FP32 || prec == MFS_FP64, MFS_EINVAL, "precision must be MFS_FP32 or MFS_FP64");
@@ -1249,10 +1951,10 @@ void check_prec(int prec) {
 void kr_begin(mfs_problem &P, const double *b, double *x, const mfs_options &o, hipStream_t s) {
   Krylov &K = P.kr;
   MFS_REQUIRE(P.opts.mg_levels, MFS_EINVAL, "solve needs the multigrid hierarchy (mg_levels = 1)");
-  MFS_REQUIRE(P.L[0].g.Np > 0, MFS_EINVAL, "solve needs a pressure space");
+  MFS_REQUIRE(P.hp || P.L[0].g.Np > 0, MFS_EINVAL, "solve needs a pressure space");
   MFS_REQUIRE(!P.ns || P.ns_ready, MFS_EINVAL, "mfs_set_linearization has not been called");
   const LevelGeom &g = P.L[0].g;
-  const int64_t n = P.dim * g.Nv + g.Np;
+  const int64_t n = sys_n(P);
   K.b = b;
   K.x = x;
   K.s = s;
@@ -1268,8 +1970,11 @@ void kr_begin(mfs_problem &P, const double *b, double *x, const mfs_options &o, 
   K.info = mfs_solve_info{};
   K.t0 = std::chrono::steady_clock::now();
   // ||b|| first (state 1 reads it as bnorm), then the residual of x0
-  launch_fill_dirichlet<double>(g, x, b, s);  // x0: lifting of b's Dirichlet rows
-  vec_fill<double>(x + P.dim * g.Nv, 0.0, g.Np, s);
+  if (P.hp)  // x0: lifting of b's Dirichlet rows
+    mask_fill_dirichlet<double>(P.hp->lev[0].vd.dir, P.hp->lev[0].vd.N, 3, x, b, s);
+  else
+    launch_fill_dirichlet<double>(g, x, b, s);
+  vec_fill<double>(x + sys_vel(P), 0.0, sys_pres(P), s);
   multi_dot<double>(b, 0, 1, b, n, K.dev + 100, P.partials, s);
   MFS_HIP(hipMemcpyAsync(K.host + 100, K.dev + 100, sizeof(double), hipMemcpyDeviceToHost, s));
   MFS_HIP(hipStreamSynchronize(s));
@@ -1285,8 +1990,14 @@ extern "C" {
 int mfs_n_dofs(const mfs_problem *p, int level, int64_t *n_u, int64_t *n_p) {
   return guard([&] {
     check_level(p, level);
-    if (n_u) *n_u = p->L[level].g.Nv;
-    if (n_p) *n_p = p->L[level].g.Np;
+    if (level < p->nhp) {
+      if (n_u) *n_u = p->hp->lev[level].V.N;
+      if (n_p) *n_p = level == 0 ? p->hp->Pr.N : 0;
+      return;
+    }
+    const int l = level - p->nhp;
+    if (n_u) *n_u = p->L[l].g.Nv;
+    if (n_p) *n_p = p->hp ? 0 : p->L[l].g.Np;
   });
 }
 
@@ -1294,22 +2005,31 @@ int mfs_n_levels(const mfs_problem *p, int *n) {
   return guard([&] {
     check_problem(p);
     MFS_REQUIRE(n != nullptr, MFS_EINVAL, "n is NULL");
-    *n = p->nlev;
+    *n = p->nhp + p->nlev;
   });
 }
 
 int mfs_level_info(const mfs_problem *p, int level, int *k, int *n) {
   return guard([&] {
     check_level(p, level);
-    if (k) *k = p->L[level].g.k;
+    if (level < p->nhp) {
+      const auto &d = p->hp->lev[level].V.deg;
+      if (k) *k = *std::max_element(d.begin(), d.end());
+      if (n)
+        for (int a = 0; a < 3; ++a) n[a] = p->hp->n[a];
+      return;
+    }
+    const int l = level - p->nhp;
+    if (k) *k = p->L[l].g.k;
     if (n)
-      for (int a = 0; a < 3; ++a) n[a] = p->L[level].g.n[a];
+      for (int a = 0; a < 3; ++a) n[a] = p->L[l].g.n[a];
   });
 }
 
 int mfs_support_points(const mfs_problem *p, int deg, double *xyz) {
   return guard([&] {
     check_problem(p);
+    MFS_REQUIRE(!p->hp, MFS_EUNSUPPORTED, "support points of hp spaces are not provided");
     MFS_REQUIRE(deg >= 1 && deg <= 7, MFS_EINVAL, "degree out of range");
     MFS_REQUIRE(xyz != nullptr, MFS_EINVAL, "buffer is NULL");
     const Level &L = p->L[0];
@@ -1378,6 +2098,10 @@ int mfs_vmult(mfs_problem *p, int op, int prec, int level, void *dst, const void
     check_prec(prec);
     MFS_REQUIRE(dst && src, MFS_EINVAL, "NULL vector");
     MFS_REQUIRE(dst != src, MFS_EINVAL, "dst and src must not alias");
+    if (p->hp) {
+      hp_vmult(*p, op, prec, level, dst, src, S(stream));
+      return;
+    }
     if (prec == MFS_FP64)
       apply_op<double>(*p, op, level, (double *)dst, (const double *)src, S(stream));
     else
@@ -1389,8 +2113,13 @@ int mfs_diagonal(mfs_problem *p, int level, double *dst, void *stream) {
   return guard([&] {
     check_level(p, level);
     MFS_REQUIRE(dst != nullptr, MFS_EINVAL, "NULL vector");
-    const Level &L = p->L[level];
     hipStream_t s = S(stream);
+    if (p->hp && level < p->nhp) {
+      vec_copy<double>(dst, p->hp->lev[level].diag, p->hp->lev[level].V.N, s);
+      return;
+    }
+    if (p->hp) level -= p->nhp;
+    const Level &L = p->L[level];
     if (p->ns) {
       MFS_REQUIRE(p->ns_ready, MFS_EINVAL, "mfs_set_linearization has not been called");
       ns_diagonal(*p, level, dst, s);
@@ -1407,7 +2136,7 @@ int mfs_get_lambda(const mfs_problem *p, int level, double *lambda) {
   return guard([&] {
     check_level(p, level);
     MFS_REQUIRE(lambda != nullptr, MFS_EINVAL, "NULL output");
-    *lambda = p->L[level].lambda;
+    *lambda = level < p->nhp ? p->hp->lev[level].lambda : p->L[level - p->nhp].lambda;
   });
 }
 
@@ -1415,7 +2144,10 @@ int mfs_set_lambda(mfs_problem *p, int level, double lambda) {
   return guard([&] {
     check_level(p, level);
     MFS_REQUIRE(lambda > 0, MFS_EINVAL, "lambda must be positive");
-    p->L[level].lambda = lambda;
+    if (level < p->nhp)
+      p->hp->lev[level].lambda = lambda;
+    else
+      p->L[level - p->nhp].lambda = lambda;
   });
 }
 
@@ -1426,7 +2158,12 @@ int mfs_vcycle(mfs_problem *p, int prec, void *dst, const void *src, void *strea
     MFS_REQUIRE(p->opts.mg_levels, MFS_EINVAL, "problem was set up without multigrid levels");
     MFS_REQUIRE(dst && src && dst != src, MFS_EINVAL, "bad vectors");
     MFS_REQUIRE(!p->ns || p->ns_ready, MFS_EINVAL, "mfs_set_linearization has not been called");
-    if (p->ns) {
+    if (p->hp) {
+      if (prec == MFS_FP64)
+        hp_vcycle<double>(*p, 0, (double *)dst, (const double *)src, S(stream));
+      else
+        hp_vcycle<float>(*p, 0, (float *)dst, (const float *)src, S(stream));
+    } else if (p->ns) {
       if (prec == MFS_FP64)
         ns_vcycle<double>(*p, 0, (double *)dst, (const double *)src, S(stream));
       else
@@ -1442,7 +2179,15 @@ int mfs_prolongate_add(mfs_problem *p, int prec, int fine, void *dst, const void
   return guard([&] {
     check_level(p, fine);
     check_prec(prec);
-    MFS_REQUIRE(fine + 1 < p->nlev, MFS_EINVAL, "no coarser level below %d", fine);
+    MFS_REQUIRE(fine + 1 < p->nhp + p->nlev, MFS_EINVAL, "no coarser level below %d", fine);
+    if (fine < p->nhp) {
+      if (prec == MFS_FP64)
+        hp_prolongate_add<double>(*p, fine, (double *)dst, (const double *)src, S(stream));
+      else
+        hp_prolongate_add<float>(*p, fine, (float *)dst, (const float *)src, S(stream));
+      return;
+    }
+    fine -= p->nhp;
     const Level &F = p->L[fine], &C = p->L[fine + 1];
     const int ncp = p->ns ? 1 : 0;
     if (prec == MFS_FP64)
@@ -1458,7 +2203,15 @@ int mfs_restrict(mfs_problem *p, int prec, int fine, void *dst, const void *src,
   return guard([&] {
     check_level(p, fine);
     check_prec(prec);
-    MFS_REQUIRE(fine + 1 < p->nlev, MFS_EINVAL, "no coarser level below %d", fine);
+    MFS_REQUIRE(fine + 1 < p->nhp + p->nlev, MFS_EINVAL, "no coarser level below %d", fine);
+    if (fine < p->nhp) {
+      if (prec == MFS_FP64)
+        hp_restrict<double>(*p, fine, (double *)dst, (const double *)src, S(stream));
+      else
+        hp_restrict<float>(*p, fine, (float *)dst, (const float *)src, S(stream));
+      return;
+    }
+    fine -= p->nhp;
     const Level &F = p->L[fine], &C = p->L[fine + 1];
     const int ncp = p->ns ? 1 : 0;
     if (prec == MFS_FP64)
@@ -1474,7 +2227,8 @@ int mfs_precondition(mfs_problem *p, int prec, void *dst, const void *src, void 
   return guard([&] {
     check_problem(p);
     check_prec(prec);
-    MFS_REQUIRE(p->opts.mg_levels && p->L[0].g.Np > 0, MFS_EINVAL, "needs multigrid levels and a pressure space");
+    MFS_REQUIRE(p->opts.mg_levels && (p->hp || p->L[0].g.Np > 0), MFS_EINVAL,
+                "needs multigrid levels and a pressure space");
     MFS_REQUIRE(dst && src && dst != src, MFS_EINVAL, "bad vectors");
     MFS_REQUIRE(!p->ns || p->ns_ready, MFS_EINVAL, "mfs_set_linearization has not been called");
     if (prec == MFS_FP64)
@@ -1489,6 +2243,7 @@ int mfs_rhs(mfs_problem *p, const double *f_qp, const double *u_dirichlet, doubl
     check_problem(p);
     MFS_REQUIRE(f_qp && u_dirichlet && b, MFS_EINVAL, "NULL vector");
     MFS_REQUIRE(!p->ns, MFS_EUNSUPPORTED, "mfs_rhs assembles the Stokes right-hand side only");
+    MFS_REQUIRE(!p->hp, MFS_EUNSUPPORTED, "mfs_rhs is not provided for hp problems");
     const Level &L = p->L[0];
     const LevelGeom &g = L.g;
     MFS_REQUIRE(g.Np > 0, MFS_EINVAL, "needs a pressure space");

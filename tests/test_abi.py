@@ -69,3 +69,13 @@ def test_navier_stokes_options_validated_on_host():
     fp1 = mfs.mfs_footprint(3, [8, 8, 8], inputs.structured_vertices(3, [8, 8, 8]), 1,
                             mfs.mfs_default_options(pressure_offset=0, mg_levels=0))
     assert fp1 >= 8 ** 3 * 8 * 16 * 12
+
+
+def test_hp_setup_validates_degrees_on_host():
+    X = inputs.structured_vertices(3, [2, 2, 2])
+    with pytest.raises(mfs.MfsError) as e:
+        mfs.mfs_setup_hp([2, 2, 2], X, [2, 3, 7, 2, 2, 2, 2, 2], 1.0, stream=0)
+    assert e.value.code == mfs.MFS_EINVAL
+    with pytest.raises(mfs.MfsError) as e:
+        mfs.mfs_setup_hp([2, 2, 2], X, [2] * 8, 1.0, mfs.mfs_default_options(pressure_offset=0), stream=0)
+    assert e.value.code == mfs.MFS_EINVAL
