@@ -202,6 +202,53 @@ def ns_section(mfs, torch, inputs, args):
     return out
 
 
+def hp_section(mfs, torch, inputs, args):
+    """hp-adaptive Stokes (Sec. 3, minimum rule): velocity degree drawn per
+    4^3-cell block from {2..6} (seed 0), pressure k-1, n^3 cells, vertex noise
+    0.1h, nu = 1.  Stokes vmult throughput in FP64/FP32, and a solve
+    K x = K y (y ~ U[-1, 1], zero Dirichlet rows) to 1e-8 with the FP32
+    multigrid (hp p-levels to k = 2, then the structured h-levels) inside FP64
+    FGMRES, against the all-FP64 method."""
+    n = args.hp_n
+    deg = inputs.block_degrees([n] * 3, seed=0, block=4, lo=2, hi=6)
+    X = inputs.structured_vertices(3, [n] * 3, noise=0.1, seed=0)
+    out = {"workload": f"hp Stokes {n}^3 cells, k per 4^3 block uniform in 2..6 (seed 0), pressure k-1, "
+                       f"vertex noise 0.1h, nu=1",
+           "degree_histogram": {int(k): int((deg == k).sum()) for k in range(2, 7)}}
+    for name, prec in (("fp32_mg_fp64_fgmres", mfs.MFS_FP32), ("fp64", mfs.MFS_FP64)):
+        opts = mfs.mfs_default_options(precond_precision=prec, rtol=1e-8, maxit=300)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = mfs.mfs_setup_hp([n] * 3, X, deg, 1.0, opts)
+        torch.cuda.synchronize()
+        setup = time.perf_counter() - t0
+        try:
+            nu_, np_ = mfs.mfs_n_dofs(h, 0)
+            N = 3 * nu_ + np_
+            out["n_dofs"] = N
+            if name == "fp64":
+                for p, pname in ((mfs.MFS_FP64, "f64"), (mfs.MFS_FP32, "f32")):
+                    _, per = time_vmult(mfs, torch, h, N, p, max(10, args.steps // 2), 3)
+                    out[f"vmult_{pname}"] = {"dofs_per_s": N / float(per.mean()),
+                                             "avg_launch_us": float(per.mean()) * 1e6}
+            y = torch.from_numpy(inputs.uniform_vector(N, 3)).cuda()
+            b = torch.empty_like(y)
+            mfs.mfs_vmult(h, mfs.MFS_OP_STOKES, mfs.MFS_FP64, 0, b, y)  # Dirichlet rows of b carry y
+            times, info = [], None
+            for rep in range(2):
+                x = torch.zeros(N, dtype=torch.float64, device="cuda")
+                torch.cuda.synchronize()
+                t2 = time.perf_counter()
+                info = mfs.mfs_solve(h, b, x, opts)
+                times.append(time.perf_counter() - t2)
+            out[name] = {"setup_s": setup, "solve_s": min(times), "iterations": info.iterations,
+                         "rel_residual": info.rel_residual, "status": info.status}
+        finally:
+            mfs.mfs_destroy(h)
+    out["speedup_mixed_vs_fp64"] = out["fp64"]["solve_s"] / out["fp32_mg_fp64_fgmres"]["solve_s"]
+    return out
+
+
 def serving_section(args):
     """Bounded sample of the served stream: Poisson arrivals, n in {8, 16, 32},
     k in {2, 3}; continuous batching with FP32 multigrid vs sequential FP64."""
@@ -231,6 +278,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--serve-rate", type=float, default=8.0)
     ap.add_argument("--no-ns", action="store_true", help="skip the Navier-Stokes measurements")
+    ap.add_argument("--no-hp", action="store_true", help="skip the hp measurements")
+    ap.add_argument("--hp-n", type=int, default=32)
     ap.add_argument("--ns-n", type=int, default=128)
     ap.add_argument("--ns-solve-n", type=int, default=32)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -308,6 +357,8 @@ def main():
                                 "frac": fl / FP64_PEAK, "flop_per_dof": FLOP_PER_DOF[k]}
     if not args.no_ns:
         line["navier_stokes"] = ns_section(mfs, torch, inputs, args)
+    if not args.no_hp:
+        line["hp"] = hp_section(mfs, torch, inputs, args)
     if not args.no_solve:
         line["solve"] = solve_section(mfs, torch, inputs, args)
         line["serving"] = serving_section(args)

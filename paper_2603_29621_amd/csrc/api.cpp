@@ -77,6 +77,9 @@ struct Level {
   float *qd32 = nullptr;
   double *nsinv64 = nullptr;
   float *nsinv32 = nullptr;
+  // scratch of the three-pass restriction to the next coarser level
+  double *rs64 = nullptr;
+  float *rs32 = nullptr;
 };
 
 struct Krylov {
@@ -365,6 +368,10 @@ void plan_arena(Arena &A, mfs_problem &P, const std::vector<LevelGeom> &G) {
       L.qd32 = A.take<float>(ns_qd_elems(G[l]));
       L.nsinv64 = A.take<double>((P.dim + 1) * G[l].Nv);
       L.nsinv32 = A.take<float>((P.dim + 1) * G[l].Nv);
+      if (l + 1 < G.size()) {
+        L.rs64 = A.take<double>(restrict_work_elems(G[l], G[l + 1], P.dim + 1));
+        L.rs32 = A.take<float>(restrict_work_elems(G[l], G[l + 1], P.dim + 1));
+      }
     }
     const bool full = P.opts.mg_levels != 0;
     plan_ns_work(A, P.w64, G, P.dim, full);
@@ -400,6 +407,10 @@ void plan_arena(Arena &A, mfs_problem &P, const std::vector<LevelGeom> &G) {
     L.face32 = A.take<float>(q2_face_elems(G[l]));
     L.invdiag64 = A.take<double>(G[l].Nv);
     L.invdiag32 = A.take<float>(G[l].Nv);
+    if (l + 1 < G.size()) {
+      L.rs64 = A.take<double>(restrict_work_elems(G[l], G[l + 1], P.dim));
+      L.rs32 = A.take<float>(restrict_work_elems(G[l], G[l + 1], P.dim));
+    }
   }
   const bool full = P.opts.mg_levels != 0;
   plan_prec_work(A, P.w64, G, P.dim, full);
@@ -497,6 +508,16 @@ PrecWork<double> &work<double>(mfs_problem &P) {
 template <>
 PrecWork<float> &work<float>(mfs_problem &P) {
   return P.w32;
+}
+template <typename T>
+T *rwork(const Level &L);
+template <>
+double *rwork<double>(const Level &L) {
+  return L.rs64;
+}
+template <>
+float *rwork<float>(const Level &L) {
+  return L.rs32;
 }
 template <typename T>
 const T *invdiag(const Level &L);
@@ -917,7 +938,7 @@ void vcycle_level(mfs_problem &P, int l, T *x, const T *b, hipStream_t s) {
   apply_A<T>(P, l, r, x, s);
   vec_axpby<T>(r, T(1), b, T(-1), n, s);  // r = b - A x
   Level &C = P.L[l + 1];
-  launch_restrict<T>(L.g, C.g, L.h_to_coarser, L.emb.data(), W.b[l + 1], r, s);
+  launch_restrict<T>(L.g, C.g, L.h_to_coarser, L.emb.data(), W.b[l + 1], r, s, 0, rwork<T>(L));
   vcycle_level<T>(P, l + 1, W.x[l + 1], W.b[l + 1], s);
   launch_prolongate_add<T>(L.g, C.g, L.h_to_coarser, L.emb.data(), x, W.x[l + 1], s);
   chebyshev<T>(P, l, x, b, false, s);
@@ -955,7 +976,7 @@ void ns_vcycle(mfs_problem &P, int l, T *x, const T *b, hipStream_t s) {
   apply_ns<T>(P, l, r, x, s);
   vec_axpby<T>(r, T(1), b, T(-1), n, s);  // r = b - J x
   Level &C = P.L[l + 1];
-  launch_restrict<T>(L.g, C.g, L.h_to_coarser, L.emb.data(), W.b[l + 1], r, s, 1);
+  launch_restrict<T>(L.g, C.g, L.h_to_coarser, L.emb.data(), W.b[l + 1], r, s, 1, rwork<T>(L));
   ns_vcycle<T>(P, l + 1, W.x[l + 1], W.b[l + 1], s);
   launch_prolongate_add<T>(L.g, C.g, L.h_to_coarser, L.emb.data(), x, W.x[l + 1], s, 1);
   ns_relax<T>(P, l, x, b, s);
@@ -2216,10 +2237,10 @@ int mfs_restrict(mfs_problem *p, int prec, int fine, void *dst, const void *src,
     const int ncp = p->ns ? 1 : 0;
     if (prec == MFS_FP64)
       launch_restrict<double>(F.g, C.g, F.h_to_coarser, F.emb.data(), (double *)dst, (const double *)src, S(stream),
-                              ncp);
+                              ncp, F.rs64);
     else
       launch_restrict<float>(F.g, C.g, F.h_to_coarser, F.emb.data(), (float *)dst, (const float *)src, S(stream),
-                             ncp);
+                             ncp, F.rs32);
   });
 }
 

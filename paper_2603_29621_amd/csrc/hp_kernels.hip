@@ -12,37 +12,44 @@ namespace {
 constexpr int HB = 256;
 unsigned grid_for(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + HB - 1) / HB, 65535 * 8)); }
 
-template <typename T>
-__global__ void k_gather(int64_t nrows, int ncomp, const int64_t *row_ptr, const int *col, const double *val,
+// NC components at once: the map entries are read once
+template <typename T, int NC>
+__global__ void k_gather(int64_t nrows, const int64_t *row_ptr, const int *col, const double *val,
                          const int64_t *row_ev, const int *row_nb, const T *x, int64_t N, T *ev) {
   for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < nrows; r += (int64_t)gridDim.x * blockDim.x) {
     const int64_t b = row_ptr[r], e = row_ptr[r + 1];
+    double s[NC] = {};
+    for (int64_t j = b; j < e; ++j) {
+      const double w = val[j];
+      const int64_t c = col[j];
+#pragma unroll
+      for (int comp = 0; comp < NC; ++comp) s[comp] += w * (double)x[comp * N + c];
+    }
     const int64_t base = row_ev[r];
     const int nb = row_nb[r];
-    for (int comp = 0; comp < ncomp; ++comp) {
-      double s = 0;
-      for (int64_t j = b; j < e; ++j) s += val[j] * (double)x[comp * N + col[j]];
-      ev[base + (int64_t)comp * nb] = (T)s;
-    }
+#pragma unroll
+    for (int comp = 0; comp < NC; ++comp) ev[base + (int64_t)comp * nb] = (T)s[comp];
   }
 }
 
-template <typename T>
-__global__ void k_scatter(int64_t N, int ncomp, const int64_t *tptr, const int64_t *tev, const int *tnb,
-                          const double *tval, const uint8_t *dir, const T *ev, const T *src, T *dst) {
+template <typename T, int NC>
+__global__ void k_scatter(int64_t N, const int64_t *tptr, const int64_t *tev, const int *tnb, const double *tval,
+                          const uint8_t *dir, const T *ev, const T *src, T *dst) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
-    const bool d = dir != nullptr && dir[i];
-    for (int comp = 0; comp < ncomp; ++comp) {
-      T out;
-      if (d) {
-        out = src ? src[comp * N + i] : T(0);
-      } else {
-        double s = 0;
-        for (int64_t j = tptr[i]; j < tptr[i + 1]; ++j) s += tval[j] * (double)ev[tev[j] + (int64_t)comp * tnb[j]];
-        out = (T)s;
-      }
-      dst[comp * N + i] = out;
+    if (dir != nullptr && dir[i]) {
+#pragma unroll
+      for (int comp = 0; comp < NC; ++comp) dst[comp * N + i] = src ? src[comp * N + i] : T(0);
+      continue;
     }
+    double s[NC] = {};
+    for (int64_t j = tptr[i]; j < tptr[i + 1]; ++j) {
+      const double w = tval[j];
+      const int64_t e = tev[j], nb = tnb[j];
+#pragma unroll
+      for (int comp = 0; comp < NC; ++comp) s[comp] += w * (double)ev[e + comp * nb];
+    }
+#pragma unroll
+    for (int comp = 0; comp < NC; ++comp) dst[comp * N + i] = (T)s[comp];
   }
 }
 
@@ -181,8 +188,12 @@ template <typename T>
 void hp_gather(int64_t nrows, int ncomp, const int64_t *row_ptr, const int *col, const double *val,
                const int64_t *row_ev, const int *row_nb, const T *x, int64_t N, T *ev, hipStream_t s) {
   if (nrows == 0) return;
-  hipLaunchKernelGGL(k_gather<T>, dim3(grid_for(nrows)), dim3(HB), 0, s, nrows, ncomp, row_ptr, col, val, row_ev,
-                     row_nb, x, N, ev);
+  if (ncomp == 3)
+    hipLaunchKernelGGL((k_gather<T, 3>), dim3(grid_for(nrows)), dim3(HB), 0, s, nrows, row_ptr, col, val, row_ev,
+                       row_nb, x, N, ev);
+  else
+    hipLaunchKernelGGL((k_gather<T, 1>), dim3(grid_for(nrows)), dim3(HB), 0, s, nrows, row_ptr, col, val, row_ev,
+                       row_nb, x, N, ev);
   MFS_HIP(hipGetLastError());
 }
 
@@ -190,8 +201,12 @@ template <typename T>
 void hp_scatter(int64_t N, int ncomp, const int64_t *tptr, const int64_t *tev, const int *tnb, const double *tval,
                 const uint8_t *dirichlet, const T *ev, const T *src, T *dst, hipStream_t s) {
   if (N == 0) return;
-  hipLaunchKernelGGL(k_scatter<T>, dim3(grid_for(N)), dim3(HB), 0, s, N, ncomp, tptr, tev, tnb, tval, dirichlet, ev,
-                     src, dst);
+  if (ncomp == 3)
+    hipLaunchKernelGGL((k_scatter<T, 3>), dim3(grid_for(N)), dim3(HB), 0, s, N, tptr, tev, tnb, tval, dirichlet, ev,
+                       src, dst);
+  else
+    hipLaunchKernelGGL((k_scatter<T, 1>), dim3(grid_for(N)), dim3(HB), 0, s, N, tptr, tev, tnb, tval, dirichlet, ev,
+                       src, dst);
   MFS_HIP(hipGetLastError());
 }
 

@@ -23,7 +23,30 @@ void compress(std::vector<std::pair<int64_t, double>> &w) {
   w.resize(o);
 }
 
-std::vector<double> lag1(int m, double t) { return lagrange_values(gll_nodes(m), std::vector<double>{t}); }
+// GLL nodes of degree m (cached) and the Lagrange basis on them at t
+const std::vector<double> &gll(int m) {
+  static const std::vector<std::vector<double>> cache = [] {
+    std::vector<std::vector<double>> c(MAXQ);
+    for (int k = 1; k < MAXQ; ++k) c[k] = gll_nodes(k);
+    return c;
+  }();
+  return cache[m];
+}
+struct Lag {
+  double v[MAXQ];
+  double operator[](int j) const { return v[j]; }
+};
+Lag lag1(int m, double t) {
+  const auto &x = gll(m);
+  Lag L;
+  for (int j = 0; j <= m; ++j) {
+    double p = 1.0;
+    for (int l = 0; l <= m; ++l)
+      if (l != j) p *= (t - x[l]) / (x[j] - x[l]);
+    L.v[j] = p;
+  }
+  return L;
+}
 
 }  // namespace
 
@@ -134,7 +157,7 @@ void HpSpaceHost::build(const int n_[3], const std::vector<int> &degrees) {
     row_base[c] = (int64_t)row_ptr.size() - 1;
     const int cc[3] = {(int)(c % n[0]), (int)((c / n[0]) % n[1]), (int)(c / ((int64_t)n[0] * n[1]))};
     const int k = deg[c];
-    const auto x = gll_nodes(k);
+    const auto &x = gll(k);
     for (int l = 0; l <= k; ++l)
       for (int j = 0; j <= k; ++j)
         for (int i = 0; i <= k; ++i) {
@@ -183,7 +206,7 @@ void HpSpaceHost::edge_weights(int a, const int e[3], double t, double scale,
                                std::vector<std::pair<int64_t, double>> &out) const {
   const int64_t ei = eidx(a, e);
   const int m = edeg[a][ei];
-  const auto L = lag1(m, t);
+  const Lag L = lag1(m, t);
   int end[3] = {e[0], e[1], e[2]};
   end[a] += 1;
   for (int j = 0; j <= m; ++j) {
@@ -204,8 +227,8 @@ void HpSpaceHost::face_weights(int a, const int f[3], double s, double t,
   const int a1 = a == 0 ? 1 : 0, a2 = a == 2 ? 1 : 2;
   const int64_t fi = fidx(a, f);
   const int m = fdeg[a][fi];
-  const auto x = gll_nodes(m);
-  const auto Ls = lag1(m, s), Lt = lag1(m, t);
+  const auto &x = gll(m);
+  const Lag Ls = lag1(m, s), Lt = lag1(m, t);
   for (int q = 0; q <= m; ++q)
     for (int p = 0; p <= m; ++p) {
       const double w = Ls[p] * Lt[q];
@@ -246,7 +269,7 @@ void HpSpaceHost::reference_point(int64_t g, double p[3]) const {
       const int idx[3] = {(int)(e % ebox[a][0]), (int)((e / ebox[a][0]) % ebox[a][1]),
                           (int)(e / ((int64_t)ebox[a][0] * ebox[a][1]))};
       for (int b = 0; b < 3; ++b) p[b] = idx[b];
-      p[a] += gll_nodes(m)[j + 1];
+      p[a] += gll(m)[j + 1];
       return;
     }
   }
@@ -261,7 +284,7 @@ void HpSpaceHost::reference_point(int64_t g, double p[3]) const {
       const int a1 = a == 0 ? 1 : 0, a2 = a == 2 ? 1 : 2;
       const int idx[3] = {(int)(f % fbox[a][0]), (int)((f / fbox[a][0]) % fbox[a][1]),
                           (int)(f / ((int64_t)fbox[a][0] * fbox[a][1]))};
-      const auto x = gll_nodes(m);
+      const auto &x = gll(m);
       for (int b = 0; b < 3; ++b) p[b] = idx[b];
       p[a1] += x[1 + j % (m - 1)];
       p[a2] += x[1 + j / (m - 1)];
@@ -271,7 +294,7 @@ void HpSpaceHost::reference_point(int64_t g, double p[3]) const {
   const int64_t c = (int64_t)(std::upper_bound(coff.begin(), coff.end(), g) - coff.begin()) - 1;
   const int k = deg[c];
   const int64_t j = g - coff[c];
-  const auto x = gll_nodes(k);
+  const auto &x = gll(k);
   const int cc[3] = {(int)(c % n[0]), (int)((c / n[0]) % n[1]), (int)(c / ((int64_t)n[0] * n[1]))};
   p[0] = cc[0] + x[1 + j % (k - 1)];
   p[1] = cc[1] + x[1 + (j / (k - 1)) % (k - 1)];

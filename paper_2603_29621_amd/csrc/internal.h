@@ -127,9 +127,12 @@ void launch_fill_dirichlet(const LevelGeom &g, T *dst_u, const T *src_u, hipStre
 template <typename T>
 void launch_prolongate_add(const LevelGeom &fine, const LevelGeom &coarse, bool h_transfer, const double *emb_host,
                            T *dst_fine, const T *src_coarse, hipStream_t s, int ncp = 0);
+// work: scratch of restrict_work_elems(fine, coarse, dim + ncp) elements for
+// the three-pass form (nullptr: one-pass gather)
 template <typename T>
 void launch_restrict(const LevelGeom &fine, const LevelGeom &coarse, bool h_transfer, const double *emb_host,
-                     T *dst_coarse, const T *src_fine, hipStream_t s, int ncp = 0);
+                     T *dst_coarse, const T *src_fine, hipStream_t s, int ncp = 0, T *work = nullptr);
+int64_t restrict_work_elems(const LevelGeom &fine, const LevelGeom &coarse, int ncomp);
 
 // ----------------------------------------------------------------- Navier-Stokes (ns_kernels.hip)
 // per-quadrature-point linearisation data: u0 (3), grad u0 (9), R(u0) (3),

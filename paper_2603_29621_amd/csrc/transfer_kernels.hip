@@ -12,8 +12,12 @@
 //    coarse cell (every coarse cell containing the node yields the same value
 //    because the coarse function is continuous, so the weighted sum over the m
 //    cells equals this single evaluation);
-//  * restriction: thread per coarse node, gathering w * E * r_f over the fine
-//    nodes of every coarse cell that contains it, direction by direction.
+//  * restriction: the transpose, applied direction by direction in three
+//    passes (x, then y, then z), each a banded 1D operator: a coarse node
+//    gathers the fine nodes of the (one or two) coarse cells that contain it.
+//    Because the coarse basis functions are continuous, the averaged weights
+//    W = 1/m of eq. (transfer) equal evaluation in one owner cell per fine node
+//    (the lower cell, the last one at the end), which is what the passes use.
 // Vectors hold `ncu` components carrying the Dirichlet constraints (the
 // velocity) followed by `ncp` unconstrained ones (the equal-order pressure of
 // the monolithic Navier-Stokes hierarchy), each of one scalar node grid.
@@ -140,6 +144,41 @@ __global__ void k_restrict(TransferArgs a, T *dst, const T *src) {
   }
 }
 
+// one separable restriction pass along direction d: out has the coarse node
+// count along d and the input extents elsewhere; components < ncu carry the
+// Dirichlet masks (fine and coarse boundary nodes along d are dropped)
+template <typename T>
+__global__ void k_restrict_pass(TransferArgs a, int d, int ni0, int ni1, int ni2, int no0, int no1, int no2,
+                                int ncomp, int64_t in_stride, int64_t out_stride, const T *in, T *out) {
+  const int64_t nout = (int64_t)no0 * no1 * no2;
+  const int F = a.F, kc = a.kc, nc = a.nc[d], nf = a.nf[d], ncn = a.ncn[d];
+  for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < nout; o += (int64_t)gridDim.x * blockDim.x) {
+    const int o0 = (int)(o % no0), o1 = (int)((o / no0) % no1), o2 = (int)(o / ((int64_t)no0 * no1));
+    const int j = d == 0 ? o0 : (d == 1 ? o1 : o2);
+    const int64_t sd = d == 0 ? 1 : (d == 1 ? (int64_t)ni0 : (int64_t)ni0 * ni1);
+    const int64_t base = (d == 0 ? 0 : o0) + (int64_t)ni0 * ((d == 1 ? 0 : o1) + (int64_t)ni1 * (d == 2 ? 0 : o2));
+    const bool cbnd = j == 0 || j == ncn - 1;
+    // fine range of the coarse cells containing j
+    const int C0 = (j % kc == 0 && j > 0) ? j / kc - 1 : j / kc;
+    const int C1 = j / kc < nc ? j / kc : nc - 1;
+    const int f0 = F * C0, f1 = F * (C1 + 1);
+    for (int comp = 0; comp < ncomp; ++comp) {
+      const bool con = comp < a.ncu;
+      double acc = 0;
+      if (!(con && cbnd)) {
+        for (int f = f0; f <= f1; ++f) {
+          if (con && (f == 0 || f == nf - 1)) continue;
+          const int own = f / F < nc ? f / F : nc - 1;
+          const int jl = j - kc * own;
+          if (jl < 0 || jl > kc) continue;
+          acc += a.E[(f - F * own) * MAXQ + jl] * (double)in[comp * in_stride + base + sd * f];
+        }
+      }
+      out[comp * out_stride + o] = (T)acc;
+    }
+  }
+}
+
 static TransferArgs make_targs(const LevelGeom &fine, const LevelGeom &coarse, bool h, const double *emb_host,
                                int ncp) {
   TransferArgs a{};
@@ -170,19 +209,50 @@ void launch_prolongate_add(const LevelGeom &fine, const LevelGeom &coarse, bool 
 }
 template <typename T>
 void launch_restrict(const LevelGeom &fine, const LevelGeom &coarse, bool h, const double *emb, T *dst_coarse,
-                     const T *src_fine, hipStream_t s, int ncp) {
+                     const T *src_fine, hipStream_t s, int ncp, T *work) {
   const TransferArgs a = make_targs(fine, coarse, h, emb, ncp);
-  hipLaunchKernelGGL(k_restrict<T>, dim3((unsigned)((coarse.Nv + 255) / 256)), dim3(256), 0, s, a, dst_coarse,
-                     src_fine);
-  MFS_HIP(hipGetLastError());
+  if (work == nullptr) {  // single-pass gather (no scratch available)
+    hipLaunchKernelGGL(k_restrict<T>, dim3((unsigned)((coarse.Nv + 255) / 256)), dim3(256), 0, s, a, dst_coarse,
+                       src_fine);
+    MFS_HIP(hipGetLastError());
+    return;
+  }
+  const int ncomp = a.ncu + a.ncp;
+  int ext[3] = {fine.nv[0], fine.nv[1], fine.nv[2]};
+  const T *in = src_fine;
+  int64_t in_stride = fine.Nv;
+  T *bufs[2] = {work, work + (int64_t)ncomp * restrict_work_elems(fine, coarse, 1) / 2};
+  for (int d = 0; d < fine.dim; ++d) {
+    int oext[3] = {ext[0], ext[1], ext[2]};
+    oext[d] = coarse.nv[d];
+    const int64_t nout = (int64_t)oext[0] * oext[1] * oext[2];
+    const bool last = d == fine.dim - 1;
+    T *out = last ? dst_coarse : bufs[d & 1];
+    const int64_t out_stride = last ? coarse.Nv : nout;
+    const unsigned grid = (unsigned)std::min<int64_t>((nout + 255) / 256, 65535);
+    hipLaunchKernelGGL(k_restrict_pass<T>, dim3(grid), dim3(256), 0, s, a, d, ext[0], ext[1], ext[2], oext[0],
+                       oext[1], oext[2], ncomp, in_stride, out_stride, in, out);
+    MFS_HIP(hipGetLastError());
+    in = out;
+    in_stride = nout;
+    for (int b = 0; b < 3; ++b) ext[b] = oext[b];
+  }
+}
+
+// scratch (elements) of the three-pass restriction for ncomp components: the
+// two intermediate arrays after the x and y passes
+int64_t restrict_work_elems(const LevelGeom &fine, const LevelGeom &coarse, int ncomp) {
+  const int64_t a1 = (int64_t)coarse.nv[0] * fine.nv[1] * fine.nv[2];
+  const int64_t a2 = (int64_t)coarse.nv[0] * coarse.nv[1] * fine.nv[2];
+  return 2 * ncomp * std::max(a1, a2);
 }
 template void launch_prolongate_add<double>(const LevelGeom &, const LevelGeom &, bool, const double *, double *,
                                             const double *, hipStream_t, int);
 template void launch_prolongate_add<float>(const LevelGeom &, const LevelGeom &, bool, const double *, float *,
                                            const float *, hipStream_t, int);
 template void launch_restrict<double>(const LevelGeom &, const LevelGeom &, bool, const double *, double *,
-                                      const double *, hipStream_t, int);
+                                      const double *, hipStream_t, int, double *);
 template void launch_restrict<float>(const LevelGeom &, const LevelGeom &, bool, const double *, float *,
-                                     const float *, hipStream_t, int);
+                                     const float *, hipStream_t, int, float *);
 
 }  // namespace mfs
