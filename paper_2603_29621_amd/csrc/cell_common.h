@@ -6,17 +6,49 @@
 
 namespace mfs {
 
+// Thread layout: one thread per quadrature point.  When a cell's points fit
+// in a wavefront (NQ <= 64) the cells are packed per wavefront (64 / NQ of
+// them, the remaining lanes idle) and the LDS sweeps of a cell synchronise
+// at wavefront scope only; larger cells span several wavefronts and use
+// workgroup barriers.
 template <int DIM, int K, int KP>
 struct Shape {
   static constexpr int Q = K + 1;
   static constexpr int N = K + 1;
   static constexpr int M = KP + 1;
   static constexpr int NQ = DIM == 2 ? Q * Q : Q * Q * Q;
-  static constexpr int CPB = NQ >= 256 ? 1 : 256 / NQ;
-  static constexpr int NT = CPB * NQ;
-  static constexpr int BLOCK = (NT + 63) / 64 * 64;
+  static constexpr bool WAVE = NQ <= 64;
+  static constexpr int CPW = WAVE ? 64 / NQ : 0;  // cells per wavefront
+  static constexpr int CPB = WAVE ? 4 * CPW : (NQ >= 256 ? 1 : 256 / NQ);
+  static constexpr int NT = WAVE ? 256 : CPB * NQ;
+  static constexpr int BLOCK = WAVE ? 256 : (NT + 63) / 64 * 64;
   static constexpr int NV = 1 << DIM;
+  // thread -> (cell e of the block, point t); inactive threads get a valid e
+  __device__ static void map(int tid, int &e, int &t, bool &active) {
+    if (WAVE) {
+      const int w = tid >> 6, l = tid & 63, sl = l / NQ;
+      active = sl < CPW;
+      e = w * CPW + (active ? sl : 0);
+      t = active ? l - sl * NQ : 0;
+    } else {
+      active = tid < NT;
+      e = active ? tid / NQ : CPB - 1;
+      t = active ? tid - e * NQ : 0;
+    }
+  }
 };
+
+// synchronisation of the threads of one cell between LDS sweeps
+template <bool WAVE>
+__device__ __forceinline__ void csync() {
+  if (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
 
 // out = sum_m mat(r, m) in[.. m ..] along direction DIR; TR reads mat(m, r).
 template <int DIM, int Q, int DIR, int C, bool TR, typename T>
@@ -142,21 +174,21 @@ struct CellCtx {
     if (DIM == 2) {
       T v = sweep<DIM, Q, 0, C, false>(b0, S, qi, qj, ql);
       if (active) b1[t] = v;
-      __syncthreads();
+      csync<Sh::WAVE>();
       v = sweep<DIM, Q, 1, C, false>(b1, S, qi, qj, ql);
       if (active) b0[t] = v;
-      __syncthreads();
+      csync<Sh::WAVE>();
       return b0;
     } else {
       T v = sweep<DIM, Q, 0, C, false>(b0, S, qi, qj, ql);
       if (active) b1[t] = v;
-      __syncthreads();
+      csync<Sh::WAVE>();
       v = sweep<DIM, Q, 1, C, false>(b1, S, qi, qj, ql);
       if (active) b0[t] = v;
-      __syncthreads();
+      csync<Sh::WAVE>();
       v = sweep<DIM, Q, 2, C, false>(b0, S, qi, qj, ql);
       if (active) b1[t] = v;
-      __syncthreads();
+      csync<Sh::WAVE>();
       return b1;
     }
   }
@@ -169,15 +201,15 @@ struct CellCtx {
     if (DIM == 2) {
       T v = sweep<DIM, Q, 1, Q, true>(in, S, qi, qj, ql);
       if (active) o[t] = v;
-      __syncthreads();
+      csync<Sh::WAVE>();
       return sweep<DIM, Q, 0, Q, true>(o, S, qi, qj, ql);
     } else {
       T v = sweep<DIM, Q, 2, Q, true>(in, S, qi, qj, ql);
       if (active) o[t] = v;
-      __syncthreads();
+      csync<Sh::WAVE>();
       v = sweep<DIM, Q, 1, Q, true>(o, S, qi, qj, ql);
       if (active) in[t] = v;
-      __syncthreads();
+      csync<Sh::WAVE>();
       return sweep<DIM, Q, 0, Q, true>(in, S, qi, qj, ql);
     }
   }
@@ -189,7 +221,7 @@ struct CellCtx {
     g[0] = sweep<DIM, Q, 0, Q, false>(vals, D, qi, qj, ql);
     g[1] = sweep<DIM, Q, 1, Q, false>(vals, D, qi, qj, ql);
     if (DIM == 3) g[2] = sweep<DIM, Q, 2, Q, false>(vals, D, qi, qj, ql);
-    __syncthreads();
+    csync<Sh::WAVE>();
   }
 
   // test with reference gradients: sum_q f_b(q) d_b phi_i(q) -> nodal value
@@ -199,15 +231,15 @@ struct CellCtx {
       b1[t] = f[1];
       if (DIM == 3) b2[t] = f[2];
     }
-    __syncthreads();
+    csync<Sh::WAVE>();
     const T *D = tab + TAB_D;
     T r = sweep<DIM, Q, 0, Q, true>(b0, D, qi, qj, ql) + sweep<DIM, Q, 1, Q, true>(b1, D, qi, qj, ql);
     if (DIM == 3) r += sweep<DIM, Q, 2, Q, true>(b2, D, qi, qj, ql);
-    __syncthreads();
+    csync<Sh::WAVE>();
     if (active) b0[t] = r;
-    __syncthreads();
+    csync<Sh::WAVE>();
     T v = integrate<N, TAB_S>(b0);
-    __syncthreads();
+    csync<Sh::WAVE>();
     return v;
   }
 };

@@ -31,9 +31,8 @@ __global__ void __launch_bounds__((Shape<3, K, K - 1>::BLOCK)) cell_kernel_ev(Ev
   const int tid = threadIdx.x;
   for (int i = tid; i < TAB_SIZE; i += Sh::BLOCK) s_tab[i] = a.tab[i];
   CellCtx<DIM, K, K - 1, T> c;
-  c.active = tid < Sh::NT;
-  const int e = c.active ? tid / NQ : CPB - 1;
-  c.t = c.active ? tid - e * NQ : 0;
+  int e;
+  Sh::map(tid, e, c.t, c.active);
   const int slot = blockIdx.x * CPB + e;
   c.valid = c.active && slot < a.ncells;
   const int cell = c.valid ? a.ev.cells[slot] : 0;
@@ -71,7 +70,7 @@ __global__ void __launch_bounds__((Shape<3, K, K - 1>::BLOCK)) cell_kernel_ev(Ev
     for (int comp = 0; comp < DIM; ++comp) {
       const T v = c.valid ? a.ev.in_u[ou + comp * NQ + c.t] : T(0);
       if (c.active) c.b0[c.t] = v;
-      __syncthreads();
+      csync<Sh::WAVE>();
       c.gradient(g[comp]);
     }
   }
@@ -79,10 +78,10 @@ __global__ void __launch_bounds__((Shape<3, K, K - 1>::BLOCK)) cell_kernel_ev(Ev
   if (NEED_P) {
     const T v = (c.valid && ploc) ? a.ev.in_p[op + jp] : T(0);
     if (c.active) c.b0[c.t] = v;
-    __syncthreads();
+    csync<Sh::WAVE>();
     const T *vals = c.template interpolate<M, TAB_SP>();
     pval = vals[c.t];
-    __syncthreads();
+    csync<Sh::WAVE>();
   }
 
   T xi[3] = {s_tab[TAB_X + c.qi], s_tab[TAB_X + c.qj], s_tab[TAB_X + c.ql]};
@@ -140,7 +139,7 @@ __global__ void __launch_bounds__((Shape<3, K, K - 1>::BLOCK)) cell_kernel_ev(Ev
   }
   if (OUT_P) {
     if (c.active) c.b0[c.t] = qv;
-    __syncthreads();
+    csync<Sh::WAVE>();
     const T r = c.template integrate<M, TAB_SP>(c.b0);
     if (c.valid && ploc) a.ev.out_p[op + jp] = r;
   }

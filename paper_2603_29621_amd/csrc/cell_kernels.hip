@@ -44,9 +44,8 @@ __global__ void __launch_bounds__((Shape<DIM, K, KP>::BLOCK)) cell_kernel(CellAr
   const int tid = threadIdx.x;
   for (int i = tid; i < TAB_SIZE; i += Sh::BLOCK) s_tab[i] = a.tab[i];
   CellCtx<DIM, K, KP, T> c;
-  c.active = tid < Sh::NT;
-  const int e = c.active ? tid / NQ : CPB - 1;
-  c.t = c.active ? tid - e * NQ : 0;
+  int e;
+  Sh::map(tid, e, c.t, c.active);
   const int cell = blockIdx.x * CPB + e;
   c.valid = c.active && cell < a.ncells;
   c.qi = c.t % Q;
@@ -86,7 +85,7 @@ __global__ void __launch_bounds__((Shape<DIM, K, KP>::BLOCK)) cell_kernel(CellAr
       T v = 0;
       if (c.valid && (a.src_all ? dir : !dir)) v = a.src_u[comp * a.Nv + vnode];
       if (c.active) c.b0[c.t] = v;
-      __syncthreads();
+      csync<Sh::WAVE>();
       c.gradient(g[comp]);
     }
   }
@@ -97,10 +96,10 @@ __global__ void __launch_bounds__((Shape<DIM, K, KP>::BLOCK)) cell_kernel(CellAr
     T v = 0;
     if (c.valid && ploc) v = a.src_p[pnode];
     if (c.active) c.b0[c.t] = v;
-    __syncthreads();
+    csync<Sh::WAVE>();
     const T *vals = c.template interpolate<Sh::M, TAB_SP>();
     pval = vals[c.t];
-    __syncthreads();
+    csync<Sh::WAVE>();
   }
 
   // geometry at this Gauss point
@@ -161,7 +160,7 @@ __global__ void __launch_bounds__((Shape<DIM, K, KP>::BLOCK)) cell_kernel(CellAr
   }
   if (OUT_P) {
     if (c.active) c.b0[c.t] = qv;
-    __syncthreads();
+    csync<Sh::WAVE>();
     const T r = c.template integrate<Sh::M, TAB_SP>(c.b0);
     if (c.valid && ploc) atomic_add(a.dst_p + pnode, r);
   }
@@ -178,9 +177,9 @@ __global__ void __launch_bounds__((Shape<DIM, K, 0>::BLOCK)) laplace_diag_kernel
   __shared__ T s_X[CPB][Sh::NV * DIM];
   const int tid = threadIdx.x;
   for (int i = tid; i < TAB_SIZE; i += Sh::BLOCK) s_tab[i] = a.tab[i];
-  const bool active = tid < Sh::NT;
-  const int e = active ? tid / NQ : CPB - 1;
-  const int t = active ? tid - e * NQ : 0;
+  int e, t;
+  bool active;
+  Sh::map(tid, e, t, active);
   const int cell = blockIdx.x * CPB + e;
   const bool valid = active && cell < a.ncells;
   const int qi = t % Q, qj = (t / Q) % Q, ql = DIM == 3 ? t / (Q * Q) : 0;
@@ -271,9 +270,9 @@ __global__ void __launch_bounds__((Shape<DIM, K, KP>::BLOCK)) mass_diag_kernel(C
   __shared__ T s_X[CPB][Sh::NV * DIM];
   const int tid = threadIdx.x;
   for (int i = tid; i < TAB_SIZE; i += Sh::BLOCK) s_tab[i] = a.tab[i];
-  const bool active = tid < Sh::NT;
-  const int e = active ? tid / NQ : CPB - 1;
-  const int t = active ? tid - e * NQ : 0;
+  int e, t;
+  bool active;
+  Sh::map(tid, e, t, active);
   const int cell = blockIdx.x * CPB + e;
   const bool valid = active && cell < a.ncells;
   const int qi = t % Q, qj = (t / Q) % Q, ql = DIM == 3 ? t / (Q * Q) : 0;
@@ -330,9 +329,8 @@ __global__ void __launch_bounds__((Shape<DIM, K, 0>::BLOCK))
   const int tid = threadIdx.x;
   for (int i = tid; i < TAB_SIZE; i += Sh::BLOCK) s_tab[i] = a.tab[i];
   CellCtx<DIM, K, 0, T> c;
-  c.active = tid < Sh::NT;
-  const int e = c.active ? tid / NQ : CPB - 1;
-  c.t = c.active ? tid - e * NQ : 0;
+  int e;
+  Sh::map(tid, e, c.t, c.active);
   const int cell = blockIdx.x * CPB + e;
   c.valid = c.active && cell < a.ncells;
   c.qi = c.t % Q;

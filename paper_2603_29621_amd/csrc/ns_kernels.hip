@@ -23,15 +23,42 @@ namespace mfs {
 
 namespace nsk {
 
+// one thread per quadrature point; cells that fit in a wavefront are packed
+// per wavefront and synchronise at wavefront scope (see cell_common.h)
 template <int DIM, int K>
 struct Shape {
   static constexpr int Q = K + 1;
   static constexpr int NQ = DIM == 2 ? Q * Q : Q * Q * Q;
-  static constexpr int CPB = NQ >= 256 ? 1 : 256 / NQ;
-  static constexpr int NT = CPB * NQ;
-  static constexpr int BLOCK = (NT + 63) / 64 * 64;
+  static constexpr bool WAVE = NQ <= 64;
+  static constexpr int CPW = WAVE ? 64 / NQ : 0;
+  static constexpr int CPB = WAVE ? 4 * CPW : (NQ >= 256 ? 1 : 256 / NQ);
+  static constexpr int NT = WAVE ? 256 : CPB * NQ;
+  static constexpr int BLOCK = WAVE ? 256 : (NT + 63) / 64 * 64;
   static constexpr int NV = 1 << DIM;
+  __device__ static void map(int tid, int &e, int &t, bool &active) {
+    if (WAVE) {
+      const int w = tid >> 6, l = tid & 63, sl = l / NQ;
+      active = sl < CPW;
+      e = w * CPW + (active ? sl : 0);
+      t = active ? l - sl * NQ : 0;
+    } else {
+      active = tid < NT;
+      e = active ? tid / NQ : CPB - 1;
+      t = active ? tid - e * NQ : 0;
+    }
+  }
 };
+
+template <bool WAVE>
+__device__ __forceinline__ void csync() {
+  if (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
 
 template <typename T>
 struct Args {
@@ -124,15 +151,15 @@ struct Ctx {
     const T *S = tab + TAB_S;
     T v = sweep<DIM, Q, 0, Q, false>(b0, S, qi, qj, ql);
     if (active) b1[t] = v;
-    __syncthreads();
+    csync<Shape<DIM, K>::WAVE>();
     v = sweep<DIM, Q, 1, Q, false>(b1, S, qi, qj, ql);
     if (active) b0[t] = v;
-    __syncthreads();
+    csync<Shape<DIM, K>::WAVE>();
     T *vals = b0;
     if (DIM == 3) {
       v = sweep<DIM, Q, 2, Q, false>(b0, S, qi, qj, ql);
       if (active) b1[t] = v;
-      __syncthreads();
+      csync<Shape<DIM, K>::WAVE>();
       vals = b1;
     }
     val = vals[t];
@@ -140,14 +167,14 @@ struct Ctx {
     g[0] = sweep<DIM, Q, 0, Q, false>(vals, D, qi, qj, ql);
     g[1] = sweep<DIM, Q, 1, Q, false>(vals, D, qi, qj, ql);
     g[2] = DIM == 3 ? sweep<DIM, Q, 2, Q, false>(vals, D, qi, qj, ql) : T(0);
-    __syncthreads();
+    csync<Shape<DIM, K>::WAVE>();
     if (HESS) {
       if (active) {
         b0[t] = g[0];
         b1[t] = g[1];
         if (DIM == 3) b2[t] = g[2];
       }
-      __syncthreads();
+      csync<Shape<DIM, K>::WAVE>();
       if (DIM == 2) {
         h[0] = sweep<DIM, Q, 0, Q, false>(b0, D, qi, qj, ql);
         h[1] = sweep<DIM, Q, 0, Q, false>(b1, D, qi, qj, ql);
@@ -160,7 +187,7 @@ struct Ctx {
         h[4] = sweep<DIM, Q, 1, Q, false>(b2, D, qi, qj, ql);
         h[5] = sweep<DIM, Q, 2, Q, false>(b2, D, qi, qj, ql);
       }
-      __syncthreads();
+      csync<Shape<DIM, K>::WAVE>();
     }
   }
   // test with value and reference-gradient coefficients -> nodal value
@@ -170,30 +197,30 @@ struct Ctx {
       b1[t] = f[1];
       if (DIM == 3) b2[t] = f[2];
     }
-    __syncthreads();
+    csync<Shape<DIM, K>::WAVE>();
     const T *D = tab + TAB_D;
     T r = val + sweep<DIM, Q, 0, Q, true>(b0, D, qi, qj, ql) + sweep<DIM, Q, 1, Q, true>(b1, D, qi, qj, ql);
     if (DIM == 3) r += sweep<DIM, Q, 2, Q, true>(b2, D, qi, qj, ql);
-    __syncthreads();
+    csync<Shape<DIM, K>::WAVE>();
     if (active) b0[t] = r;
-    __syncthreads();
+    csync<Shape<DIM, K>::WAVE>();
     const T *S = tab + TAB_S;
     T out;
     if (DIM == 2) {
       T v = sweep<DIM, Q, 1, Q, true>(b0, S, qi, qj, ql);
       if (active) b1[t] = v;
-      __syncthreads();
+      csync<Shape<DIM, K>::WAVE>();
       out = sweep<DIM, Q, 0, Q, true>(b1, S, qi, qj, ql);
     } else {
       T v = sweep<DIM, Q, 2, Q, true>(b0, S, qi, qj, ql);
       if (active) b1[t] = v;
-      __syncthreads();
+      csync<Shape<DIM, K>::WAVE>();
       v = sweep<DIM, Q, 1, Q, true>(b1, S, qi, qj, ql);
       if (active) b0[t] = v;
-      __syncthreads();
+      csync<Shape<DIM, K>::WAVE>();
       out = sweep<DIM, Q, 0, Q, true>(b0, S, qi, qj, ql);
     }
-    __syncthreads();
+    csync<Shape<DIM, K>::WAVE>();
     return out;
   }
 };
@@ -230,9 +257,8 @@ __device__ __forceinline__ T laplacian(const T h[6], const T I[3][3]) {
   const int tid = threadIdx.x;                                                                         \
   for (int i = tid; i < TAB_SIZE; i += Sh::BLOCK) s_tab[i] = a.tab[i];                                 \
   Ctx<DIM, K, T> c;                                                                                    \
-  c.active = tid < Sh::NT;                                                                             \
-  const int e = c.active ? tid / NQ : CPB - 1;                                                         \
-  c.t = c.active ? tid - e * NQ : 0;                                                                   \
+  int e;                                                                                               \
+  Sh::map(tid, e, c.t, c.active);                                                                      \
   const int cell = blockIdx.x * CPB + e;                                                               \
   c.valid = c.active && cell < a.ncells;                                                               \
   c.qi = c.t % Q;                                                                                      \
@@ -275,7 +301,7 @@ __global__ void __launch_bounds__((Shape<DIM, K>::BLOCK)) ns_linearize_kernel(Ar
   T u[3] = {}, U[3][3] = {}, lap[3] = {};
   for (int comp = 0; comp < DIM; ++comp) {
     if (c.active) c.b0[c.t] = c.valid ? a.src[comp * a.Nv + nd] : T(0);
-    __syncthreads();
+    csync<Sh::WAVE>();
     T val, g[3], h[6];
     c.template evaluate<true>(val, g, h);
     u[comp] = val;
@@ -288,9 +314,9 @@ __global__ void __launch_bounds__((Shape<DIM, K>::BLOCK)) ns_linearize_kernel(Ar
   }
   // cell volume
   if (c.active && c.t == 0) s_vol[e] = 0;
-  __syncthreads();
+  csync<Sh::WAVE>();
   if (c.valid) atomicAdd(&s_vol[e], JxW);
-  __syncthreads();
+  csync<Sh::WAVE>();
   const T hK = pow(s_vol[e], T(1) / T(DIM)) / T(K);
   T speed2 = 0, R0[3];
   for (int comp = 0; comp < DIM; ++comp) {
@@ -330,7 +356,7 @@ __global__ void __launch_bounds__((Shape<DIM, K>::BLOCK)) ns_jacobian_kernel(Arg
   T w[3] = {}, G[3][3] = {}, L[3] = {};
   for (int comp = 0; comp < DIM; ++comp) {
     if (c.active) c.b0[c.t] = (c.valid && !dir) ? a.src[comp * a.Nv + nd] : T(0);
-    __syncthreads();
+    csync<Sh::WAVE>();
     T val, g[3], h[6];
     c.template evaluate<true>(val, g, h);
     w[comp] = val;
@@ -344,7 +370,7 @@ __global__ void __launch_bounds__((Shape<DIM, K>::BLOCK)) ns_jacobian_kernel(Arg
   T P, gP[3] = {};
   {
     if (c.active) c.b0[c.t] = c.valid ? a.src[DIM * a.Nv + nd] : T(0);
-    __syncthreads();
+    csync<Sh::WAVE>();
     T g[3], h[6];
     c.template evaluate<false>(P, g, h);
     for (int x = 0; x < DIM; ++x) {

@@ -184,18 +184,30 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) st
     const int gx = gx0 + lx;
     const bool xin = tid < (NT / VX) * VX && gx < a.nv0;
     const bool xdir = gx == 0 || gx == a.nv0 - 1;
-    // rows (c, lz, ly) in steps of NT / VX
-    for (int row = tid / VX; row < 3 * VZ * VY; row += NT / VX) {
+    // rows (c, lz, ly) in steps of NT / VX: every global load of the thread
+    // is issued before the first LDS store, so their latencies overlap
+    constexpr int RSTEP = NT / VX, NROW = 3 * VZ * VY, NIT = (NROW + RSTEP - 1) / RSTEP;
+    T vv[NIT];
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      const int row = tid / VX + it * RSTEP;
       const int c = row / (VZ * VY), rr = row - c * (VZ * VY);
       const int lz = rr / VY, ly = rr - lz * VY;
       const int gy = gy0 + ly, gz = gz0 + lz;
       T v = 0;
-      if (xin && gy < a.nv1 && gz < a.nv2) {
+      if (row < NROW && xin && gy < a.nv1 && gz < a.nv2) {
         const bool dir = xdir || gy == 0 || gz == 0 || gy == a.nv1 - 1 || gz == a.nv2 - 1;
         if (!dir) v = a.src_u[c * a.Nv + gx + (int64_t)a.nv0 * (gy + (int64_t)a.nv1 * gz)];
       }
-      if (tid < (NT / VX) * VX) {
-        sU[c * NVB + xpos(lx) + RX * ly + RXY * lz] = v;
+      vv[it] = v;
+    }
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      const int row = tid / VX + it * RSTEP;
+      const int c = row / (VZ * VY), rr = row - c * (VZ * VY);
+      const int lz = rr / VY, ly = rr - lz * VY;
+      if (row < NROW && tid < RSTEP * VX) {
+        sU[c * NVB + xpos(lx) + RX * ly + RXY * lz] = vv[it];
         sO[c * NVB + xpos(lx) + RX * ly + RXY * lz] = 0;
       }
     }
