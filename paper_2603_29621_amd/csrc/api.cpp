@@ -115,6 +115,10 @@ struct HpDevSpace {
   int64_t *tptr = nullptr, *tev = nullptr;
   int *tnb = nullptr;
   double *tval = nullptr;
+  // unknowns whose transposed list is longer than HP_SCATTER_LIGHT (summed
+  // by a wave each instead of a thread)
+  int64_t nheavy = 0;
+  int64_t *heavy = nullptr;
   uint8_t *dir = nullptr;
   int64_t *owner_ev = nullptr;
   int *owner_nb = nullptr;
@@ -1050,6 +1054,11 @@ template <typename T>
 void hp_gather_space(const HpDevSpace &d, int ncomp, const T *x, T *ev, hipStream_t s) {
   hp_gather<T>(d.nrows, ncomp, d.row_ptr, d.col, d.val, d.row_ev, d.row_nb, x, d.N, ev, s);
 }
+template <typename T>
+void hp_scatter_space(const HpDevSpace &d, int ncomp, bool use_dir, const T *ev, const T *src, T *dst, hipStream_t s) {
+  hp_scatter<T>(d.N, ncomp, d.tptr, d.tev, d.tnb, d.tval, use_dir ? d.dir : nullptr, d.nheavy, d.heavy, ev, src, dst,
+                s);
+}
 
 // dst = op(src) on hp level l: mode of the cell kernels; velocity output
 // Dirichlet rows = src_u (A, Stokes) or 0 (B)
@@ -1076,11 +1085,8 @@ void hp_apply(mfs_problem &P, int l, int mode, T *dst_u, T *dst_p, const T *src_
     launch_cell_op_ev<T>(S0.g, L.class_k[c], dev<T>(S0).X, hp_tab<T>(H, L.class_k[c]), mode, (T)P.nu, ev, s);
   }
   if (out_u)
-    hp_scatter<T>(L.vd.N, 3, L.vd.tptr, L.vd.tev, L.vd.tnb, L.vd.tval, L.vd.dir, V.ev_out,
-                  (mode & M_LAPLACE) ? src_u : nullptr, dst_u, s);
-  if (out_p)
-    hp_scatter<T>(H.pd.N, 1, H.pd.tptr, H.pd.tev, H.pd.tnb, H.pd.tval, nullptr, hp_evp<T>(H, true), nullptr, dst_p,
-                  s);
+    hp_scatter_space<T>(L.vd, 3, true, V.ev_out, (mode & M_LAPLACE) ? src_u : nullptr, dst_u, s);
+  if (out_p) hp_scatter_space<T>(H.pd, 1, false, hp_evp<T>(H, true), nullptr, dst_p, s);
 }
 
 template <typename T>
@@ -1123,12 +1129,12 @@ void hp_restrict(mfs_problem &P, int l, T *bc, const T *rf, hipStream_t s) {
     HpLevel &C = H.lev[l + 1];
     T *evc = hpv<T>(C).ev_in;
     hp_embed<T>(H.ncells, 3, F.deg, C.deg, H.embed, F.off_u, C.off_u, evf, evc, true, s);
-    hp_scatter<T>(C.vd.N, 3, C.vd.tptr, C.vd.tev, C.vd.tnb, C.vd.tval, C.vd.dir, evc, nullptr, bc, s);
+    hp_scatter_space<T>(C.vd, 3, true, evc, nullptr, bc, s);
   } else {
     T *tmp = std::is_same<T, double>::value ? (T *)H.tmp2_64 : (T *)H.tmp2_32;
     T *evc = std::is_same<T, double>::value ? (T *)H.ev2_64 : (T *)H.ev2_32;
     hp_embed<T>(H.ncells, 3, F.deg, H.deg2, H.embed, F.off_u, H.off_u2, evf, evc, true, s);
-    hp_scatter<T>(H.v2d.N, 3, H.v2d.tptr, H.v2d.tev, H.v2d.tnb, H.v2d.tval, H.v2d.dir, evc, nullptr, tmp, s);
+    hp_scatter_space<T>(H.v2d, 3, true, evc, nullptr, tmp, s);
     permute<T>(H.v2d.N, 3, H.perm2, tmp, H.v2d.N, bc, P.L[0].g.Nv, true, s);
   }
 }
@@ -1629,6 +1635,9 @@ void hp_upload(HpData &H, const HpSpaceHost &V, bool constrained, const std::vec
       tnb[o] = rnb[r];
       tval[o] = val[q];
     }
+  std::vector<int64_t> heavy;
+  for (int64_t g = 0; g < V.N; ++g)
+    if (tcount[g + 1] - tcount[g] > HP_SCATTER_LIGHT) heavy.push_back(g);
   std::vector<int64_t> oev(V.N);
   std::vector<int> onb(V.N);
   for (int64_t g = 0; g < V.N; ++g) {
@@ -1645,6 +1654,8 @@ void hp_upload(HpData &H, const HpSpaceHost &V, bool constrained, const std::vec
   d.tev = H.upload(tev, s);
   d.tnb = H.upload(tnb, s);
   d.tval = H.upload(tval, s);
+  d.nheavy = (int64_t)heavy.size();
+  d.heavy = heavy.empty() ? nullptr : H.upload(heavy, s);
   d.owner_ev = H.upload(oev, s);
   d.owner_nb = H.upload(onb, s);
   d.dir = constrained ? H.upload(V.dirichlet, s) : nullptr;

@@ -50,6 +50,15 @@ __device__ __forceinline__ void csync() {
   }
 }
 
+// Materialise a value in a register at this point of the program.  Values
+// swept out of LDS are needed only after later sweeps; without this the
+// compiler keeps the loaded operands live until the use instead of the one
+// result (tens of extra registers per sweep, lower occupancy).
+template <typename T>
+__device__ __forceinline__ void pin(T &v) {
+  asm volatile("" : "+v"(v));
+}
+
 // out = sum_m mat(r, m) in[.. m ..] along direction DIR; TR reads mat(m, r).
 template <int DIM, int Q, int DIR, int C, bool TR, typename T>
 __device__ __forceinline__ T sweep(const T *in, const T *mat, int qi, int qj, int ql) {
@@ -221,6 +230,9 @@ struct CellCtx {
     g[0] = sweep<DIM, Q, 0, Q, false>(vals, D, qi, qj, ql);
     g[1] = sweep<DIM, Q, 1, Q, false>(vals, D, qi, qj, ql);
     if (DIM == 3) g[2] = sweep<DIM, Q, 2, Q, false>(vals, D, qi, qj, ql);
+    pin(g[0]);
+    pin(g[1]);
+    if (DIM == 3) pin(g[2]);
     csync<Sh::WAVE>();
   }
 

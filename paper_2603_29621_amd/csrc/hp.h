@@ -63,9 +63,14 @@ struct HpTransposed {
 
 // ---------------------------------------------------------------- device kernels (hp_kernels.hip)
 // dst[comp*Nu + i] = dirichlet[i] ? (src ? src[..] : 0) : sum_r w_r ev[tev_r + comp*tnb_r]
+// Lists of up to HP_SCATTER_LIGHT entries are summed by one thread each; the
+// unknowns in heavy[0..nheavy) (exactly those with longer lists and no
+// Dirichlet flag) by one wave each, in a fixed order.
+constexpr int HP_SCATTER_LIGHT = 16;
 template <typename T>
 void hp_scatter(int64_t N, int ncomp, const int64_t *tptr, const int64_t *tev, const int *tnb, const double *tval,
-                const uint8_t *dirichlet, const T *ev, const T *src, T *dst, hipStream_t s);
+                const uint8_t *dirichlet, int64_t nheavy, const int64_t *heavy, const T *ev, const T *src, T *dst,
+                hipStream_t s);
 // E-vector gather: ev[row_ev[r] + comp*row_nb[r]] = sum_j val_j x[comp*N + col_j]
 // over the rows r of the local->global map, comp < ncomp
 template <typename T>

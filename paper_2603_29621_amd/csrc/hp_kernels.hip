@@ -41,15 +41,45 @@ __global__ void k_scatter(int64_t N, const int64_t *tptr, const int64_t *tev, co
       for (int comp = 0; comp < NC; ++comp) dst[comp * N + i] = src ? src[comp * N + i] : T(0);
       continue;
     }
+    const int64_t b = tptr[i], e = tptr[i + 1];
+    if (e - b > HP_SCATTER_LIGHT) continue;  // summed by k_scatter_heavy
     double s[NC] = {};
-    for (int64_t j = tptr[i]; j < tptr[i + 1]; ++j) {
+    for (int64_t j = b; j < e; ++j) {
       const double w = tval[j];
-      const int64_t e = tev[j], nb = tnb[j];
+      const int64_t o = tev[j], nb = tnb[j];
 #pragma unroll
-      for (int comp = 0; comp < NC; ++comp) s[comp] += w * (double)ev[e + comp * nb];
+      for (int comp = 0; comp < NC; ++comp) s[comp] += w * (double)ev[o + comp * nb];
     }
 #pragma unroll
     for (int comp = 0; comp < NC; ++comp) dst[comp * N + i] = (T)s[comp];
+  }
+}
+
+// one wave per long list: strided partial sums over the lanes, then a
+// butterfly over the wave (the same order on every call)
+template <typename T, int NC>
+__global__ void __launch_bounds__(HB) k_scatter_heavy(int64_t N, int64_t nheavy, const int64_t *heavy,
+                                                      const int64_t *tptr, const int64_t *tev, const int *tnb,
+                                                      const double *tval, const T *ev, T *dst) {
+  const int lane = threadIdx.x & 63;
+  const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t h = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6; h < nheavy; h += waves) {
+    const int64_t i = heavy[h];
+    const int64_t b = tptr[i], e = tptr[i + 1];
+    double s[NC] = {};
+    for (int64_t j = b + lane; j < e; j += 64) {
+      const double w = tval[j];
+      const int64_t o = tev[j], nb = tnb[j];
+#pragma unroll
+      for (int comp = 0; comp < NC; ++comp) s[comp] += w * (double)ev[o + comp * nb];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+      for (int comp = 0; comp < NC; ++comp) s[comp] += __shfl_xor(s[comp], off, 64);
+    if (lane == 0)
+#pragma unroll
+      for (int comp = 0; comp < NC; ++comp) dst[comp * N + i] = (T)s[comp];
   }
 }
 
@@ -199,14 +229,23 @@ void hp_gather(int64_t nrows, int ncomp, const int64_t *row_ptr, const int *col,
 
 template <typename T>
 void hp_scatter(int64_t N, int ncomp, const int64_t *tptr, const int64_t *tev, const int *tnb, const double *tval,
-                const uint8_t *dirichlet, const T *ev, const T *src, T *dst, hipStream_t s) {
+                const uint8_t *dirichlet, int64_t nheavy, const int64_t *heavy, const T *ev, const T *src, T *dst,
+                hipStream_t s) {
   if (N == 0) return;
-  if (ncomp == 3)
+  const unsigned hgrid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((nheavy + HB / 64 - 1) / (HB / 64), 65535 * 8));
+  if (ncomp == 3) {
     hipLaunchKernelGGL((k_scatter<T, 3>), dim3(grid_for(N)), dim3(HB), 0, s, N, tptr, tev, tnb, tval, dirichlet, ev,
                        src, dst);
-  else
+    if (nheavy > 0)
+      hipLaunchKernelGGL((k_scatter_heavy<T, 3>), dim3(hgrid), dim3(HB), 0, s, N, nheavy, heavy, tptr, tev, tnb, tval,
+                         ev, dst);
+  } else {
     hipLaunchKernelGGL((k_scatter<T, 1>), dim3(grid_for(N)), dim3(HB), 0, s, N, tptr, tev, tnb, tval, dirichlet, ev,
                        src, dst);
+    if (nheavy > 0)
+      hipLaunchKernelGGL((k_scatter_heavy<T, 1>), dim3(hgrid), dim3(HB), 0, s, N, nheavy, heavy, tptr, tev, tnb, tval,
+                         ev, dst);
+  }
   MFS_HIP(hipGetLastError());
 }
 
@@ -275,7 +314,7 @@ void colour_extract(const int *colour, int64_t N, const int cols[3], const doubl
   template void hp_gather<T>(int64_t, int, const int64_t *, const int *, const double *, const int64_t *,           \
                              const int *, const T *, int64_t, T *, hipStream_t);                                     \
   template void hp_scatter<T>(int64_t, int, const int64_t *, const int64_t *, const int *, const double *,          \
-                              const uint8_t *, const T *, const T *, T *, hipStream_t);                              \
+                              const uint8_t *, int64_t, const int64_t *, const T *, const T *, T *, hipStream_t);    \
   template void hp_embed<T>(int64_t, int, const int *, const int *, const double *, const int64_t *,                \
                             const int64_t *, const T *, T *, bool, hipStream_t);                                     \
   template void hp_inject<T>(int64_t, int, const int64_t *, const int *, const T *, T *, bool, hipStream_t);        \

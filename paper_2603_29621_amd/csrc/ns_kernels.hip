@@ -17,48 +17,16 @@
 // [cell][field][point] so the threads of a cell read consecutive words.
 #include <algorithm>
 
-#include "internal.h"
+#include "cell_common.h"
 
 namespace mfs {
 
 namespace nsk {
 
-// one thread per quadrature point; cells that fit in a wavefront are packed
-// per wavefront and synchronise at wavefront scope (see cell_common.h)
+// one thread per quadrature point, laid out as the cell kernels' (velocity and
+// pressure share the degree here)
 template <int DIM, int K>
-struct Shape {
-  static constexpr int Q = K + 1;
-  static constexpr int NQ = DIM == 2 ? Q * Q : Q * Q * Q;
-  static constexpr bool WAVE = NQ <= 64;
-  static constexpr int CPW = WAVE ? 64 / NQ : 0;
-  static constexpr int CPB = WAVE ? 4 * CPW : (NQ >= 256 ? 1 : 256 / NQ);
-  static constexpr int NT = WAVE ? 256 : CPB * NQ;
-  static constexpr int BLOCK = WAVE ? 256 : (NT + 63) / 64 * 64;
-  static constexpr int NV = 1 << DIM;
-  __device__ static void map(int tid, int &e, int &t, bool &active) {
-    if (WAVE) {
-      const int w = tid >> 6, l = tid & 63, sl = l / NQ;
-      active = sl < CPW;
-      e = w * CPW + (active ? sl : 0);
-      t = active ? l - sl * NQ : 0;
-    } else {
-      active = tid < NT;
-      e = active ? tid / NQ : CPB - 1;
-      t = active ? tid - e * NQ : 0;
-    }
-  }
-};
-
-template <bool WAVE>
-__device__ __forceinline__ void csync() {
-  if (WAVE) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  } else {
-    __syncthreads();
-  }
-}
+using Shape = mfs::Shape<DIM, K, K>;
 
 template <typename T>
 struct Args {
@@ -71,17 +39,6 @@ struct Args {
   T nu, alpha, dt;
   int newton;
 };
-
-template <int DIM, int Q, int DIR, int C, bool TR, typename T>
-__device__ __forceinline__ T sweep(const T *in, const T *mat, int qi, int qj, int ql) {
-  const int r = DIR == 0 ? qi : (DIR == 1 ? qj : ql);
-  const int base = DIR == 0 ? Q * (qj + Q * ql) : (DIR == 1 ? qi + Q * Q * ql : qi + Q * qj);
-  constexpr int stride = DIR == 0 ? 1 : (DIR == 1 ? Q : Q * Q);
-  T s = 0;
-#pragma unroll
-  for (int m = 0; m < C; ++m) s += (TR ? mat[m * MAXQ + r] : mat[r * MAXQ + m]) * in[base + m * stride];
-  return s;
-}
 
 template <int DIM, typename T>
 __device__ __forceinline__ T jac_inv(const T *Xc, const T xi[3], T I[3][3]) {
@@ -167,6 +124,10 @@ struct Ctx {
     g[0] = sweep<DIM, Q, 0, Q, false>(vals, D, qi, qj, ql);
     g[1] = sweep<DIM, Q, 1, Q, false>(vals, D, qi, qj, ql);
     g[2] = DIM == 3 ? sweep<DIM, Q, 2, Q, false>(vals, D, qi, qj, ql) : T(0);
+    pin(val);
+    pin(g[0]);
+    pin(g[1]);
+    pin(g[2]);
     csync<Shape<DIM, K>::WAVE>();
     if (HESS) {
       if (active) {
@@ -187,6 +148,8 @@ struct Ctx {
         h[4] = sweep<DIM, Q, 1, Q, false>(b2, D, qi, qj, ql);
         h[5] = sweep<DIM, Q, 2, Q, false>(b2, D, qi, qj, ql);
       }
+#pragma unroll
+      for (int i = 0; i < (DIM == 2 ? 3 : 6); ++i) pin(h[i]);
       csync<Shape<DIM, K>::WAVE>();
     }
   }
