@@ -145,6 +145,60 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+# Space dimension of every live handle made here, so that vector arguments can
+# be checked against the lengths the library will read and write (the C ABI
+# takes bare pointers and cannot).
+_dims: dict = {}
+
+
+def _word(prec):
+    import torch
+
+    return torch.float64 if prec == MFS_FP64 else torch.float32
+
+
+def _arg(t, n, dtype, what):
+    """Pointer of a device tensor that holds at least n elements of dtype."""
+    if t is None:
+        raise ValueError(f"{what}: a device tensor is required")
+    if t.dtype != dtype:
+        raise ValueError(f"{what}: dtype {t.dtype}, the call needs {dtype}")
+    if n is not None and t.numel() < n:
+        raise ValueError(f"{what}: {t.numel()} elements, the call needs {n}")
+    return _ptr(t)
+
+
+def _sizes(h, level):
+    """(dim, n_u, n_p, navier_stokes) of a level, dim None for foreign handles."""
+    nu, np_ = mfs_n_dofs(h, level)
+    nu0, np0 = (nu, np_) if level == 0 else mfs_n_dofs(h, 0)
+    return _dims.get(h.value), nu, np_, np0 == nu0
+
+
+def _vec_len(h, level, full):
+    dim, nu, np_, ns = _sizes(h, level)
+    if dim is None:
+        return None
+    return dim * nu + np_ if (full or ns) else dim * nu
+
+
+def _op_len(h, op, level):
+    dim, nu, np_, ns = _sizes(h, level)
+    if dim is None:
+        return None, None
+    vel, full = dim * nu, dim * nu + np_
+    return {MFS_OP_STOKES: (full, full), MFS_OP_NS_JACOBIAN: (full, full), MFS_OP_A: (vel, vel),
+            MFS_OP_B: (vel, np_), MFS_OP_BT: (np_, vel), MFS_OP_MASS_P: (np_, np_)}.get(op, (None, None))
+
+
+def _qp_len(h):
+    dim = _dims.get(h.value)
+    if dim is None:
+        return None
+    k, n = mfs_level_info(h, 0)
+    return int(np.prod(n[:dim])) * (k + 1) ** dim * dim
+
+
 def mfs_default_options(**overrides) -> mfs_options:
     o = mfs_options()
     lib().mfs_default_options(ctypes.byref(o))
@@ -176,6 +230,7 @@ def mfs_setup(dim, n, vertices, k, nu, opts=None, stream=None) -> ctypes.c_void_
     h = ctypes.c_void_p(0)
     _check(lib().mfs_setup(ctypes.byref(m), int(k), float(nu), ctypes.byref(opts) if opts else None,
                            _stream(stream), ctypes.byref(h)))
+    _dims[h.value] = int(dim)
     return h
 
 
@@ -186,10 +241,12 @@ def mfs_setup_hp(n, vertices, cell_degree, nu, opts=None, stream=None) -> ctypes
     h = ctypes.c_void_p(0)
     _check(lib().mfs_setup_hp(ctypes.byref(m), deg.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), float(nu),
                               ctypes.byref(opts) if opts else None, _stream(stream), ctypes.byref(h)))
+    _dims[h.value] = 3
     return h
 
 
 def mfs_destroy(h):
+    _dims.pop(getattr(h, "value", None), None)
     _check(lib().mfs_destroy(h))
 
 
@@ -225,15 +282,23 @@ def mfs_quadrature_points(h, n_cells, n_q, dim):
 
 
 def mfs_quadrature_points_device(h, dst, stream=None):
-    _check(lib().mfs_quadrature_points_device(h, _ptr(dst), _stream(stream)))
+    import torch
+
+    _check(lib().mfs_quadrature_points_device(h, _arg(dst, _qp_len(h), torch.float64, "dst"), _stream(stream)))
 
 
 def mfs_vmult(h, op, prec, level, dst, src, stream=None):
-    _check(lib().mfs_vmult(h, op, prec, level, _ptr(dst), _ptr(src), _stream(stream)))
+    nd, ns_ = _op_len(h, op, level)
+    _check(lib().mfs_vmult(h, op, prec, level, _arg(dst, nd, _word(prec), "dst"), _arg(src, ns_, _word(prec), "src"),
+                           _stream(stream)))
 
 
 def mfs_diagonal(h, level, dst, stream=None):
-    _check(lib().mfs_diagonal(h, level, _ptr(dst), _stream(stream)))
+    import torch
+
+    dim, nu, _, ns = _sizes(h, level)
+    n = None if dim is None else ((dim + 1) * nu if ns else nu)
+    _check(lib().mfs_diagonal(h, level, _arg(dst, n, torch.float64, "dst"), _stream(stream)))
 
 
 def mfs_get_lambda(h, level):
@@ -247,36 +312,55 @@ def mfs_set_lambda(h, level, value):
 
 
 def mfs_vcycle(h, prec, dst, src, stream=None):
-    _check(lib().mfs_vcycle(h, prec, _ptr(dst), _ptr(src), _stream(stream)))
+    n = _vec_len(h, 0, False)
+    _check(lib().mfs_vcycle(h, prec, _arg(dst, n, _word(prec), "dst"), _arg(src, n, _word(prec), "src"),
+                            _stream(stream)))
 
 
 def mfs_prolongate_add(h, prec, fine, dst, src, stream=None):
-    _check(lib().mfs_prolongate_add(h, prec, fine, _ptr(dst), _ptr(src), _stream(stream)))
+    nf, nc = _vec_len(h, fine, False), _vec_len(h, fine + 1, False)
+    _check(lib().mfs_prolongate_add(h, prec, fine, _arg(dst, nf, _word(prec), "dst"), _arg(src, nc, _word(prec), "src"),
+                                    _stream(stream)))
 
 
 def mfs_restrict(h, prec, fine, dst, src, stream=None):
-    _check(lib().mfs_restrict(h, prec, fine, _ptr(dst), _ptr(src), _stream(stream)))
+    nf, nc = _vec_len(h, fine, False), _vec_len(h, fine + 1, False)
+    _check(lib().mfs_restrict(h, prec, fine, _arg(dst, nc, _word(prec), "dst"), _arg(src, nf, _word(prec), "src"),
+                              _stream(stream)))
 
 
 def mfs_precondition(h, prec, dst, src, stream=None):
-    _check(lib().mfs_precondition(h, prec, _ptr(dst), _ptr(src), _stream(stream)))
+    n = _vec_len(h, 0, True)
+    _check(lib().mfs_precondition(h, prec, _arg(dst, n, _word(prec), "dst"), _arg(src, n, _word(prec), "src"),
+                                  _stream(stream)))
 
 
 def mfs_rhs(h, f_qp, u_dirichlet, b, stream=None):
-    _check(lib().mfs_rhs(h, _ptr(f_qp), _ptr(u_dirichlet), _ptr(b), _stream(stream)))
+    import torch
+
+    f64 = torch.float64
+    _check(lib().mfs_rhs(h, _arg(f_qp, _qp_len(h), f64, "f_qp"), _arg(u_dirichlet, _vec_len(h, 0, False), f64, "u_dirichlet"),
+                         _arg(b, _vec_len(h, 0, True), f64, "b"), _stream(stream)))
 
 
 def mfs_solve(h, b, x, opts=None, stream=None) -> mfs_solve_info:
     info = mfs_solve_info()
-    rc = lib().mfs_solve(h, _ptr(b), _ptr(x), ctypes.byref(opts) if opts else None, ctypes.byref(info),
-                         _stream(stream))
+    import torch
+
+    n = _vec_len(h, 0, True)
+    rc = lib().mfs_solve(h, _arg(b, n, torch.float64, "b"), _arg(x, n, torch.float64, "x"),
+                         ctypes.byref(opts) if opts else None, ctypes.byref(info), _stream(stream))
     if rc not in (MFS_OK, MFS_ENOCONV):
         _check(rc)
     return info
 
 
 def mfs_solve_begin(h, b, x, opts=None, stream=None):
-    _check(lib().mfs_solve_begin(h, _ptr(b), _ptr(x), ctypes.byref(opts) if opts else None, _stream(stream)))
+    import torch
+
+    n = _vec_len(h, 0, True)
+    _check(lib().mfs_solve_begin(h, _arg(b, n, torch.float64, "b"), _arg(x, n, torch.float64, "x"),
+                                 ctypes.byref(opts) if opts else None, _stream(stream)))
 
 
 def mfs_solve_advance(h):
@@ -287,7 +371,11 @@ def mfs_solve_advance(h):
 
 
 def mfs_set_linearization(h, u0, dt, newton, stream=None):
-    _check(lib().mfs_set_linearization(h, _ptr(u0), float(dt), int(newton), _stream(stream)))
+    import torch
+
+    dim, nu, _, _ = _sizes(h, 0)
+    n = None if dim is None else dim * nu
+    _check(lib().mfs_set_linearization(h, _arg(u0, n, torch.float64, "u0"), float(dt), int(newton), _stream(stream)))
 
 
 @dataclass

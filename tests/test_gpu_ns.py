@@ -212,8 +212,9 @@ def test_ns_errors():
             mfs.mfs_vmult(h, mfs.MFS_OP_NS_JACOBIAN, mfs.MFS_FP64, 0, y, torch.ones_like(y))
         with pytest.raises(mfs.MfsError):
             mfs.mfs_set_linearization(h, torch.zeros(2 * 81, dtype=torch.float64, device="cuda"), 0.0, 1)
+        f_qp = torch.zeros(16 * 9 * 2, dtype=torch.float64, device="cuda")
         with pytest.raises(mfs.MfsError) as e:
-            mfs.mfs_rhs(h, y, y, y)
+            mfs.mfs_rhs(h, f_qp, y, y)
         assert e.value.code == mfs.MFS_EUNSUPPORTED
     finally:
         mfs.mfs_destroy(h)

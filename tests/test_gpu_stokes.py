@@ -171,6 +171,35 @@ def test_inverted_cell_rejected():
     assert e.value.code == mfs.MFS_EINVAL and "cell" in str(e.value)
 
 
+def test_binding_rejects_short_or_mistyped_vectors():
+    """The binding checks every vector against the length and word the call
+    reads and writes, before anything is enqueued."""
+    dim, n, k = 3, [2, 2, 2], 2
+    X = inputs.structured_vertices(dim, n)
+    h = mfs.mfs_setup(dim, n, X, k, 1.0, mfs.mfs_default_options(mg_levels=0))
+    try:
+        nu, np_ = mfs.mfs_n_dofs(h, 0)
+        N = dim * nu + np_
+        ok = torch.zeros(N, dtype=torch.float64, device="cuda")
+        short = torch.zeros(N - 1, dtype=torch.float64, device="cuda")
+        with pytest.raises(ValueError, match="needs"):
+            mfs.mfs_vmult(h, mfs.MFS_OP_STOKES, mfs.MFS_FP64, 0, short, ok)
+        with pytest.raises(ValueError, match="needs"):
+            mfs.mfs_vmult(h, mfs.MFS_OP_STOKES, mfs.MFS_FP64, 0, ok, short)
+        with pytest.raises(ValueError, match="dtype"):
+            mfs.mfs_vmult(h, mfs.MFS_OP_STOKES, mfs.MFS_FP32, 0, ok, ok)
+        with pytest.raises(ValueError, match="needs"):
+            mfs.mfs_vmult(h, mfs.MFS_OP_A, mfs.MFS_FP64, 0, ok[: dim * nu - 1], ok)
+        with pytest.raises(ValueError, match="needs"):
+            mfs.mfs_solve(h, ok, short)
+        # exact lengths pass
+        mfs.mfs_vmult(h, mfs.MFS_OP_BT, mfs.MFS_FP64, 0, torch.zeros(np_, dtype=torch.float64, device="cuda"),
+                      ok[: dim * nu])
+        torch.cuda.synchronize()
+    finally:
+        mfs.mfs_destroy(h)
+
+
 # ------------------------------------------------------------------ multigrid
 MG_CASES = [(2, [8, 8], 2, 0.2), (2, [4, 6], 3, 0.1), (3, [4, 4, 4], 2, 0.2), (3, [2, 2, 4], 3, 0.2)]
 
