@@ -179,36 +179,34 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) st
   const int tid = threadIdx.x;
 
   // ---- load the brick (velocity nodal values, pressure, vertices); clear outputs
+  // Thread -> node (lx, ly) of a z-plane of the brick, planes (c, lz) in turn:
+  // the node offsets are per-thread constants and the plane offsets uniform,
+  // and every global load is issued before the first LDS store.
+  constexpr int PLANE = VX * VY;  // 153 <= NT
+  const bool pl_on = tid < PLANE;
+  const int plx = tid % VX, ply = tid / VX;
+  const int pgx = gx0 + plx, pgy = gy0 + ply;
+  const bool xy_in = pl_on && pgx < a.nv0 && pgy < a.nv1;
+  const bool xy_dir = pgx == 0 || pgy == 0 || pgx == a.nv0 - 1 || pgy == a.nv1 - 1;
+  const int64_t xy_off = pgx + (int64_t)a.nv0 * pgy;
+  const int lds_xy = xpos(plx) + RX * ply;
+  const int64_t zstride = (int64_t)a.nv0 * a.nv1;
   {
-    const int lx = tid % VX;
-    const int gx = gx0 + lx;
-    const bool xin = tid < (NT / VX) * VX && gx < a.nv0;
-    const bool xdir = gx == 0 || gx == a.nv0 - 1;
-    // rows (c, lz, ly) in steps of NT / VX: every global load of the thread
-    // is issued before the first LDS store, so their latencies overlap
-    constexpr int RSTEP = NT / VX, NROW = 3 * VZ * VY, NIT = (NROW + RSTEP - 1) / RSTEP;
-    T vv[NIT];
+    T vv[3 * VZ];
 #pragma unroll
-    for (int it = 0; it < NIT; ++it) {
-      const int row = tid / VX + it * RSTEP;
-      const int c = row / (VZ * VY), rr = row - c * (VZ * VY);
-      const int lz = rr / VY, ly = rr - lz * VY;
-      const int gy = gy0 + ly, gz = gz0 + lz;
+    for (int pl = 0; pl < 3 * VZ; ++pl) {
+      const int c = pl / VZ, lz = pl % VZ;
+      const int gz = gz0 + lz;
       T v = 0;
-      if (row < NROW && xin && gy < a.nv1 && gz < a.nv2) {
-        const bool dir = xdir || gy == 0 || gz == 0 || gy == a.nv1 - 1 || gz == a.nv2 - 1;
-        if (!dir) v = a.src_u[c * a.Nv + gx + (int64_t)a.nv0 * (gy + (int64_t)a.nv1 * gz)];
-      }
-      vv[it] = v;
+      if (xy_in && !xy_dir && gz > 0 && gz < a.nv2 - 1) v = a.src_u[c * a.Nv + zstride * gz + xy_off];
+      vv[pl] = v;
     }
 #pragma unroll
-    for (int it = 0; it < NIT; ++it) {
-      const int row = tid / VX + it * RSTEP;
-      const int c = row / (VZ * VY), rr = row - c * (VZ * VY);
-      const int lz = rr / VY, ly = rr - lz * VY;
-      if (row < NROW && tid < RSTEP * VX) {
-        sU[c * NVB + xpos(lx) + RX * ly + RXY * lz] = vv[it];
-        sO[c * NVB + xpos(lx) + RX * ly + RXY * lz] = 0;
+    for (int pl = 0; pl < 3 * VZ; ++pl) {
+      const int c = pl / VZ, lz = pl % VZ;
+      if (pl_on) {
+        sU[c * NVB + RXY * lz + lds_xy] = vv[pl];
+        sO[c * NVB + RXY * lz + lds_xy] = 0;
       }
     }
   }
@@ -437,20 +435,20 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) st
   // brick's slot of the face buffer (summed by the combine kernel)
   T *fb = a.face + (int64_t)b * FACE_PER_BRICK;
   {
-    const int lx = tid % VX;
-    const int gx = gx0 + lx;
-    const bool xok = tid < (NT / VX) * VX && gx > 0 && gx < a.nv0 - 1;
-    const bool xin = lx > 0 && lx < VX - 1;
-    for (int row = tid / VX; row < 3 * VZ * VY; row += NT / VX) {
-      const int cc = row / (VZ * VY), rr = row - cc * (VZ * VY);
-      const int lz = rr / VY, ly = rr - lz * VY;
-      const int gy = gy0 + ly, gz = gz0 + lz;
-      if (!xok || gy == 0 || gz == 0 || gy >= a.nv1 - 1 || gz >= a.nv2 - 1) continue;
-      const T v = sO[cc * NVB + xpos(lx) + RX * ly + RXY * lz];
-      if (xin && ly > 0 && ly < VY - 1 && lz > 0 && lz < VZ - 1)
-        a.dst_u[cc * a.Nv + gx + (int64_t)a.nv0 * (gy + (int64_t)a.nv1 * gz)] = v;
+    // same plane mapping as the load; Dirichlet rows and nodes outside the
+    // mesh are left to the combine kernel
+    const bool st_ok = pl_on && pgx > 0 && pgx < a.nv0 - 1 && pgy > 0 && pgy < a.nv1 - 1;
+    const bool xy_int = plx > 0 && plx < VX - 1 && ply > 0 && ply < VY - 1;
+#pragma unroll
+    for (int pl = 0; pl < 3 * VZ; ++pl) {
+      const int c = pl / VZ, lz = pl % VZ;
+      const int gz = gz0 + lz;
+      if (!st_ok || gz == 0 || gz >= a.nv2 - 1) continue;
+      const T v = sO[c * NVB + RXY * lz + lds_xy];
+      if (xy_int && lz > 0 && lz < VZ - 1)
+        a.dst_u[c * a.Nv + zstride * gz + xy_off] = v;
       else
-        fb[cc * NVF + lx + VX * (ly + VY * lz)] = v;
+        fb[c * NVF + PLANE * lz + tid] = v;
     }
   }
   if (PRES)
