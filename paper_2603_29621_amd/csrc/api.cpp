@@ -545,7 +545,7 @@ template <typename T>
 void apply_A(mfs_problem &P, int l, T *dst, const T *src, hipStream_t s) {
   const Level &L = P.L[l];
   if (use_specialised() && q2_face_elems(L.g) > 0 &&
-      launch_stokes_q2<T>(L.g, dev<T>(L).X, false, (T)P.nu, dst, nullptr, src, nullptr, face<T>(L), s))
+      launch_stokes_q2<T>(L.g, dev<T>(L).X, Q2_A, (T)P.nu, dst, nullptr, src, nullptr, face<T>(L), s))
     return;
   launch_fill_dirichlet<T>(L.g, dst, src, s);
   launch_cell_op<T>(L.g, dev<T>(L), M_LAPLACE, (T)P.nu, dst, nullptr, src, nullptr, s);
@@ -604,7 +604,7 @@ void apply_op(mfs_problem &P, int op, int l, T *dst, const T *src, hipStream_t s
     case MFS_OP_STOKES:
       MFS_REQUIRE(g.kp > 0, MFS_EINVAL, "level %d has no pressure space", l);
       if (use_specialised() && q2_face_elems(g) > 0 &&
-          launch_stokes_q2<T>(g, dev<T>(L).X, true, (T)P.nu, dst, dst + nu, src, src + nu, face<T>(L), s))
+          launch_stokes_q2<T>(g, dev<T>(L).X, Q2_STOKES, (T)P.nu, dst, dst + nu, src, src + nu, face<T>(L), s))
         break;
       launch_fill_dirichlet<T>(g, dst, src, s);
       vec_fill<T>(dst + nu, T(0), g.Np, s);
@@ -612,6 +612,9 @@ void apply_op(mfs_problem &P, int op, int l, T *dst, const T *src, hipStream_t s
       break;
     case MFS_OP_B:
       MFS_REQUIRE(g.kp > 0, MFS_EINVAL, "level %d has no pressure space", l);
+      if (use_specialised() && q2_face_elems(g) > 0 &&
+          launch_stokes_q2<T>(g, dev<T>(L).X, Q2_B, (T)P.nu, dst, nullptr, nullptr, src, face<T>(L), s))
+        break;
       launch_fill_dirichlet<T>(g, dst, (const T *)nullptr, s);
       launch_cell_op<T>(g, dev<T>(L), M_GRADP, (T)P.nu, dst, nullptr, nullptr, src, s);
       break;

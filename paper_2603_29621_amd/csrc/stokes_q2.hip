@@ -163,8 +163,13 @@ __device__ __forceinline__ float recip(float d) {
   return __builtin_fmaf(r, e, r);
 }
 
-template <typename T, bool PRES>
+// KM: Q2_STOKES (velocity rows A u + B p, pressure rows B^T u), Q2_A (A u),
+// Q2_B (B p alone: no velocity input, no pressure output)
+template <typename T, int KM>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) stokes_q2_kernel(Args<T> a) {
+  constexpr bool PRES = KM != Q2_A;     // pressure input
+  constexpr bool VIN = KM != Q2_B;      // velocity input
+  constexpr bool POUT = KM == Q2_STOKES;  // pressure output
   __shared__ T sU[3 * NVB];  // input velocity of the brick
   __shared__ T sO[3 * NVB];  // output velocity, one slice per component wave
   __shared__ T sP[NPB];      // input pressure
@@ -198,14 +203,14 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) st
       const int c = pl / VZ, lz = pl % VZ;
       const int gz = gz0 + lz;
       T v = 0;
-      if (xy_in && !xy_dir && gz > 0 && gz < a.nv2 - 1) v = a.src_u[c * a.Nv + zstride * gz + xy_off];
+      if (VIN && xy_in && !xy_dir && gz > 0 && gz < a.nv2 - 1) v = a.src_u[c * a.Nv + zstride * gz + xy_off];
       vv[pl] = v;
     }
 #pragma unroll
     for (int pl = 0; pl < 3 * VZ; ++pl) {
       const int c = pl / VZ, lz = pl % VZ;
       if (pl_on) {
-        sU[c * NVB + RXY * lz + lds_xy] = vv[pl];
+        if (VIN) sU[c * NVB + RXY * lz + lds_xy] = vv[pl];
         sO[c * NVB + RXY * lz + lds_xy] = 0;
       }
     }
@@ -246,7 +251,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) st
     asm volatile("" ::: "memory");
     // forward: reference gradient of component c at the 9 points of slab sl
     T g[3][9];
-    {
+    if (VIN) {
       T za[9], zb[9];  // z-contracted nodal planes: values (S) and z-derivative (DS)
 #pragma unroll
       for (int j = 0; j < 3; ++j)
@@ -342,21 +347,25 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) st
         A[2][2] = J0[0] * J1[1] - J0[1] * J1[0];
         const T det = J0[0] * A[0][0] + J0[1] * A[0][1] + J0[2] * A[0][2];
         const T w = ws * Tab<T>::w(i) * Tab<T>::w(j);
-        const T nd = a.nu * recip(det);
         // z = adj^T ghat (= det * physical gradient of component c)
-        T z[3];
+        T z[3] = {0, 0, 0};
+        if (VIN) {
 #pragma unroll
-        for (int x = 0; x < 3; ++x) z[x] = A[0][x] * g[0][q] + A[1][x] * g[1][q] + A[2][x] * g[2][q];
-        if (PRES) {
+          for (int x = 0; x < 3; ++x) z[x] = A[0][x] * g[0][q] + A[1][x] * g[1][q] + A[2][x] * g[2][q];
+        }
+        if (POUT) {
           const T qa = -w * (oh[0] * z[0] + oh[1] * z[1] + oh[2] * z[2]);
 #pragma unroll
           for (int m = 0; m < 2; ++m)
 #pragma unroll
             for (int n = 0; n < 2; ++n) pacc[n + 2 * m] += (Tab<T>::Sp(i, n) * Tab<T>::Sp(j, m)) * qa;
         }
-        T v[3];
+        T v[3] = {0, 0, 0};
+        if (VIN) {
+          const T nd = a.nu * recip(det);
 #pragma unroll
-        for (int x = 0; x < 3; ++x) v[x] = nd * z[x];
+          for (int x = 0; x < 3; ++x) v[x] = nd * z[x];
+        }
         if (PRES) {
           const T p = Tab<T>::Sp(i, 0) * (Tab<T>::Sp(j, 0) * pz[0] + Tab<T>::Sp(j, 1) * pz[2]) +
                       Tab<T>::Sp(i, 1) * (Tab<T>::Sp(j, 0) * pz[1] + Tab<T>::Sp(j, 1) * pz[3]);
@@ -370,7 +379,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) st
 
     // backward: integrate against the test functions, add into the brick slice
     if (valid) {
-      if (PRES) {
+      if (POUT) {
         // pressure cells are 1 node apart: one node offset per batch
 #pragma unroll
         for (int lz = 0; lz < 2; ++lz)
@@ -451,7 +460,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) st
         fb[c * NVF + PLANE * lz + tid] = v;
     }
   }
-  if (PRES)
+  if (POUT)
     for (int idx = tid; idx < NPB; idx += NT) {
       const int lx = idx % PX, ly = (idx / PX) % PY, lz = idx / (PX * PY);
       const int px = BX * bx + lx, py = BY * by + ly, pz = BZ * bz + lz;
@@ -467,8 +476,9 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) st
 
 // Face nodes: sum the partials of every brick containing the node, in a fixed
 // order (z, y, x brick index); Dirichlet rows: dst = src.
-template <typename T, bool PRES>
+template <typename T, int KM>
 __global__ void __launch_bounds__(256) q2_combine_kernel(Args<T> a) {
+  constexpr bool POUT = KM == Q2_STOKES;
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < a.Nv) {
     const int gx = (int)(i % a.nv0);
@@ -477,7 +487,7 @@ __global__ void __launch_bounds__(256) q2_combine_kernel(Args<T> a) {
     const bool dir = gx == 0 || gy == 0 || gz == 0 || gx == a.nv0 - 1 || gy == a.nv1 - 1 || gz == a.nv2 - 1;
     if (dir) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) a.dst_u[c * a.Nv + i] = a.src_u[c * a.Nv + i];
+      for (int c = 0; c < 3; ++c) a.dst_u[c * a.Nv + i] = KM != Q2_B ? a.src_u[c * a.Nv + i] : T(0);
     } else if (gx % (2 * BX) == 0 || gy % (2 * BY) == 0 || gz % (2 * BZ) == 0) {
       int bxs[2], bys[2], bzs[2], nxs = 0, nys = 0, nzs = 0;
       auto bricks = [](int g, int B2, int nb, int *out, int &cnt) {
@@ -502,7 +512,7 @@ __global__ void __launch_bounds__(256) q2_combine_kernel(Args<T> a) {
       for (int c = 0; c < 3; ++c) a.dst_u[c * a.Nv + i] = acc[c];
     }
   }
-  if (PRES) {
+  if (POUT) {
     const int64_t Np = (int64_t)a.np0 * a.np1 * (a.n2 + 1);
     if (i < Np) {
       const int px = (int)(i % a.np0);
@@ -542,10 +552,10 @@ int64_t q2_face_elems(const LevelGeom &g) {
 }
 
 template <typename T>
-bool launch_stokes_q2(const LevelGeom &g, const T *X, bool pressure, T nu, T *dst_u, T *dst_p, const T *src_u,
+bool launch_stokes_q2(const LevelGeom &g, const T *X, int mode, T nu, T *dst_u, T *dst_p, const T *src_u,
                       const T *src_p, T *face, hipStream_t s) {
   if (g.dim != 3 || g.k != 2 || face == nullptr) return false;
-  if (pressure && g.kp != 1) return false;
+  if (mode != Q2_A && g.kp != 1) return false;
   q2::Args<T> a{};
   a.n0 = g.n[0];
   a.n1 = g.n[1];
@@ -567,22 +577,26 @@ bool launch_stokes_q2(const LevelGeom &g, const T *X, bool pressure, T nu, T *ds
   a.dst_p = dst_p;
   a.face = face;
   a.nu = nu;
-  const int64_t nthreads = pressure ? std::max<int64_t>(g.Nv, g.Np) : g.Nv;
+  const int64_t nthreads = mode == Q2_STOKES ? std::max<int64_t>(g.Nv, g.Np) : g.Nv;
   const unsigned cgrid = (unsigned)((nthreads + 255) / 256);
-  if (pressure) {
-    hipLaunchKernelGGL((q2::stokes_q2_kernel<T, true>), dim3(a.nblocks), dim3(q2::NT), 0, s, a);
-    hipLaunchKernelGGL((q2::q2_combine_kernel<T, true>), dim3(cgrid), dim3(256), 0, s, a);
+#define Q2_GO(KM)                                                                                       \
+  hipLaunchKernelGGL((q2::stokes_q2_kernel<T, KM>), dim3(a.nblocks), dim3(q2::NT), 0, s, a);            \
+  hipLaunchKernelGGL((q2::q2_combine_kernel<T, KM>), dim3(cgrid), dim3(256), 0, s, a);
+  if (mode == Q2_STOKES) {
+    Q2_GO(Q2_STOKES)
+  } else if (mode == Q2_B) {
+    Q2_GO(Q2_B)
   } else {
-    hipLaunchKernelGGL((q2::stokes_q2_kernel<T, false>), dim3(a.nblocks), dim3(q2::NT), 0, s, a);
-    hipLaunchKernelGGL((q2::q2_combine_kernel<T, false>), dim3(cgrid), dim3(256), 0, s, a);
+    Q2_GO(Q2_A)
   }
+#undef Q2_GO
   MFS_HIP(hipGetLastError());
   return true;
 }
 
-template bool launch_stokes_q2<double>(const LevelGeom &, const double *, bool, double, double *, double *,
+template bool launch_stokes_q2<double>(const LevelGeom &, const double *, int, double, double *, double *,
                                        const double *, const double *, double *, hipStream_t);
-template bool launch_stokes_q2<float>(const LevelGeom &, const float *, bool, float, float *, float *, const float *,
+template bool launch_stokes_q2<float>(const LevelGeom &, const float *, int, float, float *, float *, const float *,
                                       const float *, float *, hipStream_t);
 
 }  // namespace mfs

@@ -99,12 +99,18 @@ def test_stokes_operators_fp32(dim, n, k, noise):
     h, X = _setup(dim, n, k, noise, nu)
     try:
         S = fem.Space(dim, n, X, k)
-        K, _ = fem.stokes_operator(S, nu)
+        K, mats = fem.stokes_operator(S, nu)
         x = inputs.uniform_vector(S.n_dofs, 12).astype(np.float32).astype(np.float64)
         src = cuda(x, torch.float32)
         dst = torch.empty_like(src)
         mfs.mfs_vmult(h, mfs.MFS_OP_STOKES, mfs.MFS_FP32, 0, dst, src)
         assert relerr(host(dst), K @ x) <= 1e-5
+        # gradient block B alone (Dirichlet rows 0)
+        nvel = dim * S.Nv
+        Z = (~S.velocity_dirichlet_mask()[:nvel]).astype(float)
+        du = torch.empty(nvel, dtype=torch.float32, device="cuda")
+        mfs.mfs_vmult(h, mfs.MFS_OP_B, mfs.MFS_FP32, 0, du, cuda(x[nvel:], torch.float32))
+        assert relerr(host(du), Z * (mats["B"] @ x[nvel:])) <= 1e-5
     finally:
         mfs.mfs_destroy(h)
 
