@@ -625,6 +625,9 @@ void apply_op(mfs_problem &P, int op, int l, T *dst, const T *src, hipStream_t s
       break;
     case MFS_OP_MASS_P:
       MFS_REQUIRE(g.kp > 0, MFS_EINVAL, "level %d has no pressure space", l);
+      if (use_specialised() && q2_face_elems(g) > 0 &&
+          launch_stokes_q2<T>(g, dev<T>(L).X, Q2_MASSP, (T)P.nu, nullptr, dst, nullptr, src, face<T>(L), s))
+        break;
       vec_fill<T>(dst, T(0), g.Np, s);
       launch_cell_op<T>(g, dev<T>(L), M_MASSP, (T)P.nu, nullptr, dst, nullptr, src, s);
       break;

@@ -92,10 +92,11 @@ void launch_cell_op(const LevelGeom &g, const DevLevel<T> &d, int mode, T nu, T 
 // specialised 3D degree-2 kernel, writing every entry of its velocity output
 // itself: Q2_STOKES (Stokes Q2/Q1: dst_u = A src_u + B src_p, dst_p = B^T
 // src_u; Dirichlet rows dst_u = src_u), Q2_A (dst_u = A src_u, Dirichlet rows
-// = src_u), Q2_B (dst_u = B src_p, Dirichlet rows 0; src_u and dst_p unused);
+// = src_u), Q2_B (dst_u = B src_p, Dirichlet rows 0; src_u and dst_p unused),
+// Q2_MASSP (dst_p = M_p src_p; velocity arguments unused);
 // `face` is a scratch buffer of q2_face_elems(g) elements.  Returns false when
 // the level does not qualify.
-constexpr int Q2_A = 0, Q2_STOKES = 1, Q2_B = 2;
+constexpr int Q2_A = 0, Q2_STOKES = 1, Q2_B = 2, Q2_MASSP = 3;
 int64_t q2_face_elems(const LevelGeom &g);
 template <typename T>
 bool launch_stokes_q2(const LevelGeom &g, const T *X, int mode, T nu, T *dst_u, T *dst_p, const T *src_u,

@@ -164,12 +164,16 @@ __device__ __forceinline__ float recip(float d) {
 }
 
 // KM: Q2_STOKES (velocity rows A u + B p, pressure rows B^T u), Q2_A (A u),
-// Q2_B (B p alone: no velocity input, no pressure output)
+// Q2_B (B p alone: no velocity input, no pressure output), Q2_MASSP (pressure
+// mass matrix alone; wave c integrates z-slab c of every cell and the three
+// partial sums meet in the pressure output)
 template <typename T, int KM>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) stokes_q2_kernel(Args<T> a) {
-  constexpr bool PRES = KM != Q2_A;     // pressure input
-  constexpr bool VIN = KM != Q2_B;      // velocity input
-  constexpr bool POUT = KM == Q2_STOKES;  // pressure output
+  constexpr bool MASS = KM == Q2_MASSP;
+  constexpr bool PRES = KM != Q2_A;                      // pressure input
+  constexpr bool VIN = KM == Q2_STOKES || KM == Q2_A;    // velocity input
+  constexpr bool POUT = KM == Q2_STOKES || MASS;         // pressure output
+  constexpr bool VOUT = !MASS;                           // velocity output
   __shared__ T sU[3 * NVB];  // input velocity of the brick
   __shared__ T sO[3 * NVB];  // output velocity, one slice per component wave
   __shared__ T sP[NPB];      // input pressure
@@ -211,7 +215,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) st
       const int c = pl / VZ, lz = pl % VZ;
       if (pl_on) {
         if (VIN) sU[c * NVB + RXY * lz + lds_xy] = vv[pl];
-        sO[c * NVB + RXY * lz + lds_xy] = 0;
+        if (VOUT) sO[c * NVB + RXY * lz + lds_xy] = 0;
       }
     }
   }
@@ -245,7 +249,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) st
   T *oc = &sO[c * NVB + ex + RX * 2 * ey + RXY * 2 * ez];
 
 #pragma unroll 1
-  for (int sl = 0; sl < 3; ++sl) {
+  for (int sl = MASS ? c : 0; sl < (MASS ? c + 1 : 3); ++sl) {
     // re-read the nodal values from LDS in every slab instead of keeping all
     // 27 in registers across the loop (register budget: occupancy)
     asm volatile("" ::: "memory");
@@ -353,28 +357,33 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) st
 #pragma unroll
           for (int x = 0; x < 3; ++x) z[x] = A[0][x] * g[0][q] + A[1][x] * g[1][q] + A[2][x] * g[2][q];
         }
+        T p = 0;
+        if (PRES)
+          p = Tab<T>::Sp(i, 0) * (Tab<T>::Sp(j, 0) * pz[0] + Tab<T>::Sp(j, 1) * pz[2]) +
+              Tab<T>::Sp(i, 1) * (Tab<T>::Sp(j, 0) * pz[1] + Tab<T>::Sp(j, 1) * pz[3]);
         if (POUT) {
-          const T qa = -w * (oh[0] * z[0] + oh[1] * z[1] + oh[2] * z[2]);
+          // pressure test integrand: mass (p q det w) or this component's share of -(div u) q
+          const T qa = MASS ? w * det * p : -w * (oh[0] * z[0] + oh[1] * z[1] + oh[2] * z[2]);
 #pragma unroll
           for (int m = 0; m < 2; ++m)
 #pragma unroll
             for (int n = 0; n < 2; ++n) pacc[n + 2 * m] += (Tab<T>::Sp(i, n) * Tab<T>::Sp(j, m)) * qa;
         }
-        T v[3] = {0, 0, 0};
-        if (VIN) {
-          const T nd = a.nu * recip(det);
+        if (VOUT) {
+          T v[3] = {0, 0, 0};
+          if (VIN) {
+            const T nd = a.nu * recip(det);
 #pragma unroll
-          for (int x = 0; x < 3; ++x) v[x] = nd * z[x];
+            for (int x = 0; x < 3; ++x) v[x] = nd * z[x];
+          }
+          if (PRES) {
+#pragma unroll
+            for (int x = 0; x < 3; ++x) v[x] -= oh[x] * p;
+          }
+          // test-gradient coefficients: w * adj * v
+#pragma unroll
+          for (int bb = 0; bb < 3; ++bb) g[bb][q] = w * (A[bb][0] * v[0] + A[bb][1] * v[1] + A[bb][2] * v[2]);
         }
-        if (PRES) {
-          const T p = Tab<T>::Sp(i, 0) * (Tab<T>::Sp(j, 0) * pz[0] + Tab<T>::Sp(j, 1) * pz[2]) +
-                      Tab<T>::Sp(i, 1) * (Tab<T>::Sp(j, 0) * pz[1] + Tab<T>::Sp(j, 1) * pz[3]);
-#pragma unroll
-          for (int x = 0; x < 3; ++x) v[x] -= oh[x] * p;
-        }
-        // test-gradient coefficients: w * adj * v
-#pragma unroll
-        for (int bb = 0; bb < 3; ++bb) g[bb][q] = w * (A[bb][0] * v[0] + A[bb][1] * v[1] + A[bb][2] * v[2]);
       }
 
     // backward: integrate against the test functions, add into the brick slice
@@ -391,6 +400,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) st
               lds_batch_end<T>();
             }
       }
+      if (!VOUT) continue;
       T r[9];
 #pragma unroll
       for (int j = 0; j < 3; ++j)
@@ -443,7 +453,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) st
   // ---- write the brick: interior nodes to dst, face-node partial sums to the
   // brick's slot of the face buffer (summed by the combine kernel)
   T *fb = a.face + (int64_t)b * FACE_PER_BRICK;
-  {
+  if (VOUT) {
     // same plane mapping as the load; Dirichlet rows and nodes outside the
     // mesh are left to the combine kernel
     const bool st_ok = pl_on && pgx > 0 && pgx < a.nv0 - 1 && pgy > 0 && pgy < a.nv1 - 1;
@@ -478,9 +488,9 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) st
 // order (z, y, x brick index); Dirichlet rows: dst = src.
 template <typename T, int KM>
 __global__ void __launch_bounds__(256) q2_combine_kernel(Args<T> a) {
-  constexpr bool POUT = KM == Q2_STOKES;
+  constexpr bool POUT = KM == Q2_STOKES || KM == Q2_MASSP;
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < a.Nv) {
+  if (KM != Q2_MASSP && i < a.Nv) {
     const int gx = (int)(i % a.nv0);
     const int64_t r = i / a.nv0;
     const int gy = (int)(r % a.nv1), gz = (int)(r / a.nv1);
@@ -577,13 +587,15 @@ bool launch_stokes_q2(const LevelGeom &g, const T *X, int mode, T nu, T *dst_u, 
   a.dst_p = dst_p;
   a.face = face;
   a.nu = nu;
-  const int64_t nthreads = mode == Q2_STOKES ? std::max<int64_t>(g.Nv, g.Np) : g.Nv;
+  const int64_t nthreads = mode == Q2_STOKES ? std::max<int64_t>(g.Nv, g.Np) : (mode == Q2_MASSP ? g.Np : g.Nv);
   const unsigned cgrid = (unsigned)((nthreads + 255) / 256);
 #define Q2_GO(KM)                                                                                       \
   hipLaunchKernelGGL((q2::stokes_q2_kernel<T, KM>), dim3(a.nblocks), dim3(q2::NT), 0, s, a);            \
   hipLaunchKernelGGL((q2::q2_combine_kernel<T, KM>), dim3(cgrid), dim3(256), 0, s, a);
   if (mode == Q2_STOKES) {
     Q2_GO(Q2_STOKES)
+  } else if (mode == Q2_MASSP) {
+    Q2_GO(Q2_MASSP)
   } else if (mode == Q2_B) {
     Q2_GO(Q2_B)
   } else {
