@@ -1291,11 +1291,10 @@ void kr_enqueue_step(mfs_problem &P, hipStream_t s) {
   }
   apply_system(P, K.w, zj, s);
   // classical Gram-Schmidt, twice
+  // (the second pass's dots and the norm are fused with the updates before them)
   multi_dot<double>(K.V, n, j + 1, K.w, n, K.dev, P.partials, s);
-  multi_axpy<double>(K.w, K.V, n, j + 1, K.dev, n, s);
-  multi_dot<double>(K.V, n, j + 1, K.w, n, K.dev + 32, P.partials, s);
-  multi_axpy<double>(K.w, K.V, n, j + 1, K.dev + 32, n, s);
-  multi_dot<double>(K.w, 0, 1, K.w, n, K.dev + 64, P.partials, s);
+  axpy_dot<double>(K.w, K.V, n, j + 1, K.dev, j + 1, false, n, K.dev + 32, P.partials, s);
+  axpy_dot<double>(K.w, K.V, n, j + 1, K.dev + 32, 0, true, n, K.dev + 64, P.partials, s);
   scale_inv_sqrt<double>(K.V + (int64_t)(j + 1) * n, K.w, n, K.dev + 64, s);
   MFS_HIP(hipMemcpyAsync(K.host, K.dev, 65 * sizeof(double), hipMemcpyDeviceToHost, s));
   MFS_HIP(hipEventRecord(K.ev, s));

@@ -196,6 +196,11 @@ void multi_dot(const T *V, int64_t ld, int m, const T *w, int64_t n, double *out
 // w -= sum_i h[i] V_i  (h on device)
 template <typename T>
 void multi_axpy(T *w, const T *V, int64_t ld, int m, const double *h, int64_t n, hipStream_t s);
+// one pass over V: w -= sum_{i<m} h[i] V_i, then out[i] = <V_i, w> for i < md
+// (md is 0 or m) and, when norm, out[md] = <w, w>, over the updated w
+template <typename T>
+void axpy_dot(T *w, const T *V, int64_t ld, int m, const double *h, int md, bool norm, int64_t n, double *out,
+              double *partials, hipStream_t s);
 // y = sum_i h[i] V_i (+ y if accumulate)
 template <typename T>
 void multi_combine(T *y, const T *V, int64_t ld, int m, const double *h, int64_t n, bool accumulate,
@@ -220,6 +225,6 @@ void vec_mul(T *y, const T *a, const T *x, int64_t n, hipStream_t s);
 // p -= (*num / *den) * one_vector   (pressure mean shift)
 void shift_mean(double *p, int64_t n, const double *num, const double *den, hipStream_t s);
 
-constexpr int DOT_BLOCKS = 512;
+constexpr int DOT_BLOCKS = 2048;
 
 }  // namespace mfs

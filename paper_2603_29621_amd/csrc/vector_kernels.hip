@@ -209,6 +209,72 @@ void multi_axpy(T *w, const T *V, int64_t ld, int m, const double *h, int64_t n,
   hipLaunchKernelGGL(k_multi_axpy<T>, dim3(nblocks(n)), dim3(VB), 0, s, w, V, ld, m, h, n);
 }
 
+// fused update and dot products (see axpy_dot); the same chunking and
+// reduction order as k_multi_dot_partial
+template <typename T, int MM>
+__global__ void __launch_bounds__(256) k_axpy_dot_partial(T *w, const T *V, int64_t ld, int m, const double *h,
+                                                          int md, int norm, int64_t n, double *partials) {
+  __shared__ double sh[MAXM];
+  if ((int)threadIdx.x < m) sh[threadIdx.x] = h[threadIdx.x];
+  __syncthreads();
+  double acc[MM + 1];
+#pragma unroll
+  for (int i = 0; i <= MM; ++i) acc[i] = 0.0;
+  const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t beg = blockIdx.x * chunk;
+  const int64_t end = beg + chunk < n ? beg + chunk : n;
+  for (int64_t j = beg + threadIdx.x; j < end; j += blockDim.x) {
+    double v[MM];
+    double wj = (double)w[j];
+#pragma unroll
+    for (int i = 0; i < MM; ++i)
+      if (i < m) {
+        v[i] = (double)V[i * ld + j];
+        wj -= sh[i] * v[i];
+      }
+    const T wt = (T)wj;
+    w[j] = wt;
+    const double wd = (double)wt;
+#pragma unroll
+    for (int i = 0; i < MM; ++i)
+      if (i < md) acc[i] += v[i] * wd;
+    if (norm) acc[MM] += wd * wd;
+  }
+  __shared__ double red[256];
+  const int nd = md + (norm ? 1 : 0);
+  for (int k = 0; k < nd; ++k) {
+    double a = 0;
+#pragma unroll
+    for (int i = 0; i <= MM; ++i)
+      if (i == (k < md ? k : MM)) a = acc[i];
+    red[threadIdx.x] = a;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+      if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[k * DOT_BLOCKS + blockIdx.x] = red[0];
+    __syncthreads();
+  }
+}
+template <typename T>
+void axpy_dot(T *w, const T *V, int64_t ld, int m, const double *h, int md, bool norm, int64_t n, double *out,
+              double *partials, hipStream_t s) {
+  MFS_REQUIRE(m >= 1 && m <= MAXM - 1 && (md == 0 || md == m), MFS_EINVAL, "axpy_dot: m=%d md=%d", m, md);
+  int nb = (int)((n + 2047) / 2048);
+  nb = nb < 1 ? 1 : (nb > DOT_BLOCKS ? DOT_BLOCKS : nb);
+  const int nf = norm ? 1 : 0;
+  if (m <= 4)
+    hipLaunchKernelGGL((k_axpy_dot_partial<T, 4>), dim3(nb), dim3(256), 0, s, w, V, ld, m, h, md, nf, n, partials);
+  else if (m <= 8)
+    hipLaunchKernelGGL((k_axpy_dot_partial<T, 8>), dim3(nb), dim3(256), 0, s, w, V, ld, m, h, md, nf, n, partials);
+  else if (m <= 16)
+    hipLaunchKernelGGL((k_axpy_dot_partial<T, 16>), dim3(nb), dim3(256), 0, s, w, V, ld, m, h, md, nf, n, partials);
+  else
+    hipLaunchKernelGGL((k_axpy_dot_partial<T, 32>), dim3(nb), dim3(256), 0, s, w, V, ld, m, h, md, nf, n, partials);
+  if (md + nf > 0) hipLaunchKernelGGL(k_multi_dot_final, dim3(md + nf), dim3(256), 0, s, partials, nb, out);
+}
+
 template <typename T>
 __global__ void k_multi_combine(T *y, const T *V, int64_t ld, int m, const double *h, int64_t n, int acc_in) {
   __shared__ double sh[MAXM];
@@ -326,6 +392,8 @@ void launch_reciprocal_boundary_one(const LevelGeom &g, double *d, hipStream_t s
   template void multi_dot<T>(const T *, int64_t, int, const T *, int64_t, double *, double *,     \
                              hipStream_t);                                                        \
   template void multi_axpy<T>(T *, const T *, int64_t, int, const double *, int64_t, hipStream_t); \
+  template void axpy_dot<T>(T *, const T *, int64_t, int, const double *, int, bool, int64_t, double *, \
+                            double *, hipStream_t);                                               \
   template void multi_combine<T>(T *, const T *, int64_t, int, const double *, int64_t, bool,     \
                                  hipStream_t);                                                    \
   template void dense_apply<T>(const double *, int, const T *, T *, hipStream_t);                 \
