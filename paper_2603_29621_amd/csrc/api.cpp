@@ -82,8 +82,20 @@ struct Level {
   float *rs32 = nullptr;
 };
 
+// Stride of the Krylov basis vectors: the length rounded up to an odd number
+// of 256-byte units, so that the up to 31 vectors that the Gram-Schmidt
+// kernels stream side by side start at staggered offsets modulo the HBM
+// channel interleave (a stride that is a multiple of 4 KB sent all streams
+// to the same channels at once).
+int64_t kr_ld(int64_t n) {
+  int64_t l = (n + 31) / 32 * 32;
+  if ((l / 32) % 2 == 0) l += 32;
+  return l;
+}
+
 struct Krylov {
   int m = 30;
+  int64_t ld = 0;  // basis stride (kr_ld of the system length)
   double *V = nullptr, *Z = nullptr, *w = nullptr;
   double *dev = nullptr;     // device scalars: h[32], h2[32], nrm2, misc
   double *host = nullptr;    // pinned readback
@@ -391,8 +403,9 @@ void plan_arena(Arena &A, mfs_problem &P, const std::vector<LevelGeom> &G) {
     Krylov &K = P.kr;
     K.m = std::max(1, std::min(P.opts.restart, 30));
     const int64_t nk = full ? ntot : 0;
-    K.V = A.take<double>((K.m + 1) * nk);
-    K.Z = A.take<double>(K.m * nk);
+    K.ld = kr_ld(nk);
+    K.V = A.take<double>((K.m + 1) * (nk ? K.ld : 0));
+    K.Z = A.take<double>(K.m * (nk ? K.ld : 0));
     K.w = A.take<double>(nk);
     K.dev = A.take<double>(128);
     K.ydev = A.take<double>(64);
@@ -407,8 +420,8 @@ void plan_arena(Arena &A, mfs_problem &P, const std::vector<LevelGeom> &G) {
     L.tab64 = A.take<double>(TAB_SIZE);
     L.tab32 = A.take<float>(TAB_SIZE);
     L.diag = A.take<double>(G[l].Nv);
-    L.face64 = A.take<double>(q2_face_elems(G[l]));
-    L.face32 = A.take<float>(q2_face_elems(G[l]));
+    L.face64 = A.take<double>(q2_face_elems(G[l]) + q1_face_elems(G[l]));
+    L.face32 = A.take<float>(q2_face_elems(G[l]) + q1_face_elems(G[l]));
     L.invdiag64 = A.take<double>(G[l].Nv);
     L.invdiag32 = A.take<float>(G[l].Nv);
     if (l + 1 < G.size()) {
@@ -430,8 +443,9 @@ void plan_arena(Arena &A, mfs_problem &P, const std::vector<LevelGeom> &G) {
   Krylov &K = P.kr;
   K.m = std::max(1, std::min(P.opts.restart, 30));
   const int64_t nk = full ? ntot : 0;  // Krylov space only when the solver is available
-  K.V = A.take<double>((K.m + 1) * nk);
-  K.Z = A.take<double>(K.m * nk);
+  K.ld = kr_ld(nk);
+  K.V = A.take<double>((K.m + 1) * (nk ? K.ld : 0));
+  K.Z = A.take<double>(K.m * (nk ? K.ld : 0));
   K.w = A.take<double>(nk);
   K.dev = A.take<double>(128);
   K.ydev = A.take<double>(64);
@@ -546,6 +560,9 @@ void apply_A(mfs_problem &P, int l, T *dst, const T *src, hipStream_t s) {
   const Level &L = P.L[l];
   if (use_specialised() && q2_face_elems(L.g) > 0 &&
       launch_stokes_q2<T>(L.g, dev<T>(L).X, Q2_A, (T)P.nu, dst, nullptr, src, nullptr, face<T>(L), s))
+    return;
+  if (use_specialised() && q1_face_elems(L.g) > 0 &&
+      launch_laplace_q1<T>(L.g, dev<T>(L).X, (T)P.nu, dst, src, face<T>(L), s))
     return;
   launch_fill_dirichlet<T>(L.g, dst, src, s);
   launch_cell_op<T>(L.g, dev<T>(L), M_LAPLACE, (T)P.nu, dst, nullptr, src, nullptr, s);
@@ -1281,7 +1298,7 @@ void kr_enqueue_step(mfs_problem &P, hipStream_t s) {
   Krylov &K = P.kr;
   const int64_t n = sys_n(P);
   const int j = K.j;
-  double *vj = K.V + (int64_t)j * n, *zj = K.Z + (int64_t)j * n;
+  double *vj = K.V + (int64_t)j * K.ld, *zj = K.Z + (int64_t)j * K.ld;
   if (K.prec == MFS_FP32) {
     vec_cast<float, double>(P.w32.full_in, vj, n, s);
     precondition_any<float>(P, P.w32.full_out, P.w32.full_in, s);
@@ -1292,10 +1309,10 @@ void kr_enqueue_step(mfs_problem &P, hipStream_t s) {
   apply_system(P, K.w, zj, s);
   // classical Gram-Schmidt, twice
   // (the second pass's dots and the norm are fused with the updates before them)
-  multi_dot<double>(K.V, n, j + 1, K.w, n, K.dev, P.partials, s);
-  axpy_dot<double>(K.w, K.V, n, j + 1, K.dev, j + 1, false, n, K.dev + 32, P.partials, s);
-  axpy_dot<double>(K.w, K.V, n, j + 1, K.dev + 32, 0, true, n, K.dev + 64, P.partials, s);
-  scale_inv_sqrt<double>(K.V + (int64_t)(j + 1) * n, K.w, n, K.dev + 64, s);
+  multi_dot<double>(K.V, K.ld, j + 1, K.w, n, K.dev, P.partials, s);
+  axpy_dot<double>(K.w, K.V, K.ld, j + 1, K.dev, j + 1, false, n, K.dev + 32, P.partials, s);
+  axpy_dot<double>(K.w, K.V, K.ld, j + 1, K.dev + 32, 0, true, n, K.dev + 64, P.partials, s);
+  scale_inv_sqrt<double>(K.V + (int64_t)(j + 1) * K.ld, K.w, n, K.dev + 64, s);
   MFS_HIP(hipMemcpyAsync(K.host, K.dev, 65 * sizeof(double), hipMemcpyDeviceToHost, s));
   MFS_HIP(hipEventRecord(K.ev, s));
 }
@@ -1316,7 +1333,7 @@ void kr_enqueue_update(mfs_problem &P, hipStream_t s) {
     MFS_HIP(hipStreamSynchronize(s));  // previous use of yhost finished
     std::memcpy(K.yhost, y.data(), m * sizeof(double));
     MFS_HIP(hipMemcpyAsync(K.ydev, K.yhost, m * sizeof(double), hipMemcpyHostToDevice, s));
-    multi_combine<double>(K.x, K.Z, n, m, K.ydev, n, true, s);
+    multi_combine<double>(K.x, K.Z, K.ld, m, K.ydev, n, true, s);
   }
   kr_enqueue_residual(P, s);
 }
@@ -1856,8 +1873,9 @@ void hp_build(mfs_problem &P, const std::vector<int> &deg0, hipStream_t s) {
   P.w64.full_out = H.alloc<double>(ntot);
   if (P.opts.mg_levels) {
     Krylov &K = P.kr;
-    K.V = H.alloc<double>((K.m + 1) * ntot);
-    K.Z = H.alloc<double>(K.m * ntot);
+    K.ld = kr_ld(ntot);
+    K.V = H.alloc<double>((K.m + 1) * K.ld);
+    K.Z = H.alloc<double>(K.m * K.ld);
     K.w = H.alloc<double>(ntot);
   }
   MFS_HIP(hipStreamSynchronize(s));

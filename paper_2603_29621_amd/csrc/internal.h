@@ -101,6 +101,12 @@ int64_t q2_face_elems(const LevelGeom &g);
 template <typename T>
 bool launch_stokes_q2(const LevelGeom &g, const T *X, int mode, T nu, T *dst_u, T *dst_p, const T *src_u,
                       const T *src_p, T *face, hipStream_t s);
+// specialised 3D degree-1 kernel for the velocity block: dst = A src
+// (Dirichlet rows = src); `face` is a scratch buffer of q1_face_elems(g)
+// elements.  Returns false when the level does not qualify.
+int64_t q1_face_elems(const LevelGeom &g);
+template <typename T>
+bool launch_laplace_q1(const LevelGeom &g, const T *X, T nu, T *dst, const T *src, T *face, hipStream_t s);
 // diagonal of the scalar Laplacian block (FP64): diag[Nv]
 void launch_laplace_diagonal(const LevelGeom &g, const double *X, const double *tab, double nu, double *diag,
                              hipStream_t s);

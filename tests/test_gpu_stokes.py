@@ -251,6 +251,29 @@ def test_levels_transfers_and_lambda(dim, n, k, noise):
         mfs.mfs_destroy(h)
 
 
+@pytest.mark.parametrize("n,noise", [([12, 10, 6], 0.2), ([16, 8, 4], 0.1), ([2, 2, 2], 0.2)])
+def test_velocity_block_on_every_level(n, noise):
+    """A on every level of a 3D Q2/Q1 hierarchy (degree 2, then degree 1,
+    then coarser degree-1 meshes) against the oracle's level matrices, FP64
+    and FP32; several bricks and ragged brick tails."""
+    dim, k, nu = 3, 2, 0.9
+    h, X = _setup(dim, n, k, noise, nu, mg_levels=1)
+    try:
+        H = _oracle_hierarchy(dim, n, X, k, nu, 5)
+        assert mfs.mfs_n_levels(h) == len(H.spaces)
+        for l, S in enumerate(H.spaces):
+            x = inputs.uniform_vector(dim * S.Nv, 70 + l)
+            y = torch.empty(dim * S.Nv, dtype=torch.float64, device="cuda")
+            mfs.mfs_vmult(h, mfs.MFS_OP_A, mfs.MFS_FP64, l, y, cuda(x))
+            assert relerr(host(y), H.A[l] @ x) <= 1e-12, l
+            x32 = x.astype(np.float32).astype(np.float64)
+            y32 = torch.empty(dim * S.Nv, dtype=torch.float32, device="cuda")
+            mfs.mfs_vmult(h, mfs.MFS_OP_A, mfs.MFS_FP32, l, y32, cuda(x32, torch.float32))
+            assert relerr(host(y32), H.A[l] @ x32) <= 1e-5, l
+    finally:
+        mfs.mfs_destroy(h)
+
+
 @pytest.mark.parametrize("dim,n,k,noise", MG_CASES)
 def test_vcycle_and_block_preconditioner_fp64(dim, n, k, noise):
     nu = 1.3
