@@ -130,7 +130,38 @@ void cheb_update(const LevelGeom &g, T *x, T *d, const T *b, const T *Ax, const 
 }
 
 // ------------------------------------------------------------ reductions
+// Multi-vector kernels over the Krylov basis.  Every thread reads the same
+// element of up to MM columns; the loads are unconditional (columns beyond m
+// re-read column m - 1 and get coefficient 0), so all of them are in flight
+// at once instead of one guarded load, and one wait, per column.
 constexpr int MAXM = 32;
+
+template <typename T, int MM>
+__device__ __forceinline__ void load_cols(const T *V, int64_t ld, int m, int64_t j, double v[MM]) {
+#pragma unroll
+  for (int i = 0; i < MM; ++i) {
+    const int ii = i < m ? i : m - 1;
+    v[i] = (double)V[ii * ld + j];
+  }
+}
+
+// m coefficients from device memory into LDS, zero-padded to MAXM
+__device__ __forceinline__ void load_coefs(double *sh, const double *h, int m) {
+  if ((int)threadIdx.x < MAXM) sh[threadIdx.x] = (int)threadIdx.x < m ? h[threadIdx.x] : 0.0;
+  __syncthreads();
+}
+
+// block tree reduction of per-thread values, written to partials[k * DOT_BLOCKS + block]
+__device__ __forceinline__ void block_partial(double a, int k, double *partials, double *red) {
+  red[threadIdx.x] = a;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[k * DOT_BLOCKS + blockIdx.x] = red[0];
+  __syncthreads();
+}
 
 template <typename T, int MM>
 __global__ void __launch_bounds__(256) k_multi_dot_partial(const T *V, int64_t ld, int m, const T *w, int64_t n,
@@ -143,22 +174,16 @@ __global__ void __launch_bounds__(256) k_multi_dot_partial(const T *V, int64_t l
   const int64_t beg = blockIdx.x * chunk;
   const int64_t end = beg + chunk < n ? beg + chunk : n;
   for (int64_t j = beg + threadIdx.x; j < end; j += blockDim.x) {
+    double v[MM];
+    load_cols<T, MM>(V, ld, m, j, v);
     const double wj = (double)w[j];
 #pragma unroll
-    for (int i = 0; i < MM; ++i)
-      if (i < m) acc[i] += (double)V[i * ld + j] * wj;
+    for (int i = 0; i < MM; ++i) acc[i] += v[i] * wj;
   }
   __shared__ double red[256];
-  for (int i = 0; i < m && i < MM; ++i) {
-    red[threadIdx.x] = acc[i];
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) partials[i * DOT_BLOCKS + blockIdx.x] = red[0];
-    __syncthreads();
-  }
+#pragma unroll
+  for (int i = 0; i < MM; ++i)
+    if (i < m) block_partial(acc[i], i, partials, red);
 }
 
 __global__ void __launch_bounds__(256) k_multi_dot_final(const double *partials, int nb, double *out) {
@@ -175,38 +200,73 @@ __global__ void __launch_bounds__(256) k_multi_dot_final(const double *partials,
   if (threadIdx.x == 0) out[i] = red[0];
 }
 
-template <typename T>
-void multi_dot(const T *V, int64_t ld, int m, const T *w, int64_t n, double *out, double *partials, hipStream_t s) {
-  MFS_REQUIRE(m >= 1 && m <= MAXM, MFS_EINVAL, "multi_dot: m=%d out of range", m);
+// column-group sizes the multi-vector kernels are instantiated for
+#define MFS_MM_DISPATCH(m, KERNEL_LAUNCH) \
+  do {                                    \
+    if ((m) <= 1) {                       \
+      constexpr int MM = 1;               \
+      KERNEL_LAUNCH;                      \
+    } else if ((m) <= 2) {                \
+      constexpr int MM = 2;               \
+      KERNEL_LAUNCH;                      \
+    } else if ((m) <= 4) {                \
+      constexpr int MM = 4;               \
+      KERNEL_LAUNCH;                      \
+    } else if ((m) <= 8) {                \
+      constexpr int MM = 8;               \
+      KERNEL_LAUNCH;                      \
+    } else if ((m) <= 12) {               \
+      constexpr int MM = 12;              \
+      KERNEL_LAUNCH;                      \
+    } else if ((m) <= 16) {               \
+      constexpr int MM = 16;              \
+      KERNEL_LAUNCH;                      \
+    } else if ((m) <= 20) {               \
+      constexpr int MM = 20;              \
+      KERNEL_LAUNCH;                      \
+    } else if ((m) <= 24) {               \
+      constexpr int MM = 24;              \
+      KERNEL_LAUNCH;                      \
+    } else if ((m) <= 28) {               \
+      constexpr int MM = 28;              \
+      KERNEL_LAUNCH;                      \
+    } else {                              \
+      constexpr int MM = 32;              \
+      KERNEL_LAUNCH;                      \
+    }                                     \
+  } while (0)
+
+int dot_blocks(int64_t n) {
   int nb = (int)((n + 2047) / 2048);
-  nb = nb < 1 ? 1 : (nb > DOT_BLOCKS ? DOT_BLOCKS : nb);
-  if (m <= 1)
-    hipLaunchKernelGGL((k_multi_dot_partial<T, 1>), dim3(nb), dim3(256), 0, s, V, ld, m, w, n, partials);
-  else if (m <= 4)
-    hipLaunchKernelGGL((k_multi_dot_partial<T, 4>), dim3(nb), dim3(256), 0, s, V, ld, m, w, n, partials);
-  else if (m <= 8)
-    hipLaunchKernelGGL((k_multi_dot_partial<T, 8>), dim3(nb), dim3(256), 0, s, V, ld, m, w, n, partials);
-  else if (m <= 16)
-    hipLaunchKernelGGL((k_multi_dot_partial<T, 16>), dim3(nb), dim3(256), 0, s, V, ld, m, w, n, partials);
-  else
-    hipLaunchKernelGGL((k_multi_dot_partial<T, 32>), dim3(nb), dim3(256), 0, s, V, ld, m, w, n, partials);
-  hipLaunchKernelGGL(k_multi_dot_final, dim3(m), dim3(256), 0, s, partials, nb, out);
+  return nb < 1 ? 1 : (nb > DOT_BLOCKS ? DOT_BLOCKS : nb);
 }
 
 template <typename T>
-__global__ void k_multi_axpy(T *w, const T *V, int64_t ld, int m, const double *h, int64_t n) {
+void multi_dot(const T *V, int64_t ld, int m, const T *w, int64_t n, double *out, double *partials, hipStream_t s) {
+  MFS_REQUIRE(m >= 1 && m <= MAXM, MFS_EINVAL, "multi_dot: m=%d out of range", m);
+  const int nb = dot_blocks(n);
+  MFS_MM_DISPATCH(m, hipLaunchKernelGGL((k_multi_dot_partial<T, MM>), dim3(nb), dim3(256), 0, s, V, ld, m, w, n,
+                                        partials));
+  hipLaunchKernelGGL(k_multi_dot_final, dim3(m), dim3(256), 0, s, partials, nb, out);
+}
+
+template <typename T, int MM>
+__global__ void __launch_bounds__(VB) k_multi_axpy(T *w, const T *V, int64_t ld, int m, const double *h, int64_t n) {
   __shared__ double sh[MAXM];
-  if ((int)threadIdx.x < m) sh[threadIdx.x] = h[threadIdx.x];
-  __syncthreads();
+  load_coefs(sh, h, m);
   for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+    double v[MM];
+    load_cols<T, MM>(V, ld, m, j, v);
     double acc = (double)w[j];
-    for (int i = 0; i < m; ++i) acc -= sh[i] * (double)V[i * ld + j];
+#pragma unroll
+    for (int i = 0; i < MM; ++i) acc -= sh[i] * v[i];
     w[j] = (T)acc;
   }
 }
 template <typename T>
 void multi_axpy(T *w, const T *V, int64_t ld, int m, const double *h, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_multi_axpy<T>, dim3(nblocks(n)), dim3(VB), 0, s, w, V, ld, m, h, n);
+  MFS_REQUIRE(m >= 1 && m <= MAXM, MFS_EINVAL, "multi_axpy: m=%d out of range", m);
+  MFS_MM_DISPATCH(m, hipLaunchKernelGGL((k_multi_axpy<T, MM>), dim3(nblocks(n)), dim3(VB), 0, s, w, V, ld, m, h, n));
 }
 
 // fused update and dot products (see axpy_dot); the same chunking and
@@ -215,8 +275,7 @@ template <typename T, int MM>
 __global__ void __launch_bounds__(256) k_axpy_dot_partial(T *w, const T *V, int64_t ld, int m, const double *h,
                                                           int md, int norm, int64_t n, double *partials) {
   __shared__ double sh[MAXM];
-  if ((int)threadIdx.x < m) sh[threadIdx.x] = h[threadIdx.x];
-  __syncthreads();
+  load_coefs(sh, h, m);
   double acc[MM + 1];
 #pragma unroll
   for (int i = 0; i <= MM; ++i) acc[i] = 0.0;
@@ -225,70 +284,53 @@ __global__ void __launch_bounds__(256) k_axpy_dot_partial(T *w, const T *V, int6
   const int64_t end = beg + chunk < n ? beg + chunk : n;
   for (int64_t j = beg + threadIdx.x; j < end; j += blockDim.x) {
     double v[MM];
+    load_cols<T, MM>(V, ld, m, j, v);
     double wj = (double)w[j];
 #pragma unroll
-    for (int i = 0; i < MM; ++i)
-      if (i < m) {
-        v[i] = (double)V[i * ld + j];
-        wj -= sh[i] * v[i];
-      }
+    for (int i = 0; i < MM; ++i) wj -= sh[i] * v[i];
     const T wt = (T)wj;
     w[j] = wt;
     const double wd = (double)wt;
 #pragma unroll
-    for (int i = 0; i < MM; ++i)
-      if (i < md) acc[i] += v[i] * wd;
-    if (norm) acc[MM] += wd * wd;
+    for (int i = 0; i < MM; ++i) acc[i] += v[i] * wd;
+    acc[MM] += wd * wd;
   }
   __shared__ double red[256];
-  const int nd = md + (norm ? 1 : 0);
-  for (int k = 0; k < nd; ++k) {
-    double a = 0;
 #pragma unroll
-    for (int i = 0; i <= MM; ++i)
-      if (i == (k < md ? k : MM)) a = acc[i];
-    red[threadIdx.x] = a;
-    __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
-      if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) partials[k * DOT_BLOCKS + blockIdx.x] = red[0];
-    __syncthreads();
-  }
+  for (int i = 0; i < MM; ++i)
+    if (i < md) block_partial(acc[i], i, partials, red);
+  if (norm) block_partial(acc[MM], md, partials, red);
 }
 template <typename T>
 void axpy_dot(T *w, const T *V, int64_t ld, int m, const double *h, int md, bool norm, int64_t n, double *out,
               double *partials, hipStream_t s) {
   MFS_REQUIRE(m >= 1 && m <= MAXM - 1 && (md == 0 || md == m), MFS_EINVAL, "axpy_dot: m=%d md=%d", m, md);
-  int nb = (int)((n + 2047) / 2048);
-  nb = nb < 1 ? 1 : (nb > DOT_BLOCKS ? DOT_BLOCKS : nb);
+  const int nb = dot_blocks(n);
   const int nf = norm ? 1 : 0;
-  if (m <= 4)
-    hipLaunchKernelGGL((k_axpy_dot_partial<T, 4>), dim3(nb), dim3(256), 0, s, w, V, ld, m, h, md, nf, n, partials);
-  else if (m <= 8)
-    hipLaunchKernelGGL((k_axpy_dot_partial<T, 8>), dim3(nb), dim3(256), 0, s, w, V, ld, m, h, md, nf, n, partials);
-  else if (m <= 16)
-    hipLaunchKernelGGL((k_axpy_dot_partial<T, 16>), dim3(nb), dim3(256), 0, s, w, V, ld, m, h, md, nf, n, partials);
-  else
-    hipLaunchKernelGGL((k_axpy_dot_partial<T, 32>), dim3(nb), dim3(256), 0, s, w, V, ld, m, h, md, nf, n, partials);
+  MFS_MM_DISPATCH(m, hipLaunchKernelGGL((k_axpy_dot_partial<T, MM>), dim3(nb), dim3(256), 0, s, w, V, ld, m, h, md,
+                                        nf, n, partials));
   if (md + nf > 0) hipLaunchKernelGGL(k_multi_dot_final, dim3(md + nf), dim3(256), 0, s, partials, nb, out);
 }
 
-template <typename T>
-__global__ void k_multi_combine(T *y, const T *V, int64_t ld, int m, const double *h, int64_t n, int acc_in) {
+template <typename T, int MM>
+__global__ void __launch_bounds__(VB) k_multi_combine(T *y, const T *V, int64_t ld, int m, const double *h, int64_t n,
+                                                      int acc_in) {
   __shared__ double sh[MAXM];
-  if ((int)threadIdx.x < m) sh[threadIdx.x] = h[threadIdx.x];
-  __syncthreads();
+  load_coefs(sh, h, m);
   for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+    double v[MM];
+    load_cols<T, MM>(V, ld, m, j, v);
     double acc = acc_in ? (double)y[j] : 0.0;
-    for (int i = 0; i < m; ++i) acc += sh[i] * (double)V[i * ld + j];
+#pragma unroll
+    for (int i = 0; i < MM; ++i) acc += sh[i] * v[i];
     y[j] = (T)acc;
   }
 }
 template <typename T>
 void multi_combine(T *y, const T *V, int64_t ld, int m, const double *h, int64_t n, bool accumulate, hipStream_t s) {
-  hipLaunchKernelGGL(k_multi_combine<T>, dim3(nblocks(n)), dim3(VB), 0, s, y, V, ld, m, h, n, accumulate ? 1 : 0);
+  MFS_REQUIRE(m >= 1 && m <= MAXM, MFS_EINVAL, "multi_combine: m=%d out of range", m);
+  MFS_MM_DISPATCH(m, hipLaunchKernelGGL((k_multi_combine<T, MM>), dim3(nblocks(n)), dim3(VB), 0, s, y, V, ld, m, h,
+                                        n, accumulate ? 1 : 0));
 }
 
 // out = Ainv in, Ainv symmetric n x n FP64 (column-major = row-major)
