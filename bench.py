@@ -35,7 +35,7 @@ FLOP_PER_DOF = {2: 318.0, 3: 243.0, 4: 217.0}
 # HBM bytes per FP64 Q2/Q1 vmult on 64^3 cells measured with rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (scaled by 2.00 and 1.00, the factors a 256 MiB device copy gives) for the
 # current cell + combine kernels; to be re-measured whenever those kernels change.
-MEASURED_TRAFFIC = {(2, 64, "f64"): 308.4e6}
+MEASURED_TRAFFIC = {(2, 64, "f64"): 308.7e6}
 
 
 def algorithmic_bytes(dim, n, k, word):
@@ -255,12 +255,20 @@ def serving_section(args):
     import inputs
     from paper_2603_29621_amd import serving
 
+    import dataclasses
+
     reqs = inputs.request_stream(args.serve_requests, args.serve_rate, seed=0, sizes=(8, 16, 32), degrees=(2, 3))
     served = serving.Server(200e9).run(reqs)
     seq = serving.run_sequential(reqs)
-    return {"sample": f"{args.serve_requests} requests, Poisson rate {args.serve_rate}/s, n in {{8,16,32}}, "
-                      f"k in {{2,3}}, nu log-uniform [1e-2, 1], noise 0.1h, rtol 1e-8",
-            "served_fp32_mg": serving.summarize(served), "sequential_fp64": serving.summarize(seq)}
+    out = {"sample": f"{args.serve_requests} requests, Poisson rate {args.serve_rate}/s, n in {{8,16,32}}, "
+                     f"k in {{2,3}}, nu log-uniform [1e-2, 1], noise 0.1h, rtol 1e-8",
+           "served_fp32_mg": serving.summarize(served), "sequential_fp64": serving.summarize(seq)}
+    # capacity: the same requests all arriving at t = 0
+    burst = [dataclasses.replace(r, arrival=0.0) for r in reqs]
+    out["burst"] = {"sample": "the same requests, all arriving at t = 0",
+                    "served_fp32_mg": serving.summarize(serving.Server(200e9).run(burst)),
+                    "sequential_fp64": serving.summarize(serving.run_sequential(burst))}
+    return out
 
 
 def main():
