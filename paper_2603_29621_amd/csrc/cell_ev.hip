@@ -46,6 +46,21 @@ __global__ void __launch_bounds__((Shape<3, K, K - 1>::BLOCK)) cell_kernel_ev(Ev
   c.b1 = &s_buf[1][e * NQ];
   c.b2 = &s_buf[2][e * NQ];
   c.tab = s_tab;
+  constexpr bool NEED_U = (MODE & (M_LAPLACE | M_DIVU)) != 0;
+  constexpr bool NEED_P = (MODE & (M_GRADP | M_MASSP)) != 0;
+  constexpr bool OUT_U = (MODE & (M_LAPLACE | M_GRADP)) != 0;
+  constexpr bool OUT_P = (MODE & (M_DIVU | M_MASSP)) != 0;
+  const int64_t ou = c.valid ? a.ev.off_u[cell] : 0;
+  const int64_t op = c.valid ? a.ev.off_p[cell] : 0;
+  const bool ploc = c.p_local();
+  const int jp = c.qi + M * (c.qj + M * c.ql);
+  // source values of every component loaded before the vertex loads and the barrier
+  T su[3] = {0, 0, 0}, sp = 0;
+  if (NEED_U && c.valid) {
+#pragma unroll
+    for (int comp = 0; comp < DIM; ++comp) su[comp] = a.ev.in_u[ou + comp * NQ + c.t];
+  }
+  if (NEED_P && c.valid && ploc) sp = a.ev.in_p[op + jp];
   if (c.valid)
     for (int idx = c.t; idx < Sh::NV * DIM; idx += NQ) {
       const int v = idx / DIM, comp = idx % DIM;
@@ -55,29 +70,18 @@ __global__ void __launch_bounds__((Shape<3, K, K - 1>::BLOCK)) cell_kernel_ev(Ev
     }
   __syncthreads();
 
-  constexpr bool NEED_U = (MODE & (M_LAPLACE | M_DIVU)) != 0;
-  constexpr bool NEED_P = (MODE & (M_GRADP | M_MASSP)) != 0;
-  constexpr bool OUT_U = (MODE & (M_LAPLACE | M_GRADP)) != 0;
-  constexpr bool OUT_P = (MODE & (M_DIVU | M_MASSP)) != 0;
-  const int64_t ou = c.valid ? a.ev.off_u[cell] : 0;
-  const int64_t op = c.valid ? a.ev.off_p[cell] : 0;
-  const bool ploc = c.p_local();
-  const int jp = c.qi + M * (c.qj + M * c.ql);
-
   T g[3][3] = {};
   if (NEED_U) {
 #pragma unroll
     for (int comp = 0; comp < DIM; ++comp) {
-      const T v = c.valid ? a.ev.in_u[ou + comp * NQ + c.t] : T(0);
-      if (c.active) c.b0[c.t] = v;
+      if (c.active) c.b0[c.t] = su[comp];
       csync<Sh::WAVE>();
       c.gradient(g[comp]);
     }
   }
   T pval = 0;
   if (NEED_P) {
-    const T v = (c.valid && ploc) ? a.ev.in_p[op + jp] : T(0);
-    if (c.active) c.b0[c.t] = v;
+    if (c.active) c.b0[c.t] = sp;
     csync<Sh::WAVE>();
     const T *vals = c.template interpolate<M, TAB_SP>();
     pval = vals[c.t];

@@ -62,6 +62,22 @@ __global__ void __launch_bounds__((Shape<DIM, K, KP>::BLOCK)) cell_kernel(CellAr
   c.b1 = &s_buf[1][e * NQ];
   c.b2 = &s_buf[2][e * NQ];
   c.tab = s_tab;
+  const bool dir = c.valid ? c.vel_dirichlet(a.nv0, a.nv1, a.nv2) : true;
+  const int64_t vnode = c.valid ? c.vel_node(a.nv0, a.nv1) : 0;
+  constexpr bool NEED_U = (MODE & (M_LAPLACE | M_DIVU)) != 0;
+  constexpr bool NEED_P = (MODE & (M_GRADP | M_MASSP)) != 0;
+  constexpr bool OUT_U = (MODE & (M_LAPLACE | M_GRADP)) != 0;
+  constexpr bool OUT_P = (MODE & (M_DIVU | M_MASSP)) != 0;
+  const bool ploc = c.p_local();
+  const int64_t pnode = (c.valid && ploc) ? c.p_node(a.np0, a.np1) : 0;
+  // the nodal source values of every component are loaded before the vertex
+  // loads and the barrier, so their latencies overlap
+  T su[3] = {0, 0, 0}, sp = 0;
+  if (NEED_U && c.valid && (a.src_all ? dir : !dir)) {
+#pragma unroll
+    for (int comp = 0; comp < DIM; ++comp) su[comp] = a.src_u[comp * a.Nv + vnode];
+  }
+  if (NEED_P && c.valid && ploc) sp = a.src_p[pnode];
   if (c.valid)
     for (int idx = c.t; idx < Sh::NV * DIM; idx += NQ) {
       const int v = idx / DIM, comp = idx % DIM;
@@ -71,31 +87,18 @@ __global__ void __launch_bounds__((Shape<DIM, K, KP>::BLOCK)) cell_kernel(CellAr
     }
   __syncthreads();
 
-  const bool dir = c.valid ? c.vel_dirichlet(a.nv0, a.nv1, a.nv2) : true;
-  const int64_t vnode = c.valid ? c.vel_node(a.nv0, a.nv1) : 0;
-  constexpr bool NEED_U = (MODE & (M_LAPLACE | M_DIVU)) != 0;
-  constexpr bool NEED_P = (MODE & (M_GRADP | M_MASSP)) != 0;
-  constexpr bool OUT_U = (MODE & (M_LAPLACE | M_GRADP)) != 0;
-  constexpr bool OUT_P = (MODE & (M_DIVU | M_MASSP)) != 0;
-
   T g[3][3] = {};
   if (NEED_U) {
 #pragma unroll
     for (int comp = 0; comp < DIM; ++comp) {
-      T v = 0;
-      if (c.valid && (a.src_all ? dir : !dir)) v = a.src_u[comp * a.Nv + vnode];
-      if (c.active) c.b0[c.t] = v;
+      if (c.active) c.b0[c.t] = su[comp];
       csync<Sh::WAVE>();
       c.gradient(g[comp]);
     }
   }
   T pval = 0;
-  const bool ploc = c.p_local();
-  const int64_t pnode = (c.valid && ploc) ? c.p_node(a.np0, a.np1) : 0;
   if (NEED_P) {
-    T v = 0;
-    if (c.valid && ploc) v = a.src_p[pnode];
-    if (c.active) c.b0[c.t] = v;
+    if (c.active) c.b0[c.t] = sp;
     csync<Sh::WAVE>();
     const T *vals = c.template interpolate<Sh::M, TAB_SP>();
     pval = vals[c.t];

@@ -238,6 +238,14 @@ __device__ __forceinline__ T laplacian(const T h[6], const T I[3][3]) {
   c.b1 = &s_buf[1][e * NQ];                                                                            \
   c.b2 = &s_buf[2][e * NQ];                                                                            \
   c.tab = s_tab;                                                                                       \
+  const int64_t nd = c.valid ? c.node(a.nv0, a.nv1) : 0;                                               \
+  const bool dir = c.valid ? c.dirichlet(a.nv0, a.nv1, a.nv2) : true;                                  \
+  T *qd = a.qd + ((int64_t)(c.valid ? cell : 0) * NS_QD) * NQ + c.t;
+
+// second half of the prologue: vertices to LDS, barrier, geometry at the
+// point (global loads a kernel issues between the two halves overlap the
+// vertex loads and the barrier)
+#define NSK_PROLOGUE_B                                                                                 \
   if (c.valid)                                                                                         \
     for (int idx = c.t; idx < Sh::NV * DIM; idx += NQ) {                                               \
       const int v_ = idx / DIM, comp_ = idx % DIM;                                                     \
@@ -251,15 +259,13 @@ __device__ __forceinline__ T laplacian(const T h[6], const T I[3][3]) {
   const T det = jac_inv<DIM>(s_X[e], xi, I);                                                           \
   T wq = s_tab[TAB_W + c.qi] * s_tab[TAB_W + c.qj];                                                    \
   if (DIM == 3) wq *= s_tab[TAB_W + c.ql];                                                             \
-  const T JxW = det * wq;                                                                              \
-  const int64_t nd = c.valid ? c.node(a.nv0, a.nv1) : 0;                                               \
-  const bool dir = c.valid ? c.dirichlet(a.nv0, a.nv1, a.nv2) : true;                                  \
-  T *qd = a.qd + ((int64_t)(c.valid ? cell : 0) * NS_QD) * NQ + c.t;
+  const T JxW = det * wq;
 
 // linearisation data at the quadrature points from the nodal velocity u0
 template <int DIM, int K, typename T>
 __global__ void __launch_bounds__((Shape<DIM, K>::BLOCK)) ns_linearize_kernel(Args<T> a) {
   NSK_PROLOGUE
+  NSK_PROLOGUE_B
   __shared__ T s_vol[CPB];
   T u[3] = {}, U[3][3] = {}, lap[3] = {};
   for (int comp = 0; comp < DIM; ++comp) {
@@ -306,19 +312,24 @@ __global__ void __launch_bounds__((Shape<DIM, K>::BLOCK)) ns_linearize_kernel(Ar
 template <int DIM, int K, typename T>
 __global__ void __launch_bounds__((Shape<DIM, K>::BLOCK)) ns_jacobian_kernel(Args<T> a) {
   NSK_PROLOGUE
-  // linearisation data of this point
+  // every global load of the point (nodal source values of the 4 fields,
+  // linearisation data) is issued before the vertex loads and the barrier
+  T sv[4] = {0, 0, 0, 0};
   T u0[3] = {}, U[3][3] = {}, R0[3] = {}, dl = 0;
   if (c.valid) {
+    for (int comp = 0; comp < DIM; ++comp) sv[comp] = dir ? T(0) : a.src[comp * a.Nv + nd];
+    sv[DIM] = a.src[DIM * a.Nv + nd];
     for (int x = 0; x < DIM; ++x) u0[x] = qd[x * NQ];
     for (int cc = 0; cc < DIM; ++cc)
       for (int x = 0; x < DIM; ++x) U[cc][x] = qd[(3 + 3 * cc + x) * NQ];
     for (int x = 0; x < DIM; ++x) R0[x] = qd[(12 + x) * NQ];
     dl = qd[15 * NQ];
   }
+  NSK_PROLOGUE_B
   // trial fields
   T w[3] = {}, G[3][3] = {}, L[3] = {};
   for (int comp = 0; comp < DIM; ++comp) {
-    if (c.active) c.b0[c.t] = (c.valid && !dir) ? a.src[comp * a.Nv + nd] : T(0);
+    if (c.active) c.b0[c.t] = sv[comp];
     csync<Sh::WAVE>();
     T val, g[3], h[6];
     c.template evaluate<true>(val, g, h);
@@ -332,7 +343,7 @@ __global__ void __launch_bounds__((Shape<DIM, K>::BLOCK)) ns_jacobian_kernel(Arg
   }
   T P, gP[3] = {};
   {
-    if (c.active) c.b0[c.t] = c.valid ? a.src[DIM * a.Nv + nd] : T(0);
+    if (c.active) c.b0[c.t] = sv[DIM];
     csync<Sh::WAVE>();
     T g[3], h[6];
     c.template evaluate<false>(P, g, h);
@@ -388,6 +399,7 @@ __global__ void __launch_bounds__((Shape<DIM, K>::BLOCK)) ns_jacobian_kernel(Arg
 }
 
 #undef NSK_PROLOGUE
+#undef NSK_PROLOGUE_B
 
 }  // namespace nsk
 
