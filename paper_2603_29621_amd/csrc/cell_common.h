@@ -160,6 +160,11 @@ struct CellCtx {
   bool valid, active;
   T *b0, *b1, *b2;
   const T *tab;
+  // buffer i of this cell = bb + i * bstride (the batched sweeps below use
+  // up to max(2, DIM) * NC of them; b0, b1, b2 are buffers 0, 1, 2)
+  T *bb = nullptr;
+  int bstride = 0;
+  __device__ __forceinline__ T *buf(int i) const { return bb + i * bstride; }
 
   __device__ __forceinline__ bool vel_dirichlet(int nv0, int nv1, int nv2) const {
     const int gx = cx * K + qi, gy = cy * K + qj, gz = cz * K + ql;
@@ -233,6 +238,96 @@ struct CellCtx {
     pin(g[0]);
     pin(g[1]);
     if (DIM == 3) pin(g[2]);
+    csync<Sh::WAVE>();
+  }
+
+  // Reference gradients of NC fields at point t.  On entry buffer i (i < NC)
+  // holds the nodal values of field i and the caller has synchronised; the
+  // fields pass through every sweep together, one synchronisation per pass.
+  template <int NC>
+  __device__ __forceinline__ void gradients(T g[][3]) {
+    const T *S = tab + TAB_S, *D = tab + TAB_D;
+    T v[NC];
+#pragma unroll
+    for (int i = 0; i < NC; ++i) v[i] = sweep<DIM, Q, 0, N, false>(buf(i), S, qi, qj, ql);
+#pragma unroll
+    for (int i = 0; i < NC; ++i)
+      if (active) buf(NC + i)[t] = v[i];
+    csync<Sh::WAVE>();
+#pragma unroll
+    for (int i = 0; i < NC; ++i) v[i] = sweep<DIM, Q, 1, N, false>(buf(NC + i), S, qi, qj, ql);
+#pragma unroll
+    for (int i = 0; i < NC; ++i)
+      if (active) buf(i)[t] = v[i];
+    csync<Sh::WAVE>();
+    int vb = 0;  // buffer offset of the point values
+    if (DIM == 3) {
+#pragma unroll
+      for (int i = 0; i < NC; ++i) v[i] = sweep<DIM, Q, 2, N, false>(buf(i), S, qi, qj, ql);
+#pragma unroll
+      for (int i = 0; i < NC; ++i)
+        if (active) buf(NC + i)[t] = v[i];
+      csync<Sh::WAVE>();
+      vb = NC;
+    }
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+      g[i][0] = sweep<DIM, Q, 0, Q, false>(buf(vb + i), D, qi, qj, ql);
+      g[i][1] = sweep<DIM, Q, 1, Q, false>(buf(vb + i), D, qi, qj, ql);
+      if (DIM == 3) g[i][2] = sweep<DIM, Q, 2, Q, false>(buf(vb + i), D, qi, qj, ql);
+      pin(g[i][0]);
+      pin(g[i][1]);
+      if (DIM == 3) pin(g[i][2]);
+    }
+    csync<Sh::WAVE>();
+  }
+
+  // Transposed: nodal results r[i] = sum_q f_i,b(q) d_b phi(q) of NC fields,
+  // all fields per pass (buffers 0 .. DIM*NC-1)
+  template <int NC>
+  __device__ __forceinline__ void integrate_gradients(const T f[][3], T r[]) {
+    const T *S = tab + TAB_S, *D = tab + TAB_D;
+#pragma unroll
+    for (int i = 0; i < NC; ++i)
+#pragma unroll
+      for (int b = 0; b < DIM; ++b)
+        if (active) buf(DIM * i + b)[t] = f[i][b];
+    csync<Sh::WAVE>();
+    T v[NC];
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+      v[i] = sweep<DIM, Q, 0, Q, true>(buf(DIM * i), D, qi, qj, ql) +
+             sweep<DIM, Q, 1, Q, true>(buf(DIM * i + 1), D, qi, qj, ql);
+      if (DIM == 3) v[i] += sweep<DIM, Q, 2, Q, true>(buf(DIM * i + 2), D, qi, qj, ql);
+      pin(v[i]);
+    }
+    csync<Sh::WAVE>();
+#pragma unroll
+    for (int i = 0; i < NC; ++i)
+      if (active) buf(i)[t] = v[i];
+    csync<Sh::WAVE>();
+    int src = 0;
+    if (DIM == 3) {
+#pragma unroll
+      for (int i = 0; i < NC; ++i) v[i] = sweep<DIM, Q, 2, Q, true>(buf(i), S, qi, qj, ql);
+#pragma unroll
+      for (int i = 0; i < NC; ++i)
+        if (active) buf(NC + i)[t] = v[i];
+      csync<Sh::WAVE>();
+      src = NC;
+    }
+#pragma unroll
+    for (int i = 0; i < NC; ++i) v[i] = sweep<DIM, Q, 1, Q, true>(buf(src + i), S, qi, qj, ql);
+    const int dstb = src == 0 ? NC : 0;
+#pragma unroll
+    for (int i = 0; i < NC; ++i)
+      if (active) buf(dstb + i)[t] = v[i];
+    csync<Sh::WAVE>();
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+      r[i] = sweep<DIM, Q, 0, Q, true>(buf(dstb + i), S, qi, qj, ql);
+      pin(r[i]);
+    }
     csync<Sh::WAVE>();
   }
 

@@ -25,7 +25,8 @@ __global__ void __launch_bounds__((Shape<3, K, K - 1>::BLOCK)) cell_kernel_ev(Ev
   using Sh = Shape<DIM, K, K - 1>;
   constexpr int NQ = Sh::NQ, CPB = Sh::CPB, Q = Sh::Q, M = Sh::M;
   __shared__ T s_tab[TAB_SIZE];
-  __shared__ T s_buf[3][CPB * NQ];
+  constexpr int NBUF = DIM * DIM > 3 ? DIM * DIM : 3;  // batched sweeps of DIM fields
+  __shared__ T s_buf[NBUF][CPB * NQ];
   __shared__ T s_X[CPB][Sh::NV * DIM];
 
   const int tid = threadIdx.x;
@@ -45,6 +46,8 @@ __global__ void __launch_bounds__((Shape<3, K, K - 1>::BLOCK)) cell_kernel_ev(Ev
   c.b0 = &s_buf[0][e * NQ];
   c.b1 = &s_buf[1][e * NQ];
   c.b2 = &s_buf[2][e * NQ];
+  c.bb = &s_buf[0][e * NQ];
+  c.bstride = CPB * NQ;
   c.tab = s_tab;
   constexpr bool NEED_U = (MODE & (M_LAPLACE | M_DIVU)) != 0;
   constexpr bool NEED_P = (MODE & (M_GRADP | M_MASSP)) != 0;
@@ -73,11 +76,10 @@ __global__ void __launch_bounds__((Shape<3, K, K - 1>::BLOCK)) cell_kernel_ev(Ev
   T g[3][3] = {};
   if (NEED_U) {
 #pragma unroll
-    for (int comp = 0; comp < DIM; ++comp) {
-      if (c.active) c.b0[c.t] = su[comp];
-      csync<Sh::WAVE>();
-      c.gradient(g[comp]);
-    }
+    for (int comp = 0; comp < DIM; ++comp)
+      if (c.active) c.buf(comp)[c.t] = su[comp];
+    csync<Sh::WAVE>();
+    c.template gradients<DIM>(g);
   }
   T pval = 0;
   if (NEED_P) {
@@ -135,11 +137,11 @@ __global__ void __launch_bounds__((Shape<3, K, K - 1>::BLOCK)) cell_kernel_ev(Ev
   if (MODE & M_MASSP) qv += JxW * pval;
 
   if (OUT_U) {
+    T r[3];
+    c.template integrate_gradients<DIM>(f, r);
 #pragma unroll
-    for (int comp = 0; comp < DIM; ++comp) {
-      const T r = c.integrate_gradient(f[comp]);
-      if (c.valid) a.ev.out_u[ou + comp * NQ + c.t] = r;
-    }
+    for (int comp = 0; comp < DIM; ++comp)
+      if (c.valid) a.ev.out_u[ou + comp * NQ + c.t] = r[comp];
   }
   if (OUT_P) {
     if (c.active) c.b0[c.t] = qv;

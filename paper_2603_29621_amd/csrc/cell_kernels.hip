@@ -38,7 +38,8 @@ __global__ void __launch_bounds__((Shape<DIM, K, KP>::BLOCK)) cell_kernel(CellAr
   using Sh = Shape<DIM, K, KP>;
   constexpr int NQ = Sh::NQ, CPB = Sh::CPB, Q = Sh::Q;
   __shared__ T s_tab[TAB_SIZE];
-  __shared__ T s_buf[3][CPB * NQ];
+  constexpr int NBUF = DIM * DIM > 3 ? DIM * DIM : 3;  // batched sweeps of DIM fields
+  __shared__ T s_buf[NBUF][CPB * NQ];
   __shared__ T s_X[CPB][Sh::NV * DIM];
 
   const int tid = threadIdx.x;
@@ -61,6 +62,8 @@ __global__ void __launch_bounds__((Shape<DIM, K, KP>::BLOCK)) cell_kernel(CellAr
   c.b0 = &s_buf[0][e * NQ];
   c.b1 = &s_buf[1][e * NQ];
   c.b2 = &s_buf[2][e * NQ];
+  c.bb = &s_buf[0][e * NQ];
+  c.bstride = CPB * NQ;
   c.tab = s_tab;
   const bool dir = c.valid ? c.vel_dirichlet(a.nv0, a.nv1, a.nv2) : true;
   const int64_t vnode = c.valid ? c.vel_node(a.nv0, a.nv1) : 0;
@@ -90,11 +93,10 @@ __global__ void __launch_bounds__((Shape<DIM, K, KP>::BLOCK)) cell_kernel(CellAr
   T g[3][3] = {};
   if (NEED_U) {
 #pragma unroll
-    for (int comp = 0; comp < DIM; ++comp) {
-      if (c.active) c.b0[c.t] = su[comp];
-      csync<Sh::WAVE>();
-      c.gradient(g[comp]);
-    }
+    for (int comp = 0; comp < DIM; ++comp)
+      if (c.active) c.buf(comp)[c.t] = su[comp];
+    csync<Sh::WAVE>();
+    c.template gradients<DIM>(g);
   }
   T pval = 0;
   if (NEED_P) {
@@ -155,11 +157,11 @@ __global__ void __launch_bounds__((Shape<DIM, K, KP>::BLOCK)) cell_kernel(CellAr
   if (MODE & M_MASSP) qv += JxW * pval;
 
   if (OUT_U) {
+    T r[3];
+    c.template integrate_gradients<DIM>(f, r);
 #pragma unroll
-    for (int comp = 0; comp < DIM; ++comp) {
-      const T r = c.integrate_gradient(f[comp]);
-      if (c.valid && !dir) atomic_add(a.dst_u + comp * a.Nv + vnode, r);
-    }
+    for (int comp = 0; comp < DIM; ++comp)
+      if (c.valid && !dir) atomic_add(a.dst_u + comp * a.Nv + vnode, r[comp]);
   }
   if (OUT_P) {
     if (c.active) c.b0[c.t] = qv;
