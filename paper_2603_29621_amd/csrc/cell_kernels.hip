@@ -31,6 +31,9 @@ struct CellArgs {
   T *dst_p;
   T nu;
   int src_all;  // 1: read source values on Dirichlet rows only (the lifting of boundary data)
+  // cell-local outputs (velocity [cell][dim][(k+1)^dim], pressure
+  // [cell][(kp+1)^dim]) instead of atomic additions into dst, when non-null
+  T *ev_u, *ev_p;
 };
 
 template <int DIM, int K, int KP, typename T, int MODE>
@@ -159,15 +162,26 @@ __global__ void __launch_bounds__((Shape<DIM, K, KP>::BLOCK)) cell_kernel(CellAr
   if (OUT_U) {
     T r[3];
     c.template integrate_gradients<DIM>(f, r);
+    if (a.ev_u) {
+      if (c.valid)
 #pragma unroll
-    for (int comp = 0; comp < DIM; ++comp)
-      if (c.valid && !dir) atomic_add(a.dst_u + comp * a.Nv + vnode, r[comp]);
+        for (int comp = 0; comp < DIM; ++comp) a.ev_u[((int64_t)cell * DIM + comp) * NQ + c.t] = r[comp];
+    } else {
+#pragma unroll
+      for (int comp = 0; comp < DIM; ++comp)
+        if (c.valid && !dir) atomic_add(a.dst_u + comp * a.Nv + vnode, r[comp]);
+    }
   }
   if (OUT_P) {
     if (c.active) c.b0[c.t] = qv;
     csync<Sh::WAVE>();
     const T r = c.template integrate<Sh::M, TAB_SP>(c.b0);
-    if (c.valid && ploc) atomic_add(a.dst_p + pnode, r);
+    if (a.ev_p) {
+      constexpr int M = Sh::M, MP = DIM == 3 ? M * M * M : M * M;
+      if (c.valid && ploc) a.ev_p[(int64_t)cell * MP + c.qi + M * (c.qj + M * c.ql)] = r;
+    } else if (c.valid && ploc) {
+      atomic_add(a.dst_p + pnode, r);
+    }
   }
 }
 
@@ -580,6 +594,102 @@ void launch_load_vector(const LevelGeom &g, const double *X, const double *tab, 
 }
 
 // ---------------------------------------------------------------- Dirichlet fill
+// Node gather of cell-local results (3D): every row of dst_u (Dirichlet rows
+// = dir_src, or 0) and of dst_p is the sum of the contributions of the cells
+// that contain the node, in a fixed order (z, y, x cell index), so the result
+// is deterministic.  Along one direction a node at grid index x of a degree-d
+// grid lies in cells x/d - 1 (local index d) and x/d (local 0) when d divides
+// x, otherwise in cell x/d at local index x % d.
+__device__ __forceinline__ int node_cells(int x, int d, int ncell, int cell[2], int loc[2]) {
+  const int c = x / d, l = x - c * d;
+  int cnt = 0;
+  if (l == 0 && c >= 1) {
+    cell[cnt] = c - 1;
+    loc[cnt++] = d;
+  }
+  if (c < ncell) {
+    cell[cnt] = c;
+    loc[cnt++] = l;
+  }
+  return cnt;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) cell_gather_kernel(CellArgs<T> a, int k, int kp, T *dst_u, T *dst_p,
+                                                           const T *dir_src) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int Q = k + 1, NQ = Q * Q * Q;
+  if (dst_u && i < a.Nv) {
+    const int gx = (int)(i % a.nv0);
+    const int64_t r = i / a.nv0;
+    const int gy = (int)(r % a.nv1), gz = (int)(r / a.nv1);
+    if (gx == 0 || gy == 0 || gz == 0 || gx == a.nv0 - 1 || gy == a.nv1 - 1 || gz == a.nv2 - 1) {
+      for (int c = 0; c < 3; ++c) dst_u[c * a.Nv + i] = dir_src ? dir_src[c * a.Nv + i] : T(0);
+    } else {
+      int cx[2], lx[2], cy[2], ly[2], cz[2], lz[2];
+      const int nx = node_cells(gx, k, a.n0, cx, lx), ny = node_cells(gy, k, a.n1, cy, ly),
+                nz = node_cells(gz, k, a.n2, cz, lz);
+      T acc[3] = {0, 0, 0};
+      for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+          for (int x = 0; x < nx; ++x) {
+            const int64_t cell = cx[x] + (int64_t)a.n0 * (cy[y] + (int64_t)a.n1 * cz[z]);
+            const int loc = lx[x] + Q * (ly[y] + Q * lz[z]);
+            for (int c = 0; c < 3; ++c) acc[c] += a.ev_u[(cell * 3 + c) * NQ + loc];
+          }
+      for (int c = 0; c < 3; ++c) dst_u[c * a.Nv + i] = acc[c];
+    }
+  }
+  if (dst_p && i < a.Np) {
+    const int M = kp + 1, MP = M * M * M;
+    const int px = (int)(i % a.np0);
+    const int64_t r = i / a.np0;
+    const int py = (int)(r % a.np1), pz = (int)(r / a.np1);
+    int cx[2], lx[2], cy[2], ly[2], cz[2], lz[2];
+    const int nx = node_cells(px, kp, a.n0, cx, lx), ny = node_cells(py, kp, a.n1, cy, ly),
+              nz = node_cells(pz, kp, a.n2, cz, lz);
+    T acc = 0;
+    for (int z = 0; z < nz; ++z)
+      for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+          const int64_t cell = cx[x] + (int64_t)a.n0 * (cy[y] + (int64_t)a.n1 * cz[z]);
+          acc += a.ev_p[cell * MP + lx[x] + M * (ly[y] + M * lz[z])];
+        }
+    dst_p[i] = acc;
+  }
+}
+
+int64_t cell_ev_elems(const LevelGeom &g) {
+  if (g.dim != 3 || g.k < 3) return 0;
+  const int64_t q = g.k + 1, m = g.kp > 0 ? g.kp + 1 : 0;
+  return g.ncells * (3 * q * q * q + m * m * m);
+}
+
+template <typename T>
+void launch_cell_op_gather(const LevelGeom &g, const DevLevel<T> &d, int mode, T nu, T *dst_u, T *dst_p,
+                           const T *src_u, const T *src_p, const T *dir_src, T *ev, hipStream_t s) {
+  MFS_REQUIRE(g.dim == 3 && g.k >= 3 && ev != nullptr, MFS_EINVAL, "cell gather needs a 3D level of degree >= 3");
+  CellArgs<T> a = make_args<T>(g, d.X, d.tab);
+  a.nu = nu;
+  a.src_u = src_u;
+  a.src_p = src_p;
+  a.ev_u = ev;
+  const int64_t q = g.k + 1;
+  a.ev_p = ev + g.ncells * 3 * q * q * q;
+  dispatch_k<3, T>(a, g.k, g.kp, mode, s);
+  const bool out_u = mode & (M_LAPLACE | M_GRADP), out_p = mode & (M_DIVU | M_MASSP);
+  const int64_t n = std::max<int64_t>(out_u ? g.Nv : 0, out_p ? g.Np : 0);
+  if (n > 0)
+    hipLaunchKernelGGL((cell_gather_kernel<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, g.k, g.kp,
+                       out_u ? dst_u : (T *)nullptr, out_p ? dst_p : (T *)nullptr, dir_src);
+  MFS_HIP(hipGetLastError());
+}
+template void launch_cell_op_gather<double>(const LevelGeom &, const DevLevel<double> &, int, double, double *,
+                                            double *, const double *, const double *, const double *, double *,
+                                            hipStream_t);
+template void launch_cell_op_gather<float>(const LevelGeom &, const DevLevel<float> &, int, float, float *, float *,
+                                           const float *, const float *, const float *, float *, hipStream_t);
+
 template <typename T>
 __global__ void fill_dirichlet_kernel(int dim, int nv0, int nv1, int nv2, int64_t Nv, T *dst, const T *src) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

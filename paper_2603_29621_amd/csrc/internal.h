@@ -89,6 +89,14 @@ enum CellMode : int {
 template <typename T>
 void launch_cell_op(const LevelGeom &g, const DevLevel<T> &d, int mode, T nu, T *dst_u, T *dst_p,
                     const T *src_u, const T *src_p, hipStream_t s, bool src_all = false);  // src_all: lifting (Dirichlet nodes only)
+// generic cell operator (3D, degree >= 3) with cell-local outputs and a
+// deterministic node gather instead of atomic additions: every row of dst_u
+// (Dirichlet rows = dir_src, 0 when null) and of dst_p is written; `ev` is a
+// scratch buffer of cell_ev_elems(g) elements
+int64_t cell_ev_elems(const LevelGeom &g);
+template <typename T>
+void launch_cell_op_gather(const LevelGeom &g, const DevLevel<T> &d, int mode, T nu, T *dst_u, T *dst_p,
+                           const T *src_u, const T *src_p, const T *dir_src, T *ev, hipStream_t s);
 // specialised 3D degree-2 kernel, writing every entry of its velocity output
 // itself: Q2_STOKES (Stokes Q2/Q1: dst_u = A src_u + B src_p, dst_p = B^T
 // src_u; Dirichlet rows dst_u = src_u), Q2_A (dst_u = A src_u, Dirichlet rows
