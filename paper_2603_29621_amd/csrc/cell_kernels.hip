@@ -659,6 +659,36 @@ __global__ void __launch_bounds__(256) cell_gather_kernel(CellArgs<T> a, int k, 
   }
 }
 
+template <typename T>
+void launch_node_gather(const LevelGeom &g, int k, int kp, T *ev_u, T *ev_p, T *dst_u, T *dst_p, const T *dir_src,
+                        hipStream_t s) {
+  MFS_REQUIRE(g.dim == 3, MFS_EINVAL, "node gather is 3D");
+  CellArgs<T> a{};
+  a.n0 = g.n[0];
+  a.n1 = g.n[1];
+  a.n2 = g.n[2];
+  a.ncells = (int)g.ncells;
+  a.nv0 = k * g.n[0] + 1;
+  a.nv1 = k * g.n[1] + 1;
+  a.nv2 = k * g.n[2] + 1;
+  a.np0 = kp * g.n[0] + 1;
+  a.np1 = kp * g.n[1] + 1;
+  a.np2 = kp * g.n[2] + 1;
+  a.Nv = (int64_t)a.nv0 * a.nv1 * a.nv2;
+  a.Np = (int64_t)a.np0 * a.np1 * a.np2;
+  a.ev_u = ev_u;
+  a.ev_p = ev_p;
+  const int64_t n = std::max<int64_t>(dst_u ? a.Nv : 0, dst_p ? a.Np : 0);
+  if (n > 0)
+    hipLaunchKernelGGL((cell_gather_kernel<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, k, kp, dst_u,
+                       dst_p, dir_src);
+  MFS_HIP(hipGetLastError());
+}
+template void launch_node_gather<double>(const LevelGeom &, int, int, double *, double *, double *, double *,
+                                         const double *, hipStream_t);
+template void launch_node_gather<float>(const LevelGeom &, int, int, float *, float *, float *, float *, const float *,
+                                        hipStream_t);
+
 int64_t cell_ev_elems(const LevelGeom &g) {
   if (g.dim != 3 || g.k < 3) return 0;
   const int64_t q = g.k + 1, m = g.kp > 0 ? g.kp + 1 : 0;

@@ -89,6 +89,12 @@ enum CellMode : int {
 template <typename T>
 void launch_cell_op(const LevelGeom &g, const DevLevel<T> &d, int mode, T nu, T *dst_u, T *dst_p,
                     const T *src_u, const T *src_p, hipStream_t s, bool src_all = false);  // src_all: lifting (Dirichlet nodes only)
+// node gather of cell-local results on a 3D structured grid: velocity
+// [cell][3][(k+1)^3] into the degree-k grid (Dirichlet rows = dir_src, 0 when
+// null), pressure [cell][(kp+1)^3] into the degree-kp grid; fixed order
+template <typename T>
+void launch_node_gather(const LevelGeom &g, int k, int kp, T *ev_u, T *ev_p, T *dst_u, T *dst_p, const T *dir_src,
+                        hipStream_t s);
 // generic cell operator (3D, degree >= 3) with cell-local outputs and a
 // deterministic node gather instead of atomic additions: every row of dst_u
 // (Dirichlet rows = dir_src, 0 when null) and of dst_p is written; `ev` is a
@@ -163,10 +169,13 @@ inline int64_t ns_qd_elems(const LevelGeom &g) {
 }
 // what = 0: qd = linearisation data of the nodal velocity src (dim*Nv);
 // what = 1: dst += J src on the free velocity rows and all pressure rows
-// (src, dst full equal-order vectors; the Dirichlet rows of dst untouched)
+// (src, dst full equal-order vectors; the Dirichlet rows of dst untouched);
+// with ev (3D, ncells * 4 * (k+1)^3 elements) the cell results are written
+// there instead ([cell][3][(k+1)^3] velocity, then [cell][(k+1)^3] pressure)
+// and dst is not touched
 template <typename T>
 void launch_ns(const LevelGeom &g, const T *X, const T *tab, int what, T nu, T dt, int newton, const T *src, T *dst,
-               T *qd, hipStream_t s);
+               T *qd, hipStream_t s, T *ev = nullptr);
 // coarse velocity = fine velocity at the shared nodes (fine index 2 * coarse
 // index per direction; h-coarsening at k <= 2 and p-coarsening 2 -> 1)
 void launch_ns_inject(const LevelGeom &fine, const LevelGeom &coarse, const double *u_fine, double *u_coarse,

@@ -38,6 +38,7 @@ struct Args {
   T *qd;
   T nu, alpha, dt;
   int newton;
+  T *ev;  // cell-local outputs instead of atomics when non-null (3D)
 };
 
 template <int DIM, typename T>
@@ -384,7 +385,11 @@ __global__ void __launch_bounds__((Shape<DIM, K>::BLOCK)) ns_jacobian_kernel(Arg
       f[b] = JxW * s;
     }
     const T r = c.integrate(JxW * val_u[comp], f);
-    if (c.valid && !dir) atomicAdd(a.dst + comp * a.Nv + nd, r);
+    if (a.ev) {
+      if (c.valid) a.ev[((int64_t)cell * 3 + comp) * NQ + c.t] = r;
+    } else if (c.valid && !dir) {
+      atomicAdd(a.dst + comp * a.Nv + nd, r);
+    }
   }
   {
     T f[3] = {};
@@ -394,7 +399,11 @@ __global__ void __launch_bounds__((Shape<DIM, K>::BLOCK)) ns_jacobian_kernel(Arg
       f[b] = JxW * s;
     }
     const T r = c.integrate(JxW * div, f);
-    if (c.valid) atomicAdd(a.dst + DIM * a.Nv + nd, r);
+    if (a.ev) {
+      if (c.valid) a.ev[(int64_t)a.ncells * 3 * NQ + (int64_t)cell * NQ + c.t] = r;
+    } else if (c.valid) {
+      atomicAdd(a.dst + DIM * a.Nv + nd, r);
+    }
   }
 }
 
@@ -405,7 +414,7 @@ __global__ void __launch_bounds__((Shape<DIM, K>::BLOCK)) ns_jacobian_kernel(Arg
 
 template <typename T>
 void launch_ns(const LevelGeom &g, const T *X, const T *tab, int what, T nu, T dt, int newton, const T *src, T *dst,
-               T *qd, hipStream_t s) {
+               T *qd, hipStream_t s, T *ev) {
   MFS_REQUIRE(g.kp == g.k, MFS_EUNSUPPORTED, "Navier-Stokes operator needs equal-order elements");
   nsk::Args<T> a{};
   a.n0 = g.n[0];
@@ -425,6 +434,8 @@ void launch_ns(const LevelGeom &g, const T *X, const T *tab, int what, T nu, T d
   a.dt = dt;
   a.alpha = T(1.5) / dt;
   a.newton = newton;
+  MFS_REQUIRE(ev == nullptr || g.dim == 3, MFS_EINVAL, "cell-local Navier-Stokes outputs are 3D");
+  a.ev = ev;
 #define NS_GO(D, KK)                                                                                             \
   {                                                                                                              \
     using Sh = nsk::Shape<D, KK>;                                                                                \
@@ -446,9 +457,9 @@ void launch_ns(const LevelGeom &g, const T *X, const T *tab, int what, T nu, T d
 }
 
 template void launch_ns<double>(const LevelGeom &, const double *, const double *, int, double, double, int,
-                                const double *, double *, double *, hipStream_t);
+                                const double *, double *, double *, hipStream_t, double *);
 template void launch_ns<float>(const LevelGeom &, const float *, const float *, int, float, float, int, const float *,
-                               float *, float *, hipStream_t);
+                               float *, float *, hipStream_t, float *);
 
 namespace {
 
