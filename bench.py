@@ -112,7 +112,7 @@ def solve_section(mfs, torch, inputs, args):
     req = inputs.Request(0, 0.0, n, k, 1.0, 0.2, 0)
     out = {"workload": f"3D Stokes Q2/Q1 {n}^3 cells, vertex noise 0.2h, nu=1, manufactured solution, rtol 1e-8"}
     for name, prec in (("fp32_mg_fp64_fgmres", mfs.MFS_FP32), ("fp64", mfs.MFS_FP64)):
-        opts = mfs.mfs_default_options(precond_precision=prec, rtol=1e-8, maxit=300)
+        opts = mfs.mfs_default_options(precond_precision=prec, rtol=1e-8, maxit=300, graphs=args.graphs)
         s = torch.cuda.Stream()
         t0 = time.perf_counter()
         h, b, x = serving._setup_request(req, opts, s)
@@ -173,7 +173,8 @@ def ns_section(mfs, torch, inputs, args):
     X = inputs.structured_vertices(3, [n] * 3)
     solve = {"workload": f"Q2Q2 {n}^3, J x = J y, rtol 1e-8, monolithic MG (h then p, 5 Jacobi sweeps, omega 0.5)"}
     for name, prec in (("fp32_mg_fp64_fgmres", mfs.MFS_FP32), ("fp64", mfs.MFS_FP64)):
-        opts = mfs.mfs_default_options(pressure_offset=0, precond_precision=prec, rtol=1e-8, maxit=200)
+        opts = mfs.mfs_default_options(pressure_offset=0, precond_precision=prec, rtol=1e-8, maxit=200,
+                                       graphs=args.graphs)
         t0 = time.perf_counter()
         h = mfs.mfs_setup(3, [n] * 3, X, k, nu, opts)
         try:
@@ -216,7 +217,7 @@ def hp_section(mfs, torch, inputs, args):
                        f"vertex noise 0.1h, nu=1",
            "degree_histogram": {int(k): int((deg == k).sum()) for k in range(2, 7)}}
     for name, prec in (("fp32_mg_fp64_fgmres", mfs.MFS_FP32), ("fp64", mfs.MFS_FP64)):
-        opts = mfs.mfs_default_options(precond_precision=prec, rtol=1e-8, maxit=300)
+        opts = mfs.mfs_default_options(precond_precision=prec, rtol=1e-8, maxit=300, graphs=args.graphs)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         h = mfs.mfs_setup_hp([n] * 3, X, deg, 1.0, opts)
@@ -258,7 +259,7 @@ def serving_section(args):
     import dataclasses
 
     reqs = inputs.request_stream(args.serve_requests, args.serve_rate, seed=0, sizes=(8, 16, 32), degrees=(2, 3))
-    served = serving.Server(200e9).run(reqs)
+    served = serving.Server(200e9, graphs=args.graphs).run(reqs)
     seq = serving.run_sequential(reqs)
     out = {"sample": f"{args.serve_requests} requests, Poisson rate {args.serve_rate}/s, n in {{8,16,32}}, "
                      f"k in {{2,3}}, nu log-uniform [1e-2, 1], noise 0.1h, rtol 1e-8",
@@ -266,7 +267,7 @@ def serving_section(args):
     # capacity: the same requests all arriving at t = 0
     burst = [dataclasses.replace(r, arrival=0.0) for r in reqs]
     out["burst"] = {"sample": "the same requests, all arriving at t = 0",
-                    "served_fp32_mg": serving.summarize(serving.Server(200e9).run(burst)),
+                    "served_fp32_mg": serving.summarize(serving.Server(200e9, graphs=args.graphs).run(burst)),
                     "sequential_fp64": serving.summarize(serving.run_sequential(burst))}
     return out
 
@@ -285,6 +286,8 @@ def main():
     ap.add_argument("--solve-n", type=int, default=64)
     ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--serve-rate", type=float, default=8.0)
+    ap.add_argument("--no-graphs", dest="graphs", action="store_const", const=0, default=1,
+                    help="launch the FP32 preconditioner kernel by kernel instead of replaying its recorded graph")
     ap.add_argument("--no-ns", action="store_true", help="skip the Navier-Stokes measurements")
     ap.add_argument("--no-hp", action="store_true", help="skip the hp measurements")
     ap.add_argument("--hp-n", type=int, default=32)

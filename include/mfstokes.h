@@ -96,6 +96,9 @@ typedef struct mfs_options {
   /* monolithic Navier-Stokes multigrid (Sec. 5) */
   int relax_steps;       /* damped point-Jacobi sweeps before and after the coarse correction (5) */
   double relax_omega;    /* Jacobi damping omega (0.5) */
+  /* solve loop */
+  int graphs;            /* 1: the FP32 preconditioner of a solve is recorded once per problem as a
+                            HIP graph and replayed each FGMRES iteration; 0: launched kernel by kernel */
 } mfs_options;
 
 typedef struct mfs_solve_info {

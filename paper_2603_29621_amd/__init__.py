@@ -70,6 +70,7 @@ class mfs_options(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("relax_steps", ctypes.c_int),
         ("relax_omega", ctypes.c_double),
+        ("graphs", ctypes.c_int),
     ]
 
 

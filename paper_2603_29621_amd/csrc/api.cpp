@@ -107,6 +107,7 @@ struct Krylov {
   // state
   int state = 0;  // 0 idle, 1 wait initial residual, 2 wait Arnoldi step, 3 wait final check, 4 done
   int j = 0, iters = 0, maxit = 0, prec = MFS_FP32;
+  bool graphs = true;
   double rtol = 1e-8, bnorm = 0, beta = 0;
   std::vector<double> H, cs, sn, gv;
   const double *b = nullptr;
@@ -242,6 +243,11 @@ struct mfs_problem {
   // structured degree-2 levels in L
   HpData *hp = nullptr;
   int nhp = 0;
+  // recorded FP32 preconditioner (between w32.full_in and w32.full_out), its
+  // capture stream, and whether recording failed once (then launched eagerly)
+  hipGraphExec_t prec_graph = nullptr;
+  hipStream_t cap_stream = nullptr;
+  bool graph_failed = false;
 };
 
 namespace {
@@ -490,6 +496,8 @@ void check_mesh(const mfs_mesh *mesh, int k, const mfs_options &o) {
 
 void release(mfs_problem *P) {
   if (!P) return;
+  if (P->prec_graph) (void)hipGraphExecDestroy(P->prec_graph);
+  if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
   if (P->kr.ev) (void)hipEventDestroy(P->kr.ev);
   if (P->kr.host) (void)hipHostFree(P->kr.host);
   if (P->kr.yhost) (void)hipHostFree(P->kr.yhost);
@@ -1344,6 +1352,55 @@ void precondition_any(mfs_problem &P, T *y, const T *r, hipStream_t s) {
     precondition<T>(P, y, r, s);
 }
 
+// The recorded preconditioner holds host values that were current when it
+// was recorded (smoother intervals, the linearisation's dt and Newton flag,
+// option counts); calls that change them drop the recording.
+void drop_prec_graph(mfs_problem &P) {
+  if (P.prec_graph) (void)hipGraphExecDestroy(P.prec_graph);
+  P.prec_graph = nullptr;
+}
+
+// FP32 preconditioner from w32.full_in to w32.full_out on stream s.  Its
+// launches (a few hundred small kernels per V-cycle and Schur solve, no host
+// synchronisation and no memset) are recorded once on a private stream and
+// replayed as one graph launch, so that small problems do not pay the host
+// cost of every launch in each FGMRES iteration.  Recording that fails
+// (e.g. a runtime without stream capture) falls back to direct launches.
+void precondition_fp32(mfs_problem &P, hipStream_t s) {
+  float *y = P.w32.full_out, *r = P.w32.full_in;
+  if (!P.kr.graphs || P.graph_failed) {
+    precondition_any<float>(P, y, r, s);
+    return;
+  }
+  if (!P.prec_graph) {
+    if (!P.cap_stream) MFS_HIP(hipStreamCreateWithFlags(&P.cap_stream, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(P.cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      (void)hipGetLastError();
+      P.graph_failed = true;
+      precondition_any<float>(P, y, r, s);
+      return;
+    }
+    try {
+      precondition_any<float>(P, y, r, P.cap_stream);
+    } catch (...) {
+      if (hipStreamEndCapture(P.cap_stream, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    MFS_HIP(hipStreamEndCapture(P.cap_stream, &g));
+    const hipError_t e = hipGraphInstantiate(&P.prec_graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      P.prec_graph = nullptr;
+      P.graph_failed = true;
+      precondition_any<float>(P, y, r, s);
+      return;
+    }
+  }
+  MFS_HIP(hipGraphLaunch(P.prec_graph, s));
+}
+
 // ---------------------------------------------------------------- FGMRES
 void kr_enqueue_residual(mfs_problem &P, hipStream_t s) {
   Krylov &K = P.kr;
@@ -1362,7 +1419,7 @@ void kr_enqueue_step(mfs_problem &P, hipStream_t s) {
   double *vj = K.V + (int64_t)j * K.ld, *zj = K.Z + (int64_t)j * K.ld;
   if (K.prec == MFS_FP32) {
     vec_cast<float, double>(P.w32.full_in, vj, n, s);
-    precondition_any<float>(P, P.w32.full_out, P.w32.full_in, s);
+    precondition_fp32(P, s);
     vec_cast<double, float>(zj, P.w32.full_out, n, s);
   } else {
     precondition_any<double>(P, zj, vj, s);
@@ -1523,6 +1580,7 @@ void mfs_default_options(mfs_options *o) {
   o->seed = 0;
   o->relax_steps = 5;
   o->relax_omega = 0.5;
+  o->graphs = 1;
 }
 
 const char *mfs_last_error(void) { return get_error(); }
@@ -2077,6 +2135,7 @@ void kr_begin(mfs_problem &P, const double *b, double *x, const mfs_options &o, 
   K.rtol = o.rtol;
   K.maxit = o.maxit;
   K.prec = o.precond_precision;
+  K.graphs = o.graphs != 0;
   K.iters = 0;
   K.j = 0;
   K.H.assign((size_t)(K.m + 1) * K.m, 0.0);
@@ -2264,6 +2323,7 @@ int mfs_set_lambda(mfs_problem *p, int level, double lambda) {
       p->hp->lev[level].lambda = lambda;
     else
       p->L[level - p->nhp].lambda = lambda;
+    drop_prec_graph(*p);
   });
 }
 
@@ -2438,6 +2498,7 @@ int mfs_set_linearization(mfs_problem *p, const double *u0, double dt, int newto
     MFS_REQUIRE(p->ns, MFS_EINVAL, "linearisation needs a problem set up with pressure_offset = 0");
     MFS_REQUIRE(u0 != nullptr, MFS_EINVAL, "u0 is NULL");
     MFS_REQUIRE(dt > 0 && std::isfinite(dt), MFS_EINVAL, "dt must be positive");
+    drop_prec_graph(*p);
     ns_set_linearization(*p, u0, dt, newton, S(stream));
   });
 }

@@ -48,8 +48,8 @@ class Result:
         return self.completed - self.arrival
 
 
-def _options(precond, rtol, maxit):
-    return mfs.mfs_default_options(precond_precision=precond, rtol=rtol, maxit=maxit)
+def _options(precond, rtol, maxit, graphs=1):
+    return mfs.mfs_default_options(precond_precision=precond, rtol=rtol, maxit=maxit, graphs=graphs)
 
 
 def request_footprint(req, opts) -> int:
@@ -106,10 +106,11 @@ def _setup_request(req, opts, stream):
 
 class Server:
     def __init__(self, budget_bytes: float, max_active: int = 32, precond=mfs.MFS_FP32, rtol: float = 1e-8,
-                 maxit: int = 300, setup_workers: int = 2, max_bypass_s: float = 2.0, keep_solutions=False):
+                 maxit: int = 300, setup_workers: int = 2, max_bypass_s: float = 2.0, keep_solutions=False,
+                 graphs: int = 1):
         self.budget = float(budget_bytes)
         self.max_active = max_active
-        self.opts = _options(precond, rtol, maxit)
+        self.opts = _options(precond, rtol, maxit, graphs)
         self.setup_workers = setup_workers
         self.max_bypass_s = max_bypass_s
         self.keep = keep_solutions

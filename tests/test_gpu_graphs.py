@@ -1,0 +1,122 @@
+"""The recorded FP32 preconditioner (one HIP graph per problem, replayed in
+every FGMRES iteration) against the same solve launched kernel by kernel.
+
+Each solve replays the graph once per iteration, with the FP64 operator, the
+Gram-Schmidt kernels and a host synchronisation on the Arnoldi coefficients
+between two replays.  A replay that read stale inputs or wrote elsewhere
+would change the Krylov space, hence the iteration count and the solution at
+the level of the solve tolerance (1e-10).  The bound on the difference is the
+run-to-run difference of two direct-launch solves (zero when the kernels sum
+in a fixed order) times 100, at least 1e-13.
+
+Also checked: the recording follows changes of the smoother intervals
+(mfs_set_lambda) and of the linearisation (mfs_set_linearization), it is
+reused across solves with a new right-hand side, and it serves a solve
+enqueued on the null stream and on a side stream.
+"""
+import numpy as np
+import pytest
+import torch
+
+import inputs
+import paper_2603_29621_amd as mfs
+
+pytestmark = pytest.mark.gpu
+
+
+def cuda(x, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda", dtype)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+def relerr(y, ref):
+    d = y - ref
+    n2 = np.linalg.norm(ref)
+    return np.linalg.norm(d) / (n2 if n2 > 0 else 1)
+
+
+def _solve(h, b, graphs, stream=None, **kw):
+    x = torch.zeros_like(b)
+    opts = mfs.mfs_default_options(rtol=1e-10, maxit=200, precond_precision=mfs.MFS_FP32, graphs=graphs, **kw)
+    if stream is None:
+        info = mfs.mfs_solve(h, b, x, opts)
+    else:
+        with torch.cuda.stream(stream):
+            info = mfs.mfs_solve(h, b, x, opts, stream=stream.cuda_stream)
+        stream.synchronize()
+    assert info.status == 0 and info.rel_residual <= 1e-10
+    return host(x), info.iterations
+
+
+def _check_against_direct(h, b, stream=None, **kw):
+    xe, ie = _solve(h, b, 0, **kw)
+    xe2, ie2 = _solve(h, b, 0, **kw)
+    bound = max(100 * relerr(xe2, xe), 1e-13)
+    for _ in range(2):  # first solve records (if needed), the second replays only
+        xg, ig = _solve(h, b, 1, stream=stream, **kw)
+        assert relerr(xg, xe) <= bound, (relerr(xg, xe), bound)
+        assert abs(ig - ie) <= (0 if ie == ie2 else 1)
+    return xe
+
+
+def _rhs(h, op, N, seed):
+    """b = K x_t for a seeded x_t: a consistent right-hand side of the system
+    operator (FP64, level 0)."""
+    xt = cuda(inputs.uniform_vector(N, seed))
+    b = torch.empty_like(xt)
+    mfs.mfs_vmult(h, op, mfs.MFS_FP64, 0, b, xt)
+    torch.cuda.synchronize()
+    return b
+
+
+@pytest.mark.parametrize("n,k,side", [([6, 5, 4], 2, False), ([4, 4, 3], 3, True)])
+def test_stokes_graph_solve_matches_direct(n, k, side):
+    X = inputs.structured_vertices(3, n, noise=0.2, seed=3)
+    h = mfs.mfs_setup(3, n, X, k, 0.8, mfs.mfs_default_options())
+    try:
+        nv, np_ = mfs.mfs_n_dofs(h, 0)
+        N = 3 * nv + np_
+        stream = torch.cuda.Stream() if side else None
+        _check_against_direct(h, _rhs(h, mfs.MFS_OP_STOKES, N, 11), stream)
+        _check_against_direct(h, _rhs(h, mfs.MFS_OP_STOKES, N, 12), stream)  # new right-hand side, same recording
+        lam = mfs.mfs_get_lambda(h, 0)
+        mfs.mfs_set_lambda(h, 0, 1.5 * lam)  # the recording must be dropped
+        _check_against_direct(h, _rhs(h, mfs.MFS_OP_STOKES, N, 12), stream)
+    finally:
+        mfs.mfs_destroy(h)
+
+
+def test_ns_graph_solve_matches_direct():
+    dim, n, k, nu = 3, [8, 6, 6], 1, 1e-3
+    X = inputs.structured_vertices(dim, n, noise=0.1, seed=3)
+    h = mfs.mfs_setup(dim, n, X, k, nu, mfs.mfs_default_options(pressure_offset=0))
+    try:
+        u0 = inputs.ns_velocity(dim, [k * v + 1 for v in n], 5)
+        dt = 1.0 / (max(n) * k) / np.abs(u0).max()
+        mfs.mfs_set_linearization(h, cuda(u0), dt, 1)
+        nv, _ = mfs.mfs_n_dofs(h, 0)
+        N = (dim + 1) * nv
+        b = _rhs(h, mfs.MFS_OP_NS_JACOBIAN, N, 21)
+        x1 = _check_against_direct(h, b, pressure_offset=0)
+        mfs.mfs_set_linearization(h, cuda(u0), 0.5 * dt, 0)  # new dt and Picard: drop the recording
+        x2 = _check_against_direct(h, b, pressure_offset=0)
+        assert relerr(x2, x1) > 1e-6  # the second system is a different one
+    finally:
+        mfs.mfs_destroy(h)
+
+
+def test_hp_graph_solve_matches_direct():
+    n = [4, 4, 4]
+    deg = inputs.block_degrees(n, seed=5, block=2, lo=2, hi=6)
+    X = inputs.structured_vertices(3, n, noise=0.1, seed=2)
+    h = mfs.mfs_setup_hp(n, X, np.asarray(deg, dtype=np.int32), 1.0, mfs.mfs_default_options())
+    try:
+        nv, np_ = mfs.mfs_n_dofs(h, 0)
+        N = 3 * nv + np_
+        _check_against_direct(h, _rhs(h, mfs.MFS_OP_STOKES, N, 31))
+    finally:
+        mfs.mfs_destroy(h)
