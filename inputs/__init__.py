@@ -28,6 +28,7 @@ __all__ = [
     "manufactured_2d",
     "manufactured_3d",
     "fourier_field",
+    "refined_mesh",
     "request_stream",
     "Request",
 ]
@@ -238,6 +239,65 @@ def fourier_field(seed: int, n_modes: int = 8) -> FourierField:
     b -= (b * kn).sum(1, keepdims=True) * kn
     scale = math.sqrt(0.5 * ((a ** 2).sum() + (b ** 2).sum()))
     return FourierField(kap, a / scale, b / scale)
+
+
+# ---------------------------------------------------------------------------
+# Locally refined meshes
+# ---------------------------------------------------------------------------
+_FACE_EDGE = [(a, b, c) for a in (-1, 0, 1) for b in (-1, 0, 1) for c in (-1, 0, 1)
+              if 1 <= abs(a) + abs(b) + abs(c) <= 2]
+
+
+def _dilate(m: np.ndarray) -> np.ndarray:
+    """Cells of a boolean [z, y, x] grid that are set or share a face or an
+    edge with a set cell."""
+    out = m.copy()
+    Z, Y, X = m.shape
+    for dz, dy, dx in _FACE_EDGE:
+        src = m[max(0, -dz):Z - max(0, dz), max(0, -dy):Y - max(0, dy), max(0, -dx):X - max(0, dx)]
+        out[max(0, dz):Z - max(0, -dz), max(0, dy):Y - max(0, -dy), max(0, dx):X - max(0, -dx)] |= src
+    return out
+
+
+def refined_mesh(n: int, seed: int = 0, levels: int = 2, centre=None, radius=None) -> dict:
+    """Leaves of a locally refined mesh of the unit cube: n^3 base cells;
+    cells whose centre lies in a sphere are split into 8 children, ``levels``
+    times; then a 2:1 closure over face and edge neighbours (a cell whose
+    face or edge neighbour is refined is refined too, finest level first).
+    Sphere: centre ~ U[0.3, 0.7]^3, radius ~ U[0.1, 0.2] (PCG64), unless given.
+
+    Returns {"n", "levels", "centre", "radius", "level" [nc] int32,
+    "idx" [nc, 3] int32}: cell (l, i, j, k) spans
+    [i, i + 1] x [j, j + 1] x [k, k + 1] / (n 2^l).  Leaves are listed by
+    level, then lexicographically (x fastest) within a level."""
+    rng = _rng(seed)
+    c0 = rng.uniform(0.3, 0.7, 3)
+    r0 = rng.uniform(0.1, 0.2)
+    centre = c0 if centre is None else np.asarray(centre, dtype=np.float64)
+    radius = r0 if radius is None else float(radius)
+    ref = []  # ref[l]: [z, y, x] booleans, level-l cell is split
+    for l in range(levels):
+        m = n << l
+        ax = (np.arange(m) + 0.5) / m
+        zz, yy, xx = np.meshgrid(ax, ax, ax, indexing="ij")
+        inside = (xx - centre[0]) ** 2 + (yy - centre[1]) ** 2 + (zz - centre[2]) ** 2 < radius ** 2
+        if l > 0:  # only children of split cells exist
+            inside &= ref[l - 1].repeat(2, 0).repeat(2, 1).repeat(2, 2)
+        ref.append(inside)
+    for l in range(levels - 1, 0, -1):  # 2:1 closure
+        need = _dilate(ref[l])
+        m = n << (l - 1)
+        ref[l - 1] |= need.reshape(m, 2, m, 2, m, 2).any(axis=(1, 3, 5))
+    lev, idx = [], []
+    for l in range(levels + 1):
+        m = n << l
+        exists = np.ones((m, m, m), dtype=bool) if l == 0 else ref[l - 1].repeat(2, 0).repeat(2, 1).repeat(2, 2)
+        leaf = exists & ~ref[l] if l < levels else exists
+        z, y, x = np.nonzero(leaf)
+        lev.append(np.full(len(x), l, dtype=np.int32))
+        idx.append(np.stack([x, y, z], 1).astype(np.int32))
+    return {"n": int(n), "levels": int(levels), "centre": centre, "radius": radius,
+            "level": np.concatenate(lev), "idx": np.concatenate(idx)}
 
 
 # ---------------------------------------------------------------------------
