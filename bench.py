@@ -168,6 +168,9 @@ def ns_section(mfs, torch, inputs, args):
             mfs.mfs_destroy(h)
     out["workload"] = (f"3D SUPG/PSPG Navier-Stokes Jacobian, {args.ns_n}^3 Cartesian cells, BDF2 dt={dt}, "
                        f"nu={nu}, Newton about the 8-mode Fourier field")
+    # the same Jacobian on the locally refined mesh (hanging nodes)
+    if args.ns_refined:
+        out["refined"] = refined_ns_section(mfs, torch, inputs, args, dt, nu)
     # Newton-step solve
     n, k = args.ns_solve_n, 2
     X = inputs.structured_vertices(3, [n] * 3)
@@ -200,6 +203,43 @@ def ns_section(mfs, torch, inputs, args):
             mfs.mfs_destroy(h)
     solve["speedup_mixed_vs_fp64"] = solve["fp64"]["solve_s"] / solve["fp32_mg_fp64_fgmres"]["solve_s"]
     out["solve"] = solve
+    return out
+
+
+def refined_ns_section(mfs, torch, inputs, args, dt, nu):
+    """Jacobian throughput on n^3 Cartesian cells with 2 levels of local
+    refinement in a seeded sphere (radius 0.15, 2:1 closure over faces and
+    edges): gather through the hanging-node maps, cell kernel, transposed
+    scatter."""
+    n = args.ns_n
+    mesh = inputs.refined_mesh(n, seed=0, levels=2, radius=0.15)
+    F = inputs.fourier_field(0)
+    out = {"workload": f"{n}^3 base cells + 2 levels in a sphere (centre {np.round(mesh['centre'], 3).tolist()}, "
+                       f"radius 0.15, seed 0), {len(mesh['level'])} cells "
+                       f"({np.bincount(mesh['level']).tolist()} per level), Newton, dt={dt}, nu={nu}"}
+    for k in (1, 2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = mfs.mfs_setup_refined(mesh, k, nu)
+        setup = time.perf_counter() - t0
+        try:
+            nu_, _ = mfs.mfs_n_dofs(h, 0)
+            N = 4 * nu_
+            pts = mfs.mfs_support_points(h, k, nu_, 3)
+            u0 = np.empty((3, nu_))
+            for a in range(0, nu_, 1 << 22):
+                u0[:, a:a + (1 << 22)] = F(pts[a:a + (1 << 22)]).T
+            del pts
+            mfs.mfs_set_linearization(h, torch.from_numpy(u0.ravel()).cuda(), dt, 1)
+            del u0
+            res = {"N": N, "setup_s": setup}
+            for prec, name in ((mfs.MFS_FP64, "f64"), (mfs.MFS_FP32, "f32")):
+                _, per = time_vmult(mfs, torch, h, N, prec, max(10, args.steps // 2), 3, op=mfs.MFS_OP_NS_JACOBIAN)
+                avg = float(per.mean())
+                res[name] = {"dofs_per_s": N / avg, "avg_launch_us": avg * 1e6}
+            out[f"Q{k}Q{k}"] = res
+        finally:
+            mfs.mfs_destroy(h)
     return out
 
 
@@ -292,6 +332,8 @@ def main():
     ap.add_argument("--no-hp", action="store_true", help="skip the hp measurements")
     ap.add_argument("--hp-n", type=int, default=32)
     ap.add_argument("--ns-n", type=int, default=128)
+    ap.add_argument("--no-ns-refined", dest="ns_refined", action="store_false",
+                    help="skip the Jacobian on the locally refined mesh")
     ap.add_argument("--ns-solve-n", type=int, default=32)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 256 MiB device copy first (reference kernel for HBM byte counters)")

@@ -162,6 +162,42 @@ int mfs_destroy(mfs_problem *p);
 int mfs_setup_hp(const mfs_mesh *mesh, const int *cell_degree, double nu, const mfs_options *opts, void *stream,
                  mfs_problem **out);
 
+/* Locally refined mesh of the unit cube: the leaves of octrees over n^3
+ * Cartesian base cells.  Leaf c has refinement level level[c] in [0, levels]
+ * and index (idx[3c], idx[3c+1], idx[3c+2]) on its level's grid of
+ * (n 2^level)^3 cells, i.e. it spans [i, i+1] x [j, j+1] x [m, m+1] / (n 2^level).
+ * Host arrays, read during the call only.  The leaves must partition the cube. */
+typedef struct mfs_refined_mesh {
+  int n;             /* base cells per direction */
+  int levels;        /* finest refinement level present, in [0, 4] */
+  int64_t ncells;    /* number of leaves */
+  const int *level;  /* [ncells] */
+  const int *idx;    /* [ncells][3] */
+} mfs_refined_mesh;
+
+/*
+ * setup on a locally refined mesh (Sec. 5: the stabilised Navier-Stokes
+ * problem on meshes with hanging nodes): equal-order Q_k/Q_k, k in {1, 2}
+ * (opts->pressure_offset must be 0), operators only (opts->mg_levels must
+ * be 0).  The space is the continuous one: a node of a finer cell that lies
+ * on a face or edge of a coarser neighbour without being one of its nodes
+ * (a hanging node) takes the neighbour's interpolant there, realised by the
+ * cell-local constraint maps C_e of eq. (transfer).  Unknowns: every other
+ * node position, numbered in lexicographic order of position (x fastest);
+ * vectors blocked [u_0 | u_1 | u_2 | p] with n_u = n_p = number of unknowns;
+ * velocity unknowns on the boundary of the cube are Dirichlet unknowns.
+ * Offers mfs_set_linearization (u0: 3 n_u values at the unknowns),
+ * mfs_vmult with MFS_OP_NS_JACOBIAN on level 0 (FP64 or FP32), mfs_n_dofs,
+ * mfs_n_levels (1), mfs_level_info (k, base n) and mfs_support_points
+ * (deg = k: the unknowns' coordinates); every other call returns
+ * MFS_EUNSUPPORTED.  MFS_EINVAL when the leaves are out of range, overlap or
+ * leave a gap; MFS_EUNSUPPORTED for other degrees or options.  The hanging-
+ * node maps are built on the host (sort of all cell-node positions) and
+ * copied to the device; `stream` is synchronised before returning.
+ */
+int mfs_setup_refined(const mfs_refined_mesh *mesh, int k, double nu, const mfs_options *opts, void *stream,
+                      mfs_problem **out);
+
 /* Sizes at level `level` (0 = finest): scalar velocity nodes per component and
  * pressure nodes (0 on levels without pressure; n_u on every level of a
  * Navier-Stokes problem). */

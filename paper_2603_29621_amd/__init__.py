@@ -38,7 +38,7 @@ EXPORTED = [
     "mfs_quadrature_points_device", "mfs_vmult",
     "mfs_diagonal", "mfs_get_lambda", "mfs_set_lambda", "mfs_vcycle", "mfs_prolongate_add", "mfs_restrict",
     "mfs_precondition", "mfs_rhs", "mfs_solve", "mfs_solve_begin", "mfs_solve_advance",
-    "mfs_set_linearization", "mfs_setup_hp",
+    "mfs_set_linearization", "mfs_setup_hp", "mfs_setup_refined",
 ]
 
 
@@ -74,6 +74,11 @@ class mfs_options(ctypes.Structure):
     ]
 
 
+class mfs_refined_mesh(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("levels", ctypes.c_int), ("ncells", ctypes.c_int64),
+                ("level", ctypes.POINTER(ctypes.c_int)), ("idx", ctypes.POINTER(ctypes.c_int))]
+
+
 class mfs_solve_info(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("status", ctypes.c_int), ("rel_residual", ctypes.c_double),
                 ("seconds", ctypes.c_double)]
@@ -100,6 +105,8 @@ def lib():
         L.mfs_destroy.argtypes = [vp]
         L.mfs_setup_hp.argtypes = [ctypes.POINTER(mfs_mesh), ctypes.POINTER(ctypes.c_int), ctypes.c_double,
                                    ctypes.POINTER(mfs_options), vp, ctypes.POINTER(vp)]
+        L.mfs_setup_refined.argtypes = [ctypes.POINTER(mfs_refined_mesh), ctypes.c_int, ctypes.c_double,
+                                        ctypes.POINTER(mfs_options), vp, ctypes.POINTER(vp)]
         L.mfs_n_dofs.argtypes = [vp, ctypes.c_int, i64p, i64p]
         L.mfs_n_levels.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
         L.mfs_level_info.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
@@ -242,6 +249,28 @@ def mfs_setup_hp(n, vertices, cell_degree, nu, opts=None, stream=None) -> ctypes
     h = ctypes.c_void_p(0)
     _check(lib().mfs_setup_hp(ctypes.byref(m), deg.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), float(nu),
                               ctypes.byref(opts) if opts else None, _stream(stream), ctypes.byref(h)))
+    _dims[h.value] = 3
+    return h
+
+
+def mfs_setup_refined(mesh, k, nu, opts=None, stream=None) -> ctypes.c_void_p:
+    """Equal-order Navier-Stokes problem on a locally refined mesh given as
+    {"n", "levels", "level" [nc], "idx" [nc, 3]} (the leaves)."""
+    lev = np.ascontiguousarray(mesh["level"], dtype=np.int32)
+    idx = np.ascontiguousarray(mesh["idx"], dtype=np.int32).reshape(-1, 3)
+    if len(idx) != len(lev):
+        raise ValueError("level and idx must list the same cells")
+    m = mfs_refined_mesh()
+    m.n = int(mesh["n"])
+    m.levels = int(mesh["levels"])
+    m.ncells = len(lev)
+    m.level = lev.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+    m.idx = idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+    if opts is None:
+        opts = mfs_default_options(pressure_offset=0, mg_levels=0)
+    h = ctypes.c_void_p(0)
+    _check(lib().mfs_setup_refined(ctypes.byref(m), int(k), float(nu), ctypes.byref(opts), _stream(stream),
+                                   ctypes.byref(h)))
     _dims[h.value] = 3
     return h
 

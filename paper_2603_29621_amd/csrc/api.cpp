@@ -22,6 +22,7 @@
 #include <type_traits>
 #include <vector>
 
+#include "amr.h"
 #include "hp.h"
 #include "internal.h"
 
@@ -213,6 +214,31 @@ struct HpData {
   }
 };
 
+// ------------------------------------------------------------- refined meshes
+// Equal-order Navier-Stokes on a locally refined mesh: the unknowns' maps to
+// the cell-local values (E-vectors [cell][3][(k+1)^3] velocity, then
+// [cell][(k+1)^3] pressure), the per-cell corners, the 1D tables and the
+// linearisation data.
+struct AmrData {
+  HpData H;        // device allocations and uploads
+  AmrSpaceHost S;  // host space (the row maps are released after the upload)
+  LevelGeom g{};   // degree and cell count for the cell kernels
+  int64_t N = 0, NQ = 0;
+  HpDevSpace vd;   // velocity: Dirichlet columns dropped, 3 components
+  HpDevSpace pd;   // scalar, unconstrained (pressure; components of u0)
+  double *X64 = nullptr;
+  float *X32 = nullptr;
+  double *tab64 = nullptr;
+  float *tab32 = nullptr;
+  double *qd64 = nullptr;
+  float *qd32 = nullptr;
+  double *ev64[2] = {};  // in, out
+  float *ev32[2] = {};
+  double dt = 0.0;
+  int newton = 1;
+  bool ready = false;
+};
+
 }  // namespace
 
 struct mfs_problem {
@@ -243,6 +269,9 @@ struct mfs_problem {
   // structured degree-2 levels in L
   HpData *hp = nullptr;
   int nhp = 0;
+  // refined-mesh problem: its levels come first (global numbers 0 .. namr-1)
+  AmrData *amr = nullptr;
+  int namr = 0;
   // recorded FP32 preconditioner (between w32.full_in and w32.full_out), its
   // capture stream, and whether recording failed once (then launched eagerly)
   hipGraphExec_t prec_graph = nullptr;
@@ -503,6 +532,7 @@ void release(mfs_problem *P) {
   if (P->kr.yhost) (void)hipHostFree(P->kr.yhost);
   if (P->arena) (void)hipFree(P->arena);
   delete P->hp;
+  delete P->amr;
   delete P;
 }
 
@@ -2039,6 +2069,118 @@ void hp_build(mfs_problem &P, const std::vector<int> &deg0, hipStream_t s) {
     for (int l = 0; l < P.nhp; ++l) H.lev[l].lambda = P.opts.cheb_safety * hp_estimate_lambda(P, l, s);
   MFS_HIP(hipStreamSynchronize(s));
 }
+// ---------------------------------------------------------------- refined meshes
+template <typename T>
+T *amr_ev(AmrData &A, int i);
+template <>
+double *amr_ev<double>(AmrData &A, int i) {
+  return A.ev64[i];
+}
+template <>
+float *amr_ev<float>(AmrData &A, int i) {
+  return A.ev32[i];
+}
+template <typename T>
+const T *amr_tab(const AmrData &A) {
+  if constexpr (sizeof(T) == 8) return A.tab64; else return A.tab32;
+}
+template <typename T>
+const T *amr_X(const AmrData &A) {
+  if constexpr (sizeof(T) == 8) return A.X64; else return A.X32;
+}
+template <typename T>
+T *amr_qd(AmrData &A) {
+  if constexpr (sizeof(T) == 8) return A.qd64; else return A.qd32;
+}
+
+void amr_build(mfs_problem &P, const mfs_refined_mesh &m, int k, hipStream_t s) {
+  AmrData &A = *P.amr;
+  A.S.build(m.n, m.levels, m.ncells, m.level, m.idx, k);
+  const int64_t nc = A.S.ncells, NQ = (int64_t)(k + 1) * (k + 1) * (k + 1);
+  A.N = A.S.N;
+  A.NQ = NQ;
+  LevelGeom &g = A.g;
+  g.dim = 3;
+  g.k = g.kp = k;
+  g.n[0] = g.n[1] = 1;
+  g.n[2] = (int)nc;
+  g.ncells = nc;
+  g.nv[0] = g.nv[1] = k + 1;
+  g.nv[2] = (int)(k * nc + 1);
+  g.np[0] = g.np[1] = k + 1;
+  g.np[2] = g.nv[2];
+  g.Nv = g.Np = (int64_t)g.nv[0] * g.nv[1] * g.nv[2];
+  std::vector<int64_t> offu(nc), offp(nc);
+  for (int64_t c = 0; c < nc; ++c) {
+    offu[c] = c * 3 * NQ;
+    offp[c] = 3 * nc * NQ + c * NQ;
+  }
+  hp_upload(A.H, A.S.V, true, offu, true, A.vd, s);
+  hp_upload(A.H, A.S.V, false, offp, false, A.pd, s);
+  A.X64 = A.H.upload(A.S.Xcell, s);
+  std::vector<float> x32(A.S.Xcell.begin(), A.S.Xcell.end());
+  A.X32 = A.H.upload(x32, s);
+  const auto tab = make_tables(k, k);
+  std::vector<float> tab32(tab.begin(), tab.end());
+  A.tab64 = A.H.upload(tab, s);
+  A.tab32 = A.H.upload(tab32, s);
+  A.qd64 = A.H.alloc<double>(nc * NQ * NS_QD);
+  A.qd32 = A.H.alloc<float>(nc * NQ * NS_QD);
+  for (int i = 0; i < 2; ++i) {
+    A.ev64[i] = A.H.alloc<double>(4 * nc * NQ);
+    A.ev32[i] = A.H.alloc<float>(4 * nc * NQ);
+  }
+  MFS_HIP(hipStreamSynchronize(s));
+  // the row maps and corners live on the device now
+  A.S.V = HpSpaceHost();
+  std::vector<double>().swap(A.S.Xcell);
+}
+
+// mfs_set_linearization on a refined mesh: u0 (3 blocks of N) through the
+// unconstrained scalar map into the velocity slots, then the point data
+void amr_set_linearization(mfs_problem &P, const double *u0, double dt, int newton, hipStream_t s) {
+  AmrData &A = *P.amr;
+  A.ready = false;
+  A.dt = dt;
+  A.newton = newton ? 1 : 0;
+  double *ev = A.ev64[0];
+  for (int c = 0; c < 3; ++c) {
+    hp_gather_space<double>(A.pd, 1, u0 + c * A.N, ev, s);
+    launch_ev_to_velocity(ev, A.g.ncells, (int)A.NQ, c, s);
+  }
+  launch_ns<double>(A.g, nullptr, A.tab64, 0, P.nu, dt, A.newton, nullptr, nullptr, A.qd64, s, nullptr, ev, A.X64);
+  vec_cast<float, double>(A.qd32, A.qd64, A.g.ncells * A.NQ * NS_QD, s);
+  MFS_HIP(hipStreamSynchronize(s));
+  A.ready = true;
+}
+
+// constrained Jacobian on a refined mesh: gather with the constraints (the
+// velocity's Dirichlet columns dropped), cell kernel on the E-vectors,
+// transposed scatter (identity on the velocity Dirichlet rows)
+template <typename T>
+void amr_apply_ns(mfs_problem &P, T *dst, const T *src, hipStream_t s) {
+  AmrData &A = *P.amr;
+  MFS_REQUIRE(A.ready, MFS_EINVAL, "mfs_set_linearization has not been called");
+  T *evi = amr_ev<T>(A, 0), *evo = amr_ev<T>(A, 1);
+  const int64_t N = A.N;
+  hp_gather_space<T>(A.vd, 3, src, evi, s);
+  hp_gather_space<T>(A.pd, 1, src + 3 * N, evi, s);
+  launch_ns<T>(A.g, nullptr, amr_tab<T>(A), 1, (T)P.nu, (T)A.dt, A.newton, nullptr, nullptr, amr_qd<T>(A), s, evo,
+               evi, amr_X<T>(A));
+  hp_scatter_space<T>(A.vd, 3, true, evo, src, dst, s);
+  hp_scatter_space<T>(A.pd, 1, false, evo, nullptr, dst + 3 * N, s);
+}
+
+void amr_vmult(mfs_problem &P, int op, int prec, int level, void *dst, const void *src, hipStream_t s) {
+  MFS_REQUIRE(level == 0, MFS_EUNSUPPORTED, "refined-mesh problems have one level");
+  MFS_REQUIRE(op == MFS_OP_NS_JACOBIAN, MFS_EUNSUPPORTED,
+              "refined-mesh problems provide the Navier-Stokes Jacobian (operator %d requested)", op);
+  if (prec == MFS_FP64)
+    amr_apply_ns<double>(P, (double *)dst, (const double *)src, s);
+  else
+    amr_apply_ns<float>(P, (float *)dst, (const float *)src, s);
+}
+
 // mfs_vmult on an hp problem: the hp levels (all operators on the finest,
 // the velocity block on the others), then the structured levels
 void hp_vmult(mfs_problem &P, int op, int prec, int level, void *dst, const void *src, hipStream_t s) {
@@ -2109,14 +2251,52 @@ int mfs_setup_hp(const mfs_mesh *mesh, const int *cell_degree, double nu, const 
   return MFS_OK;
 }
 
+int mfs_setup_refined(const mfs_refined_mesh *mesh, int k, double nu, const mfs_options *opts, void *stream,
+                      mfs_problem **out) {
+  mfs_problem *P = nullptr;
+  int rc = guard([&] {
+    MFS_REQUIRE(out != nullptr, MFS_EINVAL, "out is NULL");
+    *out = nullptr;
+    MFS_REQUIRE(mesh != nullptr, MFS_EINVAL, "mesh is NULL");
+    MFS_REQUIRE(nu > 0 && std::isfinite(nu), MFS_EINVAL, "nu must be positive");
+    mfs_options o;
+    if (opts)
+      o = *opts;
+    else
+      mfs_default_options(&o);
+    MFS_REQUIRE(o.pressure_offset == 0, MFS_EUNSUPPORTED,
+                "refined meshes provide the equal-order Navier-Stokes Jacobian (pressure_offset = 0)");
+    MFS_REQUIRE(o.mg_levels == 0, MFS_EUNSUPPORTED, "refined meshes provide operators only (mg_levels = 0)");
+    P = new mfs_problem();
+    P->dim = 3;
+    P->nu = nu;
+    P->opts = o;
+    P->stream = S(stream);
+    P->ns = true;
+    P->namr = 1;
+    P->amr = new AmrData();
+    amr_build(*P, *mesh, k, S(stream));
+    *out = P;
+  });
+  if (rc != MFS_OK) {
+    release(P);
+    return rc;
+  }
+  return MFS_OK;
+}
+
 }  // extern "C"
 
 namespace {
 void check_problem(const mfs_problem *p) { MFS_REQUIRE(p != nullptr, MFS_EINVAL, "problem is NULL"); }
 void check_level(const mfs_problem *p, int level) {
   check_problem(p);
-  MFS_REQUIRE(level >= 0 && level < p->nhp + p->nlev, MFS_EINVAL, "level %d out of range [0, %d)", level,
-              p->nhp + p->nlev);
+  MFS_REQUIRE(level >= 0 && level < p->namr + p->nhp + p->nlev, MFS_EINVAL, "level %d out of range [0, %d)", level,
+              p->namr + p->nhp + p->nlev);
+}
+void no_amr(const mfs_problem *p, const char *what) {
+  check_problem(p);
+  MFS_REQUIRE(!p->amr, MFS_EUNSUPPORTED, "%s is not available on a refined-mesh problem", what);
 }
 void check_prec(int prec) {
   MFS_REQUIRE(prec == MFS_FP32 || prec == MFS_FP64, MFS_EINVAL, "precision must be MFS_FP32 or MFS_FP64");
@@ -2165,6 +2345,11 @@ extern "C" {
 int mfs_n_dofs(const mfs_problem *p, int level, int64_t *n_u, int64_t *n_p) {
   return guard([&] {
     check_level(p, level);
+    if (p->amr) {
+      if (n_u) *n_u = p->amr->N;
+      if (n_p) *n_p = p->amr->N;
+      return;
+    }
     if (level < p->nhp) {
       if (n_u) *n_u = p->hp->lev[level].V.N;
       if (n_p) *n_p = level == 0 ? p->hp->Pr.N : 0;
@@ -2180,13 +2365,19 @@ int mfs_n_levels(const mfs_problem *p, int *n) {
   return guard([&] {
     check_problem(p);
     MFS_REQUIRE(n != nullptr, MFS_EINVAL, "n is NULL");
-    *n = p->nhp + p->nlev;
+    *n = p->namr + p->nhp + p->nlev;
   });
 }
 
 int mfs_level_info(const mfs_problem *p, int level, int *k, int *n) {
   return guard([&] {
     check_level(p, level);
+    if (p->amr) {
+      if (k) *k = p->amr->g.k;
+      if (n)
+        for (int a = 0; a < 3; ++a) n[a] = p->amr->S.n;
+      return;
+    }
     if (level < p->nhp) {
       const auto &d = p->hp->lev[level].V.deg;
       if (k) *k = *std::max_element(d.begin(), d.end());
@@ -2207,6 +2398,12 @@ int mfs_support_points(const mfs_problem *p, int deg, double *xyz) {
     MFS_REQUIRE(!p->hp, MFS_EUNSUPPORTED, "support points of hp spaces are not provided");
     MFS_REQUIRE(deg >= 1 && deg <= 7, MFS_EINVAL, "degree out of range");
     MFS_REQUIRE(xyz != nullptr, MFS_EINVAL, "buffer is NULL");
+    if (p->amr) {
+      const AmrSpaceHost &A = p->amr->S;
+      MFS_REQUIRE(deg == A.k, MFS_EUNSUPPORTED, "refined meshes provide the points of degree %d", A.k);
+      for (int64_t i = 0; i < 3 * A.N; ++i) xyz[i] = (double)A.tpos[i] / (double)A.R;
+      return;
+    }
     const Level &L = p->L[0];
     const int dim = p->dim;
     const auto nodes = gll_nodes(deg);
@@ -2244,7 +2441,7 @@ int mfs_support_points(const mfs_problem *p, int deg, double *xyz) {
 
 int mfs_quadrature_points(const mfs_problem *p, double *xyz) {
   return guard([&] {
-    check_problem(p);
+    no_amr(p, "quadrature points");
     MFS_REQUIRE(xyz != nullptr, MFS_EINVAL, "buffer is NULL");
     const Level &L = p->L[0];
     const int64_t nq = L.g.ncells * ipow(L.g.k + 1, p->dim) * p->dim;
@@ -2260,6 +2457,7 @@ int mfs_quadrature_points(const mfs_problem *p, double *xyz) {
 
 int mfs_quadrature_points_device(const mfs_problem *p, double *xyz, void *stream) {
   return guard([&] {
+    no_amr(p, "quadrature points");
     check_problem(p);
     MFS_REQUIRE(xyz != nullptr, MFS_EINVAL, "buffer is NULL");
     const Level &L = p->L[0];
@@ -2273,6 +2471,10 @@ int mfs_vmult(mfs_problem *p, int op, int prec, int level, void *dst, const void
     check_prec(prec);
     MFS_REQUIRE(dst && src, MFS_EINVAL, "NULL vector");
     MFS_REQUIRE(dst != src, MFS_EINVAL, "dst and src must not alias");
+    if (p->amr) {
+      amr_vmult(*p, op, prec, level, dst, src, S(stream));
+      return;
+    }
     if (p->hp) {
       hp_vmult(*p, op, prec, level, dst, src, S(stream));
       return;
@@ -2286,6 +2488,7 @@ int mfs_vmult(mfs_problem *p, int op, int prec, int level, void *dst, const void
 
 int mfs_diagonal(mfs_problem *p, int level, double *dst, void *stream) {
   return guard([&] {
+    no_amr(p, "mfs_diagonal");
     check_level(p, level);
     MFS_REQUIRE(dst != nullptr, MFS_EINVAL, "NULL vector");
     hipStream_t s = S(stream);
@@ -2309,6 +2512,7 @@ int mfs_diagonal(mfs_problem *p, int level, double *dst, void *stream) {
 
 int mfs_get_lambda(const mfs_problem *p, int level, double *lambda) {
   return guard([&] {
+    no_amr(p, "mfs_get_lambda");
     check_level(p, level);
     MFS_REQUIRE(lambda != nullptr, MFS_EINVAL, "NULL output");
     *lambda = level < p->nhp ? p->hp->lev[level].lambda : p->L[level - p->nhp].lambda;
@@ -2317,6 +2521,7 @@ int mfs_get_lambda(const mfs_problem *p, int level, double *lambda) {
 
 int mfs_set_lambda(mfs_problem *p, int level, double lambda) {
   return guard([&] {
+    no_amr(p, "mfs_set_lambda");
     check_level(p, level);
     MFS_REQUIRE(lambda > 0, MFS_EINVAL, "lambda must be positive");
     if (level < p->nhp)
@@ -2329,6 +2534,7 @@ int mfs_set_lambda(mfs_problem *p, int level, double lambda) {
 
 int mfs_vcycle(mfs_problem *p, int prec, void *dst, const void *src, void *stream) {
   return guard([&] {
+    no_amr(p, "mfs_vcycle");
     check_problem(p);
     check_prec(prec);
     MFS_REQUIRE(p->opts.mg_levels, MFS_EINVAL, "problem was set up without multigrid levels");
@@ -2353,6 +2559,7 @@ int mfs_vcycle(mfs_problem *p, int prec, void *dst, const void *src, void *strea
 
 int mfs_prolongate_add(mfs_problem *p, int prec, int fine, void *dst, const void *src, void *stream) {
   return guard([&] {
+    no_amr(p, "mfs_prolongate_add");
     check_level(p, fine);
     check_prec(prec);
     MFS_REQUIRE(fine + 1 < p->nhp + p->nlev, MFS_EINVAL, "no coarser level below %d", fine);
@@ -2377,6 +2584,7 @@ int mfs_prolongate_add(mfs_problem *p, int prec, int fine, void *dst, const void
 
 int mfs_restrict(mfs_problem *p, int prec, int fine, void *dst, const void *src, void *stream) {
   return guard([&] {
+    no_amr(p, "mfs_restrict");
     check_level(p, fine);
     check_prec(prec);
     MFS_REQUIRE(fine + 1 < p->nhp + p->nlev, MFS_EINVAL, "no coarser level below %d", fine);
@@ -2401,6 +2609,7 @@ int mfs_restrict(mfs_problem *p, int prec, int fine, void *dst, const void *src,
 
 int mfs_precondition(mfs_problem *p, int prec, void *dst, const void *src, void *stream) {
   return guard([&] {
+    no_amr(p, "mfs_precondition");
     check_problem(p);
     check_prec(prec);
     MFS_REQUIRE(p->opts.mg_levels && (p->hp || p->L[0].g.Np > 0), MFS_EINVAL,
@@ -2416,6 +2625,7 @@ int mfs_precondition(mfs_problem *p, int prec, void *dst, const void *src, void 
 
 int mfs_rhs(mfs_problem *p, const double *f_qp, const double *u_dirichlet, double *b, void *stream) {
   return guard([&] {
+    no_amr(p, "mfs_rhs");
     check_problem(p);
     MFS_REQUIRE(f_qp && u_dirichlet && b, MFS_EINVAL, "NULL vector");
     MFS_REQUIRE(!p->ns, MFS_EUNSUPPORTED, "mfs_rhs assembles the Stokes right-hand side only");
@@ -2441,6 +2651,7 @@ int mfs_rhs(mfs_problem *p, const double *f_qp, const double *u_dirichlet, doubl
 
 int mfs_solve_begin(mfs_problem *p, const double *b, double *x, const mfs_options *opts, void *stream) {
   return guard([&] {
+    no_amr(p, "the solve");
     check_problem(p);
     MFS_REQUIRE(b && x && (const void *)b != (void *)x, MFS_EINVAL, "bad vectors");
     mfs_options o = opts ? *opts : p->opts;
@@ -2499,7 +2710,10 @@ int mfs_set_linearization(mfs_problem *p, const double *u0, double dt, int newto
     MFS_REQUIRE(u0 != nullptr, MFS_EINVAL, "u0 is NULL");
     MFS_REQUIRE(dt > 0 && std::isfinite(dt), MFS_EINVAL, "dt must be positive");
     drop_prec_graph(*p);
-    ns_set_linearization(*p, u0, dt, newton, S(stream));
+    if (p->amr)
+      amr_set_linearization(*p, u0, dt, newton, S(stream));
+    else
+      ns_set_linearization(*p, u0, dt, newton, S(stream));
   });
 }
 

@@ -39,6 +39,12 @@ struct Args {
   T nu, alpha, dt;
   int newton;
   T *ev;  // cell-local outputs instead of atomics when non-null (3D)
+  // cell-local inputs (3D): velocity [cell][3][(k+1)^3], then pressure
+  // [cell][(k+1)^3] (ev layout; the linearisation reads the velocity part),
+  // and per-cell corner coordinates [cell][8][3] (x fastest) instead of the
+  // structured vertex grid; with evin, src, dst and the node grid are unused
+  const T *evin;
+  const T *Xcell;
 };
 
 template <int DIM, typename T>
@@ -247,7 +253,9 @@ __device__ __forceinline__ T laplacian(const T h[6], const T I[3][3]) {
 // point (global loads a kernel issues between the two halves overlap the
 // vertex loads and the barrier)
 #define NSK_PROLOGUE_B                                                                                 \
-  if (c.valid)                                                                                         \
+  if (c.valid && a.Xcell)                                                                              \
+    for (int idx = c.t; idx < Sh::NV * DIM; idx += NQ) s_X[e][idx] = a.Xcell[(int64_t)cell * Sh::NV * DIM + idx]; \
+  else if (c.valid)                                                                                    \
     for (int idx = c.t; idx < Sh::NV * DIM; idx += NQ) {                                               \
       const int v_ = idx / DIM, comp_ = idx % DIM;                                                     \
       const int vx = c.cx + (v_ & 1), vy = c.cy + ((v_ >> 1) & 1), vz = c.cz + ((v_ >> 2) & 1);        \
@@ -270,7 +278,9 @@ __global__ void __launch_bounds__((Shape<DIM, K>::BLOCK)) ns_linearize_kernel(Ar
   __shared__ T s_vol[CPB];
   T u[3] = {}, U[3][3] = {}, lap[3] = {};
   for (int comp = 0; comp < DIM; ++comp) {
-    if (c.active) c.b0[c.t] = c.valid ? a.src[comp * a.Nv + nd] : T(0);
+    T v0 = T(0);
+    if (c.valid) v0 = a.evin ? a.evin[((int64_t)cell * 3 + comp) * NQ + c.t] : a.src[comp * a.Nv + nd];
+    if (c.active) c.b0[c.t] = v0;
     csync<Sh::WAVE>();
     T val, g[3], h[6];
     c.template evaluate<true>(val, g, h);
@@ -317,9 +327,14 @@ __global__ void __launch_bounds__((Shape<DIM, K>::BLOCK)) ns_jacobian_kernel(Arg
   // linearisation data) is issued before the vertex loads and the barrier
   T sv[4] = {0, 0, 0, 0};
   T u0[3] = {}, U[3][3] = {}, R0[3] = {}, dl = 0;
-  if (c.valid) {
+  if (c.valid && a.evin) {
+    for (int comp = 0; comp < DIM; ++comp) sv[comp] = a.evin[((int64_t)cell * 3 + comp) * NQ + c.t];
+    sv[DIM] = a.evin[(int64_t)a.ncells * 3 * NQ + (int64_t)cell * NQ + c.t];
+  } else if (c.valid) {
     for (int comp = 0; comp < DIM; ++comp) sv[comp] = dir ? T(0) : a.src[comp * a.Nv + nd];
     sv[DIM] = a.src[DIM * a.Nv + nd];
+  }
+  if (c.valid) {
     for (int x = 0; x < DIM; ++x) u0[x] = qd[x * NQ];
     for (int cc = 0; cc < DIM; ++cc)
       for (int x = 0; x < DIM; ++x) U[cc][x] = qd[(3 + 3 * cc + x) * NQ];
@@ -414,7 +429,7 @@ __global__ void __launch_bounds__((Shape<DIM, K>::BLOCK)) ns_jacobian_kernel(Arg
 
 template <typename T>
 void launch_ns(const LevelGeom &g, const T *X, const T *tab, int what, T nu, T dt, int newton, const T *src, T *dst,
-               T *qd, hipStream_t s, T *ev) {
+               T *qd, hipStream_t s, T *ev, const T *evin, const T *Xcell) {
   MFS_REQUIRE(g.kp == g.k, MFS_EUNSUPPORTED, "Navier-Stokes operator needs equal-order elements");
   nsk::Args<T> a{};
   a.n0 = g.n[0];
@@ -436,6 +451,10 @@ void launch_ns(const LevelGeom &g, const T *X, const T *tab, int what, T nu, T d
   a.newton = newton;
   MFS_REQUIRE(ev == nullptr || g.dim == 3, MFS_EINVAL, "cell-local Navier-Stokes outputs are 3D");
   a.ev = ev;
+  MFS_REQUIRE(evin == nullptr || (g.dim == 3 && Xcell != nullptr && (what == 0 || ev != nullptr)), MFS_EINVAL,
+              "cell-local Navier-Stokes inputs need 3D, corner coordinates and cell-local outputs");
+  a.evin = evin;
+  a.Xcell = Xcell;
 #define NS_GO(D, KK)                                                                                             \
   {                                                                                                              \
     using Sh = nsk::Shape<D, KK>;                                                                                \
@@ -457,9 +476,10 @@ void launch_ns(const LevelGeom &g, const T *X, const T *tab, int what, T nu, T d
 }
 
 template void launch_ns<double>(const LevelGeom &, const double *, const double *, int, double, double, int,
-                                const double *, double *, double *, hipStream_t, double *);
+                                const double *, double *, double *, hipStream_t, double *, const double *,
+                                const double *);
 template void launch_ns<float>(const LevelGeom &, const float *, const float *, int, float, float, int, const float *,
-                               float *, float *, hipStream_t, float *);
+                               float *, float *, hipStream_t, float *, const float *, const float *);
 
 namespace {
 
@@ -488,6 +508,14 @@ __global__ void k_color_extract(LevelGeom g, int q, int color, int comp, const d
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= g.Nv) return;
   if (node_color(g, q, i) == color) diag[comp * g.Nv + i] = y[comp * g.Nv + i];
+}
+
+// ev[(cell*3 + comp)*nq + t] = ev[3*ncells*nq + cell*nq + t]
+__global__ void k_ev_to_velocity(double *ev, int64_t ncells, int nq, int comp) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= ncells * nq) return;
+  const int64_t cell = i / nq, t = i % nq;
+  ev[(cell * 3 + comp) * nq + t] = ev[3 * ncells * nq + i];
 }
 
 template <typename T>
@@ -520,6 +548,12 @@ void launch_color_extract(const LevelGeom &g, int q, int color, int comp, const 
                           hipStream_t s) {
   hipLaunchKernelGGL(k_color_extract, dim3((unsigned)((g.Nv + 255) / 256)), dim3(256), 0, s, g, q, color, comp, y,
                      diag);
+  MFS_HIP(hipGetLastError());
+}
+
+void launch_ev_to_velocity(double *ev, int64_t ncells, int nq, int comp, hipStream_t s) {
+  hipLaunchKernelGGL(k_ev_to_velocity, dim3((unsigned)((ncells * nq + 255) / 256)), dim3(256), 0, s, ev, ncells, nq,
+                     comp);
   MFS_HIP(hipGetLastError());
 }
 

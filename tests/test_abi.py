@@ -31,6 +31,7 @@ def test_default_options():
     o = mfs.mfs_default_options()
     assert o.pressure_offset == 1 and o.cheb_degree == 5 and o.restart == 30
     assert o.precond_precision == mfs.MFS_FP32 and abs(o.rtol - 1e-8) < 1e-20
+    assert o.graphs == 1
 
 
 def test_footprint_and_validation_host_only():
@@ -79,3 +80,22 @@ def test_hp_setup_validates_degrees_on_host():
     with pytest.raises(mfs.MfsError) as e:
         mfs.mfs_setup_hp([2, 2, 2], X, [2] * 8, 1.0, mfs.mfs_default_options(pressure_offset=0), stream=0)
     assert e.value.code == mfs.MFS_EINVAL
+
+
+def test_refined_mesh_validation_host_only():
+    """mfs_setup_refined rejects bad leaves and unsupported options before it
+    touches the device (null stream, no GPU needed)."""
+    m = inputs.refined_mesh(3, 0, levels=2, centre=[0.4, 0.5, 0.55], radius=0.3)
+    overlap = dict(m, idx=m["idx"].copy())
+    overlap["idx"][5] = overlap["idx"][6]
+    gap = dict(m, level=m["level"][1:], idx=m["idx"][1:])
+    deep = dict(m, level=m["level"].copy())
+    deep["level"][0] = 3
+    cases = [(overlap, 2, None, mfs.MFS_EINVAL), (gap, 2, None, mfs.MFS_EINVAL), (deep, 2, None, mfs.MFS_EINVAL),
+             (m, 3, None, mfs.MFS_EUNSUPPORTED),
+             (m, 2, mfs.mfs_default_options(pressure_offset=1, mg_levels=0), mfs.MFS_EUNSUPPORTED),
+             (m, 2, mfs.mfs_default_options(pressure_offset=0, mg_levels=1), mfs.MFS_EUNSUPPORTED)]
+    for mesh, k, opts, code in cases:
+        with pytest.raises(mfs.MfsError) as e:
+            mfs.mfs_setup_refined(mesh, k, 0.01, opts, stream=0)
+        assert e.value.code == code
