@@ -14,6 +14,10 @@
   A wrong constraint weight breaks this identity (checked by planting one).
 * The constrained Jacobian: element loop = assembled matrix, the constant
   pressure is in its kernel.
+* Multigrid: global coarsening reaches the uniform base mesh one level at a
+  time; on a mesh refined everywhere the hierarchy and its V-cycle are the
+  structured ones; the transfers interpolate Q_k polynomials exactly and
+  vanish on Dirichlet rows; FGMRES with the V-cycle converges.
 """
 import numpy as np
 import pytest
@@ -114,3 +118,52 @@ def test_constrained_jacobian(k, newton):
     assert np.abs(J @ e).max() <= 1e-13 * abs(J).max()
     mask = S.ns_dirichlet_true()
     assert np.all(J[mask][:, ~mask].nnz == 0)
+
+
+# ------------------------------------------------------------------ multigrid
+from oracle import amr_mg, ns_mg  # noqa: E402
+
+
+def test_global_coarsening_sequence():
+    m = inputs.refined_mesh(**MESH)
+    seq = [m]
+    while seq[-1]["level"].max() > 0:
+        seq.append(amr_mg.coarsen(seq[-1]))
+    assert [s["level"].max() for s in seq] == list(range(m["level"].max(), -1, -1))
+    for s in seq:
+        _, count = _level_map(dict(s, levels=m["levels"]))
+        assert (count == 1).all()
+    assert len(seq[-1]["level"]) == m["n"] ** 3
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_multigrid_of_refinement_everywhere_is_structured(k):
+    m = inputs.refined_mesh(2, 0, levels=1, centre=[0.5] * 3, radius=10.0)
+    S = amr.AmrSpace(m, k)
+    u0 = inputs.fourier_field(4)(S.true_points()).T.ravel()
+    H = amr_mg.AmrNSHierarchy(m, k, 0.01, 1e-2, u0)
+    Hs = ns_mg.NSHierarchy(3, [4, 4, 4], inputs.structured_vertices(3, [4, 4, 4]), k, 0.01, 1e-2, u0)
+    b = inputs.uniform_vector(4 * S.N, 5)
+    ref = Hs.vcycle(b)
+    assert np.abs(H.vcycle(b) - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_refined_multigrid_transfers_and_solve(k):
+    m = inputs.refined_mesh(**MESH)
+    S = amr.AmrSpace(m, k)
+    u0 = inputs.fourier_field(4)(S.true_points()).T.ravel()
+    H = amr_mg.AmrNSHierarchy(m, k, 0.01, 1e-2, u0)
+    assert H.nga == 2
+    q = lambda p: 1 + p[:, 0] ** k + p[:, 1] * p[:, 2] ** k  # noqa: E731
+    for j in range(H.nga):  # the pressure block interpolates Q_k polynomials exactly
+        Sf, Sc = H.spaces[j], H.spaces[j + 1]
+        Pp = H.P[j][3 * Sf.N:, 3 * Sc.N:]
+        assert np.abs(Pp @ q(Sc.true_points()) - q(Sf.true_points())).max() < 1e-13
+        assert abs(H.P[j][:3 * Sf.N][H.fixed[j][:3 * Sf.N]]).max() == 0  # Dirichlet rows
+    xt = inputs.uniform_vector(4 * S.N, 3)
+    xt[H.fixed[0]] = 0.0
+    b = H.J[0] @ xt
+    x, its, rel = H.solve(b, rtol=1e-8)
+    assert rel <= 1e-8 and its <= 12
+    assert np.linalg.norm(b - H.J[0] @ x) <= 1.01e-8 * np.linalg.norm(b)
