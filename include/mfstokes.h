@@ -178,22 +178,38 @@ typedef struct mfs_refined_mesh {
 /*
  * setup on a locally refined mesh (Sec. 5: the stabilised Navier-Stokes
  * problem on meshes with hanging nodes): equal-order Q_k/Q_k, k in {1, 2}
- * (opts->pressure_offset must be 0), operators only (opts->mg_levels must
- * be 0).  The space is the continuous one: a node of a finer cell that lies
- * on a face or edge of a coarser neighbour without being one of its nodes
- * (a hanging node) takes the neighbour's interpolant there, realised by the
- * cell-local constraint maps C_e of eq. (transfer).  Unknowns: every other
- * node position, numbered in lexicographic order of position (x fastest);
- * vectors blocked [u_0 | u_1 | u_2 | p] with n_u = n_p = number of unknowns;
- * velocity unknowns on the boundary of the cube are Dirichlet unknowns.
- * Offers mfs_set_linearization (u0: 3 n_u values at the unknowns),
- * mfs_vmult with MFS_OP_NS_JACOBIAN on level 0 (FP64 or FP32), mfs_n_dofs,
- * mfs_n_levels (1), mfs_level_info (k, base n) and mfs_support_points
- * (deg = k: the unknowns' coordinates); every other call returns
+ * (opts->pressure_offset must be 0).  The space is the continuous one: a node
+ * of a finer cell that lies on a face or edge of a coarser neighbour without
+ * being one of its nodes (a hanging node) takes the neighbour's interpolant
+ * there, realised by the cell-local constraint maps C_e of eq. (transfer).
+ * Unknowns: every other node position, numbered in lexicographic order of
+ * position (x fastest); vectors blocked [u_0 | u_1 | u_2 | p] with
+ * n_u = n_p = number of unknowns; velocity unknowns on the boundary of the
+ * cube are Dirichlet unknowns.
+ *
+ * opts->mg_levels = 0: level 0 only.  opts->mg_levels = 1: the monolithic
+ * multigrid of Sec. 5 with global coarsening: level j + 1 is level j with
+ * every family of eight leaves replaced by its parent, down to the uniform
+ * base mesh; the levels above the base (0 .. G-1, G = finest refinement level
+ * present, which must be >= 1) have their own Jacobian and Jacobi diagonal
+ * (by colour probes), and the base mesh and its coarsenings are the levels
+ * G .. of the structured Navier-Stokes hierarchy of mfs_setup (Cartesian
+ * base cube).  Transfers between GC levels: the coarse field at the fine
+ * unknowns (Dirichlet velocity rows and columns zero, pressure
+ * unconstrained); restriction is the transpose.
+ *
+ * Offers mfs_set_linearization (u0: 3 n_u values at the level-0 unknowns,
+ * copied at the coarse unknowns level by level), mfs_vmult with
+ * MFS_OP_NS_JACOBIAN on every level, mfs_n_dofs, mfs_n_levels,
+ * mfs_level_info, mfs_support_points (deg = k: the level-0 unknowns'
+ * coordinates), and with multigrid mfs_diagonal, mfs_prolongate_add,
+ * mfs_restrict, mfs_vcycle, mfs_precondition (one V-cycle) and the solve
+ * calls; mfs_rhs, the quadrature-point queries and the lambda calls return
  * MFS_EUNSUPPORTED.  MFS_EINVAL when the leaves are out of range, overlap or
- * leave a gap; MFS_EUNSUPPORTED for other degrees or options.  The hanging-
- * node maps are built on the host (sort of all cell-node positions) and
- * copied to the device; `stream` is synchronised before returning.
+ * leave a gap, or for multigrid on an unrefined mesh; MFS_EUNSUPPORTED for
+ * other degrees or options.  The hanging-node maps are built on the host
+ * (sort of all cell-node positions) and copied to the device; `stream` is
+ * synchronised before returning.
  */
 int mfs_setup_refined(const mfs_refined_mesh *mesh, int k, double nu, const mfs_options *opts, void *stream,
                       mfs_problem **out);

@@ -36,6 +36,29 @@ struct AmrSpaceHost {
   // validates the leaves (levels, index ranges, a partition of the cube) and
   // builds everything above; throws mfs::Error(MFS_EINVAL) on bad input
   void build(int n, int L, int64_t ncells, const int *level, const int *idx, int k);
+  // greedy colouring of the unknowns (needs the row maps): no two unknowns
+  // that appear in one cell's rows share a colour
+  std::vector<int> colours(int *ncolours) const;
 };
+
+// Global coarsening: every family of eight leaves replaced by its parent;
+// cells listed by level, then lexicographically (x fastest) within a level.
+void amr_coarsen(int n, const std::vector<int> &level, const std::vector<int> &idx, std::vector<int> &level_c,
+                 std::vector<int> &idx_c);
+
+// Cell relation between a mesh and its global coarsening: parent[f] = coarse
+// cell holding fine cell f, octant[f] = child position (bit a: upper half
+// along axis a) or 8 when the cell is unchanged; cptr/child list the fine
+// cells of every coarse cell (CSR, ascending fine ids).
+struct AmrTransferHost {
+  std::vector<int> parent, child;
+  std::vector<uint8_t> octant;
+  std::vector<int64_t> cptr;
+};
+AmrTransferHost amr_transfer(int n, const std::vector<int> &lf, const std::vector<int> &xf,
+                             const std::vector<int> &lc, const std::vector<int> &xc);
+// for every unknown of the coarse space, the unknown of the fine space at the
+// same position (each coarse unknown is one)
+std::vector<int64_t> amr_injection(const AmrSpaceHost &fine, const AmrSpaceHost &coarse);
 
 }  // namespace mfs

@@ -2,6 +2,7 @@
 // unknown numbering, hanging-node constraints and the cell-local row maps.
 #include <algorithm>
 #include <cmath>
+#include <unordered_map>
 #include <utility>
 
 #include "amr.h"
@@ -234,6 +235,145 @@ void AmrSpaceHost::build(int n_, int L_, int64_t ncells_, const int *level_, con
     for (int v = 0; v < 8; ++v)
       for (int a = 0; a < 3; ++a) Xcell[c * 24 + v * 3 + a] = (idx[3 * c + a] + ((v >> a) & 1)) * h;
   }
+}
+
+std::vector<int> AmrSpaceHost::colours(int *ncolours) const {
+  // cells of every unknown (CSR)
+  std::vector<int64_t> cptr((size_t)N + 1, 0);
+  for (int64_t c = 0; c < ncells; ++c)
+    for (int64_t r = V.row_base[c]; r < V.row_base[c + 1]; ++r)
+      for (int64_t q = V.row_ptr[r]; q < V.row_ptr[r + 1]; ++q) cptr[V.col[q] + 1] += 1;
+  for (int64_t g = 0; g < N; ++g) cptr[g + 1] += cptr[g];
+  std::vector<int> cells((size_t)cptr[N]);
+  {
+    std::vector<int64_t> fill(cptr.begin(), cptr.end() - 1);
+    for (int64_t c = 0; c < ncells; ++c)
+      for (int64_t r = V.row_base[c]; r < V.row_base[c + 1]; ++r)
+        for (int64_t q = V.row_ptr[r]; q < V.row_ptr[r + 1]; ++q) cells[fill[V.col[q]]++] = (int)c;
+  }
+  std::vector<int> col((size_t)N, -1);
+  std::vector<int64_t> seen;  // colour -> the last unknown that met it
+  std::vector<int> last_cell((size_t)ncells, -1);
+  int nc = 0;
+  for (int64_t g = 0; g < N; ++g) {
+    for (int64_t e = cptr[g]; e < cptr[g + 1]; ++e) {
+      const int c = cells[e];
+      if (last_cell[c] == (int)g) continue;  // a cell listed twice for g
+      last_cell[c] = (int)g;
+      for (int64_t q = V.row_ptr[V.row_base[c]]; q < V.row_ptr[V.row_base[c + 1]]; ++q) {
+        const int o = col[V.col[q]];
+        if (o >= 0) seen[o] = g;
+      }
+    }
+    int pick = 0;
+    while (pick < nc && seen[pick] == g) ++pick;
+    if (pick == nc) {
+      seen.push_back(-1);
+      ++nc;
+    }
+    col[g] = pick;
+  }
+  *ncolours = nc;
+  return col;
+}
+
+void amr_coarsen(int n, const std::vector<int> &level, const std::vector<int> &idx, std::vector<int> &level_c,
+                 std::vector<int> &idx_c) {
+  const int64_t nc = (int64_t)level.size();
+  int L = 0;
+  for (int l : level) L = std::max(L, l);
+  // children count of every parent, by (level of the parent, index)
+  std::unordered_map<int64_t, int> count;
+  auto pkey = [&](int l, int64_t x, int64_t y, int64_t z) {
+    const int64_t m = (int64_t)n << l;
+    return ((int64_t)l << 56) | (x + m * (y + m * z));
+  };
+  for (int64_t c = 0; c < nc; ++c)
+    if (level[c] > 0) count[pkey(level[c] - 1, idx[3 * c] / 2, idx[3 * c + 1] / 2, idx[3 * c + 2] / 2)] += 1;
+  struct Cell {
+    int l, x, y, z;
+  };
+  std::vector<Cell> out;
+  out.reserve((size_t)nc);
+  std::unordered_map<int64_t, int> emitted;
+  for (int64_t c = 0; c < nc; ++c) {
+    const int l = level[c];
+    if (l > 0) {
+      const int px = idx[3 * c] / 2, py = idx[3 * c + 1] / 2, pz = idx[3 * c + 2] / 2;
+      const int64_t key = pkey(l - 1, px, py, pz);
+      if (count[key] == 8) {
+        if (emitted.emplace(key, 1).second) out.push_back({l - 1, px, py, pz});
+        continue;
+      }
+    }
+    out.push_back({l, idx[3 * c], idx[3 * c + 1], idx[3 * c + 2]});
+  }
+  std::sort(out.begin(), out.end(), [](const Cell &a, const Cell &b) {
+    if (a.l != b.l) return a.l < b.l;
+    if (a.z != b.z) return a.z < b.z;
+    if (a.y != b.y) return a.y < b.y;
+    return a.x < b.x;
+  });
+  level_c.resize(out.size());
+  idx_c.resize(3 * out.size());
+  for (size_t i = 0; i < out.size(); ++i) {
+    level_c[i] = out[i].l;
+    idx_c[3 * i] = out[i].x;
+    idx_c[3 * i + 1] = out[i].y;
+    idx_c[3 * i + 2] = out[i].z;
+  }
+  (void)L;
+}
+
+AmrTransferHost amr_transfer(int n, const std::vector<int> &lf, const std::vector<int> &xf,
+                             const std::vector<int> &lc, const std::vector<int> &xc) {
+  const int64_t ncf = (int64_t)lf.size(), ncc = (int64_t)lc.size();
+  auto key = [&](int l, int64_t x, int64_t y, int64_t z) {
+    const int64_t m = (int64_t)n << l;
+    return ((int64_t)l << 56) | (x + m * (y + m * z));
+  };
+  std::unordered_map<int64_t, int> coarse;
+  coarse.reserve((size_t)ncc * 2);
+  for (int64_t c = 0; c < ncc; ++c) coarse[key(lc[c], xc[3 * c], xc[3 * c + 1], xc[3 * c + 2])] = (int)c;
+  AmrTransferHost T;
+  T.parent.resize((size_t)ncf);
+  T.octant.resize((size_t)ncf);
+  for (int64_t f = 0; f < ncf; ++f) {
+    const int l = lf[f];
+    auto same = coarse.find(key(l, xf[3 * f], xf[3 * f + 1], xf[3 * f + 2]));
+    if (same != coarse.end()) {
+      T.parent[f] = same->second;
+      T.octant[f] = 8;
+      continue;
+    }
+    MFS_REQUIRE(l > 0, MFS_EINVAL, "coarsening lost a base cell");
+    auto par = coarse.find(key(l - 1, xf[3 * f] / 2, xf[3 * f + 1] / 2, xf[3 * f + 2] / 2));
+    MFS_REQUIRE(par != coarse.end(), MFS_EINVAL, "fine cell without a coarse parent");
+    T.parent[f] = par->second;
+    T.octant[f] = (uint8_t)((xf[3 * f] & 1) | ((xf[3 * f + 1] & 1) << 1) | ((xf[3 * f + 2] & 1) << 2));
+  }
+  T.cptr.assign((size_t)ncc + 1, 0);
+  for (int64_t f = 0; f < ncf; ++f) T.cptr[T.parent[f] + 1] += 1;
+  for (int64_t c = 0; c < ncc; ++c) T.cptr[c + 1] += T.cptr[c];
+  T.child.resize((size_t)ncf);
+  std::vector<int64_t> fill(T.cptr.begin(), T.cptr.end() - 1);
+  for (int64_t f = 0; f < ncf; ++f) T.child[fill[T.parent[f]]++] = (int)f;
+  return T;
+}
+
+std::vector<int64_t> amr_injection(const AmrSpaceHost &fine, const AmrSpaceHost &coarse) {
+  MFS_REQUIRE(fine.R == 2 * coarse.R, MFS_EINVAL, "levels are not one coarsening apart");
+  std::vector<int64_t> inj((size_t)coarse.N);
+  const int64_t R1 = fine.R + 1;
+  auto kf = [&](int64_t g) { return fine.tpos[3 * g] + R1 * (fine.tpos[3 * g + 1] + R1 * fine.tpos[3 * g + 2]); };
+  int64_t f = 0;
+  for (int64_t g = 0; g < coarse.N; ++g) {
+    const int64_t key = 2 * coarse.tpos[3 * g] + R1 * (2 * coarse.tpos[3 * g + 1] + R1 * 2 * coarse.tpos[3 * g + 2]);
+    while (f < fine.N && kf(f) < key) ++f;
+    MFS_REQUIRE(f < fine.N && kf(f) == key, MFS_EINVAL, "a coarse unknown is not a fine unknown");
+    inj[g] = f;
+  }
+  return inj;
 }
 
 }  // namespace mfs

@@ -23,6 +23,7 @@
 #include <vector>
 
 #include "amr.h"
+#include "amr_kernels.h"
 #include "hp.h"
 #include "internal.h"
 
@@ -215,30 +216,52 @@ struct HpData {
 };
 
 // ------------------------------------------------------------- refined meshes
-// Equal-order Navier-Stokes on a locally refined mesh: the unknowns' maps to
-// the cell-local values (E-vectors [cell][3][(k+1)^3] velocity, then
-// [cell][(k+1)^3] pressure), the per-cell corners, the 1D tables and the
-// linearisation data.
-struct AmrData {
-  HpData H;        // device allocations and uploads
-  AmrSpaceHost S;  // host space (the row maps are released after the upload)
+// Equal-order Navier-Stokes on a locally refined mesh.  Level j of the
+// global coarsening sequence: the unknowns' maps to the cell-local values
+// (E-vectors [cell][3][(k+1)^3] velocity, then [cell][(k+1)^3] pressure), the
+// per-cell corners, the linearisation data, the Jacobi diagonal, V-cycle
+// work vectors, and the cell and unknown relations to level j + 1.
+struct AmrLevel {
+  AmrSpaceHost S;  // host space (row maps released after the upload)
   LevelGeom g{};   // degree and cell count for the cell kernels
   int64_t N = 0, NQ = 0;
   HpDevSpace vd;   // velocity: Dirichlet columns dropped, 3 components
   HpDevSpace pd;   // scalar, unconstrained (pressure; components of u0)
   double *X64 = nullptr;
   float *X32 = nullptr;
-  double *tab64 = nullptr;
-  float *tab32 = nullptr;
   double *qd64 = nullptr;
   float *qd32 = nullptr;
   double *ev64[2] = {};  // in, out
   float *ev32[2] = {};
+  double *u0 = nullptr;                        // 3 N
+  double *diag = nullptr;                      // 4 N, diag(J)
+  double *inv64 = nullptr;                     // 4 N, 1 / diag(J)
+  float *inv32 = nullptr;
+  double *w64[4] = {};                         // x, b, r, d (4 N each)
+  float *w32[4] = {};
+  int *colour = nullptr;
+  int ncolours = 0;
+  // relation to level j + 1 (the next coarser)
+  int *parent = nullptr;
+  uint8_t *octant = nullptr;
+  int64_t *cptr = nullptr;  // CSR of the fine cells per coarse cell
+  int *child = nullptr;
+  int64_t *inject = nullptr;  // coarse unknown -> fine unknown
+};
+
+struct AmrData {
+  HpData H;  // device allocations and uploads
+  int n = 0, k = 0, L = 0;
+  bool mg = false;  // GC levels + structured hierarchy of the base mesh
+  std::vector<AmrLevel> lev;  // finest first; with mg the last is the uniform base mesh
+  double *tab64 = nullptr;
+  float *tab32 = nullptr;
+  AmrEmbed E{};
+  double *ones = nullptr, *scratch = nullptr;  // N0 each (pressure mean)
   double dt = 0.0;
   int newton = 1;
   bool ready = false;
 };
-
 }  // namespace
 
 struct mfs_problem {
@@ -1360,7 +1383,16 @@ void hp_precondition(mfs_problem &P, T *y, const T *r, hipStream_t s) {
 
 // the system operator and its preconditioner: Stokes (block preconditioner)
 // or Navier-Stokes Jacobian (monolithic V-cycle)
+template <typename T>
+void amr_apply_ns(mfs_problem &P, int j, T *dst, const T *src, hipStream_t s);
+template <typename T>
+void amr_vcycle(mfs_problem &P, int j, T *x, const T *b, hipStream_t s);
+
 void apply_system(mfs_problem &P, double *dst, const double *src, hipStream_t s) {
+  if (P.amr) {
+    amr_apply_ns<double>(P, 0, dst, src, s);
+    return;
+  }
   if (P.hp) {
     const int64_t nu = 3 * P.hp->lev[0].vd.N;
     hp_apply<double>(P, 0, M_LAPLACE | M_GRADP | M_DIVU, dst, dst + nu, src, src + nu, s);
@@ -1369,12 +1401,20 @@ void apply_system(mfs_problem &P, double *dst, const double *src, hipStream_t s)
   apply_op<double>(P, P.ns ? MFS_OP_NS_JACOBIAN : MFS_OP_STOKES, 0, dst, src, s);
 }
 // sizes of the system vectors
-int64_t sys_vel(const mfs_problem &P) { return P.hp ? 3 * P.hp->lev[0].vd.N : P.dim * P.L[0].g.Nv; }
-int64_t sys_pres(const mfs_problem &P) { return P.hp ? P.hp->pd.N : P.L[0].g.Np; }
+int64_t sys_vel(const mfs_problem &P) {
+  if (P.amr) return 3 * P.amr->lev[0].N;
+  return P.hp ? 3 * P.hp->lev[0].vd.N : P.dim * P.L[0].g.Nv;
+}
+int64_t sys_pres(const mfs_problem &P) {
+  if (P.amr) return P.amr->lev[0].N;
+  return P.hp ? P.hp->pd.N : P.L[0].g.Np;
+}
 int64_t sys_n(const mfs_problem &P) { return sys_vel(P) + sys_pres(P); }
 template <typename T>
 void precondition_any(mfs_problem &P, T *y, const T *r, hipStream_t s) {
-  if (P.hp)
+  if (P.amr)
+    amr_vcycle<T>(P, 0, y, r, s);
+  else if (P.hp)
     hp_precondition<T>(P, y, r, s);
   else if (P.ns)
     ns_vcycle<T>(P, 0, y, r, s);
@@ -1490,11 +1530,11 @@ void kr_finish(mfs_problem &P, double rel, int status) {
   Krylov &K = P.kr;
   hipStream_t s = K.s;
   const int64_t nu = sys_vel(P), np = sys_pres(P);
-  const double *m1 = P.hp ? P.hp->m1 : P.m1;
+  const double *m1 = P.amr ? P.amr->ones : P.hp ? P.hp->m1 : P.m1;
   // pressure with zero mass-weighted mean (Navier-Stokes: m1 = 1, nodal mean)
   if (np > 0) {
     double *num = P.scal + 4 * PCG_MAX + 8, *den = num + 1;
-    double *ones = P.hp ? P.hp->ones : P.tmp_full;  // scratch of >= np entries
+    double *ones = P.amr ? P.amr->scratch : P.hp ? P.hp->ones : P.tmp_full;  // scratch of >= np entries
     multi_dot<double>(m1, 0, 1, K.x + nu, np, num, P.partials, s);
     vec_fill<double>(ones, 1.0, np, s);
     multi_dot<double>(m1, 0, 1, ones, np, den, P.partials, s);
@@ -2071,35 +2111,41 @@ void hp_build(mfs_problem &P, const std::vector<int> &deg0, hipStream_t s) {
 }
 // ---------------------------------------------------------------- refined meshes
 template <typename T>
-T *amr_ev(AmrData &A, int i);
-template <>
-double *amr_ev<double>(AmrData &A, int i) {
-  return A.ev64[i];
-}
-template <>
-float *amr_ev<float>(AmrData &A, int i) {
-  return A.ev32[i];
+T *amr_ev(AmrLevel &V, int i) {
+  if constexpr (sizeof(T) == 8) return V.ev64[i]; else return V.ev32[i];
 }
 template <typename T>
 const T *amr_tab(const AmrData &A) {
   if constexpr (sizeof(T) == 8) return A.tab64; else return A.tab32;
 }
 template <typename T>
-const T *amr_X(const AmrData &A) {
-  if constexpr (sizeof(T) == 8) return A.X64; else return A.X32;
+const T *amr_X(const AmrLevel &V) {
+  if constexpr (sizeof(T) == 8) return V.X64; else return V.X32;
 }
 template <typename T>
-T *amr_qd(AmrData &A) {
-  if constexpr (sizeof(T) == 8) return A.qd64; else return A.qd32;
+T *amr_qd(AmrLevel &V) {
+  if constexpr (sizeof(T) == 8) return V.qd64; else return V.qd32;
 }
+template <typename T>
+T *amr_w(AmrLevel &V, int i) {
+  if constexpr (sizeof(T) == 8) return V.w64[i]; else return V.w32[i];
+}
+template <typename T>
+const T *amr_inv(const AmrLevel &V) {
+  if constexpr (sizeof(T) == 8) return V.inv64; else return V.inv32;
+}
+// levels with their own Jacobian (the uniform base of the multigrid sequence
+// belongs to the structured hierarchy)
+int amr_nop(const AmrData &A) { return A.mg ? (int)A.lev.size() - 1 : 1; }
 
-void amr_build(mfs_problem &P, const mfs_refined_mesh &m, int k, hipStream_t s) {
-  AmrData &A = *P.amr;
-  A.S.build(m.n, m.levels, m.ncells, m.level, m.idx, k);
-  const int64_t nc = A.S.ncells, NQ = (int64_t)(k + 1) * (k + 1) * (k + 1);
-  A.N = A.S.N;
-  A.NQ = NQ;
-  LevelGeom &g = A.g;
+// device data of a level; `op`: the level applies its own Jacobian
+void amr_level_upload(AmrData &A, AmrLevel &V, bool op, bool work, hipStream_t s) {
+  AmrSpaceHost &S = V.S;
+  const int k = A.k;
+  const int64_t nc = S.ncells, NQ = (int64_t)(k + 1) * (k + 1) * (k + 1);
+  V.N = S.N;
+  V.NQ = NQ;
+  LevelGeom &g = V.g;
   g.dim = 3;
   g.k = g.kp = k;
   g.n[0] = g.n[1] = 1;
@@ -2115,70 +2161,249 @@ void amr_build(mfs_problem &P, const mfs_refined_mesh &m, int k, hipStream_t s) 
     offu[c] = c * 3 * NQ;
     offp[c] = 3 * nc * NQ + c * NQ;
   }
-  hp_upload(A.H, A.S.V, true, offu, true, A.vd, s);
-  hp_upload(A.H, A.S.V, false, offp, false, A.pd, s);
-  A.X64 = A.H.upload(A.S.Xcell, s);
-  std::vector<float> x32(A.S.Xcell.begin(), A.S.Xcell.end());
-  A.X32 = A.H.upload(x32, s);
-  const auto tab = make_tables(k, k);
-  std::vector<float> tab32(tab.begin(), tab.end());
-  A.tab64 = A.H.upload(tab, s);
-  A.tab32 = A.H.upload(tab32, s);
-  A.qd64 = A.H.alloc<double>(nc * NQ * NS_QD);
-  A.qd32 = A.H.alloc<float>(nc * NQ * NS_QD);
+  HpData &H = A.H;
+  hp_upload(H, S.V, true, offu, true, V.vd, s);
+  hp_upload(H, S.V, false, offp, false, V.pd, s);
   for (int i = 0; i < 2; ++i) {
-    A.ev64[i] = A.H.alloc<double>(4 * nc * NQ);
-    A.ev32[i] = A.H.alloc<float>(4 * nc * NQ);
+    V.ev64[i] = H.alloc<double>(4 * nc * NQ);
+    V.ev32[i] = H.alloc<float>(4 * nc * NQ);
   }
+  if (op) {
+    V.X64 = H.upload(S.Xcell, s);
+    std::vector<float> x32(S.Xcell.begin(), S.Xcell.end());
+    V.X32 = H.upload(x32, s);
+    V.qd64 = H.alloc<double>(nc * NQ * NS_QD);
+    V.qd32 = H.alloc<float>(nc * NQ * NS_QD);
+    V.u0 = H.alloc<double>(3 * V.N);
+    if (A.mg) {
+      V.diag = H.alloc<double>(4 * V.N);
+      V.inv64 = H.alloc<double>(4 * V.N);
+      V.inv32 = H.alloc<float>(4 * V.N);
+      int ncol = 0;
+      const std::vector<int> col = S.colours(&ncol);
+      V.colour = H.upload(col, s);
+      V.ncolours = ncol;
+      MFS_HIP(hipStreamSynchronize(s));  // col goes out of scope
+    }
+    MFS_HIP(hipStreamSynchronize(s));  // x32 goes out of scope
+  }
+  if (work)
+    for (int i = 0; i < 4; ++i) {
+      V.w64[i] = H.alloc<double>(4 * V.N);
+      V.w32[i] = H.alloc<float>(4 * V.N);
+    }
   MFS_HIP(hipStreamSynchronize(s));
-  // the row maps and corners live on the device now
-  A.S.V = HpSpaceHost();
-  std::vector<double>().swap(A.S.Xcell);
+  S.V = HpSpaceHost();  // the row maps and corners live on the device now
+  std::vector<double>().swap(S.Xcell);
 }
 
-// mfs_set_linearization on a refined mesh: u0 (3 blocks of N) through the
-// unconstrained scalar map into the velocity slots, then the point data
+// the levels: the given mesh, and with multigrid its global coarsenings down
+// to the uniform base mesh, with their cell and unknown relations
+void amr_build(mfs_problem &P, const mfs_refined_mesh &m, int k, bool mg, hipStream_t s) {
+  AmrData &A = *P.amr;
+  A.n = m.n;
+  A.k = k;
+  A.L = m.levels;
+  A.mg = mg;
+  A.lev.emplace_back();
+  A.lev[0].S.build(m.n, m.levels, m.ncells, m.level, m.idx, k);
+  if (mg) {
+    int top = 0;
+    for (int l : A.lev[0].S.level) top = std::max(top, l);
+    MFS_REQUIRE(top >= 1, MFS_EINVAL, "the mesh is not refined: set up the base mesh with mfs_setup");
+    for (int j = 1; j <= top; ++j) {
+      std::vector<int> lc, xc;
+      amr_coarsen(m.n, A.lev[j - 1].S.level, A.lev[j - 1].S.idx, lc, xc);
+      A.lev.emplace_back();
+      A.lev[j].S.build(m.n, m.levels - j, (int64_t)lc.size(), lc.data(), xc.data(), k);
+    }
+  }
+  const int nop = amr_nop(A);
+  HpData &H = A.H;
+  for (size_t j = 0; j + 1 < A.lev.size(); ++j) {
+    AmrLevel &F = A.lev[j], &C = A.lev[j + 1];
+    const AmrTransferHost T = amr_transfer(m.n, F.S.level, F.S.idx, C.S.level, C.S.idx);
+    F.parent = H.upload(T.parent, s);
+    F.octant = H.upload(T.octant, s);
+    F.cptr = H.upload(T.cptr, s);
+    F.child = H.upload(T.child, s);
+    const std::vector<int64_t> inj = amr_injection(F.S, C.S);
+    F.inject = H.upload(inj, s);
+    MFS_HIP(hipStreamSynchronize(s));  // T and inj go out of scope
+  }
+  for (size_t j = 0; j < A.lev.size(); ++j) amr_level_upload(A, A.lev[j], (int)j < nop, mg, s);
+  const auto tab = make_tables(k, k);
+  std::vector<float> tab32(tab.begin(), tab.end());
+  A.tab64 = H.upload(tab, s);
+  A.tab32 = H.upload(tab32, s);
+  A.E.k = k;
+  for (int h = 0; h < 2; ++h)
+    for (int t = 0; t <= k; ++t)
+      for (int q = 0; q <= k; ++q) {
+        // coarse basis function q of the k+1 equispaced nodes at fine node t of half h
+        const double x = 0.5 * (h + (double)t / k);
+        double v = 1.0;
+        for (int r = 0; r <= k; ++r)
+          if (r != q) v *= (x - (double)r / k) / ((double)(q - r) / k);
+        A.E.w[h][t][q] = v;
+      }
+  const int64_t N0 = A.lev[0].N;
+  A.ones = H.alloc<double>(N0);
+  A.scratch = H.alloc<double>(N0);
+  vec_fill<double>(A.ones, 1.0, N0, s);
+  MFS_HIP(hipStreamSynchronize(s));
+}
+
+// constrained Jacobian on level j: gather with the constraints (the
+// velocity's Dirichlet columns dropped), cell kernel on the E-vectors,
+// transposed scatter (identity on the velocity Dirichlet rows)
+template <typename T>
+void amr_apply_ns(mfs_problem &P, int j, T *dst, const T *src, hipStream_t s) {
+  AmrData &A = *P.amr;
+  MFS_REQUIRE(A.ready, MFS_EINVAL, "mfs_set_linearization has not been called");
+  AmrLevel &V = A.lev[j];
+  T *evi = amr_ev<T>(V, 0), *evo = amr_ev<T>(V, 1);
+  const int64_t N = V.N;
+  hp_gather_space<T>(V.vd, 3, src, evi, s);
+  hp_gather_space<T>(V.pd, 1, src + 3 * N, evi, s);
+  launch_ns<T>(V.g, nullptr, amr_tab<T>(A), 1, (T)P.nu, (T)A.dt, A.newton, nullptr, nullptr, amr_qd<T>(V), s, evo,
+               evi, amr_X<T>(V));
+  hp_scatter_space<T>(V.vd, 3, true, evo, src, dst, s);
+  hp_scatter_space<T>(V.pd, 1, false, evo, nullptr, dst + 3 * N, s);
+}
+
+// prolongation from level j+1 to level j (added to xf): gather the coarse
+// cells' values through the coarse constraints, embed them in the fine
+// cells, take each fine unknown from its owner slot (Dirichlet velocity rows
+// and columns zero, pressure unconstrained)
+template <typename T>
+void amr_prolongate_add(mfs_problem &P, int j, T *xf, const T *xc, hipStream_t s) {
+  AmrData &A = *P.amr;
+  AmrLevel &F = A.lev[j], &C = A.lev[j + 1];
+  T *evc = amr_ev<T>(C, 0), *evf = amr_ev<T>(F, 1);
+  hp_gather_space<T>(C.vd, 3, xc, evc, s);
+  hp_gather_space<T>(C.pd, 1, xc + 3 * C.N, evc, s);
+  amr_embed<T>(A.E, F.S.ncells, C.S.ncells, F.parent, F.octant, evc, evf, s);
+  hp_inject<T>(F.N, 3, F.vd.owner_ev, F.vd.owner_nb, evf, xf, true, s);
+  hp_inject<T>(F.N, 1, F.pd.owner_ev, F.pd.owner_nb, evf, xf + 3 * F.N, true, s);
+}
+
+// restriction (the transpose) from level j to level j+1
+template <typename T>
+void amr_restrict(mfs_problem &P, int j, T *bc, const T *rf, hipStream_t s) {
+  AmrData &A = *P.amr;
+  AmrLevel &F = A.lev[j], &C = A.lev[j + 1];
+  T *evc = amr_ev<T>(C, 0), *evf = amr_ev<T>(F, 1);
+  vec_fill<T>(evf, T(0), 4 * F.S.ncells * F.NQ, s);
+  hp_inject_t<T>(F.N, 3, F.vd.owner_ev, F.vd.owner_nb, rf, evf, s);
+  hp_inject_t<T>(F.N, 1, F.pd.owner_ev, F.pd.owner_nb, rf + 3 * F.N, evf, s);
+  amr_embed_t<T>(A.E, F.S.ncells, C.S.ncells, F.cptr, F.child, F.octant, evf, evc, s);
+  hp_scatter_space<T>(C.vd, 3, true, evc, nullptr, bc, s);
+  hp_scatter_space<T>(C.pd, 1, false, evc, nullptr, bc + 3 * C.N, s);
+}
+
+template <typename T>
+void amr_relax(mfs_problem &P, int j, T *x, const T *b, hipStream_t s) {
+  AmrLevel &V = P.amr->lev[j];
+  T *d = amr_w<T>(V, 3);
+  for (int it = 0; it < P.opts.relax_steps; ++it) {
+    amr_apply_ns<T>(P, j, d, x, s);
+    jacobi_relax<T>(x, b, d, amr_inv<T>(V), (T)P.opts.relax_omega, 4 * V.N, s);
+  }
+}
+
+// one V-cycle from level j: as the structured monolithic V-cycle, with the
+// GC levels first and the structured hierarchy of the base mesh below them
+template <typename T>
+void amr_vcycle(mfs_problem &P, int j, T *x, const T *b, hipStream_t s) {
+  AmrData &A = *P.amr;
+  MFS_REQUIRE(A.mg, MFS_EUNSUPPORTED, "problem was set up without multigrid levels");
+  if (j == amr_nop(A)) {
+    ns_vcycle<T>(P, 0, x, b, s);
+    return;
+  }
+  AmrLevel &V = A.lev[j], &C = A.lev[j + 1];
+  mask_fill_dirichlet<T>(V.vd.dir, V.N, 3, x, b, s);  // x = b on Dirichlet rows, 0 elsewhere
+  vec_fill<T>(x + 3 * V.N, T(0), V.N, s);
+  amr_relax<T>(P, j, x, b, s);
+  T *r = amr_w<T>(V, 2);
+  amr_apply_ns<T>(P, j, r, x, s);
+  vec_axpby<T>(r, T(1), b, T(-1), 4 * V.N, s);  // r = b - J x
+  T *xc = amr_w<T>(C, 0), *bc = amr_w<T>(C, 1);
+  amr_restrict<T>(P, j, bc, r, s);
+  amr_vcycle<T>(P, j + 1, xc, bc, s);
+  amr_prolongate_add<T>(P, j, x, xc, s);
+  amr_relax<T>(P, j, x, b, s);
+}
+
+// Jacobi diagonal of level j by colour probes (FP64): J applied to the
+// indicator of one colour in one component gives the diagonal entries of
+// that colour (no two unknowns of a colour meet in a cell)
+void amr_diagonal(mfs_problem &P, int j, double *diag, hipStream_t s) {
+  AmrLevel &V = P.amr->lev[j];
+  double *e = V.w64[0], *y = V.w64[1];
+  for (int col = 0; col < V.ncolours; ++col)
+    for (int comp = 0; comp < 4; ++comp) {
+      amr_colour_probe(V.colour, V.N, col, comp, e, s);
+      amr_apply_ns<double>(P, j, y, e, s);
+      amr_colour_take(V.colour, V.N, col, comp, y, diag, s);
+    }
+}
+
+// mfs_set_linearization on a refined mesh: u0 at the unknowns of level 0,
+// copied at the coarse unknowns level by level; point data per level (u0
+// through the unconstrained scalar map into the velocity slots); with
+// multigrid the structured base levels and the GC levels' diagonals
 void amr_set_linearization(mfs_problem &P, const double *u0, double dt, int newton, hipStream_t s) {
   AmrData &A = *P.amr;
   A.ready = false;
   A.dt = dt;
   A.newton = newton ? 1 : 0;
-  double *ev = A.ev64[0];
-  for (int c = 0; c < 3; ++c) {
-    hp_gather_space<double>(A.pd, 1, u0 + c * A.N, ev, s);
-    launch_ev_to_velocity(ev, A.g.ncells, (int)A.NQ, c, s);
+  const int nop = amr_nop(A);
+  MFS_HIP(hipMemcpyAsync(A.lev[0].u0, u0, 3 * A.lev[0].N * sizeof(double), hipMemcpyDeviceToDevice, s));
+  for (int j = 1; j < nop; ++j)
+    permute<double>(A.lev[j].N, 3, A.lev[j - 1].inject, A.lev[j - 1].u0, A.lev[j - 1].N, A.lev[j].u0, A.lev[j].N,
+                    false, s);
+  for (int j = 0; j < nop; ++j) {
+    AmrLevel &V = A.lev[j];
+    double *ev = V.ev64[0];
+    for (int c = 0; c < 3; ++c) {
+      hp_gather_space<double>(V.pd, 1, V.u0 + c * V.N, ev, s);
+      launch_ev_to_velocity(ev, V.g.ncells, (int)V.NQ, c, s);
+    }
+    launch_ns<double>(V.g, nullptr, A.tab64, 0, P.nu, dt, A.newton, nullptr, nullptr, V.qd64, s, nullptr, ev, V.X64);
+    vec_cast<float, double>(V.qd32, V.qd64, V.g.ncells * V.NQ * NS_QD, s);
   }
-  launch_ns<double>(A.g, nullptr, A.tab64, 0, P.nu, dt, A.newton, nullptr, nullptr, A.qd64, s, nullptr, ev, A.X64);
-  vec_cast<float, double>(A.qd32, A.qd64, A.g.ncells * A.NQ * NS_QD, s);
+  if (A.mg) {
+    AmrLevel &F = A.lev[nop - 1], &B = A.lev[nop];
+    MFS_REQUIRE(B.N == P.L[0].g.Nv, MFS_EINVAL, "base level mismatch");
+    permute<double>(B.N, 3, F.inject, F.u0, F.N, P.tmp_full, B.N, false, s);
+    ns_set_linearization(P, P.tmp_full, dt, newton, s);  // structured levels; synchronises
+    A.ready = true;
+    try {
+      for (int j = 0; j < nop; ++j) {
+        AmrLevel &V = A.lev[j];
+        amr_diagonal(P, j, V.diag, s);
+        launch_reciprocal(V.inv64, V.inv32, V.diag, 4 * V.N, s);
+      }
+      MFS_HIP(hipStreamSynchronize(s));
+    } catch (...) {
+      A.ready = false;
+      throw;
+    }
+    return;
+  }
   MFS_HIP(hipStreamSynchronize(s));
   A.ready = true;
 }
 
-// constrained Jacobian on a refined mesh: gather with the constraints (the
-// velocity's Dirichlet columns dropped), cell kernel on the E-vectors,
-// transposed scatter (identity on the velocity Dirichlet rows)
-template <typename T>
-void amr_apply_ns(mfs_problem &P, T *dst, const T *src, hipStream_t s) {
-  AmrData &A = *P.amr;
-  MFS_REQUIRE(A.ready, MFS_EINVAL, "mfs_set_linearization has not been called");
-  T *evi = amr_ev<T>(A, 0), *evo = amr_ev<T>(A, 1);
-  const int64_t N = A.N;
-  hp_gather_space<T>(A.vd, 3, src, evi, s);
-  hp_gather_space<T>(A.pd, 1, src + 3 * N, evi, s);
-  launch_ns<T>(A.g, nullptr, amr_tab<T>(A), 1, (T)P.nu, (T)A.dt, A.newton, nullptr, nullptr, amr_qd<T>(A), s, evo,
-               evi, amr_X<T>(A));
-  hp_scatter_space<T>(A.vd, 3, true, evo, src, dst, s);
-  hp_scatter_space<T>(A.pd, 1, false, evo, nullptr, dst + 3 * N, s);
-}
-
 void amr_vmult(mfs_problem &P, int op, int prec, int level, void *dst, const void *src, hipStream_t s) {
-  MFS_REQUIRE(level == 0, MFS_EUNSUPPORTED, "refined-mesh problems have one level");
   MFS_REQUIRE(op == MFS_OP_NS_JACOBIAN, MFS_EUNSUPPORTED,
               "refined-mesh problems provide the Navier-Stokes Jacobian (operator %d requested)", op);
   if (prec == MFS_FP64)
-    amr_apply_ns<double>(P, (double *)dst, (const double *)src, s);
+    amr_apply_ns<double>(P, level, (double *)dst, (const double *)src, s);
   else
-    amr_apply_ns<float>(P, (float *)dst, (const float *)src, s);
+    amr_apply_ns<float>(P, level, (float *)dst, (const float *)src, s);
 }
 
 // mfs_vmult on an hp problem: the hp levels (all operators on the finest,
@@ -2266,16 +2491,50 @@ int mfs_setup_refined(const mfs_refined_mesh *mesh, int k, double nu, const mfs_
       mfs_default_options(&o);
     MFS_REQUIRE(o.pressure_offset == 0, MFS_EUNSUPPORTED,
                 "refined meshes provide the equal-order Navier-Stokes Jacobian (pressure_offset = 0)");
-    MFS_REQUIRE(o.mg_levels == 0, MFS_EUNSUPPORTED, "refined meshes provide operators only (mg_levels = 0)");
-    P = new mfs_problem();
-    P->dim = 3;
-    P->nu = nu;
-    P->opts = o;
-    P->stream = S(stream);
-    P->ns = true;
-    P->namr = 1;
+    MFS_REQUIRE(k == 1 || k == 2, MFS_EUNSUPPORTED, "refined meshes support degrees 1 and 2 (got %d)", k);
+    MFS_REQUIRE(mesh->n >= 1 && mesh->n <= 4096, MFS_EINVAL, "base cells per direction %d out of range", mesh->n);
+    const bool mg = o.mg_levels != 0;
+    if (mg) {
+      // the structured hierarchy of the uniform base mesh (Cartesian unit cube)
+      const int n = mesh->n;
+      std::vector<double> X((size_t)3 * (n + 1) * (n + 1) * (n + 1));
+      for (int z = 0; z <= n; ++z)
+        for (int y = 0; y <= n; ++y)
+          for (int x = 0; x <= n; ++x) {
+            const size_t v = (size_t)x + (size_t)(n + 1) * (y + (size_t)(n + 1) * z);
+            X[3 * v] = (double)x / n;
+            X[3 * v + 1] = (double)y / n;
+            X[3 * v + 2] = (double)z / n;
+          }
+      mfs_mesh bm{};
+      bm.dim = 3;
+      bm.n[0] = bm.n[1] = bm.n[2] = n;
+      bm.vertices = X.data();
+      const int rcb = mfs_setup(&bm, k, nu, &o, stream, &P);
+      if (rcb != MFS_OK) throw mfs::Error{rcb};
+    } else {
+      P = new mfs_problem();
+      P->dim = 3;
+      P->nu = nu;
+      P->opts = o;
+      P->stream = S(stream);
+      P->ns = true;
+    }
     P->amr = new AmrData();
-    amr_build(*P, *mesh, k, S(stream));
+    amr_build(*P, *mesh, k, mg, S(stream));
+    AmrData &A = *P->amr;
+    P->namr = amr_nop(A);
+    if (mg) {
+      // FGMRES and the FP32 staging vectors at the size of the refined system
+      const int64_t n0 = 4 * A.lev[0].N;
+      Krylov &K = P->kr;
+      K.ld = kr_ld(n0);
+      K.V = A.H.alloc<double>((K.m + 1) * K.ld);
+      K.Z = A.H.alloc<double>(K.m * K.ld);
+      K.w = A.H.alloc<double>(n0);
+      P->w32.full_in = A.H.alloc<float>(n0);
+      P->w32.full_out = A.H.alloc<float>(n0);
+    }
     *out = P;
   });
   if (rc != MFS_OK) {
@@ -2307,6 +2566,7 @@ void kr_begin(mfs_problem &P, const double *b, double *x, const mfs_options &o, 
   MFS_REQUIRE(P.opts.mg_levels, MFS_EINVAL, "solve needs the multigrid hierarchy (mg_levels = 1)");
   MFS_REQUIRE(P.hp || P.L[0].g.Np > 0, MFS_EINVAL, "solve needs a pressure space");
   MFS_REQUIRE(!P.ns || P.ns_ready, MFS_EINVAL, "mfs_set_linearization has not been called");
+  MFS_REQUIRE(!P.amr || P.amr->ready, MFS_EINVAL, "mfs_set_linearization has not been called");
   const LevelGeom &g = P.L[0].g;
   const int64_t n = sys_n(P);
   K.b = b;
@@ -2325,7 +2585,9 @@ void kr_begin(mfs_problem &P, const double *b, double *x, const mfs_options &o, 
   K.info = mfs_solve_info{};
   K.t0 = std::chrono::steady_clock::now();
   // ||b|| first (state 1 reads it as bnorm), then the residual of x0
-  if (P.hp)  // x0: lifting of b's Dirichlet rows
+  if (P.amr)  // x0: lifting of b's Dirichlet rows
+    mask_fill_dirichlet<double>(P.amr->lev[0].vd.dir, P.amr->lev[0].N, 3, x, b, s);
+  else if (P.hp)
     mask_fill_dirichlet<double>(P.hp->lev[0].vd.dir, P.hp->lev[0].vd.N, 3, x, b, s);
   else
     launch_fill_dirichlet<double>(g, x, b, s);
@@ -2346,9 +2608,12 @@ int mfs_n_dofs(const mfs_problem *p, int level, int64_t *n_u, int64_t *n_p) {
   return guard([&] {
     check_level(p, level);
     if (p->amr) {
-      if (n_u) *n_u = p->amr->N;
-      if (n_p) *n_p = p->amr->N;
-      return;
+      if (level < p->namr) {
+        if (n_u) *n_u = p->amr->lev[level].N;
+        if (n_p) *n_p = p->amr->lev[level].N;
+        return;
+      }
+      level -= p->namr;
     }
     if (level < p->nhp) {
       if (n_u) *n_u = p->hp->lev[level].V.N;
@@ -2373,10 +2638,13 @@ int mfs_level_info(const mfs_problem *p, int level, int *k, int *n) {
   return guard([&] {
     check_level(p, level);
     if (p->amr) {
-      if (k) *k = p->amr->g.k;
-      if (n)
-        for (int a = 0; a < 3; ++a) n[a] = p->amr->S.n;
-      return;
+      if (level < p->namr) {
+        if (k) *k = p->amr->k;
+        if (n)
+          for (int a = 0; a < 3; ++a) n[a] = p->amr->n;
+        return;
+      }
+      level -= p->namr;
     }
     if (level < p->nhp) {
       const auto &d = p->hp->lev[level].V.deg;
@@ -2399,7 +2667,7 @@ int mfs_support_points(const mfs_problem *p, int deg, double *xyz) {
     MFS_REQUIRE(deg >= 1 && deg <= 7, MFS_EINVAL, "degree out of range");
     MFS_REQUIRE(xyz != nullptr, MFS_EINVAL, "buffer is NULL");
     if (p->amr) {
-      const AmrSpaceHost &A = p->amr->S;
+      const AmrSpaceHost &A = p->amr->lev[0].S;
       MFS_REQUIRE(deg == A.k, MFS_EUNSUPPORTED, "refined meshes provide the points of degree %d", A.k);
       for (int64_t i = 0; i < 3 * A.N; ++i) xyz[i] = (double)A.tpos[i] / (double)A.R;
       return;
@@ -2472,8 +2740,11 @@ int mfs_vmult(mfs_problem *p, int op, int prec, int level, void *dst, const void
     MFS_REQUIRE(dst && src, MFS_EINVAL, "NULL vector");
     MFS_REQUIRE(dst != src, MFS_EINVAL, "dst and src must not alias");
     if (p->amr) {
-      amr_vmult(*p, op, prec, level, dst, src, S(stream));
-      return;
+      if (level < p->namr) {
+        amr_vmult(*p, op, prec, level, dst, src, S(stream));
+        return;
+      }
+      level -= p->namr;
     }
     if (p->hp) {
       hp_vmult(*p, op, prec, level, dst, src, S(stream));
@@ -2488,10 +2759,19 @@ int mfs_vmult(mfs_problem *p, int op, int prec, int level, void *dst, const void
 
 int mfs_diagonal(mfs_problem *p, int level, double *dst, void *stream) {
   return guard([&] {
-    no_amr(p, "mfs_diagonal");
     check_level(p, level);
     MFS_REQUIRE(dst != nullptr, MFS_EINVAL, "NULL vector");
     hipStream_t s = S(stream);
+    if (p->amr) {
+      MFS_REQUIRE(p->amr->mg, MFS_EUNSUPPORTED, "problem was set up without multigrid levels");
+      MFS_REQUIRE(p->amr->ready, MFS_EINVAL, "mfs_set_linearization has not been called");
+      if (level < p->namr) {
+        AmrLevel &V = p->amr->lev[level];
+        vec_copy<double>(dst, V.diag, 4 * V.N, s);
+        return;
+      }
+      level -= p->namr;
+    }
     if (p->hp && level < p->nhp) {
       vec_copy<double>(dst, p->hp->lev[level].diag, p->hp->lev[level].V.N, s);
       return;
@@ -2534,13 +2814,17 @@ int mfs_set_lambda(mfs_problem *p, int level, double lambda) {
 
 int mfs_vcycle(mfs_problem *p, int prec, void *dst, const void *src, void *stream) {
   return guard([&] {
-    no_amr(p, "mfs_vcycle");
     check_problem(p);
     check_prec(prec);
     MFS_REQUIRE(p->opts.mg_levels, MFS_EINVAL, "problem was set up without multigrid levels");
     MFS_REQUIRE(dst && src && dst != src, MFS_EINVAL, "bad vectors");
     MFS_REQUIRE(!p->ns || p->ns_ready, MFS_EINVAL, "mfs_set_linearization has not been called");
-    if (p->hp) {
+    if (p->amr) {
+      if (prec == MFS_FP64)
+        amr_vcycle<double>(*p, 0, (double *)dst, (const double *)src, S(stream));
+      else
+        amr_vcycle<float>(*p, 0, (float *)dst, (const float *)src, S(stream));
+    } else if (p->hp) {
       if (prec == MFS_FP64)
         hp_vcycle<double>(*p, 0, (double *)dst, (const double *)src, S(stream));
       else
@@ -2559,10 +2843,19 @@ int mfs_vcycle(mfs_problem *p, int prec, void *dst, const void *src, void *strea
 
 int mfs_prolongate_add(mfs_problem *p, int prec, int fine, void *dst, const void *src, void *stream) {
   return guard([&] {
-    no_amr(p, "mfs_prolongate_add");
     check_level(p, fine);
     check_prec(prec);
-    MFS_REQUIRE(fine + 1 < p->nhp + p->nlev, MFS_EINVAL, "no coarser level below %d", fine);
+    MFS_REQUIRE(fine + 1 < p->namr + p->nhp + p->nlev, MFS_EINVAL, "no coarser level below %d", fine);
+    if (p->amr) {
+      if (fine < p->namr) {
+        if (prec == MFS_FP64)
+          amr_prolongate_add<double>(*p, fine, (double *)dst, (const double *)src, S(stream));
+        else
+          amr_prolongate_add<float>(*p, fine, (float *)dst, (const float *)src, S(stream));
+        return;
+      }
+      fine -= p->namr;
+    }
     if (fine < p->nhp) {
       if (prec == MFS_FP64)
         hp_prolongate_add<double>(*p, fine, (double *)dst, (const double *)src, S(stream));
@@ -2584,10 +2877,19 @@ int mfs_prolongate_add(mfs_problem *p, int prec, int fine, void *dst, const void
 
 int mfs_restrict(mfs_problem *p, int prec, int fine, void *dst, const void *src, void *stream) {
   return guard([&] {
-    no_amr(p, "mfs_restrict");
     check_level(p, fine);
     check_prec(prec);
-    MFS_REQUIRE(fine + 1 < p->nhp + p->nlev, MFS_EINVAL, "no coarser level below %d", fine);
+    MFS_REQUIRE(fine + 1 < p->namr + p->nhp + p->nlev, MFS_EINVAL, "no coarser level below %d", fine);
+    if (p->amr) {
+      if (fine < p->namr) {
+        if (prec == MFS_FP64)
+          amr_restrict<double>(*p, fine, (double *)dst, (const double *)src, S(stream));
+        else
+          amr_restrict<float>(*p, fine, (float *)dst, (const float *)src, S(stream));
+        return;
+      }
+      fine -= p->namr;
+    }
     if (fine < p->nhp) {
       if (prec == MFS_FP64)
         hp_restrict<double>(*p, fine, (double *)dst, (const double *)src, S(stream));
@@ -2609,7 +2911,6 @@ int mfs_restrict(mfs_problem *p, int prec, int fine, void *dst, const void *src,
 
 int mfs_precondition(mfs_problem *p, int prec, void *dst, const void *src, void *stream) {
   return guard([&] {
-    no_amr(p, "mfs_precondition");
     check_problem(p);
     check_prec(prec);
     MFS_REQUIRE(p->opts.mg_levels && (p->hp || p->L[0].g.Np > 0), MFS_EINVAL,
@@ -2651,7 +2952,6 @@ int mfs_rhs(mfs_problem *p, const double *f_qp, const double *u_dirichlet, doubl
 
 int mfs_solve_begin(mfs_problem *p, const double *b, double *x, const mfs_options *opts, void *stream) {
   return guard([&] {
-    no_amr(p, "the solve");
     check_problem(p);
     MFS_REQUIRE(b && x && (const void *)b != (void *)x, MFS_EINVAL, "bad vectors");
     mfs_options o = opts ? *opts : p->opts;

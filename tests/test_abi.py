@@ -93,8 +93,7 @@ def test_refined_mesh_validation_host_only():
     deep["level"][0] = 3
     cases = [(overlap, 2, None, mfs.MFS_EINVAL), (gap, 2, None, mfs.MFS_EINVAL), (deep, 2, None, mfs.MFS_EINVAL),
              (m, 3, None, mfs.MFS_EUNSUPPORTED),
-             (m, 2, mfs.mfs_default_options(pressure_offset=1, mg_levels=0), mfs.MFS_EUNSUPPORTED),
-             (m, 2, mfs.mfs_default_options(pressure_offset=0, mg_levels=1), mfs.MFS_EUNSUPPORTED)]
+             (m, 2, mfs.mfs_default_options(pressure_offset=1, mg_levels=0), mfs.MFS_EUNSUPPORTED)]
     for mesh, k, opts, code in cases:
         with pytest.raises(mfs.MfsError) as e:
             mfs.mfs_setup_refined(mesh, k, 0.01, opts, stream=0)

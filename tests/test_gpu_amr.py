@@ -1,9 +1,13 @@
-"""GPU parity of the Navier-Stokes Jacobian on locally refined meshes (hanging
-nodes) against the CPU oracle, through the C ABI.
+"""GPU parity of the Navier-Stokes path on locally refined meshes (hanging
+nodes) against the CPU oracle, through the C ABI: the constrained Jacobian,
+and with multigrid the global-coarsening levels (operators, Jacobi
+diagonals, transfers), the V-cycle and the FGMRES solve.
 
-Tolerances as for the structured Jacobian: FP64 within 1e-12 relative
-(2-norm and max-norm), FP32 within 2e-5.  The oracle's constrained Jacobian
-(C^T J_raw C with the Dirichlet rows) is pinned in test_oracle_amr.py.
+Tolerances as on structured meshes: FP64 operators, diagonals and transfers
+within 1e-12 relative (2-norm and max-norm), FP32 Jacobian within 2e-5,
+V-cycle within 1e-9 (FP64) and 1e-4 (FP32), solves to the FGMRES tolerance.
+The oracle's constrained Jacobian (C^T J_raw C with the Dirichlet rows) and
+its multigrid are pinned in test_oracle_amr.py.
 """
 import numpy as np
 import pytest
@@ -123,11 +127,109 @@ def test_refined_errors():
         with pytest.raises(mfs.MfsError) as e:
             mfs.mfs_vmult(h, mfs.MFS_OP_STOKES, mfs.MFS_FP64, 0, y, x)
         assert e.value.code == mfs.MFS_EUNSUPPORTED
-        with pytest.raises(mfs.MfsError) as e:
+        with pytest.raises(mfs.MfsError) as e:  # set up without multigrid levels
             mfs.mfs_vcycle(h, mfs.MFS_FP64, y, x)
-        assert e.value.code == mfs.MFS_EUNSUPPORTED
+        assert e.value.code == mfs.MFS_EINVAL
         with pytest.raises(mfs.MfsError) as e:
             mfs.mfs_solve(h, x, y)
+        assert e.value.code == mfs.MFS_EINVAL
+        with pytest.raises(mfs.MfsError) as e:
+            mfs.mfs_diagonal(h, 0, y)
         assert e.value.code == mfs.MFS_EUNSUPPORTED
+    finally:
+        mfs.mfs_destroy(h)
+
+
+# ------------------------------------------------------------------ multigrid
+from oracle import amr_mg  # noqa: E402
+
+MG_CASES = [("n3L2", 1), ("n3L2", 2), ("n4L2seed", 2)]
+
+
+def _mg_problem(name, k, nu=0.01, dt=1e-2, newton=1):
+    mesh = inputs.refined_mesh(**MESHES[name])
+    S = amr.AmrSpace(mesh, k)
+    u0 = inputs.fourier_field(4)(S.true_points()).T.ravel()
+    H = amr_mg.AmrNSHierarchy(mesh, k, nu, dt, u0, newton=bool(newton))
+    h = mfs.mfs_setup_refined(mesh, k, nu, mfs.mfs_default_options(pressure_offset=0, mg_levels=1))
+    mfs.mfs_set_linearization(h, cuda(u0), dt, newton)
+    return h, H
+
+
+@pytest.mark.parametrize("name,k", MG_CASES)
+def test_refined_levels_operators_diagonals_transfers(name, k):
+    h, H = _mg_problem(name, k)
+    try:
+        assert mfs.mfs_n_levels(h) == H.nga + len(H.base.spaces)
+        for j in range(H.nga):
+            Sf, Sc = H.spaces[j], H.spaces[j + 1]
+            assert mfs.mfs_n_dofs(h, j) == (Sf.N, Sf.N)
+            Nf, Nc = 4 * Sf.N, 4 * Sc.N
+            x = inputs.uniform_vector(Nf, 40 + j)
+            y = torch.empty(Nf, dtype=torch.float64, device="cuda")
+            mfs.mfs_vmult(h, mfs.MFS_OP_NS_JACOBIAN, mfs.MFS_FP64, j, y, cuda(x))
+            assert relerr(host(y), H.J[j] @ x) <= 1e-12
+            d = torch.empty(Nf, dtype=torch.float64, device="cuda")
+            mfs.mfs_diagonal(h, j, d)
+            assert relerr(host(d), 1.0 / H.Dinv[j]) <= 1e-12
+            xc = inputs.uniform_vector(Nc, 50 + j)
+            yf = torch.zeros(Nf, dtype=torch.float64, device="cuda")
+            mfs.mfs_prolongate_add(h, mfs.MFS_FP64, j, yf, cuda(xc))
+            assert relerr(host(yf), H.P[j] @ xc) <= 1e-12
+            yc = torch.empty(Nc, dtype=torch.float64, device="cuda")
+            mfs.mfs_restrict(h, mfs.MFS_FP64, j, yc, cuda(x))
+            assert relerr(host(yc), H.P[j].T @ x) <= 1e-12
+        # the first structured level is the uniform base mesh
+        Sb = H.base.spaces[0]
+        assert mfs.mfs_n_dofs(h, H.nga) == (Sb.Nv, Sb.Nv)
+        xb = inputs.uniform_vector(4 * Sb.Nv, 60)
+        yb = torch.empty(4 * Sb.Nv, dtype=torch.float64, device="cuda")
+        mfs.mfs_vmult(h, mfs.MFS_OP_NS_JACOBIAN, mfs.MFS_FP64, H.nga, yb, cuda(xb))
+        assert relerr(host(yb), H.base.J[0] @ xb) <= 1e-12
+    finally:
+        mfs.mfs_destroy(h)
+
+
+@pytest.mark.parametrize("name,k", MG_CASES)
+def test_refined_vcycle(name, k):
+    """FP64 V-cycle within 1e-9 of the oracle (about 30 operator applications
+    and the dense coarse inverse against an LU solve, as on structured
+    meshes); FP32 within 1e-4."""
+    h, H = _mg_problem(name, k)
+    try:
+        N = 4 * H.spaces[0].N
+        b = inputs.uniform_vector(N, 70)
+        ref = H.vcycle(b)
+        y = torch.empty(N, dtype=torch.float64, device="cuda")
+        mfs.mfs_vcycle(h, mfs.MFS_FP64, y, cuda(b))
+        assert relerr(host(y), ref) <= 1e-9
+        y32 = torch.empty(N, dtype=torch.float32, device="cuda")
+        mfs.mfs_vcycle(h, mfs.MFS_FP32, y32, cuda(b, torch.float32))
+        assert relerr(host(y32), ref) <= 1e-4
+    finally:
+        mfs.mfs_destroy(h)
+
+
+@pytest.mark.parametrize("name,k", MG_CASES)
+def test_refined_solve(name, k):
+    h, H = _mg_problem(name, k)
+    try:
+        N = 4 * H.spaces[0].N
+        xt = inputs.uniform_vector(N, 80)
+        xt[H.fixed[0]] = 0.0
+        b = H.J[0] @ xt
+        x_ref, its_ref, _ = H.solve(b, rtol=1e-10)
+        for prec in (mfs.MFS_FP64, mfs.MFS_FP32):
+            x = torch.zeros(N, dtype=torch.float64, device="cuda")
+            info = mfs.mfs_solve(h, cuda(b), x, mfs.mfs_default_options(pressure_offset=0, rtol=1e-10,
+                                                                          precond_precision=prec))
+            assert info.status == 0 and info.rel_residual <= 1e-10
+            xs = host(x)
+            assert abs(xs[3 * H.spaces[0].N:].mean()) <= 1e-12 * np.abs(xs).max()
+            assert relerr(xs, x_ref) <= 1e-6
+            if prec == mfs.MFS_FP64:
+                assert abs(info.iterations - its_ref) <= 1
+            else:
+                assert info.iterations <= its_ref + 3
     finally:
         mfs.mfs_destroy(h)

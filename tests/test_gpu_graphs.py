@@ -9,7 +9,8 @@ the level of the solve tolerance (1e-10).  The bound on the difference is the
 run-to-run difference of two direct-launch solves (zero when the kernels sum
 in a fixed order) times 100, at least 1e-13.
 
-Also checked: the recording follows changes of the smoother intervals
+Also checked (Stokes, Navier-Stokes, hp, refined meshes): the recording
+follows changes of the smoother intervals
 (mfs_set_lambda) and of the linearisation (mfs_set_linearization), it is
 reused across solves with a new right-hand side, and it serves a solve
 enqueued on the null stream and on a side stream.
@@ -118,5 +119,22 @@ def test_hp_graph_solve_matches_direct():
         nv, np_ = mfs.mfs_n_dofs(h, 0)
         N = 3 * nv + np_
         _check_against_direct(h, _rhs(h, mfs.MFS_OP_STOKES, N, 31))
+    finally:
+        mfs.mfs_destroy(h)
+
+
+def test_refined_graph_solve_matches_direct():
+    mesh = inputs.refined_mesh(3, 0, levels=2, centre=[0.4, 0.5, 0.55], radius=0.3)
+    h = mfs.mfs_setup_refined(mesh, 2, 0.01, mfs.mfs_default_options(pressure_offset=0, mg_levels=1))
+    try:
+        nv, _ = mfs.mfs_n_dofs(h, 0)
+        pts = mfs.mfs_support_points(h, 2, nv, 3)
+        u0 = inputs.fourier_field(4)(pts).T.ravel()
+        mfs.mfs_set_linearization(h, cuda(u0), 1e-2, 1)
+        b = _rhs(h, mfs.MFS_OP_NS_JACOBIAN, 4 * nv, 41)
+        x1 = _check_against_direct(h, b, pressure_offset=0)
+        mfs.mfs_set_linearization(h, cuda(u0), 5e-3, 1)  # drop the recording
+        x2 = _check_against_direct(h, b, pressure_offset=0)
+        assert relerr(x2, x1) > 1e-6
     finally:
         mfs.mfs_destroy(h)
