@@ -240,6 +240,42 @@ def refined_ns_section(mfs, torch, inputs, args, dt, nu):
             out[f"Q{k}Q{k}"] = res
         finally:
             mfs.mfs_destroy(h)
+    # Newton-step solve on the refined mesh of the solve size: monolithic
+    # multigrid (global coarsening to the base mesh, then h and p)
+    n, k = args.ns_solve_n, 2
+    mesh = inputs.refined_mesh(n, seed=0, levels=2, radius=0.15)
+    solve = {"workload": f"Q2Q2 on {n}^3 base cells + 2 levels (radius 0.15, seed 0, {len(mesh['level'])} cells), "
+                         "J x = J y, rtol 1e-8, GC levels then the structured h and p levels, 5 Jacobi sweeps, "
+                         "omega 0.5"}
+    for name, prec in (("fp32_mg_fp64_fgmres", mfs.MFS_FP32), ("fp64", mfs.MFS_FP64)):
+        opts = mfs.mfs_default_options(pressure_offset=0, mg_levels=1, precond_precision=prec, rtol=1e-8,
+                                       maxit=200, graphs=args.graphs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = mfs.mfs_setup_refined(mesh, k, nu, opts)
+        try:
+            nu_, _ = mfs.mfs_n_dofs(h, 0)
+            N = 4 * nu_
+            u0 = F(mfs.mfs_support_points(h, k, nu_, 3)).T.ravel()
+            mfs.mfs_set_linearization(h, torch.from_numpy(u0).cuda(), dt, 1)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            y = torch.from_numpy(inputs.uniform_vector(N, 3)).cuda()
+            b = torch.empty_like(y)
+            mfs.mfs_vmult(h, mfs.MFS_OP_NS_JACOBIAN, mfs.MFS_FP64, 0, b, y)  # Dirichlet rows of b = y
+            times, info = [], None
+            for rep in range(2):
+                x = torch.zeros(N, dtype=torch.float64, device="cuda")
+                torch.cuda.synchronize()
+                t2 = time.perf_counter()
+                info = mfs.mfs_solve(h, b, x, opts)
+                times.append(time.perf_counter() - t2)
+            solve[name] = {"N": N, "levels": mfs.mfs_n_levels(h), "setup_s": t1 - t0, "solve_s": min(times),
+                           "iterations": info.iterations, "rel_residual": info.rel_residual, "status": info.status}
+        finally:
+            mfs.mfs_destroy(h)
+    solve["speedup_mixed_vs_fp64"] = solve["fp64"]["solve_s"] / solve["fp32_mg_fp64_fgmres"]["solve_s"]
+    out["solve"] = solve
     return out
 
 
