@@ -113,6 +113,47 @@ def test_refined_matches_assembled_matrix_and_kernel():
         mfs.mfs_destroy(h)
 
 
+def test_refined_jacobian_full_size_properties():
+    """128^3 base cells + 2 levels in the bench's sphere (3.97 M cells), Q1Q1,
+    in the launch configuration the bench times: the oracle cannot build this
+    space, so properties that hold at any size are checked.  The constant
+    pressure is in the kernel (the velocity unknowns vanish on the boundary);
+    Dirichlet rows are the identity; FP32 agrees with FP64 to 2e-5; a
+    second application repeats the first bit for bit (no atomics)."""
+    mesh = inputs.refined_mesh(128, seed=0, levels=2, radius=0.15)
+    nu, dt = 0.01, 1e-2
+    h = mfs.mfs_setup_refined(mesh, 1, nu)
+    try:
+        n_u, _ = mfs.mfs_n_dofs(h, 0)
+        assert n_u == 3969031
+        pts = mfs.mfs_support_points(h, 1, n_u, 3)
+        u0 = inputs.fourier_field(0)(pts).T.ravel()
+        mfs.mfs_set_linearization(h, cuda(u0), dt, 1)
+        N = 4 * n_u
+        e = torch.zeros(N, dtype=torch.float64, device="cuda")
+        e[3 * n_u:] = 1.0
+        y = torch.empty_like(e)
+        mfs.mfs_vmult(h, mfs.MFS_OP_NS_JACOBIAN, mfs.MFS_FP64, 0, y, e)
+        x = cuda(inputs.uniform_vector(N, 5))
+        z = torch.empty_like(x)
+        mfs.mfs_vmult(h, mfs.MFS_OP_NS_JACOBIAN, mfs.MFS_FP64, 0, z, x)
+        scale = float(z.abs().max())
+        assert float(y.abs().max()) <= 1e-12 * scale
+        bnd = np.any((pts == 0.0) | (pts == 1.0), axis=1)
+        zz, xx = host(z), host(x)
+        for c in range(3):
+            sl = slice(c * n_u, (c + 1) * n_u)
+            assert np.array_equal(zz[sl][bnd], xx[sl][bnd])
+        z2 = torch.empty_like(x)
+        mfs.mfs_vmult(h, mfs.MFS_OP_NS_JACOBIAN, mfs.MFS_FP64, 0, z2, x)
+        assert torch.equal(z, z2)
+        z32 = torch.empty(N, dtype=torch.float32, device="cuda")
+        mfs.mfs_vmult(h, mfs.MFS_OP_NS_JACOBIAN, mfs.MFS_FP32, 0, z32, x.float())
+        assert relerr(host(z32), zz) <= 2e-5
+    finally:
+        mfs.mfs_destroy(h)
+
+
 def test_refined_errors():
     mesh = inputs.refined_mesh(**MESHES["n3L2"])
     h, S = _problem(mesh, 1, 0.01)
