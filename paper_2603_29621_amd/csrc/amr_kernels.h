@@ -15,6 +15,7 @@ struct AmrEmbed {
   double w[2][3][3];
 };
 
+// E-vectors: velocity [cell][(k+1)^3][3], then pressure [cell][(k+1)^3].
 // fine E-vector (ncf cells, 4 components) from the coarse one (ncc cells):
 // each fine cell takes its parent's values through the embedding of its
 // octant (octant 8: the same cell, copied)

@@ -4,17 +4,19 @@
 // diagonal.
 //
 // E-vector layout of a level with nc cells and nq = (k+1)^3 nodes per cell:
-// component c < 3 of cell e at (e*3 + c)*nq, the fourth (pressure) at
-// 3*nc*nq + e*nq.
+// component c < 3 of node t of cell e at (e*nq + t)*3 + c, the fourth
+// (pressure) at 3*nc*nq + e*nq + t.
 #include "amr_kernels.h"
 
 namespace mfs {
 
 namespace {
 
+// first slot of component comp of cell e, and the stride between its nodes
 __device__ __forceinline__ int64_t ev_at(int64_t nc, int nq, int64_t e, int comp) {
-  return comp < 3 ? (e * 3 + comp) * nq : 3 * nc * nq + e * nq;
+  return comp < 3 ? e * nq * 3 + comp : 3 * nc * nq + e * nq;
 }
+__device__ __forceinline__ int ev_step(int comp) { return comp < 3 ? 3 : 1; }
 
 // weight of coarse node s for fine node t of a child in octant o (8: the
 // same cell, identity)
@@ -50,12 +52,13 @@ __global__ void k_embed(AmrEmbed E, int64_t ncf, int64_t ncc, const int *parent,
   const int64_t c = parent[f];
   const int o = oct[f];
   const T *src = evc + ev_at(ncc, nq, c, comp);
+  const int st = ev_step(comp);
   double acc = 0.0;
   for (int s = 0; s < nq; ++s) {
     const double w = embed_weight(E, o, t, s);
-    if (w != 0.0) acc += w * (double)src[s];
+    if (w != 0.0) acc += w * (double)src[s * st];
   }
-  evf[ev_at(ncf, nq, f, comp) + t] = (T)acc;
+  evf[ev_at(ncf, nq, f, comp) + t * st] = (T)acc;
 }
 
 // coarse[c][comp][s] = sum over the children f of c, sum_t W(oct[f])[t][s] fine[f][comp][t]
@@ -73,12 +76,13 @@ __global__ void k_embed_t(AmrEmbed E, int64_t ncf, int64_t ncc, const int64_t *c
     const int64_t f = child[e];
     const int o = oct[f];
     const T *src = evf + ev_at(ncf, nq, f, comp);
+    const int st = ev_step(comp);
     for (int t = 0; t < nq; ++t) {
       const double w = embed_weight(E, o, t, s);
-      if (w != 0.0) acc += w * (double)src[t];
+      if (w != 0.0) acc += w * (double)src[t * st];
     }
   }
-  evc[ev_at(ncc, nq, c, comp) + s] = (T)acc;
+  evc[ev_at(ncc, nq, c, comp) + s * ev_step(comp)] = (T)acc;
 }
 
 __global__ void k_colour_probe(const int *colour, int64_t N, int col, int comp, double *out) {

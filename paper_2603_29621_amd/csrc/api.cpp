@@ -218,7 +218,7 @@ struct HpData {
 // ------------------------------------------------------------- refined meshes
 // Equal-order Navier-Stokes on a locally refined mesh.  Level j of the
 // global coarsening sequence: the unknowns' maps to the cell-local values
-// (E-vectors [cell][3][(k+1)^3] velocity, then [cell][(k+1)^3] pressure), the
+// (E-vectors [cell][(k+1)^3][3] velocity, then [cell][(k+1)^3] pressure), the
 // per-cell corners, the linearisation data, the Jacobi diagonal, V-cycle
 // work vectors, and the cell and unknown relations to level j + 1.
 struct AmrLevel {
@@ -1807,8 +1807,10 @@ namespace {
 // device copy of an hp space's maps; ev_off: per-cell E-vector offset of the
 // cell's first component block, ncomp_stride: whether rows carry a component
 // stride ((k+1)^3 for the velocity)
+// interleave (with vector_comp): the three components of a cell-local node
+// are adjacent (slot 3 j + comp) instead of (k+1)^3 apart
 void hp_upload(HpData &H, const HpSpaceHost &V, bool constrained, const std::vector<int64_t> &ev_off, bool vector_comp,
-               HpDevSpace &d, hipStream_t s) {
+               HpDevSpace &d, hipStream_t s, bool interleave = false) {
   const int64_t ncells = (int64_t)V.deg.size();
   d.N = V.N;
   d.nrows = V.row_base[ncells];
@@ -1823,8 +1825,8 @@ void hp_upload(HpData &H, const HpSpaceHost &V, bool constrained, const std::vec
     const int k = V.deg[c], nb = (k + 1) * (k + 1) * (k + 1);
     for (int j = 0; j < nb; ++j) {
       const int64_t r = V.row_base[c] + j;
-      rev[r] = ev_off[c] + j;
-      rnb[r] = vector_comp ? nb : 0;
+      rev[r] = ev_off[c] + (vector_comp && interleave ? 3 * j : j);
+      rnb[r] = vector_comp ? (interleave ? 1 : nb) : 0;
       for (int64_t q = V.row_ptr[r]; q < V.row_ptr[r + 1]; ++q) {
         const int g = V.col[q];
         if (constrained && V.dirichlet[g]) continue;
@@ -1853,8 +1855,9 @@ void hp_upload(HpData &H, const HpSpaceHost &V, bool constrained, const std::vec
   std::vector<int> onb(V.N);
   for (int64_t g = 0; g < V.N; ++g) {
     const int c = V.owner_cell[g], k = V.deg[c], nb = (k + 1) * (k + 1) * (k + 1);
-    oev[g] = (constrained && V.dirichlet[g]) ? -1 : ev_off[c] + V.owner_local[g];
-    onb[g] = vector_comp ? nb : 0;
+    oev[g] = (constrained && V.dirichlet[g]) ? -1
+                                              : ev_off[c] + (vector_comp && interleave ? 3 : 1) * V.owner_local[g];
+    onb[g] = vector_comp ? (interleave ? 1 : nb) : 0;
   }
   d.row_ptr = H.upload(ptr, s);
   d.col = H.upload(col, s);
@@ -2162,7 +2165,7 @@ void amr_level_upload(AmrData &A, AmrLevel &V, bool op, bool work, hipStream_t s
     offp[c] = 3 * nc * NQ + c * NQ;
   }
   HpData &H = A.H;
-  hp_upload(H, S.V, true, offu, true, V.vd, s);
+  hp_upload(H, S.V, true, offu, true, V.vd, s, true);  // velocity slots [cell][node][3]
   hp_upload(H, S.V, false, offp, false, V.pd, s);
   for (int i = 0; i < 2; ++i) {
     V.ev64[i] = H.alloc<double>(4 * nc * NQ);

@@ -172,13 +172,13 @@ inline int64_t ns_qd_elems(const LevelGeom &g) {
 // (src, dst full equal-order vectors; the Dirichlet rows of dst untouched);
 // with ev (3D, ncells * 4 * (k+1)^3 elements) the cell results are written
 // there instead ([cell][3][(k+1)^3] velocity, then [cell][(k+1)^3] pressure)
-// and dst is not touched; with evin (3D, ev layout) the cell inputs come from
-// there and the cell corners from Xcell ([cell][8][3]) instead of src and the
-// node grid (refined meshes)
+// and dst is not touched; with evin (3D) the cell inputs come from there and
+// the cell corners from Xcell ([cell][8][3]) instead of src and the node grid
+// (refined meshes), and evin and ev hold the velocity as [cell][(k+1)^3][3]
 template <typename T>
 void launch_ns(const LevelGeom &g, const T *X, const T *tab, int what, T nu, T dt, int newton, const T *src, T *dst,
                T *qd, hipStream_t s, T *ev = nullptr, const T *evin = nullptr, const T *Xcell = nullptr);
-// ev[(cell*3 + comp)*nq + t] = ev[3*ncells*nq + cell*nq + t] (refined meshes:
+// ev[(cell*nq + t)*3 + comp] = ev[3*ncells*nq + cell*nq + t] (refined meshes:
 // a scalar gather moved into a velocity component slot)
 void launch_ev_to_velocity(double *ev, int64_t ncells, int nq, int comp, hipStream_t s);
 // coarse velocity = fine velocity at the shared nodes (fine index 2 * coarse

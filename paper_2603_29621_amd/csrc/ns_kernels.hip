@@ -39,10 +39,11 @@ struct Args {
   T nu, alpha, dt;
   int newton;
   T *ev;  // cell-local outputs instead of atomics when non-null (3D)
-  // cell-local inputs (3D): velocity [cell][3][(k+1)^3], then pressure
-  // [cell][(k+1)^3] (ev layout; the linearisation reads the velocity part),
-  // and per-cell corner coordinates [cell][8][3] (x fastest) instead of the
-  // structured vertex grid; with evin, src, dst and the node grid are unused
+  // cell-local inputs (3D): velocity [cell][(k+1)^3][3], then pressure
+  // [cell][(k+1)^3] (the linearisation reads the velocity part), and per-cell
+  // corner coordinates [cell][8][3] (x fastest) instead of the structured
+  // vertex grid; with evin, src, dst and the node grid are unused and ev
+  // takes the same interleaved velocity layout
   const T *evin;
   const T *Xcell;
 };
@@ -279,7 +280,7 @@ __global__ void __launch_bounds__((Shape<DIM, K>::BLOCK)) ns_linearize_kernel(Ar
   T u[3] = {}, U[3][3] = {}, lap[3] = {};
   for (int comp = 0; comp < DIM; ++comp) {
     T v0 = T(0);
-    if (c.valid) v0 = a.evin ? a.evin[((int64_t)cell * 3 + comp) * NQ + c.t] : a.src[comp * a.Nv + nd];
+    if (c.valid) v0 = a.evin ? a.evin[((int64_t)cell * NQ + c.t) * 3 + comp] : a.src[comp * a.Nv + nd];
     if (c.active) c.b0[c.t] = v0;
     csync<Sh::WAVE>();
     T val, g[3], h[6];
@@ -328,7 +329,7 @@ __global__ void __launch_bounds__((Shape<DIM, K>::BLOCK)) ns_jacobian_kernel(Arg
   T sv[4] = {0, 0, 0, 0};
   T u0[3] = {}, U[3][3] = {}, R0[3] = {}, dl = 0;
   if (c.valid && a.evin) {
-    for (int comp = 0; comp < DIM; ++comp) sv[comp] = a.evin[((int64_t)cell * 3 + comp) * NQ + c.t];
+    for (int comp = 0; comp < DIM; ++comp) sv[comp] = a.evin[((int64_t)cell * NQ + c.t) * 3 + comp];
     sv[DIM] = a.evin[(int64_t)a.ncells * 3 * NQ + (int64_t)cell * NQ + c.t];
   } else if (c.valid) {
     for (int comp = 0; comp < DIM; ++comp) sv[comp] = dir ? T(0) : a.src[comp * a.Nv + nd];
@@ -401,7 +402,8 @@ __global__ void __launch_bounds__((Shape<DIM, K>::BLOCK)) ns_jacobian_kernel(Arg
     }
     const T r = c.integrate(JxW * val_u[comp], f);
     if (a.ev) {
-      if (c.valid) a.ev[((int64_t)cell * 3 + comp) * NQ + c.t] = r;
+      if (c.valid)
+        a.ev[a.evin ? ((int64_t)cell * NQ + c.t) * 3 + comp : ((int64_t)cell * 3 + comp) * NQ + c.t] = r;
     } else if (c.valid && !dir) {
       atomicAdd(a.dst + comp * a.Nv + nd, r);
     }
@@ -510,12 +512,11 @@ __global__ void k_color_extract(LevelGeom g, int q, int color, int comp, const d
   if (node_color(g, q, i) == color) diag[comp * g.Nv + i] = y[comp * g.Nv + i];
 }
 
-// ev[(cell*3 + comp)*nq + t] = ev[3*ncells*nq + cell*nq + t]
+// ev[(cell*nq + t)*3 + comp] = ev[3*ncells*nq + cell*nq + t]
 __global__ void k_ev_to_velocity(double *ev, int64_t ncells, int nq, int comp) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= ncells * nq) return;
-  const int64_t cell = i / nq, t = i % nq;
-  ev[(cell * 3 + comp) * nq + t] = ev[3 * ncells * nq + i];
+  ev[i * 3 + comp] = ev[3 * ncells * nq + i];
 }
 
 template <typename T>
