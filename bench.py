@@ -46,6 +46,11 @@ def algorithmic_bytes(dim, n, k, word):
     return N, 2 * N * word + verts
 
 
+def progress(msg):
+    """One line per finished step on stderr (stdout carries only the JSON line)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def time_vmult(mfs, torch, h, N, prec, steps, warmup, rotate_bytes=600e6, op=None):
     op = mfs.MFS_OP_STOKES if op is None else op
     dt = torch.float64 if prec == mfs.MFS_FP64 else torch.float32
@@ -238,6 +243,7 @@ def refined_ns_section(mfs, torch, inputs, args, dt, nu):
                 avg = float(per.mean())
                 res[name] = {"dofs_per_s": N / avg, "avg_launch_us": avg * 1e6}
             out[f"Q{k}Q{k}"] = res
+            progress(f"refined Q{k}Q{k} Jacobian: set-up {setup:.1f} s, {res['f64']['avg_launch_us']:.0f} us FP64")
         finally:
             mfs.mfs_destroy(h)
     # Newton-step solve on the refined mesh of the solve size: monolithic
@@ -272,6 +278,7 @@ def refined_ns_section(mfs, torch, inputs, args, dt, nu):
                 times.append(time.perf_counter() - t2)
             solve[name] = {"N": N, "levels": mfs.mfs_n_levels(h), "setup_s": t1 - t0, "solve_s": min(times),
                            "iterations": info.iterations, "rel_residual": info.rel_residual, "status": info.status}
+            progress(f"refined solve {name}: set-up {t1 - t0:.1f} s, solve {min(times):.3f} s")
         finally:
             mfs.mfs_destroy(h)
     solve["speedup_mixed_vs_fp64"] = solve["fp64"]["solve_s"] / solve["fp32_mg_fp64_fgmres"]["solve_s"]
@@ -409,6 +416,7 @@ def main():
 
     main_prec = mfs.MFS_FP64 if args.prec == "f64" else mfs.MFS_FP32
     main_run = run(k, main_prec, args.steps, args.warmup)
+    progress(f"headline vmult: {main_run['avg_launch_s'] * 1e6:.1f} us")
     sweep = {}
     if not args.no_sweep:
         for kk in (2, 3, 4):
@@ -419,6 +427,7 @@ def main():
                     r = run(kk, prec, max(10, args.steps // 2), 3)
                 sweep[f"Q{kk}Q{kk-1}_{name}"] = {"dofs_per_s": r["dofs_per_s"], "frac_hbm": r["frac"],
                                                   "avg_launch_us": r["avg_launch_s"] * 1e6, "N": r["N"]}
+        progress("sweep done")
     line = {
         "metric": "Stokes vmult DoFs/s (% HBM roofline)",
         "value": main_run["dofs_per_s"],
@@ -446,13 +455,18 @@ def main():
                                 "frac": fl / FP64_PEAK, "flop_per_dof": FLOP_PER_DOF[k]}
     if not args.no_ns:
         line["navier_stokes"] = ns_section(mfs, torch, inputs, args)
+        progress("navier_stokes done")
     if not args.no_hp:
         line["hp"] = hp_section(mfs, torch, inputs, args)
+        progress("hp done")
     if not args.no_solve:
         line["solve"] = solve_section(mfs, torch, inputs, args)
+        progress("solve done")
         line["serving"] = serving_section(args)
+        progress("serving done")
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline_oracle()
+        progress("cpu baseline done")
     print(json.dumps(line))
 
 
