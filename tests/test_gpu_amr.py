@@ -38,6 +38,10 @@ MESHES = {
     "n3L2": dict(n=3, seed=0, levels=2, centre=[0.4, 0.5, 0.55], radius=0.3),
     "n4L2seed": dict(n=4, seed=1, levels=2),
     "n6L1": dict(n=6, seed=2, levels=1, radius=0.3),
+    # degenerate cases: one base cell refined twice; a mesh refined everywhere
+    # (no hanging nodes, the structured mesh of twice the resolution)
+    "n1L2": dict(n=1, seed=0, levels=2, centre=[0.3, 0.4, 0.6], radius=0.45),
+    "n2all": dict(n=2, seed=0, levels=1, centre=[0.5, 0.5, 0.5], radius=10.0),
 }
 
 
@@ -154,6 +158,22 @@ def test_refined_jacobian_full_size_properties():
         mfs.mfs_destroy(h)
 
 
+def test_refined_multigrid_needs_refinement():
+    """Multigrid on a mesh without refined cells is rejected (the structured
+    set-up serves it); operators alone are fine."""
+    mesh = {"n": 2, "levels": 0, "level": np.zeros(8, dtype=np.int32),
+            "idx": np.array([[x, y, z] for z in range(2) for y in range(2) for x in range(2)], dtype=np.int32)}
+    with pytest.raises(mfs.MfsError) as e:
+        mfs.mfs_setup_refined(mesh, 2, 0.01, mfs.mfs_default_options(pressure_offset=0, mg_levels=1))
+    assert e.value.code == mfs.MFS_EINVAL
+    h = mfs.mfs_setup_refined(mesh, 2, 0.01)
+    try:
+        S = amr.AmrSpace(mesh, 2)
+        assert mfs.mfs_n_dofs(h, 0) == (S.N, S.N) == (125, 125)
+    finally:
+        mfs.mfs_destroy(h)
+
+
 def test_refined_errors():
     mesh = inputs.refined_mesh(**MESHES["n3L2"])
     h, S = _problem(mesh, 1, 0.01)
@@ -184,7 +204,7 @@ def test_refined_errors():
 # ------------------------------------------------------------------ multigrid
 from oracle import amr_mg  # noqa: E402
 
-MG_CASES = [("n3L2", 1), ("n3L2", 2), ("n4L2seed", 2)]
+MG_CASES = [("n3L2", 1), ("n3L2", 2), ("n4L2seed", 2), ("n6L1", 2), ("n1L2", 2), ("n2all", 1)]
 
 
 def _mg_problem(name, k, nu=0.01, dt=1e-2, newton=1):
