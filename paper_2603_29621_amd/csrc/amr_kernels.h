@@ -15,7 +15,42 @@ struct AmrEmbed {
   double w[2][3][3];
 };
 
-// E-vectors: velocity [cell][(k+1)^3][3], then pressure [cell][(k+1)^3].
+// E-vectors of a level: [cell][(k+1)^3][4], the three velocity components and
+// the pressure of a cell-local node side by side (row r = cell*(k+1)^3 + node
+// holds slots 4r .. 4r+3).
+
+// Maps between the unknowns (4 blocks of N) and the E-vector rows.
+struct AmrMaps {
+  int64_t N = 0, nrows = 0;
+  const int64_t *row_ptr = nullptr;  // CSR over rows: unknown, weight
+  const int *col = nullptr;
+  const double *val = nullptr;
+  const int64_t *tptr = nullptr;  // transposed, per unknown: row, weight
+  const int *trow = nullptr;
+  const double *tval = nullptr;
+  const uint8_t *dir = nullptr;   // velocity Dirichlet unknowns
+  const int *owner = nullptr;     // a row holding the unknown's own node
+  int64_t nheavy = 0;             // unknowns with more than AMR_LIGHT rows
+  const int64_t *heavy = nullptr;
+};
+constexpr int AMR_LIGHT = 16;
+
+// ev rows = C x: components 0 .. ncomp-1 of the 4 blocks of x; with mask the
+// velocity values of Dirichlet unknowns are taken as 0 (the constrained
+// operator ignores them)
+template <typename T>
+void amr_gather(const AmrMaps &M, int ncomp, bool mask, const T *x, T *ev, hipStream_t s);
+// dst = C^T ev (all 4 components); velocity rows of Dirichlet unknowns are
+// src (or 0 without src) instead
+template <typename T>
+void amr_scatter(const AmrMaps &M, const T *ev, const T *src, T *dst, hipStream_t s);
+// x (+)= the value at each unknown's owner row (velocity of Dirichlet
+// unknowns skipped); transpose: ev owner rows = x (ev cleared beforehand)
+template <typename T>
+void amr_inject(const AmrMaps &M, const T *ev, T *x, bool add, hipStream_t s);
+template <typename T>
+void amr_inject_t(const AmrMaps &M, const T *x, T *ev, hipStream_t s);
+
 // fine E-vector (ncf cells, 4 components) from the coarse one (ncc cells):
 // each fine cell takes its parent's values through the embedding of its
 // octant (octant 8: the same cell, copied)

@@ -4,8 +4,9 @@
 // diagonal.
 //
 // E-vector layout of a level with nc cells and nq = (k+1)^3 nodes per cell:
-// component c < 3 of node t of cell e at (e*nq + t)*3 + c, the fourth
-// (pressure) at 3*nc*nq + e*nq + t.
+// component c of node t of cell e at (e*nq + t)*4 + c.
+#include <algorithm>
+
 #include "amr_kernels.h"
 
 namespace mfs {
@@ -14,9 +15,105 @@ namespace {
 
 // first slot of component comp of cell e, and the stride between its nodes
 __device__ __forceinline__ int64_t ev_at(int64_t nc, int nq, int64_t e, int comp) {
-  return comp < 3 ? e * nq * 3 + comp : 3 * nc * nq + e * nq;
+  (void)nc;
+  return e * nq * 4 + comp;
 }
-__device__ __forceinline__ int ev_step(int comp) { return comp < 3 ? 3 : 1; }
+__device__ __forceinline__ int ev_step(int comp) {
+  (void)comp;
+  return 4;
+}
+
+constexpr int AB = 256;
+unsigned agrid(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + AB - 1) / AB, 65535 * 8)); }
+
+template <typename T, int NC, bool MASK>
+__global__ void k_amr_gather(AmrMaps M, const T *x, T *ev) {
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < M.nrows; r += (int64_t)gridDim.x * blockDim.x) {
+    double s[NC] = {};
+    for (int64_t j = M.row_ptr[r]; j < M.row_ptr[r + 1]; ++j) {
+      const int64_t c = M.col[j];
+      const double w = M.val[j];
+      const bool d = MASK && M.dir[c];
+#pragma unroll
+      for (int comp = 0; comp < NC; ++comp)
+        if (!(d && comp < 3)) s[comp] += w * (double)x[comp * M.N + c];
+    }
+#pragma unroll
+    for (int comp = 0; comp < NC; ++comp) ev[4 * r + comp] = (T)s[comp];
+  }
+}
+
+// one thread per unknown with a list of at most AMR_LIGHT rows, four
+// components read together from each row
+template <typename T>
+__global__ void k_amr_scatter(AmrMaps M, const T *ev, const T *src, T *dst) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < M.N; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = M.tptr[i], e = M.tptr[i + 1];
+    if (e - b > AMR_LIGHT) continue;  // summed by k_amr_scatter_heavy
+    double s[4] = {0, 0, 0, 0};
+    for (int64_t j = b; j < e; ++j) {
+      const double w = M.tval[j];
+      const T *v = ev + 4 * (int64_t)M.trow[j];
+#pragma unroll
+      for (int comp = 0; comp < 4; ++comp) s[comp] += w * (double)v[comp];
+    }
+    const bool d = M.dir[i];
+#pragma unroll
+    for (int comp = 0; comp < 4; ++comp)
+      dst[comp * M.N + i] = (d && comp < 3) ? (src ? src[comp * M.N + i] : T(0)) : (T)s[comp];
+  }
+}
+
+// one wave per long list: strided partial sums, then a butterfly (the same
+// order on every call)
+template <typename T>
+__global__ void __launch_bounds__(AB) k_amr_scatter_heavy(AmrMaps M, const T *ev, const T *src, T *dst) {
+  const int lane = threadIdx.x & 63;
+  const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t h = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6; h < M.nheavy; h += waves) {
+    const int64_t i = M.heavy[h];
+    double s[4] = {0, 0, 0, 0};
+    for (int64_t j = M.tptr[i] + lane; j < M.tptr[i + 1]; j += 64) {
+      const double w = M.tval[j];
+      const T *v = ev + 4 * (int64_t)M.trow[j];
+#pragma unroll
+      for (int comp = 0; comp < 4; ++comp) s[comp] += w * (double)v[comp];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+      for (int comp = 0; comp < 4; ++comp) s[comp] += __shfl_xor(s[comp], off, 64);
+    if (lane == 0) {
+      const bool d = M.dir[i];
+#pragma unroll
+      for (int comp = 0; comp < 4; ++comp)
+        dst[comp * M.N + i] = (d && comp < 3) ? (src ? src[comp * M.N + i] : T(0)) : (T)s[comp];
+    }
+  }
+}
+
+template <typename T>
+__global__ void k_amr_inject(AmrMaps M, const T *ev, T *x, int add) {
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < M.N; g += (int64_t)gridDim.x * blockDim.x) {
+    const T *v = ev + 4 * (int64_t)M.owner[g];
+    const int c0 = M.dir[g] ? 3 : 0;
+    for (int comp = c0; comp < 4; ++comp) {
+      if (add)
+        x[comp * M.N + g] += v[comp];
+      else
+        x[comp * M.N + g] = v[comp];
+    }
+  }
+}
+
+template <typename T>
+__global__ void k_amr_inject_t(AmrMaps M, const T *x, T *ev) {
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < M.N; g += (int64_t)gridDim.x * blockDim.x) {
+    T *v = ev + 4 * (int64_t)M.owner[g];
+    const int c0 = M.dir[g] ? 3 : 0;
+    for (int comp = c0; comp < 4; ++comp) v[comp] = x[comp * M.N + g];
+  }
+}
 
 // weight of coarse node s for fine node t of a child in octant o (8: the
 // same cell, identity)
@@ -103,6 +200,40 @@ unsigned nblocks(int64_t n) { return (unsigned)((n + 255) / 256); }
 }  // namespace
 
 template <typename T>
+void amr_gather(const AmrMaps &M, int ncomp, bool mask, const T *x, T *ev, hipStream_t s) {
+  const dim3 g(agrid(M.nrows)), b(AB);
+  if (ncomp == 4 && mask)
+    hipLaunchKernelGGL((k_amr_gather<T, 4, true>), g, b, 0, s, M, x, ev);
+  else if (ncomp == 4)
+    hipLaunchKernelGGL((k_amr_gather<T, 4, false>), g, b, 0, s, M, x, ev);
+  else if (ncomp == 3 && !mask)
+    hipLaunchKernelGGL((k_amr_gather<T, 3, false>), g, b, 0, s, M, x, ev);
+  else
+    MFS_REQUIRE(false, MFS_EINVAL, "amr_gather: unsupported component count");
+  MFS_HIP(hipGetLastError());
+}
+
+template <typename T>
+void amr_scatter(const AmrMaps &M, const T *ev, const T *src, T *dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_amr_scatter<T>, dim3(agrid(M.N)), dim3(AB), 0, s, M, ev, src, dst);
+  if (M.nheavy > 0)
+    hipLaunchKernelGGL(k_amr_scatter_heavy<T>, dim3(agrid(M.nheavy * 64)), dim3(AB), 0, s, M, ev, src, dst);
+  MFS_HIP(hipGetLastError());
+}
+
+template <typename T>
+void amr_inject(const AmrMaps &M, const T *ev, T *x, bool add, hipStream_t s) {
+  hipLaunchKernelGGL(k_amr_inject<T>, dim3(agrid(M.N)), dim3(AB), 0, s, M, ev, x, add ? 1 : 0);
+  MFS_HIP(hipGetLastError());
+}
+
+template <typename T>
+void amr_inject_t(const AmrMaps &M, const T *x, T *ev, hipStream_t s) {
+  hipLaunchKernelGGL(k_amr_inject_t<T>, dim3(agrid(M.N)), dim3(AB), 0, s, M, x, ev);
+  MFS_HIP(hipGetLastError());
+}
+
+template <typename T>
 void amr_embed(const AmrEmbed &E, int64_t ncf, int64_t ncc, const int *parent, const uint8_t *oct, const T *evc,
                T *evf, hipStream_t s) {
   const int nq = (E.k + 1) * (E.k + 1) * (E.k + 1);
@@ -128,6 +259,15 @@ void amr_colour_take(const int *colour, int64_t N, int col, int comp, const doub
   hipLaunchKernelGGL(k_colour_take, dim3(nblocks(N)), dim3(256), 0, s, colour, N, col, comp, y, diag);
   MFS_HIP(hipGetLastError());
 }
+
+#define AMR_INST(T)                                                                                    \
+  template void amr_gather<T>(const AmrMaps &, int, bool, const T *, T *, hipStream_t);                 \
+  template void amr_scatter<T>(const AmrMaps &, const T *, const T *, T *, hipStream_t);                \
+  template void amr_inject<T>(const AmrMaps &, const T *, T *, bool, hipStream_t);                      \
+  template void amr_inject_t<T>(const AmrMaps &, const T *, T *, hipStream_t);
+AMR_INST(double)
+AMR_INST(float)
+#undef AMR_INST
 
 template void amr_embed<double>(const AmrEmbed &, int64_t, int64_t, const int *, const uint8_t *, const double *,
                                 double *, hipStream_t);

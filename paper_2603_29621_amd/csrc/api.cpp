@@ -218,15 +218,15 @@ struct HpData {
 // ------------------------------------------------------------- refined meshes
 // Equal-order Navier-Stokes on a locally refined mesh.  Level j of the
 // global coarsening sequence: the unknowns' maps to the cell-local values
-// (E-vectors [cell][(k+1)^3][3] velocity, then [cell][(k+1)^3] pressure), the
+// (E-vectors [cell][(k+1)^3][4]: velocity components and pressure of a node
+// side by side), the
 // per-cell corners, the linearisation data, the Jacobi diagonal, V-cycle
 // work vectors, and the cell and unknown relations to level j + 1.
 struct AmrLevel {
   AmrSpaceHost S;  // host space (row maps released after the upload)
   LevelGeom g{};   // degree and cell count for the cell kernels
   int64_t N = 0, NQ = 0;
-  HpDevSpace vd;   // velocity: Dirichlet columns dropped, 3 components
-  HpDevSpace pd;   // scalar, unconstrained (pressure; components of u0)
+  AmrMaps M;       // unknowns <-> E-vector rows (constraints, Dirichlet mask, owners)
   double *X64 = nullptr;
   float *X32 = nullptr;
   double *qd64 = nullptr;
@@ -2141,6 +2141,46 @@ const T *amr_inv(const AmrLevel &V) {
 // belongs to the structured hierarchy)
 int amr_nop(const AmrData &A) { return A.mg ? (int)A.lev.size() - 1 : 1; }
 
+// device maps of a level: rows are cell-major ((k+1)^3 per cell), so row r's
+// E-vector slots are 4r .. 4r+3 and the lists need no slot offsets
+void amr_maps_upload(HpData &H, const AmrSpaceHost &S, AmrMaps &M, hipStream_t s) {
+  const HpSpaceHost &V = S.V;
+  const int64_t nrows = V.row_base[S.ncells], N = S.N;
+  M.N = N;
+  M.nrows = nrows;
+  std::vector<int64_t> tptr((size_t)N + 1, 0);
+  for (int64_t q = 0; q < V.row_ptr[nrows]; ++q) tptr[V.col[q] + 1] += 1;
+  for (int64_t g = 0; g < N; ++g) tptr[g + 1] += tptr[g];
+  std::vector<int> trow((size_t)tptr[N]);
+  std::vector<double> tval((size_t)tptr[N]);
+  {
+    std::vector<int64_t> fill(tptr.begin(), tptr.end() - 1);
+    for (int64_t r = 0; r < nrows; ++r)
+      for (int64_t q = V.row_ptr[r]; q < V.row_ptr[r + 1]; ++q) {
+        const int64_t o = fill[V.col[q]]++;
+        trow[o] = (int)r;
+        tval[o] = V.val[q];
+      }
+  }
+  std::vector<int64_t> heavy;
+  for (int64_t g = 0; g < N; ++g)
+    if (tptr[g + 1] - tptr[g] > AMR_LIGHT) heavy.push_back(g);
+  const int64_t nb = V.row_base[1] - V.row_base[0];
+  std::vector<int> owner((size_t)N);
+  for (int64_t g = 0; g < N; ++g) owner[g] = (int)(V.owner_cell[g] * nb + V.owner_local[g]);
+  M.row_ptr = H.upload(V.row_ptr, s);
+  M.col = H.upload(V.col, s);
+  M.val = H.upload(V.val, s);
+  M.tptr = H.upload(tptr, s);
+  M.trow = H.upload(trow, s);
+  M.tval = H.upload(tval, s);
+  M.dir = H.upload(V.dirichlet, s);
+  M.owner = H.upload(owner, s);
+  M.nheavy = (int64_t)heavy.size();
+  M.heavy = heavy.empty() ? nullptr : H.upload(heavy, s);
+  MFS_HIP(hipStreamSynchronize(s));  // the host vectors go out of scope
+}
+
 // device data of a level; `op`: the level applies its own Jacobian
 void amr_level_upload(AmrData &A, AmrLevel &V, bool op, bool work, hipStream_t s) {
   AmrSpaceHost &S = V.S;
@@ -2159,14 +2199,8 @@ void amr_level_upload(AmrData &A, AmrLevel &V, bool op, bool work, hipStream_t s
   g.np[0] = g.np[1] = k + 1;
   g.np[2] = g.nv[2];
   g.Nv = g.Np = (int64_t)g.nv[0] * g.nv[1] * g.nv[2];
-  std::vector<int64_t> offu(nc), offp(nc);
-  for (int64_t c = 0; c < nc; ++c) {
-    offu[c] = c * 3 * NQ;
-    offp[c] = 3 * nc * NQ + c * NQ;
-  }
   HpData &H = A.H;
-  hp_upload(H, S.V, true, offu, true, V.vd, s, true);  // velocity slots [cell][node][3]
-  hp_upload(H, S.V, false, offp, false, V.pd, s);
+  amr_maps_upload(H, S, V.M, s);
   for (int i = 0; i < 2; ++i) {
     V.ev64[i] = H.alloc<double>(4 * nc * NQ);
     V.ev32[i] = H.alloc<float>(4 * nc * NQ);
@@ -2266,13 +2300,10 @@ void amr_apply_ns(mfs_problem &P, int j, T *dst, const T *src, hipStream_t s) {
   MFS_REQUIRE(A.ready, MFS_EINVAL, "mfs_set_linearization has not been called");
   AmrLevel &V = A.lev[j];
   T *evi = amr_ev<T>(V, 0), *evo = amr_ev<T>(V, 1);
-  const int64_t N = V.N;
-  hp_gather_space<T>(V.vd, 3, src, evi, s);
-  hp_gather_space<T>(V.pd, 1, src + 3 * N, evi, s);
+  amr_gather<T>(V.M, 4, true, src, evi, s);
   launch_ns<T>(V.g, nullptr, amr_tab<T>(A), 1, (T)P.nu, (T)A.dt, A.newton, nullptr, nullptr, amr_qd<T>(V), s, evo,
                evi, amr_X<T>(V));
-  hp_scatter_space<T>(V.vd, 3, true, evo, src, dst, s);
-  hp_scatter_space<T>(V.pd, 1, false, evo, nullptr, dst + 3 * N, s);
+  amr_scatter<T>(V.M, evo, src, dst, s);
 }
 
 // prolongation from level j+1 to level j (added to xf): gather the coarse
@@ -2284,11 +2315,9 @@ void amr_prolongate_add(mfs_problem &P, int j, T *xf, const T *xc, hipStream_t s
   AmrData &A = *P.amr;
   AmrLevel &F = A.lev[j], &C = A.lev[j + 1];
   T *evc = amr_ev<T>(C, 0), *evf = amr_ev<T>(F, 1);
-  hp_gather_space<T>(C.vd, 3, xc, evc, s);
-  hp_gather_space<T>(C.pd, 1, xc + 3 * C.N, evc, s);
+  amr_gather<T>(C.M, 4, true, xc, evc, s);
   amr_embed<T>(A.E, F.S.ncells, C.S.ncells, F.parent, F.octant, evc, evf, s);
-  hp_inject<T>(F.N, 3, F.vd.owner_ev, F.vd.owner_nb, evf, xf, true, s);
-  hp_inject<T>(F.N, 1, F.pd.owner_ev, F.pd.owner_nb, evf, xf + 3 * F.N, true, s);
+  amr_inject<T>(F.M, evf, xf, true, s);
 }
 
 // restriction (the transpose) from level j to level j+1
@@ -2298,11 +2327,9 @@ void amr_restrict(mfs_problem &P, int j, T *bc, const T *rf, hipStream_t s) {
   AmrLevel &F = A.lev[j], &C = A.lev[j + 1];
   T *evc = amr_ev<T>(C, 0), *evf = amr_ev<T>(F, 1);
   vec_fill<T>(evf, T(0), 4 * F.S.ncells * F.NQ, s);
-  hp_inject_t<T>(F.N, 3, F.vd.owner_ev, F.vd.owner_nb, rf, evf, s);
-  hp_inject_t<T>(F.N, 1, F.pd.owner_ev, F.pd.owner_nb, rf + 3 * F.N, evf, s);
+  amr_inject_t<T>(F.M, rf, evf, s);
   amr_embed_t<T>(A.E, F.S.ncells, C.S.ncells, F.cptr, F.child, F.octant, evf, evc, s);
-  hp_scatter_space<T>(C.vd, 3, true, evc, nullptr, bc, s);
-  hp_scatter_space<T>(C.pd, 1, false, evc, nullptr, bc + 3 * C.N, s);
+  amr_scatter<T>(C.M, evc, nullptr, bc, s);
 }
 
 template <typename T>
@@ -2326,7 +2353,7 @@ void amr_vcycle(mfs_problem &P, int j, T *x, const T *b, hipStream_t s) {
     return;
   }
   AmrLevel &V = A.lev[j], &C = A.lev[j + 1];
-  mask_fill_dirichlet<T>(V.vd.dir, V.N, 3, x, b, s);  // x = b on Dirichlet rows, 0 elsewhere
+  mask_fill_dirichlet<T>(V.M.dir, V.N, 3, x, b, s);  // x = b on Dirichlet rows, 0 elsewhere
   vec_fill<T>(x + 3 * V.N, T(0), V.N, s);
   amr_relax<T>(P, j, x, b, s);
   T *r = amr_w<T>(V, 2);
@@ -2370,10 +2397,7 @@ void amr_set_linearization(mfs_problem &P, const double *u0, double dt, int newt
   for (int j = 0; j < nop; ++j) {
     AmrLevel &V = A.lev[j];
     double *ev = V.ev64[0];
-    for (int c = 0; c < 3; ++c) {
-      hp_gather_space<double>(V.pd, 1, V.u0 + c * V.N, ev, s);
-      launch_ev_to_velocity(ev, V.g.ncells, (int)V.NQ, c, s);
-    }
+    amr_gather<double>(V.M, 3, false, V.u0, ev, s);  // u0 keeps its boundary values
     launch_ns<double>(V.g, nullptr, A.tab64, 0, P.nu, dt, A.newton, nullptr, nullptr, V.qd64, s, nullptr, ev, V.X64);
     vec_cast<float, double>(V.qd32, V.qd64, V.g.ncells * V.NQ * NS_QD, s);
   }
@@ -2589,7 +2613,7 @@ void kr_begin(mfs_problem &P, const double *b, double *x, const mfs_options &o, 
   K.t0 = std::chrono::steady_clock::now();
   // ||b|| first (state 1 reads it as bnorm), then the residual of x0
   if (P.amr)  // x0: lifting of b's Dirichlet rows
-    mask_fill_dirichlet<double>(P.amr->lev[0].vd.dir, P.amr->lev[0].N, 3, x, b, s);
+    mask_fill_dirichlet<double>(P.amr->lev[0].M.dir, P.amr->lev[0].N, 3, x, b, s);
   else if (P.hp)
     mask_fill_dirichlet<double>(P.hp->lev[0].vd.dir, P.hp->lev[0].vd.N, 3, x, b, s);
   else

@@ -174,13 +174,11 @@ inline int64_t ns_qd_elems(const LevelGeom &g) {
 // there instead ([cell][3][(k+1)^3] velocity, then [cell][(k+1)^3] pressure)
 // and dst is not touched; with evin (3D) the cell inputs come from there and
 // the cell corners from Xcell ([cell][8][3]) instead of src and the node grid
-// (refined meshes), and evin and ev hold the velocity as [cell][(k+1)^3][3]
+// (refined meshes), and evin and ev hold [cell][(k+1)^3][4] (velocity
+// components and pressure of a node side by side)
 template <typename T>
 void launch_ns(const LevelGeom &g, const T *X, const T *tab, int what, T nu, T dt, int newton, const T *src, T *dst,
                T *qd, hipStream_t s, T *ev = nullptr, const T *evin = nullptr, const T *Xcell = nullptr);
-// ev[(cell*nq + t)*3 + comp] = ev[3*ncells*nq + cell*nq + t] (refined meshes:
-// a scalar gather moved into a velocity component slot)
-void launch_ev_to_velocity(double *ev, int64_t ncells, int nq, int comp, hipStream_t s);
 // coarse velocity = fine velocity at the shared nodes (fine index 2 * coarse
 // index per direction; h-coarsening at k <= 2 and p-coarsening 2 -> 1)
 void launch_ns_inject(const LevelGeom &fine, const LevelGeom &coarse, const double *u_fine, double *u_coarse,

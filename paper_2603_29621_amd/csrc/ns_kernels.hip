@@ -39,11 +39,11 @@ struct Args {
   T nu, alpha, dt;
   int newton;
   T *ev;  // cell-local outputs instead of atomics when non-null (3D)
-  // cell-local inputs (3D): velocity [cell][(k+1)^3][3], then pressure
-  // [cell][(k+1)^3] (the linearisation reads the velocity part), and per-cell
-  // corner coordinates [cell][8][3] (x fastest) instead of the structured
-  // vertex grid; with evin, src, dst and the node grid are unused and ev
-  // takes the same interleaved velocity layout
+  // cell-local inputs (3D): [cell][(k+1)^3][4], the three velocity
+  // components and the pressure of a node side by side (the linearisation
+  // reads the velocity), and per-cell corner coordinates [cell][8][3]
+  // (x fastest) instead of the structured vertex grid; with evin, src, dst
+  // and the node grid are unused and ev takes the same layout
   const T *evin;
   const T *Xcell;
 };
@@ -280,7 +280,7 @@ __global__ void __launch_bounds__((Shape<DIM, K>::BLOCK)) ns_linearize_kernel(Ar
   T u[3] = {}, U[3][3] = {}, lap[3] = {};
   for (int comp = 0; comp < DIM; ++comp) {
     T v0 = T(0);
-    if (c.valid) v0 = a.evin ? a.evin[((int64_t)cell * NQ + c.t) * 3 + comp] : a.src[comp * a.Nv + nd];
+    if (c.valid) v0 = a.evin ? a.evin[((int64_t)cell * NQ + c.t) * 4 + comp] : a.src[comp * a.Nv + nd];
     if (c.active) c.b0[c.t] = v0;
     csync<Sh::WAVE>();
     T val, g[3], h[6];
@@ -329,8 +329,7 @@ __global__ void __launch_bounds__((Shape<DIM, K>::BLOCK)) ns_jacobian_kernel(Arg
   T sv[4] = {0, 0, 0, 0};
   T u0[3] = {}, U[3][3] = {}, R0[3] = {}, dl = 0;
   if (c.valid && a.evin) {
-    for (int comp = 0; comp < DIM; ++comp) sv[comp] = a.evin[((int64_t)cell * NQ + c.t) * 3 + comp];
-    sv[DIM] = a.evin[(int64_t)a.ncells * 3 * NQ + (int64_t)cell * NQ + c.t];
+    for (int comp = 0; comp <= DIM; ++comp) sv[comp] = a.evin[((int64_t)cell * NQ + c.t) * 4 + comp];
   } else if (c.valid) {
     for (int comp = 0; comp < DIM; ++comp) sv[comp] = dir ? T(0) : a.src[comp * a.Nv + nd];
     sv[DIM] = a.src[DIM * a.Nv + nd];
@@ -403,7 +402,7 @@ __global__ void __launch_bounds__((Shape<DIM, K>::BLOCK)) ns_jacobian_kernel(Arg
     const T r = c.integrate(JxW * val_u[comp], f);
     if (a.ev) {
       if (c.valid)
-        a.ev[a.evin ? ((int64_t)cell * NQ + c.t) * 3 + comp : ((int64_t)cell * 3 + comp) * NQ + c.t] = r;
+        a.ev[a.evin ? ((int64_t)cell * NQ + c.t) * 4 + comp : ((int64_t)cell * 3 + comp) * NQ + c.t] = r;
     } else if (c.valid && !dir) {
       atomicAdd(a.dst + comp * a.Nv + nd, r);
     }
@@ -417,7 +416,8 @@ __global__ void __launch_bounds__((Shape<DIM, K>::BLOCK)) ns_jacobian_kernel(Arg
     }
     const T r = c.integrate(JxW * div, f);
     if (a.ev) {
-      if (c.valid) a.ev[(int64_t)a.ncells * 3 * NQ + (int64_t)cell * NQ + c.t] = r;
+      if (c.valid)
+        a.ev[a.evin ? ((int64_t)cell * NQ + c.t) * 4 + 3 : (int64_t)a.ncells * 3 * NQ + (int64_t)cell * NQ + c.t] = r;
     } else if (c.valid) {
       atomicAdd(a.dst + DIM * a.Nv + nd, r);
     }
@@ -512,13 +512,6 @@ __global__ void k_color_extract(LevelGeom g, int q, int color, int comp, const d
   if (node_color(g, q, i) == color) diag[comp * g.Nv + i] = y[comp * g.Nv + i];
 }
 
-// ev[(cell*nq + t)*3 + comp] = ev[3*ncells*nq + cell*nq + t]
-__global__ void k_ev_to_velocity(double *ev, int64_t ncells, int nq, int comp) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= ncells * nq) return;
-  ev[i * 3 + comp] = ev[3 * ncells * nq + i];
-}
-
 template <typename T>
 __global__ void k_jacobi_relax(T *x, const T *b, const T *t, const T *invdiag, T omega, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -549,12 +542,6 @@ void launch_color_extract(const LevelGeom &g, int q, int color, int comp, const 
                           hipStream_t s) {
   hipLaunchKernelGGL(k_color_extract, dim3((unsigned)((g.Nv + 255) / 256)), dim3(256), 0, s, g, q, color, comp, y,
                      diag);
-  MFS_HIP(hipGetLastError());
-}
-
-void launch_ev_to_velocity(double *ev, int64_t ncells, int nq, int comp, hipStream_t s) {
-  hipLaunchKernelGGL(k_ev_to_velocity, dim3((unsigned)((ncells * nq + 255) / 256)), dim3(256), 0, s, ev, ncells, nq,
-                     comp);
   MFS_HIP(hipGetLastError());
 }
 
