@@ -154,7 +154,7 @@ struct HpLevel {
   HpSpaceHost V;
   HpDevSpace vd;
   int64_t ev_size = 0;
-  int64_t *off_u = nullptr;  // per cell: E-vector offset of the cell's [3][(k+1)^3] block
+  int64_t *off_u = nullptr;  // per cell: E-vector offset of the cell's [(k+1)^3][3] block
   int *deg = nullptr;        // per cell degree (device)
   std::vector<int> class_k, class_n;
   std::vector<int *> class_cells;
@@ -1973,7 +1973,7 @@ void hp_build(mfs_problem &P, const std::vector<int> &deg0, hipStream_t s) {
     HpLevel &L = H.lev[l];
     L.V.build(H.n, degs[l]);
     const auto off = ev_offsets(degs[l], 3, 0, &L.ev_size);
-    hp_upload(H, L.V, true, off, true, L.vd, s);
+    hp_upload(H, L.V, true, off, true, L.vd, s, true);
     L.off_u = H.upload(off, s);
     L.deg = H.upload(degs[l], s);
     for (int k = 2; k <= 6; ++k) {
@@ -2007,7 +2007,7 @@ void hp_build(mfs_problem &P, const std::vector<int> &deg0, hipStream_t s) {
     std::vector<int> d2(H.ncells, 2);
     H.V2.build(H.n, d2);
     const auto off = ev_offsets(d2, 3, 0, &H.ev2_size);
-    hp_upload(H, H.V2, true, off, true, H.v2d, s);
+    hp_upload(H, H.V2, true, off, true, H.v2d, s, true);
     H.off_u2 = H.upload(off, s);
     H.deg2 = H.upload(d2, s);
     std::vector<int64_t> perm(H.V2.N);

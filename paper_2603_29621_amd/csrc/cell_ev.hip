@@ -61,7 +61,7 @@ __global__ void __launch_bounds__((Shape<3, K, K - 1>::BLOCK)) cell_kernel_ev(Ev
   T su[3] = {0, 0, 0}, sp = 0;
   if (NEED_U && c.valid) {
 #pragma unroll
-    for (int comp = 0; comp < DIM; ++comp) su[comp] = a.ev.in_u[ou + comp * NQ + c.t];
+    for (int comp = 0; comp < DIM; ++comp) su[comp] = a.ev.in_u[ou + 3 * c.t + comp];
   }
   if (NEED_P && c.valid && ploc) sp = a.ev.in_p[op + jp];
   if (c.valid)
@@ -141,7 +141,7 @@ __global__ void __launch_bounds__((Shape<3, K, K - 1>::BLOCK)) cell_kernel_ev(Ev
     c.template integrate_gradients<DIM>(f, r);
 #pragma unroll
     for (int comp = 0; comp < DIM; ++comp)
-      if (c.valid) a.ev.out_u[ou + comp * NQ + c.t] = r[comp];
+      if (c.valid) a.ev.out_u[ou + 3 * c.t + comp] = r[comp];
   }
   if (OUT_P) {
     if (c.active) c.b0[c.t] = qv;

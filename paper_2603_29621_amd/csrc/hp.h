@@ -79,7 +79,7 @@ void hp_gather(int64_t nrows, int ncomp, const int64_t *row_ptr, const int *col,
 // per cell c of the list: ev_f = (E (x) E (x) E) ev_c (transpose: ev_c = (E^T..) ev_f)
 // with E the 1D embedding from the coarse degree kc[c] to the fine degree
 // kf[c] (tables[kf][kc], MAXQ x MAXQ row-major [fine node][coarse node]),
-// ncomp blocks per cell
+// ncomp components of a node side by side
 template <typename T>
 void hp_embed(int64_t ncells, int ncomp, const int *kf, const int *kc, const double *tables,
               const int64_t *off_f, const int64_t *off_c, const T *in, T *out, bool transpose, hipStream_t s);
@@ -111,7 +111,8 @@ void colour_indicator(const int *colour, int64_t N, const int cols[3], double *o
 void colour_extract(const int *colour, int64_t N, const int cols[3], const double *y, double *diag, hipStream_t s);
 
 // cell kernels on E-vectors (cell_kernels.hip): one degree class of cells,
-// local values in, local results out (velocity [3][(k+1)^3], pressure [k^3]
+// local values in, local results out (velocity [(k+1)^3][3], components of a
+// node side by side, pressure [k^3]
 // per cell at the per-cell offsets)
 template <typename T>
 struct EvArgs {

@@ -102,7 +102,7 @@ __global__ void __launch_bounds__(256) k_embed(int64_t ncells, int ncomp, const 
   const int sin3 = ni * ni * ni, sout3 = no * no * no;
   for (int comp = 0; comp < ncomp; ++comp) {
     __syncthreads();
-    for (int i = threadIdx.x; i < sin3; i += blockDim.x) s_a[i] = (double)in[oi + (int64_t)comp * sin3 + i];
+    for (int i = threadIdx.x; i < sin3; i += blockDim.x) s_a[i] = (double)in[oi + (int64_t)i * ncomp + comp];
     __syncthreads();
     // x: [l][j][i_in] -> [l][j][i_out]
     for (int t = threadIdx.x; t < no * ni * ni; t += blockDim.x) {
@@ -125,7 +125,7 @@ __global__ void __launch_bounds__(256) k_embed(int64_t ncells, int ncomp, const 
       const int i = t % no, j = (t / no) % no, lo = t / (no * no);
       double s = 0;
       for (int m = 0; m < ni; ++m) s += (transpose ? s_E[m * MAXQ + lo] : s_E[lo * MAXQ + m]) * s_a[i + no * (j + no * m)];
-      out[oo + (int64_t)comp * sout3 + t] = (T)s;
+      out[oo + (int64_t)t * ncomp + comp] = (T)s;
     }
   }
 }
