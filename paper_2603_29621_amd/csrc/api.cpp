@@ -518,6 +518,26 @@ void plan_arena(Arena &A, mfs_problem &P, const std::vector<LevelGeom> &G) {
   K.ydev = A.take<double>(64);
 }
 
+// every cell an axis-aligned box: coordinate a of a vertex depends on its
+// index along a only
+bool cartesian_grid(const std::vector<double> &X, const LevelGeom &g) {
+  const int d = g.dim;
+  const int m0 = g.n[0] + 1, m1 = g.n[1] + 1, m2 = d == 3 ? g.n[2] + 1 : 1;
+  for (int z = 0; z < m2; ++z)
+    for (int y = 0; y < m1; ++y)
+      for (int x = 0; x < m0; ++x) {
+        const int64_t v = x + (int64_t)m0 * (y + (int64_t)m1 * z);
+        const int idx[3] = {x, y, z};
+        for (int a = 0; a < d; ++a) {
+          int r[3] = {0, 0, 0};
+          r[a] = idx[a];
+          const int64_t ref = r[0] + (int64_t)m0 * (r[1] + (int64_t)m1 * r[2]);
+          if (X[v * d + a] != X[ref * d + a]) return false;
+        }
+      }
+  return true;
+}
+
 void check_options(const mfs_options &o) {
   MFS_REQUIRE(o.cheb_degree >= 1 && o.cheb_degree <= 32, MFS_EINVAL, "cheb_degree %d out of range", o.cheb_degree);
   MFS_REQUIRE(o.cheb_range > 1.0, MFS_EINVAL, "cheb_range must exceed 1");
@@ -1727,6 +1747,7 @@ int mfs_setup(const mfs_mesh *mesh, int k, double nu, const mfs_options *opts, v
             const int64_t fv = (int64_t)x * st + (int64_t)fn0 * ((int64_t)y * st + (int64_t)fn1 * z * st);
             for (int a = 0; a < dim; ++a) L.Xhost[v * dim + a] = mesh->vertices[fv * dim + a];
           }
+      L.g.cart = cartesian_grid(L.Xhost, L.g) ? 1 : 0;
       std::vector<float> X32(L.Xhost.begin(), L.Xhost.end());
       MFS_HIP(hipMemcpyAsync(L.X64, L.Xhost.data(), L.Xhost.size() * sizeof(double), hipMemcpyHostToDevice, s));
       MFS_HIP(hipMemcpyAsync(L.X32, X32.data(), X32.size() * sizeof(float), hipMemcpyHostToDevice, s));
@@ -2199,6 +2220,7 @@ void amr_level_upload(AmrData &A, AmrLevel &V, bool op, bool work, hipStream_t s
   g.np[0] = g.np[1] = k + 1;
   g.np[2] = g.nv[2];
   g.Nv = g.Np = (int64_t)g.nv[0] * g.nv[1] * g.nv[2];
+  g.cart = 1;  // octree leaves of a Cartesian cube
   HpData &H = A.H;
   amr_maps_upload(H, S, V.M, s);
   for (int i = 0; i < 2; ++i) {

@@ -69,6 +69,7 @@ struct LevelGeom {
   int k, kp;       // velocity / pressure degree (kp = 0: no pressure space)
   int nv[3], np[3];
   int64_t Nv, Np, ncells;
+  int cart;        // 1: every cell an axis-aligned box (the Navier-Stokes kernels use it)
 };
 
 template <typename T>

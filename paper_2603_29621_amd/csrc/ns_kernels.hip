@@ -111,7 +111,9 @@ struct Ctx {
   }
   // nodal value of this thread in b0 on entry: value, reference gradient,
   // and (HESS) reference Hessian (00, 01, 11 | 00, 01, 02, 11, 12, 22) at the point
-  template <bool HESS>
+  // MIXED = false: the mixed second derivatives are not formed (their
+  // entries of h are left as they are; Cartesian cells do not need them)
+  template <bool HESS, bool MIXED = true>
   __device__ __forceinline__ void evaluate(T &val, T g[3], T h[6]) {
     const T *S = tab + TAB_S;
     T v = sweep<DIM, Q, 0, Q, false>(b0, S, qi, qj, ql);
@@ -146,18 +148,19 @@ struct Ctx {
       csync<Shape<DIM, K>::WAVE>();
       if (DIM == 2) {
         h[0] = sweep<DIM, Q, 0, Q, false>(b0, D, qi, qj, ql);
-        h[1] = sweep<DIM, Q, 0, Q, false>(b1, D, qi, qj, ql);
+        if (MIXED) h[1] = sweep<DIM, Q, 0, Q, false>(b1, D, qi, qj, ql);
         h[2] = sweep<DIM, Q, 1, Q, false>(b1, D, qi, qj, ql);
       } else {
         h[0] = sweep<DIM, Q, 0, Q, false>(b0, D, qi, qj, ql);
-        h[1] = sweep<DIM, Q, 0, Q, false>(b1, D, qi, qj, ql);
-        h[2] = sweep<DIM, Q, 0, Q, false>(b2, D, qi, qj, ql);
+        if (MIXED) h[1] = sweep<DIM, Q, 0, Q, false>(b1, D, qi, qj, ql);
+        if (MIXED) h[2] = sweep<DIM, Q, 0, Q, false>(b2, D, qi, qj, ql);
         h[3] = sweep<DIM, Q, 1, Q, false>(b1, D, qi, qj, ql);
-        h[4] = sweep<DIM, Q, 1, Q, false>(b2, D, qi, qj, ql);
+        if (MIXED) h[4] = sweep<DIM, Q, 1, Q, false>(b2, D, qi, qj, ql);
         h[5] = sweep<DIM, Q, 2, Q, false>(b2, D, qi, qj, ql);
       }
 #pragma unroll
-      for (int i = 0; i < (DIM == 2 ? 3 : 6); ++i) pin(h[i]);
+      for (int i = 0; i < (DIM == 2 ? 3 : 6); ++i)
+        if (MIXED || i == 0 || i == (DIM == 2 ? 2 : 3) || i == 5) pin(h[i]);
       csync<Shape<DIM, K>::WAVE>();
     }
   }
@@ -195,6 +198,13 @@ struct Ctx {
     return out;
   }
 };
+
+// physical Laplacian of an axis-aligned cell: sum_a I[a][a]^2 H_aa
+template <int DIM, typename T>
+__device__ __forceinline__ T laplacian_cart(const T h[6], const T I[3][3]) {
+  if (DIM == 2) return I[0][0] * I[0][0] * h[0] + I[1][1] * I[1][1] * h[2];
+  return I[0][0] * I[0][0] * h[0] + I[1][1] * I[1][1] * h[3] + I[2][2] * I[2][2] * h[5];
+}
 
 // physical Laplacian from the reference Hessian: sum_a sum_bc I[b][a] I[c][a] H_bc
 template <int DIM, typename T>
@@ -266,13 +276,29 @@ __device__ __forceinline__ T laplacian(const T h[6], const T I[3][3]) {
   __syncthreads();                                                                                     \
   T xi[3] = {s_tab[TAB_X + c.qi], s_tab[TAB_X + c.qj], DIM == 3 ? s_tab[TAB_X + c.ql] : T(0)};         \
   T I[3][3] = {};                                                                                      \
-  const T det = jac_inv<DIM>(s_X[e], xi, I);                                                           \
+  T det_ = T(1);                                                                                       \
+  if constexpr (CART) {                                                                                \
+    /* axis-aligned box: J = diag(h), the off-diagonals of I stay zero */                              \
+    const T hx = s_X[e][DIM] - s_X[e][0], hy = s_X[e][2 * DIM + 1] - s_X[e][1];                        \
+    I[0][0] = T(1) / hx;                                                                               \
+    I[1][1] = T(1) / hy;                                                                               \
+    det_ = hx * hy;                                                                                    \
+    if (DIM == 3) {                                                                                    \
+      const T hz = s_X[e][4 * DIM + 2] - s_X[e][2];                                                    \
+      I[2][2] = T(1) / hz;                                                                             \
+      det_ *= hz;                                                                                      \
+    }                                                                                                  \
+  } else {                                                                                             \
+    det_ = jac_inv<DIM>(s_X[e], xi, I);                                                                \
+  }                                                                                                    \
+  const T det = det_;                                                                                  \
   T wq = s_tab[TAB_W + c.qi] * s_tab[TAB_W + c.qj];                                                    \
   if (DIM == 3) wq *= s_tab[TAB_W + c.ql];                                                             \
   const T JxW = det * wq;
 
 // linearisation data at the quadrature points from the nodal velocity u0
-template <int DIM, int K, typename T>
+// (CART: every cell an axis-aligned box)
+template <int DIM, int K, typename T, bool CART>
 __global__ void __launch_bounds__((Shape<DIM, K>::BLOCK)) ns_linearize_kernel(Args<T> a) {
   NSK_PROLOGUE
   NSK_PROLOGUE_B
@@ -284,14 +310,14 @@ __global__ void __launch_bounds__((Shape<DIM, K>::BLOCK)) ns_linearize_kernel(Ar
     if (c.active) c.b0[c.t] = v0;
     csync<Sh::WAVE>();
     T val, g[3], h[6];
-    c.template evaluate<true>(val, g, h);
+    c.template evaluate<true, !CART>(val, g, h);
     u[comp] = val;
     for (int x = 0; x < DIM; ++x) {
       T s = 0;
       for (int b = 0; b < DIM; ++b) s += I[b][x] * g[b];
       U[comp][x] = s;
     }
-    lap[comp] = laplacian<DIM>(h, I);
+    lap[comp] = CART ? laplacian_cart<DIM>(h, I) : laplacian<DIM>(h, I);
   }
   // cell volume
   if (c.active && c.t == 0) s_vol[e] = 0;
@@ -320,8 +346,8 @@ __global__ void __launch_bounds__((Shape<DIM, K>::BLOCK)) ns_linearize_kernel(Ar
   }
 }
 
-// Jacobian application
-template <int DIM, int K, typename T>
+// Jacobian application (CART: every cell an axis-aligned box)
+template <int DIM, int K, typename T, bool CART>
 __global__ void __launch_bounds__((Shape<DIM, K>::BLOCK)) ns_jacobian_kernel(Args<T> a) {
   NSK_PROLOGUE
   // every global load of the point (nodal source values of the 4 fields,
@@ -348,14 +374,14 @@ __global__ void __launch_bounds__((Shape<DIM, K>::BLOCK)) ns_jacobian_kernel(Arg
     if (c.active) c.b0[c.t] = sv[comp];
     csync<Sh::WAVE>();
     T val, g[3], h[6];
-    c.template evaluate<true>(val, g, h);
+    c.template evaluate<true, !CART>(val, g, h);
     w[comp] = val;
     for (int x = 0; x < DIM; ++x) {
       T s = 0;
       for (int b = 0; b < DIM; ++b) s += I[b][x] * g[b];
       G[comp][x] = s;
     }
-    L[comp] = laplacian<DIM>(h, I);
+    L[comp] = CART ? laplacian_cart<DIM>(h, I) : laplacian<DIM>(h, I);
   }
   T P, gP[3] = {};
   {
@@ -457,14 +483,21 @@ void launch_ns(const LevelGeom &g, const T *X, const T *tab, int what, T nu, T d
               "cell-local Navier-Stokes inputs need 3D, corner coordinates and cell-local outputs");
   a.evin = evin;
   a.Xcell = Xcell;
-#define NS_GO(D, KK)                                                                                             \
+#define NS_GO2(D, KK, C)                                                                                         \
   {                                                                                                              \
     using Sh = nsk::Shape<D, KK>;                                                                                \
     const int grid = (int)((g.ncells + Sh::CPB - 1) / Sh::CPB);                                                  \
     if (what == 0)                                                                                               \
-      hipLaunchKernelGGL((nsk::ns_linearize_kernel<D, KK, T>), dim3(grid), dim3(Sh::BLOCK), 0, s, a);            \
+      hipLaunchKernelGGL((nsk::ns_linearize_kernel<D, KK, T, C>), dim3(grid), dim3(Sh::BLOCK), 0, s, a);         \
     else                                                                                                         \
-      hipLaunchKernelGGL((nsk::ns_jacobian_kernel<D, KK, T>), dim3(grid), dim3(Sh::BLOCK), 0, s, a);             \
+      hipLaunchKernelGGL((nsk::ns_jacobian_kernel<D, KK, T, C>), dim3(grid), dim3(Sh::BLOCK), 0, s, a);          \
+  }
+#define NS_GO(D, KK)        \
+  {                         \
+    if (g.cart)             \
+      NS_GO2(D, KK, true)   \
+    else                    \
+      NS_GO2(D, KK, false)  \
   }
   if (g.dim == 2) {
     if (g.k == 1) NS_GO(2, 1) else if (g.k == 2) NS_GO(2, 2) else if (g.k == 3) NS_GO(2, 3)
@@ -474,6 +507,7 @@ void launch_ns(const LevelGeom &g, const T *X, const T *tab, int what, T nu, T d
     else MFS_REQUIRE(false, MFS_EUNSUPPORTED, "Navier-Stokes degree %d", g.k);
   }
 #undef NS_GO
+#undef NS_GO2
   MFS_HIP(hipGetLastError());
 }
 
