@@ -115,32 +115,13 @@ __global__ void k_amr_inject_t(AmrMaps M, const T *x, T *ev) {
   }
 }
 
-// weight of coarse node s for fine node t of a child in octant o (8: the
-// same cell, identity)
-__device__ __forceinline__ double embed_weight(const AmrEmbed &E, int oct, int t, int s) {
-  const int q = E.k + 1;
-  double w = 1.0;
-  for (int a = 0; a < 3; ++a) {
-    int ta = t, sa = s;
-    for (int b = 0; b < a; ++b) {
-      ta /= q;
-      sa /= q;
-    }
-    ta %= q;
-    sa %= q;
-    if (oct == 8)
-      w *= (ta == sa) ? 1.0 : 0.0;
-    else
-      w *= E.w[(oct >> a) & 1][ta][sa];
-  }
-  return w;
-}
-
-// fine[f][comp][t] = sum_s W(oct[f])[t][s] coarse[parent[f]][comp][s]
+// fine[f][comp][t] = sum_s W(oct[f])[t][s] coarse[parent[f]][comp][s]:
+// unchanged cells (octant 8) copy, split cells apply the tensor product of
+// the three half-cell 1D embeddings
 template <typename T>
 __global__ void k_embed(AmrEmbed E, int64_t ncf, int64_t ncc, const int *parent, const uint8_t *oct, const T *evc,
                         T *evf) {
-  const int nq = (E.k + 1) * (E.k + 1) * (E.k + 1);
+  const int q = E.k + 1, nq = q * q * q;
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= ncf * 4 * nq) return;
   const int t = (int)(i % nq);
@@ -150,36 +131,52 @@ __global__ void k_embed(AmrEmbed E, int64_t ncf, int64_t ncc, const int *parent,
   const int o = oct[f];
   const T *src = evc + ev_at(ncc, nq, c, comp);
   const int st = ev_step(comp);
-  double acc = 0.0;
-  for (int s = 0; s < nq; ++s) {
-    const double w = embed_weight(E, o, t, s);
-    if (w != 0.0) acc += w * (double)src[s * st];
+  T out;
+  if (o == 8) {
+    out = src[t * st];
+  } else {
+    const int tx = t % q, ty = (t / q) % q, tz = t / (q * q);
+    const double *wx = E.w[o & 1][tx], *wy = E.w[(o >> 1) & 1][ty], *wz = E.w[(o >> 2) & 1][tz];
+    double acc = 0.0;
+    for (int sz = 0; sz < q; ++sz)
+      for (int sy = 0; sy < q; ++sy) {
+        const double wyz = wy[sy] * wz[sz];
+        for (int sx = 0; sx < q; ++sx) acc += wx[sx] * wyz * (double)src[(sx + q * (sy + q * sz)) * st];
+      }
+    out = (T)acc;
   }
-  evf[ev_at(ncf, nq, f, comp) + t * st] = (T)acc;
+  evf[ev_at(ncf, nq, f, comp) + t * st] = out;
 }
 
 // coarse[c][comp][s] = sum over the children f of c, sum_t W(oct[f])[t][s] fine[f][comp][t]
 template <typename T>
 __global__ void k_embed_t(AmrEmbed E, int64_t ncf, int64_t ncc, const int64_t *cptr, const int *child,
                           const uint8_t *oct, const T *evf, T *evc) {
-  const int nq = (E.k + 1) * (E.k + 1) * (E.k + 1);
+  const int q = E.k + 1, nq = q * q * q;
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= ncc * 4 * nq) return;
   const int s = (int)(i % nq);
   const int comp = (int)((i / nq) % 4);
   const int64_t c = i / (4 * nq);
+  const int sx = s % q, sy = (s / q) % q, sz = s / (q * q);
+  const int st = ev_step(comp);
   double acc = 0.0;
   for (int64_t e = cptr[c]; e < cptr[c + 1]; ++e) {
     const int64_t f = child[e];
     const int o = oct[f];
     const T *src = evf + ev_at(ncf, nq, f, comp);
-    const int st = ev_step(comp);
-    for (int t = 0; t < nq; ++t) {
-      const double w = embed_weight(E, o, t, s);
-      if (w != 0.0) acc += w * (double)src[t * st];
+    if (o == 8) {
+      acc += (double)src[s * st];
+      continue;
     }
+    const int hx = o & 1, hy = (o >> 1) & 1, hz = (o >> 2) & 1;
+    for (int tz = 0; tz < q; ++tz)
+      for (int ty = 0; ty < q; ++ty) {
+        const double wyz = E.w[hy][ty][sy] * E.w[hz][tz][sz];
+        for (int tx = 0; tx < q; ++tx) acc += E.w[hx][tx][sx] * wyz * (double)src[(tx + q * (ty + q * tz)) * st];
+      }
   }
-  evc[ev_at(ncc, nq, c, comp) + s * ev_step(comp)] = (T)acc;
+  evc[ev_at(ncc, nq, c, comp) + s * st] = (T)acc;
 }
 
 __global__ void k_colour_probe(const int *colour, int64_t N, int col, int comp, double *out) {
