@@ -214,6 +214,13 @@ typedef struct mfs_refined_mesh {
 int mfs_setup_refined(const mfs_refined_mesh *mesh, int k, double nu, const mfs_options *opts, void *stream,
                       mfs_problem **out);
 
+/* Host only (no device call): sizes of the refined-mesh space that
+ * mfs_setup_refined would build, without building it on the device.
+ * n_unknowns = unknowns per component (n_u = n_p), n_hanging = hanging node
+ * positions.  Validates the leaves like mfs_setup_refined (MFS_EINVAL,
+ * MFS_EUNSUPPORTED). */
+int mfs_refined_count(const mfs_refined_mesh *mesh, int k, int64_t *n_unknowns, int64_t *n_hanging);
+
 /* Sizes at level `level` (0 = finest): scalar velocity nodes per component and
  * pressure nodes (0 on levels without pressure; n_u on every level of a
  * Navier-Stokes problem). */

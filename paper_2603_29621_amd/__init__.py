@@ -38,7 +38,7 @@ EXPORTED = [
     "mfs_quadrature_points_device", "mfs_vmult",
     "mfs_diagonal", "mfs_get_lambda", "mfs_set_lambda", "mfs_vcycle", "mfs_prolongate_add", "mfs_restrict",
     "mfs_precondition", "mfs_rhs", "mfs_solve", "mfs_solve_begin", "mfs_solve_advance",
-    "mfs_set_linearization", "mfs_setup_hp", "mfs_setup_refined",
+    "mfs_set_linearization", "mfs_setup_hp", "mfs_setup_refined", "mfs_refined_count",
 ]
 
 
@@ -107,6 +107,7 @@ def lib():
                                    ctypes.POINTER(mfs_options), vp, ctypes.POINTER(vp)]
         L.mfs_setup_refined.argtypes = [ctypes.POINTER(mfs_refined_mesh), ctypes.c_int, ctypes.c_double,
                                         ctypes.POINTER(mfs_options), vp, ctypes.POINTER(vp)]
+        L.mfs_refined_count.argtypes = [ctypes.POINTER(mfs_refined_mesh), ctypes.c_int, i64p, i64p]
         L.mfs_n_dofs.argtypes = [vp, ctypes.c_int, i64p, i64p]
         L.mfs_n_levels.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
         L.mfs_level_info.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
@@ -253,9 +254,7 @@ def mfs_setup_hp(n, vertices, cell_degree, nu, opts=None, stream=None) -> ctypes
     return h
 
 
-def mfs_setup_refined(mesh, k, nu, opts=None, stream=None) -> ctypes.c_void_p:
-    """Equal-order Navier-Stokes problem on a locally refined mesh given as
-    {"n", "levels", "level" [nc], "idx" [nc, 3]} (the leaves)."""
+def _refined(mesh):
     lev = np.ascontiguousarray(mesh["level"], dtype=np.int32)
     idx = np.ascontiguousarray(mesh["idx"], dtype=np.int32).reshape(-1, 3)
     if len(idx) != len(lev):
@@ -266,6 +265,22 @@ def mfs_setup_refined(mesh, k, nu, opts=None, stream=None) -> ctypes.c_void_p:
     m.ncells = len(lev)
     m.level = lev.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
     m.idx = idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+    return m, (lev, idx)
+
+
+def mfs_refined_count(mesh, k):
+    """(unknowns per component, hanging positions) of the refined-mesh space
+    (host only)."""
+    m, _keep = _refined(mesh)
+    n, h = ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(lib().mfs_refined_count(ctypes.byref(m), int(k), ctypes.byref(n), ctypes.byref(h)))
+    return n.value, h.value
+
+
+def mfs_setup_refined(mesh, k, nu, opts=None, stream=None) -> ctypes.c_void_p:
+    """Equal-order Navier-Stokes problem on a locally refined mesh given as
+    {"n", "levels", "level" [nc], "idx" [nc, 3]} (the leaves)."""
+    m, _keep = _refined(mesh)
     if opts is None:
         opts = mfs_default_options(pressure_offset=0, mg_levels=0)
     h = ctypes.c_void_p(0)

@@ -2525,6 +2525,16 @@ int mfs_setup_hp(const mfs_mesh *mesh, const int *cell_degree, double nu, const 
   return MFS_OK;
 }
 
+int mfs_refined_count(const mfs_refined_mesh *mesh, int k, int64_t *n_unknowns, int64_t *n_hanging) {
+  return guard([&] {
+    MFS_REQUIRE(mesh != nullptr, MFS_EINVAL, "mesh is NULL");
+    AmrSpaceHost S;
+    S.build(mesh->n, mesh->levels, mesh->ncells, mesh->level, mesh->idx, k);
+    if (n_unknowns) *n_unknowns = S.N;
+    if (n_hanging) *n_hanging = S.nhanging;
+  });
+}
+
 int mfs_setup_refined(const mfs_refined_mesh *mesh, int k, double nu, const mfs_options *opts, void *stream,
                       mfs_problem **out) {
   mfs_problem *P = nullptr;

@@ -98,3 +98,17 @@ def test_refined_mesh_validation_host_only():
         with pytest.raises(mfs.MfsError) as e:
             mfs.mfs_setup_refined(mesh, k, 0.01, opts, stream=0)
         assert e.value.code == code
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_refined_space_counts_host_only(k):
+    """The host construction of the refined-mesh space (no device): unknown and
+    hanging-node counts equal the oracle's on seeded and degenerate meshes."""
+    from oracle import amr
+
+    for kw in [dict(n=3, seed=0, levels=2, centre=[0.4, 0.5, 0.55], radius=0.3), dict(n=4, seed=1, levels=2),
+               dict(n=1, seed=0, levels=2, centre=[0.3, 0.4, 0.6], radius=0.45),
+               dict(n=2, seed=0, levels=1, centre=[0.5, 0.5, 0.5], radius=10.0)]:
+        m = inputs.refined_mesh(**kw)
+        S = amr.AmrSpace(m, k)
+        assert mfs.mfs_refined_count(m, k) == (S.N, int(S.hanging.sum()))
