@@ -19,18 +19,24 @@ struct AmrEmbed {
 // the pressure of a cell-local node side by side (row r = cell*(k+1)^3 + node
 // holds slots 4r .. 4r+3).
 
-// Maps between the unknowns (4 blocks of N) and the E-vector rows.
+// Maps between the unknowns (4 blocks of N) and the E-vector rows.  Almost
+// every row is one unknown with weight 1 (a plain row); the rows of hanging
+// nodes combine several unknowns (weighted rows), kept in a CSR of their own.
+// The transposed lists split the same way.
 struct AmrMaps {
   int64_t N = 0, nrows = 0;
-  const int64_t *row_ptr = nullptr;  // CSR over rows: unknown, weight
-  const int *col = nullptr;
-  const double *val = nullptr;
-  const int64_t *tptr = nullptr;  // transposed, per unknown: row, weight
+  const int *rcol = nullptr;      // per row: its unknown, or -1 - h for weighted row h
+  const int64_t *hptr = nullptr;  // weighted rows: unknown, weight
+  const int *hcol = nullptr;
+  const double *hval = nullptr;
+  const int64_t *tptr = nullptr;  // per unknown: the plain rows holding it
   const int *trow = nullptr;
-  const double *tval = nullptr;
+  const int64_t *wptr = nullptr;  // per unknown: the weighted rows using it, with the weight
+  const int *wrow = nullptr;
+  const double *wval = nullptr;
   const uint8_t *dir = nullptr;   // velocity Dirichlet unknowns
   const int *owner = nullptr;     // a row holding the unknown's own node
-  int64_t nheavy = 0;             // unknowns with more than AMR_LIGHT rows
+  int64_t nheavy = 0;             // unknowns with more than AMR_LIGHT rows in all
   const int64_t *heavy = nullptr;
 };
 constexpr int AMR_LIGHT = 16;

@@ -29,31 +29,47 @@ unsigned agrid(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64
 template <typename T, int NC, bool MASK>
 __global__ void k_amr_gather(AmrMaps M, const T *x, T *ev) {
   for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < M.nrows; r += (int64_t)gridDim.x * blockDim.x) {
-    double s[NC] = {};
-    for (int64_t j = M.row_ptr[r]; j < M.row_ptr[r + 1]; ++j) {
-      const int64_t c = M.col[j];
-      const double w = M.val[j];
-      const bool d = MASK && M.dir[c];
+    const int c0 = M.rcol[r];
+    T out[NC];
+    if (c0 >= 0) {  // plain row
+      const bool d = MASK && M.dir[c0];
 #pragma unroll
-      for (int comp = 0; comp < NC; ++comp)
-        if (!(d && comp < 3)) s[comp] += w * (double)x[comp * M.N + c];
+      for (int comp = 0; comp < NC; ++comp) out[comp] = (d && comp < 3) ? T(0) : x[comp * M.N + c0];
+    } else {
+      const int64_t h = -1 - (int64_t)c0;
+      double s[NC] = {};
+      for (int64_t j = M.hptr[h]; j < M.hptr[h + 1]; ++j) {
+        const int64_t c = M.hcol[j];
+        const double w = M.hval[j];
+        const bool d = MASK && M.dir[c];
+#pragma unroll
+        for (int comp = 0; comp < NC; ++comp)
+          if (!(d && comp < 3)) s[comp] += w * (double)x[comp * M.N + c];
+      }
+#pragma unroll
+      for (int comp = 0; comp < NC; ++comp) out[comp] = (T)s[comp];
     }
 #pragma unroll
-    for (int comp = 0; comp < NC; ++comp) ev[4 * r + comp] = (T)s[comp];
+    for (int comp = 0; comp < NC; ++comp) ev[4 * r + comp] = out[comp];
   }
 }
 
-// one thread per unknown with a list of at most AMR_LIGHT rows, four
-// components read together from each row
+// one thread per unknown with at most AMR_LIGHT rows in all, four components
+// read together from each row: plain rows first, then the weighted ones
 template <typename T>
 __global__ void k_amr_scatter(AmrMaps M, const T *ev, const T *src, T *dst) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < M.N; i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t b = M.tptr[i], e = M.tptr[i + 1];
-    if (e - b > AMR_LIGHT) continue;  // summed by k_amr_scatter_heavy
+    const int64_t b = M.tptr[i], e = M.tptr[i + 1], wb = M.wptr[i], we = M.wptr[i + 1];
+    if ((e - b) + (we - wb) > AMR_LIGHT) continue;  // summed by k_amr_scatter_heavy
     double s[4] = {0, 0, 0, 0};
     for (int64_t j = b; j < e; ++j) {
-      const double w = M.tval[j];
       const T *v = ev + 4 * (int64_t)M.trow[j];
+#pragma unroll
+      for (int comp = 0; comp < 4; ++comp) s[comp] += (double)v[comp];
+    }
+    for (int64_t j = wb; j < we; ++j) {
+      const double w = M.wval[j];
+      const T *v = ev + 4 * (int64_t)M.wrow[j];
 #pragma unroll
       for (int comp = 0; comp < 4; ++comp) s[comp] += w * (double)v[comp];
     }
@@ -64,18 +80,19 @@ __global__ void k_amr_scatter(AmrMaps M, const T *ev, const T *src, T *dst) {
   }
 }
 
-// one wave per long list: strided partial sums, then a butterfly (the same
-// order on every call)
+// one wave per long list: strided partial sums over the plain then the
+// weighted rows, then a butterfly (the same order on every call)
 template <typename T>
 __global__ void __launch_bounds__(AB) k_amr_scatter_heavy(AmrMaps M, const T *ev, const T *src, T *dst) {
   const int lane = threadIdx.x & 63;
   const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  for (int64_t h = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6; h < M.nheavy; h += waves) {
-    const int64_t i = M.heavy[h];
+  for (int64_t hh = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6; hh < M.nheavy; hh += waves) {
+    const int64_t i = M.heavy[hh];
+    const int64_t b = M.tptr[i], nu = M.tptr[i + 1] - b, wb = M.wptr[i], nw = M.wptr[i + 1] - wb;
     double s[4] = {0, 0, 0, 0};
-    for (int64_t j = M.tptr[i] + lane; j < M.tptr[i + 1]; j += 64) {
-      const double w = M.tval[j];
-      const T *v = ev + 4 * (int64_t)M.trow[j];
+    for (int64_t j = lane; j < nu + nw; j += 64) {
+      const double w = j < nu ? 1.0 : M.wval[wb + j - nu];
+      const T *v = ev + 4 * (int64_t)(j < nu ? M.trow[b + j] : M.wrow[wb + j - nu]);
 #pragma unroll
       for (int comp = 0; comp < 4; ++comp) s[comp] += w * (double)v[comp];
     }

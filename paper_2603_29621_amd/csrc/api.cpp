@@ -2163,38 +2163,69 @@ const T *amr_inv(const AmrLevel &V) {
 int amr_nop(const AmrData &A) { return A.mg ? (int)A.lev.size() - 1 : 1; }
 
 // device maps of a level: rows are cell-major ((k+1)^3 per cell), so row r's
-// E-vector slots are 4r .. 4r+3 and the lists need no slot offsets
+// E-vector slots are 4r .. 4r+3 and the lists need no slot offsets; rows of
+// one unknown with weight 1 store only that unknown
 void amr_maps_upload(HpData &H, const AmrSpaceHost &S, AmrMaps &M, hipStream_t s) {
   const HpSpaceHost &V = S.V;
   const int64_t nrows = V.row_base[S.ncells], N = S.N;
   M.N = N;
   M.nrows = nrows;
-  std::vector<int64_t> tptr((size_t)N + 1, 0);
-  for (int64_t q = 0; q < V.row_ptr[nrows]; ++q) tptr[V.col[q] + 1] += 1;
-  for (int64_t g = 0; g < N; ++g) tptr[g + 1] += tptr[g];
-  std::vector<int> trow((size_t)tptr[N]);
-  std::vector<double> tval((size_t)tptr[N]);
+  std::vector<int> rcol((size_t)nrows);
+  std::vector<int64_t> hptr(1, 0);
+  std::vector<int> hcol;
+  std::vector<double> hval;
+  std::vector<int64_t> tptr((size_t)N + 1, 0), wptr((size_t)N + 1, 0);
+  for (int64_t r = 0; r < nrows; ++r) {
+    const int64_t b = V.row_ptr[r], e = V.row_ptr[r + 1];
+    if (e - b == 1 && V.val[b] == 1.0) {
+      rcol[r] = V.col[b];
+      tptr[V.col[b] + 1] += 1;
+      continue;
+    }
+    rcol[r] = -1 - (int)(hptr.size() - 1);
+    for (int64_t q = b; q < e; ++q) {
+      hcol.push_back(V.col[q]);
+      hval.push_back(V.val[q]);
+      wptr[V.col[q] + 1] += 1;
+    }
+    hptr.push_back((int64_t)hcol.size());
+  }
+  for (int64_t g = 0; g < N; ++g) {
+    tptr[g + 1] += tptr[g];
+    wptr[g + 1] += wptr[g];
+  }
+  std::vector<int> trow((size_t)tptr[N]), wrow((size_t)wptr[N]);
+  std::vector<double> wval((size_t)wptr[N]);
   {
-    std::vector<int64_t> fill(tptr.begin(), tptr.end() - 1);
-    for (int64_t r = 0; r < nrows; ++r)
-      for (int64_t q = V.row_ptr[r]; q < V.row_ptr[r + 1]; ++q) {
-        const int64_t o = fill[V.col[q]]++;
-        trow[o] = (int)r;
-        tval[o] = V.val[q];
+    std::vector<int64_t> tf(tptr.begin(), tptr.end() - 1), wf(wptr.begin(), wptr.end() - 1);
+    for (int64_t r = 0; r < nrows; ++r) {
+      if (rcol[r] >= 0) {
+        trow[tf[rcol[r]]++] = (int)r;
+        continue;
       }
+      const int64_t h = -1 - (int64_t)rcol[r];
+      for (int64_t q = hptr[h]; q < hptr[h + 1]; ++q) {
+        const int64_t o = wf[hcol[q]]++;
+        wrow[o] = (int)r;
+        wval[o] = hval[q];
+      }
+    }
   }
   std::vector<int64_t> heavy;
   for (int64_t g = 0; g < N; ++g)
-    if (tptr[g + 1] - tptr[g] > AMR_LIGHT) heavy.push_back(g);
+    if ((tptr[g + 1] - tptr[g]) + (wptr[g + 1] - wptr[g]) > AMR_LIGHT) heavy.push_back(g);
   const int64_t nb = V.row_base[1] - V.row_base[0];
   std::vector<int> owner((size_t)N);
   for (int64_t g = 0; g < N; ++g) owner[g] = (int)(V.owner_cell[g] * nb + V.owner_local[g]);
-  M.row_ptr = H.upload(V.row_ptr, s);
-  M.col = H.upload(V.col, s);
-  M.val = H.upload(V.val, s);
+  M.rcol = H.upload(rcol, s);
+  M.hptr = H.upload(hptr, s);
+  M.hcol = H.upload(hcol, s);
+  M.hval = H.upload(hval, s);
   M.tptr = H.upload(tptr, s);
   M.trow = H.upload(trow, s);
-  M.tval = H.upload(tval, s);
+  M.wptr = H.upload(wptr, s);
+  M.wrow = H.upload(wrow, s);
+  M.wval = H.upload(wval, s);
   M.dir = H.upload(V.dirichlet, s);
   M.owner = H.upload(owner, s);
   M.nheavy = (int64_t)heavy.size();
