@@ -126,16 +126,7 @@ struct Krylov {
 // unknowns are -1; pressure: no Dirichlet unknowns).
 struct HpDevSpace {
   int64_t N = 0, nrows = 0;
-  int64_t *row_ptr = nullptr, *row_ev = nullptr;
-  int *col = nullptr, *row_nb = nullptr;
-  double *val = nullptr;
-  int64_t *tptr = nullptr, *tev = nullptr;
-  int *tnb = nullptr;
-  double *tval = nullptr;
-  // unknowns whose transposed list is longer than HP_SCATTER_LIGHT (summed
-  // by a wave each instead of a thread)
-  int64_t nheavy = 0;
-  int64_t *heavy = nullptr;
+  HpMaps m;  // rows and transposed lists (plain / weighted)
   uint8_t *dir = nullptr;
   int64_t *owner_ev = nullptr;
   int *owner_nb = nullptr;
@@ -1217,12 +1208,11 @@ float *hp_evp<float>(HpData &H, bool out) {
 
 template <typename T>
 void hp_gather_space(const HpDevSpace &d, int ncomp, const T *x, T *ev, hipStream_t s) {
-  hp_gather<T>(d.nrows, ncomp, d.row_ptr, d.col, d.val, d.row_ev, d.row_nb, x, d.N, ev, s);
+  hp_gather<T>(d.m, ncomp, x, ev, s);
 }
 template <typename T>
 void hp_scatter_space(const HpDevSpace &d, int ncomp, bool use_dir, const T *ev, const T *src, T *dst, hipStream_t s) {
-  hp_scatter<T>(d.N, ncomp, d.tptr, d.tev, d.tnb, d.tval, use_dir ? d.dir : nullptr, d.nheavy, d.heavy, ev, src, dst,
-                s);
+  hp_scatter<T>(d.m, ncomp, use_dir ? d.dir : nullptr, ev, src, dst, s);
 }
 
 // dst = op(src) on hp level l: mode of the cell kernels; velocity output
@@ -1830,67 +1820,91 @@ namespace {
 // stride ((k+1)^3 for the velocity)
 // interleave (with vector_comp): the three components of a cell-local node
 // are adjacent (slot 3 j + comp) instead of (k+1)^3 apart
+// device maps of an hp space: rows cell by cell at the cells' E-vector
+// offsets; vector spaces (velocity) keep the three components of a node side
+// by side (slot 3 j + comp); constrained spaces drop the Dirichlet columns
+// (their values do not enter the cells) and list no rows for Dirichlet
+// unknowns (the scatter writes those rows itself)
 void hp_upload(HpData &H, const HpSpaceHost &V, bool constrained, const std::vector<int64_t> &ev_off, bool vector_comp,
-               HpDevSpace &d, hipStream_t s, bool interleave = false) {
+               HpDevSpace &d, hipStream_t s) {
   const int64_t ncells = (int64_t)V.deg.size();
   d.N = V.N;
   d.nrows = V.row_base[ncells];
-  std::vector<int64_t> ptr(d.nrows + 1, 0), rev(d.nrows);
-  std::vector<int> col, rnb(d.nrows);
-  std::vector<double> val;
-  col.reserve(V.col.size());
-  val.reserve(V.val.size());
-  // transposed lists, counted per unknown
-  std::vector<int64_t> tcount(V.N + 1, 0);
+  HpMaps &m = d.m;
+  m.N = d.N;
+  m.nrows = d.nrows;
+  m.nb = vector_comp ? 1 : 0;
+  const int stride = vector_comp ? 3 : 1;
+  std::vector<int> rcol((size_t)d.nrows), rslot((size_t)d.nrows), hcol;
+  std::vector<int64_t> hptr(1, 0), tptr((size_t)V.N + 1, 0), wptr((size_t)V.N + 1, 0);
+  std::vector<double> hval;
   for (int64_t c = 0; c < ncells; ++c) {
     const int k = V.deg[c], nb = (k + 1) * (k + 1) * (k + 1);
     for (int j = 0; j < nb; ++j) {
       const int64_t r = V.row_base[c] + j;
-      rev[r] = ev_off[c] + (vector_comp && interleave ? 3 * j : j);
-      rnb[r] = vector_comp ? (interleave ? 1 : nb) : 0;
-      for (int64_t q = V.row_ptr[r]; q < V.row_ptr[r + 1]; ++q) {
+      MFS_REQUIRE(ev_off[c] + (int64_t)stride * j < (int64_t(1) << 31), MFS_EINVAL, "E-vector too long");
+      rslot[r] = (int)(ev_off[c] + (int64_t)stride * j);
+      const int64_t b = V.row_ptr[r], e = V.row_ptr[r + 1];
+      if (e - b == 1 && V.val[b] == 1.0 && !(constrained && V.dirichlet[V.col[b]])) {
+        rcol[r] = V.col[b];
+        tptr[V.col[b] + 1] += 1;
+        continue;
+      }
+      rcol[r] = -1 - (int)(hptr.size() - 1);
+      for (int64_t q = b; q < e; ++q) {
         const int g = V.col[q];
         if (constrained && V.dirichlet[g]) continue;
-        col.push_back(g);
-        val.push_back(V.val[q]);
-        tcount[g + 1] += 1;
+        hcol.push_back(g);
+        hval.push_back(V.val[q]);
+        wptr[g + 1] += 1;
       }
-      ptr[r + 1] = (int64_t)col.size();
+      hptr.push_back((int64_t)hcol.size());
     }
   }
-  for (int64_t g = 0; g < V.N; ++g) tcount[g + 1] += tcount[g];
-  std::vector<int64_t> tev(tcount[V.N]), fill(tcount.begin(), tcount.end() - 1);
-  std::vector<int> tnb(tcount[V.N]);
-  std::vector<double> tval(tcount[V.N]);
-  for (int64_t r = 0; r < d.nrows; ++r)
-    for (int64_t q = ptr[r]; q < ptr[r + 1]; ++q) {
-      const int64_t o = fill[col[q]]++;
-      tev[o] = rev[r];
-      tnb[o] = rnb[r];
-      tval[o] = val[q];
+  for (int64_t g = 0; g < V.N; ++g) {
+    tptr[g + 1] += tptr[g];
+    wptr[g + 1] += wptr[g];
+  }
+  std::vector<int> tslot((size_t)tptr[V.N]), wslot((size_t)wptr[V.N]);
+  std::vector<double> wval((size_t)wptr[V.N]);
+  {
+    std::vector<int64_t> tf(tptr.begin(), tptr.end() - 1), wf(wptr.begin(), wptr.end() - 1);
+    for (int64_t r = 0; r < d.nrows; ++r) {
+      if (rcol[r] >= 0) {
+        tslot[tf[rcol[r]]++] = rslot[r];
+        continue;
+      }
+      const int64_t h = -1 - (int64_t)rcol[r];
+      for (int64_t q = hptr[h]; q < hptr[h + 1]; ++q) {
+        const int64_t o = wf[hcol[q]]++;
+        wslot[o] = rslot[r];
+        wval[o] = hval[q];
+      }
     }
+  }
   std::vector<int64_t> heavy;
   for (int64_t g = 0; g < V.N; ++g)
-    if (tcount[g + 1] - tcount[g] > HP_SCATTER_LIGHT) heavy.push_back(g);
+    if (!(constrained && V.dirichlet[g]) && (tptr[g + 1] - tptr[g]) + (wptr[g + 1] - wptr[g]) > HP_SCATTER_LIGHT)
+      heavy.push_back(g);
   std::vector<int64_t> oev(V.N);
   std::vector<int> onb(V.N);
   for (int64_t g = 0; g < V.N; ++g) {
-    const int c = V.owner_cell[g], k = V.deg[c], nb = (k + 1) * (k + 1) * (k + 1);
-    oev[g] = (constrained && V.dirichlet[g]) ? -1
-                                              : ev_off[c] + (vector_comp && interleave ? 3 : 1) * V.owner_local[g];
-    onb[g] = vector_comp ? (interleave ? 1 : nb) : 0;
+    const int c = V.owner_cell[g];
+    oev[g] = (constrained && V.dirichlet[g]) ? -1 : ev_off[c] + (int64_t)stride * V.owner_local[g];
+    onb[g] = vector_comp ? 1 : 0;
   }
-  d.row_ptr = H.upload(ptr, s);
-  d.col = H.upload(col, s);
-  d.val = H.upload(val, s);
-  d.row_ev = H.upload(rev, s);
-  d.row_nb = H.upload(rnb, s);
-  d.tptr = H.upload(tcount, s);
-  d.tev = H.upload(tev, s);
-  d.tnb = H.upload(tnb, s);
-  d.tval = H.upload(tval, s);
-  d.nheavy = (int64_t)heavy.size();
-  d.heavy = heavy.empty() ? nullptr : H.upload(heavy, s);
+  m.rcol = H.upload(rcol, s);
+  m.rslot = H.upload(rslot, s);
+  m.hptr = H.upload(hptr, s);
+  m.hcol = H.upload(hcol, s);
+  m.hval = H.upload(hval, s);
+  m.tptr = H.upload(tptr, s);
+  m.tslot = H.upload(tslot, s);
+  m.wptr = H.upload(wptr, s);
+  m.wslot = H.upload(wslot, s);
+  m.wval = H.upload(wval, s);
+  m.nheavy = (int64_t)heavy.size();
+  m.heavy = heavy.empty() ? nullptr : H.upload(heavy, s);
   d.owner_ev = H.upload(oev, s);
   d.owner_nb = H.upload(onb, s);
   d.dir = constrained ? H.upload(V.dirichlet, s) : nullptr;
@@ -1994,7 +2008,7 @@ void hp_build(mfs_problem &P, const std::vector<int> &deg0, hipStream_t s) {
     HpLevel &L = H.lev[l];
     L.V.build(H.n, degs[l]);
     const auto off = ev_offsets(degs[l], 3, 0, &L.ev_size);
-    hp_upload(H, L.V, true, off, true, L.vd, s, true);
+    hp_upload(H, L.V, true, off, true, L.vd, s);
     L.off_u = H.upload(off, s);
     L.deg = H.upload(degs[l], s);
     for (int k = 2; k <= 6; ++k) {
@@ -2028,7 +2042,7 @@ void hp_build(mfs_problem &P, const std::vector<int> &deg0, hipStream_t s) {
     std::vector<int> d2(H.ncells, 2);
     H.V2.build(H.n, d2);
     const auto off = ev_offsets(d2, 3, 0, &H.ev2_size);
-    hp_upload(H, H.V2, true, off, true, H.v2d, s, true);
+    hp_upload(H, H.V2, true, off, true, H.v2d, s);
     H.off_u2 = H.upload(off, s);
     H.deg2 = H.upload(d2, s);
     std::vector<int64_t> perm(H.V2.N);

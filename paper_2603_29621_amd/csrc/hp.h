@@ -62,20 +62,37 @@ struct HpTransposed {
 };
 
 // ---------------------------------------------------------------- device kernels (hp_kernels.hip)
-// dst[comp*Nu + i] = dirichlet[i] ? (src ? src[..] : 0) : sum_r w_r ev[tev_r + comp*tnb_r]
-// Lists of up to HP_SCATTER_LIGHT entries are summed by one thread each; the
-// unknowns in heavy[0..nheavy) (exactly those with longer lists and no
-// Dirichlet flag) by one wave each, in a fixed order.
+// Device map between the unknowns (ncomp blocks of N) and the cell-local
+// rows of an E-vector.  A plain row (one unknown, weight 1) stores only its
+// unknown; weighted rows (interpolated nodes at degree jumps) have a CSR of
+// their own (-1 - h in rcol).  Row r's slots start at rslot[r], components nb
+// apart.  Per unknown the transposed lists name the slots of its plain rows,
+// then the slots of its weighted rows with the weights.
+struct HpMaps {
+  int64_t N = 0, nrows = 0;
+  int nb = 0;
+  const int *rcol = nullptr, *rslot = nullptr;
+  const int64_t *hptr = nullptr;
+  const int *hcol = nullptr;
+  const double *hval = nullptr;
+  const int64_t *tptr = nullptr;
+  const int *tslot = nullptr;
+  const int64_t *wptr = nullptr;
+  const int *wslot = nullptr;
+  const double *wval = nullptr;
+  int64_t nheavy = 0;  // unknowns with more than HP_SCATTER_LIGHT rows in all (no Dirichlet flag)
+  const int64_t *heavy = nullptr;
+};
+// dst[comp*N + i] = dirichlet[i] ? (src ? src[..] : 0) : sum over i's rows of w ev[slot + comp*nb]
+// Lists of up to HP_SCATTER_LIGHT rows are summed by one thread each, the
+// heavy unknowns by one wave each, in a fixed order.
 constexpr int HP_SCATTER_LIGHT = 16;
 template <typename T>
-void hp_scatter(int64_t N, int ncomp, const int64_t *tptr, const int64_t *tev, const int *tnb, const double *tval,
-                const uint8_t *dirichlet, int64_t nheavy, const int64_t *heavy, const T *ev, const T *src, T *dst,
+void hp_scatter(const HpMaps &M, int ncomp, const uint8_t *dirichlet, const T *ev, const T *src, T *dst,
                 hipStream_t s);
-// E-vector gather: ev[row_ev[r] + comp*row_nb[r]] = sum_j val_j x[comp*N + col_j]
-// over the rows r of the local->global map, comp < ncomp
+// E-vector gather: ev[rslot[r] + comp*nb] = sum over row r of w x[comp*N + col], comp < ncomp
 template <typename T>
-void hp_gather(int64_t nrows, int ncomp, const int64_t *row_ptr, const int *col, const double *val,
-               const int64_t *row_ev, const int *row_nb, const T *x, int64_t N, T *ev, hipStream_t s);
+void hp_gather(const HpMaps &M, int ncomp, const T *x, T *ev, hipStream_t s);
 // per cell c of the list: ev_f = (E (x) E (x) E) ev_c (transpose: ev_c = (E^T..) ev_f)
 // with E the 1D embedding from the coarse degree kc[c] to the fine degree
 // kf[c] (tables[kf][kc], MAXQ x MAXQ row-major [fine node][coarse node]),

@@ -14,64 +14,74 @@ unsigned grid_for(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<in
 
 // NC components at once: the map entries are read once
 template <typename T, int NC>
-__global__ void k_gather(int64_t nrows, const int64_t *row_ptr, const int *col, const double *val,
-                         const int64_t *row_ev, const int *row_nb, const T *x, int64_t N, T *ev) {
-  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < nrows; r += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t b = row_ptr[r], e = row_ptr[r + 1];
-    double s[NC] = {};
-    for (int64_t j = b; j < e; ++j) {
-      const double w = val[j];
-      const int64_t c = col[j];
+__global__ void k_gather(HpMaps M, const T *x, T *ev) {
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < M.nrows; r += (int64_t)gridDim.x * blockDim.x) {
+    const int c0 = M.rcol[r];
+    T out[NC];
+    if (c0 >= 0) {  // plain row
 #pragma unroll
-      for (int comp = 0; comp < NC; ++comp) s[comp] += w * (double)x[comp * N + c];
+      for (int comp = 0; comp < NC; ++comp) out[comp] = x[comp * M.N + c0];
+    } else {
+      const int64_t h = -1 - (int64_t)c0;
+      double s[NC] = {};
+      for (int64_t j = M.hptr[h]; j < M.hptr[h + 1]; ++j) {
+        const double w = M.hval[j];
+        const int64_t c = M.hcol[j];
+#pragma unroll
+        for (int comp = 0; comp < NC; ++comp) s[comp] += w * (double)x[comp * M.N + c];
+      }
+#pragma unroll
+      for (int comp = 0; comp < NC; ++comp) out[comp] = (T)s[comp];
     }
-    const int64_t base = row_ev[r];
-    const int nb = row_nb[r];
+    const int64_t base = M.rslot[r];
 #pragma unroll
-    for (int comp = 0; comp < NC; ++comp) ev[base + (int64_t)comp * nb] = (T)s[comp];
+    for (int comp = 0; comp < NC; ++comp) ev[base + (int64_t)comp * M.nb] = out[comp];
   }
 }
 
 template <typename T, int NC>
-__global__ void k_scatter(int64_t N, const int64_t *tptr, const int64_t *tev, const int *tnb, const double *tval,
-                          const uint8_t *dir, const T *ev, const T *src, T *dst) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+__global__ void k_scatter(HpMaps M, const uint8_t *dir, const T *ev, const T *src, T *dst) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < M.N; i += (int64_t)gridDim.x * blockDim.x) {
     if (dir != nullptr && dir[i]) {
 #pragma unroll
-      for (int comp = 0; comp < NC; ++comp) dst[comp * N + i] = src ? src[comp * N + i] : T(0);
+      for (int comp = 0; comp < NC; ++comp) dst[comp * M.N + i] = src ? src[comp * M.N + i] : T(0);
       continue;
     }
-    const int64_t b = tptr[i], e = tptr[i + 1];
-    if (e - b > HP_SCATTER_LIGHT) continue;  // summed by k_scatter_heavy
+    const int64_t b = M.tptr[i], e = M.tptr[i + 1], wb = M.wptr[i], we = M.wptr[i + 1];
+    if ((e - b) + (we - wb) > HP_SCATTER_LIGHT) continue;  // summed by k_scatter_heavy
     double s[NC] = {};
     for (int64_t j = b; j < e; ++j) {
-      const double w = tval[j];
-      const int64_t o = tev[j], nb = tnb[j];
+      const int64_t o = M.tslot[j];
 #pragma unroll
-      for (int comp = 0; comp < NC; ++comp) s[comp] += w * (double)ev[o + comp * nb];
+      for (int comp = 0; comp < NC; ++comp) s[comp] += (double)ev[o + comp * M.nb];
+    }
+    for (int64_t j = wb; j < we; ++j) {
+      const double w = M.wval[j];
+      const int64_t o = M.wslot[j];
+#pragma unroll
+      for (int comp = 0; comp < NC; ++comp) s[comp] += w * (double)ev[o + comp * M.nb];
     }
 #pragma unroll
-    for (int comp = 0; comp < NC; ++comp) dst[comp * N + i] = (T)s[comp];
+    for (int comp = 0; comp < NC; ++comp) dst[comp * M.N + i] = (T)s[comp];
   }
 }
 
-// one wave per long list: strided partial sums over the lanes, then a
-// butterfly over the wave (the same order on every call)
+// one wave per long list: strided partial sums over the lanes (plain rows,
+// then weighted rows), then a butterfly over the wave (the same order on
+// every call)
 template <typename T, int NC>
-__global__ void __launch_bounds__(HB) k_scatter_heavy(int64_t N, int64_t nheavy, const int64_t *heavy,
-                                                      const int64_t *tptr, const int64_t *tev, const int *tnb,
-                                                      const double *tval, const T *ev, T *dst) {
+__global__ void __launch_bounds__(HB) k_scatter_heavy(HpMaps M, const T *ev, T *dst) {
   const int lane = threadIdx.x & 63;
   const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  for (int64_t h = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6; h < nheavy; h += waves) {
-    const int64_t i = heavy[h];
-    const int64_t b = tptr[i], e = tptr[i + 1];
+  for (int64_t h = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6; h < M.nheavy; h += waves) {
+    const int64_t i = M.heavy[h];
+    const int64_t b = M.tptr[i], nu = M.tptr[i + 1] - b, wb = M.wptr[i], nw = M.wptr[i + 1] - wb;
     double s[NC] = {};
-    for (int64_t j = b + lane; j < e; j += 64) {
-      const double w = tval[j];
-      const int64_t o = tev[j], nb = tnb[j];
+    for (int64_t j = lane; j < nu + nw; j += 64) {
+      const double w = j < nu ? 1.0 : M.wval[wb + j - nu];
+      const int64_t o = j < nu ? M.tslot[b + j] : M.wslot[wb + j - nu];
 #pragma unroll
-      for (int comp = 0; comp < NC; ++comp) s[comp] += w * (double)ev[o + comp * nb];
+      for (int comp = 0; comp < NC; ++comp) s[comp] += w * (double)ev[o + comp * M.nb];
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1)
@@ -79,7 +89,7 @@ __global__ void __launch_bounds__(HB) k_scatter_heavy(int64_t N, int64_t nheavy,
       for (int comp = 0; comp < NC; ++comp) s[comp] += __shfl_xor(s[comp], off, 64);
     if (lane == 0)
 #pragma unroll
-      for (int comp = 0; comp < NC; ++comp) dst[comp * N + i] = (T)s[comp];
+      for (int comp = 0; comp < NC; ++comp) dst[comp * M.N + i] = (T)s[comp];
   }
 }
 
@@ -215,36 +225,27 @@ __global__ void k_colour_ext(const int *colour, int64_t N, int c0, int c1, int c
 }  // namespace
 
 template <typename T>
-void hp_gather(int64_t nrows, int ncomp, const int64_t *row_ptr, const int *col, const double *val,
-               const int64_t *row_ev, const int *row_nb, const T *x, int64_t N, T *ev, hipStream_t s) {
-  if (nrows == 0) return;
+void hp_gather(const HpMaps &M, int ncomp, const T *x, T *ev, hipStream_t s) {
+  if (M.nrows == 0) return;
   if (ncomp == 3)
-    hipLaunchKernelGGL((k_gather<T, 3>), dim3(grid_for(nrows)), dim3(HB), 0, s, nrows, row_ptr, col, val, row_ev,
-                       row_nb, x, N, ev);
+    hipLaunchKernelGGL((k_gather<T, 3>), dim3(grid_for(M.nrows)), dim3(HB), 0, s, M, x, ev);
   else
-    hipLaunchKernelGGL((k_gather<T, 1>), dim3(grid_for(nrows)), dim3(HB), 0, s, nrows, row_ptr, col, val, row_ev,
-                       row_nb, x, N, ev);
+    hipLaunchKernelGGL((k_gather<T, 1>), dim3(grid_for(M.nrows)), dim3(HB), 0, s, M, x, ev);
   MFS_HIP(hipGetLastError());
 }
 
 template <typename T>
-void hp_scatter(int64_t N, int ncomp, const int64_t *tptr, const int64_t *tev, const int *tnb, const double *tval,
-                const uint8_t *dirichlet, int64_t nheavy, const int64_t *heavy, const T *ev, const T *src, T *dst,
+void hp_scatter(const HpMaps &M, int ncomp, const uint8_t *dirichlet, const T *ev, const T *src, T *dst,
                 hipStream_t s) {
-  if (N == 0) return;
-  const unsigned hgrid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((nheavy + HB / 64 - 1) / (HB / 64), 65535 * 8));
+  if (M.N == 0) return;
+  const unsigned hgrid =
+      (unsigned)std::max<int64_t>(1, std::min<int64_t>((M.nheavy + HB / 64 - 1) / (HB / 64), 65535 * 8));
   if (ncomp == 3) {
-    hipLaunchKernelGGL((k_scatter<T, 3>), dim3(grid_for(N)), dim3(HB), 0, s, N, tptr, tev, tnb, tval, dirichlet, ev,
-                       src, dst);
-    if (nheavy > 0)
-      hipLaunchKernelGGL((k_scatter_heavy<T, 3>), dim3(hgrid), dim3(HB), 0, s, N, nheavy, heavy, tptr, tev, tnb, tval,
-                         ev, dst);
+    hipLaunchKernelGGL((k_scatter<T, 3>), dim3(grid_for(M.N)), dim3(HB), 0, s, M, dirichlet, ev, src, dst);
+    if (M.nheavy > 0) hipLaunchKernelGGL((k_scatter_heavy<T, 3>), dim3(hgrid), dim3(HB), 0, s, M, ev, dst);
   } else {
-    hipLaunchKernelGGL((k_scatter<T, 1>), dim3(grid_for(N)), dim3(HB), 0, s, N, tptr, tev, tnb, tval, dirichlet, ev,
-                       src, dst);
-    if (nheavy > 0)
-      hipLaunchKernelGGL((k_scatter_heavy<T, 1>), dim3(hgrid), dim3(HB), 0, s, N, nheavy, heavy, tptr, tev, tnb, tval,
-                         ev, dst);
+    hipLaunchKernelGGL((k_scatter<T, 1>), dim3(grid_for(M.N)), dim3(HB), 0, s, M, dirichlet, ev, src, dst);
+    if (M.nheavy > 0) hipLaunchKernelGGL((k_scatter_heavy<T, 1>), dim3(hgrid), dim3(HB), 0, s, M, ev, dst);
   }
   MFS_HIP(hipGetLastError());
 }
@@ -311,10 +312,8 @@ void colour_extract(const int *colour, int64_t N, const int cols[3], const doubl
 }
 
 #define HP_INST(T)                                                                                                   \
-  template void hp_gather<T>(int64_t, int, const int64_t *, const int *, const double *, const int64_t *,           \
-                             const int *, const T *, int64_t, T *, hipStream_t);                                     \
-  template void hp_scatter<T>(int64_t, int, const int64_t *, const int64_t *, const int *, const double *,          \
-                              const uint8_t *, int64_t, const int64_t *, const T *, const T *, T *, hipStream_t);    \
+  template void hp_gather<T>(const HpMaps &, int, const T *, T *, hipStream_t);                                     \
+  template void hp_scatter<T>(const HpMaps &, int, const uint8_t *, const T *, const T *, T *, hipStream_t);         \
   template void hp_embed<T>(int64_t, int, const int *, const int *, const double *, const int64_t *,                \
                             const int64_t *, const T *, T *, bool, hipStream_t);                                     \
   template void hp_inject<T>(int64_t, int, const int64_t *, const int *, const T *, T *, bool, hipStream_t);        \
