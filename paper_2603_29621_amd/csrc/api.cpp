@@ -1069,16 +1069,25 @@ void chebyshev(mfs_problem &P, int l, T *x, const T *b, bool zero_start, hipStre
   const double sigma = theta / delta;
   double rho_old = 1.0 / sigma;
   T *Ax = W.r[l], *d = W.d[l];
-  if (zero_start) {
-    cheb_update<T>(L.g, x, d, b, nullptr, invdiag<T>(L), T(0), (T)(1.0 / theta), true, s);
-  } else {
+  // x += d with d from the residual b - A x: fused into the brick kernels
+  // where the level has one
+  auto step = [&](T c1, T c2, bool first) {
+    if (use_specialised() && q2_face_elems(L.g) > 0 &&
+        launch_q2_cheb<T>(L.g, dev<T>(L).X, (T)P.nu, x, d, b, invdiag<T>(L), c1, c2, first, face<T>(L), s))
+      return;
+    if (use_specialised() && q1_face_elems(L.g) > 0 &&
+        launch_q1_cheb<T>(L.g, dev<T>(L).X, (T)P.nu, x, d, b, invdiag<T>(L), c1, c2, first, face<T>(L), s))
+      return;
     apply_A<T>(P, l, Ax, x, s);
-    cheb_update<T>(L.g, x, d, b, Ax, invdiag<T>(L), T(0), (T)(1.0 / theta), true, s);
-  }
+    cheb_update<T>(L.g, x, d, b, Ax, invdiag<T>(L), c1, c2, first, s);
+  };
+  if (zero_start)
+    cheb_update<T>(L.g, x, d, b, nullptr, invdiag<T>(L), T(0), (T)(1.0 / theta), true, s);
+  else
+    step(T(0), (T)(1.0 / theta), true);
   for (int it = 1; it < P.opts.cheb_degree; ++it) {
     const double rho = 1.0 / (2.0 * sigma - rho_old);
-    apply_A<T>(P, l, Ax, x, s);
-    cheb_update<T>(L.g, x, d, b, Ax, invdiag<T>(L), (T)(rho * rho_old), (T)(2.0 * rho / delta), false, s);
+    step((T)(rho * rho_old), (T)(2.0 * rho / delta), false);
     rho_old = rho;
   }
 }

@@ -116,12 +116,25 @@ int64_t q2_face_elems(const LevelGeom &g);
 template <typename T>
 bool launch_stokes_q2(const LevelGeom &g, const T *X, int mode, T nu, T *dst_u, T *dst_p, const T *src_u,
                       const T *src_p, T *face, hipStream_t s);
+// Q2_A with one Chebyshev step fused into its output phase: on every
+// non-Dirichlet row, r = inv (b - A x), d = c2 r (first) or c1 d + c2 r,
+// x += d; Dirichlet rows of x and d are left alone.  x is updated in place:
+// brick-interior nodes by the cell kernel (no other brick reads them, and its
+// own brick has them in LDS), brick-face nodes by the combine kernel.  The
+// same arithmetic as A followed by cheb_update.
+template <typename T>
+bool launch_q2_cheb(const LevelGeom &g, const T *X, T nu, T *x, T *d, const T *b, const T *inv, T c1, T c2,
+                    bool first, T *face, hipStream_t s);
 // specialised 3D degree-1 kernel for the velocity block: dst = A src
 // (Dirichlet rows = src); `face` is a scratch buffer of q1_face_elems(g)
 // elements.  Returns false when the level does not qualify.
 int64_t q1_face_elems(const LevelGeom &g);
 template <typename T>
 bool launch_laplace_q1(const LevelGeom &g, const T *X, T nu, T *dst, const T *src, T *face, hipStream_t s);
+// the same with one Chebyshev step fused into the output (as launch_q2_cheb)
+template <typename T>
+bool launch_q1_cheb(const LevelGeom &g, const T *X, T nu, T *x, T *d, const T *b, const T *inv, T c1, T c2,
+                    bool first, T *face, hipStream_t s);
 // diagonal of the scalar Laplacian block (FP64): diag[Nv]
 void launch_laplace_diagonal(const LevelGeom &g, const double *X, const double *tab, double nu, double *diag,
                              hipStream_t s);

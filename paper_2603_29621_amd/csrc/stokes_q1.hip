@@ -48,7 +48,21 @@ struct Args {
   const T *X, *src;
   T *dst, *face;
   T nu;
+  // fused Chebyshev step (CHEB kernels): dst is the iterate x (== src)
+  const T *cb, *cinv;
+  T *cd;
+  T c1, c2;
+  int cfirst;
 };
+
+// the Chebyshev step of one row: v = (A x)_j, xo = x_j
+template <typename T>
+__device__ __forceinline__ void cheb_row(const Args<T> &a, int64_t j, int64_t node, T v, T xo) {
+  const T r = a.cinv[node] * (a.cb[j] - v);
+  const T dn = a.cfirst ? a.c2 * r : a.c1 * a.cd[j] + a.c2 * r;
+  a.cd[j] = dn;
+  a.dst[j] = xo + dn;
+}
 
 // 2-point Gauss rule on [0, 1]: 1/2 -+ 1/(2 sqrt 3), weights 1/2
 template <typename T>
@@ -83,7 +97,8 @@ __device__ __forceinline__ float recip(float d) {
   return __builtin_fmaf(r, e, r);
 }
 
-template <typename T>
+// CHEB: A followed by one Chebyshev step (see launch_q1_cheb)
+template <typename T, bool CHEB>
 __global__ void __launch_bounds__(NT) laplace_q1_kernel(Args<T> a) {
   __shared__ T sU[3 * NVB];  // input velocity
   __shared__ T sO[3 * NVB];  // output velocity, one slice per component wave
@@ -247,9 +262,13 @@ __global__ void __launch_bounds__(NT) laplace_q1_kernel(Args<T> a) {
     const int gz = gz0 + lz;
     if (!st_ok || gz == 0 || gz >= a.nv2 - 1) continue;
     const T v = sO[cc * NVB + RXY * lz + lds_xy];
-    if (xy_int && lz > 0 && lz < VZ - 1)
-      a.dst[cc * a.Nv + zstride * gz + xy_off] = v;
-    else
+    if (xy_int && lz > 0 && lz < VZ - 1) {
+      const int64_t node = zstride * gz + xy_off;
+      if (CHEB)
+        cheb_row(a, cc * a.Nv + node, node, v, sU[cc * NVB + RXY * lz + lds_xy]);
+      else
+        a.dst[cc * a.Nv + node] = v;
+    } else
       fb[cc * NVF + PLANE * lz + tid] = v;
   }
 }
@@ -259,7 +278,7 @@ __global__ void __launch_bounds__(NT) laplace_q1_kernel(Args<T> a) {
 // face); an owned brick-face node sums the partials of every brick that
 // contains it in a fixed order (z, y, x brick index); Dirichlet rows get
 // dst = src.
-template <typename T>
+template <typename T, bool CHEB>
 __global__ void __launch_bounds__(256) q1_combine_kernel(Args<T> a) {
   const int b = blockIdx.x;
   const int bx = b % a.nbx, by = (b / a.nbx) % a.nby, bz = b / (a.nbx * a.nby);
@@ -271,8 +290,9 @@ __global__ void __launch_bounds__(256) q1_combine_kernel(Args<T> a) {
     if (gx >= a.nv0 || gy >= a.nv1 || gz >= a.nv2) continue;
     const int64_t i = gx + (int64_t)a.nv0 * (gy + (int64_t)a.nv1 * gz);
     if (gx == 0 || gy == 0 || gz == 0 || gx == a.nv0 - 1 || gy == a.nv1 - 1 || gz == a.nv2 - 1) {
+      if (!CHEB)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) a.dst[c * a.Nv + i] = a.src[c * a.Nv + i];
+        for (int c = 0; c < 3; ++c) a.dst[c * a.Nv + i] = a.src[c * a.Nv + i];
       continue;
     }
     if (lx != 0 && ly != 0 && lz != 0) continue;  // brick interior: written by the cell kernel
@@ -288,7 +308,12 @@ __global__ void __launch_bounds__(256) q1_combine_kernel(Args<T> a) {
           for (int c = 0; c < 3; ++c) acc[c] += fb[c * NVF + l];
         }
 #pragma unroll
-    for (int c = 0; c < 3; ++c) a.dst[c * a.Nv + i] = acc[c];
+    for (int c = 0; c < 3; ++c) {
+      if (CHEB)
+        cheb_row(a, c * a.Nv + i, i, acc[c], a.src[c * a.Nv + i]);
+      else
+        a.dst[c * a.Nv + i] = acc[c];
+    }
   }
 }
 
@@ -301,9 +326,9 @@ int64_t q1_face_elems(const LevelGeom &g) {
   return nb * q1::FACE_PER_BRICK;
 }
 
+namespace {
 template <typename T>
-bool launch_laplace_q1(const LevelGeom &g, const T *X, T nu, T *dst, const T *src, T *face, hipStream_t s) {
-  if (g.dim != 3 || g.k != 1 || face == nullptr) return false;
+q1::Args<T> q1_args(const LevelGeom &g, const T *X, T nu, T *dst, const T *src, T *face) {
   q1::Args<T> a{};
   a.n0 = g.n[0];
   a.n1 = g.n[1];
@@ -321,11 +346,41 @@ bool launch_laplace_q1(const LevelGeom &g, const T *X, T nu, T *dst, const T *sr
   a.dst = dst;
   a.face = face;
   a.nu = nu;
-  hipLaunchKernelGGL((q1::laplace_q1_kernel<T>), dim3(a.nblocks), dim3(q1::NT), 0, s, a);
-  hipLaunchKernelGGL((q1::q1_combine_kernel<T>), dim3(a.nblocks), dim3(256), 0, s, a);
+  return a;
+}
+}  // namespace
+
+template <typename T>
+bool launch_laplace_q1(const LevelGeom &g, const T *X, T nu, T *dst, const T *src, T *face, hipStream_t s) {
+  if (g.dim != 3 || g.k != 1 || face == nullptr) return false;
+  const q1::Args<T> a = q1_args<T>(g, X, nu, dst, src, face);
+  hipLaunchKernelGGL((q1::laplace_q1_kernel<T, false>), dim3(a.nblocks), dim3(q1::NT), 0, s, a);
+  hipLaunchKernelGGL((q1::q1_combine_kernel<T, false>), dim3(a.nblocks), dim3(256), 0, s, a);
   MFS_HIP(hipGetLastError());
   return true;
 }
+
+template <typename T>
+bool launch_q1_cheb(const LevelGeom &g, const T *X, T nu, T *x, T *d, const T *b, const T *inv, T c1, T c2,
+                    bool first, T *face, hipStream_t s) {
+  if (g.dim != 3 || g.k != 1 || face == nullptr) return false;
+  q1::Args<T> a = q1_args<T>(g, X, nu, x, x, face);
+  a.cb = b;
+  a.cinv = inv;
+  a.cd = d;
+  a.c1 = c1;
+  a.c2 = c2;
+  a.cfirst = first ? 1 : 0;
+  hipLaunchKernelGGL((q1::laplace_q1_kernel<T, true>), dim3(a.nblocks), dim3(q1::NT), 0, s, a);
+  hipLaunchKernelGGL((q1::q1_combine_kernel<T, true>), dim3(a.nblocks), dim3(256), 0, s, a);
+  MFS_HIP(hipGetLastError());
+  return true;
+}
+
+template bool launch_q1_cheb<double>(const LevelGeom &, const double *, double, double *, double *, const double *,
+                                     const double *, double, double, bool, double *, hipStream_t);
+template bool launch_q1_cheb<float>(const LevelGeom &, const float *, float, float *, float *, const float *,
+                                    const float *, float, float, bool, float *, hipStream_t);
 
 template bool launch_laplace_q1<double>(const LevelGeom &, const double *, double, double *, const double *, double *,
                                         hipStream_t);

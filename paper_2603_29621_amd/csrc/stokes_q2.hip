@@ -129,7 +129,24 @@ struct Args {
   T *dst_u, *dst_p;
   T *face;  // per brick: 3 x VX*VY*VZ velocity + PX*PY*PZ pressure partial sums (face nodes only)
   T nu;
+  // fused Chebyshev step (Q2_CHEB): dst_u is the iterate x (== src_u)
+  const T *cb, *cinv;
+  T *cd;
+  T c1, c2;
+  int cfirst;
 };
+
+// Q2_A with the Chebyshev step in the output phase (library-internal mode)
+constexpr int Q2_CHEB = 4;
+
+// the Chebyshev step of one row: v = (A x)_j, xo = x_j
+template <typename T>
+__device__ __forceinline__ void cheb_row(const Args<T> &a, int64_t j, int64_t node, T v, T xo) {
+  const T r = a.cinv[node] * (a.cb[j] - v);
+  const T dn = a.cfirst ? a.c2 * r : a.c1 * a.cd[j] + a.c2 * r;
+  a.cd[j] = dn;
+  a.dst_u[j] = xo + dn;
+}
 
 // Accumulation into the LDS output slices.  Each slice belongs to one wave.
 // FP64 uses the LDS atomic add.  FP32 uses plain read-modify-writes (the FP32
@@ -170,8 +187,9 @@ __device__ __forceinline__ float recip(float d) {
 template <typename T, int KM>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) stokes_q2_kernel(Args<T> a) {
   constexpr bool MASS = KM == Q2_MASSP;
-  constexpr bool PRES = KM != Q2_A;                      // pressure input
-  constexpr bool VIN = KM == Q2_STOKES || KM == Q2_A;    // velocity input
+  constexpr bool CHEB = KM == Q2_CHEB;
+  constexpr bool PRES = KM != Q2_A && !CHEB;                     // pressure input
+  constexpr bool VIN = KM == Q2_STOKES || KM == Q2_A || CHEB;    // velocity input
   constexpr bool POUT = KM == Q2_STOKES || MASS;         // pressure output
   constexpr bool VOUT = !MASS;                           // velocity output
   __shared__ T sU[3 * NVB];  // input velocity of the brick
@@ -464,9 +482,13 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) st
       const int gz = gz0 + lz;
       if (!st_ok || gz == 0 || gz >= a.nv2 - 1) continue;
       const T v = sO[c * NVB + RXY * lz + lds_xy];
-      if (xy_int && lz > 0 && lz < VZ - 1)
-        a.dst_u[c * a.Nv + zstride * gz + xy_off] = v;
-      else
+      if (xy_int && lz > 0 && lz < VZ - 1) {
+        const int64_t node = zstride * gz + xy_off;
+        if (CHEB)
+          cheb_row(a, c * a.Nv + node, node, v, sU[c * NVB + RXY * lz + lds_xy]);
+        else
+          a.dst_u[c * a.Nv + node] = v;
+      } else
         fb[c * NVF + PLANE * lz + tid] = v;
     }
   }
@@ -496,8 +518,9 @@ __global__ void __launch_bounds__(256) q2_combine_kernel(Args<T> a) {
     const int gy = (int)(r % a.nv1), gz = (int)(r / a.nv1);
     const bool dir = gx == 0 || gy == 0 || gz == 0 || gx == a.nv0 - 1 || gy == a.nv1 - 1 || gz == a.nv2 - 1;
     if (dir) {
+      if (KM != Q2_CHEB)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) a.dst_u[c * a.Nv + i] = KM != Q2_B ? a.src_u[c * a.Nv + i] : T(0);
+        for (int c = 0; c < 3; ++c) a.dst_u[c * a.Nv + i] = KM != Q2_B ? a.src_u[c * a.Nv + i] : T(0);
     } else if (gx % (2 * BX) == 0 || gy % (2 * BY) == 0 || gz % (2 * BZ) == 0) {
       int bxs[2], bys[2], bzs[2], nxs = 0, nys = 0, nzs = 0;
       auto bricks = [](int g, int B2, int nb, int *out, int &cnt) {
@@ -519,7 +542,12 @@ __global__ void __launch_bounds__(256) q2_combine_kernel(Args<T> a) {
             for (int c = 0; c < 3; ++c) acc[c] += fb[c * NVF + l];
           }
 #pragma unroll
-      for (int c = 0; c < 3; ++c) a.dst_u[c * a.Nv + i] = acc[c];
+      for (int c = 0; c < 3; ++c) {
+        if (KM == Q2_CHEB)
+          cheb_row(a, c * a.Nv + i, i, acc[c], a.src_u[c * a.Nv + i]);
+        else
+          a.dst_u[c * a.Nv + i] = acc[c];
+      }
     }
   }
   if (POUT) {
@@ -605,6 +633,47 @@ bool launch_stokes_q2(const LevelGeom &g, const T *X, int mode, T nu, T *dst_u, 
   MFS_HIP(hipGetLastError());
   return true;
 }
+
+template <typename T>
+bool launch_q2_cheb(const LevelGeom &g, const T *X, T nu, T *x, T *d, const T *b, const T *inv, T c1, T c2,
+                    bool first, T *face, hipStream_t s) {
+  if (g.dim != 3 || g.k != 2 || face == nullptr) return false;
+  q2::Args<T> a{};
+  a.n0 = g.n[0];
+  a.n1 = g.n[1];
+  a.n2 = g.n[2];
+  a.nv0 = g.nv[0];
+  a.nv1 = g.nv[1];
+  a.nv2 = g.nv[2];
+  a.np0 = g.n[0] + 1;
+  a.np1 = g.n[1] + 1;
+  a.nbx = (g.n[0] + q2::BX - 1) / q2::BX;
+  a.nby = (g.n[1] + q2::BY - 1) / q2::BY;
+  a.nbz = (g.n[2] + q2::BZ - 1) / q2::BZ;
+  a.nblocks = a.nbx * a.nby * a.nbz;
+  a.Nv = g.Nv;
+  a.X = X;
+  a.src_u = x;
+  a.dst_u = x;
+  a.face = face;
+  a.nu = nu;
+  a.cb = b;
+  a.cinv = inv;
+  a.cd = d;
+  a.c1 = c1;
+  a.c2 = c2;
+  a.cfirst = first ? 1 : 0;
+  const unsigned cgrid = (unsigned)((g.Nv + 255) / 256);
+  hipLaunchKernelGGL((q2::stokes_q2_kernel<T, q2::Q2_CHEB>), dim3(a.nblocks), dim3(q2::NT), 0, s, a);
+  hipLaunchKernelGGL((q2::q2_combine_kernel<T, q2::Q2_CHEB>), dim3(cgrid), dim3(256), 0, s, a);
+  MFS_HIP(hipGetLastError());
+  return true;
+}
+
+template bool launch_q2_cheb<double>(const LevelGeom &, const double *, double, double *, double *, const double *,
+                                     const double *, double, double, bool, double *, hipStream_t);
+template bool launch_q2_cheb<float>(const LevelGeom &, const float *, float, float *, float *, const float *,
+                                    const float *, float, float, bool, float *, hipStream_t);
 
 template bool launch_stokes_q2<double>(const LevelGeom &, const double *, int, double, double *, double *,
                                        const double *, const double *, double *, hipStream_t);

@@ -302,6 +302,41 @@ def test_vcycle_and_block_preconditioner_fp64(dim, n, k, noise):
         mfs.mfs_destroy(h)
 
 
+@pytest.mark.parametrize("n,cheb_degree", [([20, 12, 6], 3), ([16, 8, 4], 5)])
+def test_vcycle_several_bricks(n, cheb_degree):
+    """3D Q2 V-cycle on meshes of several bricks per direction with a ragged
+    brick tail: the Chebyshev steps of the degree-2 and degree-1 levels run
+    fused into the brick kernels (iterate updated in place, face nodes in the
+    combine), in FP64 and FP32.  lambda_max by a sparse eigensolver, set on
+    both sides."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as sla
+
+    dim, k, nu = 3, 2, 1.1
+    h, X = _setup(dim, n, k, 0.2, nu, mg_levels=1, cheb_degree=cheb_degree)
+    try:
+        H = mg.Hierarchy(dim, n, X, k, nu, cheb_degree=cheb_degree)
+        assert mfs.mfs_n_levels(h) == len(H.spaces)
+        for l in range(len(H.spaces) - 1):
+            free = ~H.fixed[l]
+            d = sp.diags(np.sqrt(H.Dinv[l][free]))
+            B = d @ H.A[l][free][:, free] @ d
+            H.lam[l] = 1.2 * float(sla.eigsh(B, k=1, which="LA", tol=1e-8)[0][0])
+            mfs.mfs_set_lambda(h, l, H.lam[l])
+        nvel = dim * H.spaces[0].Nv
+        for seed in (3, 4):
+            b = inputs.uniform_vector(nvel, seed)
+            ref = H.vcycle(b)
+            out = torch.empty(nvel, dtype=torch.float64, device="cuda")
+            mfs.mfs_vcycle(h, mfs.MFS_FP64, out, cuda(b))
+            assert relerr(host(out), ref) <= 1e-11
+            out32 = torch.empty(nvel, dtype=torch.float32, device="cuda")
+            mfs.mfs_vcycle(h, mfs.MFS_FP32, out32, cuda(b, torch.float32))
+            assert relerr(host(out32), ref) <= 1e-4
+    finally:
+        mfs.mfs_destroy(h)
+
+
 # ------------------------------------------------------------------ solves
 def _ms_rhs_gpu(h, dim, n, k, S, nu):
     nq = (k + 1) ** dim
