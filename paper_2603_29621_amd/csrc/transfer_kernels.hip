@@ -76,6 +76,55 @@ __global__ void k_prolongate_add(TransferArgs a, T *dst, const T *src) {
   }
 }
 
+// 3D fast path of the prolongation for a compile-time coarse degree KC and
+// fine span F: the 1D weights of the thread's node are picked out of the
+// embedding table by uniform (scalar) loads and per-lane selects, and the
+// (KC+1)^3 coarse values are gathered with no branches (weights of the
+// constrained coarse boundary nodes are zero; every index stays in the coarse
+// grid).  FP32 vectors are interpolated in FP32.
+template <typename T, int KC, int F>
+__global__ void __launch_bounds__(256) k_prolongate_add3(TransferArgs a, T *dst, const T *src) {
+  const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (f >= a.Nf) return;
+  const int g[3] = {(int)(f % a.nf[0]), (int)((f / a.nf[0]) % a.nf[1]), (int)(f / ((int64_t)a.nf[0] * a.nf[1]))};
+  bool fine_bnd = false;
+  int C[3];
+  T w[3][KC + 1], wm[3][KC + 1];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    fine_bnd = fine_bnd || g[d] == 0 || g[d] == a.nf[d] - 1;
+    C[d] = g[d] / F;
+    if (C[d] >= a.nc[d]) C[d] = a.nc[d] - 1;
+    const int i = g[d] - F * C[d];
+#pragma unroll
+    for (int j = 0; j <= KC; ++j) {
+      T e = 0;
+#pragma unroll
+      for (int ii = 0; ii <= F; ++ii) e = ii == i ? (T)a.E[ii * MAXQ + j] : e;
+      const int cn = C[d] * KC + j;
+      w[d][j] = e;
+      wm[d][j] = (cn == 0 || cn == a.ncn[d] - 1) ? T(0) : e;
+    }
+  }
+  const int64_t sy = a.ncn[0], sz = (int64_t)a.ncn[0] * a.ncn[1];
+  const int64_t cbase = (int64_t)C[0] * KC + sy * C[1] * KC + sz * C[2] * KC;
+  for (int comp = 0; comp < a.ncu + a.ncp; ++comp) {
+    const bool con = comp < a.ncu;
+    if (con && fine_bnd) continue;
+    const T *s = src + comp * a.Nc + cbase;
+    T acc = 0;
+#pragma unroll
+    for (int j2 = 0; j2 <= KC; ++j2)
+#pragma unroll
+      for (int j1 = 0; j1 <= KC; ++j1) {
+        const T w21 = con ? wm[2][j2] * wm[1][j1] : w[2][j2] * w[1][j1];
+#pragma unroll
+        for (int j0 = 0; j0 <= KC; ++j0) acc += w21 * (con ? wm[0][j0] : w[0][j0]) * s[j0 + sy * j1 + sz * j2];
+      }
+    dst[comp * a.Nf + f] += acc;
+  }
+}
+
 // per direction: list of (fine index, coefficient) contributing to coarse node gc
 // (con: skip the fine Dirichlet nodes, whose rows of P are zero)
 __device__ __forceinline__ int restrict_list(const TransferArgs &a, int d, int gc, bool con, int *fi, double *cf) {
@@ -179,6 +228,53 @@ __global__ void k_restrict_pass(TransferArgs a, int d, int ni0, int ni1, int ni2
   }
 }
 
+// the same pass for a compile-time coarse degree KC and fine span F: the at
+// most 2F+1 fine nodes of the (one or two) coarse cells containing the
+// output node, with their weights picked out of the embedding table once per
+// thread by uniform loads and per-lane selects
+template <typename T, int KC, int F>
+__global__ void __launch_bounds__(256) k_restrict_pass3(TransferArgs a, int d, int ni0, int ni1, int ni2, int no0,
+                                                        int no1, int no2, int ncomp, int64_t in_stride,
+                                                        int64_t out_stride, const T *in, T *out) {
+  const int64_t nout = (int64_t)no0 * no1 * no2;
+  const int nc = a.nc[d], nf = a.nf[d], ncn = a.ncn[d];
+  for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < nout; o += (int64_t)gridDim.x * blockDim.x) {
+    const int o0 = (int)(o % no0), o1 = (int)((o / no0) % no1), o2 = (int)(o / ((int64_t)no0 * no1));
+    const int j = d == 0 ? o0 : (d == 1 ? o1 : o2);
+    const int64_t sd = d == 0 ? 1 : (d == 1 ? (int64_t)ni0 : (int64_t)ni0 * ni1);
+    const int64_t base = (d == 0 ? 0 : o0) + (int64_t)ni0 * ((d == 1 ? 0 : o1) + (int64_t)ni1 * (d == 2 ? 0 : o2));
+    const bool cbnd = j == 0 || j == ncn - 1;
+    const int C0 = (j % KC == 0 && j > 0) ? j / KC - 1 : j / KC;
+    const int C1 = j / KC < nc ? j / KC : nc - 1;
+    const int f0 = F * C0, f1 = F * (C1 + 1);
+    T w[2 * F + 1], wm[2 * F + 1];
+#pragma unroll
+    for (int t = 0; t <= 2 * F; ++t) {
+      const int f = f0 + t;
+      const int own = f / F < nc ? f / F : nc - 1;
+      const int jl = j - KC * own, il = f - F * own;
+      T e = 0;
+#pragma unroll
+      for (int ii = 0; ii <= F; ++ii)
+#pragma unroll
+        for (int jj = 0; jj <= KC; ++jj) e = (ii == il && jj == jl) ? (T)a.E[ii * MAXQ + jj] : e;
+      const bool in_range = f <= f1;
+      w[t] = in_range ? e : T(0);
+      wm[t] = (in_range && !cbnd && f != 0 && f != nf - 1) ? e : T(0);
+    }
+    const int nt = f1 - f0;  // < 2F + 1
+    for (int comp = 0; comp < ncomp; ++comp) {
+      const bool con = comp < a.ncu;
+      const T *s = in + comp * in_stride + base + sd * f0;
+      T acc = 0;
+#pragma unroll
+      for (int t = 0; t <= 2 * F; ++t)
+        if (t <= nt) acc += (con ? wm[t] : w[t]) * s[sd * t];
+      out[comp * out_stride + o] = acc;
+    }
+  }
+}
+
 static TransferArgs make_targs(const LevelGeom &fine, const LevelGeom &coarse, bool h, const double *emb_host,
                                int ncp) {
   TransferArgs a{};
@@ -203,8 +299,17 @@ template <typename T>
 void launch_prolongate_add(const LevelGeom &fine, const LevelGeom &coarse, bool h, const double *emb, T *dst_fine,
                            const T *src_coarse, hipStream_t s, int ncp) {
   const TransferArgs a = make_targs(fine, coarse, h, emb, ncp);
-  hipLaunchKernelGGL(k_prolongate_add<T>, dim3((unsigned)((fine.Nv + 255) / 256)), dim3(256), 0, s, a, dst_fine,
-                     src_coarse);
+  const dim3 grid((unsigned)((fine.Nv + 255) / 256)), block(256);
+  if (fine.dim == 3 && a.kc == 1 && a.F == 2)
+    hipLaunchKernelGGL((k_prolongate_add3<T, 1, 2>), grid, block, 0, s, a, dst_fine, src_coarse);
+  else if (fine.dim == 3 && a.kc == 2 && a.F == 4)
+    hipLaunchKernelGGL((k_prolongate_add3<T, 2, 4>), grid, block, 0, s, a, dst_fine, src_coarse);
+  else if (fine.dim == 3 && a.kc == 2 && a.F == 3)
+    hipLaunchKernelGGL((k_prolongate_add3<T, 2, 3>), grid, block, 0, s, a, dst_fine, src_coarse);
+  else if (fine.dim == 3 && a.kc == 3 && a.F == 4)
+    hipLaunchKernelGGL((k_prolongate_add3<T, 3, 4>), grid, block, 0, s, a, dst_fine, src_coarse);
+  else
+    hipLaunchKernelGGL(k_prolongate_add<T>, grid, block, 0, s, a, dst_fine, src_coarse);
   MFS_HIP(hipGetLastError());
 }
 template <typename T>
@@ -230,8 +335,18 @@ void launch_restrict(const LevelGeom &fine, const LevelGeom &coarse, bool h, con
     T *out = last ? dst_coarse : bufs[d & 1];
     const int64_t out_stride = last ? coarse.Nv : nout;
     const unsigned grid = (unsigned)std::min<int64_t>((nout + 255) / 256, 65535);
-    hipLaunchKernelGGL(k_restrict_pass<T>, dim3(grid), dim3(256), 0, s, a, d, ext[0], ext[1], ext[2], oext[0],
-                       oext[1], oext[2], ncomp, in_stride, out_stride, in, out);
+#define RP_ARGS a, d, ext[0], ext[1], ext[2], oext[0], oext[1], oext[2], ncomp, in_stride, out_stride, in, out
+    if (fine.dim == 3 && a.kc == 1 && a.F == 2)
+      hipLaunchKernelGGL((k_restrict_pass3<T, 1, 2>), dim3(grid), dim3(256), 0, s, RP_ARGS);
+    else if (fine.dim == 3 && a.kc == 2 && a.F == 4)
+      hipLaunchKernelGGL((k_restrict_pass3<T, 2, 4>), dim3(grid), dim3(256), 0, s, RP_ARGS);
+    else if (fine.dim == 3 && a.kc == 2 && a.F == 3)
+      hipLaunchKernelGGL((k_restrict_pass3<T, 2, 3>), dim3(grid), dim3(256), 0, s, RP_ARGS);
+    else if (fine.dim == 3 && a.kc == 3 && a.F == 4)
+      hipLaunchKernelGGL((k_restrict_pass3<T, 3, 4>), dim3(grid), dim3(256), 0, s, RP_ARGS);
+    else
+      hipLaunchKernelGGL(k_restrict_pass<T>, dim3(grid), dim3(256), 0, s, RP_ARGS);
+#undef RP_ARGS
     MFS_HIP(hipGetLastError());
     in = out;
     in_stride = nout;

@@ -251,6 +251,35 @@ def test_levels_transfers_and_lambda(dim, n, k, noise):
         mfs.mfs_destroy(h)
 
 
+@pytest.mark.parametrize("n,k", [([6, 4, 4], 2), ([4, 2, 4], 3), ([2, 2, 2], 4), ([18, 10, 6], 2)])
+def test_transfers_3d_every_level(n, k):
+    """3D prolongation and restriction on every level pair (p-transfers from
+    degree k down to 1, then degree-1 h-transfers) in FP64 and FP32 against
+    the oracle's transfer matrices; FP32 inputs are rounded to FP32 first so
+    the reference sees the same values."""
+    dim, nu = 3, 1.0
+    h, X = _setup(dim, n, k, 0.2, nu, mg_levels=1)
+    try:
+        H = mg.Hierarchy(dim, n, X, k, nu)
+        assert mfs.mfs_n_levels(h) == len(H.spaces)
+        for l in range(len(H.spaces) - 1):
+            Sf, Sc = H.spaces[l], H.spaces[l + 1]
+            for prec, dt, tol in ((mfs.MFS_FP64, torch.float64, 1e-13), (mfs.MFS_FP32, torch.float32, 1e-5)):
+                xc = inputs.uniform_vector(dim * Sc.Nv, 20 + l)
+                xf = inputs.uniform_vector(dim * Sf.Nv, 40 + l)
+                if dt == torch.float32:
+                    xc = xc.astype(np.float32).astype(np.float64)
+                    xf = xf.astype(np.float32).astype(np.float64)
+                y = cuda(xf, dt)
+                mfs.mfs_prolongate_add(h, prec, l, y, cuda(xc, dt))
+                assert relerr(host(y), xf + H.P[l] @ xc) <= tol, (l, prec)
+                r = torch.empty(dim * Sc.Nv, dtype=dt, device="cuda")
+                mfs.mfs_restrict(h, prec, l, r, cuda(xf, dt))
+                assert relerr(host(r), H.P[l].T @ xf) <= tol, (l, prec)
+    finally:
+        mfs.mfs_destroy(h)
+
+
 @pytest.mark.parametrize("n,noise", [([12, 10, 6], 0.2), ([16, 8, 4], 0.1), ([2, 2, 2], 0.2)])
 def test_velocity_block_on_every_level(n, noise):
     """A on every level of a 3D Q2/Q1 hierarchy (degree 2, then degree 1,
