@@ -1,7 +1,9 @@
 // Host construction of the conforming Q_k space on a locally refined mesh:
 // unknown numbering, hanging-node constraints and the cell-local row maps.
 #include <algorithm>
+#include <array>
 #include <cmath>
+#include <thread>
 #include <unordered_map>
 #include <utility>
 
@@ -11,15 +13,49 @@ namespace mfs {
 
 namespace {
 
-// stable LSD radix sort of 64-bit words by their upper 32 bits
+// host threads for a loop of n iterations (at least 64k iterations each)
+int threads_for(int64_t n) {
+  const int64_t hw = std::max<int64_t>(1, std::min<int64_t>(std::thread::hardware_concurrency(), 16));
+  return (int)std::max<int64_t>(1, std::min<int64_t>(hw, n / 65536));
+}
+
+// f(t, lo, hi) on nt threads over the contiguous chunks of [0, n); f must not throw
+template <typename F>
+void chunks(int nt, int64_t n, F &&f) {
+  if (nt <= 1) {
+    f(0, int64_t(0), n);
+    return;
+  }
+  std::vector<std::thread> th;
+  for (int t = 0; t < nt; ++t) th.emplace_back([&, t] { f(t, n * t / nt, n * (t + 1) / nt); });
+  for (auto &x : th) x.join();
+}
+
+// stable LSD radix sort of 64-bit words by their upper 32 bits: per pass,
+// per-chunk digit counts, then every chunk scatters its words in order to its
+// own offsets, so the result is the sequential one
 void radix_sort_hi32(std::vector<uint64_t> &a) {
+  const int64_t n = (int64_t)a.size();
+  const int nt = threads_for(n);
   std::vector<uint64_t> tmp(a.size());
+  std::vector<std::array<int64_t, 256>> cnt((size_t)nt);
   for (int pass = 0; pass < 4; ++pass) {
     const int sh = 32 + 8 * pass;
-    size_t cnt[257] = {};
-    for (uint64_t v : a) cnt[((v >> sh) & 255) + 1] += 1;
-    for (int b = 0; b < 256; ++b) cnt[b + 1] += cnt[b];
-    for (uint64_t v : a) tmp[cnt[(v >> sh) & 255]++] = v;
+    chunks(nt, n, [&](int t, int64_t lo, int64_t hi) {
+      cnt[t].fill(0);
+      for (int64_t i = lo; i < hi; ++i) cnt[t][(a[i] >> sh) & 255] += 1;
+    });
+    int64_t run = 0;
+    for (int b = 0; b < 256; ++b)
+      for (int t = 0; t < nt; ++t) {
+        const int64_t c = cnt[t][b];
+        cnt[t][b] = run;
+        run += c;
+      }
+    chunks(nt, n, [&](int t, int64_t lo, int64_t hi) {
+      std::array<int64_t, 256> &off = cnt[t];
+      for (int64_t i = lo; i < hi; ++i) tmp[off[(a[i] >> sh) & 255]++] = a[i];
+    });
     a.swap(tmp);
   }
 }
@@ -77,28 +113,46 @@ void AmrSpaceHost::build(int n_, int L_, int64_t ncells_, const int *level_, con
   // positions of every cell-local node, sorted by position (stable in the slot)
   auto origin = [&](int64_t c, int a) { return (int64_t)idx[3 * c + a] * k << (L - level[c]); };
   std::vector<uint64_t> ks((size_t)(ncells * nb));
-  for (int64_t c = 0; c < ncells; ++c) {
-    const int64_t u = int64_t(1) << (L - level[c]);
-    const int64_t o0 = origin(c, 0), o1 = origin(c, 1), o2 = origin(c, 2);
-    for (int t = 0; t < nb; ++t) {
-      const int64_t p0 = o0 + (t % nb1) * u, p1 = o1 + ((t / nb1) % nb1) * u, p2 = o2 + (t / (nb1 * nb1)) * u;
-      const uint64_t key = (uint64_t)(p0 + R1 * (p1 + R1 * p2));
-      ks[c * nb + t] = (key << 32) | (uint64_t)(c * nb + t);
+  const int ntc = threads_for(ncells);
+  chunks(ntc, ncells, [&](int, int64_t c0, int64_t c1) {
+    for (int64_t c = c0; c < c1; ++c) {
+      const int64_t u = int64_t(1) << (L - level[c]);
+      const int64_t o0 = origin(c, 0), o1 = origin(c, 1), o2 = origin(c, 2);
+      for (int t = 0; t < nb; ++t) {
+        const int64_t p0 = o0 + (t % nb1) * u, p1 = o1 + ((t / nb1) % nb1) * u, p2 = o2 + (t / (nb1 * nb1)) * u;
+        const uint64_t key = (uint64_t)(p0 + R1 * (p1 + R1 * p2));
+        ks[c * nb + t] = (key << 32) | (uint64_t)(c * nb + t);
+      }
     }
-  }
+  });
   radix_sort_hi32(ks);
+  // distinct positions in sorted order: a new one starts where the key changes
+  const int64_t nks = (int64_t)ks.size();
+  const int ntk = threads_for(nks);
+  std::vector<int64_t> starts((size_t)ntk + 1, 0);
+  auto is_new = [&](int64_t i) { return i == 0 || (ks[i] >> 32) != (ks[i - 1] >> 32); };
+  chunks(ntk, nks, [&](int t, int64_t lo, int64_t hi) {
+    int64_t m = 0;
+    for (int64_t i = lo; i < hi; ++i) m += is_new(i);
+    starts[t + 1] = m;
+  });
+  for (int t = 0; t < ntk; ++t) starts[t + 1] += starts[t];
+  const int64_t Nraw = starts[ntk];
   std::vector<int> raw_of_slot((size_t)(ncells * nb));
-  std::vector<int64_t> raw_key, raw_first;  // per raw position: key and first slot
-  for (size_t i = 0; i < ks.size(); ++i) {
-    const uint64_t key = ks[i] >> 32;
-    if (raw_key.empty() || (uint64_t)raw_key.back() != key) {
-      raw_key.push_back((int64_t)key);
-      raw_first.push_back((int64_t)(ks[i] & 0xffffffffu));
+  std::vector<int64_t> raw_key((size_t)Nraw), raw_first((size_t)Nraw);  // per position: key, first slot
+  chunks(ntk, nks, [&](int t, int64_t lo, int64_t hi) {
+    int64_t r = starts[t] - 1;
+    for (int64_t i = lo; i < hi; ++i) {
+      const int64_t slot = (int64_t)(ks[i] & 0xffffffffu);
+      if (is_new(i)) {
+        ++r;
+        raw_key[r] = (int64_t)(ks[i] >> 32);
+        raw_first[r] = slot;
+      }
+      raw_of_slot[slot] = (int)r;
     }
-    raw_of_slot[ks[i] & 0xffffffffu] = (int)(raw_key.size() - 1);
-  }
+  });
   std::vector<uint64_t>().swap(ks);
-  const int64_t Nraw = (int64_t)raw_key.size();
   // leaf ids of the levels that can hold masters (all but the finest)
   std::vector<std::vector<int>> cell_at(L);
   for (int l = 0; l < L; ++l) cell_at[l].assign((size_t)(((int64_t)n << l) * ((int64_t)n << l) * ((int64_t)n << l)), -1);
@@ -110,7 +164,9 @@ void AmrSpaceHost::build(int n_, int L_, int64_t ncells_, const int *level_, con
   // hanging positions: the coarsest leaf whose closed box holds the position
   // without it being one of the leaf's nodes
   std::vector<int> master((size_t)Nraw, -1);
-  for (int64_t r = 0; r < Nraw; ++r) {
+  const int ntr = threads_for(Nraw);
+  chunks(ntr, Nraw, [&](int, int64_t r0, int64_t r1) {
+  for (int64_t r = r0; r < r1; ++r) {
     const int64_t p[3] = {raw_key[r] % R1, (raw_key[r] / R1) % R1, raw_key[r] / (R1 * R1)};
     for (int l = 0; l < L && master[r] < 0; ++l) {
       const int64_t u = int64_t(1) << (L - l), s = k * u, m = (int64_t)n << l;
@@ -128,30 +184,45 @@ void AmrSpaceHost::build(int n_, int L_, int64_t ncells_, const int *level_, con
           }
     }
   }
+  });
   std::vector<std::vector<int>>().swap(cell_at);
   // unknowns
   std::vector<int> true_of((size_t)Nraw, -1);
-  N = 0;
-  for (int64_t r = 0; r < Nraw; ++r)
-    if (master[r] < 0) true_of[r] = (int)N++;
+  {
+    std::vector<int64_t> base((size_t)ntr + 1, 0);
+    chunks(ntr, Nraw, [&](int t, int64_t r0, int64_t r1) {
+      int64_t m = 0;
+      for (int64_t r = r0; r < r1; ++r) m += master[r] < 0;
+      base[t + 1] = m;
+    });
+    for (int t = 0; t < ntr; ++t) base[t + 1] += base[t];
+    N = base[ntr];
+    chunks(ntr, Nraw, [&](int t, int64_t r0, int64_t r1) {
+      int64_t g = base[t];
+      for (int64_t r = r0; r < r1; ++r)
+        if (master[r] < 0) true_of[r] = (int)g++;
+    });
+  }
   nhanging = Nraw - N;
   tpos.resize((size_t)(3 * N));
   V.dirichlet.assign((size_t)N, 0);
   V.owner_cell.resize((size_t)N);
   V.owner_local.resize((size_t)N);
-  for (int64_t r = 0; r < Nraw; ++r) {
-    const int g = true_of[r];
-    if (g < 0) continue;
-    const int64_t p[3] = {raw_key[r] % R1, (raw_key[r] / R1) % R1, raw_key[r] / (R1 * R1)};
-    bool bnd = false;
-    for (int a = 0; a < 3; ++a) {
-      tpos[3 * g + a] = p[a];
-      bnd = bnd || p[a] == 0 || p[a] == R;
+  chunks(ntr, Nraw, [&](int, int64_t r0, int64_t r1) {
+    for (int64_t r = r0; r < r1; ++r) {
+      const int g = true_of[r];
+      if (g < 0) continue;
+      const int64_t p[3] = {raw_key[r] % R1, (raw_key[r] / R1) % R1, raw_key[r] / (R1 * R1)};
+      bool bnd = false;
+      for (int a = 0; a < 3; ++a) {
+        tpos[3 * g + a] = p[a];
+        bnd = bnd || p[a] == 0 || p[a] == R;
+      }
+      V.dirichlet[g] = bnd ? 1 : 0;
+      V.owner_cell[g] = (int)(raw_first[r] / nb);
+      V.owner_local[g] = (int)(raw_first[r] % nb);
     }
-    V.dirichlet[g] = bnd ? 1 : 0;
-    V.owner_cell[g] = (int)(raw_first[r] / nb);
-    V.owner_local[g] = (int)(raw_first[r] % nb);
-  }
+  });
   // expansions of the hanging positions, masters' levels ascending (a hanging
   // master of a level-l leaf hangs on a coarser leaf, so it comes first)
   std::vector<int64_t> hang;
@@ -204,29 +275,44 @@ void AmrSpaceHost::build(int n_, int L_, int64_t ncells_, const int *level_, con
   V.deg.assign((size_t)ncells, k);
   V.N = N;
   V.row_base.resize((size_t)ncells + 1);
-  V.row_ptr.assign(1, 0);
-  V.row_ptr.reserve((size_t)(ncells * nb + 1));
-  V.col.clear();
-  V.val.clear();
-  V.col.reserve((size_t)(ncells * nb));
-  V.val.reserve((size_t)(ncells * nb));
-  for (int64_t c = 0; c < ncells; ++c) {
-    V.row_base[c] = c * nb;
-    for (int t = 0; t < nb; ++t) {
-      const int rs = raw_of_slot[c * nb + t];
-      if (true_of[rs] >= 0) {
-        V.col.push_back(true_of[rs]);
-        V.val.push_back(1.0);
-      } else {
-        const int64_t q = hslot[rs];
-        for (int64_t e = hptr[q]; e < hptr[q + 1]; ++e) {
-          V.col.push_back(hcol[e]);
-          V.val.push_back(hval[e]);
+  V.row_ptr.assign((size_t)(ncells * nb + 1), 0);
+  auto row_len = [&](int64_t slot) -> int64_t {
+    const int rs = raw_of_slot[slot];
+    if (true_of[rs] >= 0) return 1;
+    const int64_t q = hslot[rs];
+    return hptr[q + 1] - hptr[q];
+  };
+  // entries per chunk of cells, then each chunk fills its own range in order
+  std::vector<int64_t> cbase((size_t)ntc + 1, 0);
+  chunks(ntc, ncells, [&](int t, int64_t c0, int64_t c1) {
+    int64_t m = 0;
+    for (int64_t sl = c0 * nb; sl < c1 * nb; ++sl) m += row_len(sl);
+    cbase[t + 1] = m;
+  });
+  for (int t = 0; t < ntc; ++t) cbase[t + 1] += cbase[t];
+  V.col.assign((size_t)cbase[ntc], 0);
+  V.val.assign((size_t)cbase[ntc], 0.0);
+  chunks(ntc, ncells, [&](int t, int64_t c0, int64_t c1) {
+    int64_t o = cbase[t];
+    for (int64_t c = c0; c < c1; ++c) {
+      V.row_base[c] = c * nb;
+      for (int tt = 0; tt < nb; ++tt) {
+        const int rs = raw_of_slot[c * nb + tt];
+        if (true_of[rs] >= 0) {
+          V.col[o] = true_of[rs];
+          V.val[o] = 1.0;
+          ++o;
+        } else {
+          const int64_t q = hslot[rs];
+          for (int64_t e = hptr[q]; e < hptr[q + 1]; ++e, ++o) {
+            V.col[o] = hcol[e];
+            V.val[o] = hval[e];
+          }
         }
+        V.row_ptr[c * nb + tt + 1] = o;
       }
-      V.row_ptr.push_back((int64_t)V.col.size());
     }
-  }
+  });
   V.row_base[ncells] = ncells * nb;
   // corner coordinates
   Xcell.resize((size_t)(ncells * 24));

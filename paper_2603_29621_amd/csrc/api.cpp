@@ -17,8 +17,11 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <exception>
 #include <functional>
 #include <memory>
+#include <string>
+#include <thread>
 #include <type_traits>
 #include <vector>
 
@@ -213,8 +216,19 @@ struct HpData {
 // side by side), the
 // per-cell corners, the linearisation data, the Jacobi diagonal, V-cycle
 // work vectors, and the cell and unknown relations to level j + 1.
+// host form of AmrMaps (built on a worker thread, then uploaded)
+struct AmrMapsHost {
+  int64_t N = 0, nrows = 0;
+  std::vector<int> rcol, hcol, trow, wrow, owner;
+  std::vector<int64_t> hptr, tptr, wptr, heavy;
+  std::vector<double> hval, wval;
+};
+
 struct AmrLevel {
   AmrSpaceHost S;  // host space (row maps released after the upload)
+  AmrMapsHost mh;              // host maps and colouring, released after the upload
+  std::vector<int> colour_host;
+  int ncolour_host = 0;
   LevelGeom g{};   // degree and cell count for the cell kernels
   int64_t N = 0, NQ = 0;
   AmrMaps M;       // unknowns <-> E-vector rows (constraints, Dirichlet mask, owners)
@@ -2185,19 +2199,46 @@ const T *amr_inv(const AmrLevel &V) {
 // belongs to the structured hierarchy)
 int amr_nop(const AmrData &A) { return A.mg ? (int)A.lev.size() - 1 : 1; }
 
+// f(0), ..., f(n-1) on n host threads; the first failure is rethrown here
+// with its error text (which the worker set in its own thread-local slot)
+void parallel_tasks(int n, const std::function<void(int)> &f) {
+  std::vector<std::exception_ptr> ex((size_t)std::max(n, 0));
+  std::vector<std::string> msg((size_t)std::max(n, 0));
+  std::vector<std::thread> th;
+  for (int i = 0; i < n; ++i)
+    th.emplace_back([&, i] {
+      try {
+        f(i);
+      } catch (...) {
+        ex[i] = std::current_exception();
+        msg[i] = get_error();
+      }
+    });
+  for (auto &t : th) t.join();
+  for (int i = 0; i < n; ++i)
+    if (ex[i]) {
+      set_error("%s", msg[i].c_str());
+      std::rethrow_exception(ex[i]);
+    }
+}
+
 // device maps of a level: rows are cell-major ((k+1)^3 per cell), so row r's
 // E-vector slots are 4r .. 4r+3 and the lists need no slot offsets; rows of
 // one unknown with weight 1 store only that unknown
-void amr_maps_upload(HpData &H, const AmrSpaceHost &S, AmrMaps &M, hipStream_t s) {
+void amr_maps_host(const AmrSpaceHost &S, AmrMapsHost &out) {
   const HpSpaceHost &V = S.V;
   const int64_t nrows = V.row_base[S.ncells], N = S.N;
-  M.N = N;
-  M.nrows = nrows;
-  std::vector<int> rcol((size_t)nrows);
-  std::vector<int64_t> hptr(1, 0);
-  std::vector<int> hcol;
-  std::vector<double> hval;
-  std::vector<int64_t> tptr((size_t)N + 1, 0), wptr((size_t)N + 1, 0);
+  out.N = N;
+  out.nrows = nrows;
+  std::vector<int> &rcol = out.rcol;
+  rcol.assign((size_t)nrows, 0);
+  std::vector<int64_t> &hptr = out.hptr;
+  hptr.assign(1, 0);
+  std::vector<int> &hcol = out.hcol;
+  std::vector<double> &hval = out.hval;
+  std::vector<int64_t> &tptr = out.tptr, &wptr = out.wptr;
+  tptr.assign((size_t)N + 1, 0);
+  wptr.assign((size_t)N + 1, 0);
   for (int64_t r = 0; r < nrows; ++r) {
     const int64_t b = V.row_ptr[r], e = V.row_ptr[r + 1];
     if (e - b == 1 && V.val[b] == 1.0) {
@@ -2217,8 +2258,11 @@ void amr_maps_upload(HpData &H, const AmrSpaceHost &S, AmrMaps &M, hipStream_t s
     tptr[g + 1] += tptr[g];
     wptr[g + 1] += wptr[g];
   }
-  std::vector<int> trow((size_t)tptr[N]), wrow((size_t)wptr[N]);
-  std::vector<double> wval((size_t)wptr[N]);
+  std::vector<int> &trow = out.trow, &wrow = out.wrow;
+  std::vector<double> &wval = out.wval;
+  trow.assign((size_t)tptr[N], 0);
+  wrow.assign((size_t)wptr[N], 0);
+  wval.assign((size_t)wptr[N], 0.0);
   {
     std::vector<int64_t> tf(tptr.begin(), tptr.end() - 1), wf(wptr.begin(), wptr.end() - 1);
     for (int64_t r = 0; r < nrows; ++r) {
@@ -2234,26 +2278,32 @@ void amr_maps_upload(HpData &H, const AmrSpaceHost &S, AmrMaps &M, hipStream_t s
       }
     }
   }
-  std::vector<int64_t> heavy;
+  std::vector<int64_t> &heavy = out.heavy;
+  heavy.clear();
   for (int64_t g = 0; g < N; ++g)
     if ((tptr[g + 1] - tptr[g]) + (wptr[g + 1] - wptr[g]) > AMR_LIGHT) heavy.push_back(g);
   const int64_t nb = V.row_base[1] - V.row_base[0];
-  std::vector<int> owner((size_t)N);
-  for (int64_t g = 0; g < N; ++g) owner[g] = (int)(V.owner_cell[g] * nb + V.owner_local[g]);
-  M.rcol = H.upload(rcol, s);
-  M.hptr = H.upload(hptr, s);
-  M.hcol = H.upload(hcol, s);
-  M.hval = H.upload(hval, s);
-  M.tptr = H.upload(tptr, s);
-  M.trow = H.upload(trow, s);
-  M.wptr = H.upload(wptr, s);
-  M.wrow = H.upload(wrow, s);
-  M.wval = H.upload(wval, s);
-  M.dir = H.upload(V.dirichlet, s);
-  M.owner = H.upload(owner, s);
-  M.nheavy = (int64_t)heavy.size();
-  M.heavy = heavy.empty() ? nullptr : H.upload(heavy, s);
-  MFS_HIP(hipStreamSynchronize(s));  // the host vectors go out of scope
+  out.owner.resize((size_t)N);
+  for (int64_t g = 0; g < N; ++g) out.owner[g] = (int)(V.owner_cell[g] * nb + V.owner_local[g]);
+}
+
+void amr_maps_upload(HpData &H, const AmrSpaceHost &S, const AmrMapsHost &h, AmrMaps &M, hipStream_t s) {
+  M.N = h.N;
+  M.nrows = h.nrows;
+  M.rcol = H.upload(h.rcol, s);
+  M.hptr = H.upload(h.hptr, s);
+  M.hcol = H.upload(h.hcol, s);
+  M.hval = H.upload(h.hval, s);
+  M.tptr = H.upload(h.tptr, s);
+  M.trow = H.upload(h.trow, s);
+  M.wptr = H.upload(h.wptr, s);
+  M.wrow = H.upload(h.wrow, s);
+  M.wval = H.upload(h.wval, s);
+  M.dir = H.upload(S.V.dirichlet, s);
+  M.owner = H.upload(h.owner, s);
+  M.nheavy = (int64_t)h.heavy.size();
+  M.heavy = h.heavy.empty() ? nullptr : H.upload(h.heavy, s);
+  MFS_HIP(hipStreamSynchronize(s));  // the caller may release the host vectors
 }
 
 // device data of a level; `op`: the level applies its own Jacobian
@@ -2276,7 +2326,8 @@ void amr_level_upload(AmrData &A, AmrLevel &V, bool op, bool work, hipStream_t s
   g.Nv = g.Np = (int64_t)g.nv[0] * g.nv[1] * g.nv[2];
   g.cart = 1;  // octree leaves of a Cartesian cube
   HpData &H = A.H;
-  amr_maps_upload(H, S, V.M, s);
+  amr_maps_upload(H, S, V.mh, V.M, s);
+  V.mh = AmrMapsHost();
   for (int i = 0; i < 2; ++i) {
     V.ev64[i] = H.alloc<double>(4 * nc * NQ);
     V.ev32[i] = H.alloc<float>(4 * nc * NQ);
@@ -2292,11 +2343,11 @@ void amr_level_upload(AmrData &A, AmrLevel &V, bool op, bool work, hipStream_t s
       V.diag = H.alloc<double>(4 * V.N);
       V.inv64 = H.alloc<double>(4 * V.N);
       V.inv32 = H.alloc<float>(4 * V.N);
-      int ncol = 0;
-      const std::vector<int> col = S.colours(&ncol);
-      V.colour = H.upload(col, s);
-      V.ncolours = ncol;
-      MFS_HIP(hipStreamSynchronize(s));  // col goes out of scope
+      MFS_REQUIRE(V.ncolour_host > 0, MFS_EINVAL, "level colouring missing");
+      V.colour = H.upload(V.colour_host, s);
+      V.ncolours = V.ncolour_host;
+      MFS_HIP(hipStreamSynchronize(s));
+      std::vector<int>().swap(V.colour_host);
     }
     MFS_HIP(hipStreamSynchronize(s));  // x32 goes out of scope
   }
@@ -2318,32 +2369,51 @@ void amr_build(mfs_problem &P, const mfs_refined_mesh &m, int k, bool mg, hipStr
   A.k = k;
   A.L = m.levels;
   A.mg = mg;
-  A.lev.emplace_back();
-  A.lev[0].S.build(m.n, m.levels, m.ncells, m.level, m.idx, k);
+  // the meshes of every level: the given one and, with multigrid, its global
+  // coarsenings down to the uniform base mesh
+  std::vector<std::vector<int>> lv(1), ix(1);
+  MFS_REQUIRE(m.ncells >= 1 && m.level && m.idx, MFS_EINVAL, "empty cell list");
+  MFS_REQUIRE(m.levels >= 0 && m.levels <= 4, MFS_EINVAL, "refinement levels %d out of range [0, 4]", m.levels);
+  lv[0].assign(m.level, m.level + m.ncells);
+  ix[0].assign(m.idx, m.idx + 3 * m.ncells);
   if (mg) {
     int top = 0;
-    for (int l : A.lev[0].S.level) top = std::max(top, l);
+    for (int l : lv[0]) top = std::max(top, l);
     MFS_REQUIRE(top >= 1, MFS_EINVAL, "the mesh is not refined: set up the base mesh with mfs_setup");
+    MFS_REQUIRE(top <= m.levels, MFS_EINVAL, "cell level %d above the mesh's %d levels", top, m.levels);
     for (int j = 1; j <= top; ++j) {
-      std::vector<int> lc, xc;
-      amr_coarsen(m.n, A.lev[j - 1].S.level, A.lev[j - 1].S.idx, lc, xc);
-      A.lev.emplace_back();
-      A.lev[j].S.build(m.n, m.levels - j, (int64_t)lc.size(), lc.data(), xc.data(), k);
+      lv.emplace_back();
+      ix.emplace_back();
+      amr_coarsen(m.n, lv[j - 1], ix[j - 1], lv[j], ix[j]);
     }
   }
+  const int nlev = (int)lv.size();
+  A.lev.resize(nlev);
   const int nop = amr_nop(A);
+  // host construction, one thread per level: space, maps, colouring
+  parallel_tasks(nlev, [&](int j) {
+    AmrLevel &V = A.lev[j];
+    V.S.build(m.n, m.levels - j, (int64_t)lv[j].size(), lv[j].data(), ix[j].data(), k);
+    amr_maps_host(V.S, V.mh);
+    if (mg && j < nop) V.colour_host = V.S.colours(&V.ncolour_host);
+  });
+  std::vector<AmrTransferHost> T((size_t)nlev - 1);
+  std::vector<std::vector<int64_t>> inj((size_t)nlev - 1);
+  parallel_tasks(nlev - 1, [&](int j) {
+    const AmrLevel &F = A.lev[j], &C = A.lev[j + 1];
+    T[j] = amr_transfer(m.n, F.S.level, F.S.idx, C.S.level, C.S.idx);
+    inj[j] = amr_injection(F.S, C.S);
+  });
   HpData &H = A.H;
-  for (size_t j = 0; j + 1 < A.lev.size(); ++j) {
-    AmrLevel &F = A.lev[j], &C = A.lev[j + 1];
-    const AmrTransferHost T = amr_transfer(m.n, F.S.level, F.S.idx, C.S.level, C.S.idx);
-    F.parent = H.upload(T.parent, s);
-    F.octant = H.upload(T.octant, s);
-    F.cptr = H.upload(T.cptr, s);
-    F.child = H.upload(T.child, s);
-    const std::vector<int64_t> inj = amr_injection(F.S, C.S);
-    F.inject = H.upload(inj, s);
-    MFS_HIP(hipStreamSynchronize(s));  // T and inj go out of scope
+  for (int j = 0; j + 1 < nlev; ++j) {
+    AmrLevel &F = A.lev[j];
+    F.parent = H.upload(T[j].parent, s);
+    F.octant = H.upload(T[j].octant, s);
+    F.cptr = H.upload(T[j].cptr, s);
+    F.child = H.upload(T[j].child, s);
+    F.inject = H.upload(inj[j], s);
   }
+  MFS_HIP(hipStreamSynchronize(s));  // T and inj go out of scope
   for (size_t j = 0; j < A.lev.size(); ++j) amr_level_upload(A, A.lev[j], (int)j < nop, mg, s);
   const auto tab = make_tables(k, k);
   std::vector<float> tab32(tab.begin(), tab.end());
