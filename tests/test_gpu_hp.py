@@ -87,6 +87,48 @@ def test_hp_operators(n, deg, noise):
         mfs.mfs_destroy(h)
 
 
+def test_hp_full_size_properties():
+    """The 32^3 hp workload (degrees 2..6 per 4^3 block, seed 0, noise 0.1h),
+    too large for the oracle: the constant pressure in the kernel, symmetry
+    on the free rows, and FP32 against FP64."""
+    n = [32, 32, 32]
+    deg = inputs.block_degrees(n, seed=0, block=4, lo=2, hi=6)
+    X = inputs.structured_vertices(3, n, noise=0.1, seed=0)
+    h = mfs.mfs_setup_hp(n, X, deg, 1.0, mfs.mfs_default_options(mg_levels=0))
+    try:
+        Nu, Np = mfs.mfs_n_dofs(h, 0)
+        nv = 3 * Nu
+        N = nv + Np
+
+        def K(x, op=mfs.MFS_OP_STOKES, prec=mfs.MFS_FP64, n_out=N):
+            dt = torch.float64 if prec == mfs.MFS_FP64 else torch.float32
+            y = torch.empty(n_out, dtype=dt, device="cuda")
+            mfs.mfs_vmult(h, op, prec, 0, y, cuda(x, dt))
+            return host(y)
+
+        # Dirichlet velocity rows: A x = x there, for two random x
+        x1, x2 = inputs.uniform_vector(nv, 3), inputs.uniform_vector(nv, 4)
+        dirichlet = (K(x1, mfs.MFS_OP_A, n_out=nv) == x1) & (K(x2, mfs.MFS_OP_A, n_out=nv) == x2)
+        assert 0 < dirichlet.sum() < nv // 4
+        x = inputs.uniform_vector(N, 1)
+        y = K(x)
+        scale = np.abs(y[:nv][~dirichlet]).max()
+        # constant pressure: B 1 = 0 on free rows, Dirichlet rows take the zero source
+        e = np.zeros(N)
+        e[nv:] = 1.0
+        assert np.abs(K(e)).max() <= 1e-11 * scale
+        # symmetry on the free rows
+        m = np.concatenate([dirichlet, np.zeros(Np, dtype=bool)])
+        xf, zf = np.where(m, 0.0, x), np.where(m, 0.0, inputs.uniform_vector(N, 2))
+        a, b = K(xf) @ zf, xf @ K(zf)
+        assert abs(a - b) <= 1e-11 * (np.abs(K(xf)) @ np.abs(zf))
+        # FP32 against FP64
+        x32 = x.astype(np.float32).astype(np.float64)
+        assert relerr(K(x32, prec=mfs.MFS_FP32), K(x32)) <= 1e-5
+    finally:
+        mfs.mfs_destroy(h)
+
+
 def _hier(n, deg, noise, nu=1.0):
     X, deg = _case(n, deg, noise)
     sol = hp.HpStokesSolver(n, X, deg, nu)

@@ -101,6 +101,43 @@ def test_ns_jacobian_low_viscosity_large_step():
         mfs.mfs_destroy(h)
 
 
+@pytest.mark.parametrize("k", [1, 2])
+def test_ns_jacobian_full_size_sampled(k):
+    """128^3 Cartesian cells with the linearisation of the throughput
+    measurement (Newton, dt = 1e-2, nu = 0.01, 8-mode Fourier field): sampled
+    rows against the oracle's rows from the cells that hold them (FP64
+    1e-12), FP32 against FP64 (2e-5), and the constant pressure in the
+    kernel."""
+    n, nu, dt = [128, 128, 128], 0.01, 1e-2
+    X = inputs.structured_vertices(3, n)
+    h = mfs.mfs_setup(3, n, X, k, nu, mfs.mfs_default_options(pressure_offset=0, mg_levels=0))
+    try:
+        u0 = inputs.ns_velocity(3, [k * v + 1 for v in n], seed=0)
+        mfs.mfs_set_linearization(h, cuda(u0), dt, 1)
+        Nv, Np = mfs.mfs_n_dofs(h, 0)
+        N = 3 * Nv + Np
+        dx = inputs.uniform_vector(N, 1)
+        y = torch.empty(N, dtype=torch.float64, device="cuda")
+        mfs.mfs_vmult(h, mfs.MFS_OP_NS_JACOBIAN, mfs.MFS_FP64, 0, y, cuda(dx))
+        yh = host(y)
+        S = fem.Space(3, n, X, k, k)
+        rows = np.unique(np.concatenate([
+            np.random.default_rng(5).choice(N, 300, replace=False),
+            [0, Nv - 1, Nv + Nv // 2, 3 * Nv - 1, 3 * Nv, 3 * Nv + Np // 2, N - 1]]))
+        ref = ns.sampled_jacobian_rows(S, dx, u0, nu, dt, rows)
+        scale = np.abs(ref).max()
+        assert np.abs(yh[rows] - ref).max() <= 1e-12 * scale
+        y32 = torch.empty(N, dtype=torch.float32, device="cuda")
+        mfs.mfs_vmult(h, mfs.MFS_OP_NS_JACOBIAN, mfs.MFS_FP32, 0, y32, cuda(dx, torch.float32))
+        assert relerr(host(y32), yh) <= 2e-5
+        e = np.zeros(N)
+        e[3 * Nv:] = 1.0
+        mfs.mfs_vmult(h, mfs.MFS_OP_NS_JACOBIAN, mfs.MFS_FP64, 0, y, cuda(e))
+        assert np.abs(host(y)).max() <= 1e-11 * scale
+    finally:
+        mfs.mfs_destroy(h)
+
+
 MG_CASES = [(2, [8, 8], 2), (2, [6, 10], 1), (3, [4, 4, 4], 2), (3, [6, 4, 4], 1)]
 
 
