@@ -18,6 +18,7 @@ FP64 method (FP64 preconditioner).
 """
 from __future__ import annotations
 
+import sys
 import threading
 import time
 from collections import deque
@@ -115,7 +116,9 @@ class Server:
         self.max_bypass_s = max_bypass_s
         self.keep = keep_solutions
 
-    def run(self, requests, realtime: bool = True):
+    def run(self, requests, realtime: bool = True, on_result=None):
+        """Serve the requests; on_result(result), if given, is called as each one
+        completes."""
         import torch
 
         pending = deque(sorted(requests, key=lambda r: r.arrival))
@@ -173,6 +176,8 @@ class Server:
                                      t, info.iterations, info.rel_residual, info.status,
                                      a.x if self.keep else None)
                         results.append(res)
+                        if on_result is not None:
+                            on_result(res)
                         mfs.mfs_destroy(a.h)
                         with lock:
                             used -= a.fp
@@ -186,7 +191,8 @@ class Server:
         return sorted(results, key=lambda r: r.rid)
 
 
-def run_sequential(requests, precond=mfs.MFS_FP64, rtol=1e-8, maxit=300, realtime=True, keep_solutions=False):
+def run_sequential(requests, precond=mfs.MFS_FP64, rtol=1e-8, maxit=300, realtime=True, keep_solutions=False,
+                   on_result=None):
     """Plain baseline: one solve at a time in arrival order."""
     import torch
 
@@ -205,6 +211,8 @@ def run_sequential(requests, precond=mfs.MFS_FP64, rtol=1e-8, maxit=300, realtim
         t = time.perf_counter() - t0
         out.append(Result(r.rid, r.n, r.k, r.nu, r.arrival if realtime else 0.0, adm, t, info.iterations,
                           info.rel_residual, info.status, x if keep_solutions else None))
+        if on_result is not None:
+            on_result(out[-1])
         mfs.mfs_destroy(h)
     return out
 
@@ -240,8 +248,21 @@ if __name__ == "__main__":
                                  degrees=tuple(int(v) for v in args.degrees.split(",")))
     mfs.lib()
     torch.cuda.init()
-    served = Server(args.budget_gb * 1e9).run(reqs)
-    out = {"served_fp32_mg": summarize(served)}
+
+    def reporter(name):
+        done = []
+
+        def report(res):
+            done.append(res)
+            if len(done) % 32 == 0 or len(done) == len(reqs):
+                print(f"[{name}] {len(done)}/{len(reqs)} solved, t = {res.completed:.1f} s", file=sys.stderr,
+                      flush=True)
+        return report
+
+    served = Server(args.budget_gb * 1e9).run(reqs, on_result=reporter("served"))
+    out = {"sample": f"{args.requests} requests, Poisson rate {args.rate}/s, n in {{{args.sizes}}}, "
+                     f"k in {{{args.degrees}}}, nu log-uniform [1e-2, 1], noise 0.1h, rtol 1e-8",
+           "served_fp32_mg": summarize(served)}
     if args.baseline:
-        out["sequential_fp64"] = summarize(run_sequential(reqs))
+        out["sequential_fp64"] = summarize(run_sequential(reqs, on_result=reporter("sequential")))
     print(json.dumps(out))
