@@ -108,6 +108,44 @@ def cpu_baseline_oracle(n=12, k=2):
                       f"{reps} repetitions, element loop with element matrices by full quadrature, 1 thread"}
 
 
+def solve_2d_section(mfs, torch, inputs, reps=5):
+    """The small 2D case: Q2/Q1 on 16 x 16 Cartesian cells of the unit square,
+    nu = 1, the manufactured solution u = curl(sin^2(pi x) sin^2(pi y)),
+    p = cos(pi x) cos(pi y); FP64 block preconditioner with Chebyshev degree 3,
+    FGMRES to 1e-10.  Launch-latency bound: wall time and iterations."""
+    n, k, nu = [16, 16], 2, 1.0
+    X = inputs.structured_vertices(2, n)
+    opts = mfs.mfs_default_options(rtol=1e-10, precond_precision=mfs.MFS_FP64, cheb_degree=3)
+    t0 = time.perf_counter()
+    h = mfs.mfs_setup(2, n, X, k, nu, opts)
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    try:
+        Nv, Np = mfs.mfs_n_dofs(h, 0)
+        q = mfs.mfs_quadrature_points(h, n[0] * n[1], (k + 1) ** 2, 2)
+        f = inputs.manufactured_2d(q, nu)[2]
+        sp = mfs.mfs_support_points(h, k, Nv, 2)
+        uex = inputs.manufactured_2d(sp, nu)[0]
+        b = torch.empty(2 * Nv + Np, dtype=torch.float64, device="cuda")
+        mfs.mfs_rhs(h, torch.from_numpy(np.ascontiguousarray(f)).cuda(),
+                    torch.from_numpy(np.ascontiguousarray(uex.T.ravel())).cuda(), b)
+        times, info = [], None
+        for _ in range(reps):
+            x = torch.zeros_like(b)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = mfs.mfs_solve(h, b, x, opts)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        u = x[:2 * Nv].cpu().numpy().reshape(2, Nv).T
+        err = float(np.abs(u - uex).max())
+    finally:
+        mfs.mfs_destroy(h)
+    return {"workload": "2D Stokes Q2/Q1, 16x16 Cartesian cells, nu=1, manufactured solution, FP64, Chebyshev 3, "
+                        "rtol 1e-10", "n_dofs": 2 * Nv + Np, "setup_s": setup, "solve_s_median": float(np.median(times)),
+            "iterations": info.iterations, "rel_residual": info.rel_residual, "u_max_error_vs_exact": err}
+
+
 def solve_section(mfs, torch, inputs, args):
     """3D Q2/Q1 solve on the same perturbed mesh to a 1e-8 relative residual:
     FP32 multigrid preconditioner inside FP64 FGMRES vs the plain FP64 method."""
@@ -461,6 +499,7 @@ def main():
         progress("hp done")
     if not args.no_solve:
         line["solve"] = solve_section(mfs, torch, inputs, args)
+        line["solve_2d"] = solve_2d_section(mfs, torch, inputs)
         progress("solve done")
         line["serving"] = serving_section(args)
         progress("serving done")
