@@ -1095,8 +1095,8 @@ void chebyshev(mfs_problem &P, int l, T *x, const T *b, bool zero_start, hipStre
     apply_A<T>(P, l, Ax, x, s);
     cheb_update<T>(L.g, x, d, b, Ax, invdiag<T>(L), c1, c2, first, s);
   };
-  if (zero_start)
-    cheb_update<T>(L.g, x, d, b, nullptr, invdiag<T>(L), T(0), (T)(1.0 / theta), true, s);
+  if (zero_start)  // x on entry is ignored: x = b on the Dirichlet rows, 0 elsewhere, then the first step
+    cheb_start<T>(L.g, x, d, b, invdiag<T>(L), (T)(1.0 / theta), s);
   else
     step(T(0), (T)(1.0 / theta), true);
   for (int it = 1; it < P.opts.cheb_degree; ++it) {
@@ -1115,8 +1115,7 @@ void vcycle_level(mfs_problem &P, int l, T *x, const T *b, hipStream_t s) {
     return;
   }
   const int64_t n = P.dim * L.g.Nv;
-  launch_fill_dirichlet<T>(L.g, x, b, s);  // x = b on Dirichlet rows, 0 elsewhere
-  chebyshev<T>(P, l, x, b, true, s);
+  chebyshev<T>(P, l, x, b, true, s);  // from x = b on Dirichlet rows, 0 elsewhere
   T *r = W.r[l];
   apply_A<T>(P, l, r, x, s);
   vec_axpby<T>(r, T(1), b, T(-1), n, s);  // r = b - A x

@@ -225,6 +225,10 @@ void vec_diag_scale(const LevelGeom &g, T *y, const T *invdiag, const T *x, hipS
 // inverse diagonal with 1 on Dirichlet rows
 void vec_invert_diag(const LevelGeom &g, const double *diag, double *invdiag64, float *invdiag32, hipStream_t s);
 // Chebyshev step on level vectors (velocity, dim*Nv):
+// the first step from x = 0 with the Dirichlet values of b: x = b on the
+// Dirichlet rows, d = x = c2 * invdiag * b elsewhere
+template <typename T>
+void cheb_start(const LevelGeom &g, T *x, T *d, const T *b, const T *invdiag, T c2, hipStream_t s);
 //   r = invdiag * (b - Ax) ; d = c1 * d + c2 * r ; x += d   (Dirichlet rows untouched)
 template <typename T>
 void cheb_update(const LevelGeom &g, T *x, T *d, const T *b, const T *Ax, const T *invdiag, T c1, T c2,

@@ -122,6 +122,35 @@ __global__ void k_cheb(int dim, int nv0, int nv1, int nv2, int64_t Nv, T *x, T *
     x[j] += dn;
   }
 }
+// first step from x = 0: Dirichlet rows x = b; free rows d = c2 D^{-1} b, x = d
+// (the operator vanishes there on x = 0 plus Dirichlet values, whose columns
+// the constrained operator drops)
+template <typename T>
+__global__ void k_cheb_start(int dim, int nv0, int nv1, int nv2, int64_t Nv, T *x, T *d, const T *b, const T *inv,
+                             T c2) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= Nv) return;
+  if (on_boundary(dim, nv0, nv1, nv2, i)) {
+    for (int c = 0; c < dim; ++c) x[c * Nv + i] = b[c * Nv + i];
+    return;
+  }
+  const T iv = inv[i];
+  for (int c = 0; c < dim; ++c) {
+    const int64_t j = c * Nv + i;
+    const T dn = c2 * (iv * b[j]);
+    d[j] = dn;
+    x[j] = dn;
+  }
+}
+template <typename T>
+void cheb_start(const LevelGeom &g, T *x, T *d, const T *b, const T *invdiag, T c2, hipStream_t s) {
+  hipLaunchKernelGGL(k_cheb_start<T>, dim3(nblocks(g.Nv)), dim3(VB), 0, s, g.dim, g.nv[0], g.nv[1], g.nv[2], g.Nv, x, d,
+                     b, invdiag, c2);
+}
+template void cheb_start<double>(const LevelGeom &, double *, double *, const double *, const double *, double,
+                                 hipStream_t);
+template void cheb_start<float>(const LevelGeom &, float *, float *, const float *, const float *, float, hipStream_t);
+
 template <typename T>
 void cheb_update(const LevelGeom &g, T *x, T *d, const T *b, const T *Ax, const T *invdiag, T c1, T c2, bool first,
                  hipStream_t s) {
