@@ -343,6 +343,34 @@ int mfs_solve_advance(mfs_problem *p, int *done, mfs_solve_info *info);
  */
 int mfs_set_linearization(mfs_problem *p, const double *u0, double dt, int newton, void *stream);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the 3D
+ * Taylor-Hood Q2/Q1 Stokes operator, dst = K src, on a structured mesh of
+ * n[0] x n[1] x n[2] cells, without a problem handle and without any
+ * allocation.  It is the operator mfs_vmult(MFS_OP_STOKES, level 0) applies
+ * for a problem set up by mfs_setup with dim = 3, k = 2, Taylor-Hood and the
+ * same vertices and nu, computed by the same kernels (results are identical).
+ *   n:        host array of 3 cell counts, each >= 1;
+ *   vertices: device, [(n0+1)(n1+1)(n2+1)][3] coordinates, x fastest, in
+ *             the precision `prec` (FP64: double, FP32: float); every cell
+ *             must have det J > 0 (not checked here: mfs_setup checks it);
+ *   nu > 0;  prec: MFS_FP64 or MFS_FP32;
+ *   src, dst: device, 3 Nv + Np entries, Nv = (2n0+1)(2n1+1)(2n2+1),
+ *             Np = (n0+1)(n1+1)(n2+1), blocked [u_0 | u_1 | u_2 | p] as
+ *             everywhere; non-aliasing; Dirichlet rows dst = src.
+ * Scratch: a library-owned static device array of MFS_NOALLOC_SCRATCH_BYTES
+ * per GPU (held until the process ends), which bounds the mesh: one brick of
+ * 8 x 4 x 2 cells needs 19,440 bytes in FP64 and 9,720 in FP32, so at most
+ * 1,726 bricks (FP64) or 3,452 (FP32), e.g. 32^3 cells (512 bricks).  Larger
+ * meshes return MFS_EINVAL before anything is enqueued.  Calls on one GPU
+ * share its array: calls that overlap (other streams, other host threads)
+ * race on it; calls ordered on one stream do not.  Enqueue only.
+ */
+#define MFS_NOALLOC_SCRATCH_BYTES (32u << 20)
+int mfs_stokes_vmult_noalloc(const int n[3], const void *vertices, double nu, int prec, void *dst, const void *src,
+                             void *stream);
+
 #ifdef __cplusplus
 }
 #endif

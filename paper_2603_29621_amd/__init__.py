@@ -39,6 +39,7 @@ EXPORTED = [
     "mfs_diagonal", "mfs_get_lambda", "mfs_set_lambda", "mfs_vcycle", "mfs_prolongate_add", "mfs_restrict",
     "mfs_precondition", "mfs_rhs", "mfs_solve", "mfs_solve_begin", "mfs_solve_advance",
     "mfs_set_linearization", "mfs_setup_hp", "mfs_setup_refined", "mfs_refined_count",
+    "mfs_stokes_vmult_noalloc",
 ]
 
 
@@ -127,6 +128,8 @@ def lib():
         L.mfs_solve_begin.argtypes = [vp, vp, vp, ctypes.POINTER(mfs_options), vp]
         L.mfs_solve_advance.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(mfs_solve_info)]
         L.mfs_set_linearization.argtypes = [vp, vp, ctypes.c_double, ctypes.c_int, vp]
+        L.mfs_stokes_vmult_noalloc.argtypes = [ctypes.POINTER(ctypes.c_int), vp, ctypes.c_double, ctypes.c_int, vp,
+                                               vp, vp]
         _lib = L
     return _lib
 
@@ -336,6 +339,18 @@ def mfs_vmult(h, op, prec, level, dst, src, stream=None):
     nd, ns_ = _op_len(h, op, level)
     _check(lib().mfs_vmult(h, op, prec, level, _arg(dst, nd, _word(prec), "dst"), _arg(src, ns_, _word(prec), "src"),
                            _stream(stream)))
+
+
+def mfs_stokes_vmult_noalloc(n, vertices, nu, prec, dst, src, stream=None):
+    """3D Q2/Q1 Stokes vmult on n[0] x n[1] x n[2] cells with device vertices
+    ([(n0+1)(n1+1)(n2+1)][3] in the call's precision); no allocation."""
+    nn = (ctypes.c_int * 3)(*[int(v) for v in n])
+    nv = int(np.prod([2 * int(v) + 1 for v in n]))
+    npr = int(np.prod([int(v) + 1 for v in n]))
+    w = _word(prec)
+    _check(lib().mfs_stokes_vmult_noalloc(nn, _arg(vertices, 3 * npr, w, "vertices"), float(nu), int(prec),
+                                          _arg(dst, 3 * nv + npr, w, "dst"), _arg(src, 3 * nv + npr, w, "src"),
+                                          _stream(stream)))
 
 
 def mfs_diagonal(h, level, dst, stream=None):
