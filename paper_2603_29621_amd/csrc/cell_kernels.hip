@@ -34,7 +34,21 @@ struct CellArgs {
   // cell-local outputs (velocity [cell][dim][(k+1)^dim], pressure
   // [cell][(kp+1)^dim]) instead of atomic additions into dst, when non-null
   T *ev_u, *ev_p;
+  // cells of this launch: all ncells (colour < 0), or the cells whose index
+  // parities (x, y, z) are the bits of `colour`, cm0 x cm1 x .. of them
+  // (nlaunch in total).  No two cells of one colour share a node, so a node
+  // receives at most one atomic addition per launch and the colours, launched
+  // in a fixed order on one stream, fix the order of the additions: the
+  // result is deterministic.
+  int colour, cm0, cm1, nlaunch;
 };
+
+template <typename T>
+__device__ __forceinline__ int launch_cell(const CellArgs<T> &a, int i) {
+  if (a.colour < 0) return i;
+  const int x = i % a.cm0, r = i / a.cm0, y = r % a.cm1, z = r / a.cm1;
+  return (2 * x + (a.colour & 1)) + a.n0 * ((2 * y + ((a.colour >> 1) & 1)) + a.n1 * (2 * z + (a.colour >> 2)));
+}
 
 template <int DIM, int K, int KP, typename T, int MODE>
 __global__ void __launch_bounds__((Shape<DIM, K, KP>::BLOCK)) cell_kernel(CellArgs<T> a) {
@@ -50,8 +64,9 @@ __global__ void __launch_bounds__((Shape<DIM, K, KP>::BLOCK)) cell_kernel(CellAr
   CellCtx<DIM, K, KP, T> c;
   int e;
   Sh::map(tid, e, c.t, c.active);
-  const int cell = blockIdx.x * CPB + e;
-  c.valid = c.active && cell < a.ncells;
+  const int lin = blockIdx.x * CPB + e;
+  c.valid = c.active && lin < a.nlaunch;
+  const int cell = c.valid ? launch_cell(a, lin) : 0;
   c.qi = c.t % Q;
   c.qj = (c.t / Q) % Q;
   c.ql = DIM == 3 ? c.t / (Q * Q) : 0;
@@ -199,8 +214,9 @@ __global__ void __launch_bounds__((Shape<DIM, K, 0>::BLOCK)) laplace_diag_kernel
   int e, t;
   bool active;
   Sh::map(tid, e, t, active);
-  const int cell = blockIdx.x * CPB + e;
-  const bool valid = active && cell < a.ncells;
+  const int lin = blockIdx.x * CPB + e;
+  const bool valid = active && lin < a.nlaunch;
+  const int cell = valid ? launch_cell(a, lin) : 0;
   const int qi = t % Q, qj = (t / Q) % Q, ql = DIM == 3 ? t / (Q * Q) : 0;
   int cx = 0, cy = 0, cz = 0;
   if (valid) {
@@ -292,8 +308,9 @@ __global__ void __launch_bounds__((Shape<DIM, K, KP>::BLOCK)) mass_diag_kernel(C
   int e, t;
   bool active;
   Sh::map(tid, e, t, active);
-  const int cell = blockIdx.x * CPB + e;
-  const bool valid = active && cell < a.ncells;
+  const int lin = blockIdx.x * CPB + e;
+  const bool valid = active && lin < a.nlaunch;
+  const int cell = valid ? launch_cell(a, lin) : 0;
   const int qi = t % Q, qj = (t / Q) % Q, ql = DIM == 3 ? t / (Q * Q) : 0;
   int cx = 0, cy = 0, cz = 0;
   if (valid) {
@@ -350,8 +367,9 @@ __global__ void __launch_bounds__((Shape<DIM, K, 0>::BLOCK))
   CellCtx<DIM, K, 0, T> c;
   int e;
   Sh::map(tid, e, c.t, c.active);
-  const int cell = blockIdx.x * CPB + e;
-  c.valid = c.active && cell < a.ncells;
+  const int lin = blockIdx.x * CPB + e;
+  c.valid = c.active && lin < a.nlaunch;
+  const int cell = c.valid ? launch_cell(a, lin) : 0;
   c.qi = c.t % Q;
   c.qj = (c.t / Q) % Q;
   c.ql = DIM == 3 ? c.t / (Q * Q) : 0;
@@ -418,14 +436,31 @@ static CellArgs<T> make_args(const LevelGeom &g, const T *X, const T *tab) {
   a.Np = g.Np;
   a.X = X;
   a.tab = tab;
+  a.colour = -1;
+  a.nlaunch = (int)g.ncells;
   return a;
+}
+
+// Run `launch(a)` once per cell colour (2^dim colours, fixed order) so that
+// atomic accumulation into shared nodes happens in a deterministic order.
+template <typename T, typename F>
+static void by_colour(CellArgs<T> a, int dim, F launch) {
+  for (int col = 0; col < (1 << dim); ++col) {
+    const int px = col & 1, py = (col >> 1) & 1, pz = (col >> 2) & 1;
+    a.colour = col;
+    a.cm0 = (a.n0 - px + 1) / 2;
+    a.cm1 = (a.n1 - py + 1) / 2;
+    const int cm2 = dim == 3 ? (a.n2 - pz + 1) / 2 : 1;
+    a.nlaunch = a.cm0 * a.cm1 * cm2;
+    if (a.nlaunch > 0) launch(a);
+  }
 }
 
 template <int DIM, int K, int KP, typename T, int MODE>
 static void go(const CellArgs<T> &a, hipStream_t s) {
   using Sh = Shape<DIM, K, KP>;
-  if (a.ncells == 0) return;
-  const int grid = (a.ncells + Sh::CPB - 1) / Sh::CPB;
+  if (a.nlaunch == 0) return;
+  const int grid = (a.nlaunch + Sh::CPB - 1) / Sh::CPB;
   hipLaunchKernelGGL((cell_kernel<DIM, K, KP, T, MODE>), dim3(grid), dim3(Sh::BLOCK), 0, s, a);
 }
 
@@ -484,10 +519,12 @@ void launch_cell_op(const LevelGeom &g, const DevLevel<T> &d, int mode, T nu, T 
   a.dst_p = dst_p;
   a.src_u = src_u;
   a.src_p = src_p;
+  // 3D: one launch per cell colour, so that the atomic accumulation is
+  // deterministic (2D keeps one launch: it is bound by launch latency)
   if (g.dim == 2)
     dispatch_k<2, T>(a, g.k, g.kp, mode, s);
   else
-    dispatch_k<3, T>(a, g.k, g.kp, mode, s);
+    by_colour(a, 3, [&](const CellArgs<T> &ac) { dispatch_k<3, T>(ac, g.k, g.kp, mode, s); });
   MFS_HIP(hipGetLastError());
 }
 template void launch_cell_op<double>(const LevelGeom &, const DevLevel<double> &, int, double, double *, double *,
@@ -498,13 +535,15 @@ template void launch_cell_op<float>(const LevelGeom &, const DevLevel<float> &, 
 template <int DIM, int K>
 static void go_diag(const CellArgs<double> &a, hipStream_t s) {
   using Sh = Shape<DIM, K, 0>;
-  const int grid = (a.ncells + Sh::CPB - 1) / Sh::CPB;
+  if (a.nlaunch == 0) return;
+  const int grid = (a.nlaunch + Sh::CPB - 1) / Sh::CPB;
   hipLaunchKernelGGL((laplace_diag_kernel<DIM, K>), dim3(grid), dim3(Sh::BLOCK), 0, s, a);
 }
 template <int DIM, int K>
 static void go_point(const CellArgs<double> &a, int what, double *out, const double *f, int *bad, hipStream_t s) {
   using Sh = Shape<DIM, K, 0>;
-  const int grid = (a.ncells + Sh::CPB - 1) / Sh::CPB;
+  if (a.nlaunch == 0) return;
+  const int grid = (a.nlaunch + Sh::CPB - 1) / Sh::CPB;
   hipLaunchKernelGGL((point_kernel<DIM, K>), dim3(grid), dim3(Sh::BLOCK), 0, s, a, what, out, f, bad);
 }
 
@@ -524,12 +563,14 @@ void launch_laplace_diagonal(const LevelGeom &g, const double *X, const double *
   CellArgs<double> a = make_args<double>(g, X, tab);
   a.nu = nu;
   a.dst_u = diag;
-#define CALL_DIAG(D, K) go_diag<D, K>(a, s)
-  if (g.dim == 2) {
-    MFS_K_SWITCH(2, g.k, CALL_DIAG)
-  } else {
-    MFS_K_SWITCH(3, g.k, CALL_DIAG)
-  }
+#define CALL_DIAG(D, K) go_diag<D, K>(ac, s)
+  by_colour(a, g.dim, [&](const CellArgs<double> &ac) {
+    if (g.dim == 2) {
+      MFS_K_SWITCH(2, g.k, CALL_DIAG)
+    } else {
+      MFS_K_SWITCH(3, g.k, CALL_DIAG)
+    }
+  });
 #undef CALL_DIAG
   MFS_HIP(hipGetLastError());
 }
@@ -537,7 +578,8 @@ void launch_laplace_diagonal(const LevelGeom &g, const double *X, const double *
 template <int DIM, int K, int KP>
 static void go_mass_diag(const CellArgs<double> &a, hipStream_t s) {
   using Sh = Shape<DIM, K, KP>;
-  const int grid = (a.ncells + Sh::CPB - 1) / Sh::CPB;
+  if (a.nlaunch == 0) return;
+  const int grid = (a.nlaunch + Sh::CPB - 1) / Sh::CPB;
   hipLaunchKernelGGL((mass_diag_kernel<DIM, K, KP>), dim3(grid), dim3(Sh::BLOCK), 0, s, a);
 }
 template <int DIM, int K>
@@ -558,12 +600,14 @@ static void go_mass_diag_kp(const CellArgs<double> &a, int kp, hipStream_t s) {
 void launch_mass_diagonal(const LevelGeom &g, const double *X, const double *tab, double *diag, hipStream_t s) {
   CellArgs<double> a = make_args<double>(g, X, tab);
   a.dst_p = diag;
-#define CALL_MD(D, K) go_mass_diag_kp<D, K>(a, g.kp, s)
-  if (g.dim == 2) {
-    MFS_K_SWITCH(2, g.k, CALL_MD)
-  } else {
-    MFS_K_SWITCH(3, g.k, CALL_MD)
-  }
+#define CALL_MD(D, K) go_mass_diag_kp<D, K>(ac, g.kp, s)
+  by_colour(a, g.dim, [&](const CellArgs<double> &ac) {
+    if (g.dim == 2) {
+      MFS_K_SWITCH(2, g.k, CALL_MD)
+    } else {
+      MFS_K_SWITCH(3, g.k, CALL_MD)
+    }
+  });
 #undef CALL_MD
   MFS_HIP(hipGetLastError());
 }
@@ -571,12 +615,18 @@ void launch_mass_diagonal(const LevelGeom &g, const double *X, const double *tab
 static void point_op(const LevelGeom &g, const double *X, const double *tab, int what, double *out,
                      const double *f, int *bad, hipStream_t s) {
   CellArgs<double> a = make_args<double>(g, X, tab);
-#define CALL_PT(D, K) go_point<D, K>(a, what, out, f, bad, s)
-  if (g.dim == 2) {
-    MFS_K_SWITCH(2, g.k, CALL_PT)
-  } else {
-    MFS_K_SWITCH(3, g.k, CALL_PT)
-  }
+#define CALL_PT(D, K) go_point<D, K>(ac, what, out, f, bad, s)
+  auto run = [&](const CellArgs<double> &ac) {
+    if (g.dim == 2) {
+      MFS_K_SWITCH(2, g.k, CALL_PT)
+    } else {
+      MFS_K_SWITCH(3, g.k, CALL_PT)
+    }
+  };
+  if (what == 2)  // the load vector accumulates: by colour (deterministic)
+    by_colour(a, g.dim, run);
+  else
+    run(a);
 #undef CALL_PT
   MFS_HIP(hipGetLastError());
 }

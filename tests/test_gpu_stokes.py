@@ -11,6 +11,7 @@ import torch
 import inputs
 import paper_2603_29621_amd as mfs
 from oracle import fem, krylov, mg, solve
+from bounds import bordered_error_bound
 
 pytestmark = pytest.mark.gpu
 
@@ -440,7 +441,12 @@ def test_solve_3d_mixed_precision():
         xs = host(x)
         assert np.linalg.norm(bref - K @ xs) <= 1.01e-8 * np.linalg.norm(bref)
         xd = solve.pressure_mean_free(S, solve.direct_solve(S, nu, bref, mats), mats["M"])
-        # error bound: condition number times the 1e-8 residual
-        assert np.linalg.norm(xs - xd) <= 1e-4 * np.linalg.norm(xd)
+        # error bound from the residual and the smallest eigenvalue of the
+        # bordered system, both computed by the oracle
+        bound, _ = bordered_error_bound(S, nu, bref, xs, mats)
+        err = np.linalg.norm(xs - xd)
+        print(f"3D 8^3 Q2/Q1 mixed-precision solve: error {err / np.linalg.norm(xd):.2e}, "
+              f"bound {bound / np.linalg.norm(xd):.2e}")
+        assert err <= 1.5 * bound + 1e-12 * np.linalg.norm(xd)
     finally:
         mfs.mfs_destroy(h)
