@@ -34,7 +34,7 @@
  *   tensor) of exactly the documented length, in the precision named by the
  *   call, not aliasing any other argument unless stated.  Device memory the
  *   library needs internally is allocated in mfs_setup and freed by
- *   mfs_destroy.  Streams are hipStream_t passed as void* (NULL = default).
+ *   mfs_destroy, or carved from a caller-owned arena (mfs_setup_arena).  Streams are hipStream_t passed as void* (NULL = default).
  * Errors: every call returns MFS_OK (0) or a negative code; mfs_last_error()
  *   returns a thread-local message for the last failure.  No C++ exception
  *   crosses this interface.
@@ -139,6 +139,21 @@ int mfs_footprint(const mfs_mesh *mesh, int k, const mfs_options *opts, size_t *
 int mfs_setup(const mfs_mesh *mesh, int k, double nu, const mfs_options *opts, void *stream,
               mfs_problem **out);
 int mfs_destroy(mfs_problem *p);
+
+/*
+ * mfs_setup into a caller-owned device arena (for example a torch uint8
+ * CUDA tensor) instead of a library allocation: every device array of the
+ * problem (levels, Krylov space, work vectors) is carved from `arena`, which
+ * must be 256-byte aligned, hold at least mfs_footprint() bytes (MFS_ENOMEM
+ * otherwise) and outlive the problem; mfs_destroy does not free it.  The
+ * library still keeps a small pinned readback block and, with graphs, a
+ * capture stream per problem, taken from process-wide free lists and
+ * returned to them by mfs_destroy (neither frees device memory, so neither
+ * waits for other work on the device).  Structured meshes only (mfs_setup's
+ * problems); hp and refined-mesh problems allocate their own.
+ */
+int mfs_setup_arena(const mfs_mesh *mesh, int k, double nu, const mfs_options *opts, void *arena, size_t bytes,
+                    void *stream, mfs_problem **out);
 
 /*
  * setup for the hp variant of Sec. 3: velocity degree cell_degree[c] in [2, 6]
@@ -342,6 +357,75 @@ int mfs_solve_advance(mfs_problem *p, int *done, mfs_solve_info *info);
  * `stream`.  MFS_EINVAL for a Taylor-Hood problem or dt <= 0.
  */
 int mfs_set_linearization(mfs_problem *p, const double *u0, double dt, int newton, void *stream);
+
+/*
+ * General Navier-Stokes state (Sec. 5, BDF2): the linearisation at
+ * x0 = [u0 | p0] (device FP64, full length (dim+1) n_u; velocity with its
+ * boundary values) with the BDF2 history u_hist = (4 u^n - u^{n-1}) / 3
+ * (device FP64, dim n_u; NULL: u_hist = u0), so that the time derivative is
+ * alpha (u - u_hist), alpha = 3/(2 dt), and the strong residual at the state
+ * is R(u0, p0) = alpha (u0 - u_hist) + u0.grad u0 + grad p0 - nu Lap u0
+ * (mfs_set_linearization is the case p0 = 0, u_hist = u0).  The Jacobian of
+ * mfs_vmult(MFS_OP_NS_JACOBIAN) is then the Gateaux derivative of the
+ * residual below at x0 (newton = 1) or its Oseen part (newton = 0).
+ * keep_delta = 1 keeps the SUPG/PSPG parameter delta_1 of the previous
+ * linearisation on every level (frozen during a time step), 0 recomputes it
+ * from u0 as mfs_set_linearization does.  Computes the multigrid data too
+ * (with mg_levels).  Host-synchronous; drops the recorded preconditioner.
+ */
+int mfs_set_linearization_point(mfs_problem *p, const double *x0, const double *u_hist, double dt, int newton,
+                                int keep_delta, void *stream);
+
+/*
+ * F = the residual F_NS + F_SUPG + F_PSPG of Sec. 5 at the state of the last
+ * linearisation, tested with every basis function:
+ *   (alpha (u - u_hist) + u.grad u, v) + (nu grad u, grad v) - (p, div v)
+ *   + (div u, q) + sum_K delta_1 (R(u, p), u.grad v + grad q)_K,
+ * f = 0, delta_1 as stored.  Velocity Dirichlet rows of F are 0 (the state
+ * carries the boundary values).  F: device FP64, (dim+1) n_u.  Enqueue only.
+ */
+int mfs_ns_residual(mfs_problem *p, double *F, void *stream);
+
+typedef struct mfs_newton_options {
+  int max_newton;        /* Newton iterations per step (20) */
+  double rtol;           /* stop when ||F(x_k)||_2 <= max(rtol ||F(x_0)||_2, atol) (1e-8) */
+  double atol;           /* (0) */
+  double linear_rtol;    /* FGMRES relative tolerance of each correction J dx = -F (1e-6); a
+                            correction is never solved below a tenth of the Newton target:
+                            the tolerance used is max(linear_rtol, 0.1 target / ||F(x_k)||) */
+  int linear_maxit;      /* FGMRES iterations per correction (200) */
+  int precond_precision; /* MFS_FP32 (default) or MFS_FP64 multigrid preconditioner */
+} mfs_newton_options;
+
+typedef struct mfs_newton_info {
+  int newton_iterations; /* corrections applied */
+  int linear_iterations; /* FGMRES iterations over all corrections */
+  int linear_failures;   /* corrections whose FGMRES stopped at linear_maxit */
+  int status;            /* MFS_OK or MFS_ENOCONV */
+  double res0, res;      /* ||F||_2 at the initial guess and at the result */
+  double seconds;
+} mfs_newton_info;
+
+void mfs_default_newton_options(mfs_newton_options *opts);
+
+/*
+ * One BDF2 time step of the stabilised Navier-Stokes equations (Sec. 5) by
+ * Newton's method, each correction solved by FGMRES with one monolithic
+ * multigrid V-cycle as preconditioner (the Newton-Krylov method of Sec. 5).
+ *   u_n, u_nm1: device FP64 velocities (dim n_u) of the last two steps (the
+ *     first step passes the initial velocity twice);
+ *   x: device FP64 (dim+1) n_u; on entry the initial guess, whose velocity
+ *     Dirichlet rows are the boundary values of the new time level (kept);
+ *     on exit the new state, pressure with zero nodal mean.
+ * delta_1 is frozen at u_n for the whole step, so each Jacobian is the exact
+ * derivative of the residual the step solves.  The boundary data must have
+ * zero net flux (the pressure rows of F then sum to zero, as the singular
+ * Jacobian needs).  Needs mg_levels = 1.  Host-synchronous.  MFS_ENOCONV
+ * when Newton does not reach its tolerance (x holds the last iterate, info
+ * filled).
+ */
+int mfs_ns_bdf2_step(mfs_problem *p, const double *u_n, const double *u_nm1, double *x, double dt,
+                     const mfs_newton_options *opts, mfs_newton_info *info, void *stream);
 
 /*
  * For callers that cannot allocate device memory (code under HIP graph

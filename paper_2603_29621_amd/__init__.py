@@ -39,7 +39,8 @@ EXPORTED = [
     "mfs_diagonal", "mfs_get_lambda", "mfs_set_lambda", "mfs_vcycle", "mfs_prolongate_add", "mfs_restrict",
     "mfs_precondition", "mfs_rhs", "mfs_solve", "mfs_solve_begin", "mfs_solve_advance",
     "mfs_set_linearization", "mfs_setup_hp", "mfs_setup_refined", "mfs_refined_count",
-    "mfs_stokes_vmult_noalloc",
+    "mfs_stokes_vmult_noalloc", "mfs_set_linearization_point", "mfs_ns_residual", "mfs_default_newton_options",
+    "mfs_ns_bdf2_step", "mfs_setup_arena",
 ]
 
 
@@ -85,6 +86,17 @@ class mfs_solve_info(ctypes.Structure):
                 ("seconds", ctypes.c_double)]
 
 
+class mfs_newton_options(ctypes.Structure):
+    _fields_ = [("max_newton", ctypes.c_int), ("rtol", ctypes.c_double), ("atol", ctypes.c_double),
+                ("linear_rtol", ctypes.c_double), ("linear_maxit", ctypes.c_int), ("precond_precision", ctypes.c_int)]
+
+
+class mfs_newton_info(ctypes.Structure):
+    _fields_ = [("newton_iterations", ctypes.c_int), ("linear_iterations", ctypes.c_int),
+                ("linear_failures", ctypes.c_int), ("status", ctypes.c_int), ("res0", ctypes.c_double),
+                ("res", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -104,6 +116,8 @@ def lib():
         L.mfs_setup.argtypes = [ctypes.POINTER(mfs_mesh), ctypes.c_int, ctypes.c_double, ctypes.POINTER(mfs_options),
                                 vp, ctypes.POINTER(vp)]
         L.mfs_destroy.argtypes = [vp]
+        L.mfs_setup_arena.argtypes = [ctypes.POINTER(mfs_mesh), ctypes.c_int, ctypes.c_double,
+                                      ctypes.POINTER(mfs_options), vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
         L.mfs_setup_hp.argtypes = [ctypes.POINTER(mfs_mesh), ctypes.POINTER(ctypes.c_int), ctypes.c_double,
                                    ctypes.POINTER(mfs_options), vp, ctypes.POINTER(vp)]
         L.mfs_setup_refined.argtypes = [ctypes.POINTER(mfs_refined_mesh), ctypes.c_int, ctypes.c_double,
@@ -128,6 +142,12 @@ def lib():
         L.mfs_solve_begin.argtypes = [vp, vp, vp, ctypes.POINTER(mfs_options), vp]
         L.mfs_solve_advance.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(mfs_solve_info)]
         L.mfs_set_linearization.argtypes = [vp, vp, ctypes.c_double, ctypes.c_int, vp]
+        L.mfs_set_linearization_point.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_int, ctypes.c_int, vp]
+        L.mfs_ns_residual.argtypes = [vp, vp, vp]
+        L.mfs_default_newton_options.argtypes = [ctypes.POINTER(mfs_newton_options)]
+        L.mfs_default_newton_options.restype = None
+        L.mfs_ns_bdf2_step.argtypes = [vp, vp, vp, vp, ctypes.c_double, ctypes.POINTER(mfs_newton_options),
+                                       ctypes.POINTER(mfs_newton_info), vp]
         L.mfs_stokes_vmult_noalloc.argtypes = [ctypes.POINTER(ctypes.c_int), vp, ctypes.c_double, ctypes.c_int, vp,
                                                vp, vp]
         _lib = L
@@ -242,6 +262,21 @@ def mfs_setup(dim, n, vertices, k, nu, opts=None, stream=None) -> ctypes.c_void_
     h = ctypes.c_void_p(0)
     _check(lib().mfs_setup(ctypes.byref(m), int(k), float(nu), ctypes.byref(opts) if opts else None,
                            _stream(stream), ctypes.byref(h)))
+    _dims[h.value] = int(dim)
+    return h
+
+
+def mfs_setup_arena(dim, n, vertices, k, nu, arena, opts=None, stream=None) -> ctypes.c_void_p:
+    """mfs_setup into a caller-owned device arena (a uint8 CUDA tensor of at
+    least mfs_footprint bytes, kept alive by the caller until mfs_destroy)."""
+    import torch
+
+    m, _keep = _mesh(dim, n, vertices)
+    if arena.dtype != torch.uint8 or not arena.is_cuda or not arena.is_contiguous():
+        raise ValueError("arena: a contiguous uint8 CUDA tensor is required")
+    h = ctypes.c_void_p(0)
+    _check(lib().mfs_setup_arena(ctypes.byref(m), int(k), float(nu), ctypes.byref(opts) if opts else None,
+                                 ctypes.c_void_p(arena.data_ptr()), arena.numel(), _stream(stream), ctypes.byref(h)))
     _dims[h.value] = int(dim)
     return h
 
@@ -436,6 +471,52 @@ def mfs_set_linearization(h, u0, dt, newton, stream=None):
     dim, nu, _, _ = _sizes(h, 0)
     n = None if dim is None else dim * nu
     _check(lib().mfs_set_linearization(h, _arg(u0, n, torch.float64, "u0"), float(dt), int(newton), _stream(stream)))
+
+
+def mfs_set_linearization_point(h, x0, u_hist, dt, newton=1, keep_delta=0, stream=None):
+    """Linearisation at the state x0 = [u0 | p0] with the BDF2 history u_hist
+    (None: u_hist = u0); keep_delta keeps the stored delta_1."""
+    import torch
+
+    dim, nu, _, _ = _sizes(h, 0)
+    nf = None if dim is None else (dim + 1) * nu
+    nv = None if dim is None else dim * nu
+    uh = _ptr(None) if u_hist is None else _arg(u_hist, nv, torch.float64, "u_hist")
+    _check(lib().mfs_set_linearization_point(h, _arg(x0, nf, torch.float64, "x0"), uh, float(dt), int(newton),
+                                             int(keep_delta), _stream(stream)))
+
+
+def mfs_ns_residual(h, F, stream=None):
+    import torch
+
+    dim, nu, _, _ = _sizes(h, 0)
+    nf = None if dim is None else (dim + 1) * nu
+    _check(lib().mfs_ns_residual(h, _arg(F, nf, torch.float64, "F"), _stream(stream)))
+
+
+def mfs_default_newton_options(**overrides) -> mfs_newton_options:
+    o = mfs_newton_options()
+    lib().mfs_default_newton_options(ctypes.byref(o))
+    for k, v in overrides.items():
+        setattr(o, k, v)
+    return o
+
+
+def mfs_ns_bdf2_step(h, u_n, u_nm1, x, dt, opts=None, stream=None) -> mfs_newton_info:
+    """One BDF2 step by Newton's method; x: initial guess in, new state out.
+    Returns the info (status MFS_ENOCONV is reported there, not raised)."""
+    import torch
+
+    dim, nu, _, _ = _sizes(h, 0)
+    nf = None if dim is None else (dim + 1) * nu
+    nv = None if dim is None else dim * nu
+    info = mfs_newton_info()
+    rc = lib().mfs_ns_bdf2_step(h, _arg(u_n, nv, torch.float64, "u_n"), _arg(u_nm1, nv, torch.float64, "u_nm1"),
+                                _arg(x, nf, torch.float64, "x"), float(dt), ctypes.byref(opts) if opts else None,
+                                ctypes.byref(info), _stream(stream))
+    if rc not in (MFS_OK, MFS_ENOCONV):
+        _check(rc)
+    return info
 
 
 @dataclass

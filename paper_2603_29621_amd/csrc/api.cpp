@@ -20,6 +20,7 @@
 #include <exception>
 #include <functional>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <type_traits>
@@ -238,7 +239,7 @@ struct AmrLevel {
   float *qd32 = nullptr;
   double *ev64[2] = {};  // in, out
   float *ev32[2] = {};
-  double *u0 = nullptr;                        // 3 N
+  double *u0 = nullptr;                        // 7 N: state [u0 | p0 | u~]
   double *diag = nullptr;                      // 4 N, diag(J)
   double *inv64 = nullptr;                     // 4 N, 1 / diag(J)
   float *inv32 = nullptr;
@@ -263,9 +264,11 @@ struct AmrData {
   float *tab32 = nullptr;
   AmrEmbed E{};
   double *ones = nullptr, *scratch = nullptr;  // N0 each (pressure mean)
+  double *state = nullptr;                      // 4 N0: staging of a linearisation state
   double dt = 0.0;
   int newton = 1;
   bool ready = false;
+  bool mg_ready = false;  // multigrid data of the current linearisation
 };
 }  // namespace
 
@@ -284,13 +287,16 @@ struct mfs_problem {
   double *partials = nullptr;   // reduction scratch
   double *tmp_full = nullptr;   // FP64 full-length temporary
   double *tmp2 = nullptr;       // second one (Navier-Stokes set-up)
+  double *nw_uh = nullptr, *nw_F = nullptr, *nw_dx = nullptr;  // BDF2 / Newton driver (level-0 sizes)
   Krylov kr;
   char *arena = nullptr;
   size_t arena_bytes = 0;
+  bool arena_owned = true;  // false: the caller's arena (mfs_setup_arena)
   hipStream_t stream = nullptr;
   // Navier-Stokes problem (pressure_offset = 0)
   bool ns = false;
   bool ns_ready = false;
+  bool ns_mg_ready = false;  // multigrid data of the current linearisation
   double ns_dt = 0.0;
   int ns_newton = 1;
   // hp problem: hp levels first (global level numbers 0 .. nhp-1), then the
@@ -444,7 +450,7 @@ void plan_arena(Arena &A, mfs_problem &P, const std::vector<LevelGeom> &G) {
       L.X32 = A.take<float>(nvert * P.dim);
       L.tab64 = A.take<double>(TAB_SIZE);
       L.tab32 = A.take<float>(TAB_SIZE);
-      L.u0 = A.take<double>(P.dim * G[l].Nv);
+      L.u0 = A.take<double>((2 * P.dim + 1) * G[l].Nv);  // state [u0 | p0 | u~]
       L.qd64 = A.take<double>(ns_qd_elems(G[l]));
       L.qd32 = A.take<float>(ns_qd_elems(G[l]));
       L.nsinv64 = A.take<double>((P.dim + 1) * G[l].Nv);
@@ -470,6 +476,11 @@ void plan_arena(Arena &A, mfs_problem &P, const std::vector<LevelGeom> &G) {
     P.partials = A.take<double>(32 * DOT_BLOCKS);
     P.tmp_full = A.take<double>(ntot);
     P.tmp2 = A.take<double>(ntot);
+    if (full) {  // the BDF2 / Newton driver: history, residual, correction
+      P.nw_uh = A.take<double>(P.dim * G[0].Nv);
+      P.nw_F = A.take<double>(ntot);
+      P.nw_dx = A.take<double>(ntot);
+    }
     Krylov &K = P.kr;
     K.m = std::max(1, std::min(P.opts.restart, 30));
     const int64_t nk = full ? ntot : 0;
@@ -571,14 +582,52 @@ void check_mesh(const mfs_mesh *mesh, int k, const mfs_options &o) {
   MFS_REQUIRE(nodes < (1LL << 31) / mesh->dim, MFS_EINVAL, "mesh too large for 32-bit node grid");
 }
 
+// Pinned readback blocks and capture streams are kept in process-wide free
+// lists and reused by later problems: freeing pinned memory or destroying a
+// stream waits for the whole device, which would stall the other problems
+// of a request loop every time one of them completes.
+constexpr int PINNED_DOUBLES = 192;  // Krylov readback (128) + coefficients (64)
+std::mutex g_pool_mu;
+std::vector<double *> g_pinned_free;
+std::vector<hipStream_t> g_stream_free;
+
+double *pinned_acquire() {
+  {
+    std::lock_guard<std::mutex> lock(g_pool_mu);
+    if (!g_pinned_free.empty()) {
+      double *p = g_pinned_free.back();
+      g_pinned_free.pop_back();
+      return p;
+    }
+  }
+  double *p = nullptr;
+  MFS_HIP(hipHostMalloc(&p, PINNED_DOUBLES * sizeof(double)));
+  return p;
+}
+hipStream_t capture_stream_acquire() {
+  {
+    std::lock_guard<std::mutex> lock(g_pool_mu);
+    if (!g_stream_free.empty()) {
+      hipStream_t st = g_stream_free.back();
+      g_stream_free.pop_back();
+      return st;
+    }
+  }
+  hipStream_t st = nullptr;
+  MFS_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+  return st;
+}
+
 void release(mfs_problem *P) {
   if (!P) return;
   if (P->prec_graph) (void)hipGraphExecDestroy(P->prec_graph);
-  if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
   if (P->kr.ev) (void)hipEventDestroy(P->kr.ev);
-  if (P->kr.host) (void)hipHostFree(P->kr.host);
-  if (P->kr.yhost) (void)hipHostFree(P->kr.yhost);
-  if (P->arena) (void)hipFree(P->arena);
+  {
+    std::lock_guard<std::mutex> lock(g_pool_mu);
+    if (P->cap_stream) g_stream_free.push_back(P->cap_stream);
+    if (P->kr.host) g_pinned_free.push_back(P->kr.host);
+  }
+  if (P->arena && P->arena_owned) (void)hipFree(P->arena);
   delete P->hp;
   delete P->amr;
   delete P;
@@ -1043,34 +1092,75 @@ void ns_setup_coarse(mfs_problem &P, hipStream_t s) {
   MFS_HIP(hipStreamSynchronize(s));
 }
 
-void ns_set_linearization(mfs_problem &P, const double *u0, double dt, int newton, hipStream_t s) {
+// Jacobi diagonals and the pinned coarse inverse of the current linearisation
+void ns_mg_data(mfs_problem &P, hipStream_t s) {
+  if (!P.opts.mg_levels) return;
+  for (int l = 0; l + 1 < P.nlev; ++l) {
+    Level &L = P.L[l];
+    const int64_t n = (P.dim + 1) * L.g.Nv;
+    double *d = P.w64.x[l];
+    ns_diagonal(P, l, d, s);
+    launch_reciprocal(L.nsinv64, L.nsinv32, d, n, s);
+  }
+  ns_setup_coarse(P, s);
+}
+
+// Linearisation at the state x0 = [u0 | p0] ((dim+1) Nv) with the BDF2
+// history u~ (dim Nv; NULL: u~ = u0), on every level (the coarse levels take
+// the fields at their nodes, which are fine nodes); keep_delta leaves
+// delta_1 as the previous linearisation stored it; mg: also the multigrid
+// data (diagonals, coarse inverse).  Host-synchronous.
+void ns_set_point(mfs_problem &P, const double *x0, const double *uh, double dt, int newton, int keep_delta, bool mg,
+                  hipStream_t s) {
   P.ns_ready = false;
+  P.ns_mg_ready = false;
   P.ns_dt = dt;
   P.ns_newton = newton ? 1 : 0;
-  MFS_HIP(hipMemcpyAsync(P.L[0].u0, u0, P.dim * P.L[0].g.Nv * sizeof(double), hipMemcpyDeviceToDevice, s));
-  for (int l = 1; l < P.nlev; ++l) launch_ns_inject(P.L[l - 1].g, P.L[l].g, P.L[l - 1].u0, P.L[l].u0, s);
+  const int d = P.dim;
+  const int64_t Nv = P.L[0].g.Nv;
+  double *st = P.L[0].u0;
+  MFS_HIP(hipMemcpyAsync(st, x0, (d + 1) * Nv * sizeof(double), hipMemcpyDeviceToDevice, s));
+  MFS_HIP(hipMemcpyAsync(st + (d + 1) * Nv, uh ? uh : x0, d * Nv * sizeof(double), hipMemcpyDeviceToDevice, s));
+  for (int l = 1; l < P.nlev; ++l) launch_ns_inject(P.L[l - 1].g, P.L[l].g, P.L[l - 1].u0, P.L[l].u0, s, 2 * d + 1);
+  NsPoint<double> pt;
+  pt.keep_delta = keep_delta;
   for (int l = 0; l < P.nlev; ++l) {
     Level &L = P.L[l];
-    launch_ns<double>(L.g, L.X64, L.tab64, 0, P.nu, dt, P.ns_newton, L.u0, nullptr, L.qd64, s);
+    launch_ns<double>(L.g, L.X64, L.tab64, 0, P.nu, dt, P.ns_newton, L.u0, nullptr, L.qd64, s, nullptr, nullptr,
+                      nullptr, &pt);
     vec_cast<float, double>(L.qd32, L.qd64, ns_qd_elems(L.g), s);
   }
   P.ns_ready = true;
   try {
-    if (P.opts.mg_levels) {
-      for (int l = 0; l + 1 < P.nlev; ++l) {
-        Level &L = P.L[l];
-        const int64_t n = (P.dim + 1) * L.g.Nv;
-        double *d = P.w64.x[l];
-        ns_diagonal(P, l, d, s);
-        launch_reciprocal(L.nsinv64, L.nsinv32, d, n, s);
-      }
-      ns_setup_coarse(P, s);
+    if (mg) {
+      ns_mg_data(P, s);
+      P.ns_mg_ready = true;
     }
     MFS_HIP(hipStreamSynchronize(s));
   } catch (...) {
     P.ns_ready = false;
     throw;
   }
+}
+
+// Linearisation point u0 of a Jacobian alone: p0 = 0 and u~ = u0
+void ns_set_linearization(mfs_problem &P, const double *u0, double dt, int newton, hipStream_t s) {
+  const int64_t nv = P.dim * P.L[0].g.Nv;
+  double *x0 = P.tmp2;
+  MFS_HIP(hipMemcpyAsync(x0, u0, nv * sizeof(double), hipMemcpyDeviceToDevice, s));
+  vec_fill<double>(x0 + nv, 0.0, P.L[0].g.Nv, s);
+  ns_set_point(P, x0, nullptr, dt, newton, 0, true, s);
+}
+
+// F = the nonlinear residual at the level-0 state of the last linearisation;
+// Dirichlet velocity rows 0
+void ns_residual(mfs_problem &P, double *F, hipStream_t s) {
+  MFS_REQUIRE(P.ns_ready, MFS_EINVAL, "no linearisation state: call mfs_set_linearization_point first");
+  Level &L = P.L[0];
+  const LevelGeom &g = L.g;
+  launch_fill_dirichlet<double>(g, F, (const double *)nullptr, s);
+  vec_fill<double>(F + g.dim * g.Nv, 0.0, g.Nv, s);
+  launch_ns<double>(g, L.X64, L.tab64, 2, P.nu, P.ns_dt, P.ns_newton, nullptr, F, L.qd64, s);
 }
 
 // ---------------------------------------------------------------- V-cycle
@@ -1475,7 +1565,7 @@ void precondition_fp32(mfs_problem &P, hipStream_t s) {
     return;
   }
   if (!P.prec_graph) {
-    if (!P.cap_stream) MFS_HIP(hipStreamCreateWithFlags(&P.cap_stream, hipStreamNonBlocking));
+    if (!P.cap_stream) P.cap_stream = capture_stream_acquire();
     hipGraph_t g = nullptr;
     if (hipStreamBeginCapture(P.cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
       (void)hipGetLastError();
@@ -1708,7 +1798,29 @@ int mfs_footprint(const mfs_mesh *mesh, int k, const mfs_options *opts, size_t *
   });
 }
 
+namespace {
+int setup_structured(const mfs_mesh *mesh, int k, double nu, const mfs_options *opts, void *arena, size_t bytes,
+                     void *stream, mfs_problem **out);
+}  // namespace
+
 int mfs_setup(const mfs_mesh *mesh, int k, double nu, const mfs_options *opts, void *stream, mfs_problem **out) {
+  return setup_structured(mesh, k, nu, opts, nullptr, 0, stream, out);
+}
+
+int mfs_setup_arena(const mfs_mesh *mesh, int k, double nu, const mfs_options *opts, void *arena, size_t bytes,
+                    void *stream, mfs_problem **out) {
+  if (arena == nullptr) {
+    set_error("arena is NULL");
+    return MFS_EINVAL;
+  }
+  return setup_structured(mesh, k, nu, opts, arena, bytes, stream, out);
+}
+
+}  // extern "C"
+
+namespace {
+int setup_structured(const mfs_mesh *mesh, int k, double nu, const mfs_options *opts, void *arena, size_t bytes,
+                     void *stream, mfs_problem **out) {
   mfs_problem *P = nullptr;
   int rc = guard([&] {
     MFS_REQUIRE(out != nullptr, MFS_EINVAL, "out is NULL");
@@ -1734,13 +1846,21 @@ int mfs_setup(const mfs_mesh *mesh, int k, double nu, const mfs_options *opts, v
     Arena dry;
     plan_arena(dry, *P, G);
     P->arena_bytes = dry.off;
-    MFS_HIP(hipMalloc(&P->arena, P->arena_bytes));
+    if (arena) {
+      MFS_REQUIRE(bytes >= P->arena_bytes, MFS_ENOMEM, "arena of %zu bytes, the problem needs %zu (mfs_footprint)",
+                  bytes, P->arena_bytes);
+      MFS_REQUIRE(reinterpret_cast<uintptr_t>(arena) % 256 == 0, MFS_EINVAL, "arena must be 256-byte aligned");
+      P->arena = static_cast<char *>(arena);
+      P->arena_owned = false;
+    } else {
+      MFS_HIP(hipMalloc(&P->arena, P->arena_bytes));
+    }
     Arena A;
     A.dry = false;
     A.base = P->arena;
     plan_arena(A, *P, G);
-    MFS_HIP(hipHostMalloc(&P->kr.host, 128 * sizeof(double)));
-    MFS_HIP(hipHostMalloc(&P->kr.yhost, 64 * sizeof(double)));
+    P->kr.host = pinned_acquire();
+    P->kr.yhost = P->kr.host + 128;
     MFS_HIP(hipEventCreateWithFlags(&P->kr.ev, hipEventDisableTiming));
     // vertices per level: fine vertices at indices divisible by 2^h
     const int dim = mesh->dim;
@@ -1827,6 +1947,9 @@ int mfs_setup(const mfs_mesh *mesh, int k, double nu, const mfs_options *opts, v
   }
   return MFS_OK;
 }
+}  // namespace
+
+extern "C" {
 
 int mfs_destroy(mfs_problem *p) {
   release(p);
@@ -2337,7 +2460,7 @@ void amr_level_upload(AmrData &A, AmrLevel &V, bool op, bool work, hipStream_t s
     V.X32 = H.upload(x32, s);
     V.qd64 = H.alloc<double>(nc * NQ * NS_QD);
     V.qd32 = H.alloc<float>(nc * NQ * NS_QD);
-    V.u0 = H.alloc<double>(3 * V.N);
+    V.u0 = H.alloc<double>(7 * V.N);  // state [u0 (3N) | p0 (N) | u~ (3N)]
     if (A.mg) {
       V.diag = H.alloc<double>(4 * V.N);
       V.inv64 = H.alloc<double>(4 * V.N);
@@ -2432,6 +2555,12 @@ void amr_build(mfs_problem &P, const mfs_refined_mesh &m, int k, bool mg, hipStr
   const int64_t N0 = A.lev[0].N;
   A.ones = H.alloc<double>(N0);
   A.scratch = H.alloc<double>(N0);
+  A.state = H.alloc<double>(4 * N0);
+  if (mg) {  // the BDF2 / Newton driver: history, residual, correction
+    P.nw_uh = H.alloc<double>(3 * N0);
+    P.nw_F = H.alloc<double>(4 * N0);
+    P.nw_dx = H.alloc<double>(4 * N0);
+  }
   vec_fill<double>(A.ones, 1.0, N0, s);
   MFS_HIP(hipStreamSynchronize(s));
 }
@@ -2529,29 +2658,43 @@ void amr_diagonal(mfs_problem &P, int j, double *diag, hipStream_t s) {
 // copied at the coarse unknowns level by level; point data per level (u0
 // through the unconstrained scalar map into the velocity slots); with
 // multigrid the structured base levels and the GC levels' diagonals
-void amr_set_linearization(mfs_problem &P, const double *u0, double dt, int newton, hipStream_t s) {
+// Linearisation at the state x0 = [u0 | p0] (4 N) with the BDF2 history u~
+// (3 N; NULL: u~ = u0) on every level (coarse levels take the fields at their
+// unknowns, which are fine unknowns), as ns_set_point.
+void amr_set_point(mfs_problem &P, const double *x0, const double *uh, double dt, int newton, int keep_delta,
+                   bool mg, hipStream_t s) {
   AmrData &A = *P.amr;
   A.ready = false;
+  A.mg_ready = false;
   A.dt = dt;
   A.newton = newton ? 1 : 0;
   const int nop = amr_nop(A);
-  MFS_HIP(hipMemcpyAsync(A.lev[0].u0, u0, 3 * A.lev[0].N * sizeof(double), hipMemcpyDeviceToDevice, s));
+  const int64_t N0 = A.lev[0].N;
+  MFS_HIP(hipMemcpyAsync(A.lev[0].u0, x0, 4 * N0 * sizeof(double), hipMemcpyDeviceToDevice, s));
+  MFS_HIP(hipMemcpyAsync(A.lev[0].u0 + 4 * N0, uh ? uh : x0, 3 * N0 * sizeof(double), hipMemcpyDeviceToDevice, s));
   for (int j = 1; j < nop; ++j)
-    permute<double>(A.lev[j].N, 3, A.lev[j - 1].inject, A.lev[j - 1].u0, A.lev[j - 1].N, A.lev[j].u0, A.lev[j].N,
+    permute<double>(A.lev[j].N, 7, A.lev[j - 1].inject, A.lev[j - 1].u0, A.lev[j - 1].N, A.lev[j].u0, A.lev[j].N,
                     false, s);
   for (int j = 0; j < nop; ++j) {
     AmrLevel &V = A.lev[j];
-    double *ev = V.ev64[0];
-    amr_gather<double>(V.M, 3, false, V.u0, ev, s);  // u0 keeps its boundary values
-    launch_ns<double>(V.g, nullptr, A.tab64, 0, P.nu, dt, A.newton, nullptr, nullptr, V.qd64, s, nullptr, ev, V.X64);
+    double *ev = V.ev64[0], *evh = V.ev64[1];
+    amr_gather<double>(V.M, 4, false, V.u0, ev, s);  // the state keeps its boundary values
+    amr_gather<double>(V.M, 3, false, V.u0 + 4 * V.N, evh, s);
+    NsPoint<double> pt;
+    pt.keep_delta = keep_delta;
+    pt.evhist = evh;
+    launch_ns<double>(V.g, nullptr, A.tab64, 0, P.nu, dt, A.newton, nullptr, nullptr, V.qd64, s, nullptr, ev, V.X64,
+                      &pt);
     vec_cast<float, double>(V.qd32, V.qd64, V.g.ncells * V.NQ * NS_QD, s);
   }
   if (A.mg) {
     AmrLevel &F = A.lev[nop - 1], &B = A.lev[nop];
     MFS_REQUIRE(B.N == P.L[0].g.Nv, MFS_EINVAL, "base level mismatch");
-    permute<double>(B.N, 3, F.inject, F.u0, F.N, P.tmp_full, B.N, false, s);
-    ns_set_linearization(P, P.tmp_full, dt, newton, s);  // structured levels; synchronises
+    permute<double>(B.N, 4, F.inject, F.u0, F.N, P.tmp_full, B.N, false, s);
+    permute<double>(B.N, 3, F.inject, F.u0 + 4 * F.N, F.N, P.tmp2, B.N, false, s);
+    ns_set_point(P, P.tmp_full, P.tmp2, dt, newton, keep_delta, mg, s);  // structured levels; synchronises
     A.ready = true;
+    if (!mg) return;
     try {
       for (int j = 0; j < nop; ++j) {
         AmrLevel &V = A.lev[j];
@@ -2559,6 +2702,7 @@ void amr_set_linearization(mfs_problem &P, const double *u0, double dt, int newt
         launch_reciprocal(V.inv64, V.inv32, V.diag, 4 * V.N, s);
       }
       MFS_HIP(hipStreamSynchronize(s));
+      A.mg_ready = true;
     } catch (...) {
       A.ready = false;
       throw;
@@ -2567,6 +2711,26 @@ void amr_set_linearization(mfs_problem &P, const double *u0, double dt, int newt
   }
   MFS_HIP(hipStreamSynchronize(s));
   A.ready = true;
+}
+
+// Linearisation point u0 of a Jacobian alone: p0 = 0 and u~ = u0
+void amr_set_linearization(mfs_problem &P, const double *u0, double dt, int newton, hipStream_t s) {
+  const int64_t N0 = P.amr->lev[0].N;
+  double *x0 = P.amr->state;
+  MFS_HIP(hipMemcpyAsync(x0, u0, 3 * N0 * sizeof(double), hipMemcpyDeviceToDevice, s));
+  vec_fill<double>(x0 + 3 * N0, 0.0, N0, s);
+  amr_set_point(P, x0, nullptr, dt, newton, 0, true, s);
+}
+
+// F = the nonlinear residual at the level-0 state of the last linearisation
+// (through the hanging-node maps); Dirichlet velocity rows 0
+void amr_residual(mfs_problem &P, double *F, hipStream_t s) {
+  AmrData &A = *P.amr;
+  MFS_REQUIRE(A.ready, MFS_EINVAL, "no linearisation state: call mfs_set_linearization_point first");
+  AmrLevel &V = A.lev[0];
+  double *evi = V.ev64[0], *evo = V.ev64[1];
+  launch_ns<double>(V.g, nullptr, A.tab64, 2, P.nu, A.dt, A.newton, nullptr, nullptr, V.qd64, s, evo, evi, V.X64);
+  amr_scatter<double>(V.M, evo, nullptr, F, s);
 }
 
 void amr_vmult(mfs_problem &P, int op, int prec, int level, void *dst, const void *src, hipStream_t s) {
@@ -2747,8 +2911,10 @@ void kr_begin(mfs_problem &P, const double *b, double *x, const mfs_options &o, 
   Krylov &K = P.kr;
   MFS_REQUIRE(P.opts.mg_levels, MFS_EINVAL, "solve needs the multigrid hierarchy (mg_levels = 1)");
   MFS_REQUIRE(P.hp || P.L[0].g.Np > 0, MFS_EINVAL, "solve needs a pressure space");
-  MFS_REQUIRE(!P.ns || P.ns_ready, MFS_EINVAL, "mfs_set_linearization has not been called");
-  MFS_REQUIRE(!P.amr || P.amr->ready, MFS_EINVAL, "mfs_set_linearization has not been called");
+  MFS_REQUIRE(!P.ns || (P.ns_ready && P.ns_mg_ready), MFS_EINVAL,
+              "mfs_set_linearization has not been called (or the state was set without multigrid data)");
+  MFS_REQUIRE(!P.amr || (P.amr->ready && P.amr->mg_ready), MFS_EINVAL,
+              "mfs_set_linearization has not been called (or the state was set without multigrid data)");
   const LevelGeom &g = P.L[0].g;
   const int64_t n = sys_n(P);
   K.b = b;
@@ -2782,9 +2948,166 @@ void kr_begin(mfs_problem &P, const double *b, double *x, const mfs_options &o, 
   K.state = 1;
   kr_enqueue_residual(P, s);
 }
+// the state of a Navier-Stokes problem (structured or refined) at x0 = [u0 | p0]
+void set_point_any(mfs_problem &P, const double *x0, const double *uh, double dt, int newton, int keep_delta, bool mg,
+                   hipStream_t s) {
+  if (P.amr)
+    amr_set_point(P, x0, uh, dt, newton, keep_delta, mg, s);
+  else
+    ns_set_point(P, x0, uh, dt, newton, keep_delta, mg, s);
+}
+
+// multigrid data (Jacobi diagonals, coarse inverse) of the current state
+void point_mg_any(mfs_problem &P, hipStream_t s) {
+  ns_mg_data(P, s);
+  P.ns_mg_ready = true;
+  if (P.amr) {
+    AmrData &A = *P.amr;
+    for (int j = 0; j < amr_nop(A); ++j) {
+      AmrLevel &V = A.lev[j];
+      amr_diagonal(P, j, V.diag, s);
+      launch_reciprocal(V.inv64, V.inv32, V.diag, 4 * V.N, s);
+    }
+    A.mg_ready = true;
+  }
+  MFS_HIP(hipStreamSynchronize(s));
+}
+
+double device_norm(mfs_problem &P, const double *v, int64_t n, hipStream_t s) {
+  Krylov &K = P.kr;
+  multi_dot<double>(v, 0, 1, v, n, K.dev + 110, P.partials, s);
+  MFS_HIP(hipMemcpyAsync(K.host + 110, K.dev + 110, sizeof(double), hipMemcpyDeviceToHost, s));
+  MFS_HIP(hipStreamSynchronize(s));
+  return std::sqrt(std::max(K.host[110], 0.0));
+}
+
+// One BDF2 step (Sec. 5) by Newton's method: F(x) = 0 with the time
+// derivative alpha (u - u~), u~ = (4 u^n - u^{n-1}) / 3, delta_1 frozen at u^n
+// for the whole step (so J is the exact derivative of F); each correction
+// J dx = -F by FGMRES with the monolithic multigrid preconditioner.  x holds
+// the initial guess with the new time level's Dirichlet values on entry.
+void bdf2_step(mfs_problem &P, const double *u_n, const double *u_nm1, double *x, double dt,
+               const mfs_newton_options &o, mfs_newton_info &info, hipStream_t s) {
+  const auto t0 = std::chrono::steady_clock::now();
+  info = mfs_newton_info{};
+  const int64_t nvel = sys_vel(P), n = sys_n(P);
+  // the recorded preconditioner keeps dt and the Newton flag: drop it when they change
+  if (P.ns_dt != dt || P.ns_newton != 1) drop_prec_graph(P);
+  // u~ and delta_1 at u^n (state [u^n; 0])
+  vec_copy<double>(P.nw_uh, u_n, nvel, s);
+  vec_axpby<double>(P.nw_uh, -1.0 / 3.0, u_nm1, 4.0 / 3.0, nvel, s);
+  double *st = P.nw_dx;
+  vec_copy<double>(st, u_n, nvel, s);
+  vec_fill<double>(st + nvel, 0.0, n - nvel, s);
+  set_point_any(P, st, u_n, dt, 1, 0, false, s);
+  mfs_options lo = P.opts;
+  lo.rtol = o.linear_rtol;
+  lo.maxit = o.linear_maxit;
+  lo.precond_precision = o.precond_precision;
+  for (int it = 0;; ++it) {
+    set_point_any(P, x, P.nw_uh, dt, 1, 1, false, s);
+    if (P.amr)
+      amr_residual(P, P.nw_F, s);
+    else
+      ns_residual(P, P.nw_F, s);
+    const double r = device_norm(P, P.nw_F, n, s);
+    if (it == 0) info.res0 = r;
+    info.res = r;
+    info.newton_iterations = it;
+    if (r <= std::max(o.rtol * info.res0, o.atol) || r == 0.0) {
+      info.status = MFS_OK;
+      break;
+    }
+    if (it == o.max_newton) {
+      info.status = MFS_ENOCONV;
+      break;
+    }
+    point_mg_any(P, s);
+    vec_axpby<double>(P.nw_F, 0.0, P.nw_F, -1.0, n, s);  // b = -F
+    // no need to solve beyond a tenth of the Newton target (and rounding
+    // would stop FGMRES short of a relative tolerance far below it)
+    const double target = std::max(o.rtol * info.res0, o.atol);
+    lo.rtol = std::min(0.5, std::max(o.linear_rtol, 0.1 * target / r));
+    kr_begin(P, P.nw_F, P.nw_dx, lo, s);
+    Krylov &K = P.kr;
+    while (K.state != 4) {
+      MFS_HIP(hipEventSynchronize(K.ev));
+      kr_process(P);
+    }
+    info.linear_iterations += K.info.iterations;
+    if (K.info.status != MFS_OK) info.linear_failures += 1;
+    vec_axpby<double>(x, 1.0, P.nw_dx, 1.0, n, s);  // x += dx
+  }
+  MFS_HIP(hipStreamSynchronize(s));
+  info.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
 }  // namespace
 
 extern "C" {
+
+void mfs_default_newton_options(mfs_newton_options *o) {
+  if (!o) return;
+  o->max_newton = 20;
+  o->rtol = 1e-8;
+  o->atol = 0.0;
+  o->linear_rtol = 1e-6;
+  o->linear_maxit = 200;
+  o->precond_precision = MFS_FP32;
+}
+
+int mfs_set_linearization_point(mfs_problem *p, const double *x0, const double *u_hist, double dt, int newton,
+                                int keep_delta, void *stream) {
+  return guard([&] {
+    check_problem(p);
+    MFS_REQUIRE(p->ns, MFS_EINVAL, "linearisation needs a problem set up with pressure_offset = 0");
+    MFS_REQUIRE(x0 != nullptr, MFS_EINVAL, "x0 is NULL");
+    MFS_REQUIRE(dt > 0 && std::isfinite(dt), MFS_EINVAL, "dt must be positive");
+    MFS_REQUIRE(!keep_delta || (p->amr ? p->amr->ready : p->ns_ready), MFS_EINVAL,
+                "keep_delta needs an earlier linearisation");
+    drop_prec_graph(*p);
+    set_point_any(*p, x0, u_hist, dt, newton, keep_delta, p->opts.mg_levels != 0, S(stream));
+  });
+}
+
+int mfs_ns_residual(mfs_problem *p, double *F, void *stream) {
+  return guard([&] {
+    check_problem(p);
+    MFS_REQUIRE(p->ns, MFS_EINVAL, "the residual needs a problem set up with pressure_offset = 0");
+    MFS_REQUIRE(F != nullptr, MFS_EINVAL, "F is NULL");
+    if (p->amr)
+      amr_residual(*p, F, S(stream));
+    else
+      ns_residual(*p, F, S(stream));
+  });
+}
+
+int mfs_ns_bdf2_step(mfs_problem *p, const double *u_n, const double *u_nm1, double *x, double dt,
+                     const mfs_newton_options *opts, mfs_newton_info *info, void *stream) {
+  return guard([&] {
+    check_problem(p);
+    MFS_REQUIRE(p->ns, MFS_EINVAL, "the BDF2 step needs a problem set up with pressure_offset = 0");
+    MFS_REQUIRE(p->opts.mg_levels, MFS_EINVAL, "the BDF2 step needs the multigrid hierarchy (mg_levels = 1)");
+    MFS_REQUIRE(u_n && u_nm1 && x, MFS_EINVAL, "NULL vector");
+    MFS_REQUIRE(dt > 0 && std::isfinite(dt), MFS_EINVAL, "dt must be positive");
+    mfs_newton_options o;
+    if (opts)
+      o = *opts;
+    else
+      mfs_default_newton_options(&o);
+    MFS_REQUIRE(o.max_newton >= 0 && o.max_newton <= 1000 && o.rtol >= 0 && o.atol >= 0 && o.linear_rtol > 0 &&
+                    o.linear_maxit >= 1,
+                MFS_EINVAL, "bad Newton options");
+    check_prec(o.precond_precision);
+    mfs_newton_info inf{};
+    bdf2_step(*p, u_n, u_nm1, x, dt, o, inf, S(stream));
+    if (info) *info = inf;
+    if (inf.status != MFS_OK) {
+      set_error("Newton did not reach rtol %.3e within %d iterations (||F|| %.3e from %.3e)", o.rtol, o.max_newton,
+                inf.res, inf.res0);
+      throw mfs::Error{MFS_ENOCONV};
+    }
+  });
+}
 
 int mfs_n_dofs(const mfs_problem *p, int level, int64_t *n_u, int64_t *n_p) {
   return guard([&] {
@@ -3000,7 +3323,10 @@ int mfs_vcycle(mfs_problem *p, int prec, void *dst, const void *src, void *strea
     check_prec(prec);
     MFS_REQUIRE(p->opts.mg_levels, MFS_EINVAL, "problem was set up without multigrid levels");
     MFS_REQUIRE(dst && src && dst != src, MFS_EINVAL, "bad vectors");
-    MFS_REQUIRE(!p->ns || p->ns_ready, MFS_EINVAL, "mfs_set_linearization has not been called");
+    MFS_REQUIRE(!p->ns || (p->ns_ready && p->ns_mg_ready), MFS_EINVAL,
+                "mfs_set_linearization has not been called (or the state was set without multigrid data)");
+    MFS_REQUIRE(!p->amr || (p->amr->ready && p->amr->mg_ready), MFS_EINVAL,
+                "mfs_set_linearization has not been called (or the state was set without multigrid data)");
     if (p->amr) {
       if (prec == MFS_FP64)
         amr_vcycle<double>(*p, 0, (double *)dst, (const double *)src, S(stream));
@@ -3098,7 +3424,10 @@ int mfs_precondition(mfs_problem *p, int prec, void *dst, const void *src, void 
     MFS_REQUIRE(p->opts.mg_levels && (p->hp || p->L[0].g.Np > 0), MFS_EINVAL,
                 "needs multigrid levels and a pressure space");
     MFS_REQUIRE(dst && src && dst != src, MFS_EINVAL, "bad vectors");
-    MFS_REQUIRE(!p->ns || p->ns_ready, MFS_EINVAL, "mfs_set_linearization has not been called");
+    MFS_REQUIRE(!p->ns || (p->ns_ready && p->ns_mg_ready), MFS_EINVAL,
+                "mfs_set_linearization has not been called (or the state was set without multigrid data)");
+    MFS_REQUIRE(!p->amr || (p->amr->ready && p->amr->mg_ready), MFS_EINVAL,
+                "mfs_set_linearization has not been called (or the state was set without multigrid data)");
     if (prec == MFS_FP64)
       precondition_any<double>(*p, (double *)dst, (const double *)src, S(stream));
     else

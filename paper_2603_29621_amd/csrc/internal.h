@@ -173,15 +173,27 @@ void launch_restrict(const LevelGeom &fine, const LevelGeom &coarse, bool h_tran
 int64_t restrict_work_elems(const LevelGeom &fine, const LevelGeom &coarse, int ncomp);
 
 // ----------------------------------------------------------------- Navier-Stokes (ns_kernels.hip)
-// per-quadrature-point linearisation data: u0 (3), grad u0 (9), R(u0) (3),
-// delta_1 (1), stored [cell][field][point]
-constexpr int NS_QD = 16;
+// per-quadrature-point linearisation data: u0 (3), grad u0 (9), R(u0, p0) (3),
+// delta_1 (1), the residual's Galerkin value term alpha (u0 - u~) + u0.grad u0
+// (3) and p0 (1), stored [cell][field][point]
+constexpr int NS_QD = 20;
 inline int64_t ns_qd_elems(const LevelGeom &g) {
   int64_t nq = 1;
   for (int a = 0; a < g.dim; ++a) nq *= g.k + 1;
   return g.ncells * nq * NS_QD;
 }
-// what = 0: qd = linearisation data of the nodal velocity src (dim*Nv);
+// A general linearisation state (what = 0): src holds [u0 (dim Nv) | p0 (Nv) |
+// u~ (dim Nv)] (structured grid) or evin slot 3 holds p0 and evhist slots
+// 0..2 hold u~ (cell-local inputs); keep_delta leaves delta_1 as stored.
+template <typename T>
+struct NsPoint {
+  int keep_delta = 0;
+  const T *evhist = nullptr;
+};
+// what = 0: qd = linearisation data of the nodal velocity src (dim*Nv), or of
+// the general state of `pt`;
+// what = 2: dst += the nonlinear residual at the stored state (src unused;
+// the same outputs as what = 1);
 // what = 1: dst += J src on the free velocity rows and all pressure rows
 // (src, dst full equal-order vectors; the Dirichlet rows of dst untouched);
 // with ev (3D, ncells * 4 * (k+1)^3 elements) the cell results are written
@@ -192,11 +204,13 @@ inline int64_t ns_qd_elems(const LevelGeom &g) {
 // components and pressure of a node side by side)
 template <typename T>
 void launch_ns(const LevelGeom &g, const T *X, const T *tab, int what, T nu, T dt, int newton, const T *src, T *dst,
-               T *qd, hipStream_t s, T *ev = nullptr, const T *evin = nullptr, const T *Xcell = nullptr);
-// coarse velocity = fine velocity at the shared nodes (fine index 2 * coarse
-// index per direction; h-coarsening at k <= 2 and p-coarsening 2 -> 1)
+               T *qd, hipStream_t s, T *ev = nullptr, const T *evin = nullptr, const T *Xcell = nullptr,
+               const NsPoint<T> *pt = nullptr);
+// coarse fields = fine fields at the shared nodes (fine index 2 * coarse
+// index per direction; h-coarsening at k <= 2 and p-coarsening 2 -> 1), for
+// ncomp blocked components (dim when ncomp <= 0)
 void launch_ns_inject(const LevelGeom &fine, const LevelGeom &coarse, const double *u_fine, double *u_coarse,
-                      hipStream_t s);
+                      hipStream_t s, int ncomp = 0);
 // node colouring by (i mod q, j mod q, l mod q): with q = k+1 no two nodes of
 // a colour share a cell.  indicator: out = 1 on component `comp` at the nodes
 // of `color`, 0 elsewhere (ncomp*Nv entries); extract: diag[comp*Nv + i] =

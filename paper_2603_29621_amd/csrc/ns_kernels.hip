@@ -13,8 +13,17 @@
 // reference Hessian (exact on affine cells).
 //
 // The linearisation kernel stores per quadrature point: u0 (3), grad u0 (9,
-// [comp][direction]), R(u0) (3), delta_1 (1): NS_QD = 16 values, laid out
-// [cell][field][point] so the threads of a cell read consecutive words.
+// [comp][direction]), R(u0) (3), delta_1 (1), and for the nonlinear residual
+// the Galerkin value term alpha (u0 - u~) + u0.grad u0 (3) and p0 (1):
+// NS_QD = 20 values, laid out [cell][field][point] so the threads of a cell
+// read consecutive words.  At a general state (u0, p0) with the BDF2 history
+// u~ = (4 u^n - u^{n-1}) / 3 (time derivative alpha (u - u~)), the strong
+// residual is R(u0, p0) = alpha (u0 - u~) + u0.grad u0 + grad p0 - nu Lap u0;
+// the linearisation point of a Jacobian alone has p0 = 0 and u~ = u0.
+//
+// The residual kernel tests F_NS + F_SUPG + F_PSPG at that state from the
+// stored data alone: (alpha (u - u~) + u.grad u, v) + (nu grad u - p I
+// + delta_1 R (x) u, grad v) + (div u, q) + (delta_1 R, grad q).
 #include <algorithm>
 
 #include "cell_common.h"
@@ -46,7 +55,24 @@ struct Args {
   // and the node grid are unused and ev takes the same layout
   const T *evin;
   const T *Xcell;
+  // linearisation at a general state: src = [u0 (DIM Nv) | p0 (Nv) | u~ (DIM
+  // Nv)] (with evin: slot 3 = p0, u~ in evhist slots 0..2); 0: src = u0
+  // alone, p0 = 0, u~ = u0
+  int point;
+  int keep_delta;  // leave delta_1 (field 15) as it is
+  const T *evhist;
+  // cells of this launch: all (colour < 0) or those whose index parities are
+  // the bits of `colour` (no two share a node: with one launch per colour in
+  // a fixed order, the atomic accumulation is deterministic)
+  int colour, cm0, cm1, nlaunch;
 };
+
+template <typename T>
+__device__ __forceinline__ int launch_cell(const Args<T> &a, int i) {
+  if (a.colour < 0) return i;
+  const int x = i % a.cm0, r = i / a.cm0, y = r % a.cm1, z = r / a.cm1;
+  return (2 * x + (a.colour & 1)) + a.n0 * ((2 * y + ((a.colour >> 1) & 1)) + a.n1 * (2 * z + (a.colour >> 2)));
+}
 
 template <int DIM, typename T>
 __device__ __forceinline__ T jac_inv(const T *Xc, const T xi[3], T I[3][3]) {
@@ -240,8 +266,9 @@ __device__ __forceinline__ T laplacian(const T h[6], const T I[3][3]) {
   Ctx<DIM, K, T> c;                                                                                    \
   int e;                                                                                               \
   Sh::map(tid, e, c.t, c.active);                                                                      \
-  const int cell = blockIdx.x * CPB + e;                                                               \
-  c.valid = c.active && cell < a.ncells;                                                               \
+  const int lin_ = blockIdx.x * CPB + e;                                                               \
+  c.valid = c.active && lin_ < a.nlaunch;                                                              \
+  const int cell = c.valid ? launch_cell(a, lin_) : 0;                                                 \
   c.qi = c.t % Q;                                                                                      \
   c.qj = (c.t / Q) % Q;                                                                                \
   c.ql = DIM == 3 ? c.t / (Q * Q) : 0;                                                                 \
@@ -302,7 +329,6 @@ template <int DIM, int K, typename T, bool CART>
 __global__ void __launch_bounds__((Shape<DIM, K>::BLOCK)) ns_linearize_kernel(Args<T> a) {
   NSK_PROLOGUE
   NSK_PROLOGUE_B
-  __shared__ T s_vol[CPB];
   T u[3] = {}, U[3][3] = {}, lap[3] = {};
   for (int comp = 0; comp < DIM; ++comp) {
     T v0 = T(0);
@@ -319,18 +345,43 @@ __global__ void __launch_bounds__((Shape<DIM, K>::BLOCK)) ns_linearize_kernel(Ar
     }
     lap[comp] = CART ? laplacian_cart<DIM>(h, I) : laplacian<DIM>(h, I);
   }
-  // cell volume
-  if (c.active && c.t == 0) s_vol[e] = 0;
+  // the state's pressure and the BDF2 history (u~ = u0 and p0 = 0 otherwise)
+  T p0 = 0, gp0[3] = {}, uh[3] = {u[0], u[1], u[2]};
+  if (a.point) {
+    T v0 = T(0);
+    if (c.valid) v0 = a.evin ? a.evin[((int64_t)cell * NQ + c.t) * 4 + 3] : a.src[DIM * a.Nv + nd];
+    if (c.active) c.b0[c.t] = v0;
+    csync<Sh::WAVE>();
+    T g[3], h[6];
+    c.template evaluate<false>(p0, g, h);
+    for (int x = 0; x < DIM; ++x) {
+      T s = 0;
+      for (int b = 0; b < DIM; ++b) s += I[b][x] * g[b];
+      gp0[x] = s;
+    }
+    for (int comp = 0; comp < DIM; ++comp) {
+      v0 = T(0);
+      if (c.valid)
+        v0 = a.evhist ? a.evhist[((int64_t)cell * NQ + c.t) * 4 + comp] : a.src[(DIM + 1 + comp) * a.Nv + nd];
+      if (c.active) c.b0[c.t] = v0;
+      csync<Sh::WAVE>();
+      c.template evaluate<false>(uh[comp], g, h);
+    }
+  }
+  // cell volume: every thread sums the JxW of its cell's points in a fixed order
+  if (c.active) c.b0[c.t] = c.valid ? JxW : T(0);
   csync<Sh::WAVE>();
-  if (c.valid) atomicAdd(&s_vol[e], JxW);
+  T vol = 0;
+  for (int q = 0; q < NQ; ++q) vol += c.b0[q];
   csync<Sh::WAVE>();
-  const T hK = pow(s_vol[e], T(1) / T(DIM)) / T(K);
-  T speed2 = 0, R0[3];
+  const T hK = pow(vol, T(1) / T(DIM)) / T(K);
+  T speed2 = 0, R0[3], gal[3];
   for (int comp = 0; comp < DIM; ++comp) {
     speed2 += u[comp] * u[comp];
     T s = 0;
     for (int x = 0; x < DIM; ++x) s += u[x] * U[comp][x];
-    R0[comp] = s - a.nu * lap[comp];
+    gal[comp] = a.alpha * (u[comp] - uh[comp]) + s;
+    R0[comp] = gal[comp] + gp0[comp] - a.nu * lap[comp];
   }
   const T t1 = T(2) / a.dt, t2 = T(2) * sqrt(speed2) / hK, t3 = T(4) * a.nu / (hK * hK);
   const T delta = T(1) / sqrt(t1 * t1 + t2 * t2 + T(9) * t3 * t3);
@@ -340,21 +391,32 @@ __global__ void __launch_bounds__((Shape<DIM, K>::BLOCK)) ns_linearize_kernel(Ar
       if (f < 3) v = f < DIM ? u[f] : T(0);
       else if (f < 12) v = ((f - 3) / 3 < DIM && (f - 3) % 3 < DIM) ? U[(f - 3) / 3][(f - 3) % 3] : T(0);
       else if (f < 15) v = f - 12 < DIM ? R0[f - 12] : T(0);
-      else v = delta;
+      else if (f == 15) {
+        if (a.keep_delta) continue;
+        v = delta;
+      } else if (f < 19) v = f - 16 < DIM ? gal[f - 16] : T(0);
+      else v = p0;
       qd[f * NQ] = v;
     }
   }
 }
 
 // Jacobian application (CART: every cell an axis-aligned box)
-template <int DIM, int K, typename T, bool CART>
+// RES: the nonlinear residual at the stored state instead (no source vector)
+template <int DIM, int K, typename T, bool CART, bool RES>
 __global__ void __launch_bounds__((Shape<DIM, K>::BLOCK)) ns_jacobian_kernel(Args<T> a) {
   NSK_PROLOGUE
   // every global load of the point (nodal source values of the 4 fields,
   // linearisation data) is issued before the vertex loads and the barrier
   T sv[4] = {0, 0, 0, 0};
   T u0[3] = {}, U[3][3] = {}, R0[3] = {}, dl = 0;
-  if (c.valid && a.evin) {
+  T gal[3] = {}, p0 = 0;
+  if (RES) {
+    if (c.valid) {
+      for (int x = 0; x < DIM; ++x) gal[x] = qd[(16 + x) * NQ];
+      p0 = qd[19 * NQ];
+    }
+  } else if (c.valid && a.evin) {
     for (int comp = 0; comp <= DIM; ++comp) sv[comp] = a.evin[((int64_t)cell * NQ + c.t) * 4 + comp];
   } else if (c.valid) {
     for (int comp = 0; comp < DIM; ++comp) sv[comp] = dir ? T(0) : a.src[comp * a.Nv + nd];
@@ -368,6 +430,16 @@ __global__ void __launch_bounds__((Shape<DIM, K>::BLOCK)) ns_jacobian_kernel(Arg
     dl = qd[15 * NQ];
   }
   NSK_PROLOGUE_B
+  T val_u[3], grad_u[3][3], Rl[3];
+  T div = 0;
+  if constexpr (RES) {
+    for (int cc = 0; cc < DIM; ++cc) {
+      val_u[cc] = gal[cc];
+      Rl[cc] = R0[cc];
+      div += U[cc][cc];
+      for (int x = 0; x < DIM; ++x) grad_u[cc][x] = a.nu * U[cc][x] + dl * R0[cc] * u0[x] - (x == cc ? p0 : T(0));
+    }
+  } else {
   // trial fields
   T w[3] = {}, G[3][3] = {}, L[3] = {};
   for (int comp = 0; comp < DIM; ++comp) {
@@ -396,7 +468,6 @@ __global__ void __launch_bounds__((Shape<DIM, K>::BLOCK)) ns_jacobian_kernel(Arg
     }
   }
   // point physics
-  T val_u[3], grad_u[3][3], Rl[3];
   for (int cc = 0; cc < DIM; ++cc) {
     T conv = 0, newt = 0;
     for (int x = 0; x < DIM; ++x) {
@@ -407,7 +478,6 @@ __global__ void __launch_bounds__((Shape<DIM, K>::BLOCK)) ns_jacobian_kernel(Arg
     val_u[cc] = a.alpha * w[cc] + newt + conv;
     Rl[cc] = val_u[cc] + gP[cc] - a.nu * L[cc];
   }
-  T div = 0;
   for (int cc = 0; cc < DIM; ++cc) {
     div += G[cc][cc];
     for (int x = 0; x < DIM; ++x) {
@@ -416,6 +486,7 @@ __global__ void __launch_bounds__((Shape<DIM, K>::BLOCK)) ns_jacobian_kernel(Arg
       if (x == cc) v -= P;
       grad_u[cc][x] = v;
     }
+  }
   }
   // test: physical gradient coefficients -> reference (I f), times JxW
   for (int comp = 0; comp < DIM; ++comp) {
@@ -457,7 +528,7 @@ __global__ void __launch_bounds__((Shape<DIM, K>::BLOCK)) ns_jacobian_kernel(Arg
 
 template <typename T>
 void launch_ns(const LevelGeom &g, const T *X, const T *tab, int what, T nu, T dt, int newton, const T *src, T *dst,
-               T *qd, hipStream_t s, T *ev, const T *evin, const T *Xcell) {
+               T *qd, hipStream_t s, T *ev, const T *evin, const T *Xcell, const NsPoint<T> *pt) {
   MFS_REQUIRE(g.kp == g.k, MFS_EUNSUPPORTED, "Navier-Stokes operator needs equal-order elements");
   nsk::Args<T> a{};
   a.n0 = g.n[0];
@@ -483,14 +554,27 @@ void launch_ns(const LevelGeom &g, const T *X, const T *tab, int what, T nu, T d
               "cell-local Navier-Stokes inputs need 3D, corner coordinates and cell-local outputs");
   a.evin = evin;
   a.Xcell = Xcell;
+  MFS_REQUIRE(what >= 0 && what <= 2, MFS_EINVAL, "launch_ns: what = %d", what);
+  if (pt) {
+    MFS_REQUIRE(what == 0 && (evin == nullptr || pt->evhist != nullptr), MFS_EINVAL,
+                "a general linearisation state needs the history (cell-local with evin)");
+    a.point = 1;
+    a.keep_delta = pt->keep_delta;
+    a.evhist = pt->evhist;
+  }
+  a.colour = -1;
+  a.nlaunch = (int)g.ncells;
+  auto go = [&](const nsk::Args<T> &aa) {
 #define NS_GO2(D, KK, C)                                                                                         \
   {                                                                                                              \
     using Sh = nsk::Shape<D, KK>;                                                                                \
-    const int grid = (int)((g.ncells + Sh::CPB - 1) / Sh::CPB);                                                  \
+    const int grid = (aa.nlaunch + Sh::CPB - 1) / Sh::CPB;                                                       \
     if (what == 0)                                                                                               \
-      hipLaunchKernelGGL((nsk::ns_linearize_kernel<D, KK, T, C>), dim3(grid), dim3(Sh::BLOCK), 0, s, a);         \
+      hipLaunchKernelGGL((nsk::ns_linearize_kernel<D, KK, T, C>), dim3(grid), dim3(Sh::BLOCK), 0, s, aa);        \
+    else if (what == 1)                                                                                          \
+      hipLaunchKernelGGL((nsk::ns_jacobian_kernel<D, KK, T, C, false>), dim3(grid), dim3(Sh::BLOCK), 0, s, aa);  \
     else                                                                                                         \
-      hipLaunchKernelGGL((nsk::ns_jacobian_kernel<D, KK, T, C>), dim3(grid), dim3(Sh::BLOCK), 0, s, a);          \
+      hipLaunchKernelGGL((nsk::ns_jacobian_kernel<D, KK, T, C, true>), dim3(grid), dim3(Sh::BLOCK), 0, s, aa);   \
   }
 #define NS_GO(D, KK)        \
   {                         \
@@ -499,33 +583,51 @@ void launch_ns(const LevelGeom &g, const T *X, const T *tab, int what, T nu, T d
     else                    \
       NS_GO2(D, KK, false)  \
   }
-  if (g.dim == 2) {
-    if (g.k == 1) NS_GO(2, 1) else if (g.k == 2) NS_GO(2, 2) else if (g.k == 3) NS_GO(2, 3)
-    else MFS_REQUIRE(false, MFS_EUNSUPPORTED, "Navier-Stokes degree %d", g.k);
-  } else {
-    if (g.k == 1) NS_GO(3, 1) else if (g.k == 2) NS_GO(3, 2) else if (g.k == 3) NS_GO(3, 3)
-    else MFS_REQUIRE(false, MFS_EUNSUPPORTED, "Navier-Stokes degree %d", g.k);
-  }
+    if (aa.nlaunch == 0) return;
+    if (g.dim == 2) {
+      if (g.k == 1) NS_GO(2, 1) else if (g.k == 2) NS_GO(2, 2) else if (g.k == 3) NS_GO(2, 3)
+      else MFS_REQUIRE(false, MFS_EUNSUPPORTED, "Navier-Stokes degree %d", g.k);
+    } else {
+      if (g.k == 1) NS_GO(3, 1) else if (g.k == 2) NS_GO(3, 2) else if (g.k == 3) NS_GO(3, 3)
+      else MFS_REQUIRE(false, MFS_EUNSUPPORTED, "Navier-Stokes degree %d", g.k);
+    }
 #undef NS_GO
 #undef NS_GO2
+  };
+  if (what != 0 && ev == nullptr && g.dim == 3) {
+    // atomic accumulation into the node grid (3D): one launch per cell
+    // colour, in a fixed order, so that the result is deterministic
+    for (int col = 0; col < 8; ++col) {
+      nsk::Args<T> ac = a;
+      const int px = col & 1, py = (col >> 1) & 1, pz = col >> 2;
+      ac.colour = col;
+      ac.cm0 = (g.n[0] - px + 1) / 2;
+      ac.cm1 = (g.n[1] - py + 1) / 2;
+      ac.nlaunch = ac.cm0 * ac.cm1 * ((g.n[2] - pz + 1) / 2);
+      go(ac);
+    }
+  } else {
+    go(a);
+  }
   MFS_HIP(hipGetLastError());
 }
 
 template void launch_ns<double>(const LevelGeom &, const double *, const double *, int, double, double, int,
                                 const double *, double *, double *, hipStream_t, double *, const double *,
-                                const double *);
+                                const double *, const NsPoint<double> *);
 template void launch_ns<float>(const LevelGeom &, const float *, const float *, int, float, float, int, const float *,
-                               float *, float *, hipStream_t, float *, const float *, const float *);
+                               float *, float *, hipStream_t, float *, const float *, const float *,
+                               const NsPoint<float> *);
 
 namespace {
 
-__global__ void k_ns_inject(int dim, int nf0, int nf1, int64_t Nf, int nc0, int nc1, int64_t Nc, const double *uf,
+__global__ void k_ns_inject(int ncomp, int nf0, int nf1, int64_t Nf, int nc0, int nc1, int64_t Nc, const double *uf,
                             double *uc) {
   const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (c >= Nc) return;
   const int64_t i = c % nc0, j = (c / nc0) % nc1, l = c / ((int64_t)nc0 * nc1);
   const int64_t f = 2 * i + (int64_t)nf0 * (2 * j + (int64_t)nf1 * 2 * l);
-  for (int comp = 0; comp < dim; ++comp) uc[comp * Nc + c] = uf[comp * Nf + f];
+  for (int comp = 0; comp < ncomp; ++comp) uc[comp * Nc + c] = uf[comp * Nf + f];
 }
 
 __device__ __forceinline__ int node_color(const LevelGeom &g, int q, int64_t i) {
@@ -557,11 +659,12 @@ unsigned blocks_for(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<
 }  // namespace
 
 void launch_ns_inject(const LevelGeom &fine, const LevelGeom &coarse, const double *u_fine, double *u_coarse,
-                      hipStream_t s) {
+                      hipStream_t s, int ncomp) {
   for (int a = 0; a < fine.dim; ++a)
     MFS_REQUIRE(fine.nv[a] == 2 * coarse.nv[a] - 1, MFS_EUNSUPPORTED,
                 "coarse nodes are not every second fine node (degree > 2)");
-  hipLaunchKernelGGL(k_ns_inject, dim3((unsigned)((coarse.Nv + 255) / 256)), dim3(256), 0, s, fine.dim, fine.nv[0],
+  if (ncomp <= 0) ncomp = fine.dim;
+  hipLaunchKernelGGL(k_ns_inject, dim3((unsigned)((coarse.Nv + 255) / 256)), dim3(256), 0, s, ncomp, fine.nv[0],
                      fine.nv[1], fine.Nv, coarse.nv[0], coarse.nv[1], coarse.Nv, u_fine, u_coarse);
   MFS_HIP(hipGetLastError());
 }

@@ -5,8 +5,10 @@ loop admits a request when its planned device footprint fits the memory
 budget (no head-of-line blocking: a request that does not fit yet is passed
 over for younger ones that do, until it has waited ``max_bypass_s``; then
 admission stops until it fits).  Each admitted request gets its own HIP
-stream and problem handle; setup (mesh upload, multigrid hierarchy, right-hand
-side) runs on worker threads, and the main thread advances every active
+stream and problem handle, whose device memory is one arena from torch's
+allocator (``mfs_setup_arena``; releasing it does not wait for the device);
+setup (mesh upload, multigrid hierarchy, right-hand side) runs on worker
+threads, and the main thread advances every active
 solve by one FGMRES iteration whenever its previous iteration has finished
 (``mfs_solve_advance`` never blocks).  Kernels of different requests
 therefore overlap on the device, and a request's Krylov state, mesh and
@@ -77,17 +79,23 @@ def _dummy_vertices(n):
 
 
 class _Active:
-    __slots__ = ("req", "h", "stream", "b", "x", "fp", "admitted")
+    __slots__ = ("req", "h", "stream", "b", "x", "fp", "admitted", "arena")
 
 
 def _setup_request(req, opts, stream):
-    """Build the problem and its right-hand side on `stream` (worker thread)."""
+    """Build the problem in an arena from torch's allocator and its right-hand
+    side on `stream` (worker thread).  Returns (handle, b, x, arena); the arena
+    must stay alive until the handle is destroyed.  Releasing it returns the
+    block to torch's cache, which does not wait for the device."""
     import torch
 
     import inputs
 
     X = inputs.structured_vertices(3, [req.n] * 3, noise=req.noise, seed=req.mesh_seed)
-    h = mfs.mfs_setup(3, [req.n] * 3, X, req.k, req.nu, opts, stream=stream.cuda_stream)
+    fp = mfs.mfs_footprint(3, [req.n] * 3, X, req.k, opts)
+    with torch.cuda.stream(stream):
+        arena = torch.empty(fp, dtype=torch.uint8, device="cuda")
+    h = mfs.mfs_setup_arena(3, [req.n] * 3, X, req.k, req.nu, arena, opts, stream=stream.cuda_stream)
     nv, np_ = mfs.mfs_n_dofs(h, 0)
     N = 3 * nv + np_
     nq = req.n ** 3 * (req.k + 1) ** 3
@@ -102,7 +110,7 @@ def _setup_request(req, opts, stream):
         x = torch.zeros(N, dtype=torch.float64, device="cuda")
         stream.synchronize()
         del f, uD
-    return h, b, x
+    return h, b, x, arena
 
 
 class Server:
@@ -160,10 +168,11 @@ class Server:
                 for rid in list(setups):
                     r, s, adm, fut = setups[rid]
                     if fut.done():
-                        h, b, x = fut.result()
+                        h, b, x, arena = fut.result()
                         mfs.mfs_solve_begin(h, b, x, self.opts, stream=s.cuda_stream)
                         a = _Active()
                         a.req, a.h, a.stream, a.b, a.x, a.fp, a.admitted = r, h, s, b, x, fps[rid], adm
+                        a.arena = arena
                         active[rid] = a
                         del setups[rid]
                         progressed = True
@@ -179,6 +188,7 @@ class Server:
                         if on_result is not None:
                             on_result(res)
                         mfs.mfs_destroy(a.h)
+                        a.arena = None
                         with lock:
                             used -= a.fp
                         streams.append(a.stream)
@@ -206,7 +216,7 @@ def run_sequential(requests, precond=mfs.MFS_FP64, rtol=1e-8, maxit=300, realtim
             if wait > 0:
                 time.sleep(wait)
         adm = time.perf_counter() - t0
-        h, b, x = _setup_request(r, opts, s)
+        h, b, x, arena = _setup_request(r, opts, s)
         info = mfs.mfs_solve(h, b, x, opts, stream=s.cuda_stream)
         t = time.perf_counter() - t0
         out.append(Result(r.rid, r.n, r.k, r.nu, r.arrival if realtime else 0.0, adm, t, info.iterations,
@@ -214,6 +224,7 @@ def run_sequential(requests, precond=mfs.MFS_FP64, rtol=1e-8, maxit=300, realtim
         if on_result is not None:
             on_result(out[-1])
         mfs.mfs_destroy(h)
+        del arena
     return out
 
 

@@ -450,3 +450,38 @@ def test_solve_3d_mixed_precision():
         assert err <= 1.5 * bound + 1e-12 * np.linalg.norm(xd)
     finally:
         mfs.mfs_destroy(h)
+
+
+def test_setup_in_caller_arena():
+    """mfs_setup_arena carves the problem from a caller's uint8 tensor: the
+    same operator and solve as mfs_setup, a too small arena is rejected, and
+    destroying the problem leaves the arena to its owner."""
+    dim, n, k, nu = 3, [4, 4, 4], 2, 0.6
+    X = inputs.structured_vertices(dim, n, noise=0.2, seed=2)
+    opts = mfs.mfs_default_options(rtol=1e-10, precond_precision=mfs.MFS_FP64)
+    fp = mfs.mfs_footprint(dim, n, X, k, opts)
+    small = torch.empty(fp - 256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(mfs.MfsError) as e:
+        mfs.mfs_setup_arena(dim, n, X, k, nu, small, opts)
+    assert e.value.code == mfs.MFS_ENOMEM
+    arena = torch.full((fp,), 7, dtype=torch.uint8, device="cuda")
+    h1 = mfs.mfs_setup(dim, n, X, k, nu, opts)
+    h2 = mfs.mfs_setup_arena(dim, n, X, k, nu, arena, opts)
+    try:
+        nv, np_ = mfs.mfs_n_dofs(h1, 0)
+        x = cuda(inputs.uniform_vector(dim * nv + np_, 5))
+        y1, y2 = torch.empty_like(x), torch.empty_like(x)
+        mfs.mfs_vmult(h1, mfs.MFS_OP_STOKES, mfs.MFS_FP64, 0, y1, x)
+        mfs.mfs_vmult(h2, mfs.MFS_OP_STOKES, mfs.MFS_FP64, 0, y2, x)
+        torch.cuda.synchronize()
+        assert torch.equal(y1, y2)
+        s1, s2 = torch.zeros_like(x), torch.zeros_like(x)
+        i1 = mfs.mfs_solve(h1, y1, s1, opts)
+        i2 = mfs.mfs_solve(h2, y1, s2, opts)
+        assert i1.iterations == i2.iterations and torch.equal(s1, s2)
+    finally:
+        mfs.mfs_destroy(h1)
+        mfs.mfs_destroy(h2)
+    arena.fill_(1)  # still the caller's memory
+    torch.cuda.synchronize()
+    assert int(arena.sum()) == fp
