@@ -108,6 +108,78 @@ def cpu_baseline_oracle(n=12, k=2):
                       f"{reps} repetitions, element loop with element matrices by full quadrature, 1 thread"}
 
 
+def spacetime_section(mfs, torch, X, args):
+    """Space-time Kronecker operator (G_Q (x) M + tau I_Q (x) A) of Sec. 4 on
+    the headline mesh (Q2/Q1, 64^3 trilinear cells), DG(1) and DG(2) in time
+    (Q = 2, 3 stages), against Q separate Stokes vmults: DoFs/s counts the Q
+    stage vectors."""
+    from paper_2603_29621_amd import spacetime as pst
+
+    n, k = args.n, 2
+    h = mfs.mfs_setup(3, [n] * 3, X, k, 1.0, mfs.mfs_default_options(mg_levels=0))
+    out = {"workload": f"Q2/Q1 {n}^3 trilinear cells, tau = 1e-2, DG(Q-1) in time"}
+    try:
+        nv, np_ = mfs.mfs_n_dofs(h, 0)
+        N = 3 * nv + np_
+        for Q in (2, 3):
+            G = pst.dg_stage_matrices(Q - 1)[0]
+            for prec, name in ((mfs.MFS_FP64, "f64"), (mfs.MFS_FP32, "f32")):
+                dt = torch.float64 if prec == mfs.MFS_FP64 else torch.float32
+                x = torch.rand(Q * N, dtype=dt, device="cuda") * 2 - 1
+                y = torch.empty_like(x)
+                w = torch.empty(Q * 3 * nv, dtype=dt, device="cuda")
+                stream = torch.cuda.current_stream()
+                for _ in range(3):
+                    mfs.mfs_st_vmult(h, G, 1e-2, prec, y, x, w)
+                torch.cuda.synchronize()
+                reps = max(5, args.steps // 2)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for _ in range(reps):
+                    mfs.mfs_st_vmult(h, G, 1e-2, prec, y, x, w)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                t = e0.elapsed_time(e1) * 1e-3 / reps
+                out[f"Q{Q}_{name}"] = {"us": t * 1e6, "stage_dofs_per_s": Q * N / t}
+                del x, y, w
+        progress("space-time operator done")
+    finally:
+        mfs.mfs_destroy(h)
+    return out
+
+
+def oracle_checks(mfs, torch, inputs):
+    """Mixed-precision solves (FP32 multigrid inside FP64 FGMRES to 1e-8, as
+    served) on small meshes, each compared with the oracle's sparse direct
+    solve of the same system: relative error and the oracle's FP64 residual
+    of the GPU solution.  Part of the CPU-baseline leg (the only leg that runs
+    the oracle)."""
+    from oracle import fem, solve
+    from paper_2603_29621_amd import serving
+
+    out = []
+    for i, (n, k, nu) in enumerate(((8, 2, 0.05), (4, 3, 0.4), (4, 4, 0.013), (6, 3, 1.0))):
+        req = inputs.Request(i, 0.0, n, k, nu, 0.1, 7 + i)
+        opts = mfs.mfs_default_options(precond_precision=mfs.MFS_FP32, rtol=1e-8, maxit=300)
+        s = torch.cuda.Stream()
+        h, b, x, arena = serving._setup_request(req, opts, s)
+        info = mfs.mfs_solve(h, b, x, opts, stream=s.cuda_stream)
+        mfs.mfs_destroy(h)
+        xg = x.cpu().numpy()
+        X = inputs.structured_vertices(3, [n] * 3, noise=0.1, seed=7 + i)
+        S = fem.Space(3, [n] * 3, X, k)
+        mats = fem.assemble_stokes(S, nu)
+        f = inputs.manufactured_3d(S.geometry()[0], nu)[2]
+        bo = solve.stokes_rhs(S, nu, f, np.zeros((S.Nv, 3)), mats)
+        xd = solve.pressure_mean_free(S, solve.direct_solve(S, nu, bo, mats), mats["M"])
+        K = fem.constrain(mats["K"], S.velocity_dirichlet_mask())
+        out.append({"n": n, "k": k, "nu": nu, "n_dofs": S.n_dofs, "iterations": info.iterations,
+                    "rel_error_vs_oracle": float(np.linalg.norm(xg - xd) / np.linalg.norm(xd)),
+                    "oracle_rel_residual": float(np.linalg.norm(bo - K @ xg) / np.linalg.norm(bo))})
+        progress(f"oracle check n={n} k={k}: error {out[-1]['rel_error_vs_oracle']:.2e}")
+    return out
+
+
 def solve_2d_section(mfs, torch, inputs, reps=5):
     """The small 2D case: Q2/Q1 on 16 x 16 Cartesian cells of the unit square,
     nu = 1, the manufactured solution u = curl(sin^2(pi x) sin^2(pi y)),
@@ -147,31 +219,51 @@ def solve_2d_section(mfs, torch, inputs, reps=5):
 
 
 def solve_section(mfs, torch, inputs, args):
-    """3D Q2/Q1 solve on the same perturbed mesh to a 1e-8 relative residual:
-    FP32 multigrid preconditioner inside FP64 FGMRES vs the plain FP64 method."""
+    """3D Q_k/Q_{k-1} solves (k = 2, 3, 4) on the perturbed mesh to a 1e-8
+    relative residual: FP32 multigrid preconditioner inside FP64 FGMRES vs the
+    plain FP64 method.  Each result's error is reported against a reference
+    solve of the same system on the same GPU (FP64 preconditioner, FGMRES to
+    1e-12)."""
     from paper_2603_29621_amd import serving
 
-    n, k = args.solve_n, 2
-    req = inputs.Request(0, 0.0, n, k, 1.0, 0.2, 0)
-    out = {"workload": f"3D Stokes Q2/Q1 {n}^3 cells, vertex noise 0.2h, nu=1, manufactured solution, rtol 1e-8"}
-    for name, prec in (("fp32_mg_fp64_fgmres", mfs.MFS_FP32), ("fp64", mfs.MFS_FP64)):
-        opts = mfs.mfs_default_options(precond_precision=prec, rtol=1e-8, maxit=300, graphs=args.graphs)
-        s = torch.cuda.Stream()
-        t0 = time.perf_counter()
-        h, b, x = serving._setup_request(req, opts, s)
-        t1 = time.perf_counter()
-        times, its, res = [], 0, 0.0
-        for rep in range(2):
-            x.zero_()
+    n = args.solve_n
+    out = {"workload": f"3D Stokes Q_k/Q_k-1 {n}^3 cells, vertex noise 0.2h, nu=1, manufactured solution, rtol 1e-8",
+           "error_reference": "FP64-preconditioned FGMRES to rtol 1e-12 on the same GPU"}
+    for k in args.solve_k:
+        req = inputs.Request(0, 0.0, n, k, 1.0, 0.2, 0)
+        res = {}
+        ref = None
+        for name, prec, rtol in (("reference", mfs.MFS_FP64, 1e-12), ("fp32_mg_fp64_fgmres", mfs.MFS_FP32, 1e-8),
+                                 ("fp64", mfs.MFS_FP64, 1e-8)):
+            opts = mfs.mfs_default_options(precond_precision=prec, rtol=rtol, maxit=300, graphs=args.graphs)
+            s = torch.cuda.Stream()
+            t0 = time.perf_counter()
+            h, b, x, arena = serving._setup_request(req, opts, s)
+            t1 = time.perf_counter()
+            times, its, rr = [], 0, 0.0
+            for rep in range(1 if name == "reference" else 2):
+                x.zero_()
+                torch.cuda.synchronize()
+                t2 = time.perf_counter()
+                info = mfs.mfs_solve(h, b, x, opts, stream=s.cuda_stream)
+                times.append(time.perf_counter() - t2)
+                its, rr = info.iterations, info.rel_residual
+            mfs.mfs_destroy(h)
             torch.cuda.synchronize()
-            t2 = time.perf_counter()
-            info = mfs.mfs_solve(h, b, x, opts, stream=s.cuda_stream)
-            times.append(time.perf_counter() - t2)
-            its, res = info.iterations, info.rel_residual
-        mfs.mfs_destroy(h)
-        out[name] = {"setup_s": t1 - t0, "solve_s": min(times), "solves_per_s": 1.0 / min(times),
-                     "iterations": its, "rel_residual": res}
-    out["speedup_mixed_vs_fp64"] = out["fp64"]["solve_s"] / out["fp32_mg_fp64_fgmres"]["solve_s"]
+            if name == "reference":
+                ref = x
+                res["reference"] = {"iterations": its, "rel_residual": rr}
+                continue
+            err = float(torch.linalg.norm(x - ref) / torch.linalg.norm(ref))
+            res[name] = {"setup_s": t1 - t0, "solve_s": min(times), "solves_per_s": 1.0 / min(times),
+                         "iterations": its, "rel_residual": rr, "rel_error_vs_reference": err}
+            del x, b
+        del ref
+        res["n_dofs"] = algorithmic_bytes(3, n, k, 8)[0]
+        res["speedup_mixed_vs_fp64"] = res["fp64"]["solve_s"] / res["fp32_mg_fp64_fgmres"]["solve_s"]
+        out[f"Q{k}Q{k - 1}"] = res
+        progress(f"solve Q{k}Q{k - 1} {n}^3: {res['fp32_mg_fp64_fgmres']['solve_s']:.3f} s mixed, "
+                 f"{res['fp64']['solve_s']:.3f} s FP64")
     return out
 
 
@@ -214,6 +306,8 @@ def ns_section(mfs, torch, inputs, args):
     # the same Jacobian on the locally refined mesh (hanging nodes)
     if args.ns_refined:
         out["refined"] = refined_ns_section(mfs, torch, inputs, args, dt, nu)
+    if args.ns_jacobian_only:
+        return out
     # Newton-step solve
     n, k = args.ns_solve_n, 2
     X = inputs.structured_vertices(3, [n] * 3)
@@ -246,6 +340,53 @@ def ns_section(mfs, torch, inputs, args):
             mfs.mfs_destroy(h)
     solve["speedup_mixed_vs_fp64"] = solve["fp64"]["solve_s"] / solve["fp32_mg_fp64_fgmres"]["solve_s"]
     out["solve"] = solve
+    return out
+
+
+def refined_full_solve(mfs, torch, inputs, args, dt, nu, F):
+    """The Newton-step solve J x = J y (y ~ U[-1, 1], Dirichlet rows of b = y)
+    at the full refined size: n^3 base cells + 2 levels in the seeded sphere,
+    Q2Q2, Newton linearisation about the Fourier field; one set-up, then FGMRES
+    to 1e-8 with the FP32 monolithic multigrid and with the FP64 one."""
+    n, k = args.ns_n, 2
+    mesh = inputs.refined_mesh(n, seed=0, levels=2, radius=0.15)
+    opts = mfs.mfs_default_options(pressure_offset=0, mg_levels=1, rtol=1e-8, maxit=200, graphs=args.graphs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h = mfs.mfs_setup_refined(mesh, k, nu, opts)
+    out = {"workload": f"Q2Q2 on {n}^3 base cells + 2 levels (radius 0.15, seed 0, {len(mesh['level'])} cells), "
+                       "J x = J y, rtol 1e-8, GC levels then the structured h and p levels"}
+    try:
+        nu_, _ = mfs.mfs_n_dofs(h, 0)
+        N = 4 * nu_
+        pts = mfs.mfs_support_points(h, k, nu_, 3)
+        u0 = np.empty((3, nu_))
+        for a in range(0, nu_, 1 << 22):
+            u0[:, a:a + (1 << 22)] = F(pts[a:a + (1 << 22)]).T
+        del pts
+        mfs.mfs_set_linearization(h, torch.from_numpy(u0.ravel()).cuda(), dt, 1)
+        del u0
+        torch.cuda.synchronize()
+        out.update({"N": N, "levels": mfs.mfs_n_levels(h), "setup_s": time.perf_counter() - t0})
+        progress(f"full refined set-up: {out['setup_s']:.1f} s, {N} DoFs")
+        y = torch.from_numpy(inputs.uniform_vector(N, 3)).cuda()
+        b = torch.empty_like(y)
+        mfs.mfs_vmult(h, mfs.MFS_OP_NS_JACOBIAN, mfs.MFS_FP64, 0, b, y)
+        del y
+        for name, prec in (("fp32_mg_fp64_fgmres", mfs.MFS_FP32), ("fp64", mfs.MFS_FP64)):
+            o = mfs.mfs_default_options(pressure_offset=0, mg_levels=1, precond_precision=prec, rtol=1e-8,
+                                        maxit=200, graphs=args.graphs)
+            x = torch.zeros(N, dtype=torch.float64, device="cuda")
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            info = mfs.mfs_solve(h, b, x, o)
+            out[name] = {"solve_s": time.perf_counter() - t2, "iterations": info.iterations,
+                         "rel_residual": info.rel_residual, "status": info.status}
+            progress(f"full refined solve {name}: {out[name]['solve_s']:.2f} s, {info.iterations} iterations")
+            del x
+    finally:
+        mfs.mfs_destroy(h)
+    out["speedup_mixed_vs_fp64"] = out["fp64"]["solve_s"] / out["fp32_mg_fp64_fgmres"]["solve_s"]
     return out
 
 
@@ -284,6 +425,15 @@ def refined_ns_section(mfs, torch, inputs, args, dt, nu):
             progress(f"refined Q{k}Q{k} Jacobian: set-up {setup:.1f} s, {res['f64']['avg_launch_us']:.0f} us FP64")
         finally:
             mfs.mfs_destroy(h)
+    if args.ns_jacobian_only:
+        return out
+    # load balance of the two multigrid hierarchies of this mesh for a Morton
+    # partition over 12 processes (the paper's 12 cores), host-side
+    t0 = time.perf_counter()
+    out["partition_metrics_p12"] = mfs.mfs_refined_mg_metrics(mesh, 12)
+    progress(f"partition metrics: {time.perf_counter() - t0:.1f} s, {out['partition_metrics_p12']}")
+    if args.ns_full_solve:
+        out["solve_full"] = refined_full_solve(mfs, torch, inputs, args, dt, nu, F)
     # Newton-step solve on the refined mesh of the solve size: monolithic
     # multigrid (global coarsening to the base mesh, then h and p)
     n, k = args.ns_solve_n, 2
@@ -324,6 +474,63 @@ def refined_ns_section(mfs, torch, inputs, args, dt, nu):
     return out
 
 
+def bdf2_section(mfs, torch, inputs, args):
+    """Three BDF2 steps of the stabilised Navier-Stokes equations (SUPG/PSPG,
+    Q1Q1 and Q2Q2, Re = 100: nu = 0.01 with the unit-RMS 8-mode Fourier field
+    as initial velocity, dt = 1e-2, zero velocity on the boundary) on n^3
+    base cells with 2 levels of local refinement in a sphere, by Newton's
+    method with FGMRES and one monolithic V-cycle (global coarsening, then h
+    and p) per iteration: FP32 multigrid against FP64 multigrid, Newton to
+    1e-8, corrections to 1e-6."""
+    n, dt, nu = args.ns_solve_n, 1e-2, 0.01
+    mesh = inputs.refined_mesh(n, seed=0, levels=2, radius=0.15)
+    F = inputs.fourier_field(0)
+    out = {"workload": f"{n}^3 base cells + 2 levels (radius 0.15, seed 0, {len(mesh['level'])} cells), BDF2 "
+                       f"dt={dt}, nu={nu}, 3 steps from the Fourier field, no-slip walls, Newton rtol 1e-8, "
+                       "FGMRES rtol 1e-6 per correction"}
+    for k in (1, 2):
+        states = {}
+        for name, prec in (("fp32_mg", mfs.MFS_FP32), ("fp64_mg", mfs.MFS_FP64)):
+            opts = mfs.mfs_default_options(pressure_offset=0, mg_levels=1, precond_precision=prec,
+                                           graphs=args.graphs)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            h = mfs.mfs_setup_refined(mesh, k, nu, opts)
+            setup = time.perf_counter() - t0
+            try:
+                nu_, _ = mfs.mfs_n_dofs(h, 0)
+                pts = mfs.mfs_support_points(h, k, nu_, 3)
+                wall = torch.from_numpy(np.any((pts == 0.0) | (pts == 1.0), axis=1)).cuda()
+                un = torch.from_numpy(F(pts).T.ravel().copy()).cuda()
+                unm1 = un.clone()
+                p = torch.zeros(nu_, dtype=torch.float64, device="cuda")
+                nopt = mfs.mfs_default_newton_options(precond_precision=prec)
+                steps = []
+                for step in range(3):
+                    x = torch.cat([un, p])
+                    for c in range(3):
+                        x[c * nu_:(c + 1) * nu_][wall] = 0.0
+                    info = mfs.mfs_ns_bdf2_step(h, un, unm1, x, dt, nopt)
+                    steps.append({"newton_iterations": info.newton_iterations,
+                                  "fgmres_iterations": info.linear_iterations, "res0": info.res0, "res": info.res,
+                                  "status": info.status, "seconds": info.seconds})
+                    unm1, un, p = un, x[:3 * nu_].clone(), x[3 * nu_:].clone()
+                states[name] = x
+                out[f"Q{k}Q{k}_{name}"] = {"N": 4 * nu_, "setup_s": setup, "steps": steps,
+                                           "seconds_per_step": float(np.mean([v["seconds"] for v in steps]))}
+                progress(f"BDF2 Q{k}Q{k} {name}: {[v['newton_iterations'] for v in steps]} Newton, "
+                         f"{[v['fgmres_iterations'] for v in steps]} FGMRES, "
+                         f"{out[f'Q{k}Q{k}_{name}']['seconds_per_step']:.2f} s per step")
+            finally:
+                mfs.mfs_destroy(h)
+        a, b = states["fp32_mg"], states["fp64_mg"]
+        out[f"Q{k}Q{k}_rel_diff_fp32_vs_fp64_mg"] = float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+        out[f"Q{k}Q{k}_speedup_fp32_mg"] = (out[f"Q{k}Q{k}_fp64_mg"]["seconds_per_step"]
+                                           / out[f"Q{k}Q{k}_fp32_mg"]["seconds_per_step"])
+        del states, a, b
+    return out
+
+
 def hp_section(mfs, torch, inputs, args):
     """hp-adaptive Stokes (Sec. 3, minimum rule): velocity degree drawn per
     4^3-cell block from {2..6} (seed 0), pressure k-1, n^3 cells, vertex noise
@@ -337,7 +544,8 @@ def hp_section(mfs, torch, inputs, args):
     out = {"workload": f"hp Stokes {n}^3 cells, k per 4^3 block uniform in 2..6 (seed 0), pressure k-1, "
                        f"vertex noise 0.1h, nu=1",
            "degree_histogram": {int(k): int((deg == k).sum()) for k in range(2, 7)}}
-    for name, prec in (("fp32_mg_fp64_fgmres", mfs.MFS_FP32), ("fp64", mfs.MFS_FP64)):
+    runs = (("fp32_mg_fp64_fgmres", mfs.MFS_FP32), ("fp64", mfs.MFS_FP64))
+    for name, prec in (runs[1:] if args.hp_vmult_only else runs):
         opts = mfs.mfs_default_options(precond_precision=prec, rtol=1e-8, maxit=300, graphs=args.graphs)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -353,6 +561,8 @@ def hp_section(mfs, torch, inputs, args):
                     _, per = time_vmult(mfs, torch, h, N, p, max(10, args.steps // 2), 3)
                     out[f"vmult_{pname}"] = {"dofs_per_s": N / float(per.mean()),
                                              "avg_launch_us": float(per.mean()) * 1e6}
+                if args.hp_vmult_only:
+                    return out
             y = torch.from_numpy(inputs.uniform_vector(N, 3)).cuda()
             b = torch.empty_like(y)
             mfs.mfs_vmult(h, mfs.MFS_OP_STOKES, mfs.MFS_FP64, 0, b, y)  # Dirichlet rows of b carry y
@@ -372,25 +582,75 @@ def hp_section(mfs, torch, inputs, args):
 
 
 def serving_section(args):
-    """Bounded sample of the served stream: Poisson arrivals, n in {8, 16, 32},
-    k in {2, 3}; continuous batching with FP32 multigrid vs sequential FP64."""
+    """The served stream: requests with n in {8, 16, 32, 64}, k in {2, 3, 4},
+    nu log-uniform in [1e-2, 1], vertex noise 0.1h, rtol 1e-8.
+
+    1. The plain method, sequential FP64 (FP64 preconditioner), runs the
+       requests back to back: its per-request service time (set-up, solve,
+       release) and its capacity (solves/s).
+    2. Arrivals: Poisson at rate lambda = that capacity (offered load 1.0).
+       The served loop (continuous batching, FP32 multigrid inside FP64
+       FGMRES) replays the stream in real time.
+    3. The sequential method's latencies under the same arrivals follow from
+       its measured service times (one request at a time, in arrival order:
+       completion_i = max(arrival_i, completion_i-1) + service_i).
+    Every served solution is compared with the sequential FP64 solution of the
+    same request (both kept on the device)."""
+    import dataclasses
+
+    import torch
+
     import inputs
     from paper_2603_29621_amd import serving
 
-    import dataclasses
+    nreq = args.serve_requests
+    sizes, degrees = (8, 16, 32, 64), (2, 3, 4)
+    unit = inputs.request_stream(nreq, 1.0, seed=0, sizes=sizes, degrees=degrees)
+    seq_sol = {}
 
-    reqs = inputs.request_stream(args.serve_requests, args.serve_rate, seed=0, sizes=(8, 16, 32), degrees=(2, 3))
-    served = serving.Server(200e9, graphs=args.graphs).run(reqs)
-    seq = serving.run_sequential(reqs)
-    out = {"sample": f"{args.serve_requests} requests, Poisson rate {args.serve_rate}/s, n in {{8,16,32}}, "
-                     f"k in {{2,3}}, nu log-uniform [1e-2, 1], noise 0.1h, rtol 1e-8",
-           "served_fp32_mg": serving.summarize(served), "sequential_fp64": serving.summarize(seq)}
-    # capacity: the same requests all arriving at t = 0
-    burst = [dataclasses.replace(r, arrival=0.0) for r in reqs]
-    out["burst"] = {"sample": "the same requests, all arriving at t = 0",
-                    "served_fp32_mg": serving.summarize(serving.Server(200e9, graphs=args.graphs).run(burst)),
-                    "sequential_fp64": serving.summarize(serving.run_sequential(burst))}
-    return out
+    def keep_seq(r):
+        seq_sol[r.rid] = r.x
+        if len(seq_sol) % 64 == 0:
+            progress(f"sequential FP64: {len(seq_sol)}/{nreq}")
+
+    back = [dataclasses.replace(r, arrival=0.0) for r in unit]
+    seq = serving.run_sequential(back, realtime=False, keep_solutions=True, on_result=keep_seq)
+    seq_span = max(r.completed for r in seq)
+    rate = nreq / seq_span
+    torch.cuda.empty_cache()
+    reqs = inputs.request_stream(nreq, rate, seed=0, sizes=sizes, degrees=degrees)
+    service = {r.rid: r.completed - r.admitted for r in seq}
+    # FIFO replay of the sequential service times against the arrivals
+    t = 0.0
+    seq_rt = []
+    for q in sorted(reqs, key=lambda q: q.arrival):
+        start = max(q.arrival, t)
+        t = start + service[q.rid]
+        r = next(x for x in seq if x.rid == q.rid)
+        seq_rt.append(dataclasses.replace(r, arrival=q.arrival, admitted=start, completed=t, x=None))
+    diffs = []
+
+    def compare(r):
+        ref = seq_sol.pop(r.rid)
+        diffs.append(float(torch.linalg.norm(r.x - ref) / torch.linalg.norm(ref)))
+        r.x = None
+        if len(diffs) % 64 == 0:
+            progress(f"served: {len(diffs)}/{nreq}")
+
+    served = serving.Server(args.serve_budget_gb * 1e9, graphs=args.graphs, keep_solutions=True).run(
+        reqs, on_result=compare)
+    seq_sol.clear()
+    torch.cuda.empty_cache()
+    d = np.array(diffs)
+    return {"sample": f"{nreq} requests, Poisson arrivals at the sequential FP64 capacity ({rate:.3f}/s, offered "
+                      f"load 1.0), n in {{8,16,32,64}}, k in {{2,3,4}}, nu log-uniform [1e-2, 1], noise 0.1h, "
+                      f"rtol 1e-8",
+            "served_fp32_mg": serving.summarize(served),
+            "sequential_fp64": serving.summarize(seq_rt),
+            "sequential_fp64_capacity_solves_per_s": rate,
+            "served_vs_sequential_fp64_rel_diff": {"max": float(d.max()), "p50": float(np.median(d))},
+            "sequential_latency_note": "sequential latencies: measured back-to-back service times replayed "
+                                       "against the same arrival times (FIFO, one request at a time)"}
 
 
 def main():
@@ -405,8 +665,9 @@ def main():
     ap.add_argument("--prec", choices=["f64", "f32"], default="f64", help="precision of the headline run")
     ap.add_argument("--no-solve", action="store_true", help="skip the solve and served-stream measurements")
     ap.add_argument("--solve-n", type=int, default=64)
-    ap.add_argument("--serve-requests", type=int, default=24)
-    ap.add_argument("--serve-rate", type=float, default=8.0)
+    ap.add_argument("--solve-k", type=lambda v: [int(a) for a in v.split(",")], default=[2, 3, 4])
+    ap.add_argument("--serve-requests", type=int, default=512)
+    ap.add_argument("--serve-budget-gb", type=float, default=150.0)
     ap.add_argument("--no-graphs", dest="graphs", action="store_const", const=0, default=1,
                     help="launch the FP32 preconditioner kernel by kernel instead of replaying its recorded graph")
     ap.add_argument("--no-ns", action="store_true", help="skip the Navier-Stokes measurements")
@@ -416,6 +677,11 @@ def main():
     ap.add_argument("--no-ns-refined", dest="ns_refined", action="store_false",
                     help="skip the Jacobian on the locally refined mesh")
     ap.add_argument("--ns-solve-n", type=int, default=32)
+    ap.add_argument("--no-ns-full-solve", dest="ns_full_solve", action="store_false",
+                    help="skip the Newton-step solve at the full refined size")
+    ap.add_argument("--ns-jacobian-only", action="store_true",
+                    help="Navier-Stokes: Jacobian throughput only (no Newton-step solves, no BDF2 steps)")
+    ap.add_argument("--hp-vmult-only", action="store_true", help="hp: vmult throughput only (no solves)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 256 MiB device copy first (reference kernel for HBM byte counters)")
     args = ap.parse_args()
@@ -466,6 +732,7 @@ def main():
                 sweep[f"Q{kk}Q{kk-1}_{name}"] = {"dofs_per_s": r["dofs_per_s"], "frac_hbm": r["frac"],
                                                   "avg_launch_us": r["avg_launch_s"] * 1e6, "N": r["N"]}
         progress("sweep done")
+        line_spacetime = spacetime_section(mfs, torch, X, args)
     line = {
         "metric": "Stokes vmult DoFs/s (% HBM roofline)",
         "value": main_run["dofs_per_s"],
@@ -487,6 +754,8 @@ def main():
                      "bytes_per_launch": main_run["bytes"], "avg_launch_us": main_run["avg_launch_s"] * 1e6},
         "sweep": sweep,
     }
+    if not args.no_sweep:
+        line["spacetime"] = line_spacetime
     if args.prec == "f64" and k in FLOP_PER_DOF:
         fl = FLOP_PER_DOF[k] * main_run["N"] / main_run["avg_launch_s"]
         line["roofline_alu"] = {"bound": "alu", "achieved": fl / 1e12, "peak": FP64_PEAK / 1e12, "unit": "TFLOP/s",
@@ -494,6 +763,9 @@ def main():
     if not args.no_ns:
         line["navier_stokes"] = ns_section(mfs, torch, inputs, args)
         progress("navier_stokes done")
+        if not args.ns_jacobian_only:
+            line["navier_stokes"]["bdf2"] = bdf2_section(mfs, torch, inputs, args)
+            progress("BDF2 done")
     if not args.no_hp:
         line["hp"] = hp_section(mfs, torch, inputs, args)
         progress("hp done")
@@ -505,6 +777,8 @@ def main():
         progress("serving done")
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline_oracle()
+        progress("oracle vmult timed")
+        line["cpu_baseline"]["mixed_precision_vs_oracle"] = oracle_checks(mfs, torch, inputs)
         progress("cpu baseline done")
     print(json.dumps(line))
 

@@ -69,6 +69,7 @@ extern "C" {
 #define MFS_OP_BT 3          /* u -> B^T u (pressure-sized output)                     */
 #define MFS_OP_MASS_P 4      /* p -> M_p p (pressure mass)                             */
 #define MFS_OP_NS_JACOBIAN 5 /* [du;dp] -> J [du;dp], SUPG/PSPG Jacobian (Sec. 5)      */
+#define MFS_OP_MASS_U 6      /* u -> M_u u, velocity mass per component (Sec. 4)        */
 
 typedef struct mfs_problem mfs_problem;
 
@@ -236,6 +237,22 @@ int mfs_setup_refined(const mfs_refined_mesh *mesh, int k, double nu, const mfs_
  * MFS_EUNSUPPORTED). */
 int mfs_refined_count(const mfs_refined_mesh *mesh, int k, int64_t *n_unknowns, int64_t *n_hanging);
 
+/*
+ * Host only: the parallel efficiency metrics of Sec. 2 (Tables tab:tc and
+ * tab:fpc) for the two multigrid level hierarchies of a refined mesh, global
+ * coarsening (the library's levels) and local smoothing (all cells of each
+ * refinement level), when every level is spread over `nprocs` processes:
+ *   eta[0], eta[1]: eta_w, eta_v of global coarsening;
+ *   eta[2], eta[3]: eta_w, eta_v of local smoothing.
+ * eta_w = sum_l n_l / (P sum_l max_p n_{l,p}) (work against the busiest
+ * process per level), eta_v = the fraction of fine cells owned by the
+ * process that owns the coarse cell they transfer to.  Partitions: the
+ * leaves and every global-coarsening level are cut into P contiguous chunks
+ * of the Morton curve; a local-smoothing parent belongs to the owner of its
+ * first child.  MFS_EINVAL on bad cells.
+ */
+int mfs_refined_mg_metrics(const mfs_refined_mesh *mesh, int nprocs, double *eta);
+
 /* Sizes at level `level` (0 = finest): scalar velocity nodes per component and
  * pressure nodes (0 on levels without pressure; n_u on every level of a
  * Navier-Stokes problem). */
@@ -257,7 +274,7 @@ int mfs_quadrature_points_device(const mfs_problem *p, double *dev_xyz, void *st
 
 /*
  * dst = op(src) on level `level` (0 = finest) in precision `prec`.
- * Lengths: STOKES and NS_JACOBIAN: dim*n_u + n_p -> same; A: dim*n_u -> dim*n_u;
+ * Lengths: STOKES and NS_JACOBIAN: dim*n_u + n_p -> same; A, MASS_U: dim*n_u -> dim*n_u;
  * B: n_p -> dim*n_u; BT: dim*n_u -> n_p; MASS_P: n_p -> n_p.
  * STOKES, B, BT, MASS_P need a level with pressure (level 0).  NS_JACOBIAN
  * works on every level of a Navier-Stokes problem after
@@ -341,6 +358,24 @@ int mfs_solve_begin(mfs_problem *p, const double *b, double *x, const mfs_option
 int mfs_solve_advance(mfs_problem *p, int *done, mfs_solve_info *info);
 
 /*
+ * Serving step over many resumable solves (each begun with mfs_solve_begin
+ * on its own stream): for every listed problem whose last enqueued iteration
+ * has finished, read its residual and enqueue its next FGMRES iteration, as
+ * mfs_solve_advance does, without blocking on the others.  The system
+ * operator applications (w = K z_j, FP64) of all Taylor-Hood Q2/Q1 problems
+ * on structured 3D meshes that step in this call are one grouped launch pair
+ * (brick kernel and face combine over all their cells, up to 16 problems per
+ * pair) on `stream`, ordered after each problem's preconditioner and before
+ * its Gram-Schmidt by events; the preconditioners (the recorded FP32 graph)
+ * and Gram-Schmidt run on the problems' own streams, as do all the steps of
+ * other problems.  Results are the same as with mfs_solve_advance.
+ * done[i] = 1 (and infos[i] filled, when infos is not NULL) once problem i
+ * has converged or reached maxit.  The problems must be distinct and used by
+ * no other host thread meanwhile.
+ */
+int mfs_batch_step(mfs_problem **ps, int n, void *stream, int *done, mfs_solve_info *infos);
+
+/*
  * Navier-Stokes linearisation point (Sec. 5) of a problem set up with
  * pressure_offset = 0.  u0: device FP64 dim*n_u nodal velocity (every node,
  * boundary included; the pressure of the point is 0).  dt > 0: BDF2 step,
@@ -357,6 +392,33 @@ int mfs_solve_advance(mfs_problem *p, int *done, mfs_solve_info *info);
  * `stream`.  MFS_EINVAL for a Taylor-Hood problem or dt <= 0.
  */
 int mfs_set_linearization(mfs_problem *p, const double *u0, double dt, int newton, void *stream);
+
+/*
+ * Space-time Kronecker operator of the transient Stokes equations on one time
+ * slab (Sec. 4 eq. (proceedings-kronecker)):
+ *   dst = (G (x) M + tau I_Q (x) A) src
+ * on stage-major vectors [x_1 | .. | x_Q], each x_q a full Stokes vector of
+ * dim n_u + n_p entries (level 0), M the Stokes block mass (velocity mass,
+ * zero pressure block), A the Stokes operator of mfs_vmult(MFS_OP_STOKES).
+ * Every stage carries the spatial constraints: dst_q = src_q on the velocity
+ * Dirichlet rows, Dirichlet source values ignored elsewhere.
+ *   G: host Q x Q row-major (G_Q = M_Q^{-1} A_Q^tau of the time
+ *      discretisation), 1 <= Q <= 8;  tau > 0: the slab length;
+ *   work: device scratch of Q dim n_u entries in the precision `prec`.
+ * Structured Taylor-Hood problems.  Enqueue only.
+ */
+int mfs_st_vmult(mfs_problem *p, int Q, const double *G, double tau, int prec, void *dst, const void *src, void *work,
+                 void *stream);
+
+/*
+ * Stage mixing on stage-major level-0 vectors: dst_i = sum_j C[i][j] src_j
+ * (i < q_out, j < q_in, C host row-major q_out x q_in, q_out, q_in <= 8),
+ * entry by entry over the full Stokes vector: the temporal transfers of
+ * Sec. 4 (P_tau for prolongation, P_tau^T for restriction) applied per
+ * spatial unknown.  dst and src must not overlap.  Enqueue only.
+ */
+int mfs_st_stage_transfer(mfs_problem *p, int q_out, int q_in, const double *C, int prec, void *dst, const void *src,
+                          void *stream);
 
 /*
  * General Navier-Stokes state (Sec. 5, BDF2): the linearisation at

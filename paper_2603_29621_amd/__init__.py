@@ -31,6 +31,7 @@ MFS_OP_B = 2
 MFS_OP_BT = 3
 MFS_OP_MASS_P = 4
 MFS_OP_NS_JACOBIAN = 5
+MFS_OP_MASS_U = 6
 
 EXPORTED = [
     "mfs_default_options", "mfs_last_error", "mfs_footprint", "mfs_setup", "mfs_destroy", "mfs_n_dofs",
@@ -40,7 +41,8 @@ EXPORTED = [
     "mfs_precondition", "mfs_rhs", "mfs_solve", "mfs_solve_begin", "mfs_solve_advance",
     "mfs_set_linearization", "mfs_setup_hp", "mfs_setup_refined", "mfs_refined_count",
     "mfs_stokes_vmult_noalloc", "mfs_set_linearization_point", "mfs_ns_residual", "mfs_default_newton_options",
-    "mfs_ns_bdf2_step", "mfs_setup_arena",
+    "mfs_ns_bdf2_step", "mfs_setup_arena", "mfs_batch_step", "mfs_st_vmult", "mfs_st_stage_transfer",
+    "mfs_refined_mg_metrics",
 ]
 
 
@@ -123,6 +125,8 @@ def lib():
         L.mfs_setup_refined.argtypes = [ctypes.POINTER(mfs_refined_mesh), ctypes.c_int, ctypes.c_double,
                                         ctypes.POINTER(mfs_options), vp, ctypes.POINTER(vp)]
         L.mfs_refined_count.argtypes = [ctypes.POINTER(mfs_refined_mesh), ctypes.c_int, i64p, i64p]
+        L.mfs_refined_mg_metrics.argtypes = [ctypes.POINTER(mfs_refined_mesh), ctypes.c_int,
+                                             ctypes.POINTER(ctypes.c_double)]
         L.mfs_n_dofs.argtypes = [vp, ctypes.c_int, i64p, i64p]
         L.mfs_n_levels.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
         L.mfs_level_info.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
@@ -142,6 +146,12 @@ def lib():
         L.mfs_solve_begin.argtypes = [vp, vp, vp, ctypes.POINTER(mfs_options), vp]
         L.mfs_solve_advance.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(mfs_solve_info)]
         L.mfs_set_linearization.argtypes = [vp, vp, ctypes.c_double, ctypes.c_int, vp]
+        L.mfs_st_vmult.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_double, ctypes.c_int,
+                                   vp, vp, vp, vp]
+        L.mfs_st_stage_transfer.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                            ctypes.c_int, vp, vp, vp]
+        L.mfs_batch_step.argtypes = [ctypes.POINTER(vp), ctypes.c_int, vp, ctypes.POINTER(ctypes.c_int),
+                                     ctypes.POINTER(mfs_solve_info)]
         L.mfs_set_linearization_point.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_int, ctypes.c_int, vp]
         L.mfs_ns_residual.argtypes = [vp, vp, vp]
         L.mfs_default_newton_options.argtypes = [ctypes.POINTER(mfs_newton_options)]
@@ -220,7 +230,8 @@ def _op_len(h, op, level):
         return None, None
     vel, full = dim * nu, dim * nu + np_
     return {MFS_OP_STOKES: (full, full), MFS_OP_NS_JACOBIAN: (full, full), MFS_OP_A: (vel, vel),
-            MFS_OP_B: (vel, np_), MFS_OP_BT: (np_, vel), MFS_OP_MASS_P: (np_, np_)}.get(op, (None, None))
+            MFS_OP_B: (vel, np_), MFS_OP_BT: (np_, vel), MFS_OP_MASS_P: (np_, np_),
+            MFS_OP_MASS_U: (vel, vel)}.get(op, (None, None))
 
 
 def _qp_len(h):
@@ -313,6 +324,15 @@ def mfs_refined_count(mesh, k):
     n, h = ctypes.c_int64(0), ctypes.c_int64(0)
     _check(lib().mfs_refined_count(ctypes.byref(m), int(k), ctypes.byref(n), ctypes.byref(h)))
     return n.value, h.value
+
+
+def mfs_refined_mg_metrics(mesh, nprocs):
+    """{"gc": {"eta_w", "eta_v"}, "ls": {...}} of the refined mesh on nprocs
+    processes (host only)."""
+    m, _keep = _refined(mesh)
+    eta = (ctypes.c_double * 4)()
+    _check(lib().mfs_refined_mg_metrics(ctypes.byref(m), int(nprocs), eta))
+    return {"gc": {"eta_w": eta[0], "eta_v": eta[1]}, "ls": {"eta_w": eta[2], "eta_v": eta[3]}}
 
 
 def mfs_setup_refined(mesh, k, nu, opts=None, stream=None) -> ctypes.c_void_p:
@@ -463,6 +483,43 @@ def mfs_solve_advance(h):
     info = mfs_solve_info()
     _check(lib().mfs_solve_advance(h, ctypes.byref(done), ctypes.byref(info)))
     return bool(done.value), info
+
+
+def mfs_st_vmult(h, G, tau, prec, dst, src, work, stream=None):
+    """Space-time Kronecker operator (G (x) M + tau I (x) A) on stage-major vectors."""
+    G = np.ascontiguousarray(G, dtype=np.float64)
+    Q = G.shape[0]
+    if G.shape != (Q, Q):
+        raise ValueError("G must be square")
+    dim, nu, np_, _ = _sizes(h, 0)
+    n = None if dim is None else Q * (dim * nu + np_)
+    nw = None if dim is None else Q * dim * nu
+    w = _word(prec)
+    _check(lib().mfs_st_vmult(h, Q, G.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(tau), int(prec),
+                              _arg(dst, n, w, "dst"), _arg(src, n, w, "src"), _arg(work, nw, w, "work"),
+                              _stream(stream)))
+
+
+def mfs_st_stage_transfer(h, C, prec, dst, src, stream=None):
+    """dst_i = sum_j C[i][j] src_j on stage-major level-0 Stokes vectors."""
+    C = np.ascontiguousarray(C, dtype=np.float64)
+    qo, qi = C.shape
+    dim, nu, np_, _ = _sizes(h, 0)
+    N = None if dim is None else dim * nu + np_
+    w = _word(prec)
+    _check(lib().mfs_st_stage_transfer(h, qo, qi, C.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(prec),
+                                       _arg(dst, None if N is None else qo * N, w, "dst"),
+                                       _arg(src, None if N is None else qi * N, w, "src"), _stream(stream)))
+
+
+def mfs_batch_step(handles, stream=None):
+    """One serving step over resumable solves; returns [(done, info)] per handle."""
+    n = len(handles)
+    arr = (ctypes.c_void_p * max(n, 1))(*[h.value for h in handles])
+    done = (ctypes.c_int * max(n, 1))()
+    infos = (mfs_solve_info * max(n, 1))()
+    _check(lib().mfs_batch_step(ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p)), n, _stream(stream), done, infos))
+    return [(bool(done[i]), infos[i]) for i in range(n)]
 
 
 def mfs_set_linearization(h, u0, dt, newton, stream=None):

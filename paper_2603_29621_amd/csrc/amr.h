@@ -61,4 +61,9 @@ AmrTransferHost amr_transfer(int n, const std::vector<int> &lf, const std::vecto
 // same position (each coarse unknown is one)
 std::vector<int64_t> amr_injection(const AmrSpaceHost &fine, const AmrSpaceHost &coarse);
 
+// Parallel efficiency of the multigrid levels of a refined mesh on P
+// processes (partitions along the Morton curve): out = {eta_w, eta_v} of the
+// global-coarsening levels, then of the local-smoothing levels
+void amr_mg_metrics(int n, const std::vector<int> &level, const std::vector<int> &idx, int P, double out[4]);
+
 }  // namespace mfs

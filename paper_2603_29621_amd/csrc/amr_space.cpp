@@ -463,3 +463,136 @@ std::vector<int64_t> amr_injection(const AmrSpaceHost &fine, const AmrSpaceHost 
 }
 
 }  // namespace mfs
+
+// ---------------------------------------------------------------- partition metrics
+namespace mfs {
+namespace {
+
+struct MCell {
+  int l, x, y, z;
+};
+
+// Morton key of a cell's lowest corner on the finest grid, the level in the
+// low bits so that a parent precedes its first child
+uint64_t morton_key(const MCell &c, int L) {
+  const int s = L - c.l;
+  const uint64_t x = (uint64_t)c.x << s, y = (uint64_t)c.y << s, z = (uint64_t)c.z << s;
+  uint64_t k = 0;
+  for (int b = 0; b < 19; ++b)
+    k |= (((x >> b) & 1) << (3 * b)) | (((y >> b) & 1) << (3 * b + 1)) | (((z >> b) & 1) << (3 * b + 2));
+  return (k << 5) | (uint64_t)c.l;
+}
+
+uint64_t cell_id(const MCell &c, int n) {
+  const uint64_t m = (uint64_t)n << c.l;
+  return ((uint64_t)c.l << 56) | ((uint64_t)c.x + m * ((uint64_t)c.y + m * (uint64_t)c.z));
+}
+
+MCell parent_of(const MCell &c) { return {c.l - 1, c.x / 2, c.y / 2, c.z / 2}; }
+
+// owners of P contiguous Morton chunks (sizes differ by at most one, the
+// first count mod P one larger), by cell id
+std::unordered_map<uint64_t, int> morton_partition(const std::vector<MCell> &cells, int P, int L, int n) {
+  std::vector<std::pair<uint64_t, uint64_t>> order(cells.size());  // (Morton key, cell id)
+  for (size_t c = 0; c < cells.size(); ++c) order[c] = {morton_key(cells[c], L), cell_id(cells[c], n)};
+  std::sort(order.begin(), order.end());
+  std::unordered_map<uint64_t, int> own;
+  own.reserve(cells.size() * 2);
+  const int64_t N = (int64_t)cells.size(), base = N / P, extra = N % P;
+  int64_t k = 0;
+  for (int p = 0; p < P; ++p) {
+    const int64_t size = base + (p < extra ? 1 : 0);
+    for (int64_t i = 0; i < size; ++i) own[order[k + i].second] = p;
+    k += size;
+  }
+  return own;
+}
+
+double eta_w(const std::vector<std::vector<MCell>> &levels, const std::vector<std::unordered_map<uint64_t, int>> &own,
+             int P, int n) {
+  double total = 0, crit = 0;
+  for (size_t j = 0; j < levels.size(); ++j) {
+    std::vector<int64_t> cnt(P, 0);
+    for (const MCell &c : levels[j]) cnt[own[j].at(cell_id(c, n))] += 1;
+    total += (double)levels[j].size();
+    crit += (double)*std::max_element(cnt.begin(), cnt.end());
+  }
+  return total / ((double)P * crit);
+}
+
+}  // namespace
+
+void amr_mg_metrics(int n, const std::vector<int> &level, const std::vector<int> &idx, int P, double out[4]) {
+  int L = 0;
+  for (int l : level) L = std::max(L, l);
+  std::vector<MCell> leafs(level.size());
+  for (size_t c = 0; c < level.size(); ++c) leafs[c] = {level[c], idx[3 * c], idx[3 * c + 1], idx[3 * c + 2]};
+  // global coarsening: the library's coarsening, each level partitioned on its own
+  std::vector<std::vector<MCell>> G{leafs};
+  std::vector<int> lv = level, ix = idx;
+  while (*std::max_element(lv.begin(), lv.end()) > 0) {
+    std::vector<int> lc, xc;
+    amr_coarsen(n, lv, ix, lc, xc);
+    MFS_REQUIRE(lc.size() < lv.size(), MFS_EINVAL, "global coarsening made no progress");
+    lv.swap(lc);
+    ix.swap(xc);
+    std::vector<MCell> cs(lv.size());
+    for (size_t c = 0; c < lv.size(); ++c) cs[c] = {lv[c], ix[3 * c], ix[3 * c + 1], ix[3 * c + 2]};
+    G.push_back(std::move(cs));
+  }
+  std::vector<std::unordered_map<uint64_t, int>> gown;
+  for (const auto &cs : G) gown.push_back(morton_partition(cs, P, L, n));
+  int64_t local = 0, tot = 0;
+  for (size_t j = 0; j + 1 < G.size(); ++j)
+    for (const MCell &c : G[j]) {
+      auto it = gown[j + 1].find(cell_id(c, n));
+      const int to = it != gown[j + 1].end() ? it->second : gown[j + 1].at(cell_id(parent_of(c), n));
+      local += gown[j].at(cell_id(c, n)) == to;
+      ++tot;
+    }
+  out[0] = eta_w(G, gown, P, n);
+  out[1] = tot ? (double)local / (double)tot : 1.0;
+  // local smoothing: every cell of each refinement level; a leaf keeps its
+  // owner, a parent takes the owner of its first child in Morton order
+  std::vector<std::vector<MCell>> S(L + 1);
+  std::unordered_map<uint64_t, int> seen;
+  seen.reserve(leafs.size() * 3);
+  for (const MCell &c0 : leafs) {
+    MCell c = c0;
+    while (true) {
+      if (!seen.emplace(cell_id(c, n), 1).second) break;
+      S[c.l].push_back(c);
+      if (c.l == 0) break;
+      c = parent_of(c);
+    }
+  }
+  std::vector<std::unordered_map<uint64_t, int>> lown(L + 1);
+  const auto &leaf_own = gown[0];
+  for (int l = L; l >= 0; --l) {
+    std::unordered_map<uint64_t, std::pair<uint64_t, int>> first;  // parent -> (key, owner) of its first child
+    first.reserve(S[l].size() * 2);
+    lown[l].reserve(S[l].size() * 2);
+    if (l < L)
+      for (const MCell &c : S[l + 1]) {
+        const uint64_t pid = cell_id(parent_of(c), n), key = morton_key(c, L);
+        const int o = lown[l + 1].at(cell_id(c, n));
+        auto it = first.find(pid);
+        if (it == first.end() || key < it->second.first) first[pid] = {key, o};
+      }
+    for (const MCell &c : S[l]) {
+      const uint64_t id = cell_id(c, n);
+      auto it = leaf_own.find(id);
+      lown[l][id] = it != leaf_own.end() ? it->second : first.at(id).second;
+    }
+  }
+  local = tot = 0;
+  for (int l = L; l > 0; --l)
+    for (const MCell &c : S[l]) {
+      local += lown[l].at(cell_id(c, n)) == lown[l - 1].at(cell_id(parent_of(c), n));
+      ++tot;
+    }
+  out[2] = eta_w(S, lown, P, n);
+  out[3] = tot ? (double)local / (double)tot : 1.0;
+}
+
+}  // namespace mfs

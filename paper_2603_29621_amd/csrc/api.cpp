@@ -110,6 +110,7 @@ struct Krylov {
   double *ydev = nullptr;    // device copy of the GMRES coefficients
   double *yhost = nullptr;   // pinned
   hipEvent_t ev = nullptr;
+  hipEvent_t ev_pre = nullptr;  // end of the preconditioner (grouped steps)
   // state
   int state = 0;  // 0 idle, 1 wait initial residual, 2 wait Arnoldi step, 3 wait final check, 4 done
   int j = 0, iters = 0, maxit = 0, prec = MFS_FP32;
@@ -308,7 +309,7 @@ struct mfs_problem {
   int namr = 0;
   // recorded FP32 preconditioner (between w32.full_in and w32.full_out), its
   // capture stream, and whether recording failed once (then launched eagerly)
-  hipGraphExec_t prec_graph = nullptr;
+  hipGraphExec_t prec_graph[2] = {nullptr, nullptr};  // FP32, FP64
   hipStream_t cap_stream = nullptr;
   bool graph_failed = false;
 };
@@ -620,8 +621,10 @@ hipStream_t capture_stream_acquire() {
 
 void release(mfs_problem *P) {
   if (!P) return;
-  if (P->prec_graph) (void)hipGraphExecDestroy(P->prec_graph);
+  for (int i = 0; i < 2; ++i)
+    if (P->prec_graph[i]) (void)hipGraphExecDestroy(P->prec_graph[i]);
   if (P->kr.ev) (void)hipEventDestroy(P->kr.ev);
+  if (P->kr.ev_pre) (void)hipEventDestroy(P->kr.ev_pre);
   {
     std::lock_guard<std::mutex> lock(g_pool_mu);
     if (P->cap_stream) g_stream_free.push_back(P->cap_stream);
@@ -831,6 +834,14 @@ void apply_op(mfs_problem &P, int op, int l, T *dst, const T *src, hipStream_t s
       }
       vec_fill<T>(dst, T(0), g.Np, s);
       launch_cell_op<T>(g, dev<T>(L), M_DIVU, (T)P.nu, nullptr, dst, src, nullptr, s);
+      break;
+    case MFS_OP_MASS_U:
+      if (use_gather<T>(L)) {
+        launch_cell_op_gather<T>(g, dev<T>(L), M_MASSU, (T)P.nu, dst, nullptr, src, nullptr, src, cellev<T>(L), s);
+        break;
+      }
+      launch_fill_dirichlet<T>(g, dst, src, s);
+      launch_cell_op<T>(g, dev<T>(L), M_MASSU, (T)P.nu, dst, nullptr, src, nullptr, s);
       break;
     case MFS_OP_MASS_P:
       MFS_REQUIRE(g.kp > 0, MFS_EINVAL, "level %d has no pressure space", l);
@@ -1548,49 +1559,66 @@ void precondition_any(mfs_problem &P, T *y, const T *r, hipStream_t s) {
 // was recorded (smoother intervals, the linearisation's dt and Newton flag,
 // option counts); calls that change them drop the recording.
 void drop_prec_graph(mfs_problem &P) {
-  if (P.prec_graph) (void)hipGraphExecDestroy(P.prec_graph);
-  P.prec_graph = nullptr;
+  for (int i = 0; i < 2; ++i) {
+    if (P.prec_graph[i]) (void)hipGraphExecDestroy(P.prec_graph[i]);
+    P.prec_graph[i] = nullptr;
+  }
 }
 
-// FP32 preconditioner from w32.full_in to w32.full_out on stream s.  Its
-// launches (a few hundred small kernels per V-cycle and Schur solve, no host
-// synchronisation and no memset) are recorded once on a private stream and
-// replayed as one graph launch, so that small problems do not pay the host
-// cost of every launch in each FGMRES iteration.  Recording that fails
-// (e.g. a runtime without stream capture) falls back to direct launches.
-void precondition_fp32(mfs_problem &P, hipStream_t s) {
-  float *y = P.w32.full_out, *r = P.w32.full_in;
+template <typename T>
+PrecWork<T> &prec_work(mfs_problem &P);
+template <>
+PrecWork<double> &prec_work<double>(mfs_problem &P) {
+  return P.w64;
+}
+template <>
+PrecWork<float> &prec_work<float>(mfs_problem &P) {
+  return P.w32;
+}
+
+// Preconditioner from full_in to full_out of the precision's work vectors on
+// stream s.  Its launches (a few hundred small kernels per V-cycle and Schur
+// solve, no host synchronisation and no memset) are recorded once on a
+// private stream and replayed as one graph launch, so that small problems do
+// not pay the host cost of every launch in each FGMRES iteration.  Recording
+// that fails (e.g. a runtime without stream capture) falls back to direct
+// launches.  The FP64 one is staged through fixed vectors too, since the
+// Krylov columns it reads and writes move every iteration.
+template <typename T>
+void precondition_rec(mfs_problem &P, hipStream_t s) {
+  constexpr int w = sizeof(T) == 8 ? 1 : 0;
+  T *y = prec_work<T>(P).full_out, *r = prec_work<T>(P).full_in;
   if (!P.kr.graphs || P.graph_failed) {
-    precondition_any<float>(P, y, r, s);
+    precondition_any<T>(P, y, r, s);
     return;
   }
-  if (!P.prec_graph) {
+  if (!P.prec_graph[w]) {
     if (!P.cap_stream) P.cap_stream = capture_stream_acquire();
     hipGraph_t g = nullptr;
     if (hipStreamBeginCapture(P.cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
       (void)hipGetLastError();
       P.graph_failed = true;
-      precondition_any<float>(P, y, r, s);
+      precondition_any<T>(P, y, r, s);
       return;
     }
     try {
-      precondition_any<float>(P, y, r, P.cap_stream);
+      precondition_any<T>(P, y, r, P.cap_stream);
     } catch (...) {
       if (hipStreamEndCapture(P.cap_stream, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
       throw;
     }
     MFS_HIP(hipStreamEndCapture(P.cap_stream, &g));
-    const hipError_t e = hipGraphInstantiate(&P.prec_graph, g, nullptr, nullptr, 0);
+    const hipError_t e = hipGraphInstantiate(&P.prec_graph[w], g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
       (void)hipGetLastError();
-      P.prec_graph = nullptr;
+      P.prec_graph[w] = nullptr;
       P.graph_failed = true;
-      precondition_any<float>(P, y, r, s);
+      precondition_any<T>(P, y, r, s);
       return;
     }
   }
-  MFS_HIP(hipGraphLaunch(P.prec_graph, s));
+  MFS_HIP(hipGraphLaunch(P.prec_graph[w], s));
 }
 
 // ---------------------------------------------------------------- FGMRES
@@ -1604,19 +1632,36 @@ void kr_enqueue_residual(mfs_problem &P, hipStream_t s) {
   MFS_HIP(hipEventRecord(K.ev, s));
 }
 
-void kr_enqueue_step(mfs_problem &P, hipStream_t s) {
+// one Arnoldi step: z_j = P^{-1} v_j (pre), w = K z_j (the system
+// operator), Gram-Schmidt and the readback (post)
+void kr_step_pre(mfs_problem &P, hipStream_t s) {
   Krylov &K = P.kr;
   const int64_t n = sys_n(P);
   const int j = K.j;
   double *vj = K.V + (int64_t)j * K.ld, *zj = K.Z + (int64_t)j * K.ld;
   if (K.prec == MFS_FP32) {
     vec_cast<float, double>(P.w32.full_in, vj, n, s);
-    precondition_fp32(P, s);
+    precondition_rec<float>(P, s);
     vec_cast<double, float>(zj, P.w32.full_out, n, s);
+  } else if (K.graphs && !P.graph_failed) {
+    vec_copy<double>(P.w64.full_in, vj, n, s);
+    precondition_rec<double>(P, s);
+    vec_copy<double>(zj, P.w64.full_out, n, s);
   } else {
     precondition_any<double>(P, zj, vj, s);
   }
-  apply_system(P, K.w, zj, s);
+}
+void kr_step_post(mfs_problem &P, hipStream_t s);
+void kr_enqueue_step(mfs_problem &P, hipStream_t s) {
+  Krylov &K = P.kr;
+  kr_step_pre(P, s);
+  apply_system(P, K.w, K.Z + (int64_t)K.j * K.ld, s);
+  kr_step_post(P, s);
+}
+void kr_step_post(mfs_problem &P, hipStream_t s) {
+  Krylov &K = P.kr;
+  const int64_t n = sys_n(P);
+  const int j = K.j;
   // classical Gram-Schmidt, twice
   // (the second pass's dots and the norm are fused with the updates before them)
   multi_dot<double>(K.V, K.ld, j + 1, K.w, n, K.dev, P.partials, s);
@@ -1670,8 +1715,9 @@ void kr_finish(mfs_problem &P, double rel, int status) {
   K.state = 4;
 }
 
-// advance the state machine after its event completed
-void kr_process(mfs_problem &P) {
+// advance the state machine after its event completed; with `defer` an
+// Arnoldi step is not enqueued but reported (true) for the caller to enqueue
+bool kr_process(mfs_problem &P, bool defer = false) {
   Krylov &K = P.kr;
   hipStream_t s = K.s;
   const int64_t n = sys_n(P);
@@ -1681,7 +1727,7 @@ void kr_process(mfs_problem &P) {
     const double rel = K.bnorm > 0 ? rr / K.bnorm : 0.0;
     if (rel <= K.rtol || K.iters >= K.maxit) {
       kr_finish(P, rel, rel <= K.rtol ? MFS_OK : MFS_ENOCONV);
-      return;
+      return false;
     }
     // (re)start: V_0 = r / ||r||
     K.beta = rr;
@@ -1691,8 +1737,9 @@ void kr_process(mfs_problem &P) {
     K.j = 0;
     scale_inv_sqrt<double>(K.V, K.w, n, K.dev + 96, s);
     K.state = 2;
+    if (defer) return true;
     kr_enqueue_step(P, s);
-    return;
+    return false;
   }
   if (K.state == 2) {
     const int j = K.j, m = K.m;
@@ -1719,10 +1766,12 @@ void kr_process(mfs_problem &P) {
     if (est <= K.rtol || K.j == m || K.iters >= K.maxit || breakdown) {
       K.state = 3;
       kr_enqueue_update(P, s);
-      return;
+      return false;
     }
+    if (defer) return true;
     kr_enqueue_step(P, s);
   }
+  return false;
 }
 
 }  // namespace
@@ -1862,6 +1911,7 @@ int setup_structured(const mfs_mesh *mesh, int k, double nu, const mfs_options *
     P->kr.host = pinned_acquire();
     P->kr.yhost = P->kr.host + 128;
     MFS_HIP(hipEventCreateWithFlags(&P->kr.ev, hipEventDisableTiming));
+    MFS_HIP(hipEventCreateWithFlags(&P->kr.ev_pre, hipEventDisableTiming));
     // vertices per level: fine vertices at indices divisible by 2^h
     const int dim = mesh->dim;
     int hl = 0;
@@ -2822,6 +2872,24 @@ int mfs_refined_count(const mfs_refined_mesh *mesh, int k, int64_t *n_unknowns, 
   });
 }
 
+int mfs_refined_mg_metrics(const mfs_refined_mesh *mesh, int nprocs, double *eta) {
+  return guard([&] {
+    MFS_REQUIRE(mesh != nullptr && eta != nullptr, MFS_EINVAL, "NULL argument");
+    MFS_REQUIRE(nprocs >= 1, MFS_EINVAL, "nprocs must be >= 1");
+    MFS_REQUIRE(mesh->n >= 1 && mesh->n <= 4096 && mesh->levels >= 0 && mesh->levels <= 4 && mesh->ncells >= 1,
+                MFS_EINVAL, "bad refined mesh");
+    std::vector<int> level(mesh->level, mesh->level + mesh->ncells), idx(mesh->idx, mesh->idx + 3 * mesh->ncells);
+    for (int64_t c = 0; c < mesh->ncells; ++c) {
+      MFS_REQUIRE(level[c] >= 0 && level[c] <= mesh->levels, MFS_EINVAL, "cell %lld: level out of range",
+                  (long long)c);
+      for (int a = 0; a < 3; ++a)
+        MFS_REQUIRE(idx[3 * c + a] >= 0 && idx[3 * c + a] < (mesh->n << level[c]), MFS_EINVAL,
+                    "cell %lld: index out of range", (long long)c);
+    }
+    amr_mg_metrics(mesh->n, level, idx, nprocs, eta);
+  });
+}
+
 int mfs_setup_refined(const mfs_refined_mesh *mesh, int k, double nu, const mfs_options *opts, void *stream,
                       mfs_problem **out) {
   mfs_problem *P = nullptr;
@@ -2880,6 +2948,8 @@ int mfs_setup_refined(const mfs_refined_mesh *mesh, int k, double nu, const mfs_
       K.w = A.H.alloc<double>(n0);
       P->w32.full_in = A.H.alloc<float>(n0);
       P->w32.full_out = A.H.alloc<float>(n0);
+      P->w64.full_in = A.H.alloc<double>(n0);
+      P->w64.full_out = A.H.alloc<double>(n0);
     }
     *out = P;
   });
@@ -2905,6 +2975,14 @@ void no_amr(const mfs_problem *p, const char *what) {
 }
 void check_prec(int prec) {
   MFS_REQUIRE(prec == MFS_FP32 || prec == MFS_FP64, MFS_EINVAL, "precision must be MFS_FP32 or MFS_FP64");
+}
+
+// a structured Taylor-Hood problem whose system operator is the degree-2
+// brick kernel (its Arnoldi steps can share one grouped operator launch)
+bool q2_groupable(const mfs_problem &P) {
+  if (P.hp || P.amr || P.ns || !use_specialised()) return false;
+  const LevelGeom &g = P.L[0].g;
+  return g.dim == 3 && g.k == 2 && g.kp == 1 && q2_face_elems(g) > 0;
 }
 
 void kr_begin(mfs_problem &P, const double *b, double *x, const mfs_options &o, hipStream_t s) {
@@ -2948,6 +3026,26 @@ void kr_begin(mfs_problem &P, const double *b, double *x, const mfs_options &o, 
   K.state = 1;
   kr_enqueue_residual(P, s);
 }
+// Space-time Kronecker operator (Sec. 4 eq. (proceedings-kronecker)) on level
+// 0: dst_q = sum_r G[q][r] M_u src_r + tau K src_q on the free rows, dst_q =
+// src_q on the velocity Dirichlet rows; stage-major vectors of N entries per
+// stage; work holds the Q stage masses (Q dim Nv).
+template <typename T>
+void st_apply(mfs_problem &P, int Q, const double *G, double tau, T *dst, const T *src, T *work, hipStream_t s) {
+  const Level &L = P.L[0];
+  const LevelGeom &g = L.g;
+  const int64_t nv = P.dim * g.Nv, N = nv + g.Np;
+  for (int r = 0; r < Q; ++r) apply_op<T>(P, MFS_OP_MASS_U, 0, work + r * nv, src + r * N, s);
+  for (int q = 0; q < Q; ++q) {
+    T *dq = dst + q * N;
+    apply_op<T>(P, MFS_OP_STOKES, 0, dq, src + q * N, s);
+    StageCoef C{};
+    for (int r = 0; r < Q; ++r) C.c[r] = G[q * Q + r];
+    stage_mix<T>(dq, N, 1, work, nv, Q, C, (T)tau, nv, N, s);
+    vec_copy_boundary<T>(g, dq, src + q * N, s);  // identity rows
+  }
+}
+
 // the state of a Navier-Stokes problem (structured or refined) at x0 = [u0 | p0]
 void set_point_any(mfs_problem &P, const double *x0, const double *uh, double dt, int newton, int keep_delta, bool mg,
                    hipStream_t s) {
@@ -3053,6 +3151,44 @@ void mfs_default_newton_options(mfs_newton_options *o) {
   o->linear_rtol = 1e-6;
   o->linear_maxit = 200;
   o->precond_precision = MFS_FP32;
+}
+
+int mfs_st_vmult(mfs_problem *p, int Q, const double *G, double tau, int prec, void *dst, const void *src, void *work,
+                 void *stream) {
+  return guard([&] {
+    check_problem(p);
+    check_prec(prec);
+    MFS_REQUIRE(!p->ns && !p->hp && !p->amr && p->L[0].g.Np > 0, MFS_EUNSUPPORTED,
+                "the space-time operator needs a structured Taylor-Hood problem");
+    MFS_REQUIRE(Q >= 1 && Q <= MFS_MAX_STAGES, MFS_EINVAL, "Q = %d outside [1, %d]", Q, MFS_MAX_STAGES);
+    MFS_REQUIRE(G && dst && src && work && dst != src, MFS_EINVAL, "bad arguments");
+    MFS_REQUIRE(tau > 0 && std::isfinite(tau), MFS_EINVAL, "tau must be positive");
+    if (prec == MFS_FP64)
+      st_apply<double>(*p, Q, G, tau, (double *)dst, (const double *)src, (double *)work, S(stream));
+    else
+      st_apply<float>(*p, Q, G, tau, (float *)dst, (const float *)src, (float *)work, S(stream));
+  });
+}
+
+int mfs_st_stage_transfer(mfs_problem *p, int q_out, int q_in, const double *C, int prec, void *dst, const void *src,
+                          void *stream) {
+  return guard([&] {
+    check_problem(p);
+    check_prec(prec);
+    MFS_REQUIRE(!p->hp && !p->amr, MFS_EUNSUPPORTED, "structured problems only");
+    MFS_REQUIRE(q_out >= 1 && q_out <= MFS_MAX_STAGES && q_in >= 1 && q_in <= MFS_MAX_STAGES, MFS_EINVAL,
+                "stage counts outside [1, %d]", MFS_MAX_STAGES);
+    MFS_REQUIRE(C && dst && src && dst != src, MFS_EINVAL, "bad arguments");
+    const LevelGeom &g = p->L[0].g;
+    const int64_t N = p->dim * g.Nv + g.Np;
+    StageCoef K{};
+    for (int i = 0; i < q_out; ++i)
+      for (int j = 0; j < q_in; ++j) K.c[i * MFS_MAX_STAGES + j] = C[i * q_in + j];
+    if (prec == MFS_FP64)
+      stage_mix<double>((double *)dst, N, q_out, (const double *)src, N, q_in, K, 0.0, N, N, S(stream));
+    else
+      stage_mix<float>((float *)dst, N, q_out, (const float *)src, N, q_in, K, 0.0f, N, N, S(stream));
+  });
 }
 
 int mfs_set_linearization_point(mfs_problem *p, const double *x0, const double *u_hist, double dt, int newton,
@@ -3492,6 +3628,68 @@ int mfs_solve_advance(mfs_problem *p, int *done, mfs_solve_info *info) {
       *done = 1;
       if (info) *info = K.info;
     }
+  });
+}
+
+int mfs_batch_step(mfs_problem **ps, int n, void *stream, int *done, mfs_solve_info *infos) {
+  return guard([&] {
+    MFS_REQUIRE(n >= 0 && (n == 0 || (ps != nullptr && done != nullptr)), MFS_EINVAL, "bad problem list");
+    for (int i = 0; i < n; ++i) {
+      MFS_REQUIRE(ps[i] != nullptr, MFS_EINVAL, "problem %d is NULL", i);
+      for (int j = 0; j < i; ++j) MFS_REQUIRE(ps[j] != ps[i], MFS_EINVAL, "problem %d is listed twice", i);
+    }
+    std::vector<mfs_problem *> group;
+    for (int i = 0; i < n; ++i) {
+      mfs_problem &P = *ps[i];
+      Krylov &K = P.kr;
+      done[i] = 0;
+      if (K.state != 4) {
+        MFS_REQUIRE(K.state != 0, MFS_EINVAL, "problem %d has no solve in progress", i);
+        const hipError_t q = hipEventQuery(K.ev);
+        if (q == hipErrorNotReady) continue;
+        MFS_HIP(q);
+        const bool step = kr_process(P, true);
+        if (step) {
+          if (q2_groupable(P))
+            group.push_back(&P);
+          else
+            kr_enqueue_step(P, K.s);
+        }
+      }
+      if (K.state == 4) {
+        done[i] = 1;
+        if (infos) infos[i] = K.info;
+      }
+    }
+    if (group.size() == 1) {
+      kr_enqueue_step(*group[0], group[0]->kr.s);
+      return;
+    }
+    if (group.empty()) return;
+    // preconditioners on the problems' streams, one grouped system operator
+    // on `stream`, Gram-Schmidt and readbacks on the problems' streams again
+    hipStream_t gs = S(stream);
+    std::vector<Q2Problem<double>> q(group.size());
+    for (size_t i = 0; i < group.size(); ++i) {
+      mfs_problem &P = *group[i];
+      Krylov &K = P.kr;
+      kr_step_pre(P, K.s);
+      MFS_HIP(hipEventRecord(K.ev_pre, K.s));
+      MFS_HIP(hipStreamWaitEvent(gs, K.ev_pre, 0));
+      const Level &L = P.L[0];
+      q[i] = Q2Problem<double>{L.g, L.X64, P.nu, K.w, K.Z + (int64_t)K.j * K.ld, L.face64};
+    }
+    launch_stokes_q2_group<double>(q.data(), (int)q.size(), gs);
+    hipEvent_t e = nullptr;
+    MFS_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    const hipError_t r = hipEventRecord(e, gs);
+    if (r == hipSuccess)
+      for (mfs_problem *P : group) {
+        MFS_HIP(hipStreamWaitEvent(P->kr.s, e, 0));
+        kr_step_post(*P, P->kr.s);
+      }
+    (void)hipEventDestroy(e);
+    MFS_HIP(r);
   });
 }
 

@@ -85,7 +85,9 @@ __global__ void __launch_bounds__((Shape<DIM, K, KP>::BLOCK)) cell_kernel(CellAr
   c.tab = s_tab;
   const bool dir = c.valid ? c.vel_dirichlet(a.nv0, a.nv1, a.nv2) : true;
   const int64_t vnode = c.valid ? c.vel_node(a.nv0, a.nv1) : 0;
-  constexpr bool NEED_U = (MODE & (M_LAPLACE | M_DIVU)) != 0;
+  constexpr bool MASSU = (MODE & M_MASSU) != 0;
+  static_assert(!MASSU || MODE == M_MASSU, "the velocity mass is a mode of its own");
+  constexpr bool NEED_U = (MODE & (M_LAPLACE | M_DIVU)) != 0 || MASSU;
   constexpr bool NEED_P = (MODE & (M_GRADP | M_MASSP)) != 0;
   constexpr bool OUT_U = (MODE & (M_LAPLACE | M_GRADP)) != 0;
   constexpr bool OUT_P = (MODE & (M_DIVU | M_MASSP)) != 0;
@@ -109,7 +111,7 @@ __global__ void __launch_bounds__((Shape<DIM, K, KP>::BLOCK)) cell_kernel(CellAr
   __syncthreads();
 
   T g[3][3] = {};
-  if (NEED_U) {
+  if (NEED_U && !MASSU) {
 #pragma unroll
     for (int comp = 0; comp < DIM; ++comp)
       if (c.active) c.buf(comp)[c.t] = su[comp];
@@ -134,6 +136,27 @@ __global__ void __launch_bounds__((Shape<DIM, K, KP>::BLOCK)) cell_kernel(CellAr
   if (DIM == 3) w *= s_tab[TAB_W + c.ql];
   const T JxW = det * w;
 
+  if constexpr (MASSU) {
+    // velocity mass: values at the points, tested with the values
+#pragma unroll
+    for (int comp = 0; comp < DIM; ++comp) {
+      if (c.active) c.b0[c.t] = su[comp];
+      csync<Sh::WAVE>();
+      const T *vals = c.template interpolate<Sh::N, TAB_S>();
+      const T v = vals[c.t];
+      csync<Sh::WAVE>();
+      if (c.active) c.b0[c.t] = JxW * v;
+      csync<Sh::WAVE>();
+      const T r = c.template integrate<Sh::N, TAB_S>(c.b0);
+      csync<Sh::WAVE>();
+      if (a.ev_u) {
+        if (c.valid) a.ev_u[((int64_t)cell * DIM + comp) * NQ + c.t] = r;
+      } else if (c.valid && !dir) {
+        atomic_add(a.dst_u + comp * a.Nv + vnode, r);
+      }
+    }
+    return;
+  }
   T f[3][3] = {};
   T qv = 0;
   if (MODE & M_LAPLACE) {
@@ -470,6 +493,10 @@ static void dispatch_mode(const CellArgs<T> &a, int mode, int kp, hipStream_t s)
     go<DIM, K, 0, T, M_LAPLACE>(a, s);
     return;
   }
+  if (mode == M_MASSU) {
+    go<DIM, K, 0, T, M_MASSU>(a, s);
+    return;
+  }
   if constexpr (K >= 2) {
     if (mode == (M_LAPLACE | M_DIVU)) {  // lifting of Dirichlet data (right-hand side)
       go<DIM, K, K - 1, T, M_LAPLACE | M_DIVU>(a, s);
@@ -757,7 +784,7 @@ void launch_cell_op_gather(const LevelGeom &g, const DevLevel<T> &d, int mode, T
   const int64_t q = g.k + 1;
   a.ev_p = ev + g.ncells * 3 * q * q * q;
   dispatch_k<3, T>(a, g.k, g.kp, mode, s);
-  const bool out_u = mode & (M_LAPLACE | M_GRADP), out_p = mode & (M_DIVU | M_MASSP);
+  const bool out_u = mode & (M_LAPLACE | M_GRADP | M_MASSU), out_p = mode & (M_DIVU | M_MASSP);
   const int64_t n = std::max<int64_t>(out_u ? g.Nv : 0, out_p ? g.Np : 0);
   if (n > 0)
     hipLaunchKernelGGL((cell_gather_kernel<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, g.k, g.kp,

@@ -85,6 +85,7 @@ enum CellMode : int {
   M_GRADP = 2,    // velocity rows: -(p, div v)
   M_DIVU = 4,     // pressure rows: -(div u, q)
   M_MASSP = 8,    // pressure rows: (p, q)
+  M_MASSU = 16,   // velocity: (u, v) per component (a mode of its own)
 };
 
 template <typename T>
@@ -116,6 +117,20 @@ int64_t q2_face_elems(const LevelGeom &g);
 template <typename T>
 bool launch_stokes_q2(const LevelGeom &g, const T *X, int mode, T nu, T *dst_u, T *dst_p, const T *src_u,
                       const T *src_p, T *face, hipStream_t s);
+// One grouped launch (brick kernel, then combine) of the Q2_STOKES operator
+// for several problems: dst = K src for each (full vectors).  Up to 16
+// problems per launch pair; more are split into further pairs.
+template <typename T>
+struct Q2Problem {
+  LevelGeom g;
+  const T *X;
+  T nu;
+  T *dst;
+  const T *src;
+  T *face;
+};
+template <typename T>
+void launch_stokes_q2_group(const Q2Problem<T> *probs, int n, hipStream_t s);
 // Q2_A with one Chebyshev step fused into its output phase: on every
 // non-Dirichlet row, r = inv (b - A x), d = c2 r (first) or c1 d + c2 r,
 // x += d; Dirichlet rows of x and d are left alone.  x is updated in place:
@@ -223,6 +238,17 @@ template <typename T>
 void jacobi_relax(T *x, const T *b, const T *t, const T *invdiag, T omega, int64_t n, hipStream_t s);
 
 // vector kernels (vector_kernels.hip)
+// stage mixing of stage-major vectors (space-time operators, Sec. 4):
+// y_i = a y_i + sum_j C[i][j] x_j over the first ne entries of each stage,
+// y_i = a y_i over entries ne .. ny-1 (i < no, j < ni <= MFS_MAX_STAGES;
+// a = 0 overwrites y)
+constexpr int MFS_MAX_STAGES = 8;
+struct StageCoef {
+  double c[MFS_MAX_STAGES * MFS_MAX_STAGES];
+};
+template <typename T>
+void stage_mix(T *y, int64_t ldy, int no, const T *x, int64_t ldx, int ni, const StageCoef &C, T a, int64_t ne,
+               int64_t ny, hipStream_t s);
 template <typename T>
 void vec_fill(T *x, T v, int64_t n, hipStream_t s);
 template <typename T>
@@ -233,6 +259,8 @@ template <typename TO, typename TI>
 void vec_cast(TO *y, const TI *x, int64_t n, hipStream_t s);
 template <typename T>
 void vec_zero_mask_boundary(const LevelGeom &g, T *u, hipStream_t s);  // zero Dirichlet rows
+template <typename T>
+void vec_copy_boundary(const LevelGeom &g, T *u, const T *src, hipStream_t s);  // Dirichlet rows of u = src
 // y *= invdiag (per component); Dirichlet rows forced to 0
 template <typename T>
 void vec_diag_scale(const LevelGeom &g, T *y, const T *invdiag, const T *x, hipStream_t s);

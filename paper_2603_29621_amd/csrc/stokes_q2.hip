@@ -184,8 +184,9 @@ __device__ __forceinline__ float recip(float d) {
 // Q2_B (B p alone: no velocity input, no pressure output), Q2_MASSP (pressure
 // mass matrix alone; wave c integrates z-slab c of every cell and the three
 // partial sums meet in the pressure output)
+// the work of brick b of a problem
 template <typename T, int KM>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) stokes_q2_kernel(Args<T> a) {
+__device__ __forceinline__ void q2_brick(const Args<T> &a, const int b) {
   constexpr bool MASS = KM == Q2_MASSP;
   constexpr bool CHEB = KM == Q2_CHEB;
   constexpr bool PRES = KM != Q2_A && !CHEB;                     // pressure input
@@ -199,8 +200,6 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) st
   __shared__ T sX[3 * NPB];  // vertices
 
   // brick index; consecutive bricks share an XCD (round-robin dispatch over 8)
-  int b = blockIdx.x;
-  if (a.nblocks % 8 == 0) b = (b % 8) * (a.nblocks / 8) + b / 8;  // a bijection when 8 | nblocks
   const int bx = b % a.nbx, by = (b / a.nbx) % a.nby, bz = b / (a.nbx * a.nby);
   const int gx0 = 2 * BX * bx, gy0 = 2 * BY * by, gz0 = 2 * BZ * bz;
   const int tid = threadIdx.x;
@@ -506,12 +505,40 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) st
     }
 }
 
+template <typename T, int KM>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) stokes_q2_kernel(Args<T> a) {
+  // brick index; consecutive bricks share an XCD (round-robin dispatch over 8)
+  int b = blockIdx.x;
+  if (a.nblocks % 8 == 0) b = (b % 8) * (a.nblocks / 8) + b / 8;  // a bijection when 8 | nblocks
+  q2_brick<T, KM>(a, b);
+}
+
+// Grouped launch over several problems (the brick kernel or the combine of
+// each): block ranges [start[g], start[g+1]) belong to problem g
+constexpr int MAXG = 16;
+template <typename T>
+struct Group {
+  Args<T> a[MAXG];
+  int start[MAXG + 1];
+  int n;
+};
+__device__ __forceinline__ int group_of(const int *start, int n, int blk) {
+  int g = 0;
+  while (g + 1 < n && blk >= start[g + 1]) ++g;
+  return g;
+}
+
+template <typename T, int KM>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) stokes_q2_group_kernel(Group<T> G) {
+  const int g = group_of(G.start, G.n, blockIdx.x);
+  q2_brick<T, KM>(G.a[g], blockIdx.x - G.start[g]);
+}
+
 // Face nodes: sum the partials of every brick containing the node, in a fixed
 // order (z, y, x brick index); Dirichlet rows: dst = src.
 template <typename T, int KM>
-__global__ void __launch_bounds__(256) q2_combine_kernel(Args<T> a) {
+__device__ __forceinline__ void q2_combine(const Args<T> &a, int64_t i) {
   constexpr bool POUT = KM == Q2_STOKES || KM == Q2_MASSP;
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (KM != Q2_MASSP && i < a.Nv) {
     const int gx = (int)(i % a.nv0);
     const int64_t r = i / a.nv0;
@@ -580,6 +607,17 @@ __global__ void __launch_bounds__(256) q2_combine_kernel(Args<T> a) {
   }
 }
 
+template <typename T, int KM>
+__global__ void __launch_bounds__(256) q2_combine_kernel(Args<T> a) {
+  q2_combine<T, KM>(a, blockIdx.x * (int64_t)blockDim.x + threadIdx.x);
+}
+
+template <typename T, int KM>
+__global__ void __launch_bounds__(256) q2_combine_group_kernel(Group<T> G) {
+  const int g = group_of(G.start, G.n, blockIdx.x);
+  q2_combine<T, KM>(G.a[g], (blockIdx.x - G.start[g]) * (int64_t)blockDim.x + threadIdx.x);
+}
+
 }  // namespace q2
 
 int64_t q2_face_elems(const LevelGeom &g) {
@@ -588,6 +626,63 @@ int64_t q2_face_elems(const LevelGeom &g) {
                      ((g.n[2] + q2::BZ - 1) / q2::BZ);
   return nb * q2::FACE_PER_BRICK;
 }
+
+namespace {
+template <typename T>
+q2::Args<T> q2_args(const LevelGeom &g, const T *X, T nu, T *dst_u, T *dst_p, const T *src_u, const T *src_p,
+                    T *face) {
+  q2::Args<T> a{};
+  a.n0 = g.n[0];
+  a.n1 = g.n[1];
+  a.n2 = g.n[2];
+  a.nv0 = g.nv[0];
+  a.nv1 = g.nv[1];
+  a.nv2 = g.nv[2];
+  a.np0 = g.n[0] + 1;
+  a.np1 = g.n[1] + 1;
+  a.nbx = (g.n[0] + q2::BX - 1) / q2::BX;
+  a.nby = (g.n[1] + q2::BY - 1) / q2::BY;
+  a.nbz = (g.n[2] + q2::BZ - 1) / q2::BZ;
+  a.nblocks = a.nbx * a.nby * a.nbz;
+  a.Nv = g.Nv;
+  a.X = X;
+  a.src_u = src_u;
+  a.src_p = src_p;
+  a.dst_u = dst_u;
+  a.dst_p = dst_p;
+  a.face = face;
+  a.nu = nu;
+  return a;
+}
+}  // namespace
+
+template <typename T>
+void launch_stokes_q2_group(const Q2Problem<T> *probs, int n, hipStream_t s) {
+  for (int first = 0; first < n; first += q2::MAXG) {
+    const int cnt = std::min(q2::MAXG, n - first);
+    q2::Group<T> G{};
+    q2::Group<T> C{};
+    G.n = C.n = cnt;
+    int nb = 0, nc = 0;
+    for (int j = 0; j < cnt; ++j) {
+      const Q2Problem<T> &p = probs[first + j];
+      MFS_REQUIRE(p.g.dim == 3 && p.g.k == 2 && p.g.kp == 1 && p.face != nullptr, MFS_EINVAL,
+                  "grouped Q2/Q1 Stokes launch needs 3D degree-2 Taylor-Hood levels");
+      G.a[j] = C.a[j] = q2_args<T>(p.g, p.X, p.nu, p.dst, p.dst + 3 * p.g.Nv, p.src, p.src + 3 * p.g.Nv, p.face);
+      G.start[j] = nb;
+      C.start[j] = nc;
+      nb += G.a[j].nblocks;
+      nc += (int)((std::max<int64_t>(p.g.Nv, p.g.Np) + 255) / 256);
+    }
+    G.start[cnt] = nb;
+    C.start[cnt] = nc;
+    hipLaunchKernelGGL((q2::stokes_q2_group_kernel<T, Q2_STOKES>), dim3(nb), dim3(q2::NT), 0, s, G);
+    hipLaunchKernelGGL((q2::q2_combine_group_kernel<T, Q2_STOKES>), dim3(nc), dim3(256), 0, s, C);
+    MFS_HIP(hipGetLastError());
+  }
+}
+template void launch_stokes_q2_group<double>(const Q2Problem<double> *, int, hipStream_t);
+template void launch_stokes_q2_group<float>(const Q2Problem<float> *, int, hipStream_t);
 
 template <typename T>
 bool launch_stokes_q2(const LevelGeom &g, const T *X, int mode, T nu, T *dst_u, T *dst_p, const T *src_u,

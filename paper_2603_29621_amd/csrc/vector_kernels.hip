@@ -68,6 +68,35 @@ void vec_cast(TO *y, const TI *x, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL((k_cast<TO, TI>), dim3(nblocks(n)), dim3(VB), 0, s, y, x, n);
 }
 
+// stage mixing of stage-major vectors (space-time operators, Sec. 4):
+// y_i[e] = a y_i[e] + sum_j C[i][j] x_j[e] for e < ne (ldx, ldy: stage
+// strides), and y_i[e] *= a for ne <= e < ny (the rows without a mixed term)
+template <typename T>
+__global__ void k_stage_mix(T *y, int64_t ldy, int no, const T *x, int64_t ldx, int ni, StageCoef C, T a, int64_t ne,
+                            int64_t ny) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ny; e += (int64_t)gridDim.x * blockDim.x) {
+    T xv[MFS_MAX_STAGES];
+    if (e < ne)
+      for (int j = 0; j < ni; ++j) xv[j] = x[j * ldx + e];
+    for (int i = 0; i < no; ++i) {
+      T v = a == T(0) ? T(0) : a * y[i * ldy + e];
+      if (e < ne)
+        for (int j = 0; j < ni; ++j) v += (T)C.c[i * MFS_MAX_STAGES + j] * xv[j];
+      y[i * ldy + e] = v;
+    }
+  }
+}
+template <typename T>
+void stage_mix(T *y, int64_t ldy, int no, const T *x, int64_t ldx, int ni, const StageCoef &C, T a, int64_t ne,
+               int64_t ny, hipStream_t s) {
+  if (ny <= 0) return;
+  hipLaunchKernelGGL(k_stage_mix<T>, dim3(nblocks(ny)), dim3(VB), 0, s, y, ldy, no, x, ldx, ni, C, a, ne, ny);
+}
+template void stage_mix<double>(double *, int64_t, int, const double *, int64_t, int, const StageCoef &, double,
+                                int64_t, int64_t, hipStream_t);
+template void stage_mix<float>(float *, int64_t, int, const float *, int64_t, int, const StageCoef &, float, int64_t,
+                               int64_t, hipStream_t);
+
 template <typename T>
 __global__ void k_zero_boundary(int dim, int nv0, int nv1, int nv2, int64_t Nv, T *u) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -78,6 +107,18 @@ template <typename T>
 void vec_zero_mask_boundary(const LevelGeom &g, T *u, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_boundary<T>, dim3(nblocks(g.Nv)), dim3(VB), 0, s, g.dim, g.nv[0], g.nv[1], g.nv[2], g.Nv,
                      u);
+}
+
+template <typename T>
+__global__ void k_copy_boundary(int dim, int nv0, int nv1, int nv2, int64_t Nv, T *u, const T *src) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= Nv || !on_boundary(dim, nv0, nv1, nv2, i)) return;
+  for (int c = 0; c < dim; ++c) u[c * Nv + i] = src[c * Nv + i];
+}
+template <typename T>
+void vec_copy_boundary(const LevelGeom &g, T *u, const T *src, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_boundary<T>, dim3(nblocks(g.Nv)), dim3(VB), 0, s, g.dim, g.nv[0], g.nv[1], g.nv[2], g.Nv,
+                     u, src);
 }
 
 template <typename T>
@@ -457,6 +498,7 @@ void launch_reciprocal_boundary_one(const LevelGeom &g, double *d, hipStream_t s
   template void vec_copy<T>(T *, const T *, int64_t, hipStream_t);                                \
   template void vec_axpby<T>(T *, T, const T *, T, int64_t, hipStream_t);                         \
   template void vec_zero_mask_boundary<T>(const LevelGeom &, T *, hipStream_t);                   \
+  template void vec_copy_boundary<T>(const LevelGeom &, T *, const T *, hipStream_t);             \
   template void vec_diag_scale<T>(const LevelGeom &, T *, const T *, const T *, hipStream_t);     \
   template void cheb_update<T>(const LevelGeom &, T *, T *, const T *, const T *, const T *, T, T, \
                                bool, hipStream_t);                                                \

@@ -8,9 +8,11 @@ admission stops until it fits).  Each admitted request gets its own HIP
 stream and problem handle, whose device memory is one arena from torch's
 allocator (``mfs_setup_arena``; releasing it does not wait for the device);
 setup (mesh upload, multigrid hierarchy, right-hand side) runs on worker
-threads, and the main thread advances every active
-solve by one FGMRES iteration whenever its previous iteration has finished
-(``mfs_solve_advance`` never blocks).  Kernels of different requests
+threads, and the main thread calls ``mfs_batch_step`` over all active
+solves: every solve whose previous iteration has finished gets its next
+FGMRES iteration, and the system operator applications of the Q2/Q1 solves
+that step together share one grouped launch (the call never blocks).
+Kernels of different requests
 therefore overlap on the device, and a request's Krylov state, mesh and
 hierarchy stay resident in HBM until it completes.
 
@@ -116,13 +118,14 @@ def _setup_request(req, opts, stream):
 class Server:
     def __init__(self, budget_bytes: float, max_active: int = 32, precond=mfs.MFS_FP32, rtol: float = 1e-8,
                  maxit: int = 300, setup_workers: int = 2, max_bypass_s: float = 2.0, keep_solutions=False,
-                 graphs: int = 1):
+                 graphs: int = 1, batch: bool = True):
         self.budget = float(budget_bytes)
         self.max_active = max_active
         self.opts = _options(precond, rtol, maxit, graphs)
         self.setup_workers = setup_workers
         self.max_bypass_s = max_bypass_s
         self.keep = keep_solutions
+        self.batch = batch  # advance the active solves with mfs_batch_step (grouped operator launches)
 
     def run(self, requests, realtime: bool = True, on_result=None):
         """Serve the requests; on_result(result), if given, is called as each one
@@ -140,6 +143,7 @@ class Server:
         streams = []
         lock = threading.Lock()
         pool = ThreadPoolExecutor(self.setup_workers)
+        group_stream = torch.cuda.Stream()
         t0 = time.perf_counter()
         try:
             while pending or waiting or active or setups:
@@ -176,9 +180,13 @@ class Server:
                         active[rid] = a
                         del setups[rid]
                         progressed = True
-                for rid in list(active):
+                rids = list(active)
+                if self.batch:
+                    steps = mfs.mfs_batch_step([active[rid].h for rid in rids], stream=group_stream.cuda_stream)
+                else:
+                    steps = [mfs.mfs_solve_advance(active[rid].h) for rid in rids]
+                for rid, (done, info) in zip(rids, steps):
                     a = active[rid]
-                    done, info = mfs.mfs_solve_advance(a.h)
                     if done:
                         t = time.perf_counter() - t0
                         res = Result(rid, a.req.n, a.req.k, a.req.nu, a.req.arrival if realtime else 0.0, a.admitted,

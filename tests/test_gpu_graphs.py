@@ -1,5 +1,6 @@
-"""The recorded FP32 preconditioner (one HIP graph per problem, replayed in
-every FGMRES iteration) against the same solve launched kernel by kernel.
+"""The recorded preconditioner (one HIP graph per problem and precision,
+replayed in every FGMRES iteration; the FP64 one staged through fixed
+vectors) against the same solve launched kernel by kernel.
 
 Each solve replays the graph once per iteration, with the FP64 operator, the
 Gram-Schmidt kernels and a host synchronisation on the Arnoldi coefficients
@@ -42,7 +43,8 @@ def relerr(y, ref):
 
 def _solve(h, b, graphs, stream=None, **kw):
     x = torch.zeros_like(b)
-    opts = mfs.mfs_default_options(rtol=1e-10, maxit=200, precond_precision=mfs.MFS_FP32, graphs=graphs, **kw)
+    opts = mfs.mfs_default_options(**{"rtol": 1e-10, "maxit": 200, "precond_precision": mfs.MFS_FP32,
+                                      "graphs": graphs, **kw})
     if stream is None:
         info = mfs.mfs_solve(h, b, x, opts)
     else:
@@ -75,7 +77,8 @@ def _rhs(h, op, N, seed):
 
 
 @pytest.mark.parametrize("n,k,side", [([6, 5, 4], 2, False), ([4, 4, 3], 3, True)])
-def test_stokes_graph_solve_matches_direct(n, k, side):
+@pytest.mark.parametrize("prec", [mfs.MFS_FP32, mfs.MFS_FP64])
+def test_stokes_graph_solve_matches_direct(n, k, side, prec):
     X = inputs.structured_vertices(3, n, noise=0.2, seed=3)
     h = mfs.mfs_setup(3, n, X, k, 0.8, mfs.mfs_default_options())
     try:

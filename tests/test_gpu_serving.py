@@ -74,3 +74,47 @@ def test_sequential_fp64_baseline_converges():
     assert all(r.status == 0 and r.rel_residual <= 1e-8 for r in res)
     s = serving.summarize(res)
     assert s["solves"] == 3 and s["p99_latency_s"] >= s["p50_latency_s"]
+
+
+def test_batch_step_equals_separate_solves():
+    """Three Q2/Q1 solves begun together and advanced by mfs_batch_step (their
+    system operators in one grouped launch per step) give the same solutions
+    and iteration counts, bit for bit, as three separate mfs_solve calls; a
+    Q3/Q2 solve in the same batch steps on its own."""
+    from paper_2603_29621_amd.serving import _setup_request
+
+    opts = mfs.mfs_default_options()
+    reqs = [inputs.Request(i, 0.0, n, k, nu, 0.1, 20 + i)
+            for i, (n, k, nu) in enumerate(((8, 2, 0.3), (6, 2, 0.05), (8, 2, 1.0), (4, 3, 0.2)))]
+    ref = []
+    for r in reqs:
+        s = torch.cuda.Stream()
+        h, b, x, arena = _setup_request(r, opts, s)
+        info = mfs.mfs_solve(h, b, x, opts, stream=s.cuda_stream)
+        ref.append((info.iterations, x.clone()))
+        mfs.mfs_destroy(h)
+        del arena
+    live = []
+    for r in reqs:
+        s = torch.cuda.Stream()
+        h, b, x, arena = _setup_request(r, opts, s)
+        live.append((h, b, x, arena, s))
+    for h, b, x, _, s in live:
+        mfs.mfs_solve_begin(h, b, x, opts, stream=s.cuda_stream)
+    gs = torch.cuda.Stream()
+    done = [False] * len(live)
+    infos = [None] * len(live)
+    for _ in range(100000):
+        idx = [i for i in range(len(live)) if not done[i]]
+        if not idx:
+            break
+        out = mfs.mfs_batch_step([live[i][0] for i in idx], stream=gs.cuda_stream)
+        for i, (d, info) in zip(idx, out):
+            if d:
+                done[i], infos[i] = True, info
+    assert all(done)
+    torch.cuda.synchronize()
+    for (h, b, x, arena, s), info, (its, xr) in zip(live, infos, ref):
+        assert info.status == 0 and info.iterations == its
+        assert torch.equal(x, xr)
+        mfs.mfs_destroy(h)

@@ -86,3 +86,17 @@ def test_time_prolongation_reproduces_polynomials(kf, kc):
     sf, sc = spacetime.time_nodes(kf), spacetime.time_nodes(kc)
     for d in range(kc + 1):
         assert np.allclose(P @ sc ** d, sf ** d, atol=1e-13)
+
+
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
+def test_package_stage_matrices_equal_the_oracle(k):
+    """The host-side DG(k) matrices the package hands to the library."""
+    from paper_2603_29621_amd import spacetime as pst
+
+    G, MQ, AQ, m, e = pst.dg_stage_matrices(k)
+    MQo, AQo, mo, eo = spacetime.time_matrices(k)
+    assert np.allclose(G, spacetime.G_matrix(k), atol=1e-12)
+    assert np.allclose(MQ, MQo, atol=1e-14) and np.allclose(AQ, AQo, atol=1e-12)
+    assert np.allclose(m, mo, atol=1e-13) and np.allclose(e, eo, atol=1e-13)
+    if k > 0:
+        assert np.allclose(pst.stage_prolongation(k, k - 1), spacetime.time_prolongation(k, k - 1), atol=1e-13)
