@@ -23,6 +23,8 @@ Readings where the paper gives only the method names:
   x <- x + omega D^{-1} (b - J x), before and after the coarse correction,
   with D the diagonal of the constrained J (1 on Dirichlet rows); reading
   omega = 0.5 and 5 sweeps (the paper states 5 relaxation iterations).
+  With ``smoother="asm"`` the sweeps use the additive Schwarz operator of
+  ``oracle/asm.py`` in place of D^{-1} (the paper's Exp. 4: 2 sweeps).
 * The constrained J is singular: a constant pressure lies in its kernel (the
   velocity vanishes on the whole boundary, so the pressure terms see only its
   gradient or integrate to a boundary flux).  The direct coarse solve fixes
@@ -40,7 +42,7 @@ import scipy.sparse as sp
 
 import inputs
 
-from . import basis, ns
+from . import asm, basis, ns
 from .fem import Space
 from .krylov import fgmres
 from .mg import transfer_matrix
@@ -96,9 +98,9 @@ class NSHierarchy:
     coarse factorisation."""
 
     def __init__(self, dim, n, X, k, nu, dt, u0, newton=True, p_min=1, coarse_min=2, relax_steps=5,
-                 omega=0.5):
+                 omega=0.5, smoother="jacobi"):
         self.dim, self.nu, self.dt, self.newton = dim, nu, dt, newton
-        self.relax_steps, self.omega = relax_steps, omega
+        self.relax_steps, self.omega, self.smoother = relax_steps, omega, smoother
         specs = ns_level_specs(n, k, p_min, coarse_min)
         self.spaces, self.u0 = [], []
         for nl, kl, hl in specs:
@@ -114,6 +116,12 @@ class NSHierarchy:
             self.J.append(J)
             self.Dinv.append(1.0 / J.diagonal())
             self.fixed.append(ns.ns_dirichlet_mask(S))
+        self.B = []
+        if smoother == "asm":
+            for l in range(len(self.spaces) - 1):
+                self.B.append(asm.ASM(self.J[l], asm.patches(self.spaces[l], self.fixed[l])))
+        elif smoother != "jacobi":
+            raise ValueError(smoother)
         for l in range(len(self.spaces) - 1):
             Sf, Sc = self.spaces[l], self.spaces[l + 1]
             h = Sf.n != Sc.n
@@ -133,6 +141,8 @@ class NSHierarchy:
         return la.lu_solve(self.coarse_lu, b)
 
     def relax(self, l, x, b):
+        if self.smoother == "asm":
+            return asm.relax(self.J[l], self.B[l], x, b, self.relax_steps, self.omega)
         for _ in range(self.relax_steps):
             x = x + self.omega * self.Dinv[l] * (b - self.J[l] @ x)
         return x
