@@ -35,7 +35,11 @@ FLOP_PER_DOF = {2: 318.0, 3: 243.0, 4: 217.0}
 # HBM bytes per FP64 Q2/Q1 vmult on 64^3 cells measured with rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (scaled by 2.00 and 1.00, the factors a 256 MiB device copy gives) for the
 # current cell + combine kernels; to be re-measured whenever those kernels change.
-MEASURED_TRAFFIC = {(2, 64, "f64"): 308.6e6}
+MEASURED_TRAFFIC = {(2, 64, "f64"): 308.8e6}
+# Executed FP64 flops per vmult, counted with rocprofv3 (SQ_INSTS_VALU_{FMA,MUL,ADD,TRANS}_F64,
+# 64 lanes per wave instruction, an FMA as 2 flops) over the same kernels: Q2/Q1 cell kernel
+# 4.326 GFLOP + combine 0.019 GFLOP on 64^3 cells; Q3/Q2 cell kernel 11.996 + gather 0.091.
+COUNTED_FP64_FLOP = {(2, 64): 4.345e9, (3, 64): 12.087e9}
 
 
 def algorithmic_bytes(dim, n, k, word):
@@ -757,9 +761,15 @@ def main():
     if not args.no_sweep:
         line["spacetime"] = line_spacetime
     if args.prec == "f64" and k in FLOP_PER_DOF:
-        fl = FLOP_PER_DOF[k] * main_run["N"] / main_run["avg_launch_s"]
+        # executed flops (counter-derived) where counted for this size, beside the model
+        model = FLOP_PER_DOF[k] * main_run["N"]
+        counted = COUNTED_FP64_FLOP.get((k, n))
+        fl = (counted if counted else model) / main_run["avg_launch_s"]
         line["roofline_alu"] = {"bound": "alu", "achieved": fl / 1e12, "peak": FP64_PEAK / 1e12, "unit": "TFLOP/s",
-                                "frac": fl / FP64_PEAK, "flop_per_dof": FLOP_PER_DOF[k]}
+                                "frac": fl / FP64_PEAK, "flops": "counted" if counted else "model",
+                                "counted_flop_per_dof": counted / main_run["N"] if counted else None,
+                                "model_flop_per_dof": FLOP_PER_DOF[k],
+                                "model_frac": model / main_run["avg_launch_s"] / FP64_PEAK}
     if not args.no_ns:
         line["navier_stokes"] = ns_section(mfs, torch, inputs, args)
         progress("navier_stokes done")
