@@ -62,6 +62,11 @@ extern "C" {
 #define MFS_FP64 0
 #define MFS_FP32 1
 
+/* relaxation of the monolithic Navier-Stokes multigrid (mfs_options.relax_type) */
+#define MFS_RELAX_JACOBI 0 /* damped point Jacobi x += omega D^-1 (b - J x) */
+#define MFS_RELAX_ASM 1    /* additive Schwarz: x += omega sum_P R_P^T W A_P^-1 R_P (b - J x), one patch
+                              per vertex (the unknowns within one cell of it), W = 1/multiplicity */
+
 /* operators for mfs_vmult */
 #define MFS_OP_STOKES 0      /* [u;p] -> [A u + B p ; B^T u], full vectors            */
 #define MFS_OP_A 1           /* velocity block: u -> A u (vector Laplacian, nu-scaled) */
@@ -100,6 +105,9 @@ typedef struct mfs_options {
   /* solve loop */
   int graphs;            /* 1: the FP32 preconditioner of a solve is recorded once per problem as a
                             HIP graph and replayed each FGMRES iteration; 0: launched kernel by kernel */
+  int relax_type;        /* Navier-Stokes relaxation: MFS_RELAX_JACOBI (point Jacobi) or MFS_RELAX_ASM
+                            (additive Schwarz on vertex patches, Sec. 2 and Sec. 5 Exp. 4; structured
+                            meshes, degrees 1 and 2; the paper's Exp. 4 uses 2 steps, omega = 1) */
 } mfs_options;
 
 typedef struct mfs_solve_info {

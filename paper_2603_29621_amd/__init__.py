@@ -25,6 +25,8 @@ MFS_EHIP = -4
 MFS_ENOCONV = -5
 MFS_FP64 = 0
 MFS_FP32 = 1
+MFS_RELAX_JACOBI = 0
+MFS_RELAX_ASM = 1
 MFS_OP_STOKES = 0
 MFS_OP_A = 1
 MFS_OP_B = 2
@@ -75,6 +77,7 @@ class mfs_options(ctypes.Structure):
         ("relax_steps", ctypes.c_int),
         ("relax_omega", ctypes.c_double),
         ("graphs", ctypes.c_int),
+        ("relax_type", ctypes.c_int),
     ]
 
 

@@ -85,6 +85,9 @@ struct Level {
   float *qd32 = nullptr;
   double *nsinv64 = nullptr;
   float *nsinv32 = nullptr;
+  // additive Schwarz relaxation: inverse patch matrices (vertex patches)
+  double *asm64 = nullptr;
+  float *asm32 = nullptr;
   // scratch of the three-pass restriction to the next coarser level
   double *rs64 = nullptr;
   float *rs32 = nullptr;
@@ -284,6 +287,7 @@ struct mfs_problem {
   PrecWork<double> w64;
   PrecWork<float> w32;
   double *m1 = nullptr;         // M_p 1 (pressure mean)
+  int *flags = nullptr;         // device status words (Navier-Stokes set-up)
   double *scal = nullptr;       // device scalars for PCG / means
   double *partials = nullptr;   // reduction scratch
   double *tmp_full = nullptr;   // FP64 full-length temporary
@@ -456,6 +460,11 @@ void plan_arena(Arena &A, mfs_problem &P, const std::vector<LevelGeom> &G) {
       L.qd32 = A.take<float>(ns_qd_elems(G[l]));
       L.nsinv64 = A.take<double>((P.dim + 1) * G[l].Nv);
       L.nsinv32 = A.take<float>((P.dim + 1) * G[l].Nv);
+      if (P.opts.mg_levels && P.opts.relax_type == MFS_RELAX_ASM && l + 1 < G.size()) {
+        const int64_t np = asm_patch_size(G[l]);
+        L.asm64 = A.take<double>(asm_patch_count(G[l]) * np * np);
+        L.asm32 = A.take<float>(asm_patch_count(G[l]) * np * np);
+      }
       // FP32 Jacobian: cell-local outputs and a node gather (3D)
       if (P.dim == 3) {
         const int64_t q = G[l].k + 1;
@@ -475,6 +484,7 @@ void plan_arena(Arena &A, mfs_problem &P, const std::vector<LevelGeom> &G) {
     P.m1 = A.take<double>(G[0].Nv);
     P.scal = A.take<double>(4 * PCG_MAX + 64);
     P.partials = A.take<double>(32 * DOT_BLOCKS);
+    P.flags = A.take<int>(64);
     P.tmp_full = A.take<double>(ntot);
     P.tmp2 = A.take<double>(ntot);
     if (full) {  // the BDF2 / Newton driver: history, residual, correction
@@ -564,6 +574,8 @@ void check_options(const mfs_options &o) {
               "precond_precision must be MFS_FP32 or MFS_FP64");
   MFS_REQUIRE(o.relax_steps >= 1 && o.relax_steps <= 64, MFS_EINVAL, "relax_steps out of range");
   MFS_REQUIRE(o.relax_omega > 0 && o.relax_omega < 2, MFS_EINVAL, "relax_omega must be in (0, 2)");
+  MFS_REQUIRE(o.relax_type == MFS_RELAX_JACOBI || o.relax_type == MFS_RELAX_ASM, MFS_EINVAL,
+              "relax_type must be MFS_RELAX_JACOBI or MFS_RELAX_ASM");
 }
 
 void check_mesh(const mfs_mesh *mesh, int k, const mfs_options &o) {
@@ -1103,7 +1115,35 @@ void ns_setup_coarse(mfs_problem &P, hipStream_t s) {
   MFS_HIP(hipStreamSynchronize(s));
 }
 
-// Jacobi diagonals and the pinned coarse inverse of the current linearisation
+// Additive Schwarz patch inverses of level l at the current linearisation:
+// column j of every patch matrix of a colour from one FP64 Jacobian apply to
+// the sum of the colour's unit vectors at local index j, then a batched
+// inversion; the FP32 copy serves the FP32 multigrid.
+void ns_asm_setup(mfs_problem &P, int l, hipStream_t s) {
+  Level &L = P.L[l];
+  const LevelGeom &g = L.g;
+  const int64_t n = (P.dim + 1) * g.Nv;
+  const int np = asm_patch_size(g);
+  double *x = P.w64.b[l], *y = P.w64.r[l];
+  vec_fill<double>(x, 0.0, n, s);
+  for (int c = 0; c < asm_colours(g); ++c)
+    for (int j = 0; j < np; ++j) {
+      launch_asm_probe_set(g, x, c, j, 1.0, s);
+      apply_ns<double>(P, l, y, x, s);
+      launch_asm_probe_extract(g, y, L.asm64, c, j, s);
+      launch_asm_probe_set(g, x, c, j, 0.0, s);
+    }
+  MFS_HIP(hipMemsetAsync(P.flags, 0, sizeof(int), s));
+  launch_asm_invert(g, L.asm64, P.flags, s);
+  int bad = 0;
+  MFS_HIP(hipMemcpyAsync(&bad, P.flags, sizeof(int), hipMemcpyDeviceToHost, s));
+  MFS_HIP(hipStreamSynchronize(s));
+  MFS_REQUIRE(bad == 0, MFS_EINVAL, "singular additive Schwarz patch matrix on level %d", l);
+  vec_cast<float, double>(L.asm32, L.asm64, asm_patch_count(g) * np * np, s);
+}
+
+// Jacobi diagonals (or Schwarz patch inverses) and the pinned coarse inverse
+// of the current linearisation
 void ns_mg_data(mfs_problem &P, hipStream_t s) {
   if (!P.opts.mg_levels) return;
   for (int l = 0; l + 1 < P.nlev; ++l) {
@@ -1112,6 +1152,7 @@ void ns_mg_data(mfs_problem &P, hipStream_t s) {
     double *d = P.w64.x[l];
     ns_diagonal(P, l, d, s);
     launch_reciprocal(L.nsinv64, L.nsinv32, d, n, s);
+    if (L.asm64) ns_asm_setup(P, l, s);
   }
   ns_setup_coarse(P, s);
 }
@@ -1239,7 +1280,13 @@ void ns_relax(mfs_problem &P, int l, T *x, const T *b, hipStream_t s) {
   const int64_t n = (P.dim + 1) * L.g.Nv;
   for (int it = 0; it < P.opts.relax_steps; ++it) {
     apply_ns<T>(P, l, W.d[l], x, s);
-    jacobi_relax<T>(x, b, W.d[l], ns_invdiag<T>(L), (T)P.opts.relax_omega, n, s);
+    if (L.asm64) {  // additive Schwarz: every colour with the residual b - J x of the sweep's start
+      const T *Minv = sizeof(T) == 8 ? (const T *)L.asm64 : (const T *)L.asm32;
+      for (int c = 0; c < asm_colours(L.g); ++c)
+        launch_asm_apply<T>(L.g, Minv, c, b, W.d[l], x, (T)P.opts.relax_omega, s);
+    } else {
+      jacobi_relax<T>(x, b, W.d[l], ns_invdiag<T>(L), (T)P.opts.relax_omega, n, s);
+    }
   }
 }
 
@@ -1822,6 +1869,7 @@ void mfs_default_options(mfs_options *o) {
   o->relax_steps = 5;
   o->relax_omega = 0.5;
   o->graphs = 1;
+  o->relax_type = MFS_RELAX_JACOBI;
 }
 
 const char *mfs_last_error(void) { return get_error(); }
@@ -2906,6 +2954,8 @@ int mfs_setup_refined(const mfs_refined_mesh *mesh, int k, double nu, const mfs_
     MFS_REQUIRE(o.pressure_offset == 0, MFS_EUNSUPPORTED,
                 "refined meshes provide the equal-order Navier-Stokes Jacobian (pressure_offset = 0)");
     MFS_REQUIRE(k == 1 || k == 2, MFS_EUNSUPPORTED, "refined meshes support degrees 1 and 2 (got %d)", k);
+    MFS_REQUIRE(o.relax_type == MFS_RELAX_JACOBI, MFS_EUNSUPPORTED,
+                "refined meshes relax with point Jacobi (additive Schwarz patches need a structured level)");
     MFS_REQUIRE(mesh->n >= 1 && mesh->n <= 4096, MFS_EINVAL, "base cells per direction %d out of range", mesh->n);
     const bool mg = o.mg_levels != 0;
     if (mg) {

@@ -157,6 +157,21 @@ void launch_laplace_diagonal(const LevelGeom &g, const double *X, const double *
 void launch_mass_diagonal(const LevelGeom &g, const double *X, const double *tab, double *diag, hipStream_t s);
 // r64 = 1/d, r32 = (float)(1/d)
 void launch_reciprocal(double *r64, float *r32, const double *d, int64_t n, hipStream_t s);
+
+// additive Schwarz relaxation on the vertex patches of a structured
+// equal-order level (degrees 1, 2): patch size, count, colours; column j of
+// every patch matrix of a colour by probing (set unit entries, apply J,
+// extract, reset); batched in-place inversion (status |= 1 on a zero pivot);
+// x += omega W A_P^{-1} (b - t) over the patches of one colour
+int asm_patch_size(const LevelGeom &g);
+int64_t asm_patch_count(const LevelGeom &g);
+int asm_colours(const LevelGeom &g);
+void launch_asm_probe_set(const LevelGeom &g, double *x, int colour, int j, double value, hipStream_t s);
+void launch_asm_probe_extract(const LevelGeom &g, const double *y, double *M, int colour, int j, hipStream_t s);
+void launch_asm_invert(const LevelGeom &g, double *M, int *status, hipStream_t s);
+template <typename T>
+void launch_asm_apply(const LevelGeom &g, const T *M, int colour, const T *b, const T *t, T *x, T omega,
+                      hipStream_t s);
 // d[i] = 1 on Dirichlet rows of a scalar velocity-node vector
 void launch_reciprocal_boundary_one(const LevelGeom &g, double *d, hipStream_t s);
 // det J > 0 check: writes the smallest det J * (cells) and the first bad cell
