@@ -514,7 +514,7 @@ void plan_arena(Arena &A, mfs_problem &P, const std::vector<LevelGeom> &G) {
     L.diag = A.take<double>(G[l].Nv);
     L.face64 = A.take<double>(q2_face_elems(G[l]) + q1_face_elems(G[l]));
     L.face32 = A.take<float>(q2_face_elems(G[l]) + q1_face_elems(G[l]));
-    L.ev64 = A.take<double>(G[l].k == 3 ? cell_ev_elems(G[l]) : 0);
+    L.ev64 = A.take<double>(cell_ev_elems(G[l]));
     L.ev32 = A.take<float>(cell_ev_elems(G[l]));
     L.invdiag64 = A.take<double>(G[l].Nv);
     L.invdiag32 = A.take<float>(G[l].Nv);
@@ -687,12 +687,12 @@ float *cellev<float>(const Level &L) {
   return L.ev32;
 }
 // Generic kernel with cell-local outputs and a node gather instead of global
-// atomics: in FP32 for every 3D level of degree >= 3, in FP64 for degree 3
-// only (measured at 64^3: Q3/Q2 -13% FP64, -42% FP32; Q4/Q3 -30% FP32 but
-// +20% FP64, where the cell-local arrays cost more than the FP64 atomics).
+// atomics, on every 3D level of degree >= 3 (measured at 64^3 against the
+// atomics launched one cell colour at a time: Q4/Q3 FP64 1.93 ms against
+// 2.21 ms, once the cell-local rows were laid out for the gather).
 template <typename T>
 bool use_gather(const Level &L) {
-  return cell_ev_elems(L.g) > 0 && (sizeof(T) == 4 || L.g.k == 3);
+  return cell_ev_elems(L.g) > 0;
 }
 template <typename T>
 PrecWork<T> &work(mfs_problem &P);

@@ -150,7 +150,7 @@ __global__ void __launch_bounds__((Shape<DIM, K, KP>::BLOCK)) cell_kernel(CellAr
       const T r = c.template integrate<Sh::N, TAB_S>(c.b0);
       csync<Sh::WAVE>();
       if (a.ev_u) {
-        if (c.valid) a.ev_u[((int64_t)cell * DIM + comp) * NQ + c.t] = r;
+        if (c.valid) a.ev_u[cell_slot(a.n0, a.n1, DIM, Q, c.cx, c.cy, c.cz, comp, c.qi, c.qj, c.ql)] = r;
       } else if (c.valid && !dir) {
         atomic_add(a.dst_u + comp * a.Nv + vnode, r);
       }
@@ -203,7 +203,8 @@ __global__ void __launch_bounds__((Shape<DIM, K, KP>::BLOCK)) cell_kernel(CellAr
     if (a.ev_u) {
       if (c.valid)
 #pragma unroll
-        for (int comp = 0; comp < DIM; ++comp) a.ev_u[((int64_t)cell * DIM + comp) * NQ + c.t] = r[comp];
+        for (int comp = 0; comp < DIM; ++comp)
+          a.ev_u[cell_slot(a.n0, a.n1, DIM, Q, c.cx, c.cy, c.cz, comp, c.qi, c.qj, c.ql)] = r[comp];
     } else {
 #pragma unroll
       for (int comp = 0; comp < DIM; ++comp)
@@ -215,8 +216,8 @@ __global__ void __launch_bounds__((Shape<DIM, K, KP>::BLOCK)) cell_kernel(CellAr
     csync<Sh::WAVE>();
     const T r = c.template integrate<Sh::M, TAB_SP>(c.b0);
     if (a.ev_p) {
-      constexpr int M = Sh::M, MP = DIM == 3 ? M * M * M : M * M;
-      if (c.valid && ploc) a.ev_p[(int64_t)cell * MP + c.qi + M * (c.qj + M * c.ql)] = r;
+      constexpr int M = Sh::M;
+      if (c.valid && ploc) a.ev_p[cell_slot(a.n0, a.n1, 1, M, c.cx, c.cy, c.cz, 0, c.qi, c.qj, c.ql)] = r;
     } else if (c.valid && ploc) {
       atomic_add(a.dst_p + pnode, r);
     }
@@ -695,7 +696,7 @@ template <typename T>
 __global__ void __launch_bounds__(256) cell_gather_kernel(CellArgs<T> a, int k, int kp, T *dst_u, T *dst_p,
                                                            const T *dir_src) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int Q = k + 1, NQ = Q * Q * Q;
+  const int Q = k + 1;
   if (dst_u && i < a.Nv) {
     const int gx = (int)(i % a.nv0);
     const int64_t r = i / a.nv0;
@@ -709,16 +710,14 @@ __global__ void __launch_bounds__(256) cell_gather_kernel(CellArgs<T> a, int k, 
       T acc[3] = {0, 0, 0};
       for (int z = 0; z < nz; ++z)
         for (int y = 0; y < ny; ++y)
-          for (int x = 0; x < nx; ++x) {
-            const int64_t cell = cx[x] + (int64_t)a.n0 * (cy[y] + (int64_t)a.n1 * cz[z]);
-            const int loc = lx[x] + Q * (ly[y] + Q * lz[z]);
-            for (int c = 0; c < 3; ++c) acc[c] += a.ev_u[(cell * 3 + c) * NQ + loc];
-          }
+          for (int x = 0; x < nx; ++x)
+            for (int c = 0; c < 3; ++c)
+              acc[c] += a.ev_u[cell_slot(a.n0, a.n1, 3, Q, cx[x], cy[y], cz[z], c, lx[x], ly[y], lz[z])];
       for (int c = 0; c < 3; ++c) dst_u[c * a.Nv + i] = acc[c];
     }
   }
   if (dst_p && i < a.Np) {
-    const int M = kp + 1, MP = M * M * M;
+    const int M = kp + 1;
     const int px = (int)(i % a.np0);
     const int64_t r = i / a.np0;
     const int py = (int)(r % a.np1), pz = (int)(r / a.np1);
@@ -728,10 +727,7 @@ __global__ void __launch_bounds__(256) cell_gather_kernel(CellArgs<T> a, int k, 
     T acc = 0;
     for (int z = 0; z < nz; ++z)
       for (int y = 0; y < ny; ++y)
-        for (int x = 0; x < nx; ++x) {
-          const int64_t cell = cx[x] + (int64_t)a.n0 * (cy[y] + (int64_t)a.n1 * cz[z]);
-          acc += a.ev_p[cell * MP + lx[x] + M * (ly[y] + M * lz[z])];
-        }
+        for (int x = 0; x < nx; ++x) acc += a.ev_p[cell_slot(a.n0, a.n1, 1, M, cx[x], cy[y], cz[z], 0, lx[x], ly[y], lz[z])];
     dst_p[i] = acc;
   }
 }

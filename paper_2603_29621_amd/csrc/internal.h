@@ -79,6 +79,17 @@ struct DevLevel {
   const T *invdiag = nullptr;  // inverse diagonal of A, one component [Nv]
 };
 
+// Slot of a cell-local result (3D): node (lx, ly, lz) of component comp of cell
+// (cx, cy, cz), q nodes per direction, ncomp components.  For each cell row
+// (cy, cz), component and node row (ly, lz) the slots of all cells along x lie
+// side by side, q each, so a node gather that reads x-consecutive nodes reads
+// consecutive slots, and the cells of a workgroup (consecutive in x) write
+// whole lines.
+__host__ __device__ __forceinline__ int64_t cell_slot(int n0, int n1, int ncomp, int q, int cx, int cy, int cz,
+                                                      int comp, int lx, int ly, int lz) {
+  return (((((int64_t)cz * n1 + cy) * ncomp + comp) * q + lz) * q + ly) * ((int64_t)n0 * q) + (int64_t)cx * q + lx;
+}
+
 // ----------------------------------------------------------------- kernels
 enum CellMode : int {
   M_LAPLACE = 1,  // velocity: nu (grad u, grad v)

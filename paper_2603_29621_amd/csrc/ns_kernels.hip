@@ -499,7 +499,8 @@ __global__ void __launch_bounds__((Shape<DIM, K>::BLOCK)) ns_jacobian_kernel(Arg
     const T r = c.integrate(JxW * val_u[comp], f);
     if (a.ev) {
       if (c.valid)
-        a.ev[a.evin ? ((int64_t)cell * NQ + c.t) * 4 + comp : ((int64_t)cell * 3 + comp) * NQ + c.t] = r;
+        a.ev[a.evin ? ((int64_t)cell * NQ + c.t) * 4 + comp
+                    : cell_slot(a.n0, a.n1, 3, Q, c.cx, c.cy, c.cz, comp, c.qi, c.qj, c.ql)] = r;
     } else if (c.valid && !dir) {
       atomicAdd(a.dst + comp * a.Nv + nd, r);
     }
@@ -514,7 +515,8 @@ __global__ void __launch_bounds__((Shape<DIM, K>::BLOCK)) ns_jacobian_kernel(Arg
     const T r = c.integrate(JxW * div, f);
     if (a.ev) {
       if (c.valid)
-        a.ev[a.evin ? ((int64_t)cell * NQ + c.t) * 4 + 3 : (int64_t)a.ncells * 3 * NQ + (int64_t)cell * NQ + c.t] = r;
+        a.ev[a.evin ? ((int64_t)cell * NQ + c.t) * 4 + 3
+                    : (int64_t)a.ncells * 3 * NQ + cell_slot(a.n0, a.n1, 1, Q, c.cx, c.cy, c.cz, 0, c.qi, c.qj, c.ql)] = r;
     } else if (c.valid) {
       atomicAdd(a.dst + DIM * a.Nv + nd, r);
     }
