@@ -469,6 +469,7 @@ void plan_arena(Arena &A, mfs_problem &P, const std::vector<LevelGeom> &G) {
       if (P.dim == 3) {
         const int64_t q = G[l].k + 1;
         L.ev32 = A.take<float>(G[l].ncells * 4 * q * q * q);
+        L.ev64 = A.take<double>(G[l].ncells * 4 * q * q * q);
       }
       if (l + 1 < G.size()) {
         L.rs64 = A.take<double>(restrict_work_elems(G[l], G[l + 1], P.dim + 1));
@@ -778,18 +779,16 @@ void apply_ns(mfs_problem &P, int l, T *dst, const T *src, hipStream_t s) {
   MFS_REQUIRE(P.ns_ready, MFS_EINVAL, "mfs_set_linearization has not been called");
   const Level &L = P.L[l];
   const LevelGeom &g = L.g;
-  // FP32 (3D): cell-local outputs and a deterministic node gather instead of
-  // global atomics (measured at 128^3 Q2Q2: the FP32 atomics cost 45% of the
-  // Jacobian, the FP64 ones 10%, about what the cell-local arrays would cost)
-  if constexpr (sizeof(T) == 4) {
-    if (g.dim == 3 && L.ev32 != nullptr) {
-      T *ev = L.ev32;
-      launch_ns<T>(g, dev<T>(L).X, dev<T>(L).tab, 1, (T)P.nu, (T)P.ns_dt, P.ns_newton, src, dst,
-                   const_cast<T *>(ns_qd<T>(L)), s, ev);
-      const int64_t q = g.k + 1;
-      launch_node_gather<T>(g, g.k, g.k, ev, ev + g.ncells * 3 * q * q * q, dst, dst + g.dim * g.Nv, src, s);
-      return;
-    }
+  // 3D: cell-local outputs and a deterministic node gather instead of global
+  // atomics (at 128^3 Q2Q2 the FP32 atomics cost 45% of the Jacobian; with
+  // the cell-local rows laid out for the gather it pays in FP64 too)
+  if (g.dim == 3 && cellev<T>(L) != nullptr) {
+    T *ev = cellev<T>(L);
+    launch_ns<T>(g, dev<T>(L).X, dev<T>(L).tab, 1, (T)P.nu, (T)P.ns_dt, P.ns_newton, src, dst,
+                 const_cast<T *>(ns_qd<T>(L)), s, ev);
+    const int64_t q = g.k + 1;
+    launch_node_gather<T>(g, g.k, g.k, ev, ev + g.ncells * 3 * q * q * q, dst, dst + g.dim * g.Nv, src, s);
+    return;
   }
   launch_fill_dirichlet<T>(g, dst, src, s);
   vec_fill<T>(dst + g.dim * g.Nv, T(0), g.Nv, s);
