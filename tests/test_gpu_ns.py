@@ -106,8 +106,8 @@ def test_ns_jacobian_full_size_sampled(k):
     """128^3 Cartesian cells with the linearisation of the throughput
     measurement (Newton, dt = 1e-2, nu = 0.01, 8-mode Fourier field): sampled
     rows against the oracle's rows from the cells that hold them (FP64
-    1e-12), FP32 against FP64 (2e-5), and the constant pressure in the
-    kernel."""
+    1e-12, FP32 2e-5), FP32 against FP64 on every row (2e-5), and the
+    constant pressure in the kernel."""
     n, nu, dt = [128, 128, 128], 0.01, 1e-2
     X = inputs.structured_vertices(3, n)
     h = mfs.mfs_setup(3, n, X, k, nu, mfs.mfs_default_options(pressure_offset=0, mg_levels=0))
@@ -129,7 +129,10 @@ def test_ns_jacobian_full_size_sampled(k):
         assert np.abs(yh[rows] - ref).max() <= 1e-12 * scale
         y32 = torch.empty(N, dtype=torch.float32, device="cuda")
         mfs.mfs_vmult(h, mfs.MFS_OP_NS_JACOBIAN, mfs.MFS_FP32, 0, y32, cuda(dx, torch.float32))
-        assert relerr(host(y32), yh) <= 2e-5
+        y32h = host(y32)
+        assert relerr(y32h, yh) <= 2e-5
+        # and the FP32 rows against the oracle itself
+        assert np.abs(y32h[rows] - ref).max() <= 2e-5 * scale
         e = np.zeros(N)
         e[3 * Nv:] = 1.0
         mfs.mfs_vmult(h, mfs.MFS_OP_NS_JACOBIAN, mfs.MFS_FP64, 0, y, cuda(e))

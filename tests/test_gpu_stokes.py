@@ -156,6 +156,41 @@ def test_stokes_vmult_full_size_sampled(k):
         mfs.mfs_destroy(h)
 
 
+@pytest.mark.parametrize("k", [2, 3])
+def test_solve_full_size_residual_sampled(k):
+    """The 64^3 solve of the bench (FP32 multigrid inside FP64 FGMRES to
+    1e-8) checked by the oracle at full size: b = K y with y ~ U[-1, 1]
+    (b's sampled rows equal the oracle's K y rows to 1e-12), and the oracle's
+    rows of b - K x for the GPU solution x are below 1e-8 ||b||_2, the bound
+    the 2-norm residual puts on every entry."""
+    dim, n, nu = 3, [64, 64, 64], 1.0
+    X = inputs.structured_vertices(dim, n, noise=0.2, seed=0)
+    opts = mfs.mfs_default_options(rtol=1e-8, precond_precision=mfs.MFS_FP32)
+    h = mfs.mfs_setup(dim, n, X, k, nu, opts)
+    try:
+        Nv, Np = mfs.mfs_n_dofs(h, 0)
+        N = dim * Nv + Np
+        y = inputs.uniform_vector(N, 11)
+        b = torch.empty(N, dtype=torch.float64, device="cuda")
+        mfs.mfs_vmult(h, mfs.MFS_OP_STOKES, mfs.MFS_FP64, 0, b, cuda(y))
+        x = torch.zeros_like(b)
+        info = mfs.mfs_solve(h, b, x, opts)
+        assert info.status == 0 and info.rel_residual <= 1e-8
+        bh, xh = host(b), host(x)
+        S = fem.Space(dim, n, X, k)
+        rows = np.unique(np.concatenate([
+            np.random.default_rng(6).choice(N, 400, replace=False),
+            [0, dim * Nv - 1, dim * Nv, N - 1, Nv + Nv // 2, dim * Nv + Np // 2]]))
+        Ky = fem.sampled_stokes_rows(S, nu, y, rows)
+        assert np.abs(bh[rows] - Ky).max() <= 1e-12 * np.abs(Ky).max()
+        r = Ky - fem.sampled_stokes_rows(S, nu, xh, rows)
+        bnorm = np.linalg.norm(bh)
+        print(f"64^3 Q{k}: {info.iterations} iterations, max sampled residual {np.abs(r).max() / bnorm:.2e} ||b||")
+        assert np.abs(r).max() <= 1e-8 * bnorm
+    finally:
+        mfs.mfs_destroy(h)
+
+
 def test_support_and_quadrature_points():
     dim, n, k = 3, [3, 2, 4], 3
     h, X = _setup(dim, n, k, 0.2)
