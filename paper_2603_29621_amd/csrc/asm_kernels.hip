@@ -127,6 +127,8 @@ __global__ void k_probe_extract(LevelGeom g, Colour C, const double *y, double *
 constexpr int INV_T = 256;
 template <int NP>
 __global__ void __launch_bounds__(INV_T) k_invert(double *M, int *status) {
+  constexpr int RP = NP <= 64 ? 64 : 128;  // rows per column group (whole waves)
+  constexpr int CG = INV_T / RP;           // column groups
   __shared__ double a[NP * NP];
   __shared__ double fcol[NP], rrow[NP];
   __shared__ int perm[NP];
@@ -182,13 +184,18 @@ __global__ void __launch_bounds__(INV_T) k_invert(double *M, int *status) {
       rrow[e] = e == k ? ip : a[e * NP + k] * ip;       // the scaled pivot row
     }
     __syncthreads();
-    for (int e = tid; e < NP * NP; e += INV_T) {
-      const int j = e / NP, i = e % NP;
-      const double r = rrow[j];
-      if (i == k)
-        a[e] = r;
-      else
-        a[e] = (j == k ? 0.0 : a[e]) - fcol[i] * r;
+    // thread (row i, column group h): lanes run over rows, so a column's
+    // entries are consecutive words and the pivot row value is a broadcast
+    for (int t = tid; t < RP * CG; t += INV_T) {
+      const int i = t % RP, h = t / RP;
+      if (i >= NP) continue;
+      const double f = fcol[i];
+#pragma unroll 6
+      for (int j = h; j < NP; j += CG) {
+        const double r = rrow[j];
+        double &x = a[j * NP + i];
+        x = i == k ? r : (j == k ? 0.0 : x) - f * r;
+      }
     }
     __syncthreads();
   }
