@@ -517,7 +517,6 @@ def refined_ns_section(mfs, torch, inputs, args, dt, nu):
         finally:
             mfs.mfs_destroy(h)
     solve["speedup_mixed_vs_fp64"] = solve["fp64"]["solve_s"] / solve["fp32_mg_fp64_fgmres"]["solve_s"]
-    solve["relaxation"] = relaxation_compare(mfs, torch, inputs, n, k, nu, X, args)
     out["solve"] = solve
     return out
 

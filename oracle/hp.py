@@ -319,6 +319,79 @@ class HpStokes:
         self.nvel = 3 * Nu
 
 
+def sampled_stokes_rows(n, X, deg, nu, x, rows, V=None, Pspace=None):
+    """Rows ``rows`` of the constrained hp Stokes operator (the matrix of
+    ``HpStokes``) applied to x = [u_0 | u_1 | u_2 | p], each from the cells
+    whose local maps reference the row's unknown: element matrices of those
+    cells by full quadrature, C_K^T (A_K, B_K) C_K.  For sizes too large to
+    assemble; V and Pspace may be passed in (the velocity and pressure spaces)."""
+    n = [int(v) for v in n]
+    deg = np.asarray(deg, dtype=np.int64).reshape(-1)
+    V = HpSpace(n, deg) if V is None else V
+    Pspace = HpSpace(n, deg - 1) if Pspace is None else Pspace
+    Nu, Np = V.N, Pspace.N
+    nv = 3 * Nu
+    xu = np.where(np.tile(V.dirichlet, 3), 0.0, x[:nv])
+    xp = x[nv:]
+    refV, refP = V.reference_points(), Pspace.reference_points()
+    n0, n1, n2 = n
+    cache, spaces = {}, {}
+
+    def cell_data(c):
+        if c not in cache:
+            k = int(deg[c])
+            if k not in spaces:
+                spaces[k] = Space(3, n, X, k, k - 1)
+            S = spaces[k]
+            CU, CP = V.cell_rows(c), Pspace.cell_rows(c)
+            u_loc = np.stack([CU @ xu[a * Nu:(a + 1) * Nu] for a in range(3)])  # [3, nb]
+            p_loc = CP @ xp
+            # the element matrices of the cell (full quadrature, as in
+            # stokes_element_matrices) applied to its local values:
+            # A_ij = nu sum_q JxW grad phi_i . grad phi_j,
+            # B_(a i) j = - sum_q JxW psi_j d phi_i / dx_a
+            _, _, _, invJ, JxW = S.geometry(np.array([c]))
+            q1 = basis.gauss_rule(k + 1)[0]
+            _, dN, _ = basis.tensor_basis(3, k, q1)
+            Np_, _, _ = basis.tensor_basis(3, k - 1, q1)
+            G = np.einsum("qib,qba->qia", dN, invJ[0])  # physical gradients [q, i, a]
+            w = JxW[0]
+            gu = np.einsum("qja,cj->cqa", G, u_loc)  # gradients of the 3 components at the points
+            pq = Np_ @ p_loc
+            ru = np.stack([nu * np.einsum("q,qia,qa->i", w, G, gu[a]) - np.einsum("q,q,qi->i", w, pq, G[:, :, a])
+                           for a in range(3)])
+            div = gu[0, :, 0] + gu[1, :, 1] + gu[2, :, 2]
+            rp = -np.einsum("q,q,qj->j", w, div, Np_)
+            cache[c] = (CU, CP, ru, rp)
+        return cache[c]
+
+    def cells_at(pt):
+        ranges = []
+        for b in range(3):
+            f = int(np.floor(pt[b] + 1e-12))
+            cand = [f - 1, f] if abs(pt[b] - round(pt[b])) < 1e-12 else [f]
+            ranges.append([c for c in cand if 0 <= c < n[b]])
+        return [cx + n0 * (cy + n1 * cz) for cz in ranges[2] for cy in ranges[1] for cx in ranges[0]]
+
+    out = np.zeros(len(rows))
+    for t, r in enumerate(rows):
+        r = int(r)
+        if r < nv:
+            a, g = divmod(r, Nu)
+            if V.dirichlet[g]:
+                out[t] = x[r]
+                continue
+            for c in cells_at(refV[g]):
+                CU, _, ru, _ = cell_data(c)
+                out[t] += CU[:, g].toarray().ravel() @ ru[a]
+        else:
+            g = r - nv
+            for c in cells_at(refP[g]):
+                _, CP, _, rp = cell_data(c)
+                out[t] += CP[:, g].toarray().ravel() @ rp
+    return out
+
+
 def random_block_degrees(n, seed, block=4, lo=2, hi=6):
     """Per-cell degrees constant on block^3 cell blocks, uniform in [lo, hi]
     per block (input recipe of the hp workload)."""

@@ -89,8 +89,9 @@ def test_hp_operators(n, deg, noise):
 
 def test_hp_full_size_properties():
     """The 32^3 hp workload (degrees 2..6 per 4^3 block, seed 0, noise 0.1h),
-    too large for the oracle: the constant pressure in the kernel, symmetry
-    on the free rows, and FP32 against FP64."""
+    too large to assemble: sampled rows against the oracle computed cell by
+    cell (1e-12), the constant pressure in the kernel, symmetry on the free
+    rows, and FP32 against FP64."""
     n = [32, 32, 32]
     deg = inputs.block_degrees(n, seed=0, block=4, lo=2, hi=6)
     X = inputs.structured_vertices(3, n, noise=0.1, seed=0)
@@ -125,6 +126,12 @@ def test_hp_full_size_properties():
         # FP32 against FP64
         x32 = x.astype(np.float32).astype(np.float64)
         assert relerr(K(x32, prec=mfs.MFS_FP32), K(x32)) <= 1e-5
+        # sampled rows against the oracle, cell by cell (every kind of row)
+        rows = np.unique(np.concatenate([
+            np.random.default_rng(7).choice(N, 300, replace=False),
+            [0, Nu - 1, Nu, 3 * Nu - 1, nv, N - 1]]))
+        ref = hp.sampled_stokes_rows(n, X, deg, 1.0, x, rows)
+        assert np.abs(y[rows] - ref).max() <= 1e-12 * np.abs(ref).max()
     finally:
         mfs.mfs_destroy(h)
 

@@ -186,3 +186,20 @@ def test_block_degrees_recipe():
 
 def test_gll_closed_forms_used_by_the_entities():
     assert np.allclose(basis.gll_points(2), [0, 0.5, 1])
+
+
+def test_sampled_rows_equal_the_assembled_matrix():
+    """The cell-by-cell rows used for full-size checks equal the rows of the
+    assembled constrained hp Stokes matrix (every kind of row: vertex, edge,
+    face and interior unknowns, Dirichlet rows, pressure rows)."""
+    n = [3, 2, 3]
+    deg = np.array([2, 3, 4, 2, 5, 3, 2, 2, 4, 3, 3, 2, 4, 2, 3, 5, 2, 3])
+    X = inputs.structured_vertices(3, n, noise=0.15, seed=4)
+    H = hp.HpStokes(n, X, deg, 0.9)
+    N = H.K.shape[0]
+    x = inputs.uniform_vector(N, 5)
+    rows = np.unique(np.concatenate([np.random.default_rng(2).choice(N, 150, replace=False),
+                                     [0, H.Nu, 3 * H.Nu - 1, 3 * H.Nu, N - 1]]))
+    got = hp.sampled_stokes_rows(n, X, deg, 0.9, x, rows)
+    ref = H.K @ x
+    assert np.abs(got - ref[rows]).max() <= 1e-12 * np.abs(ref).max()
