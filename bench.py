@@ -50,6 +50,25 @@ def algorithmic_bytes(dim, n, k, word):
     return N, 2 * N * word + verts
 
 
+def stream_copy_bandwidth(torch, nbytes=1 << 30, reps=10):
+    """Achievable HBM bandwidth: a device-to-device copy of 1 GiB (read + write
+    bytes over the event time, best of the repetitions)."""
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) * 1e-3)
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / best
+
+
 def progress(msg):
     """One line per finished step on stderr (stdout carries only the JSON line)."""
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
@@ -822,6 +841,7 @@ def main():
 
     main_prec = mfs.MFS_FP64 if args.prec == "f64" else mfs.MFS_FP32
     main_run = run(k, main_prec, args.steps, args.warmup)
+    copy_bw = stream_copy_bandwidth(torch)
     progress(f"headline vmult: {main_run['avg_launch_s'] * 1e6:.1f} us")
     sweep = {}
     if not args.no_sweep:
@@ -853,7 +873,9 @@ def main():
                    "n_dofs": main_run["N"], "rotating_buffers_bytes": 600e6},
         "roofline": {"bound": "hbm", "achieved": main_run["achieved_GBs"], "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                      "frac": main_run["frac"], "traffic": MEASURED_TRAFFIC.get((k, n, args.prec)),
-                     "bytes_per_launch": main_run["bytes"], "avg_launch_us": main_run["avg_launch_s"] * 1e6},
+                     "bytes_per_launch": main_run["bytes"], "avg_launch_us": main_run["avg_launch_s"] * 1e6,
+                     "stream_copy_GBs": copy_bw / 1e9, "frac_of_stream_copy": main_run["bytes"] /
+                     main_run["avg_launch_s"] / copy_bw},
         "sweep": sweep,
     }
     if not args.no_sweep:
