@@ -779,7 +779,7 @@ void launch_cell_op_gather(const LevelGeom &g, const DevLevel<T> &d, int mode, T
   a.ev_u = ev;
   const int64_t q = g.k + 1;
   a.ev_p = ev + g.ncells * 3 * q * q * q;
-  dispatch_k<3, T>(a, g.k, g.kp, mode, s);
+  if (!launch_column_cells<T>(g, d.X, mode, nu, src_u, src_p, a.ev_u, a.ev_p, s)) dispatch_k<3, T>(a, g.k, g.kp, mode, s);
   const bool out_u = mode & (M_LAPLACE | M_GRADP | M_MASSU), out_p = mode & (M_DIVU | M_MASSP);
   const int64_t n = std::max<int64_t>(out_u ? g.Nv : 0, out_p ? g.Np : 0);
   if (n > 0)

@@ -1,0 +1,566 @@
+// 3D Taylor-Hood Stokes cell kernel for degrees k >= 3 with one thread per
+// column of quadrature points.
+//
+// Weak form: Sec. 1 eq. (stokes) in the symmetric block form of Sec. 3
+// eq. (stokes_block): velocity rows nu (grad u, grad v) - (p, div v),
+// pressure rows -(div u, q); Gauss quadrature with k+1 points per direction,
+// velocity on the GLL nodes of degree k, pressure on those of degree k-1.
+//
+// Work decomposition
+//  * Thread (cell, i, j), i, j < k+1: one column of points (or nodes) along
+//    z.  Cells with (k+1)^2 <= 64 threads are packed per wavefront and their
+//    sweeps synchronise at wavefront scope.
+//  * Sum factorisation: the x and y contractions go through LDS (a thread
+//    reads one row of k+1 values per output); the z contraction of a column
+//    stays in registers.  Values, x- and y-derivatives come straight from the
+//    nodal values (basis S, derivative DS at the Gauss points).
+//  * Geometry once per point for all three velocity components: along a
+//    column the z-column of the trilinear Jacobian is constant and the other
+//    two are linear in z.
+//  * The transposed sequence integrates; every thread writes its column of
+//    nodal results into the cell-local arrays (cell_slot layout) that the
+//    node gather sums in a fixed order (deterministic, no atomics).
+#include "internal.h"
+
+namespace mfs {
+namespace col {
+
+// ---- compile-time 1D tables on [0, 1]
+constexpr double csqrt(double v) {
+  double r = v > 1 ? v : 1.0;
+  for (int i = 0; i < 80; ++i) r = 0.5 * (r + v / r);
+  return r;
+}
+
+template <int K>
+struct Tab1 {
+  static constexpr int Q = K + 1, M = K;
+  double x[Q], w[Q];         // Gauss points and weights
+  double S[Q][Q], DS[Q][Q];  // velocity basis (GLL nodes of degree K) and its derivative at the points
+  double Sp[Q][M];           // pressure basis (GLL nodes of degree K-1) at the points
+  constexpr Tab1() : x{}, w{}, S{}, DS{}, Sp{} {
+    // Gauss-Legendre rules on [-1, 1] in closed form
+    double gx[Q] = {}, gw[Q] = {};
+    if constexpr (Q == 4) {
+      const double a = csqrt(3.0 / 7.0 - 2.0 / 7.0 * csqrt(6.0 / 5.0));
+      const double b = csqrt(3.0 / 7.0 + 2.0 / 7.0 * csqrt(6.0 / 5.0));
+      const double wa = (18.0 + csqrt(30.0)) / 36.0, wb = (18.0 - csqrt(30.0)) / 36.0;
+      gx[0] = -b, gx[1] = -a, gx[2] = a, gx[3] = b;
+      gw[0] = wb, gw[1] = wa, gw[2] = wa, gw[3] = wb;
+    } else {
+      const double a = csqrt(5.0 - 2.0 * csqrt(10.0 / 7.0)) / 3.0;
+      const double b = csqrt(5.0 + 2.0 * csqrt(10.0 / 7.0)) / 3.0;
+      const double wa = (322.0 + 13.0 * csqrt(70.0)) / 900.0, wb = (322.0 - 13.0 * csqrt(70.0)) / 900.0;
+      gx[0] = -b, gx[1] = -a, gx[2] = 0.0, gx[3] = a, gx[4] = b;
+      gw[0] = wb, gw[1] = wa, gw[2] = 128.0 / 225.0, gw[3] = wa, gw[4] = wb;
+    }
+    for (int q = 0; q < Q; ++q) {
+      x[q] = 0.5 * (gx[q] + 1.0);
+      w[q] = 0.5 * gw[q];
+    }
+    // GLL nodes on [0, 1]: degree 3 {0, (1 -+ 1/sqrt 5)/2, 1}, degree 4 {0, (1 -+ sqrt(3/7))/2, 1/2, 1},
+    // degree 2 {0, 1/2, 1}
+    double nv[Q] = {}, np[M] = {};
+    auto gll = [](int deg, double *out) {
+      out[0] = 0.0;
+      out[deg] = 1.0;
+      if (deg == 2) out[1] = 0.5;
+      if (deg == 3) {
+        const double r = 1.0 / csqrt(5.0);
+        out[1] = 0.5 * (1.0 - r);
+        out[2] = 0.5 * (1.0 + r);
+      }
+      if (deg == 4) {
+        const double r = csqrt(3.0 / 7.0);
+        out[1] = 0.5 * (1.0 - r);
+        out[2] = 0.5;
+        out[3] = 0.5 * (1.0 + r);
+      }
+    };
+    gll(K, nv);
+    gll(K - 1, np);
+    for (int q = 0; q < Q; ++q) {
+      for (int n = 0; n < Q; ++n) {
+        double v = 1.0, d = 0.0;
+        for (int l = 0; l < Q; ++l) {
+          if (l == n) continue;
+          double term = 1.0 / (nv[n] - nv[l]);
+          for (int m = 0; m < Q; ++m)
+            if (m != n && m != l) term *= (x[q] - nv[m]) / (nv[n] - nv[m]);
+          d += term;
+          v *= (x[q] - nv[l]) / (nv[n] - nv[l]);
+        }
+        S[q][n] = v;
+        DS[q][n] = d;
+      }
+      for (int m = 0; m < M; ++m) {
+        double v = 1.0;
+        for (int l = 0; l < M; ++l)
+          if (l != m) v *= (x[q] - np[l]) / (np[m] - np[l]);
+        Sp[q][m] = v;
+      }
+    }
+  }
+};
+
+template <int K>
+struct C {
+  static constexpr Tab1<K> t{};
+};
+
+template <typename T>
+struct Args {
+  int n0, n1, n2, ncells;
+  int nv0, nv1, nv2, np0, np1;
+  int64_t Nv;
+  const T *X, *src_u, *src_p;
+  T *ev_u, *ev_p;
+  T nu;
+};
+
+__device__ __forceinline__ void wsync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// 1/d: hardware reciprocal refined by Newton steps
+__device__ __forceinline__ double recip(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = __builtin_fma(-d, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-d, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+__device__ __forceinline__ float recip(float d) {
+  float r = __builtin_amdgcn_rcpf(d);
+  float e = __builtin_fmaf(-d, r, 1.0f);
+  return __builtin_fmaf(r, e, r);
+}
+
+// Materialise a value in a register here: without it the compiler sinks a
+// sweep's arithmetic to the distant use and keeps the loaded LDS operands
+// live instead of the one result
+template <typename T>
+__device__ __forceinline__ void pin(T &v) {
+  asm volatile("" : "+v"(v));
+}
+
+// LDS table layout (per-lane rows and columns are read from here)
+constexpr int LT_S = 0, LT_DS = 64, LT_SP = 128, LT_X = 192, LT_W = 200, LT_SIZE = 208;  // [q * 8 + n]
+
+// occupancy target (waves per SIMD): FP64 3 (<= 168 registers), FP32 4
+template <typename T>
+constexpr int waves_target() {
+  return sizeof(T) == 8 ? 3 : 4;
+}
+
+template <int K, typename T, int MODE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_target<T>()))) column_kernel(Args<T> a) {
+  constexpr int Q = K + 1, M = K, Q2 = Q * Q, Q3 = Q2 * Q;
+  constexpr int CPW = 64 / Q2, CPB = 4 * CPW;
+  constexpr bool LAP = (MODE & M_LAPLACE) != 0, GRADP = (MODE & M_GRADP) != 0, DIVU = (MODE & M_DIVU) != 0;
+  constexpr bool NEED_U = LAP || DIVU, OUT_U = LAP || GRADP;
+  constexpr const Tab1<K> &TB = C<K>::t;
+  static_assert(Q2 <= 64, "a cell's columns fit in one wavefront");
+  __shared__ T s_tab[LT_SIZE];
+  __shared__ T s_u[CPB][3 * Q3];  // nodal velocity; later the z-integrated test coefficients
+  __shared__ T s_w[CPB][2 * Q3];  // results of an x or y sweep
+  __shared__ T s_p[CPB][M * Q2];  // nodal pressure; later pressure sweep results
+  __shared__ T s_X[CPB][24];      // vertices
+
+  const int tid = threadIdx.x;
+  for (int i = tid; i < LT_SIZE; i += 256) {
+    const int blk = i >> 6, r = (i >> 3) & 7, cc = i & 7;
+    T v = 0;
+    if (blk == 0 && r < Q && cc < Q) v = (T)TB.S[r][cc];
+    if (blk == 1 && r < Q && cc < Q) v = (T)TB.DS[r][cc];
+    if (blk == 2 && r < Q && cc < M) v = (T)TB.Sp[r][cc];
+    if (i >= LT_X && i < LT_X + Q) v = (T)TB.x[i - LT_X];
+    if (i >= LT_W && i < LT_W + Q) v = (T)TB.w[i - LT_W];
+    s_tab[i] = v;
+  }
+  const int wv = tid >> 6, ln = tid & 63, sl = ln / Q2;
+  const bool active = sl < CPW;
+  const int e = wv * CPW + (active ? sl : 0);
+  const int t = active ? ln - sl * Q2 : 0;
+  const int ti = t % Q, tj = t / Q;
+  const int lin = blockIdx.x * CPB + e;
+  const bool valid = active && lin < a.ncells;
+  int cx = 0, cy = 0, cz = 0;
+  if (valid) {
+    cx = lin % a.n0;
+    const int r = lin / a.n0;
+    cy = r % a.n1;
+    cz = r / a.n1;
+  }
+
+  // ---- load: this thread's velocity column (zero on Dirichlet nodes),
+  // pressure column, and a share of the cell's vertices
+  const int gx = cx * K + ti, gy = cy * K + tj;
+  const bool xy_dir = gx == 0 || gy == 0 || gx == a.nv0 - 1 || gy == a.nv1 - 1;
+  const int64_t xy_off = gx + (int64_t)a.nv0 * gy, zstride = (int64_t)a.nv0 * a.nv1;
+  T uv[3][Q];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int l = 0; l < Q; ++l) {
+      const int gz = cz * K + l;
+      T v = 0;
+      if (NEED_U && valid && !xy_dir && gz > 0 && gz < a.nv2 - 1) v = a.src_u[c * a.Nv + zstride * gz + xy_off];
+      uv[c][l] = v;
+    }
+  const bool pcol = ti < M && tj < M;
+  T pv[M];
+#pragma unroll
+  for (int l = 0; l < M; ++l) {
+    T v = 0;
+    if (GRADP && valid && pcol)
+      v = a.src_p[(cx * (K - 1) + ti) + (int64_t)a.np0 * ((cy * (K - 1) + tj) + (int64_t)a.np1 * (cz * (K - 1) + l))];
+    pv[l] = v;
+  }
+  if (valid)
+    for (int idx = t; idx < 24; idx += Q2) {
+      const int v = idx / 3, comp = idx % 3;
+      const int64_t vid = (cx + (v & 1)) + (int64_t)(a.n0 + 1) * ((cy + ((v >> 1) & 1)) + (int64_t)(a.n1 + 1) * (cz + (v >> 2)));
+      s_X[e][idx] = a.X[3 * vid + comp];
+    }
+  if (active) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int l = 0; l < Q; ++l) s_u[e][c * Q3 + l * Q2 + tj * Q + ti] = uv[c][l];
+    if (GRADP && pcol)
+#pragma unroll
+      for (int l = 0; l < M; ++l) s_p[e][l * M * M + tj * M + ti] = pv[l];
+  }
+  __syncthreads();
+
+  // per-lane 1D coefficients: rows (value / derivative at this thread's point
+  // i or j) and columns (the basis function of node i or j at every point)
+  const T *tS = s_tab + LT_S, *tD = s_tab + LT_DS, *tP = s_tab + LT_SP;
+
+  // ---- forward: reference gradients of the 3 components along the column
+  T g[3][3][Q];
+  if (NEED_U) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      asm volatile("" ::: "memory");
+      const T *uc = &s_u[e][c * Q3];
+      T *wa = &s_w[e][0], *wb = &s_w[e][Q3];
+      // x: values and x-derivatives at point i of node row (j, l)
+#pragma unroll
+      for (int l = 0; l < Q; ++l) {
+        T s0 = 0, s1 = 0;
+#pragma unroll
+        for (int n = 0; n < Q; ++n) {
+          const T u = uc[l * Q2 + tj * Q + n];
+          s0 += tS[ti * 8 + n] * u;
+          s1 += tD[ti * 8 + n] * u;
+        }
+        if (active) {
+          wa[l * Q2 + tj * Q + ti] = s0;
+          wb[l * Q2 + tj * Q + ti] = s1;
+        }
+      }
+      wsync();
+      // y: at point (i, j) of node layer l: value, x-derivative, y-derivative
+      T V[Q], Dx[Q], Dy[Q];
+#pragma unroll
+      for (int l = 0; l < Q; ++l) {
+        T v = 0, dx = 0, dy = 0;
+#pragma unroll
+        for (int m = 0; m < Q; ++m) {
+          const T ta = wa[l * Q2 + m * Q + ti], tb = wb[l * Q2 + m * Q + ti];
+          const T sy = tS[tj * 8 + m];
+          v += sy * ta;
+          dx += sy * tb;
+          dy += tD[tj * 8 + m] * ta;
+        }
+        V[l] = v;
+        Dx[l] = dx;
+        Dy[l] = dy;
+        pin(V[l]);
+        pin(Dx[l]);
+        pin(Dy[l]);
+      }
+      wsync();
+      // z in registers
+#pragma unroll
+      for (int qz = 0; qz < Q; ++qz) {
+        T a0 = 0, a1 = 0, a2 = 0;
+#pragma unroll
+        for (int l = 0; l < Q; ++l) {
+          const T sz = tS[qz * 8 + l];
+          a0 += sz * Dx[l];
+          a1 += sz * Dy[l];
+          a2 += tD[qz * 8 + l] * V[l];
+        }
+        g[c][0][qz] = a0;
+        g[c][1][qz] = a1;
+        g[c][2][qz] = a2;
+        pin(g[c][0][qz]);
+        pin(g[c][1][qz]);
+        pin(g[c][2][qz]);
+      }
+    }
+  }
+  // pressure values along the column
+  T pq[Q];
+  if (GRADP) {
+    // x: thread (i, j < M): point i of pressure node row (j, l)
+    T *pw = &s_w[e][0];
+    if (active && tj < M)
+#pragma unroll
+      for (int l = 0; l < M; ++l) {
+        T s0 = 0;
+#pragma unroll
+        for (int m = 0; m < M; ++m) s0 += tP[ti * 8 + m] * s_p[e][l * M * M + tj * M + m];
+        pw[l * Q * M + tj * Q + ti] = s0;
+      }
+    wsync();
+    T PV[M];
+#pragma unroll
+    for (int l = 0; l < M; ++l) {
+      T s0 = 0;
+#pragma unroll
+      for (int m = 0; m < M; ++m) s0 += tP[tj * 8 + m] * pw[l * Q * M + m * Q + ti];
+      PV[l] = s0;
+      pin(PV[l]);
+    }
+    wsync();
+#pragma unroll
+    for (int qz = 0; qz < Q; ++qz) {
+      T s0 = 0;
+#pragma unroll
+      for (int l = 0; l < M; ++l) s0 += tP[qz * 8 + l] * PV[l];
+      pq[qz] = s0;
+      pin(pq[qz]);
+    }
+  }
+
+  // ---- points of the column: geometry once for all components
+  T qv[Q];
+  {
+    const T x0 = s_tab[LT_X + ti], x1 = s_tab[LT_X + tj];
+    const T wij = s_tab[LT_W + ti] * s_tab[LT_W + tj];
+    auto V = [&](int vx, int vy, int vz, int comp) -> T { return s_X[e][3 * (vx + 2 * vy + 4 * vz) + comp]; };
+    // d x / d xi0 = a0 + xi2 da (at xi1), d x / d xi1 = b0 + xi2 db (at xi0),
+    // d x / d xi2 = J2 (bilinear in xi0, xi1, constant along the column)
+    T a0[3], da[3], b0[3], db[3], J2[3];
+#pragma unroll
+    for (int comp = 0; comp < 3; ++comp) {
+      const T e00 = (T(1) - x1) * (V(1, 0, 0, comp) - V(0, 0, 0, comp)) + x1 * (V(1, 1, 0, comp) - V(0, 1, 0, comp));
+      const T e01 = (T(1) - x1) * (V(1, 0, 1, comp) - V(0, 0, 1, comp)) + x1 * (V(1, 1, 1, comp) - V(0, 1, 1, comp));
+      a0[comp] = e00;
+      da[comp] = e01 - e00;
+      const T f00 = (T(1) - x0) * (V(0, 1, 0, comp) - V(0, 0, 0, comp)) + x0 * (V(1, 1, 0, comp) - V(1, 0, 0, comp));
+      const T f01 = (T(1) - x0) * (V(0, 1, 1, comp) - V(0, 0, 1, comp)) + x0 * (V(1, 1, 1, comp) - V(1, 0, 1, comp));
+      b0[comp] = f00;
+      db[comp] = f01 - f00;
+      const T lo = (T(1) - x0) * (V(0, 0, 1, comp) - V(0, 0, 0, comp)) + x0 * (V(1, 0, 1, comp) - V(1, 0, 0, comp));
+      const T hi = (T(1) - x0) * (V(0, 1, 1, comp) - V(0, 1, 0, comp)) + x0 * (V(1, 1, 1, comp) - V(1, 1, 0, comp));
+      J2[comp] = lo + x1 * (hi - lo);
+    }
+#pragma unroll
+    for (int qz = 0; qz < Q; ++qz) {
+      asm volatile("" ::: "memory");
+      const T x2 = s_tab[LT_X + qz];
+      T J0[3], J1[3];
+#pragma unroll
+      for (int comp = 0; comp < 3; ++comp) {
+        J0[comp] = a0[comp] + x2 * da[comp];
+        J1[comp] = b0[comp] + x2 * db[comp];
+      }
+      // rows of adj(J) = det J * J^{-1}: J1 x J2, J2 x J0, J0 x J1
+      T A[3][3];
+      A[0][0] = J1[1] * J2[2] - J1[2] * J2[1];
+      A[0][1] = J1[2] * J2[0] - J1[0] * J2[2];
+      A[0][2] = J1[0] * J2[1] - J1[1] * J2[0];
+      A[1][0] = J2[1] * J0[2] - J2[2] * J0[1];
+      A[1][1] = J2[2] * J0[0] - J2[0] * J0[2];
+      A[1][2] = J2[0] * J0[1] - J2[1] * J0[0];
+      A[2][0] = J0[1] * J1[2] - J0[2] * J1[1];
+      A[2][1] = J0[2] * J1[0] - J0[0] * J1[2];
+      A[2][2] = J0[0] * J1[1] - J0[1] * J1[0];
+      const T det = J0[0] * A[0][0] + J0[1] * A[0][1] + J0[2] * A[0][2];
+      const T w = wij * s_tab[LT_W + qz];
+      const T wnd = w * a.nu * recip(det);
+      T div = 0;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        // z = adj^T ghat = det * physical gradient of component c
+        T z[3] = {0, 0, 0};
+        if (NEED_U) {
+#pragma unroll
+          for (int x = 0; x < 3; ++x) z[x] = A[0][x] * g[c][0][qz] + A[1][x] * g[c][1][qz] + A[2][x] * g[c][2][qz];
+          div += z[c];
+        }
+        if (OUT_U) {
+          T v[3];
+#pragma unroll
+          for (int x = 0; x < 3; ++x) v[x] = LAP ? wnd * z[x] : T(0);
+          if (GRADP) v[c] -= w * pq[qz];
+          // test-gradient coefficients adj * v
+#pragma unroll
+          for (int b = 0; b < 3; ++b) {
+            g[c][b][qz] = A[b][0] * v[0] + A[b][1] * v[1] + A[b][2] * v[2];
+            pin(g[c][b][qz]);
+          }
+        }
+      }
+      qv[qz] = -w * div;
+      pin(qv[qz]);
+    }
+  }
+
+  // ---- backward: integrate against the test functions, column by column
+  const int64_t row0 = cell_slot(a.n0, a.n1, 3, Q, cx, cy, cz, 0, ti, tj, 0);
+  const int64_t cstride = cell_slot(a.n0, a.n1, 3, Q, cx, cy, cz, 1, ti, tj, 0) - row0;
+  const int64_t lstride = cell_slot(a.n0, a.n1, 3, Q, cx, cy, cz, 0, ti, tj, 1) - row0;
+  if (OUT_U) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      asm volatile("" ::: "memory");
+      // z: test coefficients of x-derivative (S), y-derivative (S) and
+      // z-derivative (DS) tests at node layer l
+      T *z0 = &s_u[e][0], *z1 = &s_u[e][Q3], *z2 = &s_u[e][2 * Q3];
+#pragma unroll
+      for (int l = 0; l < Q; ++l) {
+        T s0 = 0, s1 = 0, s2 = 0;
+#pragma unroll
+        for (int qz = 0; qz < Q; ++qz) {
+          const T sz = tS[qz * 8 + l];
+          s0 += sz * g[c][0][qz];
+          s1 += sz * g[c][1][qz];
+          s2 += tD[qz * 8 + l] * g[c][2][qz];
+        }
+        if (active) {
+          z0[l * Q2 + tj * Q + ti] = s0;
+          z1[l * Q2 + tj * Q + ti] = s1;
+          z2[l * Q2 + tj * Q + ti] = s2;
+        }
+      }
+      wsync();
+      // y transposed: thread (i, j) = (point i, node j)
+      T *wx = &s_w[e][0], *ws = &s_w[e][Q3];
+      T rx[Q], rs[Q];
+#pragma unroll
+      for (int l = 0; l < Q; ++l) {
+        T s0 = 0, s1 = 0;
+#pragma unroll
+        for (int qy = 0; qy < Q; ++qy) {
+          const T sy = tS[qy * 8 + tj], dy = tD[qy * 8 + tj];
+          s0 += sy * z0[l * Q2 + qy * Q + ti];
+          s1 += dy * z1[l * Q2 + qy * Q + ti] + sy * z2[l * Q2 + qy * Q + ti];
+        }
+        rx[l] = s0;
+        rs[l] = s1;
+        pin(rx[l]);
+        pin(rs[l]);
+      }
+      if (active)
+#pragma unroll
+        for (int l = 0; l < Q; ++l) {
+          wx[l * Q2 + tj * Q + ti] = rx[l];
+          ws[l * Q2 + tj * Q + ti] = rs[l];
+        }
+      wsync();
+      // x transposed: thread (i, j) = node (i, j)
+#pragma unroll
+      for (int l = 0; l < Q; ++l) {
+        T r = 0;
+#pragma unroll
+        for (int qx = 0; qx < Q; ++qx)
+          r += tD[qx * 8 + ti] * wx[l * Q2 + tj * Q + qx] + tS[qx * 8 + ti] * ws[l * Q2 + tj * Q + qx];
+        if (valid) a.ev_u[row0 + c * cstride + l * lstride] = r;
+      }
+      wsync();
+    }
+  }
+  if (DIVU) {
+    // pressure tests: z in registers, then y and x through LDS
+    T *pz = &s_w[e][0], *py = &s_p[e][0];
+    if (active)
+#pragma unroll
+      for (int l = 0; l < M; ++l) {
+        T s0 = 0;
+#pragma unroll
+        for (int qz = 0; qz < Q; ++qz) s0 += tP[qz * 8 + l] * qv[qz];
+        pz[l * Q2 + tj * Q + ti] = s0;
+      }
+    wsync();
+    if (active && tj < M)
+#pragma unroll
+      for (int l = 0; l < M; ++l) {
+        T s0 = 0;
+#pragma unroll
+        for (int qy = 0; qy < Q; ++qy) s0 += tP[qy * 8 + tj] * pz[l * Q2 + qy * Q + ti];
+        py[l * Q * M + tj * Q + ti] = s0;
+      }
+    wsync();
+    if (valid && pcol) {
+      const int64_t p0 = cell_slot(a.n0, a.n1, 1, M, cx, cy, cz, 0, ti, tj, 0);
+      const int64_t pl = cell_slot(a.n0, a.n1, 1, M, cx, cy, cz, 0, ti, tj, 1) - p0;
+#pragma unroll
+      for (int l = 0; l < M; ++l) {
+        T s0 = 0;
+#pragma unroll
+        for (int qx = 0; qx < Q; ++qx) s0 += tP[qx * 8 + ti] * py[l * Q * M + tj * Q + qx];
+        a.ev_p[p0 + l * pl] = s0;
+      }
+    }
+  }
+}
+
+template <int K, typename T, int MODE>
+static void go(const Args<T> &a, hipStream_t s) {
+  constexpr int CPB = 4 * (64 / ((K + 1) * (K + 1)));
+  const int grid = (a.ncells + CPB - 1) / CPB;
+  hipLaunchKernelGGL((column_kernel<K, T, MODE>), dim3(grid), dim3(256), 0, s, a);
+}
+
+template <int K, typename T>
+static bool go_mode(const Args<T> &a, int mode, hipStream_t s) {
+  switch (mode) {
+    case M_LAPLACE | M_GRADP | M_DIVU: go<K, T, M_LAPLACE | M_GRADP | M_DIVU>(a, s); return true;
+    case M_LAPLACE: go<K, T, M_LAPLACE>(a, s); return true;
+    case M_GRADP: go<K, T, M_GRADP>(a, s); return true;
+    case M_DIVU: go<K, T, M_DIVU>(a, s); return true;
+    default: return false;
+  }
+}
+
+}  // namespace col
+
+template <typename T>
+bool launch_column_cells(const LevelGeom &g, const T *X, int mode, T nu, const T *src_u, const T *src_p, T *ev_u,
+                         T *ev_p, hipStream_t s) {
+  if (g.dim != 3 || (g.k != 3 && g.k != 4) || g.kp != g.k - 1 || g.ncells == 0) return false;
+  col::Args<T> a{};
+  a.n0 = g.n[0];
+  a.n1 = g.n[1];
+  a.n2 = g.n[2];
+  a.ncells = (int)g.ncells;
+  a.nv0 = g.nv[0];
+  a.nv1 = g.nv[1];
+  a.nv2 = g.nv[2];
+  a.np0 = g.np[0];
+  a.np1 = g.np[1];
+  a.Nv = g.Nv;
+  a.X = X;
+  a.src_u = src_u;
+  a.src_p = src_p;
+  a.ev_u = ev_u;
+  a.ev_p = ev_p;
+  a.nu = nu;
+  const bool ok = g.k == 3 ? col::go_mode<3, T>(a, mode, s) : col::go_mode<4, T>(a, mode, s);
+  if (ok) MFS_HIP(hipGetLastError());
+  return ok;
+}
+template bool launch_column_cells<double>(const LevelGeom &, const double *, int, double, const double *,
+                                          const double *, double *, double *, hipStream_t);
+template bool launch_column_cells<float>(const LevelGeom &, const float *, int, float, const float *, const float *,
+                                         float *, float *, hipStream_t);
+
+}  // namespace mfs
