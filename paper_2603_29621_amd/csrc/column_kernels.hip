@@ -163,11 +163,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_
   constexpr bool NEED_U = LAP || DIVU, OUT_U = LAP || GRADP;
   constexpr const Tab1<K> &TB = C<K>::t;
   static_assert(Q2 <= 64, "a cell's columns fit in one wavefront");
+  // per-cell arrays padded by one word, so that the cells of a wavefront
+  // start on different LDS banks
   __shared__ T s_tab[LT_SIZE];
-  __shared__ T s_u[CPB][3 * Q3];  // nodal velocity; later the z-integrated test coefficients
-  __shared__ T s_w[CPB][2 * Q3];  // results of an x or y sweep
-  __shared__ T s_p[CPB][M * Q2];  // nodal pressure; later pressure sweep results
-  __shared__ T s_X[CPB][24];      // vertices
+  __shared__ T s_u[CPB][3 * Q3 + 1];  // nodal velocity; later the z-integrated test coefficients
+  __shared__ T s_w[CPB][2 * Q3 + 1];  // results of an x or y sweep
+  __shared__ T s_p[CPB][M * Q2 + 1];  // nodal pressure; later pressure sweep results
+  __shared__ T s_X[CPB][24];          // vertices
 
   const int tid = threadIdx.x;
   for (int i = tid; i < LT_SIZE; i += 256) {
