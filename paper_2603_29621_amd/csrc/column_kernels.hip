@@ -149,6 +149,20 @@ __device__ __forceinline__ void pin(T &v) {
 // LDS table layout (per-lane rows and columns are read from here)
 constexpr int LT_S = 0, LT_DS = 64, LT_SP = 128, LT_X = 192, LT_W = 200, LT_SIZE = 208;  // [q * 8 + n]
 
+// Per-cell LDS stride for n elements of T.  FP32: the smallest stride >= n
+// that is 8 words past a multiple of 32 words, so that the (cell, j, i)
+// stores and the (cell, i) row reads of a sweep spread evenly over the banks
+// (k = 3 cell kernel 323 -> 281 us at 64^3).  FP64: one element of padding,
+// which measured fewer conflicts for the 64-bit accesses than the FP32 rule
+// (k = 4: 71 M against 155 M conflict cycles per dispatch).
+template <typename T>
+constexpr int pad_stride(int n) {
+  if (sizeof(T) == 8) return n + 1;
+  int s = n;
+  while (s % 32 != 8) ++s;
+  return s;
+}
+
 // occupancy target (waves per SIMD): FP64 3 (<= 168 registers), FP32 4
 template <typename T>
 constexpr int waves_target() {
@@ -163,13 +177,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_
   constexpr bool NEED_U = LAP || DIVU, OUT_U = LAP || GRADP;
   constexpr const Tab1<K> &TB = C<K>::t;
   static_assert(Q2 <= 64, "a cell's columns fit in one wavefront");
-  // per-cell arrays padded by one word, so that the cells of a wavefront
-  // start on different LDS banks
+  // per-cell arrays padded so that the cells of a wavefront start on
+  // different LDS banks
+  constexpr int SU = pad_stride<T>(3 * Q3), SW = pad_stride<T>(2 * Q3), SP = pad_stride<T>(M * Q2);
   __shared__ T s_tab[LT_SIZE];
-  __shared__ T s_u[CPB][3 * Q3 + 1];  // nodal velocity; later the z-integrated test coefficients
-  __shared__ T s_w[CPB][2 * Q3 + 1];  // results of an x or y sweep
-  __shared__ T s_p[CPB][M * Q2 + 1];  // nodal pressure; later pressure sweep results
-  __shared__ T s_X[CPB][24];          // vertices
+  __shared__ T s_u[CPB][SU];  // nodal velocity; later the z-integrated test coefficients
+  __shared__ T s_w[CPB][SW];  // results of an x or y sweep
+  __shared__ T s_p[CPB][SP];  // nodal pressure; later pressure sweep results
+  __shared__ T s_X[CPB][24];  // vertices
 
   const int tid = threadIdx.x;
   for (int i = tid; i < LT_SIZE; i += 256) {
