@@ -174,12 +174,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_
   constexpr int Q = K + 1, M = K, Q2 = Q * Q, Q3 = Q2 * Q;
   constexpr int CPW = 64 / Q2, CPB = 4 * CPW;
   constexpr bool LAP = (MODE & M_LAPLACE) != 0, GRADP = (MODE & M_GRADP) != 0, DIVU = (MODE & M_DIVU) != 0;
-  constexpr bool NEED_U = LAP || DIVU, OUT_U = LAP || GRADP;
+  constexpr bool MASSP = (MODE & M_MASSP) != 0;
+  constexpr bool NEED_U = LAP || DIVU, OUT_U = LAP || GRADP, NEED_P = GRADP || MASSP, OUT_P = DIVU || MASSP;
   constexpr const Tab1<K> &TB = C<K>::t;
   static_assert(Q2 <= 64, "a cell's columns fit in one wavefront");
   // per-cell arrays padded so that the cells of a wavefront start on
   // different LDS banks
-  constexpr int SU = pad_stride<T>(3 * Q3), SW = pad_stride<T>(2 * Q3), SP = pad_stride<T>(M * Q2);
+  // (the pressure mass alone needs no velocity arrays and pressure-sized sweep results)
+  constexpr bool VEL = NEED_U || OUT_U;
+  constexpr int SU = pad_stride<T>(VEL ? 3 * Q3 : 1), SW = pad_stride<T>(VEL ? 2 * Q3 : M * Q2),
+                SP = pad_stride<T>(M * Q2);
   __shared__ T s_tab[LT_SIZE];
   __shared__ T s_u[CPB][SU];  // nodal velocity; later the z-integrated test coefficients
   __shared__ T s_w[CPB][SW];  // results of an x or y sweep
@@ -232,7 +236,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_
 #pragma unroll
   for (int l = 0; l < M; ++l) {
     T v = 0;
-    if (GRADP && valid && pcol)
+    if (NEED_P && valid && pcol)
       v = a.src_p[(cx * (K - 1) + ti) + (int64_t)a.np0 * ((cy * (K - 1) + tj) + (int64_t)a.np1 * (cz * (K - 1) + l))];
     pv[l] = v;
   }
@@ -247,7 +251,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_
     for (int c = 0; c < 3; ++c)
 #pragma unroll
       for (int l = 0; l < Q; ++l) s_u[e][c * Q3 + l * Q2 + tj * Q + ti] = uv[c][l];
-    if (GRADP && pcol)
+    if (NEED_P && pcol)
 #pragma unroll
       for (int l = 0; l < M; ++l) s_p[e][l * M * M + tj * M + ti] = pv[l];
   }
@@ -324,7 +328,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_
   }
   // pressure values along the column
   T pq[Q];
-  if (GRADP) {
+  if (NEED_P) {
     // x: thread (i, j < M): point i of pressure node row (j, l)
     T *pw = &s_w[e][0];
     if (active && tj < M)
@@ -426,7 +430,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_
           }
         }
       }
-      qv[qz] = -w * div;
+      qv[qz] = (DIVU ? -w * div : T(0)) + (MASSP ? w * det * pq[qz] : T(0));
       pin(qv[qz]);
     }
   }
@@ -495,7 +499,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_
       wsync();
     }
   }
-  if (DIVU) {
+  if (OUT_P) {
     // pressure tests: z in registers, then y and x through LDS
     T *pz = &s_w[e][0], *py = &s_p[e][0];
     if (active)
@@ -544,6 +548,7 @@ static bool go_mode(const Args<T> &a, int mode, hipStream_t s) {
     case M_LAPLACE: go<K, T, M_LAPLACE>(a, s); return true;
     case M_GRADP: go<K, T, M_GRADP>(a, s); return true;
     case M_DIVU: go<K, T, M_DIVU>(a, s); return true;
+    case M_MASSP: go<K, T, M_MASSP>(a, s); return true;
     default: return false;
   }
 }
@@ -553,7 +558,9 @@ static bool go_mode(const Args<T> &a, int mode, hipStream_t s) {
 template <typename T>
 bool launch_column_cells(const LevelGeom &g, const T *X, int mode, T nu, const T *src_u, const T *src_p, T *ev_u,
                          T *ev_p, hipStream_t s) {
-  if (g.dim != 3 || (g.k != 3 && g.k != 4) || g.kp != g.k - 1 || g.ncells == 0) return false;
+  // the velocity block alone also on levels without a pressure space
+  const bool pres_ok = g.kp == g.k - 1 || (mode == M_LAPLACE && g.kp == 0);
+  if (g.dim != 3 || (g.k != 3 && g.k != 4) || !pres_ok || g.ncells == 0) return false;
   col::Args<T> a{};
   a.n0 = g.n[0];
   a.n1 = g.n[1];

@@ -114,9 +114,10 @@ void launch_node_gather(const LevelGeom &g, int k, int kp, T *ev_u, T *ev_p, T *
 // scratch buffer of cell_ev_elems(g) elements
 int64_t cell_ev_elems(const LevelGeom &g);
 // 3D Taylor-Hood Stokes cell work of degree 3 or 4 with one thread per point
-// column (modes M_LAPLACE | M_GRADP | M_DIVU, M_LAPLACE, M_GRADP, M_DIVU) into
-// the cell-local arrays of the node gather; false when the level or mode is
-// not covered (the caller uses the generic kernel)
+// column (modes M_LAPLACE | M_GRADP | M_DIVU, M_LAPLACE (also on levels
+// without a pressure space), M_GRADP, M_DIVU, M_MASSP) into the cell-local
+// arrays of the node gather; false when the level or mode is not covered (the
+// caller uses the generic kernel)
 template <typename T>
 bool launch_column_cells(const LevelGeom &g, const T *X, int mode, T nu, const T *src_u, const T *src_p, T *ev_u,
                          T *ev_p, hipStream_t s);

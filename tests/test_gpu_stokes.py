@@ -316,12 +316,15 @@ def test_transfers_3d_every_level(n, k):
         mfs.mfs_destroy(h)
 
 
-@pytest.mark.parametrize("n,noise", [([12, 10, 6], 0.2), ([16, 8, 4], 0.1), ([2, 2, 2], 0.2)])
-def test_velocity_block_on_every_level(n, noise):
-    """A on every level of a 3D Q2/Q1 hierarchy (degree 2, then degree 1,
-    then coarser degree-1 meshes) against the oracle's level matrices, FP64
-    and FP32; several bricks and ragged brick tails."""
-    dim, k, nu = 3, 2, 0.9
+@pytest.mark.parametrize("n,k,noise", [([12, 10, 6], 2, 0.2), ([16, 8, 4], 2, 0.1), ([2, 2, 2], 2, 0.2),
+                                         ([5, 3, 4], 3, 0.2), ([3, 2, 4], 4, 0.1)])
+def test_velocity_block_on_every_level(n, k, noise):
+    """A on every level of a 3D Taylor-Hood hierarchy (degree k, then the
+    lower degrees without a pressure space, then coarser degree-1 meshes)
+    against the oracle's level matrices, FP64 and FP32: for k = 2 several
+    bricks and ragged brick tails; for k = 3, 4 the column kernel on the
+    velocity-only degree-3 level and ragged last workgroups."""
+    dim, nu = 3, 0.9
     h, X = _setup(dim, n, k, noise, nu, mg_levels=1)
     try:
         H = _oracle_hierarchy(dim, n, X, k, nu, 5)
