@@ -109,7 +109,8 @@ void chebyshev(mfs_problem &P, int l, T *x, const T *b, bool zero_start, hipStre
   double rho_old = 1.0 / sigma;
   T *Ax = W.r[l], *d = W.d[l];
   // x += d with d from the residual b - A x: fused into the brick kernels
-  // where the level has one
+  // where the level has one, and into the node gather on the levels that sum
+  // cell-local results
   auto step = [&](T c1, T c2, bool first) {
     if (use_specialised() && q2_face_elems(L.g) > 0 &&
         launch_q2_cheb<T>(L.g, dev<T>(L).X, (T)P.nu, x, d, b, invdiag<T>(L), c1, c2, first, face<T>(L), s))
@@ -117,6 +118,10 @@ void chebyshev(mfs_problem &P, int l, T *x, const T *b, bool zero_start, hipStre
     if (use_specialised() && q1_face_elems(L.g) > 0 &&
         launch_q1_cheb<T>(L.g, dev<T>(L).X, (T)P.nu, x, d, b, invdiag<T>(L), c1, c2, first, face<T>(L), s))
       return;
+    if (use_gather<T>(L) && L.g.dim == 3 && L.g.k >= 3) {
+      launch_cell_cheb_gather<T>(L.g, dev<T>(L), (T)P.nu, x, d, b, invdiag<T>(L), c1, c2, first, cellev<T>(L), s);
+      return;
+    }
     apply_A<T>(P, l, Ax, x, s);
     cheb_update<T>(L.g, x, d, b, Ax, invdiag<T>(L), c1, c2, first, s);
   };

@@ -793,6 +793,63 @@ template void launch_cell_op_gather<double>(const LevelGeom &, const DevLevel<do
 template void launch_cell_op_gather<float>(const LevelGeom &, const DevLevel<float> &, int, float, float *, float *,
                                            const float *, const float *, const float *, float *, hipStream_t);
 
+// The node gather of the velocity block fused with a Chebyshev step: on every
+// free row the contributions of the cells that contain the node are summed in
+// the order of cell_gather_kernel into (A x)_j, then r = D^{-1}_j (b_j - (A x)_j),
+// d_j = c2 r (first step) or c1 d_j + c2 r, x_j += d_j; Dirichlet rows keep x
+// and d.  The same arithmetic as the gather followed by the separate update,
+// without writing and re-reading A x.
+template <typename T>
+__global__ void __launch_bounds__(256) cell_gather_cheb_kernel(CellArgs<T> a, int k, T *x, T *d, const T *b,
+                                                                const T *inv, T c1, T c2, int first) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= a.Nv) return;
+  const int Q = k + 1;
+  const int gx = (int)(i % a.nv0);
+  const int64_t r = i / a.nv0;
+  const int gy = (int)(r % a.nv1), gz = (int)(r / a.nv1);
+  if (gx == 0 || gy == 0 || gz == 0 || gx == a.nv0 - 1 || gy == a.nv1 - 1 || gz == a.nv2 - 1) return;
+  int cx[2], lx[2], cy[2], ly[2], cz[2], lz[2];
+  const int nx = node_cells(gx, k, a.n0, cx, lx), ny = node_cells(gy, k, a.n1, cy, ly),
+            nz = node_cells(gz, k, a.n2, cz, lz);
+  T acc[3] = {0, 0, 0};
+  for (int z = 0; z < nz; ++z)
+    for (int y = 0; y < ny; ++y)
+      for (int xx = 0; xx < nx; ++xx)
+        for (int c = 0; c < 3; ++c)
+          acc[c] += a.ev_u[cell_slot(a.n0, a.n1, 3, Q, cx[xx], cy[y], cz[z], c, lx[xx], ly[y], lz[z])];
+  const T iv = inv[i];
+  for (int c = 0; c < 3; ++c) {
+    const int64_t j = c * a.Nv + i;
+    const T rr = iv * (b[j] - acc[c]);
+    const T dn = first ? c2 * rr : c1 * d[j] + c2 * rr;
+    d[j] = dn;
+    x[j] += dn;
+  }
+}
+
+template <typename T>
+void launch_cell_cheb_gather(const LevelGeom &g, const DevLevel<T> &dv, T nu, T *x, T *d, const T *b, const T *inv,
+                             T c1, T c2, bool first, T *ev, hipStream_t s) {
+  MFS_REQUIRE(g.dim == 3 && g.k >= 3 && ev != nullptr, MFS_EINVAL, "cell gather needs a 3D level of degree >= 3");
+  CellArgs<T> a = make_args<T>(g, dv.X, dv.tab);
+  a.nu = nu;
+  a.src_u = x;
+  a.ev_u = ev;
+  const int64_t q = g.k + 1;
+  a.ev_p = ev + g.ncells * 3 * q * q * q;
+  if (!launch_column_cells<T>(g, dv.X, M_LAPLACE, nu, x, nullptr, a.ev_u, a.ev_p, s))
+    dispatch_k<3, T>(a, g.k, g.kp, M_LAPLACE, s);
+  hipLaunchKernelGGL((cell_gather_cheb_kernel<T>), dim3((unsigned)((g.Nv + 255) / 256)), dim3(256), 0, s, a, g.k, x,
+                     d, b, inv, c1, c2, first ? 1 : 0);
+  MFS_HIP(hipGetLastError());
+}
+template void launch_cell_cheb_gather<double>(const LevelGeom &, const DevLevel<double> &, double, double *, double *,
+                                              const double *, const double *, double, double, bool, double *,
+                                              hipStream_t);
+template void launch_cell_cheb_gather<float>(const LevelGeom &, const DevLevel<float> &, float, float *, float *,
+                                             const float *, const float *, float, float, bool, float *, hipStream_t);
+
 template <typename T>
 __global__ void fill_dirichlet_kernel(int dim, int nv0, int nv1, int nv2, int64_t Nv, T *dst, const T *src) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

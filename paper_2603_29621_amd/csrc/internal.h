@@ -124,6 +124,13 @@ bool launch_column_cells(const LevelGeom &g, const T *X, int mode, T nu, const T
 template <typename T>
 void launch_cell_op_gather(const LevelGeom &g, const DevLevel<T> &d, int mode, T nu, T *dst_u, T *dst_p,
                            const T *src_u, const T *src_p, const T *dir_src, T *ev, hipStream_t s);
+// Chebyshev step on a gather level (3D, k >= 3): A x into the cell-local
+// arrays, then the node gather fused with the update of the free rows:
+// r = inv (b - A x), d = c2 r (first) or c1 d + c2 r, x += d; Dirichlet rows
+// of x and d unchanged
+template <typename T>
+void launch_cell_cheb_gather(const LevelGeom &g, const DevLevel<T> &dv, T nu, T *x, T *d, const T *b, const T *inv,
+                             T c1, T c2, bool first, T *ev, hipStream_t s);
 // specialised 3D degree-2 kernel, writing every entry of its velocity output
 // itself: Q2_STOKES (Stokes Q2/Q1: dst_u = A src_u + B src_p, dst_p = B^T
 // src_u; Dirichlet rows dst_u = src_u), Q2_A (dst_u = A src_u, Dirichlet rows
