@@ -100,9 +100,10 @@ def time_vmult(mfs, torch, h, N, prec, steps, warmup, rotate_bytes=600e6, op=Non
     return wall, per
 
 
-def cpu_baseline_oracle(n=12, k=2):
+def cpu_baseline_oracle(n=12, k=2, seconds=10.0):
     """The oracle's element-loop Stokes vmult (element matrices by full
-    quadrature, no sum factorisation) on a bounded sample mesh, 1 thread."""
+    quadrature, no sum factorisation) on a bounded sample mesh, 1 thread,
+    repeated for about ``seconds``."""
     try:
         from threadpoolctl import threadpool_limits
     except Exception:  # pragma: no cover
@@ -120,7 +121,7 @@ def cpu_baseline_oracle(n=12, k=2):
         while True:
             fem.element_loop_stokes_vmult(S, 1.0, x)
             reps += 1
-            if time.perf_counter() - t0 > 10.0:
+            if time.perf_counter() - t0 > seconds:
                 break
         t = (time.perf_counter() - t0) / reps
     finally:
@@ -907,6 +908,9 @@ def main():
         progress("serving done")
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline_oracle()
+        # the higher degrees of the sweep, on smaller sample meshes
+        line["cpu_baseline"]["by_degree"] = {f"Q{k}Q{k - 1}": cpu_baseline_oracle(n, k, seconds=5.0)
+                                             for n, k in ((8, 3), (6, 4))}
         progress("oracle vmult timed")
         line["cpu_baseline"]["mixed_precision_vs_oracle"] = oracle_checks(mfs, torch, inputs)
         progress("cpu baseline done")
