@@ -1,10 +1,14 @@
-// 3D Taylor-Hood Stokes cell kernel for degrees k >= 3 with one thread per
+// 3D Taylor-Hood Stokes cell kernel for degrees k = 3, 4 with one thread per
 // column of quadrature points.
 //
 // Weak form: Sec. 1 eq. (stokes) in the symmetric block form of Sec. 3
 // eq. (stokes_block): velocity rows nu (grad u, grad v) - (p, div v),
-// pressure rows -(div u, q); Gauss quadrature with k+1 points per direction,
+// pressure rows -(div u, q), and the pressure mass (p, q) of the Schur
+// complement approximation; Gauss quadrature with k+1 points per direction,
 // velocity on the GLL nodes of degree k, pressure on those of degree k-1.
+// Modes: the Stokes operator, the velocity block A (also on the p-levels of
+// the velocity multigrid, which carry no pressure space), B, B^T and the
+// pressure mass.
 //
 // Work decomposition
 //  * Thread (cell, i, j), i, j < k+1: one column of points (or nodes) along
