@@ -243,7 +243,7 @@ def test_binding_rejects_short_or_mistyped_vectors():
 
 
 # ------------------------------------------------------------------ multigrid
-MG_CASES = [(2, [8, 8], 2, 0.2), (2, [4, 6], 3, 0.1), (3, [4, 4, 4], 2, 0.2), (3, [2, 2, 4], 3, 0.2)]
+MG_CASES = [(2, [8, 8], 2, 0.2), (2, [4, 6], 3, 0.1), (3, [4, 4, 4], 2, 0.2), (3, [2, 2, 4], 3, 0.2), (3, [2, 3, 2], 4, 0.1)]
 
 
 def _oracle_hierarchy(dim, n, X, k, nu, cheb_degree):
