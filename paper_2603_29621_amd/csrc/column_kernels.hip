@@ -12,8 +12,8 @@
 //
 // Work decomposition
 //  * Thread (cell, i, j), i, j < k+1: one column of points (or nodes) along
-//    z.  Cells with (k+1)^2 <= 64 threads are packed per wavefront and their
-//    sweeps synchronise at wavefront scope.
+//    z.  Cells are packed per wavefront (sweeps synchronised at wavefront
+//    scope) or, where that leaves many lanes idle, across the workgroup.
 //  * Sum factorisation: the x and y contractions go through LDS (a thread
 //    reads one row of k+1 values per output); the z contraction of a column
 //    stays in registers.  Values, x- and y-derivatives come straight from the
@@ -142,6 +142,28 @@ __device__ __forceinline__ float recip(float d) {
   return __builtin_fmaf(r, e, r);
 }
 
+// Cells of a workgroup of 256 threads: packed per wavefront (a cell's
+// (k+1)^2 columns never straddle two wavefronts, and the sweeps synchronise at
+// wavefront scope), or packed across the workgroup with workgroup barriers
+// when that leaves far fewer lanes idle (FP32 at k = 4: 10 cells in 250 lanes
+// against 8 in 200; in FP64 the 10 cells' LDS would allow only two workgroups
+// per CU).
+template <int K, typename T>
+struct Layout {
+  static constexpr int Q2 = (K + 1) * (K + 1);
+  static constexpr bool WAVE = !(K == 4 && sizeof(T) == 4);
+  static constexpr int CPW = 64 / Q2;
+  static constexpr int CPB = WAVE ? 4 * CPW : 256 / Q2;
+};
+
+template <bool WAVE>
+__device__ __forceinline__ void csync() {
+  if constexpr (WAVE)
+    wsync();
+  else
+    __syncthreads();
+}
+
 // Materialise a value in a register here: without it the compiler sinks a
 // sweep's arithmetic to the distant use and keeps the loaded LDS operands
 // live instead of the one result
@@ -176,7 +198,8 @@ constexpr int waves_target() {
 template <int K, typename T, int MODE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_target<T>()))) column_kernel(Args<T> a) {
   constexpr int Q = K + 1, M = K, Q2 = Q * Q, Q3 = Q2 * Q;
-  constexpr int CPW = 64 / Q2, CPB = 4 * CPW;
+  using LY = Layout<K, T>;
+  constexpr int CPB = LY::CPB;
   constexpr bool LAP = (MODE & M_LAPLACE) != 0, GRADP = (MODE & M_GRADP) != 0, DIVU = (MODE & M_DIVU) != 0;
   constexpr bool MASSP = (MODE & M_MASSP) != 0;
   constexpr bool NEED_U = LAP || DIVU, OUT_U = LAP || GRADP, NEED_P = GRADP || MASSP, OUT_P = DIVU || MASSP;
@@ -205,10 +228,18 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_
     if (i >= LT_W && i < LT_W + Q) v = (T)TB.w[i - LT_W];
     s_tab[i] = v;
   }
-  const int wv = tid >> 6, ln = tid & 63, sl = ln / Q2;
-  const bool active = sl < CPW;
-  const int e = wv * CPW + (active ? sl : 0);
-  const int t = active ? ln - sl * Q2 : 0;
+  int e, t;
+  bool active;
+  if constexpr (LY::WAVE) {
+    const int wv = tid >> 6, ln = tid & 63, sl = ln / Q2;
+    active = sl < LY::CPW;
+    e = wv * LY::CPW + (active ? sl : 0);
+    t = active ? ln - sl * Q2 : 0;
+  } else {
+    active = tid < CPB * Q2;
+    e = active ? tid / Q2 : CPB - 1;
+    t = active ? tid - e * Q2 : 0;
+  }
   const int ti = t % Q, tj = t / Q;
   const int lin = blockIdx.x * CPB + e;
   const bool valid = active && lin < a.ncells;
@@ -288,7 +319,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_
           wb[l * Q2 + tj * Q + ti] = s1;
         }
       }
-      wsync();
+      csync<LY::WAVE>();
       // y: at point (i, j) of node layer l: value, x-derivative, y-derivative
       T V[Q], Dx[Q], Dy[Q];
 #pragma unroll
@@ -309,7 +340,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_
         pin(Dx[l]);
         pin(Dy[l]);
       }
-      wsync();
+      csync<LY::WAVE>();
       // z in registers
 #pragma unroll
       for (int qz = 0; qz < Q; ++qz) {
@@ -343,7 +374,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_
         for (int m = 0; m < M; ++m) s0 += tP[ti * 8 + m] * s_p[e][l * M * M + tj * M + m];
         pw[l * Q * M + tj * Q + ti] = s0;
       }
-    wsync();
+    csync<LY::WAVE>();
     T PV[M];
 #pragma unroll
     for (int l = 0; l < M; ++l) {
@@ -353,7 +384,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_
       PV[l] = s0;
       pin(PV[l]);
     }
-    wsync();
+    csync<LY::WAVE>();
 #pragma unroll
     for (int qz = 0; qz < Q; ++qz) {
       T s0 = 0;
@@ -466,7 +497,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_
           z2[l * Q2 + tj * Q + ti] = s2;
         }
       }
-      wsync();
+      csync<LY::WAVE>();
       // y transposed: thread (i, j) = (point i, node j)
       T *wx = &s_w[e][0], *ws = &s_w[e][Q3];
       T rx[Q], rs[Q];
@@ -490,7 +521,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_
           wx[l * Q2 + tj * Q + ti] = rx[l];
           ws[l * Q2 + tj * Q + ti] = rs[l];
         }
-      wsync();
+      csync<LY::WAVE>();
       // x transposed: thread (i, j) = node (i, j)
 #pragma unroll
       for (int l = 0; l < Q; ++l) {
@@ -500,7 +531,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_
           r += tD[qx * 8 + ti] * wx[l * Q2 + tj * Q + qx] + tS[qx * 8 + ti] * ws[l * Q2 + tj * Q + qx];
         if (valid) a.ev_u[row0 + c * cstride + l * lstride] = r;
       }
-      wsync();
+      csync<LY::WAVE>();
     }
   }
   if (OUT_P) {
@@ -514,7 +545,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_
         for (int qz = 0; qz < Q; ++qz) s0 += tP[qz * 8 + l] * qv[qz];
         pz[l * Q2 + tj * Q + ti] = s0;
       }
-    wsync();
+    csync<LY::WAVE>();
     if (active && tj < M)
 #pragma unroll
       for (int l = 0; l < M; ++l) {
@@ -523,7 +554,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_
         for (int qy = 0; qy < Q; ++qy) s0 += tP[qy * 8 + tj] * pz[l * Q2 + qy * Q + ti];
         py[l * Q * M + tj * Q + ti] = s0;
       }
-    wsync();
+    csync<LY::WAVE>();
     if (valid && pcol) {
       const int64_t p0 = cell_slot(a.n0, a.n1, 1, M, cx, cy, cz, 0, ti, tj, 0);
       const int64_t pl = cell_slot(a.n0, a.n1, 1, M, cx, cy, cz, 0, ti, tj, 1) - p0;
@@ -540,7 +571,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_
 
 template <int K, typename T, int MODE>
 static void go(const Args<T> &a, hipStream_t s) {
-  constexpr int CPB = 4 * (64 / ((K + 1) * (K + 1)));
+  constexpr int CPB = Layout<K, T>::CPB;
   const int grid = (a.ncells + CPB - 1) / CPB;
   hipLaunchKernelGGL((column_kernel<K, T, MODE>), dim3(grid), dim3(256), 0, s, a);
 }
