@@ -30,10 +30,34 @@ namespace mfs {
 namespace col {
 
 // ---- compile-time 1D tables on [0, 1]
-constexpr double csqrt(double v) {
-  double r = v > 1 ? v : 1.0;
-  for (int i = 0; i < 80; ++i) r = 0.5 * (r + v / r);
-  return r;
+
+// Legendre polynomial P_n and its derivative at t (three-term recurrence)
+constexpr void legendre(int n, double t, double &p, double &dp) {
+  double p0 = 1.0, p1 = t;
+  if (n == 0) {
+    p = 1.0;
+    dp = 0.0;
+    return;
+  }
+  for (int m = 2; m <= n; ++m) {
+    const double p2 = ((2 * m - 1) * t * p1 - (m - 1) * p0) / m;
+    p0 = p1;
+    p1 = p2;
+  }
+  p = p1;
+  dp = n * (t * p1 - p0) / (t * t - 1.0);
+}
+// cos by its Taylor series after reduction to [-pi, pi] (initial guesses only)
+constexpr double ccos(double x) {
+  constexpr double pi = 3.14159265358979323846;
+  while (x > pi) x -= 2 * pi;
+  while (x < -pi) x += 2 * pi;
+  double term = 1.0, sum = 1.0;
+  for (int k = 1; k < 30; ++k) {
+    term *= -x * x / ((2 * k - 1) * (2 * k));
+    sum += term;
+  }
+  return sum;
 }
 
 template <int K>
@@ -43,42 +67,42 @@ struct Tab1 {
   double S[Q][Q], DS[Q][Q];  // velocity basis (GLL nodes of degree K) and its derivative at the points
   double Sp[Q][M];           // pressure basis (GLL nodes of degree K-1) at the points
   constexpr Tab1() : x{}, w{}, S{}, DS{}, Sp{} {
-    // Gauss-Legendre rules on [-1, 1] in closed form
+    constexpr double pi = 3.14159265358979323846;
+    // Gauss-Legendre rule on [-1, 1]: the roots of P_Q by Newton's method from
+    // the usual cosine guesses; weights 2 / ((1 - t^2) P_Q'(t)^2)
     double gx[Q] = {}, gw[Q] = {};
-    if constexpr (Q == 4) {
-      const double a = csqrt(3.0 / 7.0 - 2.0 / 7.0 * csqrt(6.0 / 5.0));
-      const double b = csqrt(3.0 / 7.0 + 2.0 / 7.0 * csqrt(6.0 / 5.0));
-      const double wa = (18.0 + csqrt(30.0)) / 36.0, wb = (18.0 - csqrt(30.0)) / 36.0;
-      gx[0] = -b, gx[1] = -a, gx[2] = a, gx[3] = b;
-      gw[0] = wb, gw[1] = wa, gw[2] = wa, gw[3] = wb;
-    } else {
-      const double a = csqrt(5.0 - 2.0 * csqrt(10.0 / 7.0)) / 3.0;
-      const double b = csqrt(5.0 + 2.0 * csqrt(10.0 / 7.0)) / 3.0;
-      const double wa = (322.0 + 13.0 * csqrt(70.0)) / 900.0, wb = (322.0 - 13.0 * csqrt(70.0)) / 900.0;
-      gx[0] = -b, gx[1] = -a, gx[2] = 0.0, gx[3] = a, gx[4] = b;
-      gw[0] = wb, gw[1] = wa, gw[2] = 128.0 / 225.0, gw[3] = wa, gw[4] = wb;
+    for (int i = 0; i < Q; ++i) {
+      double t = -ccos(pi * (i + 0.75) / (Q + 0.5));
+      for (int it = 0; it < 100; ++it) {
+        double p = 0, dp = 0;
+        legendre(Q, t, p, dp);
+        t -= p / dp;
+      }
+      double p = 0, dp = 0;
+      legendre(Q, t, p, dp);
+      gx[i] = t;
+      gw[i] = 2.0 / ((1.0 - t * t) * dp * dp);
     }
     for (int q = 0; q < Q; ++q) {
       x[q] = 0.5 * (gx[q] + 1.0);
       w[q] = 0.5 * gw[q];
     }
-    // GLL nodes on [0, 1]: degree 3 {0, (1 -+ 1/sqrt 5)/2, 1}, degree 4 {0, (1 -+ sqrt(3/7))/2, 1/2, 1},
-    // degree 2 {0, 1/2, 1}
+    // GLL nodes of degree deg on [0, 1]: the end points and the roots of
+    // P_deg' (Newton's method on P_deg' from the Chebyshev-Gauss-Lobatto
+    // guesses, with P_deg'' from the Legendre equation)
     double nv[Q] = {}, np[M] = {};
     auto gll = [](int deg, double *out) {
       out[0] = 0.0;
       out[deg] = 1.0;
-      if (deg == 2) out[1] = 0.5;
-      if (deg == 3) {
-        const double r = 1.0 / csqrt(5.0);
-        out[1] = 0.5 * (1.0 - r);
-        out[2] = 0.5 * (1.0 + r);
-      }
-      if (deg == 4) {
-        const double r = csqrt(3.0 / 7.0);
-        out[1] = 0.5 * (1.0 - r);
-        out[2] = 0.5;
-        out[3] = 0.5 * (1.0 + r);
+      for (int i = 1; i < deg; ++i) {
+        double t = -ccos(pi * i / deg);
+        for (int it = 0; it < 100; ++it) {
+          double p = 0, dp = 0;
+          legendre(deg, t, p, dp);
+          const double d2p = (2.0 * t * dp - deg * (deg + 1) * p) / (1.0 - t * t);
+          t -= dp / d2p;
+        }
+        out[i] = 0.5 * (t + 1.0);
       }
     };
     gll(K, nv);
@@ -145,13 +169,14 @@ __device__ __forceinline__ float recip(float d) {
 // Cells of a workgroup of 256 threads: packed per wavefront (a cell's
 // (k+1)^2 columns never straddle two wavefronts, and the sweeps synchronise at
 // wavefront scope), or packed across the workgroup with workgroup barriers
-// when that leaves far fewer lanes idle (FP32 at k = 4: 10 cells in 250 lanes
-// against 8 in 200; in FP64 the 10 cells' LDS would allow only two workgroups
-// per CU).
+// where that keeps more lanes busy per CU within the LDS: k = 5 (7 cells in
+// 252 lanes against 1 cell in 36 of every 64), and in FP32 k = 4 (10 cells in
+// 250 lanes against 8 in 200) and k = 6 (5 in 245 against 4 in 196); in FP64
+// the packed k = 4 and k = 6 cells' LDS would allow too few workgroups per CU.
 template <int K, typename T>
 struct Layout {
   static constexpr int Q2 = (K + 1) * (K + 1);
-  static constexpr bool WAVE = !(K == 4 && sizeof(T) == 4);
+  static constexpr bool WAVE = !(K == 5 || (sizeof(T) == 4 && (K == 4 || K == 6)));
   static constexpr int CPW = 64 / Q2;
   static constexpr int CPB = WAVE ? 4 * CPW : 256 / Q2;
 };
@@ -190,13 +215,13 @@ constexpr int pad_stride(int n) {
 }
 
 // occupancy target (waves per SIMD): FP64 3 (<= 168 registers), FP32 4
-template <typename T>
+template <typename T, int K>
 constexpr int waves_target() {
-  return sizeof(T) == 8 ? 3 : 4;
+  return sizeof(T) == 8 ? (K <= 4 ? 3 : 2) : (K <= 4 ? 4 : 3);
 }
 
 template <int K, typename T, int MODE>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_target<T>()))) column_kernel(Args<T> a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_target<T, K>()))) column_kernel(Args<T> a) {
   constexpr int Q = K + 1, M = K, Q2 = Q * Q, Q3 = Q2 * Q;
   using LY = Layout<K, T>;
   constexpr int CPB = LY::CPB;
@@ -595,7 +620,7 @@ bool launch_column_cells(const LevelGeom &g, const T *X, int mode, T nu, const T
                          T *ev_p, hipStream_t s) {
   // the velocity block alone also on levels without a pressure space
   const bool pres_ok = g.kp == g.k - 1 || (mode == M_LAPLACE && g.kp == 0);
-  if (g.dim != 3 || (g.k != 3 && g.k != 4) || !pres_ok || g.ncells == 0) return false;
+  if (g.dim != 3 || g.k < 3 || g.k > 6 || !pres_ok || g.ncells == 0) return false;
   col::Args<T> a{};
   a.n0 = g.n[0];
   a.n1 = g.n[1];
@@ -613,7 +638,13 @@ bool launch_column_cells(const LevelGeom &g, const T *X, int mode, T nu, const T
   a.ev_u = ev_u;
   a.ev_p = ev_p;
   a.nu = nu;
-  const bool ok = g.k == 3 ? col::go_mode<3, T>(a, mode, s) : col::go_mode<4, T>(a, mode, s);
+  bool ok = false;
+  switch (g.k) {
+    case 3: ok = col::go_mode<3, T>(a, mode, s); break;
+    case 4: ok = col::go_mode<4, T>(a, mode, s); break;
+    case 5: ok = col::go_mode<5, T>(a, mode, s); break;
+    default: ok = col::go_mode<6, T>(a, mode, s); break;
+  }
   if (ok) MFS_HIP(hipGetLastError());
   return ok;
 }
