@@ -176,6 +176,7 @@ void ev_mode(const EvKArgs<T> &a, int mode, hipStream_t s) {
 template <typename T>
 void launch_cell_op_ev(const LevelGeom &g, int k, const T *X, const T *tab, int mode, T nu, const EvArgs<T> &ev,
                        hipStream_t s) {
+  if (ev.ncells > 0 && launch_column_ev<T>(g, k, X, mode, nu, ev, s)) return;
   EvKArgs<T> a{};
   a.n0 = g.n[0];
   a.n1 = g.n[1];

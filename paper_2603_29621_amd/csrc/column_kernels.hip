@@ -24,6 +24,7 @@
 //  * The transposed sequence integrates; every thread writes its column of
 //    nodal results into the cell-local arrays (cell_slot layout) that the
 //    node gather sums in a fixed order (deterministic, no atomics).
+#include "hp.h"
 #include "internal.h"
 
 namespace mfs {
@@ -144,6 +145,13 @@ struct Args {
   const T *X, *src_u, *src_p;
   T *ev_u, *ev_p;
   T nu;
+  // cell-local (E-vector) inputs and outputs of the cells of one degree class
+  // of an hp space (EV kernels): node (i, j, l) of a cell at i + Q j + Q^2 l,
+  // the three velocity components side by side
+  const int *cells;
+  const int64_t *off_u, *off_p;
+  const T *in_u, *in_p;
+  T *out_u, *out_p;
 };
 
 __device__ __forceinline__ void wsync() {
@@ -220,7 +228,8 @@ constexpr int waves_target() {
   return sizeof(T) == 8 ? (K <= 4 ? 3 : 2) : (K <= 4 ? 4 : 3);
 }
 
-template <int K, typename T, int MODE>
+// EV: cells of one hp degree class, E-vector inputs and outputs
+template <int K, typename T, int MODE, bool EV>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_target<T, K>()))) column_kernel(Args<T> a) {
   constexpr int Q = K + 1, M = K, Q2 = Q * Q, Q3 = Q2 * Q;
   using LY = Layout<K, T>;
@@ -268,13 +277,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_
   const int ti = t % Q, tj = t / Q;
   const int lin = blockIdx.x * CPB + e;
   const bool valid = active && lin < a.ncells;
+  const int cell = EV ? (valid ? a.cells[lin] : 0) : lin;
   int cx = 0, cy = 0, cz = 0;
   if (valid) {
-    cx = lin % a.n0;
-    const int r = lin / a.n0;
+    cx = cell % a.n0;
+    const int r = cell / a.n0;
     cy = r % a.n1;
     cz = r / a.n1;
   }
+  const int64_t ou = (EV && valid) ? a.off_u[cell] : 0, op = (EV && valid) ? a.off_p[cell] : 0;
 
   // ---- load: this thread's velocity column (zero on Dirichlet nodes),
   // pressure column, and a share of the cell's vertices
@@ -288,7 +299,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_
     for (int l = 0; l < Q; ++l) {
       const int gz = cz * K + l;
       T v = 0;
-      if (NEED_U && valid && !xy_dir && gz > 0 && gz < a.nv2 - 1) v = a.src_u[c * a.Nv + zstride * gz + xy_off];
+      if (EV) {
+        if (NEED_U && valid) v = a.in_u[ou + 3 * (ti + Q * tj + Q2 * l) + c];
+      } else if (NEED_U && valid && !xy_dir && gz > 0 && gz < a.nv2 - 1) {
+        v = a.src_u[c * a.Nv + zstride * gz + xy_off];
+      }
       uv[c][l] = v;
     }
   const bool pcol = ti < M && tj < M;
@@ -297,7 +312,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_
   for (int l = 0; l < M; ++l) {
     T v = 0;
     if (NEED_P && valid && pcol)
-      v = a.src_p[(cx * (K - 1) + ti) + (int64_t)a.np0 * ((cy * (K - 1) + tj) + (int64_t)a.np1 * (cz * (K - 1) + l))];
+      v = EV ? a.in_p[op + ti + M * tj + M * M * l]
+             : a.src_p[(cx * (K - 1) + ti) + (int64_t)a.np0 * ((cy * (K - 1) + tj) + (int64_t)a.np1 * (cz * (K - 1) + l))];
     pv[l] = v;
   }
   if (valid)
@@ -496,9 +512,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_
   }
 
   // ---- backward: integrate against the test functions, column by column
-  const int64_t row0 = cell_slot(a.n0, a.n1, 3, Q, cx, cy, cz, 0, ti, tj, 0);
-  const int64_t cstride = cell_slot(a.n0, a.n1, 3, Q, cx, cy, cz, 1, ti, tj, 0) - row0;
-  const int64_t lstride = cell_slot(a.n0, a.n1, 3, Q, cx, cy, cz, 0, ti, tj, 1) - row0;
+  // output slot of node (i, j, 0), component 0, and the strides to the next
+  // component and node layer
+  const int64_t row0 = EV ? ou + 3 * (ti + Q * tj) : cell_slot(a.n0, a.n1, 3, Q, cx, cy, cz, 0, ti, tj, 0);
+  const int64_t cstride = EV ? 1 : cell_slot(a.n0, a.n1, 3, Q, cx, cy, cz, 1, ti, tj, 0) - row0;
+  const int64_t lstride = EV ? 3 * Q2 : cell_slot(a.n0, a.n1, 3, Q, cx, cy, cz, 0, ti, tj, 1) - row0;
+  T *const outu = EV ? a.out_u : a.ev_u;
   if (OUT_U) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -554,7 +573,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_
 #pragma unroll
         for (int qx = 0; qx < Q; ++qx)
           r += tD[qx * 8 + ti] * wx[l * Q2 + tj * Q + qx] + tS[qx * 8 + ti] * ws[l * Q2 + tj * Q + qx];
-        if (valid) a.ev_u[row0 + c * cstride + l * lstride] = r;
+        if (valid) outu[row0 + c * cstride + l * lstride] = r;
       }
       csync<LY::WAVE>();
     }
@@ -581,34 +600,47 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_
       }
     csync<LY::WAVE>();
     if (valid && pcol) {
-      const int64_t p0 = cell_slot(a.n0, a.n1, 1, M, cx, cy, cz, 0, ti, tj, 0);
-      const int64_t pl = cell_slot(a.n0, a.n1, 1, M, cx, cy, cz, 0, ti, tj, 1) - p0;
+      const int64_t p0 = EV ? op + ti + M * tj : cell_slot(a.n0, a.n1, 1, M, cx, cy, cz, 0, ti, tj, 0);
+      const int64_t pl = EV ? M * M : cell_slot(a.n0, a.n1, 1, M, cx, cy, cz, 0, ti, tj, 1) - p0;
+      T *const outp = EV ? a.out_p : a.ev_p;
 #pragma unroll
       for (int l = 0; l < M; ++l) {
         T s0 = 0;
 #pragma unroll
         for (int qx = 0; qx < Q; ++qx) s0 += tP[qx * 8 + ti] * py[l * Q * M + tj * Q + qx];
-        a.ev_p[p0 + l * pl] = s0;
+        outp[p0 + l * pl] = s0;
       }
     }
   }
 }
 
-template <int K, typename T, int MODE>
+template <int K, typename T, int MODE, bool EV>
 static void go(const Args<T> &a, hipStream_t s) {
+  if (a.ncells == 0) return;
   constexpr int CPB = Layout<K, T>::CPB;
   const int grid = (a.ncells + CPB - 1) / CPB;
-  hipLaunchKernelGGL((column_kernel<K, T, MODE>), dim3(grid), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((column_kernel<K, T, MODE, EV>), dim3(grid), dim3(256), 0, s, a);
 }
 
-template <int K, typename T>
+template <int K, typename T, bool EV>
 static bool go_mode(const Args<T> &a, int mode, hipStream_t s) {
   switch (mode) {
-    case M_LAPLACE | M_GRADP | M_DIVU: go<K, T, M_LAPLACE | M_GRADP | M_DIVU>(a, s); return true;
-    case M_LAPLACE: go<K, T, M_LAPLACE>(a, s); return true;
-    case M_GRADP: go<K, T, M_GRADP>(a, s); return true;
-    case M_DIVU: go<K, T, M_DIVU>(a, s); return true;
-    case M_MASSP: go<K, T, M_MASSP>(a, s); return true;
+    case M_LAPLACE | M_GRADP | M_DIVU: go<K, T, M_LAPLACE | M_GRADP | M_DIVU, EV>(a, s); return true;
+    case M_LAPLACE: go<K, T, M_LAPLACE, EV>(a, s); return true;
+    case M_GRADP: go<K, T, M_GRADP, EV>(a, s); return true;
+    case M_DIVU: go<K, T, M_DIVU, EV>(a, s); return true;
+    case M_MASSP: go<K, T, M_MASSP, EV>(a, s); return true;
+    default: return false;
+  }
+}
+
+template <typename T, bool EV>
+static bool go_k(int k, const Args<T> &a, int mode, hipStream_t s) {
+  switch (k) {
+    case 3: return go_mode<3, T, EV>(a, mode, s);
+    case 4: return go_mode<4, T, EV>(a, mode, s);
+    case 5: return go_mode<5, T, EV>(a, mode, s);
+    case 6: return go_mode<6, T, EV>(a, mode, s);
     default: return false;
   }
 }
@@ -638,16 +670,35 @@ bool launch_column_cells(const LevelGeom &g, const T *X, int mode, T nu, const T
   a.ev_u = ev_u;
   a.ev_p = ev_p;
   a.nu = nu;
-  bool ok = false;
-  switch (g.k) {
-    case 3: ok = col::go_mode<3, T>(a, mode, s); break;
-    case 4: ok = col::go_mode<4, T>(a, mode, s); break;
-    case 5: ok = col::go_mode<5, T>(a, mode, s); break;
-    default: ok = col::go_mode<6, T>(a, mode, s); break;
-  }
+  const bool ok = col::go_k<T, false>(g.k, a, mode, s);
   if (ok) MFS_HIP(hipGetLastError());
   return ok;
 }
+template <typename T>
+bool launch_column_ev(const LevelGeom &g, int k, const T *X, int mode, T nu, const EvArgs<T> &ev, hipStream_t s) {
+  if (g.dim != 3 || k < 3 || k > 6) return false;
+  col::Args<T> a{};
+  a.n0 = g.n[0];
+  a.n1 = g.n[1];
+  a.n2 = g.n[2];
+  a.ncells = ev.ncells;
+  a.X = X;
+  a.nu = nu;
+  a.cells = ev.cells;
+  a.off_u = ev.off_u;
+  a.off_p = ev.off_p;
+  a.in_u = ev.in_u;
+  a.in_p = ev.in_p;
+  a.out_u = ev.out_u;
+  a.out_p = ev.out_p;
+  const bool ok = col::go_k<T, true>(k, a, mode, s);
+  if (ok) MFS_HIP(hipGetLastError());
+  return ok;
+}
+template bool launch_column_ev<double>(const LevelGeom &, int, const double *, int, double, const EvArgs<double> &,
+                                       hipStream_t);
+template bool launch_column_ev<float>(const LevelGeom &, int, const float *, int, float, const EvArgs<float> &,
+                                      hipStream_t);
 template bool launch_column_cells<double>(const LevelGeom &, const double *, int, double, const double *,
                                           const double *, double *, double *, hipStream_t);
 template bool launch_column_cells<float>(const LevelGeom &, const float *, int, float, const float *, const float *,
