@@ -26,6 +26,7 @@
 //    node gather sums in a fixed order (deterministic, no atomics).
 #include "hp.h"
 #include "internal.h"
+#include <type_traits>
 
 namespace mfs {
 namespace col {
@@ -636,9 +637,13 @@ static bool go_mode(const Args<T> &a, int mode, hipStream_t s) {
 
 template <typename T, bool EV>
 static bool go_k(int k, const Args<T> &a, int mode, hipStream_t s) {
+  if constexpr (!EV) {
+    if (k == 3) return go_mode<3, T, EV>(a, mode, s);
+  }
+  if constexpr (!EV || std::is_same_v<T, float>) {
+    if (k == 4) return go_mode<4, T, EV>(a, mode, s);
+  }
   switch (k) {
-    case 3: return go_mode<3, T, EV>(a, mode, s);
-    case 4: return go_mode<4, T, EV>(a, mode, s);
     case 5: return go_mode<5, T, EV>(a, mode, s);
     case 6: return go_mode<6, T, EV>(a, mode, s);
     default: return false;
@@ -676,7 +681,13 @@ bool launch_column_cells(const LevelGeom &g, const T *X, int mode, T nu, const T
 }
 template <typename T>
 bool launch_column_ev(const LevelGeom &g, int k, const T *X, int mode, T nu, const EvArgs<T> &ev, hipStream_t s) {
-  if (g.dim != 3 || k < 3 || k > 6) return false;
+  // Degree classes of an hp mesh hold a few thousand cells.  At k = 3 (and
+  // k = 4 in FP64) the column kernel then launches fewer waves than the chip
+  // has slots (four and two cells per wave), and the generic kernel, one
+  // thread per point, is the faster one; FP32 at k = 4 packs ten cells per
+  // workgroup and from k = 5 on the column kernel wins at these sizes too.
+  const int kmin = std::is_same_v<T, float> ? 4 : 5;
+  if (g.dim != 3 || k < kmin || k > 6) return false;
   col::Args<T> a{};
   a.n0 = g.n[0];
   a.n1 = g.n[1];

@@ -142,7 +142,7 @@ struct EvArgs {
 template <typename T>
 void launch_cell_op_ev(const LevelGeom &g, int k, const T *X, const T *tab, int mode, T nu, const EvArgs<T> &ev,
                        hipStream_t s);
-// the same work by the column kernel (degrees 3..6); false when not covered
+// the same work by the column kernel (degrees 5, 6; FP32 also 4); false when not covered
 template <typename T>
 bool launch_column_ev(const LevelGeom &g, int k, const T *X, int mode, T nu, const EvArgs<T> &ev, hipStream_t s);
 
