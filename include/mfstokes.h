@@ -429,6 +429,53 @@ int mfs_st_stage_transfer(mfs_problem *p, int q_out, int q_in, const double *C, 
                           void *stream);
 
 /*
+ * hp space-time multigrid (hp-STMG) of Sec. 4 for the Kronecker stage system
+ * K x = (G (x) M + tau I_Q (x) A) x = b on one slab with DG(kt) in time
+ * (Q = kt + 1 stages on the Gauss points of the slab) and Taylor-Hood
+ * Q_k / Q_{k-1} in space: FGMRES preconditioned by one V-cycle.
+ * Levels (the paper's two coarsening rules, no geometric coarsening in time):
+ * spatial degree k -> 2, then temporal degree kt -> 0, then h-coarsening
+ * while both n are even and larger than 2.  Transfers: per stage the
+ * constrained velocity and unconstrained pressure Lagrange transfers
+ * (restriction: their transpose); in time the coarse DG polynomial at the
+ * fine nodes, restricted by M_c^{-1} P^T M_f.  Smoother: relax_steps
+ * additive Schwarz steps x <- x + relax_omega B (b - K x) before and after
+ * the coarse correction, B the sum of the exact inverses of the vertex-star
+ * space-time patches (every velocity component at the velocity nodes
+ * |i - k v| < k and the pressure at the nodes |j - (k-1) v| < k-1 of
+ * vertex v, all Q stages, Dirichlet rows left out) weighted by the inverse
+ * number of patches holding each unknown.  Coarsest level: the dense inverse
+ * with the first pressure node of every stage pinned to zero.
+ *
+ * mfs_stmg_setup: 2D meshes (mfs_mesh, host vertices), k = 2 with kt <= 2
+ * or k = 3 with kt <= 1 (patches of at most 118 unknowns), nu, tau > 0,
+ * relax_steps in [0, 16].  Builds every level on the device (library-owned
+ * memory; MFS_EUNSUPPORTED outside these cases); synchronous.
+ * mfs_stmg_levels: number of levels, and for `level` its cells n[2], velocity
+ * degree k, stages Q and vector length Q (2 n_u + n_p) (any output may be
+ * NULL).
+ * mfs_stmg_vmult: dst = K_level src (stage-major device FP64 vectors of that
+ * length; every stage carries the Dirichlet rows as identity).  Enqueue
+ * only.
+ * mfs_stmg_vcycle: dst = one V-cycle applied to src on level 0 (device
+ * FP64); x starts from b on the Dirichlet rows and 0 elsewhere.  Enqueue
+ * only; calls on one handle must not overlap.
+ * mfs_stmg_solve: x = FGMRES(30) with one V-cycle per iteration from x = 0
+ * to ||b - K x|| <= rtol ||b|| (device FP64 b and x of the level-0 length;
+ * the constant pressure of each stage is in the kernel of K: b must be
+ * consistent).  Synchronous on the setup stream; MFS_ENOCONV with `info`
+ * filled when maxit iterations do not reach rtol.
+ */
+typedef struct mfs_stmg mfs_stmg;
+int mfs_stmg_setup(const mfs_mesh *mesh, int k, int kt, double nu, double tau, int relax_steps, double relax_omega,
+                   void *stream, mfs_stmg **out);
+int mfs_stmg_levels(const mfs_stmg *m, int level, int *n_levels, int *n, int *k, int *Q, int64_t *length);
+int mfs_stmg_vmult(mfs_stmg *m, int level, double *dst, const double *src, void *stream);
+int mfs_stmg_vcycle(mfs_stmg *m, double *dst, const double *src, void *stream);
+int mfs_stmg_solve(mfs_stmg *m, const double *b, double *x, double rtol, int maxit, mfs_solve_info *info);
+int mfs_stmg_destroy(mfs_stmg *m);
+
+/*
  * General Navier-Stokes state (Sec. 5, BDF2): the linearisation at
  * x0 = [u0 | p0] (device FP64, full length (dim+1) n_u; velocity with its
  * boundary values) with the BDF2 history u_hist = (4 u^n - u^{n-1}) / 3

@@ -44,7 +44,8 @@ EXPORTED = [
     "mfs_set_linearization", "mfs_setup_hp", "mfs_setup_refined", "mfs_refined_count",
     "mfs_stokes_vmult_noalloc", "mfs_set_linearization_point", "mfs_ns_residual", "mfs_default_newton_options",
     "mfs_ns_bdf2_step", "mfs_setup_arena", "mfs_batch_step", "mfs_st_vmult", "mfs_st_stage_transfer",
-    "mfs_refined_mg_metrics",
+    "mfs_refined_mg_metrics", "mfs_stmg_setup", "mfs_stmg_levels", "mfs_stmg_vmult", "mfs_stmg_vcycle",
+    "mfs_stmg_solve", "mfs_stmg_destroy",
 ]
 
 
@@ -163,6 +164,15 @@ def lib():
                                        ctypes.POINTER(mfs_newton_info), vp]
         L.mfs_stokes_vmult_noalloc.argtypes = [ctypes.POINTER(ctypes.c_int), vp, ctypes.c_double, ctypes.c_int, vp,
                                                vp, vp]
+        L.mfs_stmg_setup.argtypes = [ctypes.POINTER(mfs_mesh), ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                     ctypes.c_double, ctypes.c_int, ctypes.c_double, vp, ctypes.POINTER(vp)]
+        L.mfs_stmg_levels.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                      ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                      ctypes.POINTER(ctypes.c_int64)]
+        L.mfs_stmg_vmult.argtypes = [vp, ctypes.c_int, vp, vp, vp]
+        L.mfs_stmg_vcycle.argtypes = [vp, vp, vp, vp]
+        L.mfs_stmg_solve.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_int, ctypes.POINTER(mfs_solve_info)]
+        L.mfs_stmg_destroy.argtypes = [vp]
         _lib = L
     return _lib
 
@@ -612,3 +622,64 @@ class Problem:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------- hp space-time multigrid
+def mfs_stmg_setup(dim, n, vertices, k, kt, nu, tau, relax_steps=2, relax_omega=0.5, stream=None):
+    """hp-STMG of the DG(kt) / Taylor-Hood Q_k stage system on one slab (2D)."""
+    m, _keep = _mesh(dim, n, vertices)
+    h = ctypes.c_void_p(0)
+    _check(lib().mfs_stmg_setup(ctypes.byref(m), int(k), int(kt), float(nu), float(tau), int(relax_steps),
+                                float(relax_omega), _stream(stream), ctypes.byref(h)))
+    return h
+
+
+def mfs_stmg_levels(h):
+    """[{n, k, Q, length}] from the finest level to the coarsest."""
+    nl = ctypes.c_int(0)
+    _check(lib().mfs_stmg_levels(h, 0, ctypes.byref(nl), None, None, None, None))
+    out = []
+    for level in range(nl.value):
+        n = (ctypes.c_int * 2)()
+        k, Q, ln = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int64(0)
+        _check(lib().mfs_stmg_levels(h, level, None, n, ctypes.byref(k), ctypes.byref(Q), ctypes.byref(ln)))
+        out.append({"n": [n[0], n[1]], "k": k.value, "Q": Q.value, "length": ln.value})
+    return out
+
+
+def _stmg_len(h, level):
+    ln = ctypes.c_int64(0)
+    _check(lib().mfs_stmg_levels(h, level, None, None, None, None, ctypes.byref(ln)))
+    return ln.value
+
+
+def mfs_stmg_vmult(h, level, dst, src, stream=None):
+    import torch
+
+    n = _stmg_len(h, level)
+    _check(lib().mfs_stmg_vmult(h, int(level), _arg(dst, n, torch.float64, "dst"), _arg(src, n, torch.float64, "src"),
+                                _stream(stream)))
+
+
+def mfs_stmg_vcycle(h, dst, src, stream=None):
+    import torch
+
+    n = _stmg_len(h, 0)
+    _check(lib().mfs_stmg_vcycle(h, _arg(dst, n, torch.float64, "dst"), _arg(src, n, torch.float64, "src"),
+                                 _stream(stream)))
+
+
+def mfs_stmg_solve(h, b, x, rtol=1e-8, maxit=200) -> mfs_solve_info:
+    import torch
+
+    n = _stmg_len(h, 0)
+    info = mfs_solve_info()
+    rc = lib().mfs_stmg_solve(h, _arg(b, n, torch.float64, "b"), _arg(x, n, torch.float64, "x"), float(rtol),
+                              int(maxit), ctypes.byref(info))
+    if rc not in (MFS_OK, MFS_ENOCONV):
+        _check(rc)
+    return info
+
+
+def mfs_stmg_destroy(h):
+    _check(lib().mfs_stmg_destroy(h))

@@ -120,24 +120,17 @@ __global__ void k_probe_extract(LevelGeom g, Colour C, const double *y, double *
   M[pid * NP * NP + (int64_t)j * NP + i] = gi >= 0 ? y[gi] : (i == j ? 1.0 : 0.0);
 }
 
-// In-place Gauss-Jordan inversion with partial (row) pivoting, one
-// workgroup per patch, the matrix in LDS (column-major like the storage).
-// Row interchanges are recorded and undone as column interchanges at the
-// end.  A zero or non-finite pivot sets *status.
+// In-place Gauss-Jordan inversion with partial (row) pivoting of the NP x NP
+// matrix a in LDS (column-major), by the INV_T threads of a workgroup.  Row
+// interchanges are recorded and undone as column interchanges at the end.  A
+// zero or non-finite pivot sets *status.
 constexpr int INV_T = 256;
 template <int NP>
-__global__ void __launch_bounds__(INV_T) k_invert(double *M, int *status) {
+__device__ void gj_invert_lds(double *a, double *fcol, double *rrow, int *perm, int *sp, double *spiv, int *status) {
   constexpr int RP = NP <= 64 ? 64 : 128;  // rows per column group (whole waves)
   constexpr int CG = INV_T / RP;           // column groups
-  __shared__ double a[NP * NP];
-  __shared__ double fcol[NP], rrow[NP];
-  __shared__ int perm[NP];
-  __shared__ int sp;
-  __shared__ double spiv;
-  double *Mp = M + (int64_t)blockIdx.x * NP * NP;
+  static_assert(NP <= 128, "patch too large for the row groups");
   const int tid = threadIdx.x;
-  for (int e = tid; e < NP * NP; e += INV_T) a[e] = Mp[e];
-  __syncthreads();
   for (int k = 0; k < NP; ++k) {
     if (tid < 64) {  // pivot: largest |a[i][k]|, i >= k, first index on ties
       double best = -1.0;
@@ -159,12 +152,12 @@ __global__ void __launch_bounds__(INV_T) k_invert(double *M, int *status) {
         }
       }
       if (tid == 0) {
-        sp = bi;
+        *sp = bi;
         perm[k] = bi;
       }
     }
     __syncthreads();
-    const int p = sp;
+    const int p = *sp;
     if (p != k)
       for (int j = tid; j < NP; j += INV_T) {
         const double t = a[j * NP + k];
@@ -175,10 +168,10 @@ __global__ void __launch_bounds__(INV_T) k_invert(double *M, int *status) {
     if (tid == 0) {
       const double piv = a[k * NP + k];
       if (!(piv != 0.0) || !isfinite(piv)) atomicOr(status, 1);
-      spiv = 1.0 / piv;
+      *spiv = 1.0 / piv;
     }
     __syncthreads();
-    const double ip = spiv;
+    const double ip = *spiv;
     for (int e = tid; e < NP; e += INV_T) {
       fcol[e] = e == k ? 0.0 : a[k * NP + e];           // factors of the other rows
       rrow[e] = e == k ? ip : a[e * NP + k] * ip;       // the scaled pivot row
@@ -209,6 +202,21 @@ __global__ void __launch_bounds__(INV_T) k_invert(double *M, int *status) {
       }
     __syncthreads();
   }
+}
+
+// one workgroup per patch, the matrix in LDS (column-major like the storage)
+template <int NP>
+__global__ void __launch_bounds__(INV_T) k_invert(double *M, int *status) {
+  __shared__ double a[NP * NP];
+  __shared__ double fcol[NP], rrow[NP];
+  __shared__ int perm[NP];
+  __shared__ int sp;
+  __shared__ double spiv;
+  double *Mp = M + (int64_t)blockIdx.x * NP * NP;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < NP * NP; e += INV_T) a[e] = Mp[e];
+  __syncthreads();
+  gj_invert_lds<NP>(a, fcol, rrow, perm, &sp, &spiv, status);
   for (int e = tid; e < NP * NP; e += INV_T) Mp[e] = a[e];
 }
 
@@ -259,6 +267,174 @@ void dispatch(const LevelGeom &g, F &&f) {
 }
 
 inline unsigned grid_of(int64_t n, int per) { return (unsigned)std::max<int64_t>(1, (n + per - 1) / per); }
+
+// ------------------------------------------------------------------------
+// Space-time patches of a Taylor-Hood level (Sec. 4: the space-time ASM
+// smoother; the vertex-star patch with the whole slab in time).  Patch of
+// vertex v, per stage: the velocity components at the velocity nodes i with
+// |i_a - K v_a| < K and the pressure at the pressure nodes j with
+// |j_a - (K-1) v_a| < K-1; spatial slot li = field * BV + node for the
+// velocity, DIM BV + node for the pressure; absent slots (outside the
+// lattice, velocity Dirichlet) carry identity rows and columns.  The
+// space-time slot is q NPS + li (stage-major).  Same colours as above.
+template <int DIM, int K>
+struct Th {
+  static constexpr int W = 2 * K - 1, WP = 2 * K - 3;
+  static constexpr int BV = DIM == 3 ? W * W * W : W * W;
+  static constexpr int BP = DIM == 3 ? WP * WP * WP : WP * WP;
+  static constexpr int NPS = DIM * BV + BP;
+};
+
+// spatial unknown of slot li of the patch at vertex v (-1: absent); *w = 1 /
+// (number of patches holding it)
+template <int DIM, int K>
+__device__ __forceinline__ int64_t th_slot(const LevelGeom &g, const int v[3], int li, double *w) {
+  using P = Th<DIM, K>;
+  const bool vel = li < DIM * P::BV;
+  const int f = vel ? li / P::BV : DIM;
+  int nd = vel ? li % P::BV : li - DIM * P::BV;
+  const int deg = vel ? K : K - 1, wid = vel ? P::W : P::WP;
+  int64_t idx = 0, stride = 1;
+  bool bnd = false;
+  double wt = 1.0;
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    const int i = deg * v[a] - (deg - 1) + nd % wid;
+    nd /= wid;
+    const int last = deg * g.n[a];
+    if (i < 0 || i > last) return -1;
+    bnd = bnd || i == 0 || i == last;
+    if (i % deg) wt *= 0.5;
+    idx += stride * i;
+    stride *= last + 1;
+  }
+  if (vel && bnd) return -1;
+  *w = wt;
+  return vel ? f * g.Nv + idx : DIM * g.Nv + idx;
+}
+
+__device__ __forceinline__ void vertex_of(const LevelGeom &g, int64_t pid, int v[3]) {
+  v[0] = (int)(pid % (g.n[0] + 1));
+  const int64_t r = pid / (g.n[0] + 1);
+  v[1] = (int)(r % (g.n[1] + 1));
+  v[2] = (int)(r / (g.n[1] + 1));
+}
+
+template <int DIM, int K>
+__global__ void k_th_probe_set(LevelGeom g, Colour C, double *x, int j) {
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (q >= C.count) return;
+  int v[3];
+  int64_t pid;
+  patch_vertex(g, C, q, v, &pid);
+  double w;
+  const int64_t gi = th_slot<DIM, K>(g, v, j, &w);
+  if (gi >= 0) x[gi] = 1.0;
+}
+
+// column j of the spatial patch matrices of one colour from y = A e_j; with
+// nvel > 0, y holds only the first nvel rows (the velocity mass) and the
+// pressure rows are 0
+template <int DIM, int K>
+__global__ void k_th_probe_extract(LevelGeom g, Colour C, const double *y, int64_t nvel, double *M, int j) {
+  constexpr int NPS = Th<DIM, K>::NPS;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= C.count * NPS) return;
+  const int64_t q = t / NPS;
+  const int i = (int)(t % NPS);
+  int v[3];
+  int64_t pid;
+  patch_vertex(g, C, q, v, &pid);
+  double w;
+  const int64_t gi = th_slot<DIM, K>(g, v, i, &w);
+  double val = 0.0;
+  if (gi >= 0 && (nvel == 0 || gi < nvel)) val = y[gi];
+  M[pid * NPS * NPS + (int64_t)j * NPS + i] = val;
+}
+
+// space-time patch matrix G (x) M_s + tau I (x) A_s (identity on absent
+// slots), inverted in LDS; one workgroup per patch
+template <int DIM, int K, int Q>
+__global__ void __launch_bounds__(INV_T) k_th_form_invert(LevelGeom g, StageCoef G, double tau,
+                                                          const double *__restrict__ As,
+                                                          const double *__restrict__ Ms, double *Kinv,
+                                                          int *status) {
+  constexpr int NPS = Th<DIM, K>::NPS, NP = Q * NPS;
+  __shared__ double a[NP * NP];
+  __shared__ double fcol[NP], rrow[NP];
+  __shared__ int perm[NP];
+  __shared__ int present[NPS];
+  __shared__ int sp;
+  __shared__ double spiv;
+  const int64_t pid = blockIdx.x;
+  const int tid = threadIdx.x;
+  int v[3];
+  vertex_of(g, pid, v);
+  for (int i = tid; i < NPS; i += INV_T) {
+    double w;
+    present[i] = th_slot<DIM, K>(g, v, i, &w) >= 0;
+  }
+  __syncthreads();
+  const double *Ap = As + pid * NPS * NPS, *Mp = Ms + pid * NPS * NPS;
+  for (int e = tid; e < NP * NP; e += INV_T) {
+    const int c = e / NP, r = e % NP;  // column-major: a[c * NP + r]
+    const int qc = c / NPS, jc = c % NPS, qr = r / NPS, ir = r % NPS;
+    double val;
+    if (!present[jc] || !present[ir])
+      val = r == c ? 1.0 : 0.0;
+    else
+      val = G.c[qr * MFS_MAX_STAGES + qc] * Mp[jc * NPS + ir] + (qr == qc ? tau * Ap[jc * NPS + ir] : 0.0);
+    a[e] = val;
+  }
+  __syncthreads();
+  gj_invert_lds<NP>(a, fcol, rrow, perm, &sp, &spiv, status);
+  double *Kp = Kinv + pid * NP * NP;
+  for (int e = tid; e < NP * NP; e += INV_T) Kp[e] = a[e];
+}
+
+// x += omega W Kp^{-1} (b - t) on the space-time patches of one colour;
+// stage-major vectors of Q stages of N entries; NPP threads per patch
+template <int DIM, int K, int Q>
+__global__ void __launch_bounds__(APPLY_T) k_th_apply(LevelGeom g, Colour C, int64_t N,
+                                                      const double *__restrict__ Kinv,
+                                                      const double *__restrict__ b, const double *__restrict__ t,
+                                                      double *__restrict__ x, double omega) {
+  constexpr int NPS = Th<DIM, K>::NPS, NP = Q * NPS;
+  constexpr int NPP = NP <= 32 ? 32 : NP <= 64 ? 64 : 128, PPB = APPLY_T / NPP;
+  __shared__ double sr[PPB][NPP];
+  const int lp = threadIdx.x / NPP, i = threadIdx.x % NPP;
+  const int64_t q = blockIdx.x * (int64_t)PPB + lp;
+  const bool on = q < C.count;
+  int v[3] = {0, 0, 0};
+  int64_t pid = 0, gi = -1;
+  double w = 0.0;
+  if (on && i < NP) {
+    patch_vertex(g, C, q, v, &pid);
+    const int64_t gs = th_slot<DIM, K>(g, v, i % NPS, &w);
+    if (gs >= 0) gi = (i / NPS) * N + gs;
+  }
+  sr[lp][i] = gi >= 0 ? b[gi] - t[gi] : 0.0;
+  __syncthreads();
+  if (!on || i >= NP) return;
+  const double *Kp = Kinv + pid * NP * NP + i;
+  double y = 0;
+#pragma unroll 4
+  for (int j = 0; j < NP; ++j) y += Kp[(int64_t)j * NP] * sr[lp][j];
+  if (gi >= 0) x[gi] += omega * w * y;
+}
+
+// (K, Q) of the supported space-time patches: 2D, K = 2 with Q <= 3 and
+// K = 3 with Q <= 2 (at most 118 unknowns, inverted in LDS)
+template <typename F>
+void th_dispatch(const LevelGeom &g, int Q, F &&f) {
+  MFS_REQUIRE(g.dim == 2, MFS_EUNSUPPORTED, "space-time patches are built for 2D levels");
+  if (g.k == 2 && Q == 1) return f(std::integral_constant<int, 2>{}, std::integral_constant<int, 1>{});
+  if (g.k == 2 && Q == 2) return f(std::integral_constant<int, 2>{}, std::integral_constant<int, 2>{});
+  if (g.k == 2 && Q == 3) return f(std::integral_constant<int, 2>{}, std::integral_constant<int, 3>{});
+  if (g.k == 3 && Q == 1) return f(std::integral_constant<int, 3>{}, std::integral_constant<int, 1>{});
+  if (g.k == 3 && Q == 2) return f(std::integral_constant<int, 3>{}, std::integral_constant<int, 2>{});
+  MFS_REQUIRE(false, MFS_EUNSUPPORTED, "space-time patches: k = %d with %d stages not supported", g.k, Q);
+}
 
 }  // namespace
 
@@ -321,5 +497,53 @@ template void launch_asm_apply<double>(const LevelGeom &, const double *, int, c
                                        double *, double, hipStream_t);
 template void launch_asm_apply<float>(const LevelGeom &, const float *, int, const float *, const float *, float *,
                                       float, hipStream_t);
+
+int th_patch_size(const LevelGeom &g) {
+  const int w = 2 * g.k - 1, wp = 2 * g.k - 3;
+  return g.dim * (g.dim == 3 ? w * w * w : w * w) + (g.dim == 3 ? wp * wp * wp : wp * wp);
+}
+
+void launch_th_probe_set(const LevelGeom &g, double *x, int colour, int j, hipStream_t s) {
+  const Colour C = colour_of(g, colour);
+  th_dispatch(g, 1, [&](auto Kc, auto) {
+    hipLaunchKernelGGL((k_th_probe_set<2, decltype(Kc)::value>), dim3(grid_of(C.count, 256)), dim3(256), 0, s, g, C,
+                       x, j);
+  });
+  MFS_HIP(hipGetLastError());
+}
+
+void launch_th_probe_extract(const LevelGeom &g, const double *y, int64_t nvel, double *M, int colour, int j,
+                             hipStream_t s) {
+  const Colour C = colour_of(g, colour);
+  const int64_t n = C.count * th_patch_size(g);
+  th_dispatch(g, 1, [&](auto Kc, auto) {
+    hipLaunchKernelGGL((k_th_probe_extract<2, decltype(Kc)::value>), dim3(grid_of(n, 256)), dim3(256), 0, s, g, C, y,
+                       nvel, M, j);
+  });
+  MFS_HIP(hipGetLastError());
+}
+
+void launch_th_form_invert(const LevelGeom &g, int Q, const StageCoef &G, double tau, const double *As,
+                           const double *Ms, double *Kinv, int *status, hipStream_t s) {
+  const int64_t np = asm_patch_count(g);
+  MFS_REQUIRE(np <= 0x7fffffff, MFS_EINVAL, "too many patches");
+  th_dispatch(g, Q, [&](auto Kc, auto Qc) {
+    hipLaunchKernelGGL((k_th_form_invert<2, decltype(Kc)::value, decltype(Qc)::value>), dim3((unsigned)np),
+                       dim3(INV_T), 0, s, g, G, tau, As, Ms, Kinv, status);
+  });
+  MFS_HIP(hipGetLastError());
+}
+
+void launch_th_apply(const LevelGeom &g, int Q, int64_t N, const double *Kinv, int colour, const double *b,
+                     const double *t, double *x, double omega, hipStream_t s) {
+  const Colour C = colour_of(g, colour);
+  th_dispatch(g, Q, [&](auto Kc, auto Qc) {
+    constexpr int NP = decltype(Qc)::value * Th<2, decltype(Kc)::value>::NPS;
+    constexpr int PPB = APPLY_T / (NP <= 32 ? 32 : NP <= 64 ? 64 : 128);
+    hipLaunchKernelGGL((k_th_apply<2, decltype(Kc)::value, decltype(Qc)::value>), dim3(grid_of(C.count, PPB)),
+                       dim3(APPLY_T), 0, s, g, C, N, Kinv, b, t, x, omega);
+  });
+  MFS_HIP(hipGetLastError());
+}
 
 }  // namespace mfs

@@ -216,16 +216,17 @@ void launch_fill_dirichlet(const LevelGeom &g, T *dst_u, const T *src_u, hipStre
 
 // transfers between a fine level and the next coarser one
 // emb_host: host 1D embedding [F+1][kc+1] (h_embedding / p_embedding);
-// vectors: dim constrained velocity components, then `ncp` unconstrained
-// components (1: the equal-order pressure)
+// vectors: `ncu` constrained velocity components (default: dim), then `ncp`
+// unconstrained components (1: the equal-order pressure; ncu = 0, ncp = 1 on
+// the geometries of a pressure grid: a pressure of its own degree)
 template <typename T>
 void launch_prolongate_add(const LevelGeom &fine, const LevelGeom &coarse, bool h_transfer, const double *emb_host,
-                           T *dst_fine, const T *src_coarse, hipStream_t s, int ncp = 0);
+                           T *dst_fine, const T *src_coarse, hipStream_t s, int ncp = 0, int ncu = -1);
 // work: scratch of restrict_work_elems(fine, coarse, dim + ncp) elements for
 // the three-pass form (nullptr: one-pass gather)
 template <typename T>
 void launch_restrict(const LevelGeom &fine, const LevelGeom &coarse, bool h_transfer, const double *emb_host,
-                     T *dst_coarse, const T *src_fine, hipStream_t s, int ncp = 0, T *work = nullptr);
+                     T *dst_coarse, const T *src_fine, hipStream_t s, int ncp = 0, T *work = nullptr, int ncu = -1);
 int64_t restrict_work_elems(const LevelGeom &fine, const LevelGeom &coarse, int ncomp);
 
 // ----------------------------------------------------------------- Navier-Stokes (ns_kernels.hip)
@@ -290,6 +291,19 @@ struct StageCoef {
 template <typename T>
 void stage_mix(T *y, int64_t ldy, int no, const T *x, int64_t ldx, int ni, const StageCoef &C, T a, int64_t ne,
                int64_t ny, hipStream_t s);
+
+// space-time vertex patches of a Taylor-Hood level (asm_kernels.hip): probing
+// of the spatial patch matrices (Stokes operator, and the velocity mass with
+// nvel = dim Nv rows), the space-time patch inverses G (x) M_s + tau I (x) A_s,
+// and the additive update of one colour on stage-major vectors
+int th_patch_size(const LevelGeom &g);
+void launch_th_probe_set(const LevelGeom &g, double *x, int colour, int j, hipStream_t s);
+void launch_th_probe_extract(const LevelGeom &g, const double *y, int64_t nvel, double *M, int colour, int j,
+                             hipStream_t s);
+void launch_th_form_invert(const LevelGeom &g, int Q, const StageCoef &G, double tau, const double *As,
+                           const double *Ms, double *Kinv, int *status, hipStream_t s);
+void launch_th_apply(const LevelGeom &g, int Q, int64_t N, const double *Kinv, int colour, const double *b,
+                     const double *t, double *x, double omega, hipStream_t s);
 template <typename T>
 void vec_fill(T *x, T v, int64_t n, hipStream_t s);
 template <typename T>

@@ -276,10 +276,10 @@ __global__ void __launch_bounds__(256) k_restrict_pass3(TransferArgs a, int d, i
 }
 
 static TransferArgs make_targs(const LevelGeom &fine, const LevelGeom &coarse, bool h, const double *emb_host,
-                               int ncp) {
+                               int ncp, int ncu) {
   TransferArgs a{};
   a.dim = fine.dim;
-  a.ncu = fine.dim;
+  a.ncu = ncu < 0 ? fine.dim : ncu;
   a.ncp = ncp;
   a.kc = coarse.k;
   a.F = h ? 2 * coarse.k : fine.k;
@@ -297,8 +297,8 @@ static TransferArgs make_targs(const LevelGeom &fine, const LevelGeom &coarse, b
 
 template <typename T>
 void launch_prolongate_add(const LevelGeom &fine, const LevelGeom &coarse, bool h, const double *emb, T *dst_fine,
-                           const T *src_coarse, hipStream_t s, int ncp) {
-  const TransferArgs a = make_targs(fine, coarse, h, emb, ncp);
+                           const T *src_coarse, hipStream_t s, int ncp, int ncu) {
+  const TransferArgs a = make_targs(fine, coarse, h, emb, ncp, ncu);
   const dim3 grid((unsigned)((fine.Nv + 255) / 256)), block(256);
   if (fine.dim == 3 && a.kc == 1 && a.F == 2)
     hipLaunchKernelGGL((k_prolongate_add3<T, 1, 2>), grid, block, 0, s, a, dst_fine, src_coarse);
@@ -314,8 +314,8 @@ void launch_prolongate_add(const LevelGeom &fine, const LevelGeom &coarse, bool 
 }
 template <typename T>
 void launch_restrict(const LevelGeom &fine, const LevelGeom &coarse, bool h, const double *emb, T *dst_coarse,
-                     const T *src_fine, hipStream_t s, int ncp, T *work) {
-  const TransferArgs a = make_targs(fine, coarse, h, emb, ncp);
+                     const T *src_fine, hipStream_t s, int ncp, T *work, int ncu) {
+  const TransferArgs a = make_targs(fine, coarse, h, emb, ncp, ncu);
   if (work == nullptr) {  // single-pass gather (no scratch available)
     hipLaunchKernelGGL(k_restrict<T>, dim3((unsigned)((coarse.Nv + 255) / 256)), dim3(256), 0, s, a, dst_coarse,
                        src_fine);
@@ -362,12 +362,12 @@ int64_t restrict_work_elems(const LevelGeom &fine, const LevelGeom &coarse, int 
   return 2 * ncomp * std::max(a1, a2);
 }
 template void launch_prolongate_add<double>(const LevelGeom &, const LevelGeom &, bool, const double *, double *,
-                                            const double *, hipStream_t, int);
+                                            const double *, hipStream_t, int, int);
 template void launch_prolongate_add<float>(const LevelGeom &, const LevelGeom &, bool, const double *, float *,
-                                           const float *, hipStream_t, int);
+                                           const float *, hipStream_t, int, int);
 template void launch_restrict<double>(const LevelGeom &, const LevelGeom &, bool, const double *, double *,
-                                      const double *, hipStream_t, int, double *);
+                                      const double *, hipStream_t, int, double *, int);
 template void launch_restrict<float>(const LevelGeom &, const LevelGeom &, bool, const double *, float *,
-                                     const float *, hipStream_t, int, float *);
+                                     const float *, hipStream_t, int, float *, int);
 
 }  // namespace mfs
