@@ -172,6 +172,61 @@ def spacetime_section(mfs, torch, X, args):
     return out
 
 
+def stmg_section(mfs, torch, inputs, args):
+    """hp space-time multigrid of Sec. 4 (FGMRES + one V-cycle) on the stage
+    system of one slab: 2D unit square, 64^2 cells (between the 1,600 and
+    6,400 cells of the paper's first two refinements of Exp. 2, which is 2D),
+    vertex noise 0.1h, nu = 1e-3, tau = 1e-2, Q_k/Q_{k-1} with DG(1) in time,
+    k = 2, 3; a consistent right-hand side b = K x_t from a random x_t."""
+    out = {"workload": "2D Taylor-Hood Q_k/Q_k-1, 64^2 cells (vertex noise 0.1h, seed 0), DG(1) in time, "
+                       "nu = 1e-3, tau = 1e-2, b = K x_t, FGMRES(30) to rtol 1e-8, one V-cycle per iteration"}
+    n = [64, 64]
+    X = inputs.structured_vertices(2, n, noise=0.1, seed=0)
+    for k in (2, 3):
+        t0 = time.perf_counter()
+        h = mfs.mfs_stmg_setup(2, n, X, k, 1, 1e-3, 1e-2)
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t0
+        try:
+            lev = mfs.mfs_stmg_levels(h)
+            N = lev[0]["length"]
+            xt = torch.rand(N, dtype=torch.float64, device="cuda") * 2 - 1
+            b = torch.empty_like(xt)
+            mfs.mfs_stmg_vmult(h, 0, b, xt)  # Dirichlet rows of b = those of x_t
+            xt_h = xt.cpu()
+            y = torch.empty_like(xt)
+            for _ in range(2):
+                mfs.mfs_stmg_vcycle(h, y, b)
+            stream = torch.cuda.current_stream()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            reps = 10
+            e0.record(stream)
+            for _ in range(reps):
+                mfs.mfs_stmg_vcycle(h, y, b)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            vc = e0.elapsed_time(e1) * 1e-3 / reps
+            x = torch.zeros_like(xt)
+            info = mfs.mfs_stmg_solve(h, b, x, rtol=1e-8, maxit=400)
+            torch.cuda.synchronize()
+            S = lev[0]
+            nvel = N // S["Q"]
+            # velocity error against x_t (the pressure is fixed up to a constant per stage)
+            xs = x.cpu()
+            nu_ = 2 * (k * n[0] + 1) * (k * n[1] + 1)
+            vel = torch.cat([torch.arange(q * nvel, q * nvel + nu_) for q in range(S["Q"])])
+            err = float((xs[vel] - xt_h[vel]).norm() / xt_h[vel].norm())
+            out[f"Q{k}Q{k-1}_dg1"] = {
+                "n_dofs": N, "levels": [[L["n"][0], L["k"], L["Q"]] for L in lev], "setup_s": setup_s,
+                "vcycle_ms": vc * 1e3, "solve_s": info.seconds, "iterations": info.iterations,
+                "rel_residual": info.rel_residual, "status": info.status,
+                "ms_per_iteration": info.seconds / max(1, info.iterations) * 1e3, "velocity_rel_error": err}
+        finally:
+            mfs.mfs_stmg_destroy(h)
+    progress("space-time multigrid done")
+    return out
+
+
 def oracle_checks(mfs, torch, inputs):
     """Mixed-precision solves (FP32 multigrid inside FP64 FGMRES to 1e-8, as
     served) on small meshes, each compared with the oracle's sparse direct
@@ -794,6 +849,7 @@ def main():
                     help="launch the FP32 preconditioner kernel by kernel instead of replaying its recorded graph")
     ap.add_argument("--no-ns", action="store_true", help="skip the Navier-Stokes measurements")
     ap.add_argument("--no-hp", action="store_true", help="skip the hp measurements")
+    ap.add_argument("--no-stmg", action="store_true", help="skip the space-time multigrid measurements")
     ap.add_argument("--hp-n", type=int, default=32)
     ap.add_argument("--ns-n", type=int, default=128)
     ap.add_argument("--no-ns-refined", dest="ns_refined", action="store_false",
@@ -881,6 +937,8 @@ def main():
     }
     if not args.no_sweep:
         line["spacetime"] = line_spacetime
+    if not args.no_stmg:
+        line["stmg"] = stmg_section(mfs, torch, inputs, args)
     if args.prec == "f64" and k in FLOP_PER_DOF:
         # executed flops (counter-derived) where counted for this size, beside the model
         model = FLOP_PER_DOF[k] * main_run["N"]
