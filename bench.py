@@ -190,7 +190,8 @@ def stmg_section(mfs, torch, inputs, args):
         try:
             lev = mfs.mfs_stmg_levels(h)
             N = lev[0]["length"]
-            xt = torch.rand(N, dtype=torch.float64, device="cuda") * 2 - 1
+            gen = torch.Generator(device="cuda").manual_seed(7)
+            xt = torch.rand(N, dtype=torch.float64, device="cuda", generator=gen) * 2 - 1
             b = torch.empty_like(xt)
             mfs.mfs_stmg_vmult(h, 0, b, xt)  # Dirichlet rows of b = those of x_t
             xt_h = xt.cpu()
