@@ -350,6 +350,10 @@ int mfs_rhs(mfs_problem *p, const double *f_qp, const double *u_dirichlet, doubl
  * monolithic V-cycle; J is singular (constant pressures), so b must have
  * pressure rows summing to zero (true for b = J y); the pressure is returned
  * with zero nodal mean.
+ * Of `opts` (NULL: the setup options) a solve reads rtol, maxit,
+ * precond_precision and graphs; the restart length, the smoother (Chebyshev
+ * degree and range, relaxation), the Schur iterations and the hierarchy are
+ * those given to mfs_setup, whatever the other fields hold.
  */
 int mfs_solve(mfs_problem *p, const double *b, double *x, const mfs_options *opts, mfs_solve_info *info,
               void *stream);

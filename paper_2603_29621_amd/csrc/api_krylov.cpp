@@ -203,8 +203,7 @@ bool kr_process(mfs_problem &P, bool defer) {
   const int64_t n = sys_n(P);
   if (K.state == 1 || K.state == 3) {
     const double rr = std::sqrt(std::max(K.host[96], 0.0));
-    if (K.state == 1 && K.bnorm == 0.0) K.bnorm = rr;  // first call stores ||b - K x0||, replaced below
-    const double rel = K.bnorm > 0 ? rr / K.bnorm : 0.0;
+    const double rel = rr / K.bnorm;  // kr_begin set bnorm = ||b||, or 1 for b = 0
     if (rel <= K.rtol || K.iters >= K.maxit) {
       kr_finish(P, rel, rel <= K.rtol ? MFS_OK : MFS_ENOCONV);
       return false;
