@@ -626,7 +626,7 @@ class Problem:
 
 # ---------------------------------------------------------------- hp space-time multigrid
 def mfs_stmg_setup(dim, n, vertices, k, kt, nu, tau, relax_steps=2, relax_omega=0.5, stream=None):
-    """hp-STMG of the DG(kt) / Taylor-Hood Q_k stage system on one slab (2D)."""
+    """hp-STMG of the DG(kt) / Taylor-Hood Q_k stage system on one slab (2D, and 3D at k = 2)."""
     m, _keep = _mesh(dim, n, vertices)
     h = ctypes.c_void_p(0)
     _check(lib().mfs_stmg_setup(ctypes.byref(m), int(k), int(kt), float(nu), float(tau), int(relax_steps),
@@ -640,10 +640,10 @@ def mfs_stmg_levels(h):
     _check(lib().mfs_stmg_levels(h, 0, ctypes.byref(nl), None, None, None, None))
     out = []
     for level in range(nl.value):
-        n = (ctypes.c_int * 2)()
+        n = (ctypes.c_int * 3)(0, 0, 0)
         k, Q, ln = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int64(0)
         _check(lib().mfs_stmg_levels(h, level, None, n, ctypes.byref(k), ctypes.byref(Q), ctypes.byref(ln)))
-        out.append({"n": [n[0], n[1]], "k": k.value, "Q": Q.value, "length": ln.value})
+        out.append({"n": [v for v in n if v > 0], "k": k.value, "Q": Q.value, "length": ln.value})
     return out
 
 

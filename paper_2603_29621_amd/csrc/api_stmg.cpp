@@ -318,56 +318,68 @@ int mfs_stmg_setup(const mfs_mesh *mesh, int k, int kt, double nu, double tau, i
   return guard([&] {
     MFS_REQUIRE(mesh && out && mesh->vertices, MFS_EINVAL, "bad arguments");
     *out = nullptr;
-    MFS_REQUIRE(mesh->dim == 2, MFS_EUNSUPPORTED, "the space-time multigrid is built for 2D meshes");
-    MFS_REQUIRE(k == 2 || k == 3, MFS_EUNSUPPORTED, "velocity degree %d: 2 or 3 supported", k);
-    MFS_REQUIRE(kt >= 0 && kt + 1 <= (k == 2 ? 3 : 2), MFS_EUNSUPPORTED,
-                "temporal degree %d with velocity degree %d: patches of at most 118 unknowns", kt, k);
+    const int dim = mesh->dim;
+    MFS_REQUIRE(dim == 2 || dim == 3, MFS_EINVAL, "dim must be 2 or 3");
+    if (dim == 2) {
+      MFS_REQUIRE(k == 2 || k == 3, MFS_EUNSUPPORTED, "velocity degree %d: 2 or 3 supported in 2D", k);
+      MFS_REQUIRE(kt >= 0 && kt + 1 <= (k == 2 ? 3 : 2), MFS_EUNSUPPORTED,
+                  "temporal degree %d with velocity degree %d: patches of at most 118 unknowns in 2D", kt, k);
+    } else {
+      MFS_REQUIRE(k == 2 && kt >= 0 && kt <= 1, MFS_EUNSUPPORTED,
+                  "3D: velocity degree 2 with DG(0) or DG(1) in time (patches of 82 and 164 unknowns)");
+    }
     MFS_REQUIRE(nu > 0 && std::isfinite(nu) && tau > 0 && std::isfinite(tau), MFS_EINVAL,
                 "nu and tau must be positive");
     MFS_REQUIRE(relax_steps >= 0 && relax_steps <= 16 && std::isfinite(relax_omega), MFS_EINVAL,
                 "bad relaxation parameters");
-    MFS_REQUIRE(mesh->n[0] >= 1 && mesh->n[1] >= 1, MFS_EINVAL, "bad mesh size");
+    for (int a = 0; a < dim; ++a) MFS_REQUIRE(mesh->n[a] >= 1, MFS_EINVAL, "bad mesh size");
     std::unique_ptr<mfs_stmg> M(new mfs_stmg());
-    M->dim = 2;
+    M->dim = dim;
     M->tau = tau;
     M->omega = relax_omega;
     M->steps = relax_steps;
     M->s = S(stream);
     // level specifications
     struct Spec {
-      int n0, n1, k, kt, hl;
+      int n[3], k, kt, hl;
     };
-    std::vector<Spec> specs{{mesh->n[0], mesh->n[1], k, kt, 0}};
-    int kk = k, tt = kt, n0 = mesh->n[0], n1 = mesh->n[1], hl = 0;
-    while (kk > 2) specs.push_back({n0, n1, --kk, tt, hl});
-    while (tt > 0) specs.push_back({n0, n1, kk, --tt, hl});
-    while (n0 % 2 == 0 && n1 % 2 == 0 && n0 > 2 && n1 > 2) {
-      n0 /= 2;
-      n1 /= 2;
+    int nn[3] = {mesh->n[0], mesh->n[1], dim == 3 ? mesh->n[2] : 1};
+    std::vector<Spec> specs{{{nn[0], nn[1], nn[2]}, k, kt, 0}};
+    int kk = k, tt = kt, hl = 0;
+    while (kk > 2) specs.push_back({{nn[0], nn[1], nn[2]}, --kk, tt, hl});
+    while (tt > 0) specs.push_back({{nn[0], nn[1], nn[2]}, kk, --tt, hl});
+    while (true) {
+      bool ok = true;
+      for (int a = 0; a < dim; ++a) ok = ok && nn[a] % 2 == 0 && nn[a] > 2;
+      if (!ok) break;
+      for (int a = 0; a < dim; ++a) nn[a] /= 2;
       ++hl;
-      specs.push_back({n0, n1, kk, tt, hl});
+      specs.push_back({{nn[0], nn[1], nn[2]}, kk, tt, hl});
     }
     // spatial problems: one per distinct (mesh, degree)
     mfs_options o;
     mfs_default_options(&o);
     o.mg_levels = 0;
     o.pressure_offset = 1;
-    std::vector<double> X(mesh->vertices, mesh->vertices + (size_t)(mesh->n[0] + 1) * (mesh->n[1] + 1) * 2);
+    const int fx = mesh->n[0] + 1, fy = mesh->n[1] + 1;
     int last_k = -1, last_h = -1;
     for (const Spec &sp : specs) {
       StLevel L;
       if (sp.k != last_k || sp.hl != last_h) {
         const int f = 1 << sp.hl;  // keep the fine vertices of index divisible by 2^hl
-        std::vector<double> Xc((size_t)(sp.n0 + 1) * (sp.n1 + 1) * 2);
-        for (int j = 0; j <= sp.n1; ++j)
-          for (int i = 0; i <= sp.n0; ++i)
-            for (int a = 0; a < 2; ++a)
-              Xc[((size_t)j * (sp.n0 + 1) + i) * 2 + a] = X[((size_t)j * f * (mesh->n[0] + 1) + i * f) * 2 + a];
+        const int cx = sp.n[0] + 1, cy = sp.n[1] + 1, cz = dim == 3 ? sp.n[2] + 1 : 1;
+        std::vector<double> Xc((size_t)cx * cy * cz * dim);
+        for (int l = 0; l < cz; ++l)
+          for (int j = 0; j < cy; ++j)
+            for (int i = 0; i < cx; ++i)
+              for (int a = 0; a < dim; ++a)
+                Xc[(((size_t)l * cy + j) * cx + i) * dim + a] =
+                    mesh->vertices[(((size_t)l * f * fy + (size_t)j * f) * fx + (size_t)i * f) * dim + a];
         mfs_mesh mc{};
-        mc.dim = 2;
-        mc.n[0] = sp.n0;
-        mc.n[1] = sp.n1;
-        mc.n[2] = 1;
+        mc.dim = dim;
+        mc.n[0] = sp.n[0];
+        mc.n[1] = sp.n[1];
+        mc.n[2] = sp.n[2];
         mc.vertices = Xc.data();
         mfs_problem *p = nullptr;
         const int rc = mfs_setup(&mc, sp.k, nu, &o, stream, &p);
@@ -394,7 +406,7 @@ int mfs_stmg_setup(const mfs_mesh *mesh, int k, int kt, double nu, double tau, i
       L.b = M->alloc<double>(n);
       L.r = M->alloc<double>(n);
       L.t = M->alloc<double>(n);
-      L.work = M->alloc<double>((int64_t)L.Q * 2 * M->sp[L.sp]->L[0].g.Nv);
+      L.work = M->alloc<double>((int64_t)L.Q * dim * M->sp[L.sp]->L[0].g.Nv);
       if (l + 1 < nl) {
         const StLevel &C = M->lev[l + 1];
         const LevelGeom &gf = M->sp[L.sp]->L[0].g, &gc = M->sp[C.sp]->L[0].g;
@@ -438,10 +450,8 @@ int mfs_stmg_levels(const mfs_stmg *m, int level, int *n_levels, int *n, int *k,
                 (int)m->lev.size());
     const StLevel &L = m->lev[level];
     const LevelGeom &g = m->sp[L.sp]->L[0].g;
-    if (n) {
-      n[0] = g.n[0];
-      n[1] = g.n[1];
-    }
+    if (n)
+      for (int a = 0; a < g.dim; ++a) n[a] = g.n[a];
     if (k) *k = g.k;
     if (Q) *Q = L.Q;
     if (length) *length = (int64_t)L.Q * L.N;

@@ -121,15 +121,16 @@ __global__ void k_probe_extract(LevelGeom g, Colour C, const double *y, double *
 }
 
 // In-place Gauss-Jordan inversion with partial (row) pivoting of the NP x NP
-// matrix a in LDS (column-major), by the INV_T threads of a workgroup.  Row
+// matrix a (column-major; in LDS, or in global memory when it does not fit),
+// by the INV_T threads of a workgroup.  Row
 // interchanges are recorded and undone as column interchanges at the end.  A
 // zero or non-finite pivot sets *status.
 constexpr int INV_T = 256;
 template <int NP>
 __device__ void gj_invert_lds(double *a, double *fcol, double *rrow, int *perm, int *sp, double *spiv, int *status) {
-  constexpr int RP = NP <= 64 ? 64 : 128;  // rows per column group (whole waves)
-  constexpr int CG = INV_T / RP;           // column groups
-  static_assert(NP <= 128, "patch too large for the row groups");
+  constexpr int RP = NP <= 64 ? 64 : NP <= 128 ? 128 : 256;  // rows per column group (whole waves)
+  constexpr int CG = INV_T / RP;                             // column groups
+  static_assert(NP <= 256, "patch too large for the row groups");
   const int tid = threadIdx.x;
   for (int k = 0; k < NP; ++k) {
     if (tid < 64) {  // pivot: largest |a[i][k]|, i >= k, first index on ties
@@ -360,7 +361,8 @@ __global__ void __launch_bounds__(INV_T) k_th_form_invert(LevelGeom g, StageCoef
                                                           const double *__restrict__ Ms, double *Kinv,
                                                           int *status) {
   constexpr int NPS = Th<DIM, K>::NPS, NP = Q * NPS;
-  __shared__ double a[NP * NP];
+  constexpr bool IN_LDS = NP <= 128;  // 128 KB; larger patches are inverted in place in global memory
+  __shared__ double lds[IN_LDS ? NP * NP : 1];
   __shared__ double fcol[NP], rrow[NP];
   __shared__ int perm[NP];
   __shared__ int present[NPS];
@@ -376,6 +378,8 @@ __global__ void __launch_bounds__(INV_T) k_th_form_invert(LevelGeom g, StageCoef
   }
   __syncthreads();
   const double *Ap = As + pid * NPS * NPS, *Mp = Ms + pid * NPS * NPS;
+  double *Kp = Kinv + pid * NP * NP;
+  double *a = IN_LDS ? lds : Kp;
   for (int e = tid; e < NP * NP; e += INV_T) {
     const int c = e / NP, r = e % NP;  // column-major: a[c * NP + r]
     const int qc = c / NPS, jc = c % NPS, qr = r / NPS, ir = r % NPS;
@@ -388,8 +392,8 @@ __global__ void __launch_bounds__(INV_T) k_th_form_invert(LevelGeom g, StageCoef
   }
   __syncthreads();
   gj_invert_lds<NP>(a, fcol, rrow, perm, &sp, &spiv, status);
-  double *Kp = Kinv + pid * NP * NP;
-  for (int e = tid; e < NP * NP; e += INV_T) Kp[e] = a[e];
+  if constexpr (IN_LDS)
+    for (int e = tid; e < NP * NP; e += INV_T) Kp[e] = a[e];
 }
 
 // x += omega W Kp^{-1} (b - t) on the space-time patches of one colour;
@@ -400,7 +404,7 @@ __global__ void __launch_bounds__(APPLY_T) k_th_apply(LevelGeom g, Colour C, int
                                                       const double *__restrict__ b, const double *__restrict__ t,
                                                       double *__restrict__ x, double omega) {
   constexpr int NPS = Th<DIM, K>::NPS, NP = Q * NPS;
-  constexpr int NPP = NP <= 32 ? 32 : NP <= 64 ? 64 : 128, PPB = APPLY_T / NPP;
+  constexpr int NPP = NP <= 32 ? 32 : NP <= 64 ? 64 : NP <= 128 ? 128 : 256, PPB = APPLY_T / NPP;
   __shared__ double sr[PPB][NPP];
   const int lp = threadIdx.x / NPP, i = threadIdx.x % NPP;
   const int64_t q = blockIdx.x * (int64_t)PPB + lp;
@@ -423,17 +427,26 @@ __global__ void __launch_bounds__(APPLY_T) k_th_apply(LevelGeom g, Colour C, int
   if (gi >= 0) x[gi] += omega * w * y;
 }
 
-// (K, Q) of the supported space-time patches: 2D, K = 2 with Q <= 3 and
-// K = 3 with Q <= 2 (at most 118 unknowns, inverted in LDS)
+// (DIM, K, Q) of the supported space-time patches: 2D with K = 2, Q <= 3 and
+// K = 3, Q <= 2 (at most 118 unknowns, inverted in LDS); 3D with K = 2,
+// Q <= 2 (82 and 164 unknowns; 164 inverted in global memory)
 template <typename F>
 void th_dispatch(const LevelGeom &g, int Q, F &&f) {
-  MFS_REQUIRE(g.dim == 2, MFS_EUNSUPPORTED, "space-time patches are built for 2D levels");
-  if (g.k == 2 && Q == 1) return f(std::integral_constant<int, 2>{}, std::integral_constant<int, 1>{});
-  if (g.k == 2 && Q == 2) return f(std::integral_constant<int, 2>{}, std::integral_constant<int, 2>{});
-  if (g.k == 2 && Q == 3) return f(std::integral_constant<int, 2>{}, std::integral_constant<int, 3>{});
-  if (g.k == 3 && Q == 1) return f(std::integral_constant<int, 3>{}, std::integral_constant<int, 1>{});
-  if (g.k == 3 && Q == 2) return f(std::integral_constant<int, 3>{}, std::integral_constant<int, 2>{});
-  MFS_REQUIRE(false, MFS_EUNSUPPORTED, "space-time patches: k = %d with %d stages not supported", g.k, Q);
+  using I2 = std::integral_constant<int, 2>;
+  using I3 = std::integral_constant<int, 3>;
+  using I1 = std::integral_constant<int, 1>;
+  if (g.dim == 2) {
+    if (g.k == 2 && Q == 1) return f(I2{}, I2{}, I1{});
+    if (g.k == 2 && Q == 2) return f(I2{}, I2{}, I2{});
+    if (g.k == 2 && Q == 3) return f(I2{}, I2{}, I3{});
+    if (g.k == 3 && Q == 1) return f(I2{}, I3{}, I1{});
+    if (g.k == 3 && Q == 2) return f(I2{}, I3{}, I2{});
+  } else {
+    if (g.k == 2 && Q == 1) return f(I3{}, I2{}, I1{});
+    if (g.k == 2 && Q == 2) return f(I3{}, I2{}, I2{});
+  }
+  MFS_REQUIRE(false, MFS_EUNSUPPORTED, "space-time patches: dim %d, k = %d with %d stages not supported", g.dim,
+              g.k, Q);
 }
 
 }  // namespace
@@ -505,9 +518,9 @@ int th_patch_size(const LevelGeom &g) {
 
 void launch_th_probe_set(const LevelGeom &g, double *x, int colour, int j, hipStream_t s) {
   const Colour C = colour_of(g, colour);
-  th_dispatch(g, 1, [&](auto Kc, auto) {
-    hipLaunchKernelGGL((k_th_probe_set<2, decltype(Kc)::value>), dim3(grid_of(C.count, 256)), dim3(256), 0, s, g, C,
-                       x, j);
+  th_dispatch(g, 1, [&](auto D, auto Kc, auto) {
+    hipLaunchKernelGGL((k_th_probe_set<decltype(D)::value, decltype(Kc)::value>), dim3(grid_of(C.count, 256)),
+                       dim3(256), 0, s, g, C, x, j);
   });
   MFS_HIP(hipGetLastError());
 }
@@ -516,9 +529,9 @@ void launch_th_probe_extract(const LevelGeom &g, const double *y, int64_t nvel, 
                              hipStream_t s) {
   const Colour C = colour_of(g, colour);
   const int64_t n = C.count * th_patch_size(g);
-  th_dispatch(g, 1, [&](auto Kc, auto) {
-    hipLaunchKernelGGL((k_th_probe_extract<2, decltype(Kc)::value>), dim3(grid_of(n, 256)), dim3(256), 0, s, g, C, y,
-                       nvel, M, j);
+  th_dispatch(g, 1, [&](auto D, auto Kc, auto) {
+    hipLaunchKernelGGL((k_th_probe_extract<decltype(D)::value, decltype(Kc)::value>), dim3(grid_of(n, 256)),
+                       dim3(256), 0, s, g, C, y, nvel, M, j);
   });
   MFS_HIP(hipGetLastError());
 }
@@ -527,9 +540,9 @@ void launch_th_form_invert(const LevelGeom &g, int Q, const StageCoef &G, double
                            const double *Ms, double *Kinv, int *status, hipStream_t s) {
   const int64_t np = asm_patch_count(g);
   MFS_REQUIRE(np <= 0x7fffffff, MFS_EINVAL, "too many patches");
-  th_dispatch(g, Q, [&](auto Kc, auto Qc) {
-    hipLaunchKernelGGL((k_th_form_invert<2, decltype(Kc)::value, decltype(Qc)::value>), dim3((unsigned)np),
-                       dim3(INV_T), 0, s, g, G, tau, As, Ms, Kinv, status);
+  th_dispatch(g, Q, [&](auto D, auto Kc, auto Qc) {
+    hipLaunchKernelGGL((k_th_form_invert<decltype(D)::value, decltype(Kc)::value, decltype(Qc)::value>),
+                       dim3((unsigned)np), dim3(INV_T), 0, s, g, G, tau, As, Ms, Kinv, status);
   });
   MFS_HIP(hipGetLastError());
 }
@@ -537,11 +550,12 @@ void launch_th_form_invert(const LevelGeom &g, int Q, const StageCoef &G, double
 void launch_th_apply(const LevelGeom &g, int Q, int64_t N, const double *Kinv, int colour, const double *b,
                      const double *t, double *x, double omega, hipStream_t s) {
   const Colour C = colour_of(g, colour);
-  th_dispatch(g, Q, [&](auto Kc, auto Qc) {
-    constexpr int NP = decltype(Qc)::value * Th<2, decltype(Kc)::value>::NPS;
-    constexpr int PPB = APPLY_T / (NP <= 32 ? 32 : NP <= 64 ? 64 : 128);
-    hipLaunchKernelGGL((k_th_apply<2, decltype(Kc)::value, decltype(Qc)::value>), dim3(grid_of(C.count, PPB)),
-                       dim3(APPLY_T), 0, s, g, C, N, Kinv, b, t, x, omega);
+  th_dispatch(g, Q, [&](auto D, auto Kc, auto Qc) {
+    constexpr int DD = decltype(D)::value, KK = decltype(Kc)::value, QQ = decltype(Qc)::value;
+    constexpr int NP = QQ * Th<DD, KK>::NPS;
+    constexpr int PPB = APPLY_T / (NP <= 32 ? 32 : NP <= 64 ? 64 : NP <= 128 ? 128 : 256);
+    hipLaunchKernelGGL((k_th_apply<DD, KK, QQ>), dim3(grid_of(C.count, PPB)), dim3(APPLY_T), 0, s, g, C, N, Kinv, b,
+                       t, x, omega);
   });
   MFS_HIP(hipGetLastError());
 }
