@@ -136,6 +136,7 @@ struct StLevel {
   std::vector<double> G;
   double *x = nullptr, *b = nullptr, *r = nullptr, *t = nullptr, *work = nullptr;
   double *Kinv = nullptr;  // space-time patch inverses (all levels but the coarsest)
+  double *rw_v = nullptr, *rw_p = nullptr;  // scratch of the three-pass restrictions to the next level
   int kind = 0;            // transfer to the next level: 1 time, 2 space
   bool h = false;
   std::vector<double> emb_v, emb_p;
@@ -213,8 +214,8 @@ void vcycle(mfs_stmg &M, int l, hipStream_t s) {
     for (int q = 0; q < L.Q; ++q) {
       const double *rf = L.r + q * L.N;
       double *bc = C.b + q * C.N;
-      launch_restrict<double>(g, gc, L.h, L.emb_v.data(), bc, rf, s);
-      launch_restrict<double>(pf, pc, L.h, L.emb_p.data(), bc + g.dim * gc.Nv, rf + g.dim * g.Nv, s, 1, nullptr, 0);
+      launch_restrict<double>(g, gc, L.h, L.emb_v.data(), bc, rf, s, 0, L.rw_v);
+      launch_restrict<double>(pf, pc, L.h, L.emb_p.data(), bc + g.dim * gc.Nv, rf + g.dim * g.Nv, s, 1, L.rw_p, 0);
     }
   }
   vcycle(M, l + 1, s);
@@ -418,6 +419,8 @@ int mfs_stmg_setup(const mfs_mesh *mesh, int k, int kt, double nu, double tau, i
           L.h = gc.n[0] != gf.n[0];
           L.emb_v = L.h ? h_embedding(gc.k) : p_embedding(gf.k, gc.k);
           L.emb_p = L.h ? h_embedding(gc.kp) : p_embedding(gf.kp, gc.kp);
+          L.rw_v = M->alloc<double>(restrict_work_elems(gf, gc, dim));
+          L.rw_p = M->alloc<double>(restrict_work_elems(M->pg[L.sp], M->pg[C.sp], 1));
         }
       }
     }
