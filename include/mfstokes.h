@@ -438,8 +438,8 @@ int mfs_st_stage_transfer(mfs_problem *p, int q_out, int q_in, const double *C, 
  * (Q = kt + 1 stages on the Gauss points of the slab) and Taylor-Hood
  * Q_k / Q_{k-1} in space: FGMRES preconditioned by one V-cycle.
  * Levels (the paper's two coarsening rules, no geometric coarsening in time):
- * spatial degree k -> 2, then temporal degree kt -> 0, then h-coarsening
- * while both n are even and larger than 2.  Transfers: per stage the
+ * spatial degree k -> 2, then h-coarsening while every n is even and larger
+ * than 2, then the temporal degree kt -> 0 on the coarsest mesh.  Transfers: per stage the
  * constrained velocity and unconstrained pressure Lagrange transfers
  * (restriction: their transpose); in time the coarse DG polynomial at the
  * fine nodes, restricted by M_c^{-1} P^T M_f.  Smoother: relax_steps

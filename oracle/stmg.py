@@ -9,12 +9,17 @@ Readings where the paper is silent:
 * Spaces: Taylor-Hood Q_k / Q_{k-1} (continuous pressure) on every level, the
   pair the spatial operators here are built for (the paper names the
   discontinuous-pressure pair as one option among others).
-* Level order, by the two rules of Sec. 4 (polynomial before geometric; space
-  before time) with no geometric coarsening in time (time marching): first
-  the spatial degree k -> k-1 -> ... -> 2 at the temporal degree kt, then
-  the temporal degree kt -> kt-1 -> ... -> 0 (DG(0), one stage), then h in
-  space (n halved while every n is even and larger than ``coarse_min``; a
-  coarse mesh keeps the fine vertices of even index).
+* Level order, by the two rules of Sec. 4 (space before time; polynomial
+  before geometric) with no geometric coarsening in time (time marching):
+  all of space first, the spatial degree k -> k-1 -> ... -> 2 and then h
+  (n halved while every n is even and larger than ``coarse_min``; a coarse
+  mesh keeps the fine vertices of even index), all at the temporal degree
+  kt; then on the coarsest mesh the temporal degree kt -> ... -> 0 (DG(0),
+  one stage).  Lowering the temporal degree on the fine mesh instead (space
+  p, time p, then h) leaves the modes that are smooth in space and of high
+  degree in time to neither the spatially local smoother nor a coarse level:
+  on 2D Q2/Q1 with DG(1) it took 34, 87 and 150 FGMRES iterations on 16^2,
+  32^2 and 64^2 cells (nu = 1) where this order takes 12, 14 and 17.
 * Spatial transfer, per stage: the constrained Lagrange transfer of the
   velocity multigrid for every component, and the same transfer without
   constraints for the pressure of degree k-1.  Temporal transfer: the coarse
@@ -22,14 +27,14 @@ Readings where the paper is silent:
   Restriction: the transpose in space; in time M_c^{-1} P_tau^T M_f, the L2
   projection onto the coarse temporal space, because the stage rows are
   mass-scaled (M_Q^{-1} from the left).  With it the coarse temporal operator
-  is the Galerkin one.  On five small cases (2D 8^2 and 16^2, 3D 4^3;
-  k = 2, 3; kt = 1, 2) the plain transpose took 21 to over 200 FGMRES
-  iterations, this restriction 15 to 55.
+  is the Galerkin one.  (With the level order above the plain transpose
+  takes the same iteration counts within one on small cases; with time
+  coarsened on the fine mesh it took up to 4x more.)
 * Smoother: additive Schwarz over vertex-star patches with the temporal
   direction whole (the paper names cell patches and vertex-star patches;
   with the continuous pressure here the cell patches share every pressure
-  node, and their smoother diverged undamped and needed 40-200 iterations
-  damped).  Patch v holds, in every stage, every velocity component at the
+  node, and their smoother diverged undamped and needed 19-53 iterations
+  damped, against 10-15 for these patches, on five small 2D and 3D cases).  Patch v holds, in every stage, every velocity component at the
   velocity nodes i with |i_a - k v_a| < k and the pressure at the pressure
   nodes j with |j_a - (k-1) v_a| < k-1 (the open vertex star), Dirichlet
   rows left out; its matrix is the principal submatrix of the level
@@ -65,12 +70,12 @@ def level_specs(n, k, kt, coarse_min=2):
     while kk > 2:
         kk -= 1
         out.append((list(n), kk, tt, hl))
-    while tt > 0:
-        tt -= 1
-        out.append((list(n), kk, tt, hl))
     while all(v % 2 == 0 and v > max(1, coarse_min) for v in n):
         n = [v // 2 for v in n]
         hl += 1
+        out.append((list(n), kk, tt, hl))
+    while tt > 0:
+        tt -= 1
         out.append((list(n), kk, tt, hl))
     return out
 

@@ -2,10 +2,12 @@
 // Sec. 4: FGMRES preconditioned by one V-cycle on the Kronecker operator
 // G_Q (x) M + tau I_Q (x) A of eq. (proceedings-kronecker).
 //
-// Levels, by the two coarsening rules of Sec. 4 (polynomial before
-// geometric, space before time) without geometric coarsening in time: the
-// spatial degree k -> 2 at the temporal degree kt, then kt -> 0, then h in
-// space while every n is even and larger than 2.  Every level is a
+// Levels, by the two coarsening rules of Sec. 4 (space before time,
+// polynomial before geometric) without geometric coarsening in time: the
+// spatial degree k -> 2, then h while every n is even and larger than 2,
+// both at the temporal degree kt, then kt -> 0 on the coarsest mesh (modes
+// smooth in space and of high degree in time then meet a coarse level before
+// the temporal degree drops).  Every level is a
 // Taylor-Hood space with its own operator-only problem (the spatial
 // operators, the velocity mass, the Kronecker operator of api_spacetime.cpp).
 // Transfers: per stage the constrained velocity transfer and the same
@@ -348,7 +350,6 @@ int mfs_stmg_setup(const mfs_mesh *mesh, int k, int kt, double nu, double tau, i
     std::vector<Spec> specs{{{nn[0], nn[1], nn[2]}, k, kt, 0}};
     int kk = k, tt = kt, hl = 0;
     while (kk > 2) specs.push_back({{nn[0], nn[1], nn[2]}, --kk, tt, hl});
-    while (tt > 0) specs.push_back({{nn[0], nn[1], nn[2]}, kk, --tt, hl});
     while (true) {
       bool ok = true;
       for (int a = 0; a < dim; ++a) ok = ok && nn[a] % 2 == 0 && nn[a] > 2;
@@ -357,6 +358,7 @@ int mfs_stmg_setup(const mfs_mesh *mesh, int k, int kt, double nu, double tau, i
       ++hl;
       specs.push_back({{nn[0], nn[1], nn[2]}, kk, tt, hl});
     }
+    while (tt > 0) specs.push_back({{nn[0], nn[1], nn[2]}, kk, --tt, hl});
     // spatial problems: one per distinct (mesh, degree)
     mfs_options o;
     mfs_default_options(&o);

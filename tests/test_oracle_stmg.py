@@ -15,11 +15,12 @@ from oracle.fem import Space, assemble_stokes, constrain
 
 
 def test_level_order():
-    """Spatial p first, then temporal p, then spatial h (no geometric
-    coarsening in time); written out by hand from the two rules."""
+    """Space first (p, then h), then the temporal degree on the coarsest mesh
+    (no geometric coarsening in time); written out by hand from the two
+    rules."""
     got = [(tuple(n), k, kt) for n, k, kt, _ in stmg.level_specs([8, 4], 4, 2)]
-    # h stops once a direction has coarse_min = 2 cells
-    assert got == [((8, 4), 4, 2), ((8, 4), 3, 2), ((8, 4), 2, 2), ((8, 4), 2, 1), ((8, 4), 2, 0),
+    # h stops once a direction has coarse_min = 2 cells; time on the coarsest mesh
+    assert got == [((8, 4), 4, 2), ((8, 4), 3, 2), ((8, 4), 2, 2), ((4, 2), 2, 2), ((4, 2), 2, 1),
                    ((4, 2), 2, 0)]
     assert [(tuple(n), k, kt) for n, k, kt, _ in stmg.level_specs([3, 3], 2, 0)] == [((3, 3), 2, 0)]
 
@@ -112,7 +113,7 @@ def test_coarse_correction_galerkin():
     Cartesian hierarchy (Galerkin in space and time) the restricted residual
     after it vanishes: R_tot (b - K P_tot x_c) = 0."""
     H = stmg.STMG(2, [4, 4], inputs.structured_vertices(2, [4, 4], noise=0.0), 3, 1, nu=0.9, tau=0.2, steps=0)
-    assert [s[1:3] for s in H.specs] == [(3, 1), (2, 1), (2, 0), (2, 0)]
+    assert [(s[0], s[1], s[2]) for s in H.specs] == [([4, 4], 3, 1), ([4, 4], 2, 1), ([2, 2], 2, 1), ([2, 2], 2, 0)]
     rng = np.random.default_rng(4)
     N = H.K[0].shape[0]
     xt = rng.uniform(-1, 1, N)
