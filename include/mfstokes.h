@@ -451,10 +451,9 @@ int mfs_st_stage_transfer(mfs_problem *p, int q_out, int q_in, const double *C, 
  * number of patches holding each unknown.  Coarsest level: the dense inverse
  * with the first pressure node of every stage pinned to zero.
  *
- * mfs_stmg_setup: structured meshes (mfs_mesh, host vertices); in 2D k = 2
- * with kt <= 2 or k = 3 with kt <= 1, in 3D k = 2 with kt <= 1 (patches of
- * at most 118 unknowns in 2D, 164 in 3D); nu, tau > 0, relax_steps in
- * [0, 16].  Builds every level on the device (library-owned memory;
+ * mfs_stmg_setup: structured meshes (mfs_mesh, host vertices); k = 2, 3 in
+ * 2D and k = 2 in 3D, with kt <= 2 (patches of at most 177 unknowns in 2D,
+ * 246 in 3D); nu, tau > 0, relax_steps in [0, 16].  Builds every level on the device (library-owned memory;
  * MFS_EUNSUPPORTED outside these cases); synchronous.
  * mfs_stmg_levels: number of levels, and for `level` its cells n[dim],
  * velocity degree k, stages Q and vector length Q (dim n_u + n_p) (any

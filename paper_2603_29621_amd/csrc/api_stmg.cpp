@@ -325,12 +325,10 @@ int mfs_stmg_setup(const mfs_mesh *mesh, int k, int kt, double nu, double tau, i
     MFS_REQUIRE(dim == 2 || dim == 3, MFS_EINVAL, "dim must be 2 or 3");
     if (dim == 2) {
       MFS_REQUIRE(k == 2 || k == 3, MFS_EUNSUPPORTED, "velocity degree %d: 2 or 3 supported in 2D", k);
-      MFS_REQUIRE(kt >= 0 && kt + 1 <= (k == 2 ? 3 : 2), MFS_EUNSUPPORTED,
-                  "temporal degree %d with velocity degree %d: patches of at most 118 unknowns in 2D", kt, k);
     } else {
-      MFS_REQUIRE(k == 2 && kt >= 0 && kt <= 1, MFS_EUNSUPPORTED,
-                  "3D: velocity degree 2 with DG(0) or DG(1) in time (patches of 82 and 164 unknowns)");
+      MFS_REQUIRE(k == 2, MFS_EUNSUPPORTED, "3D: velocity degree 2 supported (patches of 82 unknowns per stage)");
     }
+    MFS_REQUIRE(kt >= 0 && kt <= 2, MFS_EUNSUPPORTED, "temporal degree %d: DG(0) to DG(2) supported", kt);
     MFS_REQUIRE(nu > 0 && std::isfinite(nu) && tau > 0 && std::isfinite(tau), MFS_EINVAL,
                 "nu and tau must be positive");
     MFS_REQUIRE(relax_steps >= 0 && relax_steps <= 16 && std::isfinite(relax_omega), MFS_EINVAL,

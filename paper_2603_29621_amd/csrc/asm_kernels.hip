@@ -427,9 +427,9 @@ __global__ void __launch_bounds__(APPLY_T) k_th_apply(LevelGeom g, Colour C, int
   if (gi >= 0) x[gi] += omega * w * y;
 }
 
-// (DIM, K, Q) of the supported space-time patches: 2D with K = 2, Q <= 3 and
-// K = 3, Q <= 2 (at most 118 unknowns, inverted in LDS); 3D with K = 2,
-// Q <= 2 (82 and 164 unknowns; 164 inverted in global memory)
+// (DIM, K, Q) of the supported space-time patches: 2D with K = 2, 3 and
+// Q <= 3 (at most 177 unknowns), 3D with K = 2 and Q <= 3 (82, 164, 246);
+// patches of more than 128 unknowns are inverted in global memory
 template <typename F>
 void th_dispatch(const LevelGeom &g, int Q, F &&f) {
   using I2 = std::integral_constant<int, 2>;
@@ -441,9 +441,11 @@ void th_dispatch(const LevelGeom &g, int Q, F &&f) {
     if (g.k == 2 && Q == 3) return f(I2{}, I2{}, I3{});
     if (g.k == 3 && Q == 1) return f(I2{}, I3{}, I1{});
     if (g.k == 3 && Q == 2) return f(I2{}, I3{}, I2{});
+    if (g.k == 3 && Q == 3) return f(I2{}, I3{}, I3{});
   } else {
     if (g.k == 2 && Q == 1) return f(I3{}, I2{}, I1{});
     if (g.k == 2 && Q == 2) return f(I3{}, I2{}, I2{});
+    if (g.k == 2 && Q == 3) return f(I3{}, I2{}, I3{});
   }
   MFS_REQUIRE(false, MFS_EUNSUPPORTED, "space-time patches: dim %d, k = %d with %d stages not supported", g.dim,
               g.k, Q);

@@ -37,9 +37,11 @@ def relerr(y, ref):
 
 # (n, k, kt, noise, tau): three and four levels, a p-level in space (k = 3),
 # three stages, one stage (spatial hierarchy only), odd cell counts
-# 3D: DG(1) with patches of 164 unknowns (inverted in global memory), DG(0)
+# 3D: DG(1) with patches of 164 unknowns (inverted in global memory), DG(0);
+# 2D k = 3 with DG(2) (177) and 3D DG(2) (246), also in global memory
 CASES = [([8, 8], 2, 1, 0.1, 0.05), ([4, 6], 3, 1, 0.2, 0.3), ([8, 4], 2, 2, 0.1, 0.05), ([6, 6], 2, 0, 0.2, 1.0),
-         ([4, 4, 4], 2, 1, 0.1, 0.05), ([8, 4, 4], 2, 0, 0.2, 0.5)]
+         ([4, 4, 4], 2, 1, 0.1, 0.05), ([8, 4, 4], 2, 0, 0.2, 0.5), ([4, 4], 3, 2, 0.1, 0.1),
+         ([4, 4, 4], 2, 2, 0.1, 0.05)]
 
 
 def _pair(n, k, kt, noise, tau, nu=0.7):
@@ -115,7 +117,7 @@ def test_solve(n, k, kt, noise, tau):
 def test_unsupported_cases_rejected():
     X2 = inputs.structured_vertices(2, [4, 4])
     X3 = inputs.structured_vertices(3, [2, 2, 2])
-    for args in ((3, [2, 2, 2], X3, 3, 0), (3, [2, 2, 2], X3, 2, 2), (2, [4, 4], X2, 4, 0), (2, [4, 4], X2, 3, 2),
+    for args in ((3, [2, 2, 2], X3, 3, 0), (3, [2, 2, 2], X3, 2, 3), (2, [4, 4], X2, 4, 0), (2, [4, 4], X2, 3, 3),
                  (2, [4, 4], X2, 2, 3)):
         with pytest.raises(mfs.MfsError):
             mfs.mfs_stmg_setup(args[0], args[1], args[2], args[3], args[4], 1.0, 0.1)
