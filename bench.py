@@ -209,6 +209,17 @@ def stmg_section(mfs, torch, inputs, args):
             e1.record(stream)
             torch.cuda.synchronize()
             vc = e0.elapsed_time(e1) * 1e-3 / reps
+            b32, y32 = b.float(), torch.empty(N, dtype=torch.float32, device="cuda")
+            for _ in range(2):
+                mfs.mfs_stmg_vcycle(h, y32, b32, prec=mfs.MFS_FP32)
+            e0.record(stream)
+            for _ in range(reps):
+                mfs.mfs_stmg_vcycle(h, y32, b32, prec=mfs.MFS_FP32)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            vc32 = e0.elapsed_time(e1) * 1e-3 / reps
+            x32 = torch.zeros_like(xt)
+            info32 = mfs.mfs_stmg_solve(h, b, x32, rtol=1e-8, maxit=400, prec=mfs.MFS_FP32)
             x = torch.zeros_like(xt)
             info = mfs.mfs_stmg_solve(h, b, x, rtol=1e-8, maxit=400)
             torch.cuda.synchronize()
@@ -219,11 +230,15 @@ def stmg_section(mfs, torch, inputs, args):
             nu_ = dim * int(np.prod([k * a + 1 for a in n]))
             vel = torch.cat([torch.arange(q * nvel, q * nvel + nu_) for q in range(S["Q"])])
             err = float((xs[vel] - xt_h[vel]).norm() / xt_h[vel].norm())
+            err32 = float((x32.cpu()[vel] - xt_h[vel]).norm() / xt_h[vel].norm())
             out[f"{'3d_' if dim == 3 else ''}Q{k}Q{k-1}_dg{k-1}"] = {
                 "n_dofs": N, "levels": [[L["n"][0], L["k"], L["Q"]] for L in lev], "setup_s": setup_s,
                 "vcycle_ms": vc * 1e3, "solve_s": info.seconds, "iterations": info.iterations,
                 "rel_residual": info.rel_residual, "status": info.status,
-                "ms_per_iteration": info.seconds / max(1, info.iterations) * 1e3, "velocity_rel_error": err}
+                "ms_per_iteration": info.seconds / max(1, info.iterations) * 1e3, "velocity_rel_error": err,
+                "fp32_vcycle": {"vcycle_ms": vc32 * 1e3, "solve_s": info32.seconds, "iterations": info32.iterations,
+                                "rel_residual": info32.rel_residual, "status": info32.status,
+                                "velocity_rel_error": err32}}
         finally:
             mfs.mfs_stmg_destroy(h)
     progress("space-time multigrid done")

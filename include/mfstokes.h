@@ -461,22 +461,24 @@ int mfs_st_stage_transfer(mfs_problem *p, int q_out, int q_in, const double *C, 
  * mfs_stmg_vmult: dst = K_level src (stage-major device FP64 vectors of that
  * length; every stage carries the Dirichlet rows as identity).  Enqueue
  * only.
- * mfs_stmg_vcycle: dst = one V-cycle applied to src on level 0 (device
- * FP64); x starts from b on the Dirichlet rows and 0 elsewhere.  Enqueue
- * only; calls on one handle must not overlap.
- * mfs_stmg_solve: x = FGMRES(30) with one V-cycle per iteration from x = 0
- * to ||b - K x|| <= rtol ||b|| (device FP64 b and x of the level-0 length;
- * the constant pressure of each stage is in the kernel of K: b must be
- * consistent).  Synchronous on the setup stream; MFS_ENOCONV with `info`
- * filled when maxit iterations do not reach rtol.
+ * mfs_stmg_vcycle: dst = one V-cycle applied to src on level 0, in precision
+ * prec (MFS_FP64 or MFS_FP32: device vectors of that type; the FP32 V-cycle
+ * runs every level in FP32 with FP32 copies of the patch inverses and the
+ * FP64 coarse inverse); x starts from b on the Dirichlet rows and 0
+ * elsewhere.  Enqueue only; calls on one handle must not overlap.
+ * mfs_stmg_solve: x = FGMRES(30) in FP64 with one V-cycle in precision prec
+ * per iteration, from x = 0 to ||b - K x|| <= rtol ||b|| (device FP64 b and
+ * x of the level-0 length; the constant pressure of each stage is in the
+ * kernel of K: b must be consistent).  Synchronous on the setup stream;
+ * MFS_ENOCONV with `info` filled when maxit iterations do not reach rtol.
  */
 typedef struct mfs_stmg mfs_stmg;
 int mfs_stmg_setup(const mfs_mesh *mesh, int k, int kt, double nu, double tau, int relax_steps, double relax_omega,
                    void *stream, mfs_stmg **out);
 int mfs_stmg_levels(const mfs_stmg *m, int level, int *n_levels, int *n, int *k, int *Q, int64_t *length);
 int mfs_stmg_vmult(mfs_stmg *m, int level, double *dst, const double *src, void *stream);
-int mfs_stmg_vcycle(mfs_stmg *m, double *dst, const double *src, void *stream);
-int mfs_stmg_solve(mfs_stmg *m, const double *b, double *x, double rtol, int maxit, mfs_solve_info *info);
+int mfs_stmg_vcycle(mfs_stmg *m, int prec, void *dst, const void *src, void *stream);
+int mfs_stmg_solve(mfs_stmg *m, const double *b, double *x, double rtol, int maxit, int prec, mfs_solve_info *info);
 int mfs_stmg_destroy(mfs_stmg *m);
 
 /*

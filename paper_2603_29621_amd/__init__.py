@@ -170,8 +170,9 @@ def lib():
                                       ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                       ctypes.POINTER(ctypes.c_int64)]
         L.mfs_stmg_vmult.argtypes = [vp, ctypes.c_int, vp, vp, vp]
-        L.mfs_stmg_vcycle.argtypes = [vp, vp, vp, vp]
-        L.mfs_stmg_solve.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_int, ctypes.POINTER(mfs_solve_info)]
+        L.mfs_stmg_vcycle.argtypes = [vp, ctypes.c_int, vp, vp, vp]
+        L.mfs_stmg_solve.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                     ctypes.POINTER(mfs_solve_info)]
         L.mfs_stmg_destroy.argtypes = [vp]
         _lib = L
     return _lib
@@ -661,21 +662,22 @@ def mfs_stmg_vmult(h, level, dst, src, stream=None):
                                 _stream(stream)))
 
 
-def mfs_stmg_vcycle(h, dst, src, stream=None):
+def mfs_stmg_vcycle(h, dst, src, prec=MFS_FP64, stream=None):
     import torch
 
     n = _stmg_len(h, 0)
-    _check(lib().mfs_stmg_vcycle(h, _arg(dst, n, torch.float64, "dst"), _arg(src, n, torch.float64, "src"),
-                                 _stream(stream)))
+    dt = torch.float64 if prec == MFS_FP64 else torch.float32
+    _check(lib().mfs_stmg_vcycle(h, int(prec), _arg(dst, n, dt, "dst"), _arg(src, n, dt, "src"), _stream(stream)))
 
 
-def mfs_stmg_solve(h, b, x, rtol=1e-8, maxit=200) -> mfs_solve_info:
+def mfs_stmg_solve(h, b, x, rtol=1e-8, maxit=200, prec=MFS_FP64) -> mfs_solve_info:
+    """FP64 FGMRES with one V-cycle in precision `prec` per iteration."""
     import torch
 
     n = _stmg_len(h, 0)
     info = mfs_solve_info()
     rc = lib().mfs_stmg_solve(h, _arg(b, n, torch.float64, "b"), _arg(x, n, torch.float64, "x"), float(rtol),
-                              int(maxit), ctypes.byref(info))
+                              int(maxit), int(prec), ctypes.byref(info))
     if rc not in (MFS_OK, MFS_ENOCONV):
         _check(rc)
     return info

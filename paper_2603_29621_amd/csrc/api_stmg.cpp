@@ -131,19 +131,37 @@ LevelGeom pressure_grid(const LevelGeom &g) {
 
 }  // namespace
 
+// level vectors of one precision
+template <typename T>
+struct StBuf {
+  T *x = nullptr, *b = nullptr, *r = nullptr, *t = nullptr, *work = nullptr;
+  T *Kinv = nullptr;                   // space-time patch inverses (all levels but the coarsest)
+  T *rw_v = nullptr, *rw_p = nullptr;  // scratch of the three-pass restrictions to the next level
+};
+
 struct StLevel {
   int sp = 0;       // spatial problem
   int kt = 0, Q = 1;
   int64_t N = 0;    // entries per stage: dim Nv + Np
   std::vector<double> G;
-  double *x = nullptr, *b = nullptr, *r = nullptr, *t = nullptr, *work = nullptr;
-  double *Kinv = nullptr;  // space-time patch inverses (all levels but the coarsest)
-  double *rw_v = nullptr, *rw_p = nullptr;  // scratch of the three-pass restrictions to the next level
-  int kind = 0;            // transfer to the next level: 1 time, 2 space
+  StBuf<double> d;  // FP64 V-cycle
+  StBuf<float> f;   // FP32 V-cycle (inside the FP64 FGMRES)
+  int kind = 0;     // transfer to the next level: 1 time, 2 space
   bool h = false;
   std::vector<double> emb_v, emb_p;
   StageCoef Pt{}, Rt{};
 };
+
+template <typename T>
+StBuf<T> &buf(StLevel &L);
+template <>
+StBuf<double> &buf<double>(StLevel &L) {
+  return L.d;
+}
+template <>
+StBuf<float> &buf<float>(StLevel &L) {
+  return L.f;
+}
 
 struct mfs_stmg {
   int dim = 2;
@@ -178,62 +196,70 @@ namespace {
 
 const LevelGeom &geom(const mfs_stmg &M, int l) { return M.sp[M.lev[l].sp]->L[0].g; }
 
-void level_apply(mfs_stmg &M, int l, double *dst, const double *src, hipStream_t s) {
+template <typename T>
+void level_apply(mfs_stmg &M, int l, T *dst, const T *src, hipStream_t s) {
   StLevel &L = M.lev[l];
-  st_apply<double>(*M.sp[L.sp], L.Q, L.G.data(), M.tau, dst, src, L.work, s);
+  st_apply<T>(*M.sp[L.sp], L.Q, L.G.data(), M.tau, dst, src, buf<T>(L).work, s);
 }
 
 // additive Schwarz steps x <- x + omega B (b - K x)
+template <typename T>
 void relax(mfs_stmg &M, int l, hipStream_t s) {
   StLevel &L = M.lev[l];
+  StBuf<T> &B = buf<T>(L);
   const LevelGeom &g = geom(M, l);
   for (int it = 0; it < M.steps; ++it) {
-    level_apply(M, l, L.t, L.x, s);
-    for (int c = 0; c < asm_colours(g); ++c) launch_th_apply(g, L.Q, L.N, L.Kinv, c, L.b, L.t, L.x, M.omega, s);
+    level_apply<T>(M, l, B.t, B.x, s);
+    for (int c = 0; c < asm_colours(g); ++c)
+      launch_th_apply<T>(g, L.Q, L.N, B.Kinv, c, B.b, B.t, B.x, (T)M.omega, s);
   }
 }
 
+// one V-cycle on level l from buf<T>.b into buf<T>.x
+template <typename T>
 void vcycle(mfs_stmg &M, int l, hipStream_t s) {
   StLevel &L = M.lev[l];
+  StBuf<T> &B = buf<T>(L);
   const int64_t n = (int64_t)L.Q * L.N;
   if (l == (int)M.lev.size() - 1) {
-    dense_apply<double>(M.coarse_inv, M.coarse_n, L.b, L.x, s);
+    dense_apply<T>(M.coarse_inv, M.coarse_n, B.b, B.x, s);
     return;
   }
   const LevelGeom &g = geom(M, l);
-  vec_fill<double>(L.x, 0.0, n, s);
-  for (int q = 0; q < L.Q; ++q) vec_copy_boundary<double>(g, L.x + q * L.N, L.b + q * L.N, s);
-  relax(M, l, s);
-  level_apply(M, l, L.t, L.x, s);
-  vec_copy<double>(L.r, L.b, n, s);
-  vec_axpby<double>(L.r, -1.0, L.t, 1.0, n, s);  // r = b - K x
+  vec_fill<T>(B.x, T(0), n, s);
+  for (int q = 0; q < L.Q; ++q) vec_copy_boundary<T>(g, B.x + q * L.N, B.b + q * L.N, s);
+  relax<T>(M, l, s);
+  level_apply<T>(M, l, B.t, B.x, s);
+  vec_copy<T>(B.r, B.b, n, s);
+  vec_axpby<T>(B.r, T(-1), B.t, T(1), n, s);  // r = b - K x
   StLevel &C = M.lev[l + 1];
+  StBuf<T> &CB = buf<T>(C);
   if (L.kind == 1) {
-    stage_mix<double>(C.b, C.N, C.Q, L.r, L.N, L.Q, L.Rt, 0.0, L.N, L.N, s);
+    stage_mix<T>(CB.b, C.N, C.Q, B.r, L.N, L.Q, L.Rt, T(0), L.N, L.N, s);
   } else {
     const LevelGeom &gc = geom(M, l + 1);
     const LevelGeom &pf = M.pg[L.sp], &pc = M.pg[C.sp];
     for (int q = 0; q < L.Q; ++q) {
-      const double *rf = L.r + q * L.N;
-      double *bc = C.b + q * C.N;
-      launch_restrict<double>(g, gc, L.h, L.emb_v.data(), bc, rf, s, 0, L.rw_v);
-      launch_restrict<double>(pf, pc, L.h, L.emb_p.data(), bc + g.dim * gc.Nv, rf + g.dim * g.Nv, s, 1, L.rw_p, 0);
+      const T *rf = B.r + q * L.N;
+      T *bc = CB.b + q * C.N;
+      launch_restrict<T>(g, gc, L.h, L.emb_v.data(), bc, rf, s, 0, B.rw_v);
+      launch_restrict<T>(pf, pc, L.h, L.emb_p.data(), bc + g.dim * gc.Nv, rf + g.dim * g.Nv, s, 1, B.rw_p, 0);
     }
   }
-  vcycle(M, l + 1, s);
+  vcycle<T>(M, l + 1, s);
   if (L.kind == 1) {
-    stage_mix<double>(L.x, L.N, L.Q, C.x, C.N, C.Q, L.Pt, 1.0, L.N, L.N, s);
+    stage_mix<T>(B.x, L.N, L.Q, CB.x, C.N, C.Q, L.Pt, T(1), L.N, L.N, s);
   } else {
     const LevelGeom &gc = geom(M, l + 1);
     const LevelGeom &pf = M.pg[L.sp], &pc = M.pg[C.sp];
     for (int q = 0; q < L.Q; ++q) {
-      double *xf = L.x + q * L.N;
-      const double *xc = C.x + q * C.N;
-      launch_prolongate_add<double>(g, gc, L.h, L.emb_v.data(), xf, xc, s);
-      launch_prolongate_add<double>(pf, pc, L.h, L.emb_p.data(), xf + g.dim * g.Nv, xc + g.dim * gc.Nv, s, 1, 0);
+      T *xf = B.x + q * L.N;
+      const T *xc = CB.x + q * C.N;
+      launch_prolongate_add<T>(g, gc, L.h, L.emb_v.data(), xf, xc, s);
+      launch_prolongate_add<T>(pf, pc, L.h, L.emb_p.data(), xf + g.dim * g.Nv, xc + g.dim * gc.Nv, s, 1, 0);
     }
   }
-  relax(M, l, s);
+  relax<T>(M, l, s);
 }
 
 // spatial patch matrices of level l by probing, then the space-time inverses
@@ -245,8 +271,21 @@ void setup_patches(mfs_stmg &M, int l) {
   const int nps = th_patch_size(g);
   const int64_t np = asm_patch_count(g);
   const int64_t nv = (int64_t)g.dim * g.Nv;
-  double *As = M.alloc<double>(np * nps * nps), *Ms = M.alloc<double>(np * nps * nps);
-  double *e = M.alloc<double>(L.N), *ya = M.alloc<double>(L.N), *ym = M.alloc<double>(nv);
+  std::vector<void *> tmp;  // probing scratch, freed at the end
+  auto talloc = [&](int64_t n) {
+    void *q = nullptr;
+    MFS_HIP(hipMalloc(&q, (size_t)std::max<int64_t>(n, 1) * sizeof(double)));
+    tmp.push_back(q);
+    return static_cast<double *>(q);
+  };
+  struct Free {
+    std::vector<void *> &v;
+    ~Free() {
+      for (void *q : v) (void)hipFree(q);
+    }
+  } free_tmp{tmp};
+  double *As = talloc(np * nps * nps), *Ms = talloc(np * nps * nps);
+  double *e = talloc(L.N), *ya = talloc(L.N), *ym = talloc(nv);
   for (int c = 0; c < asm_colours(g); ++c)
     for (int j = 0; j < nps; ++j) {
       vec_fill<double>(e, 0.0, L.N, s);
@@ -260,10 +299,12 @@ void setup_patches(mfs_stmg &M, int l) {
   for (int i = 0; i < L.Q; ++i)
     for (int j = 0; j < L.Q; ++j) G.c[i * MFS_MAX_STAGES + j] = L.G[(size_t)i * L.Q + j];
   const int NP = L.Q * nps;
-  L.Kinv = M.alloc<double>(np * NP * NP);
+  L.d.Kinv = M.alloc<double>(np * NP * NP);
+  L.f.Kinv = M.alloc<float>(np * NP * NP);
   int *status = M.alloc<int>(1);
   MFS_HIP(hipMemsetAsync(status, 0, sizeof(int), s));
-  launch_th_form_invert(g, L.Q, G, M.tau, As, Ms, L.Kinv, status, s);
+  launch_th_form_invert(g, L.Q, G, M.tau, As, Ms, L.d.Kinv, status, s);
+  vec_cast<float, double>(L.f.Kinv, L.d.Kinv, np * NP * NP, s);
   int hst = 0;
   MFS_HIP(hipMemcpyAsync(&hst, status, sizeof(int), hipMemcpyDeviceToHost, s));
   MFS_HIP(hipStreamSynchronize(s));
@@ -286,7 +327,7 @@ void setup_coarse(mfs_stmg &M) {
     vec_fill<double>(e, 0.0, n, M.s);
     const double one = 1.0;
     MFS_HIP(hipMemcpyAsync(e + j, &one, sizeof(double), hipMemcpyHostToDevice, M.s));
-    level_apply(M, l, y + (int64_t)j * n, e, M.s);  // column j
+    level_apply<double>(M, l, y + (int64_t)j * n, e, M.s);  // column j
     MFS_HIP(hipStreamSynchronize(M.s));
   }
   std::vector<double> colmaj((size_t)n * n), A((size_t)n * n);
@@ -402,12 +443,17 @@ int mfs_stmg_setup(const mfs_mesh *mesh, int k, int kt, double nu, double tau, i
     const int nl = (int)M->lev.size();
     for (int l = 0; l < nl; ++l) {
       StLevel &L = M->lev[l];
-      const int64_t n = (int64_t)L.Q * L.N;
-      L.x = M->alloc<double>(n);
-      L.b = M->alloc<double>(n);
-      L.r = M->alloc<double>(n);
-      L.t = M->alloc<double>(n);
-      L.work = M->alloc<double>((int64_t)L.Q * dim * M->sp[L.sp]->L[0].g.Nv);
+      const int64_t n = (int64_t)L.Q * L.N, nw = (int64_t)L.Q * dim * M->sp[L.sp]->L[0].g.Nv;
+      L.d.x = M->alloc<double>(n);
+      L.d.b = M->alloc<double>(n);
+      L.d.r = M->alloc<double>(n);
+      L.d.t = M->alloc<double>(n);
+      L.d.work = M->alloc<double>(nw);
+      L.f.x = M->alloc<float>(n);
+      L.f.b = M->alloc<float>(n);
+      L.f.r = M->alloc<float>(n);
+      L.f.t = M->alloc<float>(n);
+      L.f.work = M->alloc<float>(nw);
       if (l + 1 < nl) {
         const StLevel &C = M->lev[l + 1];
         const LevelGeom &gf = M->sp[L.sp]->L[0].g, &gc = M->sp[C.sp]->L[0].g;
@@ -419,8 +465,11 @@ int mfs_stmg_setup(const mfs_mesh *mesh, int k, int kt, double nu, double tau, i
           L.h = gc.n[0] != gf.n[0];
           L.emb_v = L.h ? h_embedding(gc.k) : p_embedding(gf.k, gc.k);
           L.emb_p = L.h ? h_embedding(gc.kp) : p_embedding(gf.kp, gc.kp);
-          L.rw_v = M->alloc<double>(restrict_work_elems(gf, gc, dim));
-          L.rw_p = M->alloc<double>(restrict_work_elems(M->pg[L.sp], M->pg[C.sp], 1));
+          const int64_t wv = restrict_work_elems(gf, gc, dim), wp = restrict_work_elems(M->pg[L.sp], M->pg[C.sp], 1);
+          L.d.rw_v = M->alloc<double>(wv);
+          L.d.rw_p = M->alloc<double>(wp);
+          L.f.rw_v = M->alloc<float>(wv);
+          L.f.rw_p = M->alloc<float>(wp);
         }
       }
     }
@@ -467,26 +516,34 @@ int mfs_stmg_vmult(mfs_stmg *m, int level, double *dst, const double *src, void 
     MFS_REQUIRE(level >= 0 && level < (int)m->lev.size(), MFS_EINVAL, "level %d outside [0, %d)", level,
                 (int)m->lev.size());
     MFS_REQUIRE(dst && src && dst != src, MFS_EINVAL, "bad arguments");
-    level_apply(*m, level, dst, src, S(stream));
+    level_apply<double>(*m, level, dst, src, S(stream));
   });
 }
 
-int mfs_stmg_vcycle(mfs_stmg *m, double *dst, const double *src, void *stream) {
+int mfs_stmg_vcycle(mfs_stmg *m, int prec, void *dst, const void *src, void *stream) {
   return guard([&] {
     check_stmg(m);
+    MFS_REQUIRE(prec == MFS_FP64 || prec == MFS_FP32, MFS_EINVAL, "bad precision %d", prec);
     MFS_REQUIRE(dst && src, MFS_EINVAL, "bad arguments");
     hipStream_t s = S(stream);
     StLevel &L = m->lev[0];
     const int64_t n = top_len(*m);
-    vec_copy<double>(L.b, src, n, s);
-    vcycle(*m, 0, s);
-    vec_copy<double>(dst, L.x, n, s);
+    if (prec == MFS_FP64) {
+      vec_copy<double>(L.d.b, (const double *)src, n, s);
+      vcycle<double>(*m, 0, s);
+      vec_copy<double>((double *)dst, L.d.x, n, s);
+    } else {
+      vec_copy<float>(L.f.b, (const float *)src, n, s);
+      vcycle<float>(*m, 0, s);
+      vec_copy<float>((float *)dst, L.f.x, n, s);
+    }
   });
 }
 
-int mfs_stmg_solve(mfs_stmg *m, const double *b, double *x, double rtol, int maxit, mfs_solve_info *info) {
+int mfs_stmg_solve(mfs_stmg *m, const double *b, double *x, double rtol, int maxit, int prec, mfs_solve_info *info) {
   return guard([&] {
     check_stmg(m);
+    MFS_REQUIRE(prec == MFS_FP64 || prec == MFS_FP32, MFS_EINVAL, "bad precision %d", prec);
     MFS_REQUIRE(b && x && info, MFS_EINVAL, "bad arguments");
     MFS_REQUIRE(rtol > 0 && maxit >= 1, MFS_EINVAL, "bad tolerance or iteration limit");
     const auto t0 = std::chrono::steady_clock::now();
@@ -508,7 +565,7 @@ int mfs_stmg_solve(mfs_stmg *m, const double *b, double *x, double rtol, int max
     int its = 0;
     // r = b - K x
     double *r0 = M.V;
-    level_apply(M, 0, M.w, x, s);
+    level_apply<double>(M, 0, M.w, x, s);
     vec_copy<double>(r0, b, n, s);
     vec_axpby<double>(r0, -1.0, M.w, 1.0, n, s);
     double beta = std::sqrt(dot(r0, r0));
@@ -522,10 +579,16 @@ int mfs_stmg_solve(mfs_stmg *m, const double *b, double *x, double rtol, int max
       double hn = 1.0;
       while (j < mm) {
         double *vj = M.V + (int64_t)j * M.ld, *zj = M.Z + (int64_t)j * M.ld;
-        vec_copy<double>(M.lev[0].b, vj, n, s);
-        vcycle(M, 0, s);
-        vec_copy<double>(zj, M.lev[0].x, n, s);
-        level_apply(M, 0, M.w, zj, s);
+        if (prec == MFS_FP64) {
+          vec_copy<double>(M.lev[0].d.b, vj, n, s);
+          vcycle<double>(M, 0, s);
+          vec_copy<double>(zj, M.lev[0].d.x, n, s);
+        } else {
+          vec_cast<float, double>(M.lev[0].f.b, vj, n, s);
+          vcycle<float>(M, 0, s);
+          vec_cast<double, float>(zj, M.lev[0].f.x, n, s);
+        }
+        level_apply<double>(M, 0, M.w, zj, s);
         // classical Gram-Schmidt, twice
         multi_dot<double>(M.V, M.ld, j + 1, M.w, n, M.dev, M.partials, s);
         multi_axpy<double>(M.w, M.V, M.ld, j + 1, M.dev, n, s);
@@ -568,7 +631,7 @@ int mfs_stmg_solve(mfs_stmg *m, const double *b, double *x, double rtol, int max
       MFS_HIP(hipMemcpyAsync(M.ydev, y.data(), j * sizeof(double), hipMemcpyHostToDevice, s));
       multi_combine<double>(x, M.Z, M.ld, j, M.ydev, n, true, s);
       MFS_HIP(hipStreamSynchronize(s));
-      level_apply(M, 0, M.w, x, s);
+      level_apply<double>(M, 0, M.w, x, s);
       vec_copy<double>(r0, b, n, s);
       vec_axpby<double>(r0, -1.0, M.w, 1.0, n, s);
       beta = std::sqrt(dot(r0, r0));

@@ -398,14 +398,13 @@ __global__ void __launch_bounds__(INV_T) k_th_form_invert(LevelGeom g, StageCoef
 
 // x += omega W Kp^{-1} (b - t) on the space-time patches of one colour;
 // stage-major vectors of Q stages of N entries; NPP threads per patch
-template <int DIM, int K, int Q>
+template <typename T, int DIM, int K, int Q>
 __global__ void __launch_bounds__(APPLY_T) k_th_apply(LevelGeom g, Colour C, int64_t N,
-                                                      const double *__restrict__ Kinv,
-                                                      const double *__restrict__ b, const double *__restrict__ t,
-                                                      double *__restrict__ x, double omega) {
+                                                      const T *__restrict__ Kinv, const T *__restrict__ b,
+                                                      const T *__restrict__ t, T *__restrict__ x, T omega) {
   constexpr int NPS = Th<DIM, K>::NPS, NP = Q * NPS;
   constexpr int NPP = NP <= 32 ? 32 : NP <= 64 ? 64 : NP <= 128 ? 128 : 256, PPB = APPLY_T / NPP;
-  __shared__ double sr[PPB][NPP];
+  __shared__ T sr[PPB][NPP];
   const int lp = threadIdx.x / NPP, i = threadIdx.x % NPP;
   const int64_t q = blockIdx.x * (int64_t)PPB + lp;
   const bool on = q < C.count;
@@ -417,14 +416,14 @@ __global__ void __launch_bounds__(APPLY_T) k_th_apply(LevelGeom g, Colour C, int
     const int64_t gs = th_slot<DIM, K>(g, v, i % NPS, &w);
     if (gs >= 0) gi = (i / NPS) * N + gs;
   }
-  sr[lp][i] = gi >= 0 ? b[gi] - t[gi] : 0.0;
+  sr[lp][i] = gi >= 0 ? b[gi] - t[gi] : T(0);
   __syncthreads();
   if (!on || i >= NP) return;
-  const double *Kp = Kinv + pid * NP * NP + i;
-  double y = 0;
+  const T *Kp = Kinv + pid * NP * NP + i;
+  T y = 0;
 #pragma unroll 4
   for (int j = 0; j < NP; ++j) y += Kp[(int64_t)j * NP] * sr[lp][j];
-  if (gi >= 0) x[gi] += omega * w * y;
+  if (gi >= 0) x[gi] += omega * (T)w * y;
 }
 
 // (DIM, K, Q) of the supported space-time patches: 2D with K = 2, 3 and
@@ -549,17 +548,22 @@ void launch_th_form_invert(const LevelGeom &g, int Q, const StageCoef &G, double
   MFS_HIP(hipGetLastError());
 }
 
-void launch_th_apply(const LevelGeom &g, int Q, int64_t N, const double *Kinv, int colour, const double *b,
-                     const double *t, double *x, double omega, hipStream_t s) {
+template <typename T>
+void launch_th_apply(const LevelGeom &g, int Q, int64_t N, const T *Kinv, int colour, const T *b, const T *t, T *x,
+                     T omega, hipStream_t s) {
   const Colour C = colour_of(g, colour);
   th_dispatch(g, Q, [&](auto D, auto Kc, auto Qc) {
     constexpr int DD = decltype(D)::value, KK = decltype(Kc)::value, QQ = decltype(Qc)::value;
     constexpr int NP = QQ * Th<DD, KK>::NPS;
     constexpr int PPB = APPLY_T / (NP <= 32 ? 32 : NP <= 64 ? 64 : NP <= 128 ? 128 : 256);
-    hipLaunchKernelGGL((k_th_apply<DD, KK, QQ>), dim3(grid_of(C.count, PPB)), dim3(APPLY_T), 0, s, g, C, N, Kinv, b,
-                       t, x, omega);
+    hipLaunchKernelGGL((k_th_apply<T, DD, KK, QQ>), dim3(grid_of(C.count, PPB)), dim3(APPLY_T), 0, s, g, C, N, Kinv,
+                       b, t, x, omega);
   });
   MFS_HIP(hipGetLastError());
 }
+template void launch_th_apply<double>(const LevelGeom &, int, int64_t, const double *, int, const double *,
+                                      const double *, double *, double, hipStream_t);
+template void launch_th_apply<float>(const LevelGeom &, int, int64_t, const float *, int, const float *,
+                                     const float *, float *, float, hipStream_t);
 
 }  // namespace mfs

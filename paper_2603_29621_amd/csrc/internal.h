@@ -302,8 +302,9 @@ void launch_th_probe_extract(const LevelGeom &g, const double *y, int64_t nvel, 
                              hipStream_t s);
 void launch_th_form_invert(const LevelGeom &g, int Q, const StageCoef &G, double tau, const double *As,
                            const double *Ms, double *Kinv, int *status, hipStream_t s);
-void launch_th_apply(const LevelGeom &g, int Q, int64_t N, const double *Kinv, int colour, const double *b,
-                     const double *t, double *x, double omega, hipStream_t s);
+template <typename T>
+void launch_th_apply(const LevelGeom &g, int Q, int64_t N, const T *Kinv, int colour, const T *b, const T *t, T *x,
+                     T omega, hipStream_t s);
 template <typename T>
 void vec_fill(T *x, T v, int64_t n, hipStream_t s);
 template <typename T>

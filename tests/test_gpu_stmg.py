@@ -3,13 +3,14 @@
 operator on every level, one V-cycle, and FGMRES solves.
 
 Tolerances: the level operators within 1e-12 relative (FP64, as the
-space-time operator); one V-cycle within 1e-9 (two relaxation steps per
-level around the coarse correction, each an operator application and a sum
-of explicit patch inverses, GPU Gauss-Jordan against the oracle's dense
+space-time operator); one V-cycle within 1e-9 in FP64 (two relaxation steps
+per level around the coarse correction, each an operator application and a
+sum of explicit patch inverses, GPU Gauss-Jordan against the oracle's dense
 inverses, and a pinned dense coarse inverse against an LU solve: the same
-bound as the additive Schwarz V-cycle); solves to 1e-10 within two
-iterations of the oracle's FGMRES, with the velocity within 1e-7 of the
-exact solution (the pressure is fixed up to a constant per stage)."""
+bound as the additive Schwarz V-cycle) and 1e-4 in FP32 (as the other FP32
+V-cycles); solves to 1e-10 within two iterations of the oracle's FGMRES
+(FP32 V-cycle: within three), with the velocity within 1e-7 of the exact
+solution (the pressure is fixed up to a constant per stage)."""
 import numpy as np
 import pytest
 import torch
@@ -80,6 +81,9 @@ def test_vcycle(n, k, kt, noise, tau):
         x = torch.empty(N, dtype=torch.float64, device="cuda")
         mfs.mfs_stmg_vcycle(h, x, cuda(b))
         assert relerr(host(x), ref) <= 1e-9
+        x32 = torch.empty(N, dtype=torch.float32, device="cuda")
+        mfs.mfs_stmg_vcycle(h, x32, cuda(b).float(), prec=mfs.MFS_FP32)
+        assert relerr(host(x32).astype(np.float64), ref) <= 1e-4
         # a second call on the same handle gives the same bits
         x2 = torch.empty_like(x)
         mfs.mfs_stmg_vcycle(h, x2, cuda(b))
@@ -100,16 +104,17 @@ def test_solve(n, k, kt, noise, tau):
         b = K @ xt
         _, its_ref, rel_ref = H.solve(b, rtol=1e-10)
         assert rel_ref <= 1e-10
-        x = torch.zeros(N, dtype=torch.float64, device="cuda")
-        info = mfs.mfs_stmg_solve(h, cuda(b), x, rtol=1e-10, maxit=200)
-        assert info.status == 0 and info.rel_residual <= 1e-10
-        assert abs(info.iterations - its_ref) <= 2
-        xs = host(x)
-        assert np.linalg.norm(b - K @ xs) <= 2e-10 * np.linalg.norm(b)
         S = H.spaces[0]
         Q, Ns = H.Q[0], S.n_dofs
         vel = np.concatenate([np.arange(q * Ns, q * Ns + S.dim * S.Nv) for q in range(Q)])
-        assert relerr(xs[vel], xt[vel]) <= 1e-7
+        for prec, slack in ((mfs.MFS_FP64, 2), (mfs.MFS_FP32, 3)):
+            x = torch.zeros(N, dtype=torch.float64, device="cuda")
+            info = mfs.mfs_stmg_solve(h, cuda(b), x, rtol=1e-10, maxit=200, prec=prec)
+            assert info.status == 0 and info.rel_residual <= 1e-10
+            assert abs(info.iterations - its_ref) <= slack
+            xs = host(x)
+            assert np.linalg.norm(b - K @ xs) <= 2e-10 * np.linalg.norm(b)
+            assert relerr(xs[vel], xt[vel]) <= 1e-7
     finally:
         mfs.mfs_stmg_destroy(h)
 
