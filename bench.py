@@ -614,48 +614,6 @@ def refined_ns_section(mfs, torch, inputs, args, dt, nu):
     return out
 
 
-def relaxation_compare(mfs, torch, inputs, n, k, nu, X, args):
-    """The same Newton-step solve with the two relaxations of the monolithic
-    multigrid: 5 damped point-Jacobi sweeps (omega 0.5) against 2 additive
-    Schwarz sweeps on vertex patches (omega 1; Sec. 5, Exp. 4), FP32 multigrid
-    in FP64 FGMRES, at the transient step and at dt = 1 (nearly stationary)."""
-    out = {"workload": f"Q2Q2 {n}^3, J x = J y, rtol 1e-8, FP32 MG in FP64 FGMRES, set-up includes the "
-                       "linearisation (and the patch inverses)"}
-    N = 4 * (k * n + 1) ** 3
-    u0 = torch.from_numpy(inputs.ns_velocity(3, [k * n + 1] * 3, seed=0)).cuda()
-    y = torch.from_numpy(inputs.uniform_vector(N, 3)).cuda()
-    for dt in (0.01, 1.0):
-        row = {}
-        for name, kw in (("jacobi_5", dict(relax_steps=5, relax_omega=0.5)),
-                         ("asm_2", dict(relax_type=mfs.MFS_RELAX_ASM, relax_steps=2, relax_omega=1.0))):
-            opts = mfs.mfs_default_options(pressure_offset=0, precond_precision=mfs.MFS_FP32, rtol=1e-8, maxit=200,
-                                           graphs=args.graphs, **kw)
-            h = mfs.mfs_setup(3, [n] * 3, X, k, nu, opts)
-            try:
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                mfs.mfs_set_linearization(h, u0, dt, 1)
-                torch.cuda.synchronize()
-                t1 = time.perf_counter()
-                b = torch.empty_like(y)
-                mfs.mfs_vmult(h, mfs.MFS_OP_NS_JACOBIAN, mfs.MFS_FP64, 0, b, y)
-                times = []
-                for rep in range(2):
-                    x = torch.zeros(N, dtype=torch.float64, device="cuda")
-                    torch.cuda.synchronize()
-                    t2 = time.perf_counter()
-                    info = mfs.mfs_solve(h, b, x, opts)
-                    times.append(time.perf_counter() - t2)
-                row[name] = {"linearization_s": t1 - t0, "solve_s": min(times), "iterations": info.iterations,
-                             "rel_residual": info.rel_residual, "status": info.status}
-            finally:
-                mfs.mfs_destroy(h)
-        out[f"dt={dt:g}"] = row
-        progress(f"relaxation dt={dt:g}: Jacobi {row['jacobi_5']['iterations']} its {row['jacobi_5']['solve_s']:.3f} s, "
-                 f"ASM {row['asm_2']['iterations']} its {row['asm_2']['solve_s']:.3f} s")
-    return out
-
-
 def bdf2_section(mfs, torch, inputs, args):
     """Three BDF2 steps of the stabilised Navier-Stokes equations (SUPG/PSPG,
     Q1Q1 and Q2Q2, Re = 100: nu = 0.01 with the unit-RMS 8-mode Fourier field

@@ -245,10 +245,11 @@ __global__ void __launch_bounds__(APPLY_T) k_asm_apply(LevelGeom g, Colour C, co
   __syncthreads();
   if (!on || i >= NP) return;
   const T *Mp = M + pid * NP * NP + i;
-  T y = 0;
-#pragma unroll 4
-  for (int j = 0; j < NP; ++j) y += Mp[(int64_t)j * NP] * sr[lp][j];
-  if (gi >= 0) x[gi] += omega * (T)w * y;
+  // four partial sums, so that a thread keeps several column loads in flight
+  T y[4] = {0, 0, 0, 0};
+#pragma unroll 8
+  for (int j = 0; j < NP; ++j) y[j & 3] += Mp[(int64_t)j * NP] * sr[lp][j];
+  if (gi >= 0) x[gi] += omega * (T)w * ((y[0] + y[1]) + (y[2] + y[3]));
 }
 
 template <int DIM, int K, typename F>
