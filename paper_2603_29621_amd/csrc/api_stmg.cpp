@@ -202,14 +202,19 @@ void level_apply(mfs_stmg &M, int l, T *dst, const T *src, hipStream_t s) {
   st_apply<T>(*M.sp[L.sp], L.Q, L.G.data(), M.tau, dst, src, buf<T>(L).work, s);
 }
 
-// additive Schwarz steps x <- x + omega B (b - K x)
+// additive Schwarz steps x <- x + omega B (b - K x).  zero_start: x holds b
+// on the Dirichlet rows and 0 elsewhere, where K x = x exactly (identity rows,
+// Dirichlet source values ignored in the others), so the first step copies.
 template <typename T>
-void relax(mfs_stmg &M, int l, hipStream_t s) {
+void relax(mfs_stmg &M, int l, bool zero_start, hipStream_t s) {
   StLevel &L = M.lev[l];
   StBuf<T> &B = buf<T>(L);
   const LevelGeom &g = geom(M, l);
   for (int it = 0; it < M.steps; ++it) {
-    level_apply<T>(M, l, B.t, B.x, s);
+    if (zero_start && it == 0)
+      vec_copy<T>(B.t, B.x, (int64_t)L.Q * L.N, s);
+    else
+      level_apply<T>(M, l, B.t, B.x, s);
     for (int c = 0; c < asm_colours(g); ++c)
       launch_th_apply<T>(g, L.Q, L.N, B.Kinv, c, B.b, B.t, B.x, (T)M.omega, s);
   }
@@ -228,7 +233,7 @@ void vcycle(mfs_stmg &M, int l, hipStream_t s) {
   const LevelGeom &g = geom(M, l);
   vec_fill<T>(B.x, T(0), n, s);
   for (int q = 0; q < L.Q; ++q) vec_copy_boundary<T>(g, B.x + q * L.N, B.b + q * L.N, s);
-  relax<T>(M, l, s);
+  relax<T>(M, l, true, s);
   level_apply<T>(M, l, B.t, B.x, s);
   vec_copy<T>(B.r, B.b, n, s);
   vec_axpby<T>(B.r, T(-1), B.t, T(1), n, s);  // r = b - K x
@@ -259,7 +264,7 @@ void vcycle(mfs_stmg &M, int l, hipStream_t s) {
       launch_prolongate_add<T>(pf, pc, L.h, L.emb_p.data(), xf + g.dim * g.Nv, xc + g.dim * gc.Nv, s, 1, 0);
     }
   }
-  relax<T>(M, l, s);
+  relax<T>(M, l, false, s);
 }
 
 // spatial patch matrices of level l by probing, then the space-time inverses
