@@ -243,12 +243,17 @@ void ns_residual(mfs_problem &P, double *F, hipStream_t s) {
 // unconstrained), recursion, prolongation, relax_steps sweeps; on the
 // coarsest level x = C b with the pinned dense inverse C.
 template <typename T>
-void ns_relax(mfs_problem &P, int l, T *x, const T *b, hipStream_t s) {
+void ns_relax(mfs_problem &P, int l, T *x, const T *b, bool zero_start, hipStream_t s) {
   PrecWork<T> &W = work<T>(P);
   const Level &L = P.L[l];
   const int64_t n = (P.dim + 1) * L.g.Nv;
   for (int it = 0; it < P.opts.relax_steps; ++it) {
-    apply_ns<T>(P, l, W.d[l], x, s);
+    // from the zero start (x = b on the Dirichlet rows, 0 elsewhere) J x = x
+    // exactly: identity rows, Dirichlet source values ignored in the others
+    if (zero_start && it == 0)
+      vec_copy<T>(W.d[l], x, n, s);
+    else
+      apply_ns<T>(P, l, W.d[l], x, s);
     if (L.asm64) {  // additive Schwarz: every colour with the residual b - J x of the sweep's start
       const T *Minv = sizeof(T) == 8 ? (const T *)L.asm64 : (const T *)L.asm32;
       for (int c = 0; c < asm_colours(L.g); ++c)
@@ -270,7 +275,7 @@ void ns_vcycle(mfs_problem &P, int l, T *x, const T *b, hipStream_t s) {
   const int64_t n = (P.dim + 1) * L.g.Nv;
   launch_fill_dirichlet<T>(L.g, x, b, s);
   vec_fill<T>(x + P.dim * L.g.Nv, T(0), L.g.Nv, s);
-  ns_relax<T>(P, l, x, b, s);
+  ns_relax<T>(P, l, x, b, true, s);
   T *r = W.r[l];
   apply_ns<T>(P, l, r, x, s);
   vec_axpby<T>(r, T(1), b, T(-1), n, s);  // r = b - J x
@@ -278,7 +283,7 @@ void ns_vcycle(mfs_problem &P, int l, T *x, const T *b, hipStream_t s) {
   launch_restrict<T>(L.g, C.g, L.h_to_coarser, L.emb.data(), W.b[l + 1], r, s, 1, rwork<T>(L));
   ns_vcycle<T>(P, l + 1, W.x[l + 1], W.b[l + 1], s);
   launch_prolongate_add<T>(L.g, C.g, L.h_to_coarser, L.emb.data(), x, W.x[l + 1], s, 1);
-  ns_relax<T>(P, l, x, b, s);
+  ns_relax<T>(P, l, x, b, false, s);
 }
 
 // the state of a Navier-Stokes problem (structured or refined) at x0 = [u0 | p0]
@@ -378,8 +383,8 @@ void bdf2_step(mfs_problem &P, const double *u_n, const double *u_nm1, double *x
 // instantiations used by the other parts of the runtime
 template void apply_ns<float>(mfs_problem &P, int l, float *dst, const float *src, hipStream_t s);
 template void apply_ns<double>(mfs_problem &P, int l, double *dst, const double *src, hipStream_t s);
-template void ns_relax<float>(mfs_problem &P, int l, float *x, const float *b, hipStream_t s);
-template void ns_relax<double>(mfs_problem &P, int l, double *x, const double *b, hipStream_t s);
+template void ns_relax<float>(mfs_problem &P, int l, float *x, const float *b, bool zero_start, hipStream_t s);
+template void ns_relax<double>(mfs_problem &P, int l, double *x, const double *b, bool zero_start, hipStream_t s);
 template void ns_vcycle<float>(mfs_problem &P, int l, float *x, const float *b, hipStream_t s);
 template void ns_vcycle<double>(mfs_problem &P, int l, double *x, const double *b, hipStream_t s);
 

@@ -293,11 +293,16 @@ void amr_restrict(mfs_problem &P, int j, T *bc, const T *rf, hipStream_t s) {
 }
 
 template <typename T>
-void amr_relax(mfs_problem &P, int j, T *x, const T *b, hipStream_t s) {
+void amr_relax(mfs_problem &P, int j, T *x, const T *b, bool zero_start, hipStream_t s) {
   AmrLevel &V = P.amr->lev[j];
   T *d = amr_w<T>(V, 3);
   for (int it = 0; it < P.opts.relax_steps; ++it) {
-    amr_apply_ns<T>(P, j, d, x, s);
+    // from the zero start (x = b on the Dirichlet rows, 0 elsewhere) J x = x
+    // exactly: identity rows, Dirichlet source values ignored in the others
+    if (zero_start && it == 0)
+      vec_copy<T>(d, x, 4 * V.N, s);
+    else
+      amr_apply_ns<T>(P, j, d, x, s);
     jacobi_relax<T>(x, b, d, amr_inv<T>(V), (T)P.opts.relax_omega, 4 * V.N, s);
   }
 }
@@ -315,7 +320,7 @@ void amr_vcycle(mfs_problem &P, int j, T *x, const T *b, hipStream_t s) {
   AmrLevel &V = A.lev[j], &C = A.lev[j + 1];
   mask_fill_dirichlet<T>(V.M.dir, V.N, 3, x, b, s);  // x = b on Dirichlet rows, 0 elsewhere
   vec_fill<T>(x + 3 * V.N, T(0), V.N, s);
-  amr_relax<T>(P, j, x, b, s);
+  amr_relax<T>(P, j, x, b, true, s);
   T *r = amr_w<T>(V, 2);
   amr_apply_ns<T>(P, j, r, x, s);
   vec_axpby<T>(r, T(1), b, T(-1), 4 * V.N, s);  // r = b - J x
@@ -323,7 +328,7 @@ void amr_vcycle(mfs_problem &P, int j, T *x, const T *b, hipStream_t s) {
   amr_restrict<T>(P, j, bc, r, s);
   amr_vcycle<T>(P, j + 1, xc, bc, s);
   amr_prolongate_add<T>(P, j, x, xc, s);
-  amr_relax<T>(P, j, x, b, s);
+  amr_relax<T>(P, j, x, b, false, s);
 }
 
 // Jacobi diagonal of level j by colour probes (FP64): J applied to the
@@ -435,8 +440,8 @@ template void amr_prolongate_add<float>(mfs_problem &P, int j, float *xf, const 
 template void amr_prolongate_add<double>(mfs_problem &P, int j, double *xf, const double *xc, hipStream_t s);
 template void amr_restrict<float>(mfs_problem &P, int j, float *bc, const float *rf, hipStream_t s);
 template void amr_restrict<double>(mfs_problem &P, int j, double *bc, const double *rf, hipStream_t s);
-template void amr_relax<float>(mfs_problem &P, int j, float *x, const float *b, hipStream_t s);
-template void amr_relax<double>(mfs_problem &P, int j, double *x, const double *b, hipStream_t s);
+template void amr_relax<float>(mfs_problem &P, int j, float *x, const float *b, bool zero_start, hipStream_t s);
+template void amr_relax<double>(mfs_problem &P, int j, double *x, const double *b, bool zero_start, hipStream_t s);
 template void amr_vcycle<float>(mfs_problem &P, int j, float *x, const float *b, hipStream_t s);
 template void amr_vcycle<double>(mfs_problem &P, int j, double *x, const double *b, hipStream_t s);
 

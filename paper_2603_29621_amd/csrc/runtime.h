@@ -616,7 +616,7 @@ void ns_set_point(mfs_problem &P, const double *x0, const double *uh, double dt,
 void ns_set_linearization(mfs_problem &P, const double *u0, double dt, int newton, hipStream_t s);
 void ns_residual(mfs_problem &P, double *F, hipStream_t s);
 template <typename T>
-void ns_relax(mfs_problem &P, int l, T *x, const T *b, hipStream_t s);
+void ns_relax(mfs_problem &P, int l, T *x, const T *b, bool zero_start, hipStream_t s);
 template <typename T>
 void ns_vcycle(mfs_problem &P, int l, T *x, const T *b, hipStream_t s);
 void set_point_any(mfs_problem &P, const double *x0, const double *uh, double dt, int newton, int keep_delta, bool mg,
@@ -667,7 +667,7 @@ void amr_prolongate_add(mfs_problem &P, int j, T *xf, const T *xc, hipStream_t s
 template <typename T>
 void amr_restrict(mfs_problem &P, int j, T *bc, const T *rf, hipStream_t s);
 template <typename T>
-void amr_relax(mfs_problem &P, int j, T *x, const T *b, hipStream_t s);
+void amr_relax(mfs_problem &P, int j, T *x, const T *b, bool zero_start, hipStream_t s);
 template <typename T>
 void amr_vcycle(mfs_problem &P, int j, T *x, const T *b, hipStream_t s);
 void amr_diagonal(mfs_problem &P, int j, double *diag, hipStream_t s);
